@@ -1,0 +1,244 @@
+"""FP64 CPU oracle for GaBP -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP path
+(``paper_0810_1119_amd``) and never imports it.
+
+The arithmetic lives in ``gabp_oracle.c`` (plain C, FP64, optional OpenMP over
+rows); this module compiles it with gcc, loads it with ctypes and adds thin
+array wrappers plus the section VII bipartite construction.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gabp_oracle.c")
+_LIB = os.path.join(_HERE, "libgabp_oracle.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_ARG, ERR_NOT_SYMMETRIC, ERR_ZERO_DIAG, ERR_BREAKDOWN, ERR_DIVERGED = -1, -2, -3, -4, -5
+STOP_RESIDUAL, STOP_MESSAGES, STOP_MEANS = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library with gcc (-O2, IEEE arithmetic, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("algorithm", C.c_int32), ("stop", C.c_int32), ("tol", C.c_double),
+                ("max_rounds", C.c_int32), ("damping", C.c_double), ("nthreads", C.c_int32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = C.CDLL(build())
+        vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        lib.orc_build_reverse.argtypes = [C.POINTER(_Csr), vp, vp]
+        lib.orc_alg1_round.argtypes = [C.POINTER(_Csr), vp, vp, vp, vp, vp, vp, vp, f64, C.c_int]
+        lib.orc_alg1_round.restype = i64
+        lib.orc_alg2_round.argtypes = lib.orc_alg1_round.argtypes
+        lib.orc_alg2_round.restype = i64
+        lib.orc_marginals.argtypes = [C.POINTER(_Csr), vp, vp, vp, vp, vp, vp, vp, C.c_int]
+        lib.orc_residual.argtypes = [C.POINTER(_Csr), vp, vp, vp]
+        lib.orc_residual.restype = f64
+        lib.orc_jacobi_variant_round.argtypes = [C.POINTER(_Csr), vp, vp, vp, vp, vp, vp]
+        lib.orc_solve.argtypes = [C.POINTER(_Csr), vp, C.POINTER(_Opts), vp, vp, vp, vp,
+                                  C.POINTER(i32), vp]
+        lib.orc_refine_solve.argtypes = [C.POINTER(_Csr), vp, f64, f64, i32, i32, f64, i32,
+                                         vp, vp, vp, C.POINTER(i32), C.POINTER(i32),
+                                         C.POINTER(f64)]
+        lib.orc_max_threads.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+class Matrix:
+    """Holds contiguous CSR arrays and the C view of them."""
+
+    def __init__(self, m):
+        self.n = int(m.n)
+        self.row_ptr = np.ascontiguousarray(m.row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(m.col, dtype=np.int32)
+        self.val = np.ascontiguousarray(m.val, dtype=np.float64)
+        self.nnz = int(self.row_ptr[-1])
+        self.c = _Csr(self.n, _p(self.row_ptr), _p(self.col), _p(self.val))
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError("length mismatch")
+    return a
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def reverse(m):
+    """(status, rev[nnz], diag[n]) -- rev of a diagonal slot is -1."""
+    M = Matrix(m)
+    rev = np.empty(M.nnz, dtype=np.int64)
+    diag = np.empty(M.n)
+    st = _load().orc_build_reverse(C.byref(M.c), _p(rev), _p(diag))
+    return st, rev, diag
+
+
+class Rounds:
+    """Round-by-round access for trajectory comparisons (P, mu per CSR slot)."""
+
+    def __init__(self, m, b, algorithm: int = 2, damping: float = 0.0, nthreads: int = 0):
+        self.M = Matrix(m)
+        self.b = _f64(b, self.M.n)
+        st, self.rev, self.diag = reverse(m)
+        if st != OK:
+            raise ValueError(f"oracle rejected the matrix: status {st}")
+        self.algorithm, self.damping, self.nthreads = algorithm, damping, nthreads
+        self.P = np.zeros(self.M.nnz)
+        self.Mu = np.zeros(self.M.nnz)
+        self.zero_cavities = 0
+
+    def step(self, count: int = 1):
+        lib = _load()
+        fn = lib.orc_alg1_round if self.algorithm == 1 else lib.orc_alg2_round
+        for _ in range(count):
+            P2, M2 = np.empty_like(self.P), np.empty_like(self.Mu)
+            self.zero_cavities += fn(C.byref(self.M.c), _p(self.b), _p(self.rev), _p(self.diag),
+                                     _p(self.P), _p(self.Mu), _p(P2), _p(M2),
+                                     self.damping, self.nthreads)
+            self.P, self.Mu = P2, M2
+        return self
+
+    def marginals(self):
+        mean, prec = np.empty(self.M.n), np.empty(self.M.n)
+        _load().orc_marginals(C.byref(self.M.c), _p(self.b), _p(self.rev), _p(self.diag),
+                              _p(self.P), _p(self.Mu), _p(mean), _p(prec), self.nthreads)
+        return mean, prec
+
+    def information(self):
+        """h = P * mu per slot (zero on the diagonal)."""
+        return self.P * self.Mu
+
+
+@dataclass
+class Result:
+    status: int
+    x: np.ndarray
+    prec: np.ndarray
+    rounds: int
+    trace: np.ndarray
+    P: np.ndarray
+    Mu: np.ndarray
+
+
+def solve(m, b, algorithm=2, stop=STOP_RESIDUAL, tol=1e-10, max_rounds=10000,
+          damping=0.0, nthreads=0, P0=None, Mu0=None) -> Result:
+    """Synchronous GaBP from zero messages (Algorithm 1 step 1) or from P0/Mu0."""
+    M = Matrix(m)
+    b = _f64(b, M.n)
+    P = np.zeros(M.nnz) if P0 is None else _f64(P0, M.nnz).copy()
+    Mu = np.zeros(M.nnz) if Mu0 is None else _f64(Mu0, M.nnz).copy()
+    x, prec = np.empty(M.n), np.empty(M.n)
+    trace = np.full(max_rounds + 1, np.nan)
+    rounds = C.c_int32(0)
+    o = _Opts(algorithm, stop, tol, max_rounds, damping, nthreads)
+    st = _load().orc_solve(C.byref(M.c), _p(b), C.byref(o), _p(P), _p(Mu), _p(x), _p(prec),
+                           C.byref(rounds), _p(trace))
+    t = int(rounds.value)
+    return Result(st, x, prec, t, trace[:t + 1], P, Mu)
+
+
+def refine_solve(m, b, tol=1e-8, inner_tol=1e-5, inner_max=100000, max_restarts=50,
+                 damping=0.0, nthreads=0):
+    """Refinement loop around GaBP (see orc_refine_solve).  Returns
+    (status, x, rounds, restarts, rel_residual)."""
+    M = Matrix(m)
+    b = _f64(b, M.n)
+    x = np.empty(M.n)
+    P, Mu = np.zeros(M.nnz), np.zeros(M.nnz)
+    rounds, restarts, rel = C.c_int32(0), C.c_int32(0), C.c_double(0)
+    st = _load().orc_refine_solve(C.byref(M.c), _p(b), tol, inner_tol, inner_max, max_restarts,
+                                  damping, nthreads, _p(x), _p(P), _p(Mu), C.byref(rounds),
+                                  C.byref(restarts), C.byref(rel))
+    return st, x, int(rounds.value), int(restarts.value), float(rel.value)
+
+
+def residual(m, b, x):
+    """(r = b - A x, ||r||_2)."""
+    M = Matrix(m)
+    b, x = _f64(b, M.n), _f64(x, M.n)
+    r = np.empty(M.n)
+    nrm = _load().orc_residual(C.byref(M.c), _p(b), _p(x), _p(r))
+    return r, float(nrm)
+
+
+def jacobi_variant(m, b, rounds: int):
+    """Proposition GaBPJ: GaBP with zero precision messages and no exclusion of
+    the target; returns the marginal means after each round (list of arrays)."""
+    M = Matrix(m)
+    b = _f64(b, M.n)
+    st, rev, diag = reverse(m)
+    if st != OK:
+        raise ValueError(st)
+    h = np.zeros(M.nnz)
+    out = []
+    for _ in range(rounds):
+        h2, mean = np.empty(M.nnz), np.empty(M.n)
+        _load().orc_jacobi_variant_round(C.byref(M.c), _p(b), _p(rev), _p(diag), _p(h), _p(h2),
+                                         _p(mean))
+        h = h2
+        out.append(mean)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Section VII: symmetric (K+N) x (K+N) system [[I_K, S^T], [S, -Psi]] with
+# right-hand side [0; y]; its first K unknowns solve (S^T S + Psi) x = S^T y
+# for Psi = sigma^2 I_N (the reading taken where the printed dimensions clash).
+# ---------------------------------------------------------------------------
+class _CSRLike:
+    def __init__(self, n, row_ptr, col, val):
+        self.n, self.row_ptr, self.col, self.val = n, row_ptr, col, val
+
+
+def bipartite_system(S: np.ndarray, y: np.ndarray, sigma2: float):
+    """CSR of [[I_K, S^T], [S, -sigma2 I_N]] (zero entries of S dropped) and [0; y]."""
+    S = np.asarray(S, dtype=np.float64)
+    N, K = S.shape
+    n = K + N
+    dense = np.zeros((n, n))
+    dense[:K, :K] = np.eye(K)
+    dense[:K, K:] = S.T
+    dense[K:, :K] = S
+    dense[K:, K:] = -sigma2 * np.eye(N)
+    r, c = np.nonzero(dense)
+    counts = np.bincount(r, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    rhs = np.concatenate([np.zeros(K), np.asarray(y, dtype=np.float64)])
+    return _CSRLike(n, row_ptr, c.astype(np.int32), dense[r, c]), rhs

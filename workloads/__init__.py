@@ -1,0 +1,337 @@
+"""Seeded synthetic inputs for the GaBP solver (Shental, Bickson et al.,
+"Gaussian Belief Propagation for Solving Systems of Linear Equations").
+
+This module builds linear systems ``A x = b`` shaped like the paper's
+workloads and holds none of the method's arithmetic: no message, cavity,
+marginal or residual is computed here.  Both the FP64 CPU oracle and the HIP
+path receive their inputs from these functions, so the two sides see the same
+numbers without sharing any solver code.
+
+Matrices are returned in CSR form with the full symmetric pattern including
+the diagonal: ``row_ptr`` int64 (n+1), ``col`` int32 (nnz, sorted within each
+row), ``val`` float64 (nnz).  Random numbers come from ``numpy.random.Generator``
+(PCG64) keyed by an explicit seed, so every input is reproducible.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "CSR", "csr_from_coo", "csr_from_dense", "dense_from_csr",
+    "poisson2d", "poisson3d", "poisson3d_varcoef", "grf_field",
+    "sdd_random", "random_tree", "detection_batch", "DetectionBatch",
+    "uniform_b", "normal_b", "tree_diameter",
+]
+
+
+@dataclass
+class CSR:
+    """Full symmetric CSR matrix (diagonal stored explicitly)."""
+    n: int
+    row_ptr: np.ndarray  # int64 [n+1]
+    col: np.ndarray      # int32 [nnz]
+    val: np.ndarray      # float64 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    @property
+    def directed_edges(self) -> int:
+        """Number of off-diagonal stored entries = directed messages per sweep."""
+        rows = np.repeat(np.arange(self.n), np.diff(self.row_ptr))
+        return int(np.count_nonzero(rows != self.col))
+
+
+def csr_from_coo(n: int, rows, cols, vals) -> CSR:
+    """Sort (row, col) pairs and pack them as CSR.  Duplicates are an error."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    key = rows * n + cols
+    order = np.argsort(key, kind="stable")
+    key = key[order]
+    if key.size > 1 and np.any(key[1:] == key[:-1]):
+        raise ValueError("duplicate (row, col) entry")
+    rows = rows[order]
+    counts = np.bincount(rows, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return CSR(n, row_ptr, cols[order].astype(np.int32), vals[order])
+
+
+def csr_from_dense(a: np.ndarray) -> CSR:
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[0]
+    r, c = np.nonzero(a)
+    return csr_from_coo(n, r, c, a[r, c])
+
+
+def dense_from_csr(m: CSR) -> np.ndarray:
+    a = np.zeros((m.n, m.n))
+    rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+    a[rows, m.col] = m.val
+    return a
+
+
+def uniform_b(n: int, seed: int) -> np.ndarray:
+    """b ~ U[-1, 1]."""
+    return np.random.default_rng([seed, 0xB]).uniform(-1.0, 1.0, n)
+
+
+def normal_b(n: int, seed: int) -> np.ndarray:
+    """b ~ N(0, 1)."""
+    return np.random.default_rng([seed, 0xB]).standard_normal(n)
+
+
+# ---------------------------------------------------------------------------
+# Poisson discretisations (section IX: 5-point stencil, Dirichlet 0, natural
+# row ordering left->right then bottom->up; extended to 7 points in 3-D).
+# ---------------------------------------------------------------------------
+def poisson2d(p: int, diag: float = 4.0, off: float = -1.0) -> CSR:
+    """p x p interior grid; unknown U(i, j) has index (i-1) + (j-1) p."""
+    idx = np.arange(p * p).reshape(p, p)  # [j, i]
+    rows, cols = [idx.ravel()], [idx.ravel()]
+    vals = [np.full(p * p, diag)]
+    for a, b in ((idx[:, :-1], idx[:, 1:]), (idx[:-1, :], idx[1:, :])):
+        for u, v in ((a, b), (b, a)):
+            rows.append(u.ravel()); cols.append(v.ravel())
+            vals.append(np.full(u.size, off))
+    return csr_from_coo(p * p, np.concatenate(rows), np.concatenate(cols),
+                        np.concatenate(vals))
+
+
+def _grid_faces(nx: int, ny: int, nz: int):
+    """Interior faces of an nx x ny x nz grid as (u, v, axis) index arrays,
+    with node index x + nx (y + ny z)."""
+    idx = np.arange(nx * ny * nz).reshape(nz, ny, nx)
+    out = []
+    for axis, (a, b) in enumerate(((idx[:, :, :-1], idx[:, :, 1:]),
+                                   (idx[:, :-1, :], idx[:, 1:, :]),
+                                   (idx[:-1, :, :], idx[1:, :, :]))):
+        out.append((a.ravel(), b.ravel(), axis))
+    return out
+
+
+def poisson3d(nx: int, ny: int, nz: int, shift: float = 0.0) -> CSR:
+    """Constant-coefficient 7-point Laplacian, Dirichlet 0: A_ii = 6 + shift,
+    A_ij = -1 for face neighbours."""
+    n = nx * ny * nz
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.full(n, 6.0 + shift)]
+    for u, v, _ in _grid_faces(nx, ny, nz):
+        rows += [u, v]; cols += [v, u]; vals += [np.full(u.size, -1.0)] * 2
+    return csr_from_coo(n, np.concatenate(rows), np.concatenate(cols),
+                        np.concatenate(vals))
+
+
+def grf_field(nx: int, ny: int, nz: int, seed: int, ell: float = 8.0,
+              std: float = 1.0) -> np.ndarray:
+    """Smooth Gaussian random field G[z, y, x]: white noise convolved
+    (periodically, by FFT) with a Gaussian kernel of width ell / sqrt(2), which
+    gives correlation exp(-r^2 / (2 ell^2)); standardised to mean 0, std ``std``."""
+    rng = np.random.default_rng([seed, 0x6F])
+    w = rng.standard_normal((nz, ny, nx))
+    sk = ell / np.sqrt(2.0)
+    freqs = [np.fft.fftfreq(m) for m in (nz, ny, nx)]
+    kz, ky, kx = np.meshgrid(*freqs, indexing="ij")
+    # Fourier transform of a unit-sum Gaussian kernel with std sk (cells)
+    g = np.exp(-2.0 * np.pi ** 2 * sk ** 2 * (kx ** 2 + ky ** 2 + kz ** 2))
+    f = np.fft.ifftn(np.fft.fftn(w) * g).real
+    f -= f.mean()
+    return f * (std / f.std())
+
+
+def poisson3d_varcoef(nx: int, ny: int, nz: int, seed: int, ell: float = 8.0,
+                      std: float = 1.0):
+    """Variable-coefficient 7-point operator -div(k grad u), Dirichlet 0.
+
+    k = exp(G) per cell with G = ``grf_field``; an interior face carries the
+    harmonic mean 2 k_i k_j / (k_i + k_j); a boundary face (to the Dirichlet
+    ghost) carries k_i.  A_ij = -k_face, A_ii = sum of the node's 6 face values.
+
+    Returns (CSR, faces) where faces = dict with float64 arrays
+    ``diag`` [n] and ``cx``, ``cy``, ``cz`` holding the coupling A_ij between
+    node i and its +x / +y / +z neighbour (0 on the last plane of each axis).
+    """
+    k = np.exp(grf_field(nx, ny, nz, seed, ell, std))  # [z, y, x]
+    diag = np.zeros((nz, ny, nx))
+    cpl = []
+    for axis in (2, 1, 0):  # x, y, z in array-axis terms
+        lo = [slice(None)] * 3; hi = [slice(None)] * 3
+        lo[axis] = slice(0, -1); hi[axis] = slice(1, None)
+        ka, kb = k[tuple(lo)], k[tuple(hi)]
+        kf = 2.0 * ka * kb / (ka + kb)
+        c = np.zeros_like(k)
+        c[tuple(lo)] = -kf
+        cpl.append(c)
+        diag[tuple(lo)] += kf
+        diag[tuple(hi)] += kf
+        # boundary faces on both ends of this axis
+        first = [slice(None)] * 3; last = [slice(None)] * 3
+        first[axis] = 0; last[axis] = -1
+        diag[tuple(first)] += k[tuple(first)]
+        diag[tuple(last)] += k[tuple(last)]
+    n = nx * ny * nz
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [diag.ravel()]
+    for (u, v, axis), c in zip(_grid_faces(nx, ny, nz), cpl):
+        cv = c.ravel()[u]
+        rows += [u, v]; cols += [v, u]; vals += [cv, cv]
+    m = csr_from_coo(n, np.concatenate(rows), np.concatenate(cols),
+                     np.concatenate(vals))
+    faces = {"diag": diag.ravel().copy(), "cx": cpl[0].ravel().copy(),
+             "cy": cpl[1].ravel().copy(), "cz": cpl[2].ravel().copy()}
+    return m, faces
+
+
+# ---------------------------------------------------------------------------
+# Random sparse symmetric strictly diagonally dominant matrix.
+# ---------------------------------------------------------------------------
+def sdd_random(n: int, seed: int, partners: int = 4, factor: float = 1.1) -> CSR:
+    """Each node draws ``partners`` distinct partners j != i uniformly; the
+    union with the transpose gives the pattern (about 2 * partners off-diagonal
+    entries per row, at least ``partners``).  One N(0, 1) value per undirected
+    pair; A_ii = factor * sum_j |A_ij|."""
+    rng = np.random.default_rng([seed, 0x5DD])
+    i = np.repeat(np.arange(n, dtype=np.int64), partners)
+    j = rng.integers(0, n - 1, size=n * partners, dtype=np.int64)
+    j += (j >= i)  # skip the node itself
+    # redraw partners repeated within a row until each row's draws are distinct
+    while True:
+        jj = j.reshape(n, partners)
+        s = np.sort(jj, axis=1)
+        dup_rows = np.nonzero(np.any(s[:, 1:] == s[:, :-1], axis=1))[0]
+        if dup_rows.size == 0:
+            break
+        for r in dup_rows:
+            row = jj[r]
+            seen = set()
+            for t in range(partners):
+                while row[t] in seen:
+                    v = int(rng.integers(0, n - 1))
+                    row[t] = v + (v >= r)
+                seen.add(int(row[t]))
+        j = jj.ravel()
+    lo = np.minimum(i, j); hi = np.maximum(i, j)
+    pairs = np.unique(lo * n + hi)
+    u = pairs // n; v = pairs % n
+    w = rng.standard_normal(pairs.size)
+    absum = np.bincount(u, np.abs(w), minlength=n) + np.bincount(v, np.abs(w), minlength=n)
+    rows = np.concatenate([u, v, np.arange(n)])
+    cols = np.concatenate([v, u, np.arange(n)])
+    vals = np.concatenate([w, w, factor * absum])
+    return csr_from_coo(n, rows, cols, vals)
+
+
+# ---------------------------------------------------------------------------
+# Random trees (Pruefer sequences) with nonzero elimination pivots.
+# ---------------------------------------------------------------------------
+def random_tree(n: int, seed: int, dominant: bool = True) -> CSR:
+    """Random labelled tree on n >= 2 nodes from a Pruefer sequence.
+
+    Off-diagonals ~ N(0, 1).  ``dominant``: A_ii = +-(1 + sum|A_ij|) U[0.5, 1.5]
+    with random signs (indefinite, usually diagonally dominant); otherwise
+    A_ii = +-U[0.5, 1.5] (not walk-summable in general)."""
+    rng = np.random.default_rng([seed, 0x7EE])
+    if n == 2:
+        edges = [(0, 1)]
+    else:
+        seq = rng.integers(0, n, size=n - 2)
+        degree = np.ones(n, dtype=np.int64)
+        np.add.at(degree, seq, 1)
+        import heapq
+        leaves = [k for k in range(n) if degree[k] == 1]
+        heapq.heapify(leaves)
+        edges = []
+        for s in seq:
+            leaf = heapq.heappop(leaves)
+            edges.append((leaf, int(s)))
+            degree[s] -= 1
+            if degree[s] == 1:
+                heapq.heappush(leaves, int(s))
+        a, b = heapq.heappop(leaves), heapq.heappop(leaves)
+        edges.append((a, b))
+    e = np.array(edges, dtype=np.int64)
+    w = rng.standard_normal(len(edges))
+    absum = np.bincount(e[:, 0], np.abs(w), minlength=n) + np.bincount(e[:, 1], np.abs(w), minlength=n)
+    sign = rng.choice([-1.0, 1.0], size=n)
+    mag = rng.uniform(0.5, 1.5, size=n)
+    d = sign * mag * ((1.0 + absum) if dominant else 1.0)
+    rows = np.concatenate([e[:, 0], e[:, 1], np.arange(n)])
+    cols = np.concatenate([e[:, 1], e[:, 0], np.arange(n)])
+    return csr_from_coo(n, rows, cols, np.concatenate([w, w, d]))
+
+
+def tree_diameter(m: CSR) -> int:
+    """Longest shortest path (in edges) of a tree, by two breadth-first searches."""
+    def bfs(src):
+        dist = np.full(m.n, -1); dist[src] = 0; q = [src]
+        for u in q:
+            for v in m.col[m.row_ptr[u]:m.row_ptr[u + 1]]:
+                if v != u and dist[v] < 0:
+                    dist[v] = dist[u] + 1; q.append(int(v))
+        far = int(np.argmax(dist))
+        return far, int(dist[far])
+    far, _ = bfs(0)
+    return bfs(far)[1]
+
+
+# ---------------------------------------------------------------------------
+# Linear detection (section VIII-B): synchronous CDMA with random spreading.
+# ---------------------------------------------------------------------------
+@dataclass
+class DetectionBatch:
+    """Packed detection instances.  Instance t has K[t] users and N[t] chips;
+    its spreading matrix S_t (N x K, row-major) sits at S[s_off[t]:s_off[t+1]],
+    its chip observations y_t (N) at y[y_off[t]:y_off[t+1]], its transmitted
+    symbols x_t (K, +-1) at x[x_off[t]:x_off[t+1]]."""
+    K: np.ndarray
+    N: np.ndarray
+    sigma2: np.ndarray
+    S: np.ndarray
+    y: np.ndarray
+    x: np.ndarray
+    s_off: np.ndarray
+    y_off: np.ndarray
+    x_off: np.ndarray
+
+    @property
+    def batch(self) -> int:
+        return int(self.K.size)
+
+    def instance(self, t: int):
+        K, N = int(self.K[t]), int(self.N[t])
+        S = self.S[self.s_off[t]:self.s_off[t + 1]].reshape(N, K)
+        return (S, self.y[self.y_off[t]:self.y_off[t + 1]],
+                self.x[self.x_off[t]:self.x_off[t + 1]], float(self.sigma2[t]))
+
+    def mmse_system(self, t: int):
+        """Dense MMSE detector system: A = S^T S + sigma^2 I, b = S^T y."""
+        S, y, _, s2 = self.instance(t)
+        return S.T @ S + s2 * np.eye(S.shape[1]), S.T @ y
+
+
+def detection_batch(batch: int, seed: int, kmin: int = 16, kmax: int = 256,
+                    load: float = 0.5, snr_db: float = 10.0) -> DetectionBatch:
+    """K ~ U{kmin..kmax}, N = K / load chips, S entries +-1/sqrt(N) iid (unit-norm
+    codes), x in {+-1}^K, y = S x + n with n ~ N(0, sigma^2 I),
+    sigma^2 = 10^(-snr_db/10)."""
+    rng = np.random.default_rng([seed, 0xDE7])
+    K = rng.integers(kmin, kmax + 1, size=batch).astype(np.int64)
+    N = np.ceil(K / load).astype(np.int64)
+    s2 = np.full(batch, 10.0 ** (-snr_db / 10.0))
+    s_off = np.zeros(batch + 1, dtype=np.int64); np.cumsum(N * K, out=s_off[1:])
+    y_off = np.zeros(batch + 1, dtype=np.int64); np.cumsum(N, out=y_off[1:])
+    x_off = np.zeros(batch + 1, dtype=np.int64); np.cumsum(K, out=x_off[1:])
+    S = np.empty(int(s_off[-1])); y = np.empty(int(y_off[-1])); x = np.empty(int(x_off[-1]))
+    for t in range(batch):
+        r = np.random.default_rng([seed, 0xDE7, t])
+        k, nn = int(K[t]), int(N[t])
+        St = r.choice([-1.0, 1.0], size=(nn, k)) / np.sqrt(nn)
+        xt = r.choice([-1.0, 1.0], size=k)
+        yt = St @ xt + np.sqrt(s2[t]) * r.standard_normal(nn)
+        S[s_off[t]:s_off[t + 1]] = St.ravel()
+        y[y_off[t]:y_off[t + 1]] = yt
+        x[x_off[t]:x_off[t + 1]] = xt
+    return DetectionBatch(K, N, s2, S, y, x, s_off, y_off, x_off)
