@@ -1,0 +1,157 @@
+/*
+ * gabp.h -- C ABI of the MI355X (gfx950) Gaussian belief propagation solver.
+ *
+ * Solves A x = b for a square symmetric A (Assumption 1, section II-C of
+ * Shental, Bickson et al., "Gaussian Belief Propagation for Solving Systems of
+ * Linear Equations: Theory and Application") by synchronous GaBP: the
+ * solution is the vector of marginal means of the Gaussian N(A^{-1} b, A^{-1})
+ * (Proposition 3, section III-A).  Every sweep runs the broadcast form of
+ * Algorithm 2 (section V): per node the aggregate precision and information
+ * of all incoming messages, then per directed edge the new message after
+ * subtracting the reverse one (eq. prec_message / mean_message of III-C).
+ * Positive definiteness is NOT required (remark of section III-A); the
+ * solver never clamps precisions.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked "device" are HIP device allocations owned by the caller;
+ *     the library never frees or retains them beyond the call, except that a
+ *     plan keeps reading the CSR arrays it was created from until it is
+ *     destroyed.  Pointers marked "host" are ordinary host memory.
+ *   - The return value is a gabp_status.  Nothing is thrown and nothing aborts.
+ *   - All device work is ordered on the given stream (NULL = default stream);
+ *     a call returns after its results are complete and visible.
+ *   - Calls on different plans and different streams are independent; calls
+ *     on one plan must not overlap.
+ *   - On GABP_NOT_CONVERGED the output x holds the last iterate; on a negative
+ *     status the outputs are unspecified.
+ */
+#ifndef GABP_H
+#define GABP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GABP_OK = 0,                 /* converged to the requested tolerance */
+  GABP_NOT_CONVERGED = 1,      /* sweep or restart budget exhausted */
+  GABP_ERR_ARG = -1,           /* bad argument: null pointer, size, unsorted or
+                                  out-of-range column, non-finite input */
+  GABP_ERR_NOT_SYMMETRIC = -2, /* pattern or values of A are not symmetric */
+  GABP_ERR_ZERO_DIAG = -3,     /* missing or zero diagonal (mu_ii = b_i / A_ii
+                                  undefined, Algorithm 1 step 1) */
+  GABP_ERR_BREAKDOWN = -4,     /* a cavity or marginal precision became exactly
+                                  zero (a zero elimination pivot, Proposition
+                                  GaBPGE) */
+  GABP_ERR_DIVERGED = -5,      /* a non-finite message or mean appeared */
+  GABP_ERR_HIP = -6,           /* a HIP runtime call failed */
+  GABP_ERR_NOMEM = -7,         /* device or pinned allocation failed */
+  GABP_ERR_UNSUPPORTED = -8    /* size beyond the library's limits (e.g. more
+                                  than 2^31 - 1 directed edges) */
+} gabp_status;
+
+/* Sparse symmetric matrix, full pattern (both triangles) including the
+ * diagonal.  Each row's columns are strictly increasing.  The graph of
+ * section II-B has an edge {i, j} for every stored A_ij != 0, i != j; every
+ * stored off-diagonal entry is one directed message per sweep.  */
+typedef struct {
+  int32_t n;                 /* unknowns, >= 0 */
+  int64_t nnz;               /* stored entries = row_ptr[n] */
+  const int64_t *row_ptr;    /* device [n+1] */
+  const int32_t *col;        /* device [nnz] */
+  const double *val;         /* device [nnz] */
+} gabp_csr;
+
+typedef struct {
+  int32_t msg_fp32;    /* 1: messages and node sums in FP32, with the residual
+                          b - A x and the correction restarts in FP64;
+                          0: everything in FP64 */
+  double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol (FP64) */
+  int32_t max_sweeps;  /* budget of synchronous sweeps over all restarts */
+  int32_t check_every; /* sweeps between checks of the marginal means */
+  double damping;      /* alpha in [0,1): P <- alpha P_old + (1-alpha) P_new
+                          and the same for the information h = P mu */
+  double inner_tol;    /* an inner solve ends when the means move by at most
+                          inner_tol * max|x| over check_every sweeps */
+  int32_t max_restarts;/* refinement restarts (mean messages zeroed,
+                          precision messages kept) */
+  int32_t group;       /* lanes per row in the sweep: 0 = chosen from the
+                          degree profile, else 4, 8, 16, 32 or 64 */
+} gabp_opts;
+
+typedef struct {
+  int32_t status;          /* gabp_status of the solve */
+  int32_t sweeps;          /* synchronous sweeps run (all restarts) */
+  int32_t restarts;        /* refinement restarts taken */
+  int32_t checks;          /* mean checks read back by the host */
+  double rel_residual;     /* final ||b - A x||_2 / ||b||_2, FP64 */
+  double residual_per_eq;  /* ||b - A x||_2 / n (section II-A norm) */
+  double seconds;          /* host wall time of the solve */
+  double sweep_ms;         /* summed device time of the sweep launches */
+  int64_t edges;           /* directed off-diagonal messages per sweep */
+  double edge_updates_per_s; /* edges * sweeps / seconds */
+} gabp_stats;
+
+/* Fills o with the defaults: FP32 messages, tol 1e-8, 20000 sweeps, checks
+ * every 4 sweeps, no damping, inner_tol 1e-6, 30 restarts, group 0. */
+void gabp_default_opts(gabp_opts *o);
+
+/* One-call solve (plan create + solve + destroy).
+ *   A        device CSR as above.
+ *   b        device [n] right-hand side.
+ *   x        device [n] output, marginal means (Algorithm 1 steps 4-5).
+ *   marg_prec  device [n] or NULL: marginal precisions P_i = A_ii + sum_k P_ki
+ *            of the final messages (exact only on trees, section IV).
+ *   o        host options or NULL for the defaults.
+ *   st       host stats or NULL. */
+int gabp_solve(const gabp_csr *A, const double *b, double *x, double *marg_prec,
+               const gabp_opts *o, gabp_stats *st, hipStream_t stream);
+
+/* FP64 residual r = b - A x (section II-A, sign flipped) and its relative norm.
+ *   r        device [n] or NULL.
+ *   rel_norm host: ||r||_2 / ||b||_2 (||r||_2 if b = 0).
+ * Deterministic: fixed-order block reduction, no floating-point atomics. */
+int gabp_residual(const gabp_csr *A, const double *b, const double *x, double *r,
+                  double *rel_norm, hipStream_t stream);
+
+/* ---- Plans: reuse the validated graph, reverse-edge index and buffers. ---- */
+typedef struct gabp_plan gabp_plan;
+
+/* Validates A on the device (sorted in-range columns, nonzero diagonal,
+ * symmetric pattern and values), builds the off-diagonal edge arrays and the
+ * reverse-edge index rev[e(i->j)] = e(j->i), and allocates the message
+ * buffers.  A's arrays must stay valid and unchanged until destroy. */
+int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan,
+                     hipStream_t stream);
+int gabp_plan_destroy(gabp_plan *plan);
+
+/* Solve A x = b from zero messages (Algorithm 1 step 1) with the plan's
+ * options; arguments as for gabp_solve. */
+int gabp_plan_solve(gabp_plan *plan, const double *b, double *x, double *marg_prec,
+                    gabp_stats *st, hipStream_t stream);
+
+/* Trajectory access (parity checks, checkpoint and resume).
+ * reset:     zero all messages and take b (device [n]) as the right-hand side.
+ * sweeps:    run exactly `count` synchronous sweeps (no checks, no restarts).
+ * marginals: mean (device [n]) and precision (device [n] or NULL) from the
+ *            current messages.
+ * get/set_messages: P and h = P * mu of every directed message i->j at the
+ *            CSR slot of A_ij (device [nnz] each, FP64; diagonal slots read
+ *            as 0 and are ignored on set). */
+int gabp_plan_reset(gabp_plan *plan, const double *b, hipStream_t stream);
+int gabp_plan_sweeps(gabp_plan *plan, int32_t count, hipStream_t stream);
+int gabp_plan_marginals(gabp_plan *plan, double *mean, double *prec, hipStream_t stream);
+int gabp_plan_get_messages(gabp_plan *plan, double *P, double *h, hipStream_t stream);
+int gabp_plan_set_messages(gabp_plan *plan, const double *P, const double *h,
+                           hipStream_t stream);
+
+/* Library version string. */
+const char *gabp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GABP_H */

@@ -1,0 +1,17 @@
+"""MI355X (gfx950) Gaussian belief propagation solver for A x = b.
+
+Thin Python binding over the C ABI of ``libgabp.so`` (declared in
+``include/gabp.h``).  Every function here only marshals arguments: device
+tensors become raw pointers, the current torch stream becomes the HIP stream,
+and the C status codes come back unchanged.  All arithmetic runs in the HIP
+kernels of the library; there is no CPU fallback, and importing this package
+fails if the library has not been built.
+"""
+from ._abi import (  # noqa: F401
+    GABP_OK, GABP_NOT_CONVERGED, GABP_ERR_ARG, GABP_ERR_NOT_SYMMETRIC, GABP_ERR_ZERO_DIAG,
+    GABP_ERR_BREAKDOWN, GABP_ERR_DIVERGED, GABP_ERR_HIP, GABP_ERR_NOMEM, GABP_ERR_UNSUPPORTED,
+    LIB_PATH, DeviceCSR, GabpError, Opts, Stats, lib, status_name,
+    gabp_default_opts, gabp_solve, gabp_residual, gabp_plan_create, gabp_plan_destroy,
+    gabp_plan_solve, gabp_plan_reset, gabp_plan_sweeps, gabp_plan_marginals,
+    gabp_plan_get_messages, gabp_plan_set_messages, gabp_version,
+)

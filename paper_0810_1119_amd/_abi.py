@@ -1,0 +1,217 @@
+"""ctypes declarations mirroring include/gabp.h and argument marshalling.
+
+Device arrays are torch tensors on the GPU; their ``data_ptr()`` is passed as
+the C pointer.  The HIP stream is torch's current stream unless one is given.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgabp.so")
+
+GABP_OK = 0
+GABP_NOT_CONVERGED = 1
+GABP_ERR_ARG = -1
+GABP_ERR_NOT_SYMMETRIC = -2
+GABP_ERR_ZERO_DIAG = -3
+GABP_ERR_BREAKDOWN = -4
+GABP_ERR_DIVERGED = -5
+GABP_ERR_HIP = -6
+GABP_ERR_NOMEM = -7
+GABP_ERR_UNSUPPORTED = -8
+
+_NAMES = {v: k for k, v in dict(globals()).items() if k.startswith("GABP_") and isinstance(v, int)}
+
+
+def status_name(code: int) -> str:
+    return _NAMES.get(int(code), f"UNKNOWN({code})")
+
+
+class GabpError(RuntimeError):
+    def __init__(self, where: str, code: int):
+        super().__init__(f"{where} failed: {status_name(code)}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+lib = C.CDLL(LIB_PATH)
+
+
+class _Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("msg_fp32", C.c_int32), ("tol", C.c_double), ("max_sweeps", C.c_int32),
+                ("check_every", C.c_int32), ("damping", C.c_double), ("inner_tol", C.c_double),
+                ("max_restarts", C.c_int32), ("group", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("sweeps", C.c_int32), ("restarts", C.c_int32),
+                ("checks", C.c_int32), ("rel_residual", C.c_double),
+                ("residual_per_eq", C.c_double), ("seconds", C.c_double),
+                ("sweep_ms", C.c_double), ("edges", C.c_int64),
+                ("edge_updates_per_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp, _i32 = C.c_void_p, C.c_int32
+_sig = {
+    "gabp_default_opts": (None, [C.POINTER(Opts)]),
+    "gabp_solve": (C.c_int, [C.POINTER(_Csr), _vp, _vp, _vp, C.POINTER(Opts), C.POINTER(Stats), _vp]),
+    "gabp_residual": (C.c_int, [C.POINTER(_Csr), _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
+    "gabp_plan_create": (C.c_int, [C.POINTER(_Csr), C.POINTER(Opts), C.POINTER(_vp), _vp]),
+    "gabp_plan_destroy": (C.c_int, [_vp]),
+    "gabp_plan_solve": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(Stats), _vp]),
+    "gabp_plan_reset": (C.c_int, [_vp, _vp, _vp]),
+    "gabp_plan_sweeps": (C.c_int, [_vp, _i32, _vp]),
+    "gabp_plan_marginals": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "gabp_plan_get_messages": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "gabp_plan_set_messages": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "gabp_version": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _check_f64(t, n, name):
+    import torch
+    if t is None:
+        return
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: expected a contiguous float64 CUDA tensor of {n} elements")
+
+
+@dataclass
+class DeviceCSR:
+    """Full symmetric CSR matrix resident on the GPU (int64 row_ptr, int32 col,
+    float64 val), and the gabp_csr view of it."""
+    n: int
+    row_ptr: object
+    col: object
+    val: object
+
+    @classmethod
+    def from_host(cls, m, device="cuda"):
+        import numpy as np
+        import torch
+        rp = torch.from_numpy(np.ascontiguousarray(m.row_ptr, dtype=np.int64)).to(device)
+        col = torch.from_numpy(np.ascontiguousarray(m.col, dtype=np.int32)).to(device)
+        val = torch.from_numpy(np.ascontiguousarray(m.val, dtype=np.float64)).to(device)
+        return cls(int(m.n), rp, col, val)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def c(self) -> _Csr:
+        return _Csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val))
+
+
+def gabp_default_opts(**overrides) -> Opts:
+    o = Opts()
+    lib.gabp_default_opts(C.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def gabp_version() -> str:
+    return lib.gabp_version().decode()
+
+
+def gabp_solve(A: DeviceCSR, b, x, marg_prec=None, opts: Opts | None = None, stream=None):
+    """Returns (status, Stats)."""
+    _check_f64(b, A.n, "b"); _check_f64(x, A.n, "x"); _check_f64(marg_prec, A.n, "marg_prec")
+    st = Stats()
+    a = A.c()
+    rc = lib.gabp_solve(C.byref(a), _ptr(b), _ptr(x), _ptr(marg_prec),
+                        C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
+    return rc, st
+
+
+def gabp_residual(A: DeviceCSR, b, x, r=None, stream=None):
+    """Returns (status, ||b - A x|| / ||b||)."""
+    _check_f64(b, A.n, "b"); _check_f64(x, A.n, "x"); _check_f64(r, A.n, "r")
+    rel = C.c_double(0.0)
+    a = A.c()
+    rc = lib.gabp_residual(C.byref(a), _ptr(b), _ptr(x), _ptr(r), C.byref(rel), _stream(stream))
+    return rc, rel.value
+
+
+def gabp_plan_create(A: DeviceCSR, opts: Opts | None = None, stream=None):
+    """Returns (status, plan handle).  The handle keeps A alive."""
+    h = C.c_void_p()
+    a = A.c()
+    rc = lib.gabp_plan_create(C.byref(a), C.byref(opts) if opts is not None else None,
+                              C.byref(h), _stream(stream))
+    return rc, (_PlanHandle(h.value, A) if rc == GABP_OK else None)
+
+
+class _PlanHandle:
+    def __init__(self, ptr, A):
+        self.ptr, self.A = ptr, A
+
+
+def gabp_plan_destroy(plan) -> int:
+    if plan is None or plan.ptr is None:
+        return GABP_ERR_ARG
+    rc = lib.gabp_plan_destroy(plan.ptr)
+    plan.ptr = None
+    return rc
+
+
+def gabp_plan_solve(plan, b, x, marg_prec=None, stream=None):
+    n = plan.A.n
+    _check_f64(b, n, "b"); _check_f64(x, n, "x"); _check_f64(marg_prec, n, "marg_prec")
+    st = Stats()
+    rc = lib.gabp_plan_solve(plan.ptr, _ptr(b), _ptr(x), _ptr(marg_prec), C.byref(st),
+                             _stream(stream))
+    return rc, st
+
+
+def gabp_plan_reset(plan, b, stream=None) -> int:
+    _check_f64(b, plan.A.n, "b")
+    return lib.gabp_plan_reset(plan.ptr, _ptr(b), _stream(stream))
+
+
+def gabp_plan_sweeps(plan, count: int, stream=None) -> int:
+    return lib.gabp_plan_sweeps(plan.ptr, int(count), _stream(stream))
+
+
+def gabp_plan_marginals(plan, mean, prec=None, stream=None) -> int:
+    _check_f64(mean, plan.A.n, "mean"); _check_f64(prec, plan.A.n, "prec")
+    return lib.gabp_plan_marginals(plan.ptr, _ptr(mean), _ptr(prec), _stream(stream))
+
+
+def gabp_plan_get_messages(plan, P, h, stream=None) -> int:
+    _check_f64(P, plan.A.nnz, "P"); _check_f64(h, plan.A.nnz, "h")
+    return lib.gabp_plan_get_messages(plan.ptr, _ptr(P), _ptr(h), _stream(stream))
+
+
+def gabp_plan_set_messages(plan, P, h, stream=None) -> int:
+    _check_f64(P, plan.A.nnz, "P"); _check_f64(h, plan.A.nnz, "h")
+    return lib.gabp_plan_set_messages(plan.ptr, _ptr(P), _ptr(h), _stream(stream))

@@ -1,0 +1,656 @@
+// GaBP on a general sparse symmetric matrix (CSR), gfx950.
+//
+// Edge layout: the off-diagonal entries of row i occupy slots
+// oprt[i] .. oprt[i+1]-1 in column order; slot e = (i -> j) holds the message
+// node i sends to node j as a (P, h) pair, h = P * mu, and rev[e] is the slot
+// of (j -> i).  A sweep is Algorithm 2 of the paper (section V) in the
+// information parametrisation:
+//   S_i = A_ii + sum_k P_ki,   H_i = b_i + sum_k h_ki          (node aggregate)
+//   P_ij = -A_ij^2 / (S_i - P_ji)                              (eq. prec_message)
+//   h_ij = -A_ij (H_i - h_ji) / (S_i - P_ji)                   (eq. mean_message times P_ij)
+// because P_ii mu_ii = b_i (eq. PhiGauss) and mu_ij = h_ij / P_ij; the
+// marginal mean is x_i = H_i / S_i (Algorithm 1 step 4).  In-messages are
+// gathered through rev[] (8 or 16 bytes each); out-messages are written
+// coalesced in the row's own slots.  Two buffers give the synchronous
+// (flooding) schedule of section III-C.
+#include "gabp_internal.h"
+
+namespace gabp {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// plan build
+// ---------------------------------------------------------------------------
+__global__ void k_plan_rows(int n, int64_t nnz, const int64_t *__restrict__ rp,
+                            const int32_t *__restrict__ col, const double *__restrict__ val,
+                            int64_t *__restrict__ deg, int64_t *__restrict__ diagpos,
+                            uint32_t *__restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t b = rp[i], e = rp[i + 1];
+  if (b < 0 || e < b || e > nnz) {
+    deg[i] = 0;
+    diagpos[i] = -1;
+    atomicOr(flags, FLAG_ARG);
+    return;
+  }
+  uint32_t f = 0;
+  int64_t dp = -1, d = 0;
+  int32_t prev = -1;
+  for (int64_t k = b; k < e; ++k) {
+    const int32_t j = col[k];
+    if (j < 0 || j >= n || j <= prev) f |= FLAG_ARG;
+    prev = j;
+    if (!isfinite(val[k])) f |= FLAG_ARG;
+    if (j == i) dp = k;
+    else ++d;
+  }
+  if (dp < 0 || val[dp] == 0.0) f |= FLAG_ZERO_DIAG;
+  deg[i] = d;
+  diagpos[i] = dp;
+  if (f) atomicOr(flags, f);
+}
+
+hipError_t launch_plan_rows(int n, int64_t nnz, const int64_t *rp, const int32_t *col,
+                            const double *val, int64_t *deg, int64_t *diagpos, uint32_t *flags,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan_rows, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, nnz,
+                     rp, col, val, deg, diagpos, flags);
+  return hipGetLastError();
+}
+
+// Exclusive scan, 1024 items per block (256 threads x 4), block totals scanned
+// recursively.
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ void k_scan_tile(const int64_t *__restrict__ in, int64_t *__restrict__ out, int64_t n,
+                            int64_t *__restrict__ tile_sum) {
+  __shared__ int64_t sh[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t run = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    v[k] = (idx < n) ? in[idx] : 0;
+    run += v[k];
+  }
+  sh[threadIdx.x] = run;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread sums
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int64_t add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t pre = sh[threadIdx.x] - run;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    if (idx < n) out[idx] = pre;
+    pre += v[k];
+  }
+  if (threadIdx.x == kBlock - 1) tile_sum[blockIdx.x] = sh[kBlock - 1];
+}
+
+__global__ void k_scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ off) {
+  const int64_t idx = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+  const int64_t add = off[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t j = idx + (int64_t)k * kBlock;
+    if (j < n) out[j] += add;
+  }
+}
+
+// Scratch of launch_scan: the padded copy of the input (n + 1 values), then
+// per recursion level the tile sums and their scan (2 * tiles + 1 values).
+size_t scan_tmp_elems(int64_t n) {
+  size_t total = (size_t)(n + 1);
+  int64_t m = n + 1;
+  while (true) {
+    const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+    total += 2 * (size_t)tiles + 1;
+    if (tiles <= 1) break;
+    m = tiles;
+  }
+  return total + 4;
+}
+
+// out[0..m) = exclusive scan of in[0..m); tmp holds the tile sums, their scan
+// and the scratch of the deeper levels.
+static hipError_t scan_rec(const int64_t *in, int64_t *out, int64_t m, int64_t *tmp,
+                           hipStream_t s) {
+  const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+  int64_t *tsum = tmp;
+  int64_t *tscan = tmp + tiles;
+  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)tiles), dim3(kBlock), 0, s, in, out, m, tsum);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || tiles == 1) return err;
+  err = scan_rec(tsum, tscan, tiles, tmp + 2 * tiles + 1, s);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(kBlock), 0, s, out, m, tscan);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_pad(const int64_t *__restrict__ in, int64_t *__restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+  else if (i == n) out[i] = 0;
+}
+
+hipError_t launch_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s) {
+  // scan n+1 values (the last one zero) so that out[n] is the total; the
+  // padded input is staged in `out` itself, then scanned out of place into tmp
+  // and copied back.
+  int64_t *pad = tmp;
+  int64_t *work = tmp + (n + 1);
+  hipLaunchKernelGGL(k_copy_pad, dim3((unsigned)((n + 1 + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, in, pad, n);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return scan_rec(pad, out, n + 1, work, s);
+}
+
+template <typename T>
+__global__ void k_plan_edges(int n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                             const double *__restrict__ val, const int64_t *__restrict__ diagpos,
+                             const int64_t *__restrict__ oprt64, int32_t *__restrict__ oprt,
+                             int32_t *__restrict__ rev, T *__restrict__ acoef,
+                             T *__restrict__ diag, uint32_t *__restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  oprt[i] = (int32_t)oprt64[i];
+  if (i == n) return;
+  const int64_t b = rp[i], e = rp[i + 1], dp = diagpos[i];
+  diag[i] = (T)val[dp];
+  int64_t o = oprt64[i];
+  uint32_t f = 0;
+  for (int64_t k = b; k < e; ++k) {
+    if (k == dp) continue;
+    const int32_t j = col[k];
+    // binary search for column i in row j (columns sorted)
+    int64_t lo = rp[j], hi = rp[j + 1] - 1, found = -1;
+    while (lo <= hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      const int32_t c = col[mid];
+      if (c == i) { found = mid; break; }
+      if (c < i) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    int32_t r = 0;
+    if (found < 0 || val[found] != val[k]) {
+      f |= FLAG_ASYM;
+    } else {
+      r = (int32_t)(oprt64[j] + (found - rp[j]) - (found > diagpos[j] ? 1 : 0));
+    }
+    rev[o] = r;
+    acoef[o] = (T)val[k];
+    ++o;
+  }
+  if (f) atomicOr(flags, f);
+}
+
+hipError_t launch_plan_edges(bool fp32, int n, const int64_t *rp, const int32_t *col,
+                             const double *val, const int64_t *diagpos, const int64_t *oprt64,
+                             int32_t *oprt, int32_t *rev, void *acoef, void *diag,
+                             uint32_t *flags, hipStream_t s) {
+  const dim3 grid((n + 1 + kBlock - 1) / kBlock);
+  if (fp32)
+    hipLaunchKernelGGL(k_plan_edges<float>, grid, dim3(kBlock), 0, s, n, rp, col, val, diagpos,
+                       oprt64, oprt, rev, (float *)acoef, (float *)diag, flags);
+  else
+    hipLaunchKernelGGL(k_plan_edges<double>, grid, dim3(kBlock), 0, s, n, rp, col, val, diagpos,
+                       oprt64, oprt, rev, (double *)acoef, (double *)diag, flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// the sweep
+// ---------------------------------------------------------------------------
+// G lanes cooperate on one row; each lane keeps up to R gathered in-messages
+// in registers so the edge update does not gather them twice.  Rows longer
+// than G*R re-gather the tail (normally an L2 hit).
+// MODE 0: sweep.  MODE 1: sweep + check of the means x_i = H_i / S_i formed
+// from the input messages.  MODE 2: means / precisions only (no messages).
+template <typename T, int G, int MODE, bool DAMP>
+__global__ __launch_bounds__(kBlock) void k_csr_sweep(
+    int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ rev,
+    const T *__restrict__ acoef, const T *__restrict__ diag, const T *__restrict__ rhs,
+    const typename Vec2<T>::type *__restrict__ min, typename Vec2<T>::type *__restrict__ mout,
+    T alpha, T *__restrict__ xprev, double *__restrict__ xacc, double *__restrict__ marg,
+    BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+  using V = typename Vec2<T>::type;
+  constexpr int R = 4;
+  if (ctl != nullptr && ctl->stop != STOP_NONE) return;  // uniform: inner solve already stopped
+  const int lane = threadIdx.x % G;
+  const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const bool active = row < n;
+  int beg = 0, end = 0;
+  if (active) {
+    beg = oprt[row];
+    end = oprt[row + 1];
+  }
+  // A1: aggregate the in-messages P_ki, h_ki (gathered through rev)
+  T pin[R], hin[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = beg + lane + r * G;
+    pin[r] = T(0);
+    hin[r] = T(0);
+    if (e < end) {
+      const V m = min[rev[e]];
+      pin[r] = m.x;
+      hin[r] = m.y;
+    }
+  }
+  T S = T(0), H = T(0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    S += pin[r];
+    H += hin[r];
+  }
+  for (int e = beg + lane + R * G; e < end; e += G) {
+    const V m = min[rev[e]];
+    S += m.x;
+    H += m.y;
+  }
+  S = group_sum<G>(S);
+  H = group_sum<G>(H);
+  if (active) {
+    S += diag[row];
+    H += rhs[row];
+  }
+
+  // A2: every out-message subtracts the reverse (in-)message
+  if (MODE != 2) {
+    bool zero = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e = beg + lane + r * G;
+      if (e < end) {
+        const T cav = S - pin[r];
+        const T cavh = H - hin[r];
+        const T a = acoef[e];
+        zero |= (cav == T(0));
+        const T inv = T(1) / cav;
+        T P = -(a * a) * inv;
+        T h = -(a * cavh) * inv;
+        if (DAMP) {
+          const V o = min[e];
+          P = alpha * o.x + (T(1) - alpha) * P;
+          h = alpha * o.y + (T(1) - alpha) * h;
+        }
+        V out;
+        out.x = P;
+        out.y = h;
+        mout[e] = out;
+      }
+    }
+    for (int e = beg + lane + R * G; e < end; e += G) {
+      const V m = min[rev[e]];
+      const T cav = S - m.x;
+      const T cavh = H - m.y;
+      const T a = acoef[e];
+      zero |= (cav == T(0));
+      const T inv = T(1) / cav;
+      T P = -(a * a) * inv;
+      T h = -(a * cavh) * inv;
+      if (DAMP) {
+        const V o = min[e];
+        P = alpha * o.x + (T(1) - alpha) * P;
+        h = alpha * o.y + (T(1) - alpha) * h;
+      }
+      V out;
+      out.x = P;
+      out.y = h;
+      mout[e] = out;
+    }
+    if (zero) atomicOr(sticky, FLAG_BREAKDOWN);
+  }
+
+  // A3: marginal means (check) or final inference
+  if (MODE >= 1) {
+    double d = 0.0, ax = 0.0;
+    uint32_t f = 0;
+    if (active && lane == 0) {
+      if (S == T(0)) f |= FLAG_BREAKDOWN;
+      const T x = H / S;
+      if (!isfinite(x)) f |= FLAG_NONFINITE;
+      if (MODE == 1) {
+        d = (double)fabs(x - xprev[row]);
+        xprev[row] = x;
+      } else {
+        if (xacc) xacc[row] += (double)H / (double)S;
+        if (marg) marg[row] = (double)S;
+      }
+      ax = (double)fabs(x);
+    }
+    if (f) atomicOr(sticky, f);
+    if (MODE == 1) {
+      __shared__ double sd[kBlock / 64], sx[kBlock / 64];
+      d = wave_max(d);
+      ax = wave_max(ax);
+      const int w = threadIdx.x / 64;
+      if ((threadIdx.x & 63) == 0) {
+        sd[w] = d;
+        sx[w] = ax;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double dm = sd[0], xm = sx[0];
+#pragma unroll
+        for (int k = 1; k < kBlock / 64; ++k) {
+          dm = fmax(dm, sd[k]);
+          xm = fmax(xm, sx[k]);
+        }
+        part[blockIdx.x].dmax = dm;
+        part[blockIdx.x].xmax = xm;
+      }
+    }
+  }
+}
+
+int sweep_blocks(int n, int group) { return (n + (kBlock / group) - 1) / (kBlock / group); }
+
+template <typename T, int G, int MODE, bool DAMP>
+static void launch_one(const SweepArgs &a, hipStream_t s) {
+  using V = typename Vec2<T>::type;
+  hipLaunchKernelGGL((k_csr_sweep<T, G, MODE, DAMP>), dim3(sweep_blocks(a.n, G)), dim3(kBlock),
+                     0, s, a.n, a.oprt, a.rev, (const T *)a.acoef, (const T *)a.diag,
+                     (const T *)a.rhs, (const V *)a.msg_in, (V *)a.msg_out, (T)a.alpha,
+                     (T *)a.xprev, a.xacc, a.marg, a.part, a.sticky, a.ctl);
+}
+
+template <typename T, int G>
+static void dispatch_mode(const SweepArgs &a, hipStream_t s) {
+  switch (a.mode) {
+    case 0: a.damp ? launch_one<T, G, 0, true>(a, s) : launch_one<T, G, 0, false>(a, s); break;
+    case 1: a.damp ? launch_one<T, G, 1, true>(a, s) : launch_one<T, G, 1, false>(a, s); break;
+    default: launch_one<T, G, 2, false>(a, s); break;
+  }
+}
+
+template <typename T>
+static hipError_t dispatch_group(const SweepArgs &a, hipStream_t s) {
+  switch (a.group) {
+    case 4: dispatch_mode<T, 4>(a, s); break;
+    case 8: dispatch_mode<T, 8>(a, s); break;
+    case 16: dispatch_mode<T, 16>(a, s); break;
+    case 32: dispatch_mode<T, 32>(a, s); break;
+    case 64: dispatch_mode<T, 64>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(const SweepArgs &a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  return a.fp32 ? dispatch_group<float>(a, s) : dispatch_group<double>(a, s);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual r = b - A x over the caller's CSR, with per-block sums of r^2
+// ---------------------------------------------------------------------------
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_csr_residual(
+    int n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
+    T *__restrict__ rT, double *__restrict__ r64, double *__restrict__ sumpart) {
+  const int lane = threadIdx.x % G;
+  const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const bool active = row < n;
+  double acc = 0.0;
+  if (active && x != nullptr)
+    for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += G) acc += val[k] * x[col[k]];
+  acc = group_sum<G>(acc);
+  double sq = 0.0;
+  if (active && lane == 0) {
+    const double ri = b[row] - acc;
+    if (rT) rT[row] = (T)ri;
+    if (r64) r64[row] = ri;
+    sq = ri * ri;
+  }
+  __shared__ double sh[kBlock / 64];
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x / 64] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+#pragma unroll
+    for (int k = 1; k < kBlock / 64; ++k) t += sh[k];
+    sumpart[blockIdx.x] = t;
+  }
+}
+
+int residual_blocks(int n, int group) { return sweep_blocks(n, group); }
+
+template <typename T>
+static hipError_t residual_group(int group, int n, const int64_t *rp, const int32_t *col,
+                                 const double *val, const double *b, const double *x, T *rT,
+                                 double *r64, double *sumpart, hipStream_t s) {
+  const dim3 grid(residual_blocks(n, group));
+  switch (group) {
+    case 4: hipLaunchKernelGGL((k_csr_residual<T, 4>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
+    case 8: hipLaunchKernelGGL((k_csr_residual<T, 8>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
+    case 16: hipLaunchKernelGGL((k_csr_residual<T, 16>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
+    case 32: hipLaunchKernelGGL((k_csr_residual<T, 32>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
+    case 64: hipLaunchKernelGGL((k_csr_residual<T, 64>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(bool fp32, int group, int n, const int64_t *rp, const int32_t *col,
+                           const double *val, const double *b, const double *x, void *rT,
+                           double *r64, double *sumpart, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  return fp32 ? residual_group<float>(group, n, rp, col, val, b, x, (float *)rT, r64, sumpart, s)
+              : residual_group<double>(group, n, rp, col, val, b, x, (double *)rT, r64, sumpart, s);
+}
+
+// ---------------------------------------------------------------------------
+// readout: reduce partials in a fixed order, run the inner-solve controller,
+// publish to pinned host memory
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_readout(const BlockPartial *__restrict__ part, int nparts,
+                                                    const double *__restrict__ sumpart, int nsum,
+                                                    const uint32_t *__restrict__ sticky,
+                                                    Ctl *__restrict__ ctl, int sweeps_in_chunk,
+                                                    int seq, HostReadout *__restrict__ host) {
+  __shared__ double sd[kBlock / 64], sx[kBlock / 64], ss[kBlock / 64];
+  const bool skipped = (nparts > 0) && ctl->stop != STOP_NONE;
+  double d = 0.0, x = 0.0, s = 0.0;
+  if (!skipped)
+    for (int k = threadIdx.x; k < nparts; k += kBlock) {
+      d = fmax(d, part[k].dmax);
+      x = fmax(x, part[k].xmax);
+      if (!isfinite(part[k].dmax)) d = part[k].dmax;  // propagate NaN / inf
+    }
+  for (int k = threadIdx.x; k < nsum; k += kBlock) s += sumpart[k];
+  d = wave_max(d);
+  x = wave_max(x);
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) {
+    sd[threadIdx.x / 64] = d;
+    sx[threadIdx.x / 64] = x;
+    ss[threadIdx.x / 64] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  d = sd[0]; x = sx[0]; s = ss[0];
+  for (int k = 1; k < kBlock / 64; ++k) {
+    d = fmax(d, sd[k]);
+    x = fmax(x, sx[k]);
+    s += ss[k];
+  }
+  const uint32_t flags = sticky ? *sticky : 0u;
+  if (nparts > 0 && !skipped) {
+    ctl->sweeps += sweeps_in_chunk;
+    ctl->checks += 1;
+    ctl->last_d = d;
+    ctl->last_x = x;
+    const double rel = d / fmax(x, 1e-300);
+    if (!isfinite(d) || !isfinite(x) || (flags & (FLAG_NONFINITE | FLAG_BREAKDOWN))) {
+      ctl->stop = STOP_NONFINITE;
+    } else if (rel <= ctl->inner_tol) {
+      ctl->stop = STOP_CONVERGED;
+    } else {
+      // progress test: a stall only counts close to the arithmetic's floor
+      if (rel < 0.99 * ctl->best) {
+        ctl->best = rel;
+        ctl->stall = 0;
+      } else {
+        ctl->stall += 1;
+      }
+      if ((ctl->stall >= 8 && rel < ctl->stall_floor) || ctl->stall >= 32)
+        ctl->stop = STOP_STALLED;
+    }
+  }
+  host->dmax = d;
+  host->xmax = x;
+  host->sum = s;
+  host->flags = flags;
+  host->stop = ctl ? ctl->stop : 0u;
+  host->sweeps = ctl ? ctl->sweeps : 0;
+  host->seq = seq;
+  __threadfence_system();
+}
+
+hipError_t launch_readout(const BlockPartial *part, int nparts, const double *sumpart, int nsum,
+                          const uint32_t *sticky, Ctl *ctl, int sweeps_in_chunk, int seq,
+                          HostReadout *host, hipStream_t s) {
+  hipLaunchKernelGGL(k_readout, dim3(1), dim3(kBlock), 0, s, part, nparts, sumpart, nsum, sticky,
+                     ctl, sweeps_in_chunk, seq, host);
+  return hipGetLastError();
+}
+
+__global__ void k_ctl_reset(Ctl *ctl, double inner_tol, double stall_floor, int full) {
+  if (threadIdx.x != 0) return;
+  ctl->stop = STOP_NONE;
+  ctl->stall = 0;
+  ctl->best = 1e300;
+  ctl->inner_tol = inner_tol;
+  ctl->stall_floor = stall_floor;
+  ctl->last_d = 0.0;
+  ctl->last_x = 0.0;
+  if (full) {
+    ctl->sweeps = 0;
+    ctl->checks = 0;
+  }
+}
+
+hipError_t launch_ctl_reset(Ctl *ctl, double inner_tol, double stall_floor, bool full,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, inner_tol, stall_floor,
+                     full ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fills, restarts, message export / import
+// ---------------------------------------------------------------------------
+template <typename V>
+__global__ void k_zero_h(int64_t E, V *__restrict__ msg) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) msg[e].y = 0;
+}
+
+hipError_t launch_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((E + kBlock - 1) / kBlock));
+  if (fp32) hipLaunchKernelGGL(k_zero_h<float2>, grid, dim3(kBlock), 0, s, E, (float2 *)msg);
+  else hipLaunchKernelGGL(k_zero_h<double2>, grid, dim3(kBlock), 0, s, E, (double2 *)msg);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_zero8(uint64_t *__restrict__ p, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) p[i] = 0;
+}
+__global__ void k_fill_zero4(uint32_t *__restrict__ p, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) p[i] = 0;
+}
+
+hipError_t launch_fill_zero(void *p, int64_t m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero8, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     (uint64_t *)p, m);
+  return hipGetLastError();
+}
+hipError_t launch_fill_zero4(void *p, int64_t m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero4, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     (uint32_t *)p, m);
+  return hipGetLastError();
+}
+
+template <typename V, bool GET>
+__global__ void k_msgs_io(int n, const int64_t *__restrict__ rp, const int64_t *__restrict__ diagpos,
+                          const int32_t *__restrict__ oprt, V *__restrict__ msg, double *__restrict__ P,
+                          double *__restrict__ h) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t b = rp[i], e = rp[i + 1], dp = diagpos[i];
+  for (int64_t k = b; k < e; ++k) {
+    if (k == dp) {
+      if (GET) { P[k] = 0.0; h[k] = 0.0; }
+      continue;
+    }
+    const int64_t o = oprt[i] + (k - b) - (k > dp ? 1 : 0);
+    if (GET) {
+      P[k] = (double)msg[o].x;
+      h[k] = (double)msg[o].y;
+    } else {
+      msg[o].x = P[k];
+      msg[o].y = h[k];
+    }
+  }
+}
+
+hipError_t launch_get_msgs(bool fp32, int n, const int64_t *rp, const int64_t *diagpos,
+                           const int32_t *oprt, const void *msg, double *P, double *h,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((n + kBlock - 1) / kBlock);
+  if (fp32) hipLaunchKernelGGL((k_msgs_io<float2, true>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, (float2 *)msg, P, h);
+  else hipLaunchKernelGGL((k_msgs_io<double2, true>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, (double2 *)msg, P, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_msgs(bool fp32, int n, const int64_t *rp, const int64_t *diagpos,
+                           const int32_t *oprt, void *msg, const double *P, const double *h,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((n + kBlock - 1) / kBlock);
+  if (fp32) hipLaunchKernelGGL((k_msgs_io<float2, false>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, (float2 *)msg, (double *)P, (double *)h);
+  else hipLaunchKernelGGL((k_msgs_io<double2, false>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, (double2 *)msg, (double *)P, (double *)h);
+  return hipGetLastError();
+}
+
+}  // namespace gabp
