@@ -74,29 +74,54 @@ typedef struct {
   int32_t check_every; /* sweeps between checks of the marginal means */
   double damping;      /* alpha in [0,1): P <- alpha P_old + (1-alpha) P_new
                           and the same for the information h = P mu */
-  double inner_tol;    /* an inner solve ends when the means move by at most
-                          inner_tol * max|x| over check_every sweeps */
+  double inner_tol;    /* an inner solve ends when the estimated relative
+                          error of the means, d q / (1 - q) / max|x| with d the
+                          largest change over one check interval and q the
+                          ratio of successive d, is at most inner_tol;
+                          0 = automatic: the first inner solve runs to the
+                          message precision's floor, later ones to the
+                          remaining factor 0.3 tol / (current residual) */
   int32_t max_restarts;/* refinement restarts (mean messages zeroed,
                           precision messages kept) */
   int32_t group;       /* lanes per row in the sweep: 0 = chosen from the
                           degree profile, else 4, 8, 16, 32 or 64 */
+  int32_t layout;      /* GABP_LAYOUT_PAIR (default): each edge slot holds both
+                          directions of its edge and nodes broadcast their
+                          aggregates (Algorithm 2, section V), so the only
+                          random access is a node-sized gather;
+                          GABP_LAYOUT_GATHER: each slot holds its out-message
+                          and in-messages are gathered through the
+                          reverse-edge index (half the message memory) */
+  int32_t grid_blocks; /* blocks of a sweep launch; rows beyond are handled
+                          by a grid-stride loop; 0 = default (2048) */
+  int32_t freeze;      /* 1 (default): once every precision message has settled
+                          (largest change <= 1e-6 |P|max in FP32, 1e-14 in FP64)
+                          pair-layout sweeps keep the precisions fixed and
+                          update the information h = P mu only; the FP64
+                          refinement absorbs the last-ulp difference.  0: never */
 } gabp_opts;
+
+enum { GABP_LAYOUT_PAIR = 0, GABP_LAYOUT_GATHER = 1 };
 
 typedef struct {
   int32_t status;          /* gabp_status of the solve */
   int32_t sweeps;          /* synchronous sweeps run (all restarts) */
+  int32_t frozen_sweeps;   /* of which with settled (fixed) precisions */
   int32_t restarts;        /* refinement restarts taken */
   int32_t checks;          /* mean checks read back by the host */
   double rel_residual;     /* final ||b - A x||_2 / ||b||_2, FP64 */
   double residual_per_eq;  /* ||b - A x||_2 / n (section II-A norm) */
   double seconds;          /* host wall time of the solve */
   double sweep_ms;         /* summed device time of the sweep launches */
+  double frozen_sweep_ms;  /* of which in sweeps with settled precisions */
   int64_t edges;           /* directed off-diagonal messages per sweep */
   double edge_updates_per_s; /* edges * sweeps / seconds */
 } gabp_stats;
 
 /* Fills o with the defaults: FP32 messages, tol 1e-8, 20000 sweeps, checks
- * every 4 sweeps, no damping, inner_tol 1e-6, 30 restarts, group 0. */
+ * every 2 sweeps, no damping, automatic inner targets (inner_tol 0),
+ * 30 restarts, group 0, pair layout, freeze on.  check_every is rounded up to
+ * an even count. */
 void gabp_default_opts(gabp_opts *o);
 
 /* One-call solve (plan create + solve + destroy).

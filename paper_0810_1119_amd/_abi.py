@@ -22,8 +22,11 @@ GABP_ERR_DIVERGED = -5
 GABP_ERR_HIP = -6
 GABP_ERR_NOMEM = -7
 GABP_ERR_UNSUPPORTED = -8
+GABP_LAYOUT_PAIR = 0
+GABP_LAYOUT_GATHER = 1
 
-_NAMES = {v: k for k, v in dict(globals()).items() if k.startswith("GABP_") and isinstance(v, int)}
+_NAMES = {v: k for k, v in dict(globals()).items()
+          if k.startswith("GABP_") and not k.startswith("GABP_LAYOUT") and isinstance(v, int)}
 
 
 def status_name(code: int) -> str:
@@ -49,14 +52,16 @@ class _Csr(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("msg_fp32", C.c_int32), ("tol", C.c_double), ("max_sweeps", C.c_int32),
                 ("check_every", C.c_int32), ("damping", C.c_double), ("inner_tol", C.c_double),
-                ("max_restarts", C.c_int32), ("group", C.c_int32)]
+                ("max_restarts", C.c_int32), ("group", C.c_int32), ("layout", C.c_int32),
+                ("grid_blocks", C.c_int32), ("freeze", C.c_int32)]
 
 
 class Stats(C.Structure):
-    _fields_ = [("status", C.c_int32), ("sweeps", C.c_int32), ("restarts", C.c_int32),
+    _fields_ = [("status", C.c_int32), ("sweeps", C.c_int32), ("frozen_sweeps", C.c_int32),
+                ("restarts", C.c_int32),
                 ("checks", C.c_int32), ("rel_residual", C.c_double),
                 ("residual_per_eq", C.c_double), ("seconds", C.c_double),
-                ("sweep_ms", C.c_double), ("edges", C.c_int64),
+                ("sweep_ms", C.c_double), ("frozen_sweep_ms", C.c_double), ("edges", C.c_int64),
                 ("edge_updates_per_s", C.c_double)]
 
     def as_dict(self):

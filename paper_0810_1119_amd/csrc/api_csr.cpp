@@ -14,7 +14,9 @@
 // device whether the inner solve is done and publishes its state to pinned
 // host memory.  The host keeps two chunks in flight, so the GPU never waits
 // for the host; chunks queued after the device decided to stop return at
-// once.
+// once.  In the pair layout, once the controller reports that every
+// precision message has settled, the host switches to information-only
+// sweeps (one freeze launch, then frozen chunks).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -36,9 +38,9 @@ int from_hip(hipError_t e) {
   return GABP_ERR_HIP;
 }
 
-#define TRY_HIP(expr)                         \
-  do {                                        \
-    hipError_t _e = (expr);                   \
+#define TRY_HIP(expr)                          \
+  do {                                         \
+    hipError_t _e = (expr);                    \
     if (_e != hipSuccess) return from_hip(_e); \
   } while (0)
 
@@ -48,12 +50,14 @@ hipError_t dalloc(P **p, size_t count, size_t elem) {
   return hipMalloc((void **)p, std::max<size_t>(1, count) * elem);
 }
 
+// Lanes per row: about two lanes per edge of an average row (measured best on
+// random graphs of mean degree 8: 16 lanes), at least 4, at most a wave.
 int choose_group(int64_t n, int64_t E) {
   const double d = n > 0 ? (double)E / (double)n : 0.0;
-  if (d < 6) return 4;
-  if (d < 12) return 8;
-  if (d < 24) return 16;
-  if (d < 48) return 32;
+  if (d < 3) return 4;
+  if (d < 6) return 8;
+  if (d < 12) return 16;
+  if (d < 24) return 32;
   return 64;
 }
 
@@ -67,17 +71,24 @@ struct gabp_plan {
   int32_t n = 0;
   int64_t E = 0;
   bool fp32 = true;
+  bool pair = true;
   int group = 8;
   size_t tsz = 4;
-  int32_t *oprt = nullptr, *rev = nullptr;
+  // graph
+  int32_t *oprt = nullptr, *ocol = nullptr, *rev = nullptr;
   int64_t *diagpos = nullptr;
   void *acoef = nullptr, *diag = nullptr, *rhs = nullptr, *xprev = nullptr;
+  // gather layout: (P, h) out-message per slot; pair layout: (P_ij, h_ij, P_ji, h_ji)
   void *msg[2] = {nullptr, nullptr};
+  void *sums[2] = {nullptr, nullptr};  // pair: (S, H) per node
+  // frozen phase (pair layout, allocated on first use)
+  void *coef = nullptr, *hp[2] = {nullptr, nullptr}, *Sfix = nullptr, *Hfz[2] = {nullptr, nullptr};
+  bool frozen = false;
   int cur = 0;
-  BlockPartial *part = nullptr;
-  int nsweep_blocks = 0;
   double *sumpart = nullptr;
   int nres_blocks = 0;
+  BlockPartial *part = nullptr;
+  int nsweep_blocks = 0;
   uint32_t *sticky = nullptr;
   Ctl *ctl = nullptr;
   HostReadout *host = nullptr;
@@ -86,38 +97,112 @@ struct gabp_plan {
   int seq = 0;
 
   void release() {
-    hipFree(oprt); hipFree(rev); hipFree(diagpos); hipFree(acoef); hipFree(diag);
-    hipFree(rhs); hipFree(xprev); hipFree(msg[0]); hipFree(msg[1]); hipFree(part);
-    hipFree(sumpart); hipFree(sticky); hipFree(ctl);
-    if (host) hipHostFree(host);
+    void *bufs[] = {oprt, ocol, rev, diagpos, acoef, diag, rhs, xprev, msg[0], msg[1],
+                    sums[0], sums[1], coef, hp[0], hp[1], Sfix, Hfz[0], Hfz[1], sumpart,
+                    part, sticky, ctl};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+    if (host) (void)hipHostFree(host);
     if (events)
       for (int k = 0; k < kRing; ++k) {
-        hipEventDestroy(ev_beg[k]); hipEventDestroy(ev_end[k]); hipEventDestroy(ev_done[k]);
+        (void)hipEventDestroy(ev_beg[k]);
+        (void)hipEventDestroy(ev_end[k]);
+        (void)hipEventDestroy(ev_done[k]);
       }
   }
 
-  SweepArgs sweep_args(int mode, const void *in, void *out) const {
-    SweepArgs a{};
-    a.fp32 = fp32;
-    a.group = group;
-    a.mode = mode;
-    a.damp = o.damping > 0.0 && mode != 2;
-    a.n = n;
-    a.oprt = oprt;
-    a.rev = rev;
-    a.acoef = acoef;
-    a.diag = diag;
-    a.rhs = rhs;
-    a.msg_in = in;
-    a.msg_out = out;
-    a.alpha = o.damping;
-    a.xprev = xprev;
-    a.part = part;
-    a.sticky = sticky;
-    return a;
+  size_t msg_bytes() const { return (pair ? 4 : 2) * tsz; }
+
+  // one synchronous sweep from buffer cur into cur ^ 1
+  hipError_t sweep(int mode, const Ctl *c, hipStream_t s) {
+    hipError_t err;
+    if (!pair) {
+      SweepArgs a{};
+      a.grid = nsweep_blocks;
+      a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0; a.n = n;
+      a.oprt = oprt; a.rev = rev; a.acoef = acoef; a.diag = diag; a.rhs = rhs;
+      a.msg_in = msg[cur]; a.msg_out = msg[cur ^ 1]; a.alpha = o.damping; a.xprev = xprev;
+      a.part = part; a.sticky = sticky; a.ctl = c;
+      err = launch_sweep(a, s);
+    } else {
+      PairArgs a{};
+      a.grid = nsweep_blocks;
+      a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0; a.frozen = frozen;
+      a.n = n; a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag; a.rhs = rhs;
+      a.alpha = o.damping; a.xprev = xprev; a.part = part; a.sticky = sticky; a.ctl = c;
+      if (frozen) {
+        a.coef = coef; a.Sfix = Sfix;
+        a.msg_in = hp[cur]; a.msg_out = hp[cur ^ 1]; a.sums_in = Hfz[cur]; a.sums_out = Hfz[cur ^ 1];
+      } else {
+        a.msg_in = msg[cur]; a.msg_out = msg[cur ^ 1]; a.sums_in = sums[cur]; a.sums_out = sums[cur ^ 1];
+      }
+      err = launch_pair_sweep(a, s);
+    }
+    cur ^= 1;
+    return err;
   }
 
-  // readout without a check: residual sums only; waits and returns the slot
+  // x += H/S and/or marginal precisions from the current state
+  hipError_t infer(double *xacc, double *marg, hipStream_t s) {
+    if (!pair) {
+      SweepArgs a{};
+      a.grid = nsweep_blocks;
+      a.fp32 = fp32; a.group = group; a.mode = 2; a.n = n; a.oprt = oprt; a.rev = rev;
+      a.acoef = acoef; a.diag = diag; a.rhs = rhs; a.msg_in = msg[cur]; a.xacc = xacc;
+      a.marg = marg; a.sticky = sticky;
+      return launch_sweep(a, s);
+    }
+    if (frozen) return launch_pair_infer(fp32, n, nullptr, Sfix, Hfz[cur], xacc, marg, sticky, s);
+    return launch_pair_infer(fp32, n, sums[cur], nullptr, nullptr, xacc, marg, sticky, s);
+  }
+
+  // zero every mean message, keep the precisions; rhs must already hold r
+  hipError_t restart(hipStream_t s) {
+    if (!pair) return launch_zero_h(fp32, E, msg[cur], s);
+    if (frozen) return launch_frozen_restart(fp32, E, n, hp[cur], rhs, Hfz[cur], s);
+    hipError_t err = launch_pair_zero_h(fp32, E, msg[cur], s);
+    if (err != hipSuccess) return err;
+    return launch_pair_aggregate(fp32, group, nsweep_blocks, n, oprt, diag, rhs, msg[cur], sums[cur], s);
+  }
+
+  // zero messages, rhs = b (and ||b||^2 into the residual partials), full state
+  hipError_t reset(const double *b, hipStream_t s) {
+    cur = 0;
+    frozen = false;
+    const int64_t words = E * (int64_t)msg_bytes() / 8;
+    hipError_t err;
+    if ((err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
+    if ((err = launch_fill_zero(msg[1], words, s)) != hipSuccess) return err;
+    if ((err = launch_fill_zero4(sticky, 1, s)) != hipSuccess) return err;
+    if ((err = launch_residual(fp32, group, nres_blocks, n, A.row_ptr, A.col, A.val, b, nullptr, rhs, nullptr,
+                               sumpart, s)) != hipSuccess)
+      return err;
+    if (pair) return launch_pair_aggregate(fp32, group, nsweep_blocks, n, oprt, diag, rhs, msg[0], sums[0], s);
+    return hipSuccess;
+  }
+
+  // allocates whichever frozen-phase buffer is still missing
+  hipError_t ensure_frozen_buffers() {
+    struct { void **p; size_t count, elem; } need[] = {
+        {&coef, (size_t)E, 2 * tsz}, {&hp[0], (size_t)E, 2 * tsz}, {&hp[1], (size_t)E, 2 * tsz},
+        {&Sfix, (size_t)n, tsz},     {&Hfz[0], (size_t)n, tsz},    {&Hfz[1], (size_t)n, tsz}};
+    for (auto &b : need)
+      if (!*b.p) {
+        hipError_t err = dalloc(b.p, b.count, b.elem);
+        if (err != hipSuccess) return err;
+      }
+    return hipSuccess;
+  }
+  bool frozen_ready() const { return coef && hp[0] && hp[1] && Sfix && Hfz[0] && Hfz[1]; }
+
+  hipError_t freeze(hipStream_t s) {
+    hipError_t err = launch_pair_freeze(fp32, group, nsweep_blocks, n, oprt, ocol, acoef, msg[cur], sums[cur],
+                                        coef, hp[cur], Sfix, Hfz[cur], s);
+    frozen = true;
+    return err;
+  }
+
+  // readout without a check: residual sums only; waits
   int read_sum(hipStream_t s, HostReadout *outv) {
     const int slot = 0;
     TRY_HIP(launch_readout(nullptr, 0, sumpart, nres_blocks, sticky, ctl, 0, ++seq, &host[slot], s));
@@ -130,7 +215,7 @@ struct gabp_plan {
 
 extern "C" {
 
-const char *gabp_version(void) { return "gabp-mi355x 0.1 (gfx950)"; }
+const char *gabp_version(void) { return "gabp-mi355x 0.2 (gfx950)"; }
 
 void gabp_default_opts(gabp_opts *o) {
   if (!o) return;
@@ -138,11 +223,13 @@ void gabp_default_opts(gabp_opts *o) {
   o->msg_fp32 = 1;
   o->tol = 1e-8;
   o->max_sweeps = 20000;
-  o->check_every = 4;
+  o->check_every = 2;
   o->damping = 0.0;
   o->inner_tol = 0.0;
   o->max_restarts = 30;
   o->group = 0;
+  o->layout = GABP_LAYOUT_PAIR;
+  o->freeze = 1;
 }
 
 static int check_csr(const gabp_csr *A) {
@@ -160,7 +247,8 @@ static int check_csr(const gabp_csr *A) {
 static int check_opts(const gabp_opts *o) {
   if (!(o->tol >= 0.0) || o->max_sweeps < 0 || o->check_every < 1 || !(o->damping >= 0.0) ||
       !(o->damping < 1.0) || !(o->inner_tol >= 0.0) || o->max_restarts < 0 ||
-      (o->group != 0 && !valid_group(o->group)))
+      (o->group != 0 && !valid_group(o->group)) || o->grid_blocks < 0 ||
+      (o->layout != GABP_LAYOUT_PAIR && o->layout != GABP_LAYOUT_GATHER))
     return GABP_ERR_ARG;
   return GABP_OK;
 }
@@ -172,7 +260,9 @@ static int plan_build(gabp_plan *p, hipStream_t s) {
   uint32_t *flags = nullptr;
   int st = GABP_OK;
   auto fail = [&](int code) {
-    hipFree(deg); hipFree(oprt64); hipFree(tmp); hipFree(flags);
+    void *bufs[] = {deg, oprt64, tmp, flags};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
     return code;
   };
   if ((st = from_hip(dalloc(&deg, n, sizeof(int64_t)))) ||
@@ -198,12 +288,13 @@ static int plan_build(gabp_plan *p, hipStream_t s) {
   if (E >= (int64_t)INT32_MAX) return fail(GABP_ERR_UNSUPPORTED);
   p->E = E;
   if ((st = from_hip(dalloc(&p->oprt, n + 1, sizeof(int32_t)))) ||
+      (st = from_hip(dalloc(&p->ocol, E, sizeof(int32_t)))) ||
       (st = from_hip(dalloc(&p->rev, E, sizeof(int32_t)))) ||
       (st = from_hip(dalloc(&p->acoef, E, p->tsz))) ||
       (st = from_hip(dalloc(&p->diag, n, p->tsz))))
     return fail(st);
   if ((st = from_hip(launch_plan_edges(p->fp32, n, A.row_ptr, A.col, A.val, p->diagpos, oprt64,
-                                       p->oprt, p->rev, p->acoef, p->diag, flags, s))))
+                                       p->oprt, p->ocol, p->rev, p->acoef, p->diag, flags, s))))
     return fail(st);
   if ((st = from_hip(hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s))) ||
       (st = from_hip(hipStreamSynchronize(s))))
@@ -227,6 +318,7 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
   p->o = opts;
   p->n = A->n;
   p->fp32 = opts.msg_fp32 != 0;
+  p->pair = opts.layout == GABP_LAYOUT_PAIR;
   p->tsz = p->fp32 ? sizeof(float) : sizeof(double);
   auto fail = [&](int code) {
     p->release();
@@ -235,27 +327,30 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
   };
   if (p->n > 0 && (st = plan_build(p, s))) return fail(st);
   p->group = opts.group ? opts.group : choose_group(p->n, p->E);
-  p->nsweep_blocks = sweep_blocks(std::max(p->n, 1), p->group);
-  p->nres_blocks = residual_blocks(std::max(p->n, 1), p->group);
-  if ((st = from_hip(dalloc(&p->msg[0], p->E, 2 * p->tsz))) ||
-      (st = from_hip(dalloc(&p->msg[1], p->E, 2 * p->tsz))) ||
+  const int cap = opts.grid_blocks > 0 ? opts.grid_blocks : kMaxSweepBlocks;
+  p->nres_blocks = residual_blocks(std::max(p->n, 1), p->group, cap);
+  p->nsweep_blocks = sweep_blocks(std::max(p->n, 1), p->group, cap);
+  if ((st = from_hip(dalloc(&p->msg[0], p->E, p->msg_bytes()))) ||
+      (st = from_hip(dalloc(&p->msg[1], p->E, p->msg_bytes()))) ||
       (st = from_hip(dalloc(&p->rhs, p->n, p->tsz))) ||
       (st = from_hip(dalloc(&p->xprev, p->n, p->tsz))) ||
-      (st = from_hip(dalloc(&p->part, p->nsweep_blocks, sizeof(BlockPartial)))) ||
       (st = from_hip(dalloc(&p->sumpart, p->nres_blocks, sizeof(double)))) ||
+      (st = from_hip(dalloc(&p->part, p->nsweep_blocks, sizeof(BlockPartial)))) ||
       (st = from_hip(dalloc(&p->sticky, 1, sizeof(uint32_t)))) ||
       (st = from_hip(dalloc(&p->ctl, 1, sizeof(Ctl)))))
+    return fail(st);
+  if (p->pair && ((st = from_hip(dalloc(&p->sums[0], p->n, 2 * p->tsz))) ||
+                  (st = from_hip(dalloc(&p->sums[1], p->n, 2 * p->tsz)))))
     return fail(st);
   if ((st = from_hip(hipHostMalloc((void **)&p->host, kRing * sizeof(HostReadout), hipHostMallocDefault))))
     return fail(st);
   for (int k = 0; k < kRing; ++k) {
     if ((st = from_hip(hipEventCreate(&p->ev_beg[k]))) || (st = from_hip(hipEventCreate(&p->ev_end[k]))) ||
         (st = from_hip(hipEventCreateWithFlags(&p->ev_done[k], hipEventDisableTiming)))) {
-      // destroy the ones made so far
       for (int j = 0; j <= k; ++j) {
-        if (p->ev_beg[j]) hipEventDestroy(p->ev_beg[j]);
-        if (p->ev_end[j]) hipEventDestroy(p->ev_end[j]);
-        if (p->ev_done[j]) hipEventDestroy(p->ev_done[j]);
+        if (p->ev_beg[j]) (void)hipEventDestroy(p->ev_beg[j]);
+        if (p->ev_end[j]) (void)hipEventDestroy(p->ev_end[j]);
+        if (p->ev_done[j]) (void)hipEventDestroy(p->ev_done[j]);
       }
       return fail(st);
     }
@@ -267,7 +362,7 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
 
 int gabp_plan_destroy(gabp_plan *p) {
   if (!p) return GABP_ERR_ARG;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   p->release();
   delete p;
   return GABP_OK;
@@ -276,23 +371,15 @@ int gabp_plan_destroy(gabp_plan *p) {
 int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
   if (!p || (p->n > 0 && !b)) return GABP_ERR_ARG;
   if (p->n == 0) return GABP_OK;
-  p->cur = 0;
-  TRY_HIP(launch_fill_zero(p->msg[0], p->E * (p->fp32 ? 1 : 2), s));
-  TRY_HIP(launch_fill_zero(p->msg[1], p->E * (p->fp32 ? 1 : 2), s));
-  TRY_HIP(launch_fill_zero4(p->sticky, 1, s));
-  TRY_HIP(launch_residual(p->fp32, p->group, p->n, p->A.row_ptr, p->A.col, p->A.val, b, nullptr,
-                          p->rhs, nullptr, p->sumpart, s));
+  TRY_HIP(p->reset(b, s));
   TRY_HIP(hipStreamSynchronize(s));
   return GABP_OK;
 }
 
 int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
   if (!p || count < 0) return GABP_ERR_ARG;
-  for (int k = 0; k < count && p->n > 0; ++k) {
-    SweepArgs a = p->sweep_args(0, p->msg[p->cur], p->msg[p->cur ^ 1]);
-    TRY_HIP(launch_sweep(a, s));
-    p->cur ^= 1;
-  }
+  if (p->frozen) return GABP_ERR_ARG;  // trajectory access needs the full state (reset first)
+  for (int k = 0; k < count && p->n > 0; ++k) TRY_HIP(p->sweep(0, nullptr, s));
   TRY_HIP(hipStreamSynchronize(s));
   return GABP_OK;
 }
@@ -301,24 +388,32 @@ int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s)
   if (!p || (p->n > 0 && !mean)) return GABP_ERR_ARG;
   if (p->n == 0) return GABP_OK;
   TRY_HIP(launch_fill_zero(mean, p->n, s));
-  SweepArgs a = p->sweep_args(2, p->msg[p->cur], nullptr);
-  a.xacc = mean;
-  a.marg = prec;
-  TRY_HIP(launch_sweep(a, s));
+  TRY_HIP(p->infer(mean, prec, s));
   TRY_HIP(hipStreamSynchronize(s));
   return GABP_OK;
 }
 
 int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
-  if (!p || (p->A.nnz > 0 && (!P || !h))) return GABP_ERR_ARG;
-  TRY_HIP(launch_get_msgs(p->fp32, p->n, p->A.row_ptr, p->diagpos, p->oprt, p->msg[p->cur], P, h, s));
+  if (!p || (p->A.nnz > 0 && (!P || !h)) || p->frozen) return GABP_ERR_ARG;
+  if (p->pair)
+    TRY_HIP(launch_pair_io(p->fp32, true, p->n, p->A.row_ptr, p->diagpos, p->oprt, p->rev,
+                           p->msg[p->cur], P, h, s));
+  else
+    TRY_HIP(launch_get_msgs(p->fp32, p->n, p->A.row_ptr, p->diagpos, p->oprt, p->msg[p->cur], P, h, s));
   TRY_HIP(hipStreamSynchronize(s));
   return GABP_OK;
 }
 
 int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipStream_t s) {
-  if (!p || (p->A.nnz > 0 && (!P || !h))) return GABP_ERR_ARG;
-  TRY_HIP(launch_set_msgs(p->fp32, p->n, p->A.row_ptr, p->diagpos, p->oprt, p->msg[p->cur], P, h, s));
+  if (!p || (p->A.nnz > 0 && (!P || !h)) || p->frozen) return GABP_ERR_ARG;
+  if (p->pair) {
+    TRY_HIP(launch_pair_io(p->fp32, false, p->n, p->A.row_ptr, p->diagpos, p->oprt, p->rev,
+                           p->msg[p->cur], (double *)P, (double *)h, s));
+    TRY_HIP(launch_pair_aggregate(p->fp32, p->group, p->nsweep_blocks, p->n, p->oprt, p->diag, p->rhs,
+                                  p->msg[p->cur], p->sums[p->cur], s));
+  } else {
+    TRY_HIP(launch_set_msgs(p->fp32, p->n, p->A.row_ptr, p->diagpos, p->oprt, p->msg[p->cur], P, h, s));
+  }
   TRY_HIP(hipStreamSynchronize(s));
   return GABP_OK;
 }
@@ -341,21 +436,26 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
   };
   if (p->n == 0) return finish(GABP_OK);
 
-  const int c = std::max(2, o.check_every + (o.check_every & 1));  // even: parity kept per chunk
-  const double inner_tol = o.inner_tol > 0 ? o.inner_tol : (p->fp32 ? 1e-5 : 0.1 * o.tol);
-  // below this relative change a lack of progress means the arithmetic's floor
-  const double stall_floor = p->fp32 ? 1e-4 : 1e-11;
-  p->cur = 0;
-  TRY_HIP(launch_fill_zero(p->msg[0], p->E * (p->fp32 ? 1 : 2), s));
-  TRY_HIP(launch_fill_zero(p->msg[1], p->E * (p->fp32 ? 1 : 2), s));
+  const int c = std::max(2, o.check_every + (o.check_every & 1));  // even: buffer parity kept
+  // Inner targets: the first pass runs to the message precision's floor (or
+  // to 0.3 tol if that is coarser); later passes only need the remaining
+  // factor tol / rel, with the same margin.  inner_tol > 0 fixes the target.
+  const double floor = p->fp32 ? 1e-6 : 1e-14;
+  // The freeze takes effect a few sweeps after the check that allows it (the
+  // chunks already queued still run full sweeps), so the precisions keep
+  // settling in between; 1e-6 leaves them at FP32 resolution by then on the
+  // workloads measured, and the FP64 refinement absorbs any remainder.
+  const double freeze_tol = (p->pair && o.freeze) ? (p->fp32 ? 1e-6 : 1e-14) : -1.0;
+  auto target_for = [&](double rel) {
+    if (o.inner_tol > 0) return o.inner_tol;
+    return std::min(0.5, std::max(0.3 * o.tol / rel, p->fp32 ? 1e-7 : 1e-15));
+  };
+  if (freeze_tol > 0) TRY_HIP(p->ensure_frozen_buffers());
+  TRY_HIP(p->reset(b, s));  // also computes ||b||^2 into the residual partials
   if (p->fp32) TRY_HIP(launch_fill_zero4(p->xprev, p->n, s));
   else TRY_HIP(launch_fill_zero(p->xprev, p->n, s));
   TRY_HIP(launch_fill_zero(x, p->n, s));
-  TRY_HIP(launch_fill_zero4(p->sticky, 1, s));
-  TRY_HIP(launch_ctl_reset(p->ctl, inner_tol, stall_floor, true, s));
-  // r = b (x = 0): right-hand side of the first inner solve and ||b||^2
-  TRY_HIP(launch_residual(p->fp32, p->group, p->n, p->A.row_ptr, p->A.col, p->A.val, b, nullptr,
-                          p->rhs, nullptr, p->sumpart, s));
+  TRY_HIP(launch_ctl_reset(p->ctl, target_for(1.0), floor, freeze_tol, true, s));
   HostReadout r0;
   int rc = p->read_sum(s, &r0);
   if (rc) return finish(rc);
@@ -364,9 +464,7 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
   if (bn == 0.0) {
     stats.rel_residual = 0.0;
     if (marg_prec) {
-      SweepArgs a = p->sweep_args(2, p->msg[p->cur], nullptr);
-      a.marg = marg_prec;
-      TRY_HIP(launch_sweep(a, s));
+      TRY_HIP(p->infer(nullptr, marg_prec, s));
       TRY_HIP(hipStreamSynchronize(s));
     }
     return finish(GABP_OK);
@@ -374,21 +472,23 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
 
   int status = GABP_NOT_CONVERGED;
   int sweeps_done = 0;
+  double rel_prev = 1.0;
   for (int pass = 0;; ++pass) {
-    if (pass > 0) TRY_HIP(launch_ctl_reset(p->ctl, inner_tol, stall_floor, false, s));
+    if (pass > 0) TRY_HIP(launch_ctl_reset(p->ctl, target_for(rel_prev), floor, freeze_tol, false, s));
     // ---- inner solve: chunks of c sweeps, lookahead, device-side stop ----
     const int budget = o.max_sweeps - sweeps_done;
     int enq = 0, rd = 0, enq_sweeps = 0, last_sweeps = sweeps_done;
-    bool stopped = false;
+    bool stopped = false, want_freeze = false;
+    bool chunk_frozen[kRing] = {};
     while (true) {
       while (!stopped && enq - rd < kLookahead && enq_sweeps < budget) {
         const int slot = enq % kRing;
+        if (want_freeze && !p->frozen && freeze_tol > 0 && p->pair && p->frozen_ready())
+          TRY_HIP(p->freeze(s));
+        chunk_frozen[slot] = p->frozen;
         for (int k = 0; k < c; ++k) {
           if (k == 0) TRY_HIP(hipEventRecord(p->ev_beg[slot], s));
-          SweepArgs a = p->sweep_args(k == c - 1 ? 1 : 0, p->msg[p->cur ^ (k & 1)],
-                                      p->msg[p->cur ^ ((k & 1) ^ 1)]);
-          a.ctl = p->ctl;
-          TRY_HIP(launch_sweep(a, s));
+          TRY_HIP(p->sweep(k == c - 1 ? 1 : 0, p->ctl, s));
         }
         TRY_HIP(hipEventRecord(p->ev_end[slot], s));
         TRY_HIP(launch_readout(p->part, p->nsweep_blocks, nullptr, 0, p->sticky, p->ctl, c, enq,
@@ -407,8 +507,13 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
         float ms = 0.f;
         TRY_HIP(hipEventElapsedTime(&ms, p->ev_beg[slot], p->ev_end[slot]));
         stats.sweep_ms += ms;
+        if (chunk_frozen[slot]) {
+          stats.frozen_sweeps += h.sweeps - last_sweeps;
+          stats.frozen_sweep_ms += ms;
+        }
         last_sweeps = h.sweeps;
       }
+      if (h.freeze) want_freeze = true;
       ++rd;
       if (h.stop != STOP_NONE) stopped = true;
       if (stopped && rd < enq) {
@@ -420,14 +525,13 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
     sweeps_done = last_sweeps;
     stats.sweeps = sweeps_done;
     // ---- x += H/S, r = b - A x (FP64), ||r|| ----
-    SweepArgs inf = p->sweep_args(2, p->msg[p->cur], nullptr);
-    inf.xacc = x;
-    TRY_HIP(launch_sweep(inf, s));
-    TRY_HIP(launch_residual(p->fp32, p->group, p->n, p->A.row_ptr, p->A.col, p->A.val, b, x,
+    TRY_HIP(p->infer(x, nullptr, s));
+    TRY_HIP(launch_residual(p->fp32, p->group, p->nres_blocks, p->n, p->A.row_ptr, p->A.col, p->A.val, b, x,
                             p->rhs, nullptr, p->sumpart, s));
     HostReadout rr;
     if ((rc = p->read_sum(s, &rr))) return finish(rc);
     const double rel = std::sqrt(rr.sum) / bn;
+    rel_prev = rel;
     stats.rel_residual = rel;
     stats.residual_per_eq = std::sqrt(rr.sum) / p->n;
     if (rr.flags & FLAG_BREAKDOWN) { status = GABP_ERR_BREAKDOWN; break; }
@@ -441,14 +545,10 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
       break;
     }
     // restart: zero the mean messages, keep the precision messages
-    TRY_HIP(launch_zero_h(p->fp32, p->E, p->msg[p->cur], s));
+    TRY_HIP(p->restart(s));
     stats.restarts += 1;
   }
-  if (marg_prec) {
-    SweepArgs a = p->sweep_args(2, p->msg[p->cur], nullptr);
-    a.marg = marg_prec;
-    TRY_HIP(launch_sweep(a, s));
-  }
+  if (marg_prec) TRY_HIP(p->infer(nullptr, marg_prec, s));
   TRY_HIP(hipStreamSynchronize(s));
   return finish(status);
 }
@@ -481,9 +581,11 @@ int gabp_residual(const gabp_csr *A, const double *b, const double *x, double *r
   HostReadout *host = nullptr;
   hipEvent_t ev = nullptr;
   auto cleanup = [&](int code) {
-    hipFree(sum); hipFree(deg); hipFree(dpos); hipFree(flags);
-    if (host) hipHostFree(host);
-    if (ev) hipEventDestroy(ev);
+    void *bufs[] = {sum, deg, dpos, flags};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+    if (host) (void)hipHostFree(host);
+    if (ev) (void)hipEventDestroy(ev);
     return code;
   };
   if ((rc = from_hip(dalloc(&sum, nb, sizeof(double)))) ||
@@ -501,10 +603,10 @@ int gabp_residual(const gabp_csr *A, const double *b, const double *x, double *r
       (rc = from_hip(hipStreamSynchronize(s))))
     return cleanup(rc);
   if (hflags & FLAG_ARG) return cleanup(GABP_ERR_ARG);
-  if ((rc = from_hip(launch_residual(false, g, A->n, A->row_ptr, A->col, A->val, b, nullptr,
+  if ((rc = from_hip(launch_residual(false, g, nb, A->n, A->row_ptr, A->col, A->val, b, nullptr,
                                      nullptr, nullptr, sum, s))) ||
       (rc = from_hip(launch_readout(nullptr, 0, sum, nb, nullptr, nullptr, 0, 0, &host[0], s))) ||
-      (rc = from_hip(launch_residual(false, g, A->n, A->row_ptr, A->col, A->val, b, x, nullptr, r,
+      (rc = from_hip(launch_residual(false, g, nb, A->n, A->row_ptr, A->col, A->val, b, x, nullptr, r,
                                      sum, s))) ||
       (rc = from_hip(launch_readout(nullptr, 0, sum, nb, nullptr, nullptr, 0, 1, &host[1], s))) ||
       (rc = from_hip(hipEventRecord(ev, s))) || (rc = from_hip(hipEventSynchronize(ev))))

@@ -1,0 +1,60 @@
+// Device helpers shared by the sweep kernels: lane-group reductions and the
+// guarded maxima a check sweep publishes.
+#pragma once
+
+#include "gabp_internal.h"
+
+namespace gabp {
+
+template <int G, typename T>
+__device__ __forceinline__ T gsum(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+template <int G, typename T>
+__device__ __forceinline__ T gmax(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide maxima of four values (every thread of the block must call);
+// thread 0 writes them to part[blockIdx.x].
+__device__ __forceinline__ void block_publish(double d, double x, double dp, double pm,
+                                              BlockPartial *part) {
+  __shared__ double sh[4][kBlock / 64];
+  d = wave_max(d);
+  x = wave_max(x);
+  dp = wave_max(dp);
+  pm = wave_max(pm);
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = d; sh[1][w] = x; sh[2][w] = dp; sh[3][w] = pm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d = sh[0][0]; x = sh[1][0]; dp = sh[2][0]; pm = sh[3][0];
+    for (int k = 1; k < kBlock / 64; ++k) {
+      d = fmax(d, sh[0][k]); x = fmax(x, sh[1][k]); dp = fmax(dp, sh[2][k]); pm = fmax(pm, sh[3][k]);
+    }
+    BlockPartial b;
+    b.dmax = d; b.xmax = x; b.dpmax = dp; b.pmax = pm;
+    part[blockIdx.x] = b;
+  }
+}
+
+}  // namespace gabp

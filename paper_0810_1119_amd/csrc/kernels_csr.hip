@@ -13,31 +13,9 @@
 // gathered through rev[] (8 or 16 bytes each); out-messages are written
 // coalesced in the row's own slots.  Two buffers give the synchronous
 // (flooding) schedule of section III-C.
-#include "gabp_internal.h"
+#include "device_common.h"
 
 namespace gabp {
-
-// ---------------------------------------------------------------------------
-// small device helpers
-// ---------------------------------------------------------------------------
-template <int G, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // ---------------------------------------------------------------------------
 // plan build
@@ -180,7 +158,8 @@ template <typename T>
 __global__ void k_plan_edges(int n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                              const double *__restrict__ val, const int64_t *__restrict__ diagpos,
                              const int64_t *__restrict__ oprt64, int32_t *__restrict__ oprt,
-                             int32_t *__restrict__ rev, T *__restrict__ acoef,
+                             int32_t *__restrict__ ocol, int32_t *__restrict__ rev,
+                             T *__restrict__ acoef,
                              T *__restrict__ diag, uint32_t *__restrict__ flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > n) return;
@@ -209,6 +188,7 @@ __global__ void k_plan_edges(int n, const int64_t *__restrict__ rp, const int32_
       r = (int32_t)(oprt64[j] + (found - rp[j]) - (found > diagpos[j] ? 1 : 0));
     }
     rev[o] = r;
+    ocol[o] = j;
     acoef[o] = (T)val[k];
     ++o;
   }
@@ -217,15 +197,15 @@ __global__ void k_plan_edges(int n, const int64_t *__restrict__ rp, const int32_
 
 hipError_t launch_plan_edges(bool fp32, int n, const int64_t *rp, const int32_t *col,
                              const double *val, const int64_t *diagpos, const int64_t *oprt64,
-                             int32_t *oprt, int32_t *rev, void *acoef, void *diag,
+                             int32_t *oprt, int32_t *ocol, int32_t *rev, void *acoef, void *diag,
                              uint32_t *flags, hipStream_t s) {
   const dim3 grid((n + 1 + kBlock - 1) / kBlock);
   if (fp32)
     hipLaunchKernelGGL(k_plan_edges<float>, grid, dim3(kBlock), 0, s, n, rp, col, val, diagpos,
-                       oprt64, oprt, rev, (float *)acoef, (float *)diag, flags);
+                       oprt64, oprt, ocol, rev, (float *)acoef, (float *)diag, flags);
   else
     hipLaunchKernelGGL(k_plan_edges<double>, grid, dim3(kBlock), 0, s, n, rp, col, val, diagpos,
-                       oprt64, oprt, rev, (double *)acoef, (double *)diag, flags);
+                       oprt64, oprt, ocol, rev, (double *)acoef, (double *)diag, flags);
   return hipGetLastError();
 }
 
@@ -246,55 +226,79 @@ __global__ __launch_bounds__(kBlock) void k_csr_sweep(
     BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
   using V = typename Vec2<T>::type;
   constexpr int R = 4;
+  constexpr int RPB = kBlock / G;
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;  // uniform: inner solve already stopped
   const int lane = threadIdx.x % G;
-  const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  const bool active = row < n;
-  int beg = 0, end = 0;
-  if (active) {
-    beg = oprt[row];
-    end = oprt[row + 1];
-  }
-  // A1: aggregate the in-messages P_ki, h_ki (gathered through rev)
-  T pin[R], hin[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int e = beg + lane + r * G;
-    pin[r] = T(0);
-    hin[r] = T(0);
-    if (e < end) {
-      const V m = min[rev[e]];
-      pin[r] = m.x;
-      hin[r] = m.y;
+  double d = 0.0, ax = 0.0;
+  uint32_t f = 0;
+  bool zero = false;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    const bool active = row < n;
+    int beg = 0, end = 0;
+    if (active) {
+      beg = oprt[row];
+      end = oprt[row + 1];
     }
-  }
-  T S = T(0), H = T(0);
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    S += pin[r];
-    H += hin[r];
-  }
-  for (int e = beg + lane + R * G; e < end; e += G) {
-    const V m = min[rev[e]];
-    S += m.x;
-    H += m.y;
-  }
-  S = group_sum<G>(S);
-  H = group_sum<G>(H);
-  if (active) {
-    S += diag[row];
-    H += rhs[row];
-  }
-
-  // A2: every out-message subtracts the reverse (in-)message
-  if (MODE != 2) {
-    bool zero = false;
+    // A1: aggregate the in-messages P_ki, h_ki (gathered through rev)
+    T pin[R], hin[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int e = beg + lane + r * G;
+      pin[r] = T(0);
+      hin[r] = T(0);
       if (e < end) {
-        const T cav = S - pin[r];
-        const T cavh = H - hin[r];
+        const V m = min[rev[e]];
+        pin[r] = m.x;
+        hin[r] = m.y;
+      }
+    }
+    T S = T(0), H = T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      S += pin[r];
+      H += hin[r];
+    }
+    for (int e = beg + lane + R * G; e < end; e += G) {
+      const V m = min[rev[e]];
+      S += m.x;
+      H += m.y;
+    }
+    S = gsum<G>(S);
+    H = gsum<G>(H);
+    if (active) {
+      S += diag[row];
+      H += rhs[row];
+    }
+
+    // A2: every out-message subtracts the reverse (in-)message
+    if (MODE != 2) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = beg + lane + r * G;
+        if (e < end) {
+          const T cav = S - pin[r];
+          const T cavh = H - hin[r];
+          const T a = acoef[e];
+          zero |= (cav == T(0));
+          const T inv = T(1) / cav;
+          T P = -(a * a) * inv;
+          T h = -(a * cavh) * inv;
+          if (DAMP) {
+            const V o = min[e];
+            P = alpha * o.x + (T(1) - alpha) * P;
+            h = alpha * o.y + (T(1) - alpha) * h;
+          }
+          V out;
+          out.x = P;
+          out.y = h;
+          mout[e] = out;
+        }
+      }
+      for (int e = beg + lane + R * G; e < end; e += G) {
+        const V m = min[rev[e]];
+        const T cav = S - m.x;
+        const T cavh = H - m.y;
         const T a = acoef[e];
         zero |= (cav == T(0));
         const T inv = T(1) / cav;
@@ -311,76 +315,36 @@ __global__ __launch_bounds__(kBlock) void k_csr_sweep(
         mout[e] = out;
       }
     }
-    for (int e = beg + lane + R * G; e < end; e += G) {
-      const V m = min[rev[e]];
-      const T cav = S - m.x;
-      const T cavh = H - m.y;
-      const T a = acoef[e];
-      zero |= (cav == T(0));
-      const T inv = T(1) / cav;
-      T P = -(a * a) * inv;
-      T h = -(a * cavh) * inv;
-      if (DAMP) {
-        const V o = min[e];
-        P = alpha * o.x + (T(1) - alpha) * P;
-        h = alpha * o.y + (T(1) - alpha) * h;
-      }
-      V out;
-      out.x = P;
-      out.y = h;
-      mout[e] = out;
-    }
-    if (zero) atomicOr(sticky, FLAG_BREAKDOWN);
-  }
 
-  // A3: marginal means (check) or final inference
-  if (MODE >= 1) {
-    double d = 0.0, ax = 0.0;
-    uint32_t f = 0;
-    if (active && lane == 0) {
+    // A3: marginal means (check) or final inference
+    if (MODE >= 1 && active && lane == 0) {
       if (S == T(0)) f |= FLAG_BREAKDOWN;
       const T x = H / S;
       if (!isfinite(x)) f |= FLAG_NONFINITE;
       if (MODE == 1) {
-        d = (double)fabs(x - xprev[row]);
+        d = fmax(d, (double)fabs(x - xprev[row]));
         xprev[row] = x;
       } else {
         if (xacc) xacc[row] += (double)H / (double)S;
         if (marg) marg[row] = (double)S;
       }
-      ax = (double)fabs(x);
-    }
-    if (f) atomicOr(sticky, f);
-    if (MODE == 1) {
-      __shared__ double sd[kBlock / 64], sx[kBlock / 64];
-      d = wave_max(d);
-      ax = wave_max(ax);
-      const int w = threadIdx.x / 64;
-      if ((threadIdx.x & 63) == 0) {
-        sd[w] = d;
-        sx[w] = ax;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double dm = sd[0], xm = sx[0];
-#pragma unroll
-        for (int k = 1; k < kBlock / 64; ++k) {
-          dm = fmax(dm, sd[k]);
-          xm = fmax(xm, sx[k]);
-        }
-        part[blockIdx.x].dmax = dm;
-        part[blockIdx.x].xmax = xm;
-      }
+      ax = fmax(ax, (double)fabs(x));
     }
   }
+  if (zero) f |= FLAG_BREAKDOWN;
+  if (f) atomicOr(sticky, f);
+  if (MODE == 1) block_publish(d, ax, 0.0, 0.0, part);
 }
 
-int sweep_blocks(int n, int group) { return (n + (kBlock / group) - 1) / (kBlock / group); }
+int sweep_blocks(int n, int group, int cap) {
+  const int need = (n + (kBlock / group) - 1) / (kBlock / group);
+  return need < cap ? (need > 0 ? need : 1) : cap;
+}
 
 template <typename T, int G, int MODE, bool DAMP>
 static void launch_one(const SweepArgs &a, hipStream_t s) {
   using V = typename Vec2<T>::type;
-  hipLaunchKernelGGL((k_csr_sweep<T, G, MODE, DAMP>), dim3(sweep_blocks(a.n, G)), dim3(kBlock),
+  hipLaunchKernelGGL((k_csr_sweep<T, G, MODE, DAMP>), dim3(a.grid), dim3(kBlock),
                      0, s, a.n, a.oprt, a.rev, (const T *)a.acoef, (const T *)a.diag,
                      (const T *)a.rhs, (const V *)a.msg_in, (V *)a.msg_out, (T)a.alpha,
                      (T *)a.xprev, a.xacc, a.marg, a.part, a.sticky, a.ctl);
@@ -421,19 +385,22 @@ __global__ __launch_bounds__(kBlock) void k_csr_residual(
     int n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
     T *__restrict__ rT, double *__restrict__ r64, double *__restrict__ sumpart) {
+  constexpr int RPB = kBlock / G;
   const int lane = threadIdx.x % G;
-  const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  const bool active = row < n;
-  double acc = 0.0;
-  if (active && x != nullptr)
-    for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += G) acc += val[k] * x[col[k]];
-  acc = group_sum<G>(acc);
   double sq = 0.0;
-  if (active && lane == 0) {
-    const double ri = b[row] - acc;
-    if (rT) rT[row] = (T)ri;
-    if (r64) r64[row] = ri;
-    sq = ri * ri;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    const bool active = row < n;
+    double acc = 0.0;
+    if (active && x != nullptr)
+      for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += G) acc += val[k] * x[col[k]];
+    acc = gsum<G>(acc);
+    if (active && lane == 0) {
+      const double ri = b[row] - acc;
+      if (rT) rT[row] = (T)ri;
+      if (r64) r64[row] = ri;
+      sq += ri * ri;
+    }
   }
   __shared__ double sh[kBlock / 64];
   sq = wave_sum(sq);
@@ -447,13 +414,14 @@ __global__ __launch_bounds__(kBlock) void k_csr_residual(
   }
 }
 
-int residual_blocks(int n, int group) { return sweep_blocks(n, group); }
+int residual_blocks(int n, int group, int cap) { return sweep_blocks(n, group, cap); }
 
 template <typename T>
-static hipError_t residual_group(int group, int n, const int64_t *rp, const int32_t *col,
-                                 const double *val, const double *b, const double *x, T *rT,
-                                 double *r64, double *sumpart, hipStream_t s) {
-  const dim3 grid(residual_blocks(n, group));
+static hipError_t residual_group(int group, int nblk, int n, const int64_t *rp,
+                                 const int32_t *col, const double *val, const double *b,
+                                 const double *x, T *rT, double *r64, double *sumpart,
+                                 hipStream_t s) {
+  const dim3 grid(nblk);
   switch (group) {
     case 4: hipLaunchKernelGGL((k_csr_residual<T, 4>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
     case 8: hipLaunchKernelGGL((k_csr_residual<T, 8>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
@@ -465,78 +433,80 @@ static hipError_t residual_group(int group, int n, const int64_t *rp, const int3
   return hipGetLastError();
 }
 
-hipError_t launch_residual(bool fp32, int group, int n, const int64_t *rp, const int32_t *col,
-                           const double *val, const double *b, const double *x, void *rT,
-                           double *r64, double *sumpart, hipStream_t s) {
+hipError_t launch_residual(bool fp32, int group, int grid, int n, const int64_t *rp,
+                           const int32_t *col, const double *val, const double *b, const double *x,
+                           void *rT, double *r64, double *sumpart, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  return fp32 ? residual_group<float>(group, n, rp, col, val, b, x, (float *)rT, r64, sumpart, s)
-              : residual_group<double>(group, n, rp, col, val, b, x, (double *)rT, r64, sumpart, s);
+  return fp32 ? residual_group<float>(group, grid, n, rp, col, val, b, x, (float *)rT, r64, sumpart, s)
+              : residual_group<double>(group, grid, n, rp, col, val, b, x, (double *)rT, r64, sumpart, s);
 }
 
 // ---------------------------------------------------------------------------
 // readout: reduce partials in a fixed order, run the inner-solve controller,
 // publish to pinned host memory
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_readout(const BlockPartial *__restrict__ part, int nparts,
-                                                    const double *__restrict__ sumpart, int nsum,
-                                                    const uint32_t *__restrict__ sticky,
-                                                    Ctl *__restrict__ ctl, int sweeps_in_chunk,
-                                                    int seq, HostReadout *__restrict__ host) {
-  __shared__ double sd[kBlock / 64], sx[kBlock / 64], ss[kBlock / 64];
-  const bool skipped = (nparts > 0) && ctl->stop != STOP_NONE;
-  double d = 0.0, x = 0.0, s = 0.0;
-  if (!skipped)
-    for (int k = threadIdx.x; k < nparts; k += kBlock) {
-      d = fmax(d, part[k].dmax);
-      x = fmax(x, part[k].xmax);
-      if (!isfinite(part[k].dmax)) d = part[k].dmax;  // propagate NaN / inf
-    }
+__global__ __launch_bounds__(kBlock) void k_readout(
+    const BlockPartial *__restrict__ part, int nparts, const double *__restrict__ sumpart, int nsum,
+    const uint32_t *__restrict__ sticky, Ctl *__restrict__ ctl, int sweeps_in_chunk, int seq,
+    HostReadout *__restrict__ host) {
+  __shared__ double sh[5][kBlock / 64];
+  double s = 0.0, d = 0.0, x = 0.0, dp = 0.0, pm = 0.0;
   for (int k = threadIdx.x; k < nsum; k += kBlock) s += sumpart[k];
+  for (int k = threadIdx.x; k < nparts; k += kBlock) {
+    const BlockPartial b = part[k];
+    d = fmax(d, b.dmax);
+    x = fmax(x, b.xmax);
+    dp = fmax(dp, b.dpmax);
+    pm = fmax(pm, b.pmax);
+  }
+  s = wave_sum(s);
   d = wave_max(d);
   x = wave_max(x);
-  s = wave_sum(s);
+  dp = wave_max(dp);
+  pm = wave_max(pm);
+  const int w = threadIdx.x / 64;
   if ((threadIdx.x & 63) == 0) {
-    sd[threadIdx.x / 64] = d;
-    sx[threadIdx.x / 64] = x;
-    ss[threadIdx.x / 64] = s;
+    sh[0][w] = s; sh[1][w] = d; sh[2][w] = x; sh[3][w] = dp; sh[4][w] = pm;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  d = sd[0]; x = sx[0]; s = ss[0];
+  s = sh[0][0]; d = sh[1][0]; x = sh[2][0]; dp = sh[3][0]; pm = sh[4][0];
   for (int k = 1; k < kBlock / 64; ++k) {
-    d = fmax(d, sd[k]);
-    x = fmax(x, sx[k]);
-    s += ss[k];
+    s += sh[0][k];
+    d = fmax(d, sh[1][k]);
+    x = fmax(x, sh[2][k]);
+    dp = fmax(dp, sh[3][k]);
+    pm = fmax(pm, sh[4][k]);
   }
   const uint32_t flags = sticky ? *sticky : 0u;
-  if (nparts > 0 && !skipped) {
+  if (nparts > 0 && ctl->stop == STOP_NONE) {
     ctl->sweeps += sweeps_in_chunk;
     ctl->checks += 1;
+    const double rel = d / fmax(x, 1e-300);
+    const double q = ctl->last_d > 0.0 ? d / ctl->last_d : 1.0;
+    const double est = (q < 1.0) ? rel * q / (1.0 - q) : 1e300;
+    ctl->est = est;
     ctl->last_d = d;
     ctl->last_x = x;
-    const double rel = d / fmax(x, 1e-300);
-    if (!isfinite(d) || !isfinite(x) || (flags & (FLAG_NONFINITE | FLAG_BREAKDOWN))) {
+    if (ctl->freeze_tol > 0.0 && dp <= ctl->freeze_tol * pm) ctl->freeze = 1;
+    if (flags & (FLAG_NONFINITE | FLAG_BREAKDOWN)) {
       ctl->stop = STOP_NONFINITE;
-    } else if (rel <= ctl->inner_tol) {
+    } else if (rel == 0.0 || est <= ctl->target) {
       ctl->stop = STOP_CONVERGED;
     } else {
-      // progress test: a stall only counts close to the arithmetic's floor
-      if (rel < 0.99 * ctl->best) {
-        ctl->best = rel;
-        ctl->stall = 0;
-      } else {
-        ctl->stall += 1;
-      }
-      if ((ctl->stall >= 8 && rel < ctl->stall_floor) || ctl->stall >= 32)
-        ctl->stop = STOP_STALLED;
+      ctl->stall = (rel < ctl->floor && q > 0.7) ? ctl->stall + 1 : 0;
+      if (ctl->stall >= 2) ctl->stop = STOP_STALLED;
     }
   }
   host->dmax = d;
   host->xmax = x;
   host->sum = s;
+  host->dpmax = dp;
+  host->pmax = pm;
   host->flags = flags;
   host->stop = ctl ? ctl->stop : 0u;
   host->sweeps = ctl ? ctl->sweeps : 0;
+  host->freeze = ctl ? ctl->freeze : 0;
   host->seq = seq;
   __threadfence_system();
 }
@@ -549,24 +519,26 @@ hipError_t launch_readout(const BlockPartial *part, int nparts, const double *su
   return hipGetLastError();
 }
 
-__global__ void k_ctl_reset(Ctl *ctl, double inner_tol, double stall_floor, int full) {
+__global__ void k_ctl_reset(Ctl *ctl, double target, double floor, double freeze_tol, int full) {
   if (threadIdx.x != 0) return;
+  ctl->freeze_tol = freeze_tol;
   ctl->stop = STOP_NONE;
   ctl->stall = 0;
-  ctl->best = 1e300;
-  ctl->inner_tol = inner_tol;
-  ctl->stall_floor = stall_floor;
+  ctl->target = target;
+  ctl->floor = floor;
   ctl->last_d = 0.0;
   ctl->last_x = 0.0;
+  ctl->est = 1e300;
   if (full) {
     ctl->sweeps = 0;
     ctl->checks = 0;
+    ctl->freeze = 0;
   }
 }
 
-hipError_t launch_ctl_reset(Ctl *ctl, double inner_tol, double stall_floor, bool full,
+hipError_t launch_ctl_reset(Ctl *ctl, double target, double floor, double freeze_tol, bool full,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, inner_tol, stall_floor,
+  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, target, floor, freeze_tol,
                      full ? 1 : 0);
   return hipGetLastError();
 }

@@ -1,0 +1,475 @@
+// GaBP sweeps in the "pair" layout, gfx950: the broadcast form of the paper's
+// Algorithm 2 (section V) mapped to memory.
+//
+// Every node i broadcasts its aggregate S_i = A_ii + sum_k P_ki and
+// H_i = b_i + sum_k h_ki (h = P mu).  Slot e = (i, j) of row i keeps both
+// directions of the edge: the message i -> j (P_ij, h_ij) that i sends and the
+// message j -> i (P_ji, h_ji) that i receives.  From the neighbour's broadcast
+// node i recomputes locally what j sends it, subtracting the message it sent j
+// (the retrieval "by means of a subtraction" of section V):
+//   P_ji' = -A_ij^2 / (S_j - P_ij),  h_ji' = -A_ij (H_j - h_ij) / (S_j - P_ij)
+// and what it sends j:
+//   P_ij' = -A_ij^2 / (S_i - P_ji),  h_ij' = -A_ij (H_i - h_ji) / (S_i - P_ji)
+// (eq. prec_message / mean_message times P).  Both copies of a message are
+// computed from bitwise-identical operands with FP contraction disabled, so
+// they stay bitwise identical.  The only
+// random access is the gather of (S_j, H_j) from an n-sized array; all slot
+// traffic is coalesced.
+//
+// Once every precision message has stopped changing (it never depends on b),
+// the "frozen" kernels keep P fixed and iterate the information only, with
+// per-slot coefficients c_ij = -A_ij / (S_i - P_ji):
+//   h_ij' = c_ij (H_i - h_ji),  h_ji' = c_ji (H_j - h_ij),  H_i' = b_i + sum h_ji'.
+// The gather then reads H_j alone (4 bytes per node).
+#include "device_common.h"
+
+namespace gabp {
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+// ---------------------------------------------------------------------------
+// full sweep (P and h), MODE 0 = sweep, 1 = sweep + check
+// ---------------------------------------------------------------------------
+template <typename T, int G, int MODE, bool DAMP>
+__global__ __launch_bounds__(kBlock) void k_pair_sweep(
+    int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
+    const T *__restrict__ acoef, const T *__restrict__ diag, const T *__restrict__ rhs,
+    const typename Vec4<T>::type *__restrict__ min, typename Vec4<T>::type *__restrict__ mout,
+    const typename Vec2<T>::type *__restrict__ sin, typename Vec2<T>::type *__restrict__ sout,
+    T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky,
+    const Ctl *__restrict__ ctl) {
+  // no FMA contraction: both stored copies of a message, and the node sums
+  // rebuilt from stored values, must round exactly like this sweep does
+#pragma clang fp contract(off)
+  using V4 = typename Vec4<T>::type;
+  using V2 = typename Vec2<T>::type;
+  constexpr int RPB = kBlock / G;  // rows per block per iteration
+  if (ctl != nullptr && ctl->stop != STOP_NONE) return;
+  const int lane = threadIdx.x % G;
+  double d = 0.0, ax = 0.0, dpb = 0.0, pmb = 0.0;
+  bool zero = false;
+  uint32_t f = 0;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    const bool active = row < n;
+    int beg = 0, end = 0;
+    V2 si;
+    si.x = T(0);
+    si.y = T(0);
+    if (active) {
+      beg = oprt[row];
+      end = oprt[row + 1];
+      si = sin[row];
+    }
+    T S = T(0), H = T(0), dp = T(0), pm = T(0);
+    for (int e = beg + lane; e < end; e += G) {
+      const int j = ocol[e];
+      const T a = acoef[e];
+      const V4 m = min[e];      // (P_ij, h_ij, P_ji, h_ji) of round t
+      const V2 sj = sin[j];     // broadcast of node j, round t
+      const T cj = sj.x - m.x;  // S_j - P_ij: cavity of j toward i
+      const T ci = si.x - m.z;  // S_i - P_ji: cavity of i toward j
+      zero |= (cj == T(0)) | (ci == T(0));
+      const T ij = T(1) / cj, ii = T(1) / ci;
+      T Pin = -(a * a) * ij, hin = -(a * (sj.y - m.y)) * ij;
+      T Pout = -(a * a) * ii, hout = -(a * (si.y - m.w)) * ii;
+      if (DAMP) {
+        const T b1 = T(1) - alpha;
+        Pin = alpha * m.z + b1 * Pin;
+        hin = alpha * m.w + b1 * hin;
+        Pout = alpha * m.x + b1 * Pout;
+        hout = alpha * m.y + b1 * hout;
+      }
+      if (MODE == 1) {
+        dp = fmax(dp, fabs(Pout - m.x));
+        pm = fmax(pm, fabs(Pout));
+      }
+      V4 o;
+      o.x = Pout; o.y = hout; o.z = Pin; o.w = hin;
+      mout[e] = o;
+      S += Pin;
+      H += hin;
+    }
+    S = gsum<G>(S);
+    H = gsum<G>(H);
+    if (active) {
+      S += diag[row];
+      H += rhs[row];
+      if (lane == 0) {
+        V2 o;
+        o.x = S;
+        o.y = H;
+        sout[row] = o;
+        if (MODE == 1) {
+          if (S == T(0)) f |= FLAG_BREAKDOWN;
+          const T x = H / S;
+          if (!isfinite(x)) f |= FLAG_NONFINITE;
+          d = fmax(d, (double)fabs(x - xprev[row]));
+          xprev[row] = x;
+          ax = fmax(ax, (double)fabs(x));
+        }
+      }
+    }
+    if (MODE == 1) {
+      dpb = fmax(dpb, (double)dp);
+      pmb = fmax(pmb, (double)pm);
+    }
+  }
+  if (zero) f |= FLAG_BREAKDOWN;
+  if (f) atomicOr(sticky, f);
+  if (MODE == 1) block_publish(d, ax, dpb, pmb, part);
+}
+
+// Aggregate (S, H) from the slots' incoming messages: used after reset,
+// message import and restarts.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_pair_aggregate(
+    int n, const int32_t *__restrict__ oprt, const T *__restrict__ diag, const T *__restrict__ rhs,
+    const typename Vec4<T>::type *__restrict__ msg, typename Vec2<T>::type *__restrict__ sums) {
+#pragma clang fp contract(off)
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    const bool active = row < n;
+    T S = T(0), H = T(0);
+    if (active)
+      for (int e = oprt[row] + lane; e < oprt[row + 1]; e += G) {
+        S += msg[e].z;
+        H += msg[e].w;
+      }
+    S = gsum<G>(S);
+    H = gsum<G>(H);
+    if (active && lane == 0) {
+      typename Vec2<T>::type o;
+      o.x = S + diag[row];
+      o.y = H + rhs[row];
+      sums[row] = o;
+    }
+  }
+}
+
+// Zero every information field (restart) and re-aggregate H = rhs.
+template <typename T>
+__global__ void k_pair_zero_h(int64_t E, typename Vec4<T>::type *__restrict__ msg) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) {
+    msg[e].y = T(0);
+    msg[e].w = T(0);
+  }
+}
+
+// x += H / S (FP64 accumulate) and/or marginal precisions from the broadcast
+// array (full layout) or from the frozen (S, H) arrays.
+template <typename T>
+__global__ void k_pair_infer(int n, const typename Vec2<T>::type *__restrict__ sums,
+                             const T *__restrict__ Sfix, const T *__restrict__ Hfz,
+                             double *__restrict__ xacc, double *__restrict__ marg,
+                             uint32_t *__restrict__ sticky) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T S, H;
+  if (sums) {
+    S = sums[i].x;
+    H = sums[i].y;
+  } else {
+    S = Sfix[i];
+    H = Hfz[i];
+  }
+  if (S == T(0)) atomicOr(sticky, FLAG_BREAKDOWN);
+  if (xacc) xacc[i] += (double)H / (double)S;
+  if (marg) marg[i] = (double)S;
+}
+
+// ---------------------------------------------------------------------------
+// freeze: P has stopped changing; derive the fixed coefficients
+// ---------------------------------------------------------------------------
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_pair_freeze(
+    int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
+    const T *__restrict__ acoef, const typename Vec4<T>::type *__restrict__ msg,
+    const typename Vec2<T>::type *__restrict__ sums, typename Vec2<T>::type *__restrict__ coef,
+    typename Vec2<T>::type *__restrict__ hp, T *__restrict__ Sfix, T *__restrict__ Hfz) {
+#pragma clang fp contract(off)
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    if (row >= n) continue;
+    const T Si = sums[row].x;
+    for (int e = oprt[row] + lane; e < oprt[row + 1]; e += G) {
+      const int j = ocol[e];
+      const T a = acoef[e];
+      const auto m = msg[e];
+      typename Vec2<T>::type c, h;
+      c.x = -a / (Si - m.z);          // c_ij: out-message coefficient
+      c.y = -a / (sums[j].x - m.x);   // c_ji: in-message coefficient
+      h.x = m.y;
+      h.y = m.w;
+      coef[e] = c;
+      hp[e] = h;
+    }
+    if (lane == 0) {
+      Sfix[row] = Si;
+      Hfz[row] = sums[row].y;
+    }
+  }
+}
+
+// frozen sweep: information only.  MODE 0 = sweep, 1 = sweep + check.
+template <typename T, int G, int MODE, bool DAMP>
+__global__ __launch_bounds__(kBlock) void k_pair_frozen(
+    int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
+    const typename Vec2<T>::type *__restrict__ coef, const T *__restrict__ rhs,
+    const T *__restrict__ Sfix, const typename Vec2<T>::type *__restrict__ hin,
+    typename Vec2<T>::type *__restrict__ hout, const T *__restrict__ Hin, T *__restrict__ Hout,
+    T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky,
+    const Ctl *__restrict__ ctl) {
+#pragma clang fp contract(off)
+  using V2 = typename Vec2<T>::type;
+  constexpr int RPB = kBlock / G;
+  if (ctl != nullptr && ctl->stop != STOP_NONE) return;
+  const int lane = threadIdx.x % G;
+  double d = 0.0, ax = 0.0;
+  uint32_t f = 0;
+  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    const bool active = row < n;
+    int beg = 0, end = 0;
+    T Hi = T(0);
+    if (active) {
+      beg = oprt[row];
+      end = oprt[row + 1];
+      Hi = Hin[row];
+    }
+    T H = T(0);
+    for (int e = beg + lane; e < end; e += G) {
+      const V2 c = coef[e];
+      const V2 h = hin[e];               // (h_ij, h_ji)
+      const T Hj = Hin[ocol[e]];
+      T ho = c.x * (Hi - h.y);
+      T hi = c.y * (Hj - h.x);
+      if (DAMP) {
+        const T b1 = T(1) - alpha;
+        ho = alpha * h.x + b1 * ho;
+        hi = alpha * h.y + b1 * hi;
+      }
+      V2 o;
+      o.x = ho;
+      o.y = hi;
+      hout[e] = o;
+      H += hi;
+    }
+    H = gsum<G>(H);
+    if (active) {
+      H += rhs[row];
+      if (lane == 0) {
+        Hout[row] = H;
+        if (MODE == 1) {
+          const T x = H / Sfix[row];
+          if (!isfinite(x)) f |= FLAG_NONFINITE;
+          d = fmax(d, (double)fabs(x - xprev[row]));
+          xprev[row] = x;
+          ax = fmax(ax, (double)fabs(x));
+        }
+      }
+    }
+  }
+  if (f) atomicOr(sticky, f);
+  if (MODE == 1) block_publish(d, ax, 0.0, 0.0, part);
+}
+
+// restart in the frozen state: h = 0, H = rhs
+template <typename T>
+__global__ void k_frozen_restart(int64_t E, int n, typename Vec2<T>::type *__restrict__ hp,
+                                 const T *__restrict__ rhs, T *__restrict__ Hfz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) {
+    hp[e].x = T(0);
+    hp[e].y = T(0);
+  }
+  if (e < n) Hfz[e] = rhs[e];
+}
+
+// ---------------------------------------------------------------------------
+// export / import in CSR slot order (pair layout holds the out-message at .xy)
+// ---------------------------------------------------------------------------
+template <typename T, bool GET>
+__global__ void k_pair_io(int n, const int64_t *__restrict__ rp, const int64_t *__restrict__ diagpos,
+                          const int32_t *__restrict__ oprt, const int32_t *__restrict__ rev,
+                          typename Vec4<T>::type *__restrict__ msg, double *__restrict__ P,
+                          double *__restrict__ h) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t b = rp[i], e = rp[i + 1], dp = diagpos[i];
+  for (int64_t k = b; k < e; ++k) {
+    if (k == dp) {
+      if (GET) { P[k] = 0.0; h[k] = 0.0; }
+      continue;
+    }
+    const int64_t o = oprt[i] + (k - b) - (k > dp ? 1 : 0);
+    if (GET) {
+      P[k] = (double)msg[o].x;
+      h[k] = (double)msg[o].y;
+    } else {
+      // i -> j goes to this slot's out fields and to the in fields of (j, i)
+      msg[o].x = (T)P[k];
+      msg[o].y = (T)h[k];
+      msg[rev[o]].z = (T)P[k];
+      msg[rev[o]].w = (T)h[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int G, int MODE, bool DAMP>
+static void pair_one(const PairArgs &a, hipStream_t s) {
+  using V4 = typename Vec4<T>::type;
+  using V2 = typename Vec2<T>::type;
+  const dim3 grid(a.grid);
+  if (a.frozen)
+    hipLaunchKernelGGL((k_pair_frozen<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.n, a.oprt,
+                       a.ocol, (const V2 *)a.coef, (const T *)a.rhs, (const T *)a.Sfix,
+                       (const V2 *)a.msg_in, (V2 *)a.msg_out, (const T *)a.sums_in,
+                       (T *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part, a.sticky, a.ctl);
+  else
+    hipLaunchKernelGGL((k_pair_sweep<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.n, a.oprt,
+                       a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,
+                       (const V4 *)a.msg_in, (V4 *)a.msg_out, (const V2 *)a.sums_in,
+                       (V2 *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part, a.sticky, a.ctl);
+}
+
+template <typename T, int G>
+static void pair_mode(const PairArgs &a, hipStream_t s) {
+  if (a.mode == 1) a.damp ? pair_one<T, G, 1, true>(a, s) : pair_one<T, G, 1, false>(a, s);
+  else a.damp ? pair_one<T, G, 0, true>(a, s) : pair_one<T, G, 0, false>(a, s);
+}
+
+template <typename T>
+static hipError_t pair_group(const PairArgs &a, hipStream_t s) {
+  switch (a.group) {
+    case 4: pair_mode<T, 4>(a, s); break;
+    case 8: pair_mode<T, 8>(a, s); break;
+    case 16: pair_mode<T, 16>(a, s); break;
+    case 32: pair_mode<T, 32>(a, s); break;
+    case 64: pair_mode<T, 64>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_sweep(const PairArgs &a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  return a.fp32 ? pair_group<float>(a, s) : pair_group<double>(a, s);
+}
+
+template <typename T>
+static hipError_t aggregate_t(int group, int nblk, int n, const int32_t *oprt, const void *diag,
+                              const void *rhs, const void *msg, void *sums, hipStream_t s) {
+  using V4 = typename Vec4<T>::type;
+  using V2 = typename Vec2<T>::type;
+  const dim3 grid(nblk);
+  switch (group) {
+    case 4: hipLaunchKernelGGL((k_pair_aggregate<T, 4>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
+    case 8: hipLaunchKernelGGL((k_pair_aggregate<T, 8>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
+    case 16: hipLaunchKernelGGL((k_pair_aggregate<T, 16>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
+    case 32: hipLaunchKernelGGL((k_pair_aggregate<T, 32>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
+    case 64: hipLaunchKernelGGL((k_pair_aggregate<T, 64>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_aggregate(bool fp32, int group, int grid, int n, const int32_t *oprt,
+                                 const void *diag, const void *rhs, const void *msg, void *sums,
+                                 hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  return fp32 ? aggregate_t<float>(group, grid, n, oprt, diag, rhs, msg, sums, s)
+              : aggregate_t<double>(group, grid, n, oprt, diag, rhs, msg, sums, s);
+}
+
+hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((E + kBlock - 1) / kBlock));
+  if (fp32) hipLaunchKernelGGL(k_pair_zero_h<float>, grid, dim3(kBlock), 0, s, E, (float4 *)msg);
+  else hipLaunchKernelGGL(k_pair_zero_h<double>, grid, dim3(kBlock), 0, s, E, (double4 *)msg);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfix, const void *Hfz,
+                             double *xacc, double *marg, uint32_t *sticky, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((n + kBlock - 1) / kBlock);
+  if (fp32)
+    hipLaunchKernelGGL(k_pair_infer<float>, grid, dim3(kBlock), 0, s, n, (const float2 *)sums,
+                       (const float *)Sfix, (const float *)Hfz, xacc, marg, sticky);
+  else
+    hipLaunchKernelGGL(k_pair_infer<double>, grid, dim3(kBlock), 0, s, n, (const double2 *)sums,
+                       (const double *)Sfix, (const double *)Hfz, xacc, marg, sticky);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t freeze_t(int group, int nblk, int n, const int32_t *oprt, const int32_t *ocol,
+                           const void *acoef, const void *msg, const void *sums, void *coef,
+                           void *hp, void *Sfix, void *Hfz, hipStream_t s) {
+  using V4 = typename Vec4<T>::type;
+  using V2 = typename Vec2<T>::type;
+  const dim3 grid(nblk);
+#define FREEZE_CASE(GG)                                                                          \
+  case GG:                                                                                       \
+    hipLaunchKernelGGL((k_pair_freeze<T, GG>), grid, dim3(kBlock), 0, s, n, oprt, ocol,        \
+                       (const T *)acoef, (const V4 *)msg, (const V2 *)sums, (V2 *)coef, (V2 *)hp, \
+                       (T *)Sfix, (T *)Hfz);                                                     \
+    break;
+  switch (group) {
+    FREEZE_CASE(4) FREEZE_CASE(8) FREEZE_CASE(16) FREEZE_CASE(32) FREEZE_CASE(64)
+    default: return hipErrorInvalidValue;
+  }
+#undef FREEZE_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_freeze(bool fp32, int group, int grid, int n, const int32_t *oprt,
+                              const int32_t *ocol, const void *acoef, const void *msg,
+                              const void *sums, void *coef, void *hp, void *Sfix, void *Hfz,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  return fp32 ? freeze_t<float>(group, grid, n, oprt, ocol, acoef, msg, sums, coef, hp, Sfix, Hfz, s)
+              : freeze_t<double>(group, grid, n, oprt, ocol, acoef, msg, sums, coef, hp, Sfix, Hfz, s);
+}
+
+hipError_t launch_frozen_restart(bool fp32, int64_t E, int n, void *hp, const void *rhs, void *Hfz,
+                                 hipStream_t s) {
+  const int64_t m = E > n ? E : n;
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((m + kBlock - 1) / kBlock));
+  if (fp32)
+    hipLaunchKernelGGL(k_frozen_restart<float>, grid, dim3(kBlock), 0, s, E, n, (float2 *)hp,
+                       (const float *)rhs, (float *)Hfz);
+  else
+    hipLaunchKernelGGL(k_frozen_restart<double>, grid, dim3(kBlock), 0, s, E, n, (double2 *)hp,
+                       (const double *)rhs, (double *)Hfz);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_io(bool fp32, bool get, int n, const int64_t *rp, const int64_t *diagpos,
+                          const int32_t *oprt, const int32_t *rev, void *msg, double *P, double *h,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((n + kBlock - 1) / kBlock);
+  if (fp32) {
+    if (get) hipLaunchKernelGGL((k_pair_io<float, true>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, rev, (float4 *)msg, P, h);
+    else hipLaunchKernelGGL((k_pair_io<float, false>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, rev, (float4 *)msg, P, h);
+  } else {
+    if (get) hipLaunchKernelGGL((k_pair_io<double, true>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, rev, (double4 *)msg, P, h);
+    else hipLaunchKernelGGL((k_pair_io<double, false>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, rev, (double4 *)msg, P, h);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gabp

@@ -96,6 +96,8 @@ def test_toy_tree_table_on_gpu(G):
     G.gabp_plan_destroy(plan)
 
 
+LAYOUT = {"pair": 0, "gather": 1}
+
 CASES = {
     "sdd_ragged": lambda: W.sdd_random(3001, 5),
     "poisson2d_33": lambda: W.poisson2d(33),
@@ -110,13 +112,14 @@ CASES = {
 
 @pytest.mark.parametrize("case", sorted(CASES))
 @pytest.mark.parametrize("group", [0, 4, 16, 64])
-def test_fp64_trajectory_matches_oracle(G, case, group):
+@pytest.mark.parametrize("layout", ["pair", "gather"])
+def test_fp64_trajectory_matches_oracle(G, case, group, layout):
     """Round-by-round FP64 messages and means against Algorithm 2 of the oracle,
-    for several lanes-per-row choices (each covers several blocks and a
-    ragged last block)."""
+    for both message layouts and several lanes-per-row choices (each covers
+    several blocks and a ragged last block)."""
     m = CASES[case]()
     b = W.uniform_b(m.n, 1)
-    Ad, plan = _plan(G, m, fp32=False, group=group)
+    Ad, plan = _plan(G, m, fp32=False, group=group, layout=LAYOUT[layout])
     assert G.gabp_plan_reset(plan, dev(b)) == G.GABP_OK
     R = oracle.Rounds(m, b, algorithm=2)
     for t in range(1, 7):
@@ -137,10 +140,11 @@ def test_fp64_trajectory_matches_oracle(G, case, group):
 
 
 @pytest.mark.parametrize("case", ["sdd_ragged", "poisson3d_13x11x7", "varcoef_9x7x5"])
-def test_fp32_trajectory_matches_oracle(G, case):
+@pytest.mark.parametrize("layout", ["pair", "gather"])
+def test_fp32_trajectory_matches_oracle(G, case, layout):
     m = CASES[case]()
     b = W.uniform_b(m.n, 2)
-    Ad, plan = _plan(G, m, fp32=True)
+    Ad, plan = _plan(G, m, fp32=True, layout=LAYOUT[layout])
     assert G.gabp_plan_reset(plan, dev(b)) == G.GABP_OK
     R = oracle.Rounds(m, b, algorithm=2)
     for t in range(1, 5):
@@ -153,10 +157,11 @@ def test_fp32_trajectory_matches_oracle(G, case):
     G.gabp_plan_destroy(plan)
 
 
-def test_damped_trajectory_matches_oracle(G):
+@pytest.mark.parametrize("layout", ["pair", "gather"])
+def test_damped_trajectory_matches_oracle(G, layout):
     m = W.poisson3d(10, 9, 8, 0.01)
     b = W.uniform_b(m.n, 3)
-    Ad, plan = _plan(G, m, fp32=False, damping=0.5)
+    Ad, plan = _plan(G, m, fp32=False, damping=0.5, layout=LAYOUT[layout])
     assert G.gabp_plan_reset(plan, dev(b)) == G.GABP_OK
     R = oracle.Rounds(m, b, algorithm=2, damping=0.5)
     for t in range(1, 6):
@@ -206,11 +211,18 @@ def test_poisson32_fp64_to_1e10(G):
 
 
 @pytest.mark.parametrize("n,seed", [(20011, 1), (257, 2)])
-def test_sdd_fp32_refined_to_1e8(G, n, seed):
-    """Random SDD, FP32 messages + FP64 refinement to 1e-8 (Theorem 1 class)."""
+@pytest.mark.parametrize("variant", [dict(layout=0, freeze=1), dict(layout=0, freeze=0),
+                                     dict(layout=1)])
+def test_sdd_fp32_refined_to_1e8(G, n, seed, variant):
+    """Random SDD, FP32 messages + FP64 refinement to 1e-8 (Theorem 1 class),
+    pair layout with and without the settled-precision phase, gather layout."""
     m = W.sdd_random(n, seed)
     b = W.normal_b(n, seed)
-    rc, st, x = _solve(G, m, b, msg_fp32=1, tol=1e-8)
+    rc, st, x = _solve(G, m, b, msg_fp32=1, tol=1e-8, **variant)
+    if variant.get("layout") == 0 and variant.get("freeze"):
+        assert st.frozen_sweeps > 0
+    else:
+        assert st.frozen_sweeps == 0
     assert rc == G.GABP_OK, G.status_name(rc)
     _, rn = oracle.residual(m, b, x)
     assert rn / np.linalg.norm(b) <= 1e-8
@@ -291,17 +303,19 @@ def test_edge_cases(G):
     np.testing.assert_allclose(x, np.linalg.solve([[3, 1], [1, 2]], [1, 1]), rtol=1e-13)
 
 
-def test_checkpoint_resume_bitwise(G):
+@pytest.mark.parametrize("layout", ["pair", "gather"])
+def test_checkpoint_resume_bitwise(G, layout):
     """Exported messages restore a plan exactly: 5 + 5 sweeps == 10 sweeps."""
     m = W.sdd_random(4001, 9)
     b = W.normal_b(m.n, 9)
-    _, p1 = _plan(G, m, fp32=True)
+    L = LAYOUT[layout]
+    _, p1 = _plan(G, m, fp32=True, layout=L)
     G.gabp_plan_reset(p1, dev(b)); G.gabp_plan_sweeps(p1, 10)
     P10, h10 = _messages(G, p1, m.nnz)
-    _, p2 = _plan(G, m, fp32=True)
+    _, p2 = _plan(G, m, fp32=True, layout=L)
     G.gabp_plan_reset(p2, dev(b)); G.gabp_plan_sweeps(p2, 5)
     P5, h5 = _messages(G, p2, m.nnz)
-    _, p3 = _plan(G, m, fp32=True)
+    _, p3 = _plan(G, m, fp32=True, layout=L)
     G.gabp_plan_reset(p3, dev(b))
     assert G.gabp_plan_set_messages(p3, dev(P5), dev(h5)) == G.GABP_OK
     G.gabp_plan_sweeps(p3, 5)
