@@ -173,6 +173,38 @@ int gabp_plan_get_messages(gabp_plan *plan, double *P, double *h, hipStream_t st
 int gabp_plan_set_messages(gabp_plan *plan, const double *P, const double *h,
                            hipStream_t stream);
 
+/* ---- Structured grids: the finite-difference Poisson operators of ----------
+ * section IX (5-point in 2-D, 7-point in 3-D), with constant or variable
+ * coefficients, as a stack of independent grids.  Node index
+ * i = x + nx (y + ny z) within a grid (natural row ordering), grid t of the
+ * stack holding nodes [t n, (t + 1) n), n = nx ny nz.  A_ij is nonzero only
+ * between face neighbours; symmetry holds by construction. */
+typedef struct {
+  int32_t nx, ny, nz;        /* extent of one grid, >= 1; nz = 1: 5-point 2-D stencil */
+  int32_t batch;             /* independent grids in the stack, >= 1 */
+  const double *diag;        /* device [batch n] A_ii, or NULL: diag_value everywhere */
+  double diag_value;
+  const double *cx, *cy, *cz;/* device [batch n] coupling of node i with its +x, +y, +z
+                                neighbour (A_{i,i+1}, A_{i,i+nx}, A_{i,i+nx ny}); values
+                                on a grid's last plane in that direction are ignored.
+                                All NULL: off_value on every interior face (cz may be
+                                NULL when nz = 1) */
+  double off_value;
+} gabp_grid;
+
+/* Plan, one-call solve and FP64 residual for grids; same conventions as the
+ * CSR entry points.  Messages of a grid plan (get/set_messages) are laid out
+ * direction-major: [6][batch n] for the directions +x, -x, +y, -y, +z, -z,
+ * entries without an edge read as 0.  A zero or non-finite coefficient is
+ * GABP_ERR_ZERO_DIAG / GABP_ERR_ARG; more than 2^31 - 1 nodes is
+ * GABP_ERR_UNSUPPORTED. */
+int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **plan,
+                          hipStream_t stream);
+int gabp_solve_grid(const gabp_grid *A, const double *b, double *x, double *marg_prec,
+                    const gabp_opts *o, gabp_stats *st, hipStream_t stream);
+int gabp_residual_grid(const gabp_grid *A, const double *b, const double *x, double *r,
+                       double *rel_norm, hipStream_t stream);
+
 /* Library version string. */
 const char *gabp_version(void);
 

@@ -69,6 +69,8 @@ def _load():
                                          vp, vp, vp, C.POINTER(i32), C.POINTER(i32),
                                          C.POINTER(f64)]
         lib.orc_max_threads.restype = C.c_int
+        lib.orc_residual_grid.argtypes = [i32, i32, i32, i32, vp, f64, vp, vp, vp, f64, vp, vp, vp]
+        lib.orc_residual_grid.restype = f64
         _lib = lib
     return _lib
 
@@ -194,6 +196,18 @@ def residual(m, b, x):
     b, x = _f64(b, M.n), _f64(x, M.n)
     r = np.empty(M.n)
     nrm = _load().orc_residual(C.byref(M.c), _p(b), _p(x), _p(r))
+    return r, float(nrm)
+
+
+def residual_grid(nx, ny, nz, batch, b, x, diag=None, dval=0.0, cx=None, cy=None, cz=None,
+                  off=0.0):
+    """(r = b - A x, ||r||_2) for a stack of 5/7-point grids (see orc_residual_grid)."""
+    n = nx * ny * nz * batch
+    b, x = _f64(b, n), _f64(x, n)
+    arr = [None if a is None else _f64(a, n) for a in (diag, cx, cy, cz)]
+    r = np.empty(n)
+    nrm = _load().orc_residual_grid(nx, ny, nz, batch, _p(arr[0]), dval, _p(arr[1]), _p(arr[2]),
+                                    _p(arr[3]), off, _p(b), _p(x), _p(r))
     return r, float(nrm)
 
 

@@ -400,3 +400,33 @@ done:
   free(rev); free(diag); free(P2); free(M2); free(r); free(d); free(dprev);
   return status;
 }
+
+/* r = b - A x for a stack of `batch` grids nx x ny x nz (node x + nx (y + ny z)
+ * per grid) with the 5/7-point operator: diag[i] (or dval everywhere) on the
+ * diagonal and, between node i and its +x / +y / +z neighbour inside the same
+ * grid, cx[i] / cy[i] / cz[i] (or off everywhere when cx is NULL).  Returns
+ * ||r||_2; r nullable.  Same residual definition as orc_residual, written
+ * for the structured case so that full-size grids need no CSR. */
+double orc_residual_grid(int32_t nx, int32_t ny, int32_t nz, int32_t batch, const double *diag,
+                         double dval, const double *cx, const double *cy, const double *cz,
+                         double off, const double *b, const double *x, double *r) {
+  const int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
+  double ss = 0.0;
+  for (int64_t t = 0; t < batch; ++t)
+    for (int64_t z = 0; z < nz; ++z)
+      for (int64_t y = 0; y < ny; ++y)
+        for (int64_t xx = 0; xx < nx; ++xx) {
+          const int64_t i = t * n + xx + nx * (y + ny * z);
+          double ax = (diag ? diag[i] : dval) * x[i];
+          if (xx + 1 < nx) ax += (cx ? cx[i] : off) * x[i + 1];
+          if (xx > 0) ax += (cx ? cx[i - 1] : off) * x[i - 1];
+          if (y + 1 < ny) ax += (cy ? cy[i] : off) * x[i + nx];
+          if (y > 0) ax += (cy ? cy[i - nx] : off) * x[i - nx];
+          if (z + 1 < nz) ax += (cz ? cz[i] : off) * x[i + nxy];
+          if (z > 0) ax += (cz ? cz[i - nxy] : off) * x[i - nxy];
+          const double ri = b[i] - ax;
+          if (r) r[i] = ri;
+          ss += ri * ri;
+        }
+  return sqrt(ss);
+}

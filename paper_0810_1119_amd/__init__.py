@@ -15,4 +15,5 @@ from ._abi import (  # noqa: F401
     gabp_default_opts, gabp_solve, gabp_residual, gabp_plan_create, gabp_plan_destroy,
     gabp_plan_solve, gabp_plan_reset, gabp_plan_sweeps, gabp_plan_marginals,
     gabp_plan_get_messages, gabp_plan_set_messages, gabp_version,
+    DeviceGrid, gabp_plan_create_grid, gabp_solve_grid, gabp_residual_grid,
 )

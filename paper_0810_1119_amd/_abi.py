@@ -82,6 +82,9 @@ _sig = {
     "gabp_plan_get_messages": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gabp_plan_set_messages": (C.c_int, [_vp, _vp, _vp, _vp]),
     "gabp_version": (C.c_char_p, []),
+    "gabp_plan_create_grid": (C.c_int, [C.c_void_p, C.POINTER(Opts), C.POINTER(_vp), _vp]),
+    "gabp_solve_grid": (C.c_int, [C.c_void_p, _vp, _vp, _vp, C.POINTER(Opts), C.POINTER(Stats), _vp]),
+    "gabp_residual_grid": (C.c_int, [C.c_void_p, _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)
@@ -220,3 +223,63 @@ def gabp_plan_get_messages(plan, P, h, stream=None) -> int:
 def gabp_plan_set_messages(plan, P, h, stream=None) -> int:
     _check_f64(P, plan.A.nnz, "P"); _check_f64(h, plan.A.nnz, "h")
     return lib.gabp_plan_set_messages(plan.ptr, _ptr(P), _ptr(h), _stream(stream))
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("batch", C.c_int32),
+                ("diag", C.c_void_p), ("diag_value", C.c_double), ("cx", C.c_void_p),
+                ("cy", C.c_void_p), ("cz", C.c_void_p), ("off_value", C.c_double)]
+
+
+@dataclass
+class DeviceGrid:
+    """Stack of `batch` grids (nx x ny x nz each, natural node order) with the
+    5/7-point operator: constant (diag_value, off_value) or per-node diagonal
+    and per-face couplings cx, cy, cz (float64 CUDA tensors of batch*n)."""
+    nx: int
+    ny: int
+    nz: int = 1
+    batch: int = 1
+    diag: object = None
+    diag_value: float = 0.0
+    cx: object = None
+    cy: object = None
+    cz: object = None
+    off_value: float = 0.0
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz * self.batch
+
+    @property
+    def nnz(self) -> int:  # message slots of a grid plan: 6 directions per node
+        return 6 * self.n
+
+    def c(self) -> _Grid:
+        return _Grid(self.nx, self.ny, self.nz, self.batch, _ptr(self.diag), self.diag_value,
+                     _ptr(self.cx), _ptr(self.cy), _ptr(self.cz), self.off_value)
+
+
+def gabp_plan_create_grid(A: DeviceGrid, opts: Opts | None = None, stream=None):
+    h = C.c_void_p()
+    a = A.c()
+    rc = lib.gabp_plan_create_grid(C.byref(a), C.byref(opts) if opts is not None else None,
+                                   C.byref(h), _stream(stream))
+    return rc, (_PlanHandle(h.value, A) if rc == GABP_OK else None)
+
+
+def gabp_solve_grid(A: DeviceGrid, b, x, marg_prec=None, opts: Opts | None = None, stream=None):
+    _check_f64(b, A.n, "b"); _check_f64(x, A.n, "x"); _check_f64(marg_prec, A.n, "marg_prec")
+    st = Stats()
+    a = A.c()
+    rc = lib.gabp_solve_grid(C.byref(a), _ptr(b), _ptr(x), _ptr(marg_prec),
+                             C.byref(opts) if opts is not None else None, C.byref(st), _stream(stream))
+    return rc, st
+
+
+def gabp_residual_grid(A: DeviceGrid, b, x, r=None, stream=None):
+    _check_f64(b, A.n, "b"); _check_f64(x, A.n, "x"); _check_f64(r, A.n, "r")
+    rel = C.c_double(0.0)
+    a = A.c()
+    rc = lib.gabp_residual_grid(C.byref(a), _ptr(b), _ptr(x), _ptr(r), C.byref(rel), _stream(stream))
+    return rc, rel.value

@@ -1,0 +1,287 @@
+// C ABI entry points shared by every matrix kind, and the solve loop.
+//
+// A solve is a sequence of inner GaBP solves with FP64 refinement between
+// them:
+//   x = 0, r = b
+//   repeat: sweeps from the current messages with right-hand side r until the
+//           marginal means settle (device-side controller), then
+//           x += H/S (FP64), r = b - A x (FP64), stop when ||r||/||b|| <= tol,
+//           else zero every h (mean) message and keep every P message -- the
+//           precision messages do not depend on the right-hand side
+//           (Algorithm 1 never reads b in the P update).
+// Sweeps are issued in chunks of `check_every` (even) launches, the last one
+// also checking the means; a single-thread readout kernel decides on the
+// device whether the inner solve is done and publishes its state to pinned
+// host memory.  The host keeps two chunks in flight, so the GPU never waits
+// for the host; chunks queued after the device decided to stop return at
+// once.  When the engine supports it and the controller reports that every
+// precision message has settled, the host switches to information-only
+// sweeps (one freeze launch, then frozen chunks).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "engine.h"
+
+namespace gabp {
+
+Engine::~Engine() {
+  void *bufs[] = {part, sumpart, sticky, ctl, xprev};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  if (host) (void)hipHostFree(host);
+  if (events)
+    for (int k = 0; k < kRing; ++k) {
+      (void)hipEventDestroy(ev_beg[k]);
+      (void)hipEventDestroy(ev_end[k]);
+      (void)hipEventDestroy(ev_done[k]);
+    }
+}
+
+int Engine::init_common(hipStream_t s) {
+  (void)s;
+  int st;
+  if ((st = from_hip(dalloc(&part, nparts, sizeof(BlockPartial)))) ||
+      (st = from_hip(dalloc(&sumpart, nsum, sizeof(double)))) ||
+      (st = from_hip(dalloc(&sticky, 1, sizeof(uint32_t)))) ||
+      (st = from_hip(dalloc(&ctl, 1, sizeof(Ctl)))) ||
+      (st = from_hip(dalloc(&xprev, n, tsz))))
+    return st;
+  if ((st = from_hip(hipHostMalloc((void **)&host, kRing * sizeof(HostReadout), hipHostMallocDefault))))
+    return st;
+  for (int k = 0; k < kRing; ++k) {
+    if ((st = from_hip(hipEventCreate(&ev_beg[k]))) || (st = from_hip(hipEventCreate(&ev_end[k]))) ||
+        (st = from_hip(hipEventCreateWithFlags(&ev_done[k], hipEventDisableTiming)))) {
+      for (int j = 0; j <= k; ++j) {
+        if (ev_beg[j]) (void)hipEventDestroy(ev_beg[j]);
+        if (ev_end[j]) (void)hipEventDestroy(ev_end[j]);
+        if (ev_done[j]) (void)hipEventDestroy(ev_done[j]);
+        ev_beg[j] = ev_end[j] = ev_done[j] = nullptr;
+      }
+      return st;
+    }
+  }
+  events = true;
+  return GABP_OK;
+}
+
+int Engine::read_sum(hipStream_t s, HostReadout *outv) {
+  const int slot = 0;
+  TRY_HIP(launch_readout(nullptr, 0, sumpart, nsum, sticky, ctl, 0, ++seq, &host[slot], s));
+  TRY_HIP(hipEventRecord(ev_done[slot], s));
+  TRY_HIP(hipEventSynchronize(ev_done[slot]));
+  *outv = host[slot];
+  return GABP_OK;
+}
+
+int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
+                 hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!p || (p->n > 0 && (!b || !x))) return GABP_ERR_ARG;
+  gabp_stats stats{};
+  stats.edges = p->E;
+  stats.status = GABP_OK;
+  const gabp_opts &o = p->o;
+  auto finish = [&](int status) {
+    stats.status = status;
+    stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats.edge_updates_per_s =
+        stats.seconds > 0 ? (double)stats.edges * stats.sweeps / stats.seconds : 0.0;
+    if (st) *st = stats;
+    return status;
+  };
+  if (p->n == 0) return finish(GABP_OK);
+
+  const int c = std::max(2, o.check_every + (o.check_every & 1));  // even: buffer parity kept
+  // Inner targets: the first pass runs to the message precision's floor (or
+  // to 0.3 tol if that is coarser); later passes only need the remaining
+  // factor tol / rel, with the same margin.  inner_tol > 0 fixes the target.
+  const double floor = p->fp32 ? 1e-6 : 1e-14;
+  // The freeze takes effect a few sweeps after the check that allows it (the
+  // chunks already queued still run full sweeps), so the precisions keep
+  // settling in between; 1e-6 leaves them at FP32 resolution by then on the
+  // workloads measured, and the FP64 refinement absorbs any remainder.
+  const bool freezing = o.freeze && p->can_freeze();
+  const double freeze_tol = freezing ? (p->fp32 ? 1e-6 : 1e-14) : -1.0;
+  auto target_for = [&](double rel) {
+    if (o.inner_tol > 0) return o.inner_tol;
+    return std::min(0.5, std::max(0.3 * o.tol / rel, p->fp32 ? 1e-7 : 1e-15));
+  };
+  if (freezing) TRY_HIP(p->ensure_frozen_buffers());
+  TRY_HIP(launch_fill_zero4(p->sticky, 1, s));
+  TRY_HIP(p->reset(b, s));  // also computes ||b||^2 into the residual partials
+  if (p->fp32) TRY_HIP(launch_fill_zero4(p->xprev, p->n, s));
+  else TRY_HIP(launch_fill_zero(p->xprev, p->n, s));
+  TRY_HIP(launch_fill_zero(x, p->n, s));
+  TRY_HIP(launch_ctl_reset(p->ctl, target_for(1.0), floor, freeze_tol, true, s));
+  HostReadout r0;
+  int rc = p->read_sum(s, &r0);
+  if (rc) return finish(rc);
+  if (!std::isfinite(r0.sum)) return finish(GABP_ERR_ARG);
+  const double bn = std::sqrt(r0.sum);
+  if (bn == 0.0) {
+    stats.rel_residual = 0.0;
+    if (marg_prec) {
+      TRY_HIP(p->infer(nullptr, marg_prec, s));
+      TRY_HIP(hipStreamSynchronize(s));
+    }
+    return finish(GABP_OK);
+  }
+
+  int status = GABP_NOT_CONVERGED;
+  int sweeps_done = 0;
+  double rel_prev = 1.0;
+  for (int pass = 0;; ++pass) {
+    if (pass > 0) TRY_HIP(launch_ctl_reset(p->ctl, target_for(rel_prev), floor, freeze_tol, false, s));
+    // ---- inner solve: chunks of c sweeps, lookahead, device-side stop ----
+    const int budget = o.max_sweeps - sweeps_done;
+    int enq = 0, rd = 0, enq_sweeps = 0, last_sweeps = sweeps_done;
+    bool stopped = false, want_freeze = false;
+    bool chunk_frozen[kRing] = {};
+    while (true) {
+      while (!stopped && enq - rd < kLookahead && enq_sweeps < budget) {
+        const int slot = enq % kRing;
+        if (want_freeze && !p->frozen && freezing && p->frozen_ready()) TRY_HIP(p->freeze(s));
+        chunk_frozen[slot] = p->frozen;
+        for (int k = 0; k < c; ++k) {
+          if (k == 0) TRY_HIP(hipEventRecord(p->ev_beg[slot], s));
+          TRY_HIP(p->sweep(k == c - 1 ? 1 : 0, p->ctl, s));
+        }
+        TRY_HIP(hipEventRecord(p->ev_end[slot], s));
+        TRY_HIP(launch_readout(p->part, p->nparts, nullptr, 0, p->sticky, p->ctl, c, enq,
+                               &p->host[slot], s));
+        TRY_HIP(hipEventRecord(p->ev_done[slot], s));
+        ++enq;
+        enq_sweeps += c;
+      }
+      if (rd == enq) break;
+      const int slot = rd % kRing;
+      TRY_HIP(hipEventSynchronize(p->ev_done[slot]));
+      const HostReadout h = p->host[slot];
+      if (h.seq != rd) return finish(GABP_ERR_HIP);
+      stats.checks += 1;
+      if (h.sweeps > last_sweeps) {  // this chunk ran (not skipped)
+        float ms = 0.f;
+        TRY_HIP(hipEventElapsedTime(&ms, p->ev_beg[slot], p->ev_end[slot]));
+        stats.sweep_ms += ms;
+        if (chunk_frozen[slot]) {
+          stats.frozen_sweeps += h.sweeps - last_sweeps;
+          stats.frozen_sweep_ms += ms;
+        }
+        last_sweeps = h.sweeps;
+      }
+      if (h.freeze) want_freeze = true;
+      ++rd;
+      if (h.stop != STOP_NONE) stopped = true;
+      if (stopped && rd < enq) {
+        // drain: the remaining queued chunks are no-ops on the device
+        TRY_HIP(hipEventSynchronize(p->ev_done[(enq - 1) % kRing]));
+        rd = enq;
+      }
+    }
+    sweeps_done = last_sweeps;
+    stats.sweeps = sweeps_done;
+    // ---- x += H/S, r = b - A x (FP64), ||r|| ----
+    TRY_HIP(p->infer(x, nullptr, s));
+    TRY_HIP(p->residual(b, x, nullptr, s));
+    HostReadout rr;
+    if ((rc = p->read_sum(s, &rr))) return finish(rc);
+    const double rel = std::sqrt(rr.sum) / bn;
+    rel_prev = rel;
+    stats.rel_residual = rel;
+    stats.residual_per_eq = std::sqrt(rr.sum) / p->n;
+    if (rr.flags & FLAG_BREAKDOWN) { status = GABP_ERR_BREAKDOWN; break; }
+    if ((rr.flags & FLAG_NONFINITE) || !std::isfinite(rel) || rel > 1e6) {
+      status = GABP_ERR_DIVERGED;
+      break;
+    }
+    if (rel <= o.tol) { status = GABP_OK; break; }
+    if (stats.restarts >= o.max_restarts || sweeps_done >= o.max_sweeps) {
+      status = GABP_NOT_CONVERGED;
+      break;
+    }
+    // restart: zero the mean messages, keep the precision messages
+    TRY_HIP(p->restart(s));
+    stats.restarts += 1;
+  }
+  if (marg_prec) TRY_HIP(p->infer(nullptr, marg_prec, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  return finish(status);
+}
+
+}  // namespace gabp
+
+using namespace gabp;
+
+extern "C" {
+
+const char *gabp_version(void) { return "gabp-mi355x 0.3 (gfx950)"; }
+
+void gabp_default_opts(gabp_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->msg_fp32 = 1;
+  o->tol = 1e-8;
+  o->max_sweeps = 20000;
+  o->check_every = 2;
+  o->damping = 0.0;
+  o->inner_tol = 0.0;
+  o->max_restarts = 30;
+  o->group = 0;
+  o->layout = GABP_LAYOUT_PAIR;
+  o->grid_blocks = 0;
+  o->freeze = 1;
+}
+
+int gabp_plan_destroy(gabp_plan *p) {
+  if (!p) return GABP_ERR_ARG;
+  (void)hipDeviceSynchronize();
+  delete p->eng;
+  delete p;
+  return GABP_OK;
+}
+
+int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
+                    hipStream_t s) {
+  if (!p || !p->eng) return GABP_ERR_ARG;
+  return engine_solve(p->eng, b, x, marg_prec, st, s);
+}
+
+int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
+  if (!p || !p->eng || (p->eng->n > 0 && !b)) return GABP_ERR_ARG;
+  if (p->eng->n == 0) return GABP_OK;
+  TRY_HIP(launch_fill_zero4(p->eng->sticky, 1, s));
+  TRY_HIP(p->eng->reset(b, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  return GABP_OK;
+}
+
+int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
+  if (!p || !p->eng || count < 0) return GABP_ERR_ARG;
+  Engine *e = p->eng;
+  if (e->frozen) return GABP_ERR_ARG;  // trajectory access needs the full state (reset first)
+  for (int k = 0; k < count && e->n > 0; ++k) TRY_HIP(e->sweep(0, nullptr, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  return GABP_OK;
+}
+
+int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s) {
+  if (!p || !p->eng || (p->eng->n > 0 && !mean)) return GABP_ERR_ARG;
+  if (p->eng->n == 0) return GABP_OK;
+  TRY_HIP(launch_fill_zero(mean, p->eng->n, s));
+  TRY_HIP(p->eng->infer(mean, prec, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  return GABP_OK;
+}
+
+int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
+  if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
+  return p->eng->get_messages(P, h, s);
+}
+
+int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipStream_t s) {
+  if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
+  return p->eng->set_messages(P, h, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Host-side solver engine shared by every matrix kind.  An engine owns the
+// device state of one system (graph arrays, message buffers, right-hand side)
+// and knows how to launch its kernels; the refinement loop, the chunked
+// sweep schedule and the device-side controller are written once in
+// engine_solve() (api.cpp) on top of this interface.
+#pragma once
+
+#include <algorithm>
+
+#include "gabp_internal.h"
+
+namespace gabp {
+
+constexpr int kRing = 4;       // readout slots / events in flight
+constexpr int kLookahead = 2;  // chunks queued ahead of the one being read
+
+inline int from_hip(hipError_t e) {
+  if (e == hipSuccess) return GABP_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return GABP_ERR_NOMEM;
+  return GABP_ERR_HIP;
+}
+
+#define TRY_HIP(expr)                          \
+  do {                                         \
+    hipError_t _e = (expr);                    \
+    if (_e != hipSuccess) return from_hip(_e); \
+  } while (0)
+
+template <typename P>
+hipError_t dalloc(P **p, size_t count, size_t elem) {
+  *p = nullptr;
+  return hipMalloc((void **)p, std::max<size_t>(1, count) * elem);
+}
+
+struct Engine {
+  gabp_opts o{};
+  int32_t n = 0;      // unknowns
+  int64_t E = 0;      // directed edges (messages per sweep)
+  bool fp32 = true;
+  size_t tsz = 4;
+  int cur = 0;        // buffer holding the latest messages
+  bool frozen = false;
+  // controller plumbing
+  BlockPartial *part = nullptr;
+  int nparts = 0;     // blocks of a check launch
+  double *sumpart = nullptr;
+  int nsum = 0;       // blocks of a residual launch
+  uint32_t *sticky = nullptr;
+  Ctl *ctl = nullptr;
+  void *xprev = nullptr;
+  HostReadout *host = nullptr;
+  hipEvent_t ev_beg[kRing] = {}, ev_end[kRing] = {}, ev_done[kRing] = {};
+  bool events = false;
+  int seq = 0;
+
+  virtual ~Engine();
+  // allocate the controller plumbing (after n, nparts, nsum are known)
+  int init_common(hipStream_t s);
+
+  // one synchronous sweep from buffer cur into cur ^ 1 (mode 0: sweep,
+  // 1: sweep + check of the means); c = controller or NULL
+  virtual hipError_t sweep(int mode, const Ctl *c, hipStream_t s) = 0;
+  // x += H/S (FP64) and/or marginal precisions, from the current messages
+  virtual hipError_t infer(double *xacc, double *marg, hipStream_t s) = 0;
+  // zero every information message, keep the precisions (rhs already holds r)
+  virtual hipError_t restart(hipStream_t s) = 0;
+  // zero all messages, rhs = b, full state; ||b||^2 into the residual partials
+  virtual hipError_t reset(const double *b, hipStream_t s) = 0;
+  // rhs = b - A x (FP64, optionally r64 = the same), ||.||^2 into the partials
+  virtual hipError_t residual(const double *b, const double *x, double *r64, hipStream_t s) = 0;
+  // settled-precision phase
+  virtual bool can_freeze() const { return false; }
+  virtual hipError_t ensure_frozen_buffers() { return hipSuccess; }
+  virtual bool frozen_ready() const { return false; }
+  virtual hipError_t freeze(hipStream_t) { return hipErrorNotSupported; }
+  // trajectory access (full state only)
+  virtual int get_messages(double *P, double *h, hipStream_t s) = 0;
+  virtual int set_messages(const double *P, const double *h, hipStream_t s) = 0;
+
+  // readout of the residual partials only; waits for it
+  int read_sum(hipStream_t s, HostReadout *outv);
+};
+
+// refinement loop around chunked sweeps (api.cpp)
+int engine_solve(Engine *e, const double *b, double *x, double *marg, gabp_stats *st,
+                 hipStream_t s);
+
+}  // namespace gabp
+
+// the opaque plan of the C ABI
+struct gabp_plan {
+  gabp::Engine *eng = nullptr;
+};

@@ -1,0 +1,347 @@
+// General sparse matrices (CSR): plan construction on the device, the two
+// message layouts (pair: both directions per edge slot with node broadcasts;
+// gather: out-messages per slot with in-messages through the reverse-edge
+// index) and the settled-precision phase of the pair layout.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "engine.h"
+
+namespace gabp {
+namespace {
+
+// Lanes per row: about two lanes per edge of an average row (measured best on
+// random graphs of mean degree 8: 16 lanes), at least 4, at most a wave.
+int choose_group(int64_t n, int64_t E) {
+  const double d = n > 0 ? (double)E / (double)n : 0.0;
+  if (d < 3) return 4;
+  if (d < 6) return 8;
+  if (d < 12) return 16;
+  if (d < 24) return 32;
+  return 64;
+}
+
+bool valid_group(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
+
+int check_csr(const gabp_csr *A) {
+  if (!A || A->n < 0 || A->nnz < 0) return GABP_ERR_ARG;
+  if (A->n > 0 && (!A->row_ptr || !A->col || !A->val)) return GABP_ERR_ARG;
+  if (A->n == 0) return GABP_OK;
+  int64_t ends[2];
+  if (hipMemcpy(&ends[0], A->row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&ends[1], A->row_ptr + A->n, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return GABP_ERR_ARG;
+  if (ends[0] != 0 || ends[1] != A->nnz) return GABP_ERR_ARG;
+  return GABP_OK;
+}
+
+}  // namespace
+
+int check_opts(const gabp_opts *o) {
+  if (!(o->tol >= 0.0) || o->max_sweeps < 0 || o->check_every < 1 || !(o->damping >= 0.0) ||
+      !(o->damping < 1.0) || !(o->inner_tol >= 0.0) || o->max_restarts < 0 ||
+      (o->group != 0 && !valid_group(o->group)) || o->grid_blocks < 0 ||
+      (o->layout != GABP_LAYOUT_PAIR && o->layout != GABP_LAYOUT_GATHER))
+    return GABP_ERR_ARG;
+  return GABP_OK;
+}
+
+struct CsrEngine : Engine {
+  gabp_csr A{};
+  bool pair = true;
+  int group = 8;
+  int grid = 1;       // blocks of a row-kernel launch
+  int32_t *oprt = nullptr, *ocol = nullptr, *rev = nullptr;
+  int64_t *diagpos = nullptr;
+  void *acoef = nullptr, *diag = nullptr, *rhs = nullptr;
+  // gather layout: (P, h) out-message per slot; pair layout: (P_ij, h_ij, P_ji, h_ji)
+  void *msg[2] = {nullptr, nullptr};
+  void *sums[2] = {nullptr, nullptr};  // pair: (S, H) per node
+  // settled-precision phase (pair layout, allocated on first use)
+  void *coef = nullptr, *hp[2] = {nullptr, nullptr}, *Sfix = nullptr, *Hfz[2] = {nullptr, nullptr};
+
+  ~CsrEngine() override {
+    void *bufs[] = {oprt, ocol, rev, diagpos, acoef, diag, rhs, msg[0], msg[1], sums[0],
+                    sums[1], coef, hp[0], hp[1], Sfix, Hfz[0], Hfz[1]};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+  }
+
+  size_t msg_bytes() const { return (pair ? 4 : 2) * tsz; }
+
+  hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
+    hipError_t err;
+    if (!pair) {
+      SweepArgs a{};
+      a.grid = grid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
+      a.n = n; a.oprt = oprt; a.rev = rev; a.acoef = acoef; a.diag = diag; a.rhs = rhs;
+      a.msg_in = msg[cur]; a.msg_out = msg[cur ^ 1]; a.alpha = o.damping; a.xprev = xprev;
+      a.part = part; a.sticky = sticky; a.ctl = c;
+      err = launch_sweep(a, s);
+    } else {
+      PairArgs a{};
+      a.grid = grid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
+      a.frozen = frozen; a.n = n; a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
+      a.rhs = rhs; a.alpha = o.damping; a.xprev = xprev; a.part = part; a.sticky = sticky;
+      a.ctl = c;
+      if (frozen) {
+        a.coef = coef; a.Sfix = Sfix;
+        a.msg_in = hp[cur]; a.msg_out = hp[cur ^ 1]; a.sums_in = Hfz[cur]; a.sums_out = Hfz[cur ^ 1];
+      } else {
+        a.msg_in = msg[cur]; a.msg_out = msg[cur ^ 1]; a.sums_in = sums[cur]; a.sums_out = sums[cur ^ 1];
+      }
+      err = launch_pair_sweep(a, s);
+    }
+    cur ^= 1;
+    return err;
+  }
+
+  hipError_t infer(double *xacc, double *marg, hipStream_t s) override {
+    if (!pair) {
+      SweepArgs a{};
+      a.grid = grid; a.fp32 = fp32; a.group = group; a.mode = 2; a.n = n; a.oprt = oprt;
+      a.rev = rev; a.acoef = acoef; a.diag = diag; a.rhs = rhs; a.msg_in = msg[cur];
+      a.xacc = xacc; a.marg = marg; a.sticky = sticky;
+      return launch_sweep(a, s);
+    }
+    if (frozen) return launch_pair_infer(fp32, n, nullptr, Sfix, Hfz[cur], xacc, marg, sticky, s);
+    return launch_pair_infer(fp32, n, sums[cur], nullptr, nullptr, xacc, marg, sticky, s);
+  }
+
+  hipError_t restart(hipStream_t s) override {
+    if (!pair) return launch_zero_h(fp32, E, msg[cur], s);
+    if (frozen) return launch_frozen_restart(fp32, E, n, hp[cur], rhs, Hfz[cur], s);
+    hipError_t err = launch_pair_zero_h(fp32, E, msg[cur], s);
+    if (err != hipSuccess) return err;
+    return launch_pair_aggregate(fp32, group, grid, n, oprt, diag, rhs, msg[cur], sums[cur], s);
+  }
+
+  hipError_t reset(const double *b, hipStream_t s) override {
+    cur = 0;
+    frozen = false;
+    const int64_t words = E * (int64_t)msg_bytes() / 8;
+    hipError_t err;
+    if ((err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
+    if ((err = launch_fill_zero(msg[1], words, s)) != hipSuccess) return err;
+    if ((err = launch_residual(fp32, group, nsum, n, A.row_ptr, A.col, A.val, b, nullptr, rhs,
+                               nullptr, sumpart, s)) != hipSuccess)
+      return err;
+    if (pair) return launch_pair_aggregate(fp32, group, grid, n, oprt, diag, rhs, msg[0], sums[0], s);
+    return hipSuccess;
+  }
+
+  hipError_t residual(const double *b, const double *x, double *r64, hipStream_t s) override {
+    return launch_residual(fp32, group, nsum, n, A.row_ptr, A.col, A.val, b, x, rhs, r64,
+                           sumpart, s);
+  }
+
+  bool can_freeze() const override { return pair; }
+
+  hipError_t ensure_frozen_buffers() override {
+    struct { void **p; size_t count, elem; } need[] = {
+        {&coef, (size_t)E, 2 * tsz}, {&hp[0], (size_t)E, 2 * tsz}, {&hp[1], (size_t)E, 2 * tsz},
+        {&Sfix, (size_t)n, tsz},     {&Hfz[0], (size_t)n, tsz},    {&Hfz[1], (size_t)n, tsz}};
+    for (auto &b : need)
+      if (!*b.p) {
+        hipError_t err = dalloc(b.p, b.count, b.elem);
+        if (err != hipSuccess) return err;
+      }
+    return hipSuccess;
+  }
+
+  bool frozen_ready() const override {
+    return coef && hp[0] && hp[1] && Sfix && Hfz[0] && Hfz[1];
+  }
+
+  hipError_t freeze(hipStream_t s) override {
+    hipError_t err = launch_pair_freeze(fp32, group, grid, n, oprt, ocol, acoef, msg[cur],
+                                        sums[cur], coef, hp[cur], Sfix, Hfz[cur], s);
+    frozen = true;
+    return err;
+  }
+
+  int get_messages(double *P, double *h, hipStream_t s) override {
+    if (A.nnz > 0 && (!P || !h)) return GABP_ERR_ARG;
+    if (pair)
+      TRY_HIP(launch_pair_io(fp32, true, n, A.row_ptr, diagpos, oprt, rev, msg[cur], P, h, s));
+    else
+      TRY_HIP(launch_get_msgs(fp32, n, A.row_ptr, diagpos, oprt, msg[cur], P, h, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    return GABP_OK;
+  }
+
+  int set_messages(const double *P, const double *h, hipStream_t s) override {
+    if (A.nnz > 0 && (!P || !h)) return GABP_ERR_ARG;
+    if (pair) {
+      TRY_HIP(launch_pair_io(fp32, false, n, A.row_ptr, diagpos, oprt, rev, msg[cur], (double *)P,
+                             (double *)h, s));
+      TRY_HIP(launch_pair_aggregate(fp32, group, grid, n, oprt, diag, rhs, msg[cur], sums[cur], s));
+    } else {
+      TRY_HIP(launch_set_msgs(fp32, n, A.row_ptr, diagpos, oprt, msg[cur], P, h, s));
+    }
+    TRY_HIP(hipStreamSynchronize(s));
+    return GABP_OK;
+  }
+
+  // validate A on the device and build the edge arrays and reverse index
+  int build(hipStream_t s) {
+    int64_t *deg = nullptr, *oprt64 = nullptr, *tmp = nullptr;
+    uint32_t *flags = nullptr;
+    int st = GABP_OK;
+    auto fail = [&](int code) {
+      void *bufs[] = {deg, oprt64, tmp, flags};
+      for (void *b : bufs)
+        if (b) (void)hipFree(b);
+      return code;
+    };
+    if ((st = from_hip(dalloc(&deg, n, sizeof(int64_t)))) ||
+        (st = from_hip(dalloc(&diagpos, n, sizeof(int64_t)))) ||
+        (st = from_hip(dalloc(&oprt64, n + 1, sizeof(int64_t)))) ||
+        (st = from_hip(dalloc(&tmp, scan_tmp_elems(n), sizeof(int64_t)))) ||
+        (st = from_hip(dalloc(&flags, 1, sizeof(uint32_t)))))
+      return fail(st);
+    if ((st = from_hip(launch_fill_zero4(flags, 1, s))) ||
+        (st = from_hip(launch_plan_rows(n, A.nnz, A.row_ptr, A.col, A.val, deg, diagpos, flags, s))))
+      return fail(st);
+    uint32_t hflags = 0;
+    if ((st = from_hip(hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s))) ||
+        (st = from_hip(hipStreamSynchronize(s))))
+      return fail(st);
+    if (hflags & FLAG_ARG) return fail(GABP_ERR_ARG);
+    if (hflags & FLAG_ZERO_DIAG) return fail(GABP_ERR_ZERO_DIAG);
+    if ((st = from_hip(launch_scan(deg, oprt64, n, tmp, s)))) return fail(st);
+    int64_t e = 0;
+    if ((st = from_hip(hipMemcpyAsync(&e, oprt64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s))) ||
+        (st = from_hip(hipStreamSynchronize(s))))
+      return fail(st);
+    if (e >= (int64_t)INT32_MAX) return fail(GABP_ERR_UNSUPPORTED);
+    E = e;
+    if ((st = from_hip(dalloc(&oprt, n + 1, sizeof(int32_t)))) ||
+        (st = from_hip(dalloc(&ocol, E, sizeof(int32_t)))) ||
+        (st = from_hip(dalloc(&rev, E, sizeof(int32_t)))) ||
+        (st = from_hip(dalloc(&acoef, E, tsz))) || (st = from_hip(dalloc(&diag, n, tsz))))
+      return fail(st);
+    if ((st = from_hip(launch_plan_edges(fp32, n, A.row_ptr, A.col, A.val, diagpos, oprt64, oprt,
+                                         ocol, rev, acoef, diag, flags, s))))
+      return fail(st);
+    if ((st = from_hip(hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s))) ||
+        (st = from_hip(hipStreamSynchronize(s))))
+      return fail(st);
+    if (hflags & FLAG_ASYM) return fail(GABP_ERR_NOT_SYMMETRIC);
+    return fail(GABP_OK);
+  }
+};
+
+}  // namespace gabp
+
+using namespace gabp;
+
+extern "C" {
+
+int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
+  if (!plan) return GABP_ERR_ARG;
+  *plan = nullptr;
+  gabp_opts opts;
+  if (o) opts = *o;
+  else gabp_default_opts(&opts);
+  int st = check_csr(A);
+  if (st) return st;
+  if ((st = check_opts(&opts))) return st;
+  CsrEngine *e = new (std::nothrow) CsrEngine();
+  if (!e) return GABP_ERR_NOMEM;
+  e->A = *A;
+  e->o = opts;
+  e->n = A->n;
+  e->fp32 = opts.msg_fp32 != 0;
+  e->pair = opts.layout == GABP_LAYOUT_PAIR;
+  e->tsz = e->fp32 ? sizeof(float) : sizeof(double);
+  auto fail = [&](int code) {
+    delete e;
+    return code;
+  };
+  if (e->n > 0 && (st = e->build(s))) return fail(st);
+  e->group = opts.group ? opts.group : choose_group(e->n, e->E);
+  const int cap = opts.grid_blocks > 0 ? opts.grid_blocks : kMaxSweepBlocks;
+  e->grid = sweep_blocks(std::max(e->n, 1), e->group, cap);
+  e->nparts = e->grid;
+  e->nsum = residual_blocks(std::max(e->n, 1), e->group, cap);
+  if ((st = e->init_common(s))) return fail(st);
+  if ((st = from_hip(dalloc(&e->msg[0], e->E, e->msg_bytes()))) ||
+      (st = from_hip(dalloc(&e->msg[1], e->E, e->msg_bytes()))) ||
+      (st = from_hip(dalloc(&e->rhs, e->n, e->tsz))))
+    return fail(st);
+  if (e->pair && ((st = from_hip(dalloc(&e->sums[0], e->n, 2 * e->tsz))) ||
+                  (st = from_hip(dalloc(&e->sums[1], e->n, 2 * e->tsz)))))
+    return fail(st);
+  gabp_plan *p = new (std::nothrow) gabp_plan();
+  if (!p) return fail(GABP_ERR_NOMEM);
+  p->eng = e;
+  *plan = p;
+  return GABP_OK;
+}
+
+int gabp_solve(const gabp_csr *A, const double *b, double *x, double *marg_prec,
+               const gabp_opts *o, gabp_stats *st, hipStream_t s) {
+  gabp_plan *p = nullptr;
+  int rc = gabp_plan_create(A, o, &p, s);
+  if (rc) {
+    if (st) { std::memset(st, 0, sizeof(*st)); st->status = rc; }
+    return rc;
+  }
+  rc = gabp_plan_solve(p, b, x, marg_prec, st, s);
+  gabp_plan_destroy(p);
+  return rc;
+}
+
+int gabp_residual(const gabp_csr *A, const double *b, const double *x, double *r,
+                  double *rel_norm, hipStream_t s) {
+  int rc = check_csr(A);
+  if (rc) return rc;
+  if (!rel_norm || (A->n > 0 && (!b || !x))) return GABP_ERR_ARG;
+  if (A->n == 0) { *rel_norm = 0.0; return GABP_OK; }
+  const int64_t nnzE = A->nnz - A->n;
+  const int g = choose_group(A->n, std::max<int64_t>(0, nnzE));
+  const int nb = residual_blocks(A->n, g);
+  double *sum = nullptr;
+  int64_t *deg = nullptr, *dpos = nullptr;
+  uint32_t *flags = nullptr;
+  HostReadout *host = nullptr;
+  hipEvent_t ev = nullptr;
+  auto cleanup = [&](int code) {
+    void *bufs[] = {sum, deg, dpos, flags};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+    if (host) (void)hipHostFree(host);
+    if (ev) (void)hipEventDestroy(ev);
+    return code;
+  };
+  if ((rc = from_hip(dalloc(&sum, nb, sizeof(double)))) ||
+      (rc = from_hip(hipHostMalloc((void **)&host, 2 * sizeof(HostReadout), hipHostMallocDefault))) ||
+      (rc = from_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming))) ||
+      (rc = from_hip(dalloc(&deg, A->n, sizeof(int64_t)))) ||
+      (rc = from_hip(dalloc(&dpos, A->n, sizeof(int64_t)))) ||
+      (rc = from_hip(dalloc(&flags, 1, sizeof(uint32_t)))))
+    return cleanup(rc);
+  // column range and ordering are validated before any x[col] gather
+  uint32_t hflags = 0;
+  if ((rc = from_hip(launch_fill_zero4(flags, 1, s))) ||
+      (rc = from_hip(launch_plan_rows(A->n, A->nnz, A->row_ptr, A->col, A->val, deg, dpos, flags, s))) ||
+      (rc = from_hip(hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s))) ||
+      (rc = from_hip(hipStreamSynchronize(s))))
+    return cleanup(rc);
+  if (hflags & FLAG_ARG) return cleanup(GABP_ERR_ARG);
+  if ((rc = from_hip(launch_residual(false, g, nb, A->n, A->row_ptr, A->col, A->val, b, nullptr,
+                                     nullptr, nullptr, sum, s))) ||
+      (rc = from_hip(launch_readout(nullptr, 0, sum, nb, nullptr, nullptr, 0, 0, &host[0], s))) ||
+      (rc = from_hip(launch_residual(false, g, nb, A->n, A->row_ptr, A->col, A->val, b, x, nullptr,
+                                     r, sum, s))) ||
+      (rc = from_hip(launch_readout(nullptr, 0, sum, nb, nullptr, nullptr, 0, 1, &host[1], s))) ||
+      (rc = from_hip(hipEventRecord(ev, s))) || (rc = from_hip(hipEventSynchronize(ev))))
+    return cleanup(rc);
+  const double bn = std::sqrt(host[0].sum), rn = std::sqrt(host[1].sum);
+  *rel_norm = bn > 0 ? rn / bn : rn;
+  return cleanup(std::isfinite(*rel_norm) ? GABP_OK : GABP_ERR_ARG);
+}
+
+}  // extern "C"

@@ -1,0 +1,301 @@
+// Structured grids: 5-point / 7-point stencils with constant or variable
+// coefficients, batched along z.  Messages live in six direction-major
+// arrays; see kernels_grid.hip.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "engine.h"
+
+namespace gabp {
+
+int check_opts(const gabp_opts *o);  // engine_csr.cpp
+
+namespace {
+
+int check_grid(const gabp_grid *A, GridGeom *g) {
+  if (!A || A->nx < 1 || A->ny < 1 || A->nz < 1 || A->batch < 1) return GABP_ERR_ARG;
+  const int64_t N = (int64_t)A->nx * A->ny * A->nz * A->batch;
+  if (N >= (int64_t)INT32_MAX / 8) return GABP_ERR_UNSUPPORTED;  // 6 N message slots in int32 range
+  const bool any = A->cx || A->cy || A->cz;
+  if (any && (!A->cx || !A->cy || (A->nz > 1 && !A->cz))) return GABP_ERR_ARG;
+  if (!A->diag && (A->diag_value == 0.0)) return GABP_ERR_ZERO_DIAG;
+  if (!A->diag && !std::isfinite(A->diag_value)) return GABP_ERR_ARG;
+  if (!any && !std::isfinite(A->off_value)) return GABP_ERR_ARG;
+  g->nx = A->nx; g->ny = A->ny; g->nz = A->nz; g->batch = A->batch; g->N = (int)N;
+  return GABP_OK;
+}
+
+bool grid_varc(const gabp_grid *A) { return A->cx || A->diag; }
+
+// With variable coefficients every array must exist: constants the caller
+// left NULL are expanded into device arrays owned by `owned`.
+int expand_coefficients(const gabp_grid *A, int64_t N, GridCoef<double> *k,
+                        std::vector<double *> *owned) {
+  k->diag = A->diag; k->cx = A->cx; k->cy = A->cy; k->cz = A->cz;
+  k->dconst = A->diag_value; k->aconst = A->off_value;
+  if (!grid_varc(A)) return GABP_OK;
+  const double *const *src[4] = {&k->diag, &k->cx, &k->cy, &k->cz};
+  const double fill[4] = {A->diag_value, A->off_value, A->off_value, A->nz > 1 ? A->off_value : 0.0};
+  for (int q = 0; q < 4; ++q) {
+    if (*src[q]) continue;
+    std::vector<double> h((size_t)N, fill[q]);
+    double *d = nullptr;
+    int st;
+    if ((st = from_hip(dalloc(&d, N, sizeof(double))))) return st;
+    owned->push_back(d);
+    if ((st = from_hip(hipMemcpy(d, h.data(), (size_t)N * sizeof(double), hipMemcpyHostToDevice))))
+      return st;
+    *const_cast<const double **>(src[q]) = d;
+  }
+  return GABP_OK;
+}
+
+int64_t grid_edges(const gabp_grid *A) {
+  const int64_t per = (int64_t)(A->nx - 1) * A->ny * A->nz + (int64_t)A->nx * (A->ny - 1) * A->nz +
+                      (int64_t)A->nx * A->ny * (A->nz - 1);
+  return 2 * per * A->batch;
+}
+
+}  // namespace
+
+struct GridEngine : Engine {
+  gabp_grid A{};
+  GridGeom g{};
+  bool varc = false;
+  int grid = 1;
+  GridCoef<double> k64{};          // caller's FP64 coefficients (residual)
+  void *wdiag = nullptr, *wcx = nullptr, *wcy = nullptr, *wcz = nullptr;  // working copies
+  std::vector<double *> owned;     // expanded constant coefficients
+  void *rhs = nullptr;
+  void *msg[2] = {nullptr, nullptr};  // (P, h)[6][N]
+  void *coef = nullptr, *hh[2] = {nullptr, nullptr}, *Sfix = nullptr;  // frozen
+
+  ~GridEngine() override {
+    void *bufs[] = {wdiag, wcx, wcy, wcz, rhs, msg[0], msg[1], coef, hh[0], hh[1], Sfix};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+    for (double *b : owned) (void)hipFree(b);
+  }
+
+  int64_t slots() const { return 6 * (int64_t)g.N; }
+
+  GridArgs args(int mode, const Ctl *c) const {
+    GridArgs a{};
+    a.g = g; a.grid = grid; a.fp32 = fp32; a.varc = varc; a.damp = o.damping > 0.0 && mode != 2;
+    a.frozen = frozen; a.mode = mode;
+    a.diag = wdiag; a.cx = wcx; a.cy = wcy; a.cz = wcz;
+    a.dconst = A.diag_value; a.aconst = A.off_value;
+    a.rhs = rhs; a.coef = coef; a.Sfix = Sfix; a.alpha = o.damping; a.xprev = xprev;
+    a.part = part; a.sticky = sticky; a.ctl = c;
+    return a;
+  }
+
+  hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
+    GridArgs a = args(mode, c);
+    a.msg_in = frozen ? hh[cur] : msg[cur];
+    a.msg_out = frozen ? hh[cur ^ 1] : msg[cur ^ 1];
+    hipError_t err = launch_grid_sweep(a, s);
+    cur ^= 1;
+    return err;
+  }
+
+  hipError_t infer(double *xacc, double *marg, hipStream_t s) override {
+    GridArgs a = args(2, nullptr);
+    a.msg_in = frozen ? hh[cur] : msg[cur];
+    a.xacc = xacc;
+    a.marg = marg;
+    return launch_grid_sweep(a, s);
+  }
+
+  hipError_t restart(hipStream_t s) override {
+    if (frozen) return fp32 ? launch_fill_zero4(hh[cur], slots(), s) : launch_fill_zero(hh[cur], slots(), s);
+    return launch_grid_zero_h(fp32, slots(), msg[cur], s);
+  }
+
+  hipError_t reset(const double *b, hipStream_t s) override {
+    cur = 0;
+    frozen = false;
+    const int64_t words = slots() * (int64_t)(2 * tsz) / 8;
+    hipError_t err;
+    if ((err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
+    if ((err = launch_fill_zero(msg[1], words, s)) != hipSuccess) return err;
+    return launch_grid_residual(g, k64, varc, nsum, b, nullptr, rhs, fp32, nullptr, sumpart, s);
+  }
+
+  hipError_t residual(const double *b, const double *x, double *r64, hipStream_t s) override {
+    return launch_grid_residual(g, k64, varc, nsum, b, x, rhs, fp32, r64, sumpart, s);
+  }
+
+  bool can_freeze() const override { return true; }
+
+  hipError_t ensure_frozen_buffers() override {
+    struct { void **p; size_t count; } need[] = {
+        {&coef, (size_t)slots()}, {&hh[0], (size_t)slots()}, {&hh[1], (size_t)slots()},
+        {&Sfix, (size_t)g.N}};
+    for (auto &b : need)
+      if (!*b.p) {
+        hipError_t err = dalloc(b.p, b.count, tsz);
+        if (err != hipSuccess) return err;
+      }
+    return hipSuccess;
+  }
+
+  bool frozen_ready() const override { return coef && hh[0] && hh[1] && Sfix; }
+
+  hipError_t freeze(hipStream_t s) override {
+    GridArgs a = args(0, nullptr);
+    a.msg_in = msg[cur];
+    a.msg_out = hh[cur];
+    hipError_t err = launch_grid_freeze(a, s);
+    frozen = true;
+    return err;
+  }
+
+  int get_messages(double *P, double *h, hipStream_t s) override {
+    if (!P || !h) return GABP_ERR_ARG;
+    TRY_HIP(launch_grid_io(fp32, true, slots(), msg[cur], P, h, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    return GABP_OK;
+  }
+
+  int set_messages(const double *P, const double *h, hipStream_t s) override {
+    if (!P || !h) return GABP_ERR_ARG;
+    TRY_HIP(launch_grid_io(fp32, false, slots(), msg[cur], (double *)P, (double *)h, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    return GABP_OK;
+  }
+
+  // validate coefficients, build working-precision copies
+  int build(hipStream_t s) {
+    varc = grid_varc(&A);
+    const int64_t N = g.N;
+    int st;
+    if ((st = expand_coefficients(&A, N, &k64, &owned))) return st;
+    uint32_t *flags = nullptr;
+    if ((st = from_hip(dalloc(&flags, 1, sizeof(uint32_t))))) return st;
+    uint32_t hflags = 0;
+    hipError_t e1 = launch_fill_zero4(flags, 1, s);
+    if (e1 == hipSuccess) e1 = launch_grid_check(g, k64, varc, nsum, flags, s);
+    if (e1 == hipSuccess) e1 = hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
+    (void)hipFree(flags);
+    if (e1 != hipSuccess) return from_hip(e1);
+    if (hflags & FLAG_ARG) return GABP_ERR_ARG;
+    if (hflags & FLAG_ZERO_DIAG) return GABP_ERR_ZERO_DIAG;
+    if (varc) {
+      if ((st = from_hip(dalloc(&wdiag, N, tsz))) || (st = from_hip(dalloc(&wcx, N, tsz))) ||
+          (st = from_hip(dalloc(&wcy, N, tsz))) || (st = from_hip(dalloc(&wcz, N, tsz))))
+        return st;
+      if ((st = from_hip(launch_to_working(fp32, N, k64.diag, wdiag, s))) ||
+          (st = from_hip(launch_to_working(fp32, N, k64.cx, wcx, s))) ||
+          (st = from_hip(launch_to_working(fp32, N, k64.cy, wcy, s))) ||
+          (st = from_hip(launch_to_working(fp32, N, k64.cz, wcz, s))))  // NULL cz -> zeros
+        return st;
+    }
+    return GABP_OK;
+  }
+};
+
+}  // namespace gabp
+
+using namespace gabp;
+
+extern "C" {
+
+int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
+  if (!plan) return GABP_ERR_ARG;
+  *plan = nullptr;
+  gabp_opts opts;
+  if (o) opts = *o;
+  else gabp_default_opts(&opts);
+  int st;
+  if ((st = check_opts(&opts))) return st;
+  GridGeom g{};
+  if ((st = check_grid(A, &g))) return st;
+  GridEngine *e = new (std::nothrow) GridEngine();
+  if (!e) return GABP_ERR_NOMEM;
+  e->A = *A;
+  e->g = g;
+  e->o = opts;
+  e->n = g.N;
+  e->E = grid_edges(A);
+  e->fp32 = opts.msg_fp32 != 0;
+  e->tsz = e->fp32 ? sizeof(float) : sizeof(double);
+  const int cap = opts.grid_blocks > 0 ? opts.grid_blocks : kMaxSweepBlocks;
+  const int need = (g.N + kBlock - 1) / kBlock;
+  e->grid = need < cap ? need : cap;
+  e->nparts = e->grid;
+  e->nsum = e->grid;
+  auto fail = [&](int code) {
+    delete e;
+    return code;
+  };
+  if ((st = e->init_common(s))) return fail(st);
+  if ((st = e->build(s))) return fail(st);
+  if ((st = from_hip(dalloc(&e->msg[0], e->slots(), 2 * e->tsz))) ||
+      (st = from_hip(dalloc(&e->msg[1], e->slots(), 2 * e->tsz))) ||
+      (st = from_hip(dalloc(&e->rhs, g.N, e->tsz))))
+    return fail(st);
+  gabp_plan *p = new (std::nothrow) gabp_plan();
+  if (!p) return fail(GABP_ERR_NOMEM);
+  p->eng = e;
+  *plan = p;
+  return GABP_OK;
+}
+
+int gabp_solve_grid(const gabp_grid *A, const double *b, double *x, double *marg_prec,
+                    const gabp_opts *o, gabp_stats *st, hipStream_t s) {
+  gabp_plan *p = nullptr;
+  int rc = gabp_plan_create_grid(A, o, &p, s);
+  if (rc) {
+    if (st) { std::memset(st, 0, sizeof(*st)); st->status = rc; }
+    return rc;
+  }
+  rc = gabp_plan_solve(p, b, x, marg_prec, st, s);
+  gabp_plan_destroy(p);
+  return rc;
+}
+
+int gabp_residual_grid(const gabp_grid *A, const double *b, const double *x, double *r,
+                       double *rel_norm, hipStream_t s) {
+  GridGeom g{};
+  int rc = check_grid(A, &g);
+  if (rc) return rc;
+  if (!rel_norm || !b || !x) return GABP_ERR_ARG;
+  const bool varc = grid_varc(A);
+  GridCoef<double> k{};
+  std::vector<double *> owned;
+  if ((rc = expand_coefficients(A, g.N, &k, &owned))) {
+    for (double *d : owned) (void)hipFree(d);
+    return rc;
+  }
+  const int need = (g.N + kBlock - 1) / kBlock;
+  const int nb = need < kMaxSweepBlocks ? need : kMaxSweepBlocks;
+  double *sum = nullptr;
+  HostReadout *host = nullptr;
+  hipEvent_t ev = nullptr;
+  auto cleanup = [&](int code) {
+    if (sum) (void)hipFree(sum);
+    for (double *d : owned) (void)hipFree(d);
+    if (host) (void)hipHostFree(host);
+    if (ev) (void)hipEventDestroy(ev);
+    return code;
+  };
+  if ((rc = from_hip(dalloc(&sum, nb, sizeof(double)))) ||
+      (rc = from_hip(hipHostMalloc((void **)&host, 2 * sizeof(HostReadout), hipHostMallocDefault))) ||
+      (rc = from_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming))))
+    return cleanup(rc);
+  if ((rc = from_hip(launch_grid_residual(g, k, varc, nb, b, nullptr, nullptr, false, nullptr, sum, s))) ||
+      (rc = from_hip(launch_readout(nullptr, 0, sum, nb, nullptr, nullptr, 0, 0, &host[0], s))) ||
+      (rc = from_hip(launch_grid_residual(g, k, varc, nb, b, x, nullptr, false, r, sum, s))) ||
+      (rc = from_hip(launch_readout(nullptr, 0, sum, nb, nullptr, nullptr, 0, 1, &host[1], s))) ||
+      (rc = from_hip(hipEventRecord(ev, s))) || (rc = from_hip(hipEventSynchronize(ev))))
+    return cleanup(rc);
+  const double bn = std::sqrt(host[0].sum), rn = std::sqrt(host[1].sum);
+  *rel_norm = bn > 0 ? rn / bn : rn;
+  return cleanup(std::isfinite(*rel_norm) ? GABP_OK : GABP_ERR_ARG);
+}
+
+}  // extern "C"

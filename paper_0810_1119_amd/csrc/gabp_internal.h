@@ -177,4 +177,43 @@ hipError_t launch_pair_io(bool fp32, bool get, int n, const int64_t *rp, const i
                           const int32_t *oprt, const int32_t *rev, void *msg, double *P, double *h,
                           hipStream_t s);
 
+// ---- structured grids (kernels_grid.hip) ----
+struct GridGeom {
+  int nx, ny, nz, batch;
+  int N;  // nx * ny * nz * batch
+};
+template <typename T> struct GridCoef {
+  const T *diag, *cx, *cy, *cz;  // per node / per face (NULL when constant)
+  T dconst, aconst;              // constant diagonal and coupling
+};
+struct GridArgs {
+  GridGeom g;
+  int grid;            // blocks of the launch
+  bool fp32, varc, damp, frozen;
+  int mode;            // 0 sweep, 1 sweep + check, 2 means / precisions only
+  const void *diag, *cx, *cy, *cz;  // working-precision coefficient arrays (varc)
+  double dconst, aconst;
+  const void *rhs;
+  const void *msg_in;  // full: (P, h)[6][N]; frozen: h[6][N]
+  void *msg_out;
+  const void *coef, *Sfix;  // frozen coefficients c[6][N] and S
+  double alpha;
+  void *xprev;
+  double *xacc, *marg;
+  BlockPartial *part;
+  uint32_t *sticky;
+  const Ctl *ctl;
+};
+hipError_t launch_grid_sweep(const GridArgs &a, hipStream_t s);
+hipError_t launch_grid_freeze(const GridArgs &a, hipStream_t s);
+hipError_t launch_grid_residual(const GridGeom &g, const GridCoef<double> &k, bool varc, int grid,
+                                const double *b, const double *x, void *rT, bool rT32, double *r64,
+                                double *sumpart, hipStream_t s);
+hipError_t launch_grid_check(const GridGeom &g, const GridCoef<double> &k, bool varc, int grid,
+                             uint32_t *flags, hipStream_t s);
+hipError_t launch_to_working(bool fp32, int64_t m, const double *in, void *out, hipStream_t s);
+hipError_t launch_grid_zero_h(bool fp32, int64_t m, void *msg, hipStream_t s);
+hipError_t launch_grid_io(bool fp32, bool get, int64_t m, void *msg, double *P, double *h,
+                          hipStream_t s);
+
 }  // namespace gabp

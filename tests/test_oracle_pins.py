@@ -291,3 +291,19 @@ def test_thread_count_bitwise_identical():
     a = oracle.Rounds(m, b, algorithm=2, nthreads=1).step(7)
     c = oracle.Rounds(m, b, algorithm=2, nthreads=4).step(7)
     assert np.array_equal(a.P, c.P) and np.array_equal(a.Mu, c.Mu)
+
+
+@pytest.mark.parametrize("shape", [(5, 4, 3, 2, False, 0.01), (6, 5, 4, 3, True, 0.0),
+                                   (7, 6, 1, 2, False, 0.0), (6, 5, 1, 2, True, 0.0)])
+def test_structured_residual_matches_csr_residual(shape):
+    """The oracle's stencil residual (used where a CSR of the full grid is too
+    large) equals its CSR residual on the same operator."""
+    nx, ny, nz, bt, vc, sh = shape
+    m, c = W.grid_stack(nx, ny, nz, bt, varcoef=vc, shift=sh, seed=3)
+    rng = np.random.default_rng(1)
+    x, b = rng.standard_normal(m.n), rng.standard_normal(m.n)
+    r1, n1 = oracle.residual(m, b, x)
+    r2, n2 = oracle.residual_grid(nx, ny, nz, bt, b, x, c["diag"], c["dval"], c["cx"], c["cy"],
+                                  c["cz"], c["off"])
+    np.testing.assert_allclose(r2, r1, rtol=0, atol=1e-13 * np.abs(r1).max())
+    assert n2 == pytest.approx(n1, rel=1e-14)

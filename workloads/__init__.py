@@ -22,7 +22,7 @@ __all__ = [
     "CSR", "csr_from_coo", "csr_from_dense", "dense_from_csr",
     "poisson2d", "poisson3d", "poisson3d_varcoef", "grf_field",
     "sdd_random", "random_tree", "detection_batch", "DetectionBatch",
-    "uniform_b", "normal_b", "tree_diameter",
+    "uniform_b", "normal_b", "tree_diameter", "grid_stack", "block_diag_csr",
 ]
 
 
@@ -335,3 +335,51 @@ def detection_batch(batch: int, seed: int, kmin: int = 16, kmax: int = 256,
         y[y_off[t]:y_off[t + 1]] = yt
         x[x_off[t]:x_off[t + 1]] = xt
     return DetectionBatch(K, N, s2, S, y, x, s_off, y_off, x_off)
+
+
+def block_diag_csr(blocks) -> CSR:
+    """Block-diagonal CSR of independent systems (node offsets accumulate)."""
+    rows, cols, vals, off = [], [], [], 0
+    for m in blocks:
+        r = np.repeat(np.arange(m.n, dtype=np.int64), np.diff(m.row_ptr))
+        rows.append(r + off); cols.append(m.col.astype(np.int64) + off); vals.append(m.val)
+        off += m.n
+    return csr_from_coo(off, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+def grid_stack(nx: int, ny: int, nz: int, batch: int = 1, varcoef: bool = False,
+               shift: float = 0.0, seed: int = 0, ell: float = 8.0, with_csr: bool = True):
+    """A stack of `batch` independent grids with the 5-point (nz = 1) or
+    7-point operator.  Constant coefficients: A_ii = 2 dim + shift, A_ij = -1.
+    Variable: grid t uses poisson3d_varcoef(seed + t).  Returns (csr or None,
+    coefficients dict: diag, cx, cy, cz arrays of batch * n, or None with
+    dval/off constants)."""
+    n = nx * ny * nz
+    if not varcoef:
+        dim = 3 if nz > 1 else 2
+        coef = {"diag": None, "cx": None, "cy": None, "cz": None,
+                "dval": 2.0 * dim + shift, "off": -1.0}
+        csr = None
+        if with_csr:
+            one = poisson3d(nx, ny, nz, shift) if nz > 1 else poisson2d_rect(nx, ny, shift)
+            csr = block_diag_csr([one] * batch) if batch > 1 else one
+        return csr, coef
+    mats, faces = [], []
+    for t in range(batch):
+        m, f = poisson3d_varcoef(nx, ny, nz, seed + t, ell=ell)
+        mats.append(m); faces.append(f)
+    coef = {k: np.concatenate([f[k] for f in faces]) for k in ("diag", "cx", "cy", "cz")}
+    coef.update(dval=0.0, off=0.0)
+    csr = (block_diag_csr(mats) if batch > 1 else mats[0]) if with_csr else None
+    return csr, coef
+
+
+def poisson2d_rect(nx: int, ny: int, shift: float = 0.0) -> CSR:
+    """nx x ny 5-point Laplacian, Dirichlet 0, index x + nx y."""
+    n = nx * ny
+    idx = np.arange(n).reshape(ny, nx)
+    rows, cols, vals = [idx.ravel()], [idx.ravel()], [np.full(n, 4.0 + shift)]
+    for a, b in ((idx[:, :-1], idx[:, 1:]), (idx[:-1, :], idx[1:, :])):
+        for u, v in ((a, b), (b, a)):
+            rows.append(u.ravel()); cols.append(v.ravel()); vals.append(np.full(u.size, -1.0))
+    return csr_from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
