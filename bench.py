@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c2"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c5"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-every", type=int, default=0)
@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--layout", type=int, default=0, help="0 pair, 1 gather")
     ap.add_argument("--freeze", type=int, default=1)
     ap.add_argument("--grid", type=int, default=0, help="sweep grid cap (0 = library default)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte "
+                         "counters) and print its bandwidth")
     return ap.parse_args()
 
 
@@ -53,12 +56,55 @@ def pair_bytes_per_sweep(n: int, E: int, check_every: int) -> float:
     return 48.0 * E + 28.0 * n + 8.0 * n / check_every
 
 
+def pair_frozen_bytes_per_sweep(n: int, E: int, check_every: int) -> float:
+    """Settled-precision pair sweep: per directed edge the coefficient pair (8),
+    the information pair read (8) and written (8), the neighbour index (4) and
+    the gathered H_j (4); per node the row offset (4), own H read (4) and
+    written (4), right-hand side (4); a check sweep also reads S (4) and the
+    previous mean and writes it (8)."""
+    return 32.0 * E + 16.0 * n + 12.0 * n / check_every
+
+
 def gather_bytes_per_sweep(n: int, E: int, check_every: int) -> float:
     """Algorithmic bytes of one FP32 gather-layout sweep: per directed edge the
     reverse index (4), the coupling (4), the gathered in-message (8) and the
     written out-message (8); per node the row offset (4), A_ii (4), the
     right-hand side (4); check sweeps add the previous mean (8)."""
     return 24.0 * E + 12.0 * n + 8.0 * n / check_every
+
+
+def grid_bytes_per_sweep(N: int, E: int, frozen: bool, damped: bool, check_every: int) -> float:
+    """Algorithmic bytes of one FP32 grid sweep (constant coefficients).
+    Full: per directed edge the in-message read at the neighbour (8), the
+    previous out-message read for damping (8) and the new one written (8);
+    settled precisions: 4-byte information messages (in, previous, written)
+    plus the fixed coefficient (4).  Per node the right-hand side (4); a check
+    sweep adds the previous mean read and written (8) and, when settled, S (4)."""
+    if frozen:
+        per_edge = 4.0 * (4 if damped else 3)
+        return per_edge * E + 4.0 * N + 12.0 * N / check_every
+    per_edge = 8.0 * (3 if damped else 2)
+    return per_edge * E + 4.0 * N + 8.0 * N / check_every
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch of a kernel from the committed PMC summary
+    (profiles/traffic.json): the average over its sweep and check variants,
+    or None when the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    vals = []
+    for name, rec in t["kernels"].items():
+        if not name.startswith(kernel_key):
+            continue
+        src = os.path.join(ROOT, "paper_0810_1119_amd", "csrc", rec["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+            return None
+        vals.append(rec["bytes_per_launch"])
+    return sum(vals) / len(vals) if vals else None
 
 
 def cpu_baseline(m, b, E, budget_s=12.0):
@@ -79,19 +125,45 @@ def cpu_baseline(m, b, E, budget_s=12.0):
                       f"{dt / runs:.2f} s per solve"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(a single graph would shard by node partition with one halo exchange "
-              "per sweep; see the design notes)", file=sys.stderr)
-        sys.exit(2)
-    import torch
+def grid_bytes_per_sweep(N: int, E: int, frozen: bool, damped: bool) -> float:
+    """Algorithmic bytes of one FP32 grid sweep (constant coefficients).
+    Full: per directed edge the in-message read at the neighbour (8), the
+    previous out-message read for damping (8) and the new one written (8);
+    settled precisions: the same with 4-byte information messages plus the
+    fixed coefficient (4).  Per node the right-hand side (4)."""
+    per_edge = (8.0 * (3 if damped else 2)) if not frozen else (4.0 * (4 if damped else 3))
+    return per_edge * E + 4.0 * N
 
-    import paper_0810_1119_amd as G
-    import workloads as W
 
-    dev = torch.device("cuda:0")
+def run_c5(args, G, W, torch, dev):
+    n1 = 256
+    N = n1 ** 3
+    _, coef = W.grid_stack(n1, n1, n1, 1, shift=0.01, with_csr=False)
+    b_h = W.uniform_b(N, args.seed)
+    A = G.DeviceGrid(n1, n1, n1, 1, diag_value=coef["dval"], off_value=coef["off"])
+    E = 2 * 3 * (n1 - 1) * n1 * n1
+    b = torch.from_numpy(b_h).to(dev)
+    x = torch.zeros(N, dtype=torch.float64, device=dev)
+    opts = G.gabp_default_opts(msg_fp32=1, tol=1e-8, damping=0.5, max_sweeps=200000)
+    if args.check_every:
+        opts.check_every = args.check_every
+    opts.freeze = args.freeze
+    opts.grid_blocks = args.grid
+    c = max(2, opts.check_every + (opts.check_every & 1))
+    rc, plan = G.gabp_plan_create_grid(A, opts)
+    if rc != G.GABP_OK:
+        raise SystemExit(f"plan_create_grid: {G.status_name(rc)}")
+    return dict(plan=plan, b=b, x=x, E=E, n=N, b_h=b_h, coef=coef,
+                workload="3-D Poisson 7-point, 256^3 (16,777,216 unknowns, 100,270,080 directed "
+                         "edges, 117,047,296 nonzeros), A_ii = 6.01, A_ij = -1, Dirichlet 0, "
+                         "b ~ U[-1,1]; FP32 messages, damping 0.5, FP64 refinement to 1e-8",
+                bytes_full=grid_bytes_per_sweep(N, E, False, True, c),
+                bytes_frozen=grid_bytes_per_sweep(N, E, True, True, c),
+                kfull="k_grid_sweep<float,*,damped,const>", kfrozen="k_grid_frozen<float,*,damped,const>",
+                tkey_full="gabp::k_grid_sweep<float, ", tkey_frozen="gabp::k_grid_frozen<float, ")
+
+
+def run_c2(args, G, W, torch, dev):
     n = 1 << 20
     m = W.sdd_random(n, args.seed)
     b_h = W.normal_b(n, args.seed)
@@ -107,13 +179,57 @@ def main():
     opts.layout = args.layout
     opts.freeze = args.freeze
     opts.grid_blocks = args.grid
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     rc, plan = G.gabp_plan_create(A, opts)
-    torch.cuda.synchronize()
-    plan_ms = (time.perf_counter() - t0) * 1e3
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create: {G.status_name(rc)}")
+    c = max(2, opts.check_every + (opts.check_every & 1))
+    pair = args.layout == 0
+    return dict(plan=plan, b=b, x=x, E=E, n=n, m=m, b_h=b_h, A=A,
+                workload="random sparse SDD A (n=2^20, ~8 off-diagonals/row, N(0,1) couplings, "
+                         "A_ii=1.1 sum|A_ij|), b~N(0,1); FP32 messages + FP64 refinement to 1e-8",
+                bytes_full=(pair_bytes_per_sweep if pair else gather_bytes_per_sweep)(n, E, c),
+                bytes_frozen=pair_frozen_bytes_per_sweep(n, E, c) if pair else None,
+                tkey_full="gabp::k_pair_sweep<float, " if pair else None,
+                tkey_frozen="gabp::k_pair_frozen<float, " if pair else None,
+                kfull=("k_pair_sweep<float,G,*> (A1 node broadcast + A2 edge update + A3 check)"
+                       if pair else "k_csr_sweep<float,G,*> (A1+A2+A3, reverse-index gather)"),
+                kfrozen="k_pair_frozen<float,G,*>" if pair else None)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(a single graph would shard by node partition with one halo exchange "
+              "per sweep; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                          "copy_ms": dt * 1e3, "copy_GBps_read_plus_write": 2 * (1 << 30) / dt / 1e9}))
+        return
+
+    import paper_0810_1119_amd as G
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w = (run_c2 if args.workload == "c2" else run_c5)(args, G, W, torch, dev)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    plan, b, x, E, n = w["plan"], w["b"], w["x"], w["E"], w["n"]
 
     for _ in range(args.warmup):
         rc, st = G.gabp_plan_solve(plan, b, x)
@@ -141,19 +257,19 @@ def main():
 
     ms_per_step = dt * 1e3 / args.steps
     value = E * sweeps / dt
-    c = max(2, opts.check_every + (opts.check_every & 1))
-    # dominant kernel: the full sweep (pair layout: k_pair_sweep; gather
-    # layout: k_csr_sweep), timed with HIP events on the solve's stream
-    full_sweeps = sweeps - frozen
-    full_ms = sweep_ms - frozen_ms
-    if args.layout == 0:
-        bps = pair_bytes_per_sweep(n, E, c)
-        kname = "k_pair_sweep<float,G,*> (A1 node broadcast + A2 edge update + A3 check)"
+    full_sweeps, full_ms = sweeps - frozen, sweep_ms - frozen_ms
+    # dominant kernel = the sweep kind with the larger share of device time,
+    # timed with HIP events on the solve's stream
+    use_frozen = frozen > 0 and frozen_ms >= full_ms and w["bytes_frozen"]
+    if use_frozen:
+        kname, bps, launches, kms = w["kfrozen"], w["bytes_frozen"], frozen, frozen_ms
+        tkey = w.get("tkey_frozen")
     else:
-        bps = gather_bytes_per_sweep(n, E, c)
-        kname = "k_csr_sweep<float,G,*> (A1 + A2 + A3 fused, reverse-index gather)"
-    avg_sweep_s = full_ms * 1e-3 / max(full_sweeps, 1)
-    achieved = bps / avg_sweep_s / 1e9
+        kname, bps, launches, kms = w["kfull"], w["bytes_full"], full_sweeps, full_ms
+        tkey = w.get("tkey_full")
+    traffic = measured_traffic(tkey) if tkey else None
+    avg_s = kms * 1e-3 / max(launches, 1)
+    achieved = bps / avg_s / 1e9
     out = {
         "metric": "GaBP edge-updates/s (solve to rel. residual 1e-8)",
         "value": value,
@@ -168,28 +284,46 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": "random sparse SDD A (n=2^20, ~8 off-diagonals/row, N(0,1) couplings, "
-                        "A_ii=1.1 sum|A_ij|), b~N(0,1); FP32 messages + FP64 refinement to 1e-8",
-            "n": n, "directed_edges": E, "nnz": int(m.nnz), "seed": args.seed,
+            "workload": w["workload"], "n": n, "directed_edges": E, "seed": args.seed,
             "sweeps_per_solve": sweeps / args.steps, "restarts_per_solve": restarts / args.steps,
             "settled_precision_sweeps_per_solve": frozen / args.steps,
-            "layout": ["pair", "gather"][args.layout], "freeze": bool(args.freeze),
             "time_to_1e-8_ms": ms_per_step, "worst_rel_residual": worst_rel,
-            "plan_ms": plan_ms, "check_every": c, "group": opts.group or "auto",
-            "grid_blocks": opts.grid_blocks or "auto",
+            "plan_ms": plan_ms,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": kname,
-            "avg_sweep_us": avg_sweep_s * 1e6, "algorithmic_bytes_per_sweep": bps,
-            "launches_timed": full_sweeps,
-            "settled_precision_sweep_avg_us": (frozen_ms * 1e3 / frozen) if frozen else None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": kname, "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bps,
+            "launches_timed": launches,
+            "full_sweep_avg_us": (full_ms * 1e3 / full_sweeps) if full_sweeps else None,
+            "settled_sweep_avg_us": (frozen_ms * 1e3 / frozen) if frozen else None,
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m, b_h, E)
+        if args.workload == "c2":
+            out["cpu_baseline"] = cpu_baseline(w["m"], w["b_h"], E)
+        else:
+            out["cpu_baseline"] = cpu_baseline_grid(w, E)
     print(json.dumps(out))
+
+
+def cpu_baseline_grid(w, E, budget_s=12.0):
+    """The oracle on the same 256^3 operator: its CSR (built once, not timed)
+    swept with Algorithm 2 for a bounded number of rounds."""
+    import oracle
+    import workloads as W
+    m = W.poisson3d(256, 256, 256, 0.01)
+    R = oracle.Rounds(m, w["b_h"], algorithm=2, damping=0.5)
+    t0 = time.perf_counter()
+    rounds = 0
+    while time.perf_counter() - t0 < budget_s and rounds < 50:
+        R.step()
+        rounds += 1
+    dt = time.perf_counter() - t0
+    return {"value": E * rounds / dt, "unit": "edge-updates/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{rounds} damped FP64 oracle rounds (Algorithm 2, OpenMP over rows) of the "
+                      f"same 256^3 system in {dt:.1f} s (a bounded slice of a solve)"}
 
 
 if __name__ == "__main__":

@@ -307,3 +307,17 @@ def test_structured_residual_matches_csr_residual(shape):
                                   c["cz"], c["off"])
     np.testing.assert_allclose(r2, r1, rtol=0, atol=1e-13 * np.abs(r1).max())
     assert n2 == pytest.approx(n1, rel=1e-14)
+
+
+def test_poisson3d_row_order_construction():
+    """The sort-free 7-point construction equals the face-list construction."""
+    for dims in [(5, 4, 3), (1, 6, 2), (7, 1, 1), (3, 3, 3)]:
+        a = W.poisson3d(*dims, shift=0.01)
+        nx, ny, nz = dims
+        n = nx * ny * nz
+        rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.full(n, 6.01)]
+        for u, v, _ in W._grid_faces(nx, ny, nz):
+            rows += [u, v]; cols += [v, u]; vals += [np.full(u.size, -1.0)] * 2
+        b = W.csr_from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+        assert np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col, b.col)
+        assert np.array_equal(a.val, b.val)

@@ -117,13 +117,22 @@ def _grid_faces(nx: int, ny: int, nz: int):
 
 def poisson3d(nx: int, ny: int, nz: int, shift: float = 0.0) -> CSR:
     """Constant-coefficient 7-point Laplacian, Dirichlet 0: A_ii = 6 + shift,
-    A_ij = -1 for face neighbours."""
+    A_ij = -1 for face neighbours.  Built directly in row order (columns of a
+    row are -z, -y, -x, diagonal, +x, +y, +z, already sorted), so large grids
+    need no sort."""
     n = nx * ny * nz
-    rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.full(n, 6.0 + shift)]
-    for u, v, _ in _grid_faces(nx, ny, nz):
-        rows += [u, v]; cols += [v, u]; vals += [np.full(u.size, -1.0)] * 2
-    return csr_from_coo(n, np.concatenate(rows), np.concatenate(cols),
-                        np.concatenate(vals))
+    i = np.arange(n, dtype=np.int64)
+    x, y, z = i % nx, (i // nx) % ny, i // (nx * ny)
+    nxy = nx * ny
+    cand = [(z > 0, i - nxy), (y > 0, i - nx), (x > 0, i - 1), (None, i),
+            (x < nx - 1, i + 1), (y < ny - 1, i + nx), (z < nz - 1, i + nxy)]
+    mask = np.stack([np.ones(n, bool) if ok is None else ok for ok, _ in cand], axis=1)
+    counts = mask.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col = np.stack([j for _, j in cand], axis=1)[mask].astype(np.int32)
+    val = np.where(np.arange(7) == 3, 6.0 + shift, -1.0)[None, :].repeat(n, 0)[mask]
+    return CSR(n, row_ptr, col, val)
 
 
 def grf_field(nx: int, ny: int, nz: int, seed: int, ell: float = 8.0,
