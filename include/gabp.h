@@ -99,6 +99,14 @@ typedef struct {
                           pair-layout sweeps keep the precisions fixed and
                           update the information h = P mu only; the FP64
                           refinement absorbs the last-ulp difference.  0: never */
+  int32_t batch_waves; /* batched solves: wavefronts (64 lanes) per workgroup,
+                          4, 8 or 16; 0 = chosen by the plan's autotuner */
+  int32_t adapt_damping; /* batched solves, 1 (default): an instance whose means
+                          stop contracting (ratio of successive changes >= 0.95
+                          at 8 checks in a row after the first 32 sweeps of a
+                          pass) or turn non-finite runs that pass again from
+                          zero messages with the damping raised to 0.3, then
+                          0.5, then 0.7 (damping as in section VI-D); 0 = never */
 } gabp_opts;
 
 enum { GABP_LAYOUT_PAIR = 0, GABP_LAYOUT_GATHER = 1 };
@@ -116,11 +124,14 @@ typedef struct {
   double frozen_sweep_ms;  /* of which in sweeps with settled precisions */
   int64_t edges;           /* directed off-diagonal messages per sweep */
   double edge_updates_per_s; /* edges * sweeps / seconds */
+  double damping;          /* damping factor in use at the end (batched
+                              instances may have raised it) */
 } gabp_stats;
 
 /* Fills o with the defaults: FP32 messages, tol 1e-8, 20000 sweeps, checks
  * every 2 sweeps, no damping, automatic inner targets (inner_tol 0),
- * 30 restarts, group 0, pair layout, freeze on.  check_every is rounded up to
+ * 30 restarts, group 0, pair layout, freeze on, batch_waves 0 (autotuned),
+ * adapt_damping on.  check_every is rounded up to
  * an even count. */
 void gabp_default_opts(gabp_opts *o);
 
@@ -204,6 +215,76 @@ int gabp_solve_grid(const gabp_grid *A, const double *b, double *x, double *marg
                     const gabp_opts *o, gabp_stats *st, hipStream_t stream);
 int gabp_residual_grid(const gabp_grid *A, const double *b, const double *x, double *r,
                        double *rel_norm, hipStream_t stream);
+
+/* ---- Batches of small dense instances, one persistent launch. -------------
+ * Each workgroup takes the next instance from a queue sorted by size (largest
+ * first) and runs all of that instance's sweeps, mean checks and FP64
+ * refinement passes on its own, so instances of very different sizes finish
+ * independently and no host round trip happens between sweeps.
+ *
+ * GABP_BATCH_BIPARTITE (section VII): instance t is a linear detector with
+ * spreading matrix S_t (N_t chips x K_t users), observations y_t and noise
+ * variance sigma2_t > 0; its answer is the MMSE estimate
+ *     x_t = (S_t^T S_t + sigma2_t I)^{-1} S_t^T y_t        (section VIII-B),
+ * computed by GaBP on the symmetric (K_t + N_t)-node system
+ *     [[I, S_t^T], [S_t, -sigma2_t I]] [x; z] = [0; y_t],
+ * whose graph is the complete bipartite graph users x chips (one edge per
+ * nonzero S entry).  GaBP on the K_t x K_t matrix S^T S + sigma2 I itself
+ * diverges when the loading K/N is large (that matrix is not walk-summable);
+ * the bipartite system has the same x and converges.
+ * Refinement: with r = S^T y - (S^T S + sigma2 I) x in FP64, the correction
+ * solves the bipartite system with right-hand side [r / sigma2; 0], whose
+ * first block is the solution d of (S^T S + sigma2 I) d = r.
+ * tol applies to ||S^T y - (S^T S + sigma2 I) x||_2 / ||S^T y||_2.
+ *
+ * GABP_BATCH_DENSE: instance t is a dense symmetric K_t x K_t matrix A_t
+ * (complete graph on its nonzero entries), solved as by gabp_solve.
+ *
+ * Packing: instance matrices back to back in `mat` (row-major), right-hand
+ * sides back to back in b (y_t of N_t entries, or b_t of K_t), solutions back
+ * to back in x (K_t entries each).  Limits: K_t <= 512 and the per-workgroup
+ * state of the largest instance must fit the 160 KB LDS (about N_t <= 4096 for
+ * FP32 messages); beyond: GABP_ERR_UNSUPPORTED. */
+enum { GABP_BATCH_BIPARTITE = 0, GABP_BATCH_DENSE = 1 };
+typedef struct {
+  int32_t kind;          /* GABP_BATCH_BIPARTITE or GABP_BATCH_DENSE */
+  int32_t count;         /* instances, >= 0 */
+  const int32_t *k;      /* host [count]: users K_t, or the order of A_t */
+  const int32_t *m;      /* host [count]: chips N_t (bipartite; NULL for dense) */
+  const double *sigma2;  /* host [count]: noise variance (bipartite; NULL for dense) */
+  const double *mat;     /* device: S_t (N_t x K_t) or A_t (K_t x K_t), packed; read
+                            by the plan until it is destroyed */
+} gabp_batch;
+/* Validates every instance on the device (finite entries; dense: exactly
+ * symmetric with nonzero diagonal; bipartite: sigma2 finite and > 0), keeps a
+ * working-precision copy of the couplings and allocates the message state
+ * (16 bytes per entry of each matrix in FP32, 32 in FP64, plus the same again
+ * once the settled-precision phase is used). */
+int gabp_plan_create_batched(const gabp_batch *B, const gabp_opts *o, gabp_plan **plan,
+                             hipStream_t stream);
+/* Solves every instance from zero messages.
+ *   b             device, packed right-hand sides as above.
+ *   x             device, packed solutions (FP64).
+ *   per_instance  host [count] or NULL: stats of each instance (status, sweeps,
+ *                 frozen_sweeps, restarts, checks, rel_residual, edges;
+ *                 residual_per_eq = ||r||_2 / K_t).
+ *   summary       host or NULL: status = the worst instance status, sweeps and
+ *                 restarts = the largest over instances, edges = directed
+ *                 messages per sweep summed over instances, seconds = wall time,
+ *                 sweep_ms = device time of the launch, edge_updates_per_s =
+ *                 sum over instances of edges x sweeps / seconds.
+ * Returns the worst instance status (a negative code if any instance failed,
+ * else GABP_NOT_CONVERGED if any did not converge, else GABP_OK).  For batched
+ * plans gabp_plan_solve does the same with `st` as the summary and marg_prec
+ * (device, packed like x, or NULL) the marginal precisions of the unknowns;
+ * gabp_plan_reset / sweeps / marginals work as for CSR plans with the node
+ * values packed per instance (bipartite: K_t users then N_t chips; dense: K_t
+ * nodes) and the same right-hand-side packing as solve; get/set_messages
+ * return GABP_ERR_UNSUPPORTED. */
+int gabp_plan_solve_batched(gabp_plan *plan, const double *b, double *x,
+                            gabp_stats *per_instance, gabp_stats *summary, hipStream_t stream);
+int gabp_solve_batched(const gabp_batch *B, const double *b, double *x, const gabp_opts *o,
+                       gabp_stats *per_instance, gabp_stats *summary, hipStream_t stream);
 
 /* Library version string. */
 const char *gabp_version(void);

@@ -16,4 +16,6 @@ from ._abi import (  # noqa: F401
     gabp_plan_solve, gabp_plan_reset, gabp_plan_sweeps, gabp_plan_marginals,
     gabp_plan_get_messages, gabp_plan_set_messages, gabp_version,
     DeviceGrid, gabp_plan_create_grid, gabp_solve_grid, gabp_residual_grid,
+    GABP_BATCH_BIPARTITE, GABP_BATCH_DENSE, DeviceBatch,
+    gabp_plan_create_batched, gabp_plan_solve_batched, gabp_solve_batched,
 )

@@ -24,9 +24,12 @@ GABP_ERR_NOMEM = -7
 GABP_ERR_UNSUPPORTED = -8
 GABP_LAYOUT_PAIR = 0
 GABP_LAYOUT_GATHER = 1
+GABP_BATCH_BIPARTITE = 0
+GABP_BATCH_DENSE = 1
 
 _NAMES = {v: k for k, v in dict(globals()).items()
-          if k.startswith("GABP_") and not k.startswith("GABP_LAYOUT") and isinstance(v, int)}
+          if k.startswith("GABP_") and not k.startswith(("GABP_LAYOUT", "GABP_BATCH"))
+          and isinstance(v, int)}
 
 
 def status_name(code: int) -> str:
@@ -53,7 +56,8 @@ class Opts(C.Structure):
     _fields_ = [("msg_fp32", C.c_int32), ("tol", C.c_double), ("max_sweeps", C.c_int32),
                 ("check_every", C.c_int32), ("damping", C.c_double), ("inner_tol", C.c_double),
                 ("max_restarts", C.c_int32), ("group", C.c_int32), ("layout", C.c_int32),
-                ("grid_blocks", C.c_int32), ("freeze", C.c_int32)]
+                ("grid_blocks", C.c_int32), ("freeze", C.c_int32), ("batch_waves", C.c_int32),
+                ("adapt_damping", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -62,7 +66,7 @@ class Stats(C.Structure):
                 ("checks", C.c_int32), ("rel_residual", C.c_double),
                 ("residual_per_eq", C.c_double), ("seconds", C.c_double),
                 ("sweep_ms", C.c_double), ("frozen_sweep_ms", C.c_double), ("edges", C.c_int64),
-                ("edge_updates_per_s", C.c_double)]
+                ("edge_updates_per_s", C.c_double), ("damping", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +89,10 @@ _sig = {
     "gabp_plan_create_grid": (C.c_int, [C.c_void_p, C.POINTER(Opts), C.POINTER(_vp), _vp]),
     "gabp_solve_grid": (C.c_int, [C.c_void_p, _vp, _vp, _vp, C.POINTER(Opts), C.POINTER(Stats), _vp]),
     "gabp_residual_grid": (C.c_int, [C.c_void_p, _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
+    "gabp_plan_create_batched": (C.c_int, [C.c_void_p, C.POINTER(Opts), C.POINTER(_vp), _vp]),
+    "gabp_plan_solve_batched": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(Stats), _vp]),
+    "gabp_solve_batched": (C.c_int, [C.c_void_p, _vp, _vp, C.POINTER(Opts), _vp, C.POINTER(Stats),
+                                     _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)
@@ -192,9 +200,17 @@ def gabp_plan_destroy(plan) -> int:
     return rc
 
 
+def _lens(plan):
+    """(right-hand side, unknowns, node values) lengths of a plan's arrays."""
+    A = plan.A
+    if isinstance(A, DeviceBatch):
+        return A.rhslen, A.xlen, A.nodes
+    return A.n, A.n, A.n
+
+
 def gabp_plan_solve(plan, b, x, marg_prec=None, stream=None):
-    n = plan.A.n
-    _check_f64(b, n, "b"); _check_f64(x, n, "x"); _check_f64(marg_prec, n, "marg_prec")
+    nb, nx, _ = _lens(plan)
+    _check_f64(b, nb, "b"); _check_f64(x, nx, "x"); _check_f64(marg_prec, nx, "marg_prec")
     st = Stats()
     rc = lib.gabp_plan_solve(plan.ptr, _ptr(b), _ptr(x), _ptr(marg_prec), C.byref(st),
                              _stream(stream))
@@ -202,7 +218,7 @@ def gabp_plan_solve(plan, b, x, marg_prec=None, stream=None):
 
 
 def gabp_plan_reset(plan, b, stream=None) -> int:
-    _check_f64(b, plan.A.n, "b")
+    _check_f64(b, _lens(plan)[0], "b")
     return lib.gabp_plan_reset(plan.ptr, _ptr(b), _stream(stream))
 
 
@@ -211,7 +227,8 @@ def gabp_plan_sweeps(plan, count: int, stream=None) -> int:
 
 
 def gabp_plan_marginals(plan, mean, prec=None, stream=None) -> int:
-    _check_f64(mean, plan.A.n, "mean"); _check_f64(prec, plan.A.n, "prec")
+    nn = _lens(plan)[2]
+    _check_f64(mean, nn, "mean"); _check_f64(prec, nn, "prec")
     return lib.gabp_plan_marginals(plan.ptr, _ptr(mean), _ptr(prec), _stream(stream))
 
 
@@ -283,3 +300,97 @@ def gabp_residual_grid(A: DeviceGrid, b, x, r=None, stream=None):
     a = A.c()
     rc = lib.gabp_residual_grid(C.byref(a), _ptr(b), _ptr(x), _ptr(r), C.byref(rel), _stream(stream))
     return rc, rel.value
+
+
+class _Batch(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("count", C.c_int32), ("k", C.c_void_p), ("m", C.c_void_p),
+                ("sigma2", C.c_void_p), ("mat", C.c_void_p)]
+
+
+@dataclass
+class DeviceBatch:
+    """A batch of dense instances for gabp_solve_batched: per-instance sizes
+    and noise variances on the host, the packed row-major matrices (float64
+    CUDA tensor) on the device.  Bipartite: S_t (N_t x K_t), right-hand sides
+    y_t; dense: A_t (K_t x K_t), right-hand sides b_t."""
+    kind: int
+    k: object
+    m: object = None
+    sigma2: object = None
+    mat: object = None
+
+    @classmethod
+    def bipartite(cls, K, N, sigma2, S, device="cuda"):
+        import numpy as np
+        import torch
+        K = np.ascontiguousarray(K, dtype=np.int32)
+        N = np.ascontiguousarray(N, dtype=np.int32)
+        s2 = np.ascontiguousarray(sigma2, dtype=np.float64)
+        mat = torch.from_numpy(np.ascontiguousarray(S, dtype=np.float64)).to(device)
+        return cls(GABP_BATCH_BIPARTITE, K, N, s2, mat)
+
+    @classmethod
+    def dense(cls, K, A, device="cuda"):
+        import numpy as np
+        import torch
+        K = np.ascontiguousarray(K, dtype=np.int32)
+        mat = torch.from_numpy(np.ascontiguousarray(A, dtype=np.float64)).to(device)
+        return cls(GABP_BATCH_DENSE, K, None, None, mat)
+
+    @property
+    def count(self) -> int:
+        return int(len(self.k))
+
+    @property
+    def xlen(self) -> int:
+        return int(sum(int(v) for v in self.k))
+
+    @property
+    def rhslen(self) -> int:
+        return int(sum(int(v) for v in (self.m if self.kind == GABP_BATCH_BIPARTITE else self.k)))
+
+    @property
+    def nodes(self) -> int:
+        extra = sum(int(v) for v in self.m) if self.kind == GABP_BATCH_BIPARTITE else 0
+        return self.xlen + int(extra)
+
+    def c(self) -> _Batch:
+        def p(a):
+            return None if a is None else a.ctypes.data_as(C.c_void_p)
+        return _Batch(self.kind, self.count, p(self.k), p(self.m), p(self.sigma2), _ptr(self.mat))
+
+
+def _batch_stats(per_instance: bool, count: int):
+    return (Stats * max(1, count))() if per_instance else None
+
+
+def gabp_plan_create_batched(B: DeviceBatch, opts: Opts | None = None, stream=None):
+    h = C.c_void_p()
+    b = B.c()
+    rc = lib.gabp_plan_create_batched(C.byref(b), C.byref(opts) if opts is not None else None,
+                                      C.byref(h), _stream(stream))
+    return rc, (_PlanHandle(h.value, B) if rc == GABP_OK else None)
+
+
+def gabp_plan_solve_batched(plan, b, x, per_instance: bool = True, stream=None):
+    """Returns (status, per-instance Stats list or None, summary Stats)."""
+    B = plan.A
+    _check_f64(b, B.rhslen, "b"); _check_f64(x, B.xlen, "x")
+    per = _batch_stats(per_instance, B.count)
+    summary = Stats()
+    rc = lib.gabp_plan_solve_batched(plan.ptr, _ptr(b), _ptr(x), per, C.byref(summary),
+                                     _stream(stream))
+    return rc, (list(per)[:B.count] if per is not None else None), summary
+
+
+def gabp_solve_batched(B: DeviceBatch, b, x, opts: Opts | None = None, per_instance: bool = True,
+                       stream=None):
+    """Returns (status, per-instance Stats list or None, summary Stats)."""
+    _check_f64(b, B.rhslen, "b"); _check_f64(x, B.xlen, "x")
+    per = _batch_stats(per_instance, B.count)
+    summary = Stats()
+    bb = B.c()
+    rc = lib.gabp_solve_batched(C.byref(bb), _ptr(b), _ptr(x),
+                                C.byref(opts) if opts is not None else None, per,
+                                C.byref(summary), _stream(stream))
+    return rc, (list(per)[:B.count] if per is not None else None), summary

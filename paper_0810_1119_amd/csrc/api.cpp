@@ -80,6 +80,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   if (!p || (p->n > 0 && (!b || !x))) return GABP_ERR_ARG;
   gabp_stats stats{};
   stats.edges = p->E;
+  stats.damping = p->o.damping;
   stats.status = GABP_OK;
   const gabp_opts &o = p->o;
   auto finish = [&](int status) {
@@ -231,23 +232,28 @@ void gabp_default_opts(gabp_opts *o) {
   o->layout = GABP_LAYOUT_PAIR;
   o->grid_blocks = 0;
   o->freeze = 1;
+  o->batch_waves = 0;
+  o->adapt_damping = 1;
 }
 
 int gabp_plan_destroy(gabp_plan *p) {
   if (!p) return GABP_ERR_ARG;
   (void)hipDeviceSynchronize();
   delete p->eng;
+  if (p->bat) batch_destroy(p->bat);
   delete p;
   return GABP_OK;
 }
 
 int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
                     hipStream_t s) {
+  if (p && p->bat) return batch_solve(p->bat, b, x, marg_prec, nullptr, st, s);
   if (!p || !p->eng) return GABP_ERR_ARG;
   return engine_solve(p->eng, b, x, marg_prec, st, s);
 }
 
 int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
+  if (p && p->bat) return batch_reset(p->bat, b, s);
   if (!p || !p->eng || (p->eng->n > 0 && !b)) return GABP_ERR_ARG;
   if (p->eng->n == 0) return GABP_OK;
   TRY_HIP(launch_fill_zero4(p->eng->sticky, 1, s));
@@ -257,6 +263,7 @@ int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
 }
 
 int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
+  if (p && p->bat) return batch_sweeps(p->bat, count, s);
   if (!p || !p->eng || count < 0) return GABP_ERR_ARG;
   Engine *e = p->eng;
   if (e->frozen) return GABP_ERR_ARG;  // trajectory access needs the full state (reset first)
@@ -266,6 +273,7 @@ int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
 }
 
 int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s) {
+  if (p && p->bat) return batch_marginals(p->bat, mean, prec, s);
   if (!p || !p->eng || (p->eng->n > 0 && !mean)) return GABP_ERR_ARG;
   if (p->eng->n == 0) return GABP_OK;
   TRY_HIP(launch_fill_zero(mean, p->eng->n, s));
@@ -275,11 +283,13 @@ int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s)
 }
 
 int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
+  if (p && p->bat) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
   return p->eng->get_messages(P, h, s);
 }
 
 int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipStream_t s) {
+  if (p && p->bat) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
   return p->eng->set_messages(P, h, s);
 }

@@ -85,9 +85,22 @@ struct Engine {
 int engine_solve(Engine *e, const double *b, double *x, double *marg, gabp_stats *st,
                  hipStream_t s);
 
+int check_opts(const gabp_opts *o);  // engine_csr.cpp
+
+// batches of dense instances (engine_dense.cpp)
+struct BatchEngine;
+int batch_create(const gabp_batch *B, const gabp_opts *o, BatchEngine **out, hipStream_t s);
+void batch_destroy(BatchEngine *e);
+int batch_solve(BatchEngine *e, const double *b, double *x, double *marg_prec, gabp_stats *per,
+                gabp_stats *summary, hipStream_t s);
+int batch_reset(BatchEngine *e, const double *b, hipStream_t s);
+int batch_sweeps(BatchEngine *e, int count, hipStream_t s);
+int batch_marginals(BatchEngine *e, double *mean, double *prec, hipStream_t s);
+
 }  // namespace gabp
 
-// the opaque plan of the C ABI
+// the opaque plan of the C ABI: one system (eng) or a batch of dense instances (bat)
 struct gabp_plan {
   gabp::Engine *eng = nullptr;
+  gabp::BatchEngine *bat = nullptr;
 };

@@ -10,7 +10,6 @@
 
 namespace gabp {
 
-int check_opts(const gabp_opts *o);  // engine_csr.cpp
 
 namespace {
 

@@ -216,4 +216,89 @@ hipError_t launch_grid_zero_h(bool fp32, int64_t m, void *msg, hipStream_t s);
 hipError_t launch_grid_io(bool fp32, bool get, int64_t m, void *msg, double *P, double *h,
                           hipStream_t s);
 
+// ---- batches of dense instances (kernels_dense.hip) ----
+// One instance of a batch.  Its couplings form a rows x cols row-major block
+// of the packed matrix array; entry (r, c) is one undirected edge between the
+// row node r and the column node c (bipartite: chip r, user c; dense: nodes
+// r < c of the upper triangle, the diagonal entries are A_ii).
+struct DenseInst {
+  int64_t mat;     // first entry of the block (also of its message state)
+  int64_t rhs;     // first right-hand-side entry (bipartite: rows; dense: cols)
+  int64_t xoff;    // first unknown of x (cols entries)
+  int64_t node;    // first node of the per-node arrays (bipartite: cols users
+                   // then rows chips; dense: cols nodes)
+  int64_t edges;   // directed messages per sweep (filled by the validation)
+  double sigma2;   // bipartite: -A_rr of every chip node
+  int32_t rows, cols;
+};
+
+// Per-instance outcome written by the persistent kernel.
+struct DenseStat {
+  int32_t status, sweeps, frozen_sweeps, restarts, checks, pad;
+  double rel;      // final relative residual (FP64)
+  double rnorm;    // final ||r||_2
+  double damping;  // damping factor in use at the end
+};
+
+enum { DENSE_SOLVE = 0, DENSE_RESET = 1, DENSE_SWEEPS = 2 };
+
+struct DenseArgs {
+  int kind;              // GABP_BATCH_BIPARTITE / GABP_BATCH_DENSE
+  bool fp32;
+  int waves;             // wavefronts per workgroup
+  int grid;              // workgroups of the persistent launch
+  int nr, nc;            // LDS capacity: largest rows and cols of the batch
+  int maxm;              // column chunks of 64 lanes per row (1, 2, 4, 8)
+  int mode;              // DENSE_*
+  int nsweeps;           // DENSE_SWEEPS: sweeps to run
+  bool fresh;            // the stored messages are all zero (read none)
+  int count;
+  const DenseInst *inst;
+  const int32_t *order;  // queue: instance indices, largest first
+  uint32_t *queue;       // next queue position (zeroed before the launch)
+  const double *mat64;   // the caller's FP64 matrices
+  const void *matT;      // couplings in the message precision
+  const double *b;
+  double *x;
+  void *state;           // (P_rc, h_rc, P_cr, h_cr) per entry
+  void *fcoef, *fh;      // settled phase: (c_rc, c_cr) and (h_rc, h_cr) per entry
+  void *tot, *nb;        // per node: (S, H) totals and right-hand side
+  DenseStat *stat;
+  double tol, alpha, inner_tol, freeze_tol, floor;
+  int max_sweeps, max_restarts, check_every;
+  bool freeze;           // settled phase allowed (buffers allocated)
+  bool adapt;            // raise the damping of instances that stop contracting
+};
+
+// Byte offsets of the dynamic LDS arrays of the persistent kernel.
+struct DenseLds {
+  int tot_row, tot_col, uni, b_row, b_col, xprev, diag, red, total;
+};
+__host__ __device__ inline DenseLds dense_lds(int nr, int nc, int waves, int tsz) {
+  auto al = [](int v) { return (v + 15) & ~15; };
+  DenseLds L{};
+  int o = 0;
+  L.tot_row = o; o = al(o + nr * 2 * tsz);
+  L.tot_col = o; o = al(o + nc * 2 * tsz);
+  L.uni = o;
+  const int colpart = waves * nc * 2 * tsz;           // per-wave column partials
+  const int resid = 8 * (2 * nc + nr + waves * 64);   // FP64 residual scratch
+  o = al(o + (colpart > resid ? colpart : resid));
+  L.b_row = o; o = al(o + nr * tsz);
+  L.b_col = o; o = al(o + nc * tsz);
+  L.xprev = o; o = al(o + nc * tsz);
+  L.diag = o; o = al(o + nc * tsz);
+  L.red = o; o = al(o + waves * 8 * 8);
+  L.total = o;
+  return L;
+}
+hipError_t launch_dense_batch(const DenseArgs &a, hipStream_t s);
+// occupancy of the persistent kernel: workgroups per compute unit (0 = cannot launch)
+int dense_batch_occupancy(const DenseArgs &a);
+hipError_t launch_dense_prepare(const DenseArgs &a, uint32_t *flags, hipStream_t s);
+// Means H/S and precisions S from the stored node totals: every node of each
+// instance (all = true, node packing) or its unknowns only (packed like x).
+hipError_t launch_dense_marginals(const DenseArgs &a, double *mean, double *prec, bool all,
+                                  hipStream_t s);
+
 }  // namespace gabp

@@ -31,7 +31,7 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for required in ("gabp_solve", "gabp_residual", "gabp_plan_create"):
+    for required in ("gabp_solve", "gabp_solve_batched", "gabp_residual", "gabp_plan_create"):
         assert required in names, required
 
 

@@ -321,6 +321,16 @@ class DetectionBatch:
         return S.T @ S + s2 * np.eye(S.shape[1]), S.T @ y
 
 
+def detection_subset(batch: int, seed: int, ids, kmin: int = 16, kmax: int = 256,
+                     load: float = 0.5, snr_db: float = 10.0) -> DetectionBatch:
+    """Instances ids of detection_batch(batch, seed, ...), drawn alone."""
+    rng = np.random.default_rng([seed, 0xDE7])
+    K = rng.integers(kmin, kmax + 1, size=batch).astype(np.int64)
+    N = np.ceil(K / load).astype(np.int64)
+    ids = np.asarray(ids, dtype=np.int64)
+    return detection_sizes(K[ids], N[ids], seed, snr_db, ids=ids)
+
+
 def detection_batch(batch: int, seed: int, kmin: int = 16, kmax: int = 256,
                     load: float = 0.5, snr_db: float = 10.0) -> DetectionBatch:
     """K ~ U{kmin..kmax}, N = K / load chips, S entries +-1/sqrt(N) iid (unit-norm
@@ -329,21 +339,85 @@ def detection_batch(batch: int, seed: int, kmin: int = 16, kmax: int = 256,
     rng = np.random.default_rng([seed, 0xDE7])
     K = rng.integers(kmin, kmax + 1, size=batch).astype(np.int64)
     N = np.ceil(K / load).astype(np.int64)
+    return detection_sizes(K, N, seed, snr_db)
+
+
+def detection_sizes(K, N, seed: int, snr_db: float = 10.0, ids=None) -> DetectionBatch:
+    """Detection instances of the given users K[t] and chips N[t] (the recipe
+    of detection_batch with explicit sizes).  Instance t draws from its own
+    stream, number ids[t] (default t), so sizes and ids taken from a
+    detection_batch reproduce any of its instances."""
+    K = np.asarray(K, dtype=np.int64)
+    N = np.asarray(N, dtype=np.int64)
+    batch = int(K.size)
+    ids = np.arange(batch) if ids is None else np.asarray(ids, dtype=np.int64)
     s2 = np.full(batch, 10.0 ** (-snr_db / 10.0))
     s_off = np.zeros(batch + 1, dtype=np.int64); np.cumsum(N * K, out=s_off[1:])
     y_off = np.zeros(batch + 1, dtype=np.int64); np.cumsum(N, out=y_off[1:])
     x_off = np.zeros(batch + 1, dtype=np.int64); np.cumsum(K, out=x_off[1:])
     S = np.empty(int(s_off[-1])); y = np.empty(int(y_off[-1])); x = np.empty(int(x_off[-1]))
     for t in range(batch):
-        r = np.random.default_rng([seed, 0xDE7, t])
+        r = np.random.default_rng([seed, 0xDE7, int(ids[t])])
         k, nn = int(K[t]), int(N[t])
-        St = r.choice([-1.0, 1.0], size=(nn, k)) / np.sqrt(nn)
+        St = r.choice([-1.0, 1.0], size=(nn, k)) / np.sqrt(max(nn, 1))
         xt = r.choice([-1.0, 1.0], size=k)
         yt = St @ xt + np.sqrt(s2[t]) * r.standard_normal(nn)
         S[s_off[t]:s_off[t + 1]] = St.ravel()
         y[y_off[t]:y_off[t + 1]] = yt
         x[x_off[t]:x_off[t + 1]] = xt
     return DetectionBatch(K, N, s2, S, y, x, s_off, y_off, x_off)
+
+
+@dataclass
+class DenseBatch:
+    """Packed dense symmetric instances: A_t (K[t] x K[t], row-major) at
+    A[a_off[t]:a_off[t+1]], right-hand side b_t at b[b_off[t]:b_off[t+1]]."""
+    K: np.ndarray
+    A: np.ndarray
+    b: np.ndarray
+    a_off: np.ndarray
+    b_off: np.ndarray
+
+    @property
+    def batch(self) -> int:
+        return int(self.K.size)
+
+    def instance(self, t: int):
+        k = int(self.K[t])
+        return (self.A[self.a_off[t]:self.a_off[t + 1]].reshape(k, k),
+                self.b[self.b_off[t]:self.b_off[t + 1]])
+
+
+def pack_dense(mats, rhs) -> DenseBatch:
+    """Packs square matrices and right-hand sides back to back."""
+    K = np.array([m.shape[0] for m in mats], dtype=np.int64)
+    a_off = np.zeros(K.size + 1, dtype=np.int64); np.cumsum(K * K, out=a_off[1:])
+    b_off = np.zeros(K.size + 1, dtype=np.int64); np.cumsum(K, out=b_off[1:])
+    A = np.concatenate([np.ascontiguousarray(m, dtype=np.float64).ravel() for m in mats]) \
+        if len(mats) else np.zeros(0)
+    b = np.concatenate([np.asarray(v, dtype=np.float64) for v in rhs]) if len(rhs) else np.zeros(0)
+    return DenseBatch(K, A, b, a_off, b_off)
+
+
+def dense_sdd_batch(batch: int, seed: int, kmin: int = 4, kmax: int = 96, density: float = 1.0,
+                    factor: float = 1.2) -> DenseBatch:
+    """K ~ U{kmin..kmax}; symmetric off-diagonals N(0,1) kept with probability
+    `density`, A_ii = factor * sum_j |A_ij| (strictly diagonally dominant; an
+    empty row gets A_ii = 1); b ~ N(0,1)."""
+    rng = np.random.default_rng([seed, 0xD5D])
+    K = rng.integers(kmin, kmax + 1, size=batch)
+    mats, rhs = [], []
+    for t in range(batch):
+        r = np.random.default_rng([seed, 0xD5D, t])
+        k = int(K[t])
+        a = np.triu(r.standard_normal((k, k)), 1)
+        a *= np.triu(r.random((k, k)) < density, 1)
+        a = a + a.T
+        d = factor * np.abs(a).sum(axis=1)
+        d[d == 0] = 1.0
+        mats.append(a + np.diag(d))
+        rhs.append(r.standard_normal(k))
+    return pack_dense(mats, rhs)
 
 
 def block_diag_csr(blocks) -> CSR:
