@@ -126,6 +126,9 @@ typedef struct {
   double edge_updates_per_s; /* edges * sweeps / seconds */
   double damping;          /* damping factor in use at the end (batched
                               instances may have raised it) */
+  int32_t batch_waves;     /* batched solves: wavefronts per workgroup of the
+                              persistent launch (the autotuner's choice) */
+  int32_t batch_groups;    /* batched solves: workgroups of that launch */
 } gabp_stats;
 
 /* Fills o with the defaults: FP32 messages, tol 1e-8, 20000 sweeps, checks

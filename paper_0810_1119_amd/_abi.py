@@ -66,7 +66,8 @@ class Stats(C.Structure):
                 ("checks", C.c_int32), ("rel_residual", C.c_double),
                 ("residual_per_eq", C.c_double), ("seconds", C.c_double),
                 ("sweep_ms", C.c_double), ("frozen_sweep_ms", C.c_double), ("edges", C.c_int64),
-                ("edge_updates_per_s", C.c_double), ("damping", C.c_double)]
+                ("edge_updates_per_s", C.c_double), ("damping", C.c_double),
+                ("batch_waves", C.c_int32), ("batch_groups", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -306,6 +306,8 @@ int batch_solve(BatchEngine *e, const double *b, double *x, double *marg_prec,
   if ((e->rhslen > 0 && !b) || (e->xlen > 0 && !x)) return GABP_ERR_ARG;
   gabp_stats sum{};
   sum.edges = e->edges;
+  sum.batch_waves = e->waves;
+  sum.batch_groups = e->grid;
   int worst = GABP_OK;
   if (e->count > 0) {
     TRY_HIP(launch_fill_zero4(e->queue, 1, s));
@@ -345,6 +347,8 @@ int batch_solve(BatchEngine *e, const double *b, double *x, double *marg_prec,
         p.residual_per_eq = I.cols > 0 ? d.rnorm / I.cols : 0.0;
         p.edges = I.edges;
         p.damping = d.damping;
+        p.batch_waves = e->waves;
+        p.batch_groups = e->grid;
       }
       sum.damping = std::max(sum.damping, d.damping);
     }
