@@ -129,6 +129,13 @@ typedef struct {
   int32_t batch_waves;     /* batched solves: wavefronts per workgroup of the
                               persistent launch (the autotuner's choice) */
   int32_t batch_groups;    /* batched solves: workgroups of that launch */
+  int32_t warm_start;      /* gabp_plan_solve_warm: 1 the network's messages were
+                              used; -1 rejected before the first sweep (the means
+                              they imply fit b worse than x = 0); -2 the warm
+                              solve did not converge and was redone from zero
+                              messages; 0 no warm start */
+  int32_t pad_;
+  double warm_rel0;        /* ||b - A x0|| / ||b|| of the warm start's means */
 } gabp_stats;
 
 /* Fills o with the defaults: FP32 messages, tol 1e-8, 20000 sweeps, checks
@@ -288,6 +295,54 @@ int gabp_plan_solve_batched(gabp_plan *plan, const double *b, double *x,
                             gabp_stats *per_instance, gabp_stats *summary, hipStream_t stream);
 int gabp_solve_batched(const gabp_batch *B, const double *b, double *x, const gabp_opts *o,
                        gabp_stats *per_instance, gabp_stats *summary, hipStream_t stream);
+
+/* ---- Learned warm start for grid solves (not part of the paper) ----------
+ * A per-node network proposes the initial messages of a structured-grid solve
+ * in place of the zero messages of Algorithm 1 step 1; the iteration, its
+ * fixed point and the answer x = A^{-1} b are unchanged.  Network: 8 inputs,
+ * two hidden layers of 64 ReLU units, 12 outputs; parameters held in bfloat16
+ * with FP32 masters and Adam moments; FP32 accumulation everywhere.
+ *   inputs of node i:  (log A_ii, a_1/A_ii, ..., a_6/A_ii, b_i/A_ii), a_d the
+ *                      coupling to the neighbour in direction d (+x, -x, +y,
+ *                      -y, +z, -z), 0 where there is none;
+ *   outputs:           (P_d/A_ii, h_d/A_ii) of the message toward direction d
+ *                      (information form h = P mu), ignored where a_d = 0.
+ * Flat parameter order (GABP_MODEL_PARAMS floats): W1 [64][8], b1 [64],
+ * W2 [64][64], b2 [64], W3 [12][64], b3 [12]. */
+enum { GABP_MODEL_INPUTS = 8, GABP_MODEL_OUTPUTS = 12, GABP_MODEL_PARAMS = 5516 };
+typedef struct gabp_model gabp_model;
+/* He-uniform weights from `seed` (splitmix64 stream), zero biases. */
+int gabp_model_create(uint64_t seed, gabp_model **model, hipStream_t stream);
+int gabp_model_destroy(gabp_model *model);
+/* params: host [GABP_MODEL_PARAMS].  get returns the bfloat16 values the
+ * kernels use (widened); set stores FP32 masters, rounds them to bfloat16 and
+ * clears the Adam state. */
+int gabp_model_get_params(const gabp_model *model, float *params, hipStream_t stream);
+int gabp_model_set_params(gabp_model *model, const float *params, hipStream_t stream);
+/* out = network(U): U device [count][8], out device [count][12]. */
+int gabp_model_forward(const gabp_model *model, const float *U, int64_t count, float *out,
+                       hipStream_t stream);
+/* Masked mean squared error / 2 over the outputs whose direction has a
+ * neighbour (U[s][1 + d] != 0), and its gradient (device [GABP_MODEL_PARAMS],
+ * may be NULL); train_step then applies one Adam step (beta 0.9, 0.999,
+ * eps 1e-8) with step size lr.  loss: host, may be NULL.  T: device [count][12].
+ * Deterministic: fixed-order reductions. */
+int gabp_model_grad(gabp_model *model, const float *U, const float *T, int64_t count,
+                    float *grad, double *loss, hipStream_t stream);
+int gabp_model_train_step(gabp_model *model, const float *U, const float *T, int64_t count,
+                          double lr, double *loss, hipStream_t stream);
+/* Inputs and targets of grid nodes: nodes device [count] node indices, or NULL
+ * for nodes 0..count-1 (an index outside [0, N) yields a zero row); b device
+ * [N]; P, h device [6][N] messages as gabp_plan_get_messages returns them for
+ * a grid plan. */
+int gabp_model_grid_features(const gabp_grid *A, const double *b, const int64_t *nodes,
+                             int64_t count, float *U, hipStream_t stream);
+int gabp_model_grid_targets(const gabp_grid *A, const double *P, const double *h,
+                            const int64_t *nodes, int64_t count, float *T, hipStream_t stream);
+/* gabp_plan_solve of a grid plan starting from the network's messages, with
+ * plain zero-message GaBP as the fallback (see gabp_stats.warm_start). */
+int gabp_plan_solve_warm(gabp_plan *plan, const gabp_model *model, const double *b, double *x,
+                         double *marg_prec, gabp_stats *st, hipStream_t stream);
 
 /* Library version string. */
 const char *gabp_version(void);

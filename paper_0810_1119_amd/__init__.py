@@ -18,4 +18,8 @@ from ._abi import (  # noqa: F401
     DeviceGrid, gabp_plan_create_grid, gabp_solve_grid, gabp_residual_grid,
     GABP_BATCH_BIPARTITE, GABP_BATCH_DENSE, DeviceBatch,
     gabp_plan_create_batched, gabp_plan_solve_batched, gabp_solve_batched,
+    GABP_MODEL_INPUTS, GABP_MODEL_OUTPUTS, GABP_MODEL_PARAMS, Model,
+    gabp_model_create, gabp_model_get_params, gabp_model_set_params, gabp_model_forward,
+    gabp_model_grad, gabp_model_train_step, gabp_model_grid_features, gabp_model_grid_targets,
+    gabp_plan_solve_warm,
 )

@@ -67,7 +67,8 @@ class Stats(C.Structure):
                 ("residual_per_eq", C.c_double), ("seconds", C.c_double),
                 ("sweep_ms", C.c_double), ("frozen_sweep_ms", C.c_double), ("edges", C.c_int64),
                 ("edge_updates_per_s", C.c_double), ("damping", C.c_double),
-                ("batch_waves", C.c_int32), ("batch_groups", C.c_int32)]
+                ("batch_waves", C.c_int32), ("batch_groups", C.c_int32),
+                ("warm_start", C.c_int32), ("pad_", C.c_int32), ("warm_rel0", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -94,6 +95,17 @@ _sig = {
     "gabp_plan_solve_batched": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(Stats), _vp]),
     "gabp_solve_batched": (C.c_int, [C.c_void_p, _vp, _vp, C.POINTER(Opts), _vp, C.POINTER(Stats),
                                      _vp]),
+    "gabp_model_create": (C.c_int, [C.c_uint64, C.POINTER(_vp), _vp]),
+    "gabp_model_destroy": (C.c_int, [_vp]),
+    "gabp_model_get_params": (C.c_int, [_vp, _vp, _vp]),
+    "gabp_model_set_params": (C.c_int, [_vp, _vp, _vp]),
+    "gabp_model_forward": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
+    "gabp_model_grad": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, C.POINTER(C.c_double), _vp]),
+    "gabp_model_train_step": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_double,
+                                        C.POINTER(C.c_double), _vp]),
+    "gabp_model_grid_features": (C.c_int, [C.c_void_p, _vp, _vp, C.c_int64, _vp, _vp]),
+    "gabp_model_grid_targets": (C.c_int, [C.c_void_p, _vp, _vp, _vp, C.c_int64, _vp, _vp]),
+    "gabp_plan_solve_warm": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(Stats), _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)
@@ -395,3 +407,114 @@ def gabp_solve_batched(B: DeviceBatch, b, x, opts: Opts | None = None, per_insta
                                 C.byref(opts) if opts is not None else None, per,
                                 C.byref(summary), _stream(stream))
     return rc, (list(per)[:B.count] if per is not None else None), summary
+
+
+# ---------------------------------------------------------------------------
+# learned warm start (grid plans)
+# ---------------------------------------------------------------------------
+GABP_MODEL_INPUTS = 8
+GABP_MODEL_OUTPUTS = 12
+GABP_MODEL_PARAMS = 5516
+
+
+def _check_f32(t, n, name):
+    import torch
+    if t is None:
+        return
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: expected a contiguous float32 CUDA tensor of {n} elements")
+
+
+class Model:
+    """Handle of a gabp_model (the warm-start network on the device)."""
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib.gabp_model_destroy(self.ptr)
+            self.ptr = None
+
+
+def gabp_model_create(seed: int = 0, stream=None):
+    h = C.c_void_p()
+    rc = lib.gabp_model_create(int(seed), C.byref(h), _stream(stream))
+    return rc, (Model(h.value) if rc == GABP_OK else None)
+
+
+def gabp_model_get_params(model: Model, stream=None):
+    import numpy as np
+    out = np.empty(GABP_MODEL_PARAMS, dtype=np.float32)
+    rc = lib.gabp_model_get_params(model.ptr, out.ctypes.data_as(C.c_void_p), _stream(stream))
+    return rc, out
+
+
+def gabp_model_set_params(model: Model, params, stream=None) -> int:
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != GABP_MODEL_PARAMS:
+        raise ValueError("params: expected 5516 values")
+    return lib.gabp_model_set_params(model.ptr, p.ctypes.data_as(C.c_void_p), _stream(stream))
+
+
+def gabp_model_forward(model: Model, U, out, stream=None) -> int:
+    n = U.numel() // GABP_MODEL_INPUTS
+    _check_f32(U, n * GABP_MODEL_INPUTS, "U"); _check_f32(out, n * GABP_MODEL_OUTPUTS, "out")
+    return lib.gabp_model_forward(model.ptr, _ptr(U), n, _ptr(out), _stream(stream))
+
+
+def gabp_model_grad(model: Model, U, T, grad=None, stream=None):
+    """Returns (status, loss); the gradient goes to `grad` (float32 CUDA, 5516)."""
+    n = U.numel() // GABP_MODEL_INPUTS
+    _check_f32(U, n * GABP_MODEL_INPUTS, "U"); _check_f32(T, n * GABP_MODEL_OUTPUTS, "T")
+    _check_f32(grad, GABP_MODEL_PARAMS, "grad")
+    loss = C.c_double(0.0)
+    rc = lib.gabp_model_grad(model.ptr, _ptr(U), _ptr(T), n, _ptr(grad), C.byref(loss),
+                             _stream(stream))
+    return rc, loss.value
+
+
+def gabp_model_train_step(model: Model, U, T, lr: float, stream=None):
+    """One Adam step; returns (status, loss before the step)."""
+    n = U.numel() // GABP_MODEL_INPUTS
+    _check_f32(U, n * GABP_MODEL_INPUTS, "U"); _check_f32(T, n * GABP_MODEL_OUTPUTS, "T")
+    loss = C.c_double(0.0)
+    rc = lib.gabp_model_train_step(model.ptr, _ptr(U), _ptr(T), n, float(lr), C.byref(loss),
+                                   _stream(stream))
+    return rc, loss.value
+
+
+def _check_i64(t, n, name):
+    import torch
+    if t is None:
+        return
+    if t.dtype != torch.int64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: expected a contiguous int64 CUDA tensor of {n} elements")
+
+
+def gabp_model_grid_features(A: DeviceGrid, b, U, nodes=None, stream=None) -> int:
+    count = A.n if nodes is None else nodes.numel()
+    _check_f64(b, A.n, "b"); _check_f32(U, count * GABP_MODEL_INPUTS, "U")
+    _check_i64(nodes, count, "nodes")
+    a = A.c()
+    return lib.gabp_model_grid_features(C.byref(a), _ptr(b), _ptr(nodes), count, _ptr(U),
+                                        _stream(stream))
+
+
+def gabp_model_grid_targets(A: DeviceGrid, P, h, T, nodes=None, stream=None) -> int:
+    count = A.n if nodes is None else nodes.numel()
+    _check_f64(P, 6 * A.n, "P"); _check_f64(h, 6 * A.n, "h")
+    _check_f32(T, count * GABP_MODEL_OUTPUTS, "T"); _check_i64(nodes, count, "nodes")
+    a = A.c()
+    return lib.gabp_model_grid_targets(C.byref(a), _ptr(P), _ptr(h), _ptr(nodes), count, _ptr(T),
+                                       _stream(stream))
+
+
+def gabp_plan_solve_warm(plan, model: Model, b, x, marg_prec=None, stream=None):
+    nb, nx, _ = _lens(plan)
+    _check_f64(b, nb, "b"); _check_f64(x, nx, "x"); _check_f64(marg_prec, nx, "marg_prec")
+    st = Stats()
+    rc = lib.gabp_plan_solve_warm(plan.ptr, model.ptr, _ptr(b), _ptr(x), _ptr(marg_prec),
+                                  C.byref(st), _stream(stream))
+    return rc, st

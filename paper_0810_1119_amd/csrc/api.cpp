@@ -75,7 +75,7 @@ int Engine::read_sum(hipStream_t s, HostReadout *outv) {
 }
 
 int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
-                 hipStream_t s) {
+                 hipStream_t s, const uint16_t *warm) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!p || (p->n > 0 && (!b || !x))) return GABP_ERR_ARG;
   gabp_stats stats{};
@@ -127,6 +127,28 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
       TRY_HIP(hipStreamSynchronize(s));
     }
     return finish(GABP_OK);
+  }
+
+  if (warm) {
+    // Messages from the warm-start network.  They are kept only if the means
+    // they imply fit b better than x = 0 does; otherwise the solve starts
+    // from zero messages as Algorithm 1 does.
+    TRY_HIP(p->warm_start(warm, s));
+    TRY_HIP(p->infer(x, nullptr, s));
+    TRY_HIP(p->residual(b, x, nullptr, s));
+    HostReadout rw;
+    if ((rc = p->read_sum(s, &rw))) return finish(rc);
+    const double rel0 = std::sqrt(rw.sum) / bn;
+    TRY_HIP(launch_fill_zero(x, p->n, s));
+    if (rel0 <= 1.0 && !(rw.flags & (FLAG_NONFINITE | FLAG_BREAKDOWN))) {
+      TRY_HIP(p->residual(b, x, nullptr, s));  // right-hand side back to b (x = 0)
+      stats.warm_start = 1;
+    } else {
+      TRY_HIP(launch_fill_zero4(p->sticky, 1, s));
+      TRY_HIP(p->reset(b, s));
+      stats.warm_start = -1;
+    }
+    stats.warm_rel0 = rel0;
   }
 
   int status = GABP_NOT_CONVERGED;

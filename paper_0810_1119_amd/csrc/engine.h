@@ -73,6 +73,9 @@ struct Engine {
   virtual hipError_t ensure_frozen_buffers() { return hipSuccess; }
   virtual bool frozen_ready() const { return false; }
   virtual hipError_t freeze(hipStream_t) { return hipErrorNotSupported; }
+  // initial messages from the warm-start network (bfloat16 parameters)
+  virtual bool has_warm_start() const { return false; }
+  virtual hipError_t warm_start(const uint16_t *, hipStream_t) { return hipErrorNotSupported; }
   // trajectory access (full state only)
   virtual int get_messages(double *P, double *h, hipStream_t s) = 0;
   virtual int set_messages(const double *P, const double *h, hipStream_t s) = 0;
@@ -83,9 +86,10 @@ struct Engine {
 
 // refinement loop around chunked sweeps (api.cpp)
 int engine_solve(Engine *e, const double *b, double *x, double *marg, gabp_stats *st,
-                 hipStream_t s);
+                 hipStream_t s, const uint16_t *warm = nullptr);
 
 int check_opts(const gabp_opts *o);  // engine_csr.cpp
+int check_grid(const gabp_grid *A, GridGeom *g);  // engine_grid.cpp
 
 // batches of dense instances (engine_dense.cpp)
 struct BatchEngine;

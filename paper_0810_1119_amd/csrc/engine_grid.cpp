@@ -10,9 +10,6 @@
 
 namespace gabp {
 
-
-namespace {
-
 int check_grid(const gabp_grid *A, GridGeom *g) {
   if (!A || A->nx < 1 || A->ny < 1 || A->nz < 1 || A->batch < 1) return GABP_ERR_ARG;
   const int64_t N = (int64_t)A->nx * A->ny * A->nz * A->batch;
@@ -25,6 +22,8 @@ int check_grid(const gabp_grid *A, GridGeom *g) {
   g->nx = A->nx; g->ny = A->ny; g->nz = A->nz; g->batch = A->batch; g->N = (int)N;
   return GABP_OK;
 }
+
+namespace {
 
 bool grid_varc(const gabp_grid *A) { return A->cx || A->diag; }
 
@@ -125,6 +124,15 @@ struct GridEngine : Engine {
 
   hipError_t residual(const double *b, const double *x, double *r64, hipStream_t s) override {
     return launch_grid_residual(g, k64, varc, nsum, b, x, rhs, fp32, r64, sumpart, s);
+  }
+
+  bool has_warm_start() const override { return true; }
+  hipError_t warm_start(const uint16_t *w, hipStream_t s) override {
+    cur = 0;
+    frozen = false;
+    return launch_grid_warm(fp32, g, varc ? wdiag : nullptr, varc ? wcx : nullptr,
+                            varc ? wcy : nullptr, varc ? wcz : nullptr, A.diag_value, A.off_value,
+                            rhs, w, msg[0], s);
   }
 
   bool can_freeze() const override { return true; }

@@ -301,4 +301,37 @@ hipError_t launch_dense_prepare(const DenseArgs &a, uint32_t *flags, hipStream_t
 hipError_t launch_dense_marginals(const DenseArgs &a, double *mean, double *prec, bool all,
                                   hipStream_t s);
 
+// ---- warm-start network (kernels_mlp.hip) ----
+struct MlpTrainArgs {
+  const uint16_t *w;            // bfloat16 parameters used by the passes
+  const float *U, *T;           // [S][8] features, [S][12] targets
+  int64_t S;
+  float *H1, *H2, *R, *D1, *D2; // activations and errors, feature-major [width][S]
+  double *part;                 // forward partials, 2 per block
+  float *gpart;                 // weight-gradient partials [blocks][params]
+  double *lossv;                // [loss, unmasked outputs]
+  float *grad;                  // nullable: the gradient
+  bool update;                  // Adam step
+  float *master, *m1, *m2;      // FP32 masters and moments
+  uint16_t *wbf;                // bfloat16 copy written by the update
+  float lr, c1, c2;             // step size, bias corrections 1 - beta^t
+};
+int mlp_params();
+int mlp_chunk();
+int mlp_fwd_blocks(int64_t S);
+hipError_t launch_mlp_set(const float *src, float *master, uint16_t *wbf, float *m1, float *m2,
+                          hipStream_t s);
+hipError_t launch_mlp_get(const uint16_t *wbf, float *dst, hipStream_t s);
+hipError_t launch_mlp_forward(const uint16_t *w, const float *U, int64_t S, float *out,
+                              hipStream_t s);
+hipError_t launch_mlp_train(const MlpTrainArgs &a, hipStream_t s);
+hipError_t launch_grid_features(const GridGeom &g, const GridCoef<double> &k, const double *b,
+                                const int64_t *nodes, int64_t count, float *U, hipStream_t s);
+hipError_t launch_grid_targets(const GridGeom &g, const GridCoef<double> &k, const double *P,
+                               const double *h, const int64_t *nodes, int64_t count, float *T,
+                               hipStream_t s);
+hipError_t launch_grid_warm(bool fp32, const GridGeom &g, const void *diag, const void *cx,
+                            const void *cy, const void *cz, double dconst, double aconst,
+                            const void *rhs, const uint16_t *w, void *msg, hipStream_t s);
+
 }  // namespace gabp

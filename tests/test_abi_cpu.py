@@ -23,7 +23,12 @@ def _declared():
 
 @pytest.fixture(scope="module")
 def lib():
-    from paper_0810_1119_amd import build
+    # build.py by path: importing the package would load the library first
+    import importlib.util
+    path = os.path.join(ROOT, "paper_0810_1119_amd", "build.py")
+    spec = importlib.util.spec_from_file_location("gabp_hip_build", path)
+    build = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(build)
     if not os.path.exists(build.LIB):
         build.build()
     return ctypes.CDLL(build.LIB)

@@ -466,3 +466,28 @@ def poisson2d_rect(nx: int, ny: int, shift: float = 0.0) -> CSR:
         for u, v in ((a, b), (b, a)):
             rows.append(u.ravel()); cols.append(v.ravel()); vals.append(np.full(u.size, -1.0))
     return csr_from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+def mlp_params(seed: int, n_in: int = 8, n_hid: int = 64, n_out: int = 12, scale: float = 1.0):
+    """Random parameters of the 8-64-64-12 warm-start network, flat in the
+    order W1 (n_hid x n_in, row-major), b1, W2, b2, W3, b3: He-uniform
+    weights (bound sqrt(6 / fan_in)) times `scale`, biases U(-0.1, 0.1)."""
+    rng = np.random.default_rng([seed, 0x31F])
+    parts = []
+    for rows, cols in ((n_hid, n_in), (n_hid, n_hid), (n_out, n_hid)):
+        bound = scale * np.sqrt(6.0 / cols)
+        parts.append(rng.uniform(-bound, bound, size=rows * cols))
+        parts.append(rng.uniform(-0.1, 0.1, size=rows))
+    return np.concatenate(parts)
+
+
+def mlp_batch(count: int, seed: int, n_in: int = 8, n_out: int = 12, p_mask: float = 0.8):
+    """Random training batch: features N(0, 1), targets N(0, 1), output mask
+    Bernoulli(p_mask) per sample and direction (pairs of outputs)."""
+    rng = np.random.default_rng([seed, 0xB7C])
+    U = rng.standard_normal((count, n_in))
+    T = rng.standard_normal((count, n_out))
+    on = rng.random((count, n_out // 2)) < p_mask
+    U[:, 1:1 + n_out // 2] *= on  # a direction without a neighbour has coupling 0
+    M = np.repeat(on, 2, axis=1).astype(np.float64)
+    return U, T * M, M
