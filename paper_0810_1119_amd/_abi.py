@@ -44,6 +44,12 @@ class GabpError(RuntimeError):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+# torch ships its own HIP runtime under the same soname as the system one that
+# libgabp.so is linked against.  Loading torch first makes the library bind to
+# that same runtime; loading the library first would put two runtimes in the
+# process and the library would then see no device.
+import torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 
 

@@ -23,7 +23,15 @@
 
 #include "engine.h"
 
+#include <cstdio>
+#include <cstdlib>
+
 namespace gabp {
+
+void report_hip(hipError_t e, const char *file, int line) {
+  static const bool on = std::getenv("GABP_VERBOSE") != nullptr;
+  if (on) std::fprintf(stderr, "gabp: %s (%d) at %s:%d\n", hipGetErrorName(e), (int)e, file, line);
+}
 
 Engine::~Engine() {
   void *bufs[] = {part, sumpart, sticky, ctl, xprev};
@@ -114,7 +122,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   if (p->fp32) TRY_HIP(launch_fill_zero4(p->xprev, p->n, s));
   else TRY_HIP(launch_fill_zero(p->xprev, p->n, s));
   TRY_HIP(launch_fill_zero(x, p->n, s));
-  TRY_HIP(launch_ctl_reset(p->ctl, target_for(1.0), floor, freeze_tol, true, s));
+  TRY_HIP(launch_ctl_reset(p->ctl, target_for(1.0), floor, freeze_tol, true, 0, s));
   HostReadout r0;
   int rc = p->read_sum(s, &r0);
   if (rc) return finish(rc);
@@ -123,7 +131,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   if (bn == 0.0) {
     stats.rel_residual = 0.0;
     if (marg_prec) {
-      TRY_HIP(p->infer(nullptr, marg_prec, s));
+      TRY_HIP(p->infer(nullptr, marg_prec, nullptr, s));
       TRY_HIP(hipStreamSynchronize(s));
     }
     return finish(GABP_OK);
@@ -134,7 +142,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
     // they imply fit b better than x = 0 does; otherwise the solve starts
     // from zero messages as Algorithm 1 does.
     TRY_HIP(p->warm_start(warm, s));
-    TRY_HIP(p->infer(x, nullptr, s));
+    TRY_HIP(p->infer(x, nullptr, nullptr, s));
     TRY_HIP(p->residual(b, x, nullptr, s));
     HostReadout rw;
     if ((rc = p->read_sum(s, &rw))) return finish(rc);
@@ -155,7 +163,10 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   int sweeps_done = 0;
   double rel_prev = 1.0;
   for (int pass = 0;; ++pass) {
-    if (pass > 0) TRY_HIP(launch_ctl_reset(p->ctl, target_for(rel_prev), floor, freeze_tol, false, s));
+    if (pass > 0) TRY_HIP(launch_ctl_reset(p->ctl, target_for(rel_prev), floor, freeze_tol, false, 0, s));
+    // the first check of the pass measures its change from these means (the
+    // messages the pass starts from), not from those of another right-hand side
+    TRY_HIP(p->infer(nullptr, nullptr, p->xprev, s));
     // ---- inner solve: chunks of c sweeps, lookahead, device-side stop ----
     const int budget = o.max_sweeps - sweeps_done;
     int enq = 0, rd = 0, enq_sweeps = 0, last_sweeps = sweeps_done;
@@ -205,11 +216,14 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
     sweeps_done = last_sweeps;
     stats.sweeps = sweeps_done;
     // ---- x += H/S, r = b - A x (FP64), ||r|| ----
-    TRY_HIP(p->infer(x, nullptr, s));
+    TRY_HIP(p->infer(x, nullptr, nullptr, s));
     TRY_HIP(p->residual(b, x, nullptr, s));
     HostReadout rr;
     if ((rc = p->read_sum(s, &rr))) return finish(rc);
     const double rel = std::sqrt(rr.sum) / bn;
+    if (std::getenv("GABP_VERBOSE"))
+      std::fprintf(stderr, "gabp: pass %d: %d sweeps (%d settled), rel. residual %.3e\n", pass,
+                   sweeps_done, stats.frozen_sweeps, rel);
     rel_prev = rel;
     stats.rel_residual = rel;
     stats.residual_per_eq = std::sqrt(rr.sum) / p->n;
@@ -227,7 +241,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
     TRY_HIP(p->restart(s));
     stats.restarts += 1;
   }
-  if (marg_prec) TRY_HIP(p->infer(nullptr, marg_prec, s));
+  if (marg_prec) TRY_HIP(p->infer(nullptr, marg_prec, nullptr, s));
   TRY_HIP(hipStreamSynchronize(s));
   return finish(status);
 }
@@ -259,6 +273,7 @@ void gabp_default_opts(gabp_opts *o) {
 }
 
 int gabp_plan_destroy(gabp_plan *p) {
+  clear_stale_error();
   if (!p) return GABP_ERR_ARG;
   (void)hipDeviceSynchronize();
   delete p->eng;
@@ -269,12 +284,14 @@ int gabp_plan_destroy(gabp_plan *p) {
 
 int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
                     hipStream_t s) {
+  clear_stale_error();
   if (p && p->bat) return batch_solve(p->bat, b, x, marg_prec, nullptr, st, s);
   if (!p || !p->eng) return GABP_ERR_ARG;
   return engine_solve(p->eng, b, x, marg_prec, st, s);
 }
 
 int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
+  clear_stale_error();
   if (p && p->bat) return batch_reset(p->bat, b, s);
   if (!p || !p->eng || (p->eng->n > 0 && !b)) return GABP_ERR_ARG;
   if (p->eng->n == 0) return GABP_OK;
@@ -285,6 +302,7 @@ int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
 }
 
 int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
+  clear_stale_error();
   if (p && p->bat) return batch_sweeps(p->bat, count, s);
   if (!p || !p->eng || count < 0) return GABP_ERR_ARG;
   Engine *e = p->eng;
@@ -295,22 +313,25 @@ int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
 }
 
 int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s) {
+  clear_stale_error();
   if (p && p->bat) return batch_marginals(p->bat, mean, prec, s);
   if (!p || !p->eng || (p->eng->n > 0 && !mean)) return GABP_ERR_ARG;
   if (p->eng->n == 0) return GABP_OK;
   TRY_HIP(launch_fill_zero(mean, p->eng->n, s));
-  TRY_HIP(p->eng->infer(mean, prec, s));
+  TRY_HIP(p->eng->infer(mean, prec, nullptr, s));
   TRY_HIP(hipStreamSynchronize(s));
   return GABP_OK;
 }
 
 int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
+  clear_stale_error();
   if (p && p->bat) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
   return p->eng->get_messages(P, h, s);
 }
 
 int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipStream_t s) {
+  clear_stale_error();
   if (p && p->bat) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
   return p->eng->set_messages(P, h, s);

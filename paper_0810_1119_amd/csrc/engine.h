@@ -14,11 +14,23 @@ namespace gabp {
 constexpr int kRing = 4;       // readout slots / events in flight
 constexpr int kLookahead = 2;  // chunks queued ahead of the one being read
 
-inline int from_hip(hipError_t e) {
+// With GABP_VERBOSE set in the environment, every HIP failure the library
+// turns into a status is reported on stderr with its source line.
+void report_hip(hipError_t e, const char *file, int line);
+
+inline int from_hip_at(hipError_t e, const char *file, int line) {
   if (e == hipSuccess) return GABP_OK;
+  report_hip(e, file, line);
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return GABP_ERR_NOMEM;
   return GABP_ERR_HIP;
 }
+#define from_hip(e) from_hip_at((e), __FILE__, __LINE__)
+
+// The launch helpers report hipGetLastError(); an error some earlier,
+// unrelated HIP call left behind (the caller's, or an optional attribute
+// query of ours) must not be taken for ours, so every entry point of the C
+// ABI starts by clearing it.
+inline void clear_stale_error() { (void)hipGetLastError(); }
 
 #define TRY_HIP(expr)                          \
   do {                                         \
@@ -60,8 +72,9 @@ struct Engine {
   // one synchronous sweep from buffer cur into cur ^ 1 (mode 0: sweep,
   // 1: sweep + check of the means); c = controller or NULL
   virtual hipError_t sweep(int mode, const Ctl *c, hipStream_t s) = 0;
-  // x += H/S (FP64) and/or marginal precisions, from the current messages
-  virtual hipError_t infer(double *xacc, double *marg, hipStream_t s) = 0;
+  // x += H/S (FP64), marginal precisions and/or the means in working
+  // precision (into `means`, n entries), from the current messages
+  virtual hipError_t infer(double *xacc, double *marg, void *means, hipStream_t s) = 0;
   // zero every information message, keep the precisions (rhs already holds r)
   virtual hipError_t restart(hipStream_t s) = 0;
   // zero all messages, rhs = b, full state; ||b||^2 into the residual partials

@@ -97,16 +97,17 @@ struct CsrEngine : Engine {
     return err;
   }
 
-  hipError_t infer(double *xacc, double *marg, hipStream_t s) override {
+  hipError_t infer(double *xacc, double *marg, void *means, hipStream_t s) override {
     if (!pair) {
       SweepArgs a{};
       a.grid = grid; a.fp32 = fp32; a.group = group; a.mode = 2; a.n = n; a.oprt = oprt;
       a.rev = rev; a.acoef = acoef; a.diag = diag; a.rhs = rhs; a.msg_in = msg[cur];
-      a.xacc = xacc; a.marg = marg; a.sticky = sticky;
+      a.xacc = xacc; a.marg = marg; a.xprev = means; a.sticky = sticky;
       return launch_sweep(a, s);
     }
-    if (frozen) return launch_pair_infer(fp32, n, nullptr, Sfix, Hfz[cur], xacc, marg, sticky, s);
-    return launch_pair_infer(fp32, n, sums[cur], nullptr, nullptr, xacc, marg, sticky, s);
+    if (frozen)
+      return launch_pair_infer(fp32, n, nullptr, Sfix, Hfz[cur], xacc, marg, means, sticky, s);
+    return launch_pair_infer(fp32, n, sums[cur], nullptr, nullptr, xacc, marg, means, sticky, s);
   }
 
   hipError_t restart(hipStream_t s) override {
@@ -240,6 +241,7 @@ using namespace gabp;
 extern "C" {
 
 int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
+  clear_stale_error();
   if (!plan) return GABP_ERR_ARG;
   *plan = nullptr;
   gabp_opts opts;
@@ -283,6 +285,7 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
 
 int gabp_solve(const gabp_csr *A, const double *b, double *x, double *marg_prec,
                const gabp_opts *o, gabp_stats *st, hipStream_t s) {
+  clear_stale_error();
   gabp_plan *p = nullptr;
   int rc = gabp_plan_create(A, o, &p, s);
   if (rc) {
@@ -296,6 +299,7 @@ int gabp_solve(const gabp_csr *A, const double *b, double *x, double *marg_prec,
 
 int gabp_residual(const gabp_csr *A, const double *b, const double *x, double *r,
                   double *rel_norm, hipStream_t s) {
+  clear_stale_error();
   int rc = check_csr(A);
   if (rc) return rc;
   if (!rel_norm || (A->n > 0 && (!b || !x))) return GABP_ERR_ARG;

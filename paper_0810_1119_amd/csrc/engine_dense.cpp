@@ -413,6 +413,7 @@ extern "C" {
 
 int gabp_plan_create_batched(const gabp_batch *B, const gabp_opts *o, gabp_plan **plan,
                              hipStream_t s) {
+  clear_stale_error();
   if (!plan) return GABP_ERR_ARG;
   *plan = nullptr;
   BatchEngine *e = nullptr;
@@ -426,12 +427,14 @@ int gabp_plan_create_batched(const gabp_batch *B, const gabp_opts *o, gabp_plan 
 
 int gabp_plan_solve_batched(gabp_plan *p, const double *b, double *x, gabp_stats *per,
                             gabp_stats *summary, hipStream_t s) {
+  clear_stale_error();
   if (!p || !p->bat) return GABP_ERR_ARG;
   return batch_solve(p->bat, b, x, nullptr, per, summary, s);
 }
 
 int gabp_solve_batched(const gabp_batch *B, const double *b, double *x, const gabp_opts *o,
                        gabp_stats *per, gabp_stats *summary, hipStream_t s) {
+  clear_stale_error();
   BatchEngine *e = nullptr;
   int st = batch_create(B, o, &e, s);
   if (st) return st;

@@ -99,11 +99,12 @@ struct GridEngine : Engine {
     return err;
   }
 
-  hipError_t infer(double *xacc, double *marg, hipStream_t s) override {
+  hipError_t infer(double *xacc, double *marg, void *means, hipStream_t s) override {
     GridArgs a = args(2, nullptr);
     a.msg_in = frozen ? hh[cur] : msg[cur];
     a.xacc = xacc;
     a.marg = marg;
+    a.xprev = means;
     return launch_grid_sweep(a, s);
   }
 
@@ -212,6 +213,7 @@ using namespace gabp;
 extern "C" {
 
 int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
+  clear_stale_error();
   if (!plan) return GABP_ERR_ARG;
   *plan = nullptr;
   gabp_opts opts;
@@ -254,6 +256,7 @@ int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **pl
 
 int gabp_solve_grid(const gabp_grid *A, const double *b, double *x, double *marg_prec,
                     const gabp_opts *o, gabp_stats *st, hipStream_t s) {
+  clear_stale_error();
   gabp_plan *p = nullptr;
   int rc = gabp_plan_create_grid(A, o, &p, s);
   if (rc) {
@@ -267,6 +270,7 @@ int gabp_solve_grid(const gabp_grid *A, const double *b, double *x, double *marg
 
 int gabp_residual_grid(const gabp_grid *A, const double *b, const double *x, double *r,
                        double *rel_norm, hipStream_t s) {
+  clear_stale_error();
   GridGeom g{};
   int rc = check_grid(A, &g);
   if (rc) return rc;

@@ -55,7 +55,10 @@ struct Ctl {
   double freeze_tol;   // precision messages count as settled when their
                        // largest change <= freeze_tol * largest |P|
   int32_t freeze;      // set once the precision messages have settled
-  int32_t pad;
+  int32_t warmup;      // checks left that only refresh the previous means: the
+                       // first check of a pass compares against means of
+                       // another right-hand side (or zeros), so its change is
+                       // no measure of this pass's convergence
 };
 
 // What the host reads back (pinned, written by the readout kernel).
@@ -128,7 +131,7 @@ hipError_t launch_readout(const BlockPartial *part, int nparts, const double *su
                           const uint32_t *sticky, Ctl *ctl, int sweeps_in_chunk, int seq,
                           HostReadout *host, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl *ctl, double target, double floor, double freeze_tol, bool full,
-                            hipStream_t s);
+                            int warmup, hipStream_t s);
 
 hipError_t launch_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s);
 hipError_t launch_fill_zero(void *p, int64_t bytes8, hipStream_t s);  // bytes8: count of 8-byte words
@@ -167,7 +170,8 @@ hipError_t launch_pair_aggregate(bool fp32, int group, int grid, int n, const in
                                  const void *rhs, const void *msg, void *sums, hipStream_t s);
 hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s);
 hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfix, const void *Hfz,
-                             double *xacc, double *marg, uint32_t *sticky, hipStream_t s);
+                             double *xacc, double *marg, void *means, uint32_t *sticky,
+                             hipStream_t s);
 hipError_t launch_pair_freeze(bool fp32, int group, int grid, int n, const int32_t *oprt, const int32_t *ocol,
                               const void *acoef, const void *msg, const void *sums, void *coef,
                               void *hp, void *Sfix, void *Hfz, hipStream_t s);

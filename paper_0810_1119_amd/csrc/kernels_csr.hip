@@ -327,6 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_sweep(
       } else {
         if (xacc) xacc[row] += (double)H / (double)S;
         if (marg) marg[row] = (double)S;
+        if (xprev) xprev[row] = x;  // means of the current messages
       }
       ax = fmax(ax, (double)fabs(x));
     }
@@ -479,7 +480,13 @@ __global__ __launch_bounds__(kBlock) void k_readout(
     pm = fmax(pm, sh[4][k]);
   }
   const uint32_t flags = sticky ? *sticky : 0u;
-  if (nparts > 0 && ctl->stop == STOP_NONE) {
+  if (nparts > 0 && ctl->stop == STOP_NONE && ctl->warmup > 0) {
+    ctl->sweeps += sweeps_in_chunk;
+    ctl->checks += 1;
+    ctl->warmup -= 1;
+    ctl->last_d = 0.0;
+    if (flags & (FLAG_NONFINITE | FLAG_BREAKDOWN)) ctl->stop = STOP_NONFINITE;
+  } else if (nparts > 0 && ctl->stop == STOP_NONE) {
     ctl->sweeps += sweeps_in_chunk;
     ctl->checks += 1;
     const double rel = d / fmax(x, 1e-300);
@@ -519,7 +526,8 @@ hipError_t launch_readout(const BlockPartial *part, int nparts, const double *su
   return hipGetLastError();
 }
 
-__global__ void k_ctl_reset(Ctl *ctl, double target, double floor, double freeze_tol, int full) {
+__global__ void k_ctl_reset(Ctl *ctl, double target, double floor, double freeze_tol, int full,
+                            int warmup) {
   if (threadIdx.x != 0) return;
   ctl->freeze_tol = freeze_tol;
   ctl->stop = STOP_NONE;
@@ -529,6 +537,7 @@ __global__ void k_ctl_reset(Ctl *ctl, double target, double floor, double freeze
   ctl->last_d = 0.0;
   ctl->last_x = 0.0;
   ctl->est = 1e300;
+  ctl->warmup = warmup;
   if (full) {
     ctl->sweeps = 0;
     ctl->checks = 0;
@@ -537,9 +546,9 @@ __global__ void k_ctl_reset(Ctl *ctl, double target, double floor, double freeze
 }
 
 hipError_t launch_ctl_reset(Ctl *ctl, double target, double floor, double freeze_tol, bool full,
-                            hipStream_t s) {
+                            int warmup, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, target, floor, freeze_tol,
-                     full ? 1 : 0);
+                     full ? 1 : 0, warmup);
   return hipGetLastError();
 }
 

@@ -423,7 +423,12 @@ __device__ DenseStat solve_instance(const DenseArgs &a, const DenseInst &I, cons
     double last_d = 0.0;
     int stall = 0, slow = 0, in_pass = 0;
     bool brk = false, nf = false, escalate = false;
-    for (int c = thread_id(); c < C; c += NT) L.xprev[c] = T(0);
+    // the first check of the pass measures its change from the means of the
+    // messages it starts from (not from zeros or another right-hand side)
+    for (int c = thread_id(); c < C; c += NT) {
+      const T2 t = L.tot_col[c];
+      L.xprev[c] = t.x != T(0) ? t.y / t.x : T(0);
+    }
     while (s.sweeps < a.max_sweeps) {
       T dp = T(0), pm = T(0);
       if (frozen) {
@@ -751,8 +756,10 @@ int dense_batch_occupancy(const DenseArgs &a) {
   const void *k = pick(a);
   if (!k) return 0;
   const size_t lds = lds_bytes(a);
-  if (lds > 65536)
+  if (lds > 65536) {
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();  // optional: the occupancy query below decides
+  }
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, a.waves * 64, lds) != hipSuccess) {
     (void)hipGetLastError();
@@ -766,8 +773,10 @@ hipError_t launch_dense_batch(const DenseArgs &a, hipStream_t s) {
   const void *k = pick(a);
   if (!k) return hipErrorInvalidValue;
   const size_t lds = lds_bytes(a);
-  if (lds > 65536)
+  if (lds > 65536) {
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();  // optional: the launch below reports what matters
+  }
   DenseArgs arg = a;
   void *params[] = {&arg};
   return hipLaunchKernel(k, dim3(a.grid), dim3(a.waves * 64), params, lds, s);

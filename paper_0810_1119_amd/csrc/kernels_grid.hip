@@ -142,6 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(
       } else {
         if (xacc) xacc[i] += (double)H / (double)S;
         if (marg) marg[i] = (double)S;
+        if (xprev) xprev[i] = x;  // means of the current messages
       }
       xmax = fmax(xmax, (double)fabs(x));
     }
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_frozen(
       } else {
         if (xacc) xacc[i] += (double)H / (double)S;
         if (marg) marg[i] = (double)S;
+        if (xprev) xprev[i] = x;  // means of the current messages
       }
       xmax = fmax(xmax, (double)fabs(x));
     }

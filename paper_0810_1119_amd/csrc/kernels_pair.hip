@@ -167,7 +167,7 @@ template <typename T>
 __global__ void k_pair_infer(int n, const typename Vec2<T>::type *__restrict__ sums,
                              const T *__restrict__ Sfix, const T *__restrict__ Hfz,
                              double *__restrict__ xacc, double *__restrict__ marg,
-                             uint32_t *__restrict__ sticky) {
+                             T *__restrict__ means, uint32_t *__restrict__ sticky) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T S, H;
@@ -181,6 +181,7 @@ __global__ void k_pair_infer(int n, const typename Vec2<T>::type *__restrict__ s
   if (S == T(0)) atomicOr(sticky, FLAG_BREAKDOWN);
   if (xacc) xacc[i] += (double)H / (double)S;
   if (marg) marg[i] = (double)S;
+  if (means) means[i] = H / S;
 }
 
 // ---------------------------------------------------------------------------
@@ -401,15 +402,17 @@ hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s) {
 }
 
 hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfix, const void *Hfz,
-                             double *xacc, double *marg, uint32_t *sticky, hipStream_t s) {
+                             double *xacc, double *marg, void *means, uint32_t *sticky,
+                             hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const dim3 grid((n + kBlock - 1) / kBlock);
   if (fp32)
     hipLaunchKernelGGL(k_pair_infer<float>, grid, dim3(kBlock), 0, s, n, (const float2 *)sums,
-                       (const float *)Sfix, (const float *)Hfz, xacc, marg, sticky);
+                       (const float *)Sfix, (const float *)Hfz, xacc, marg, (float *)means, sticky);
   else
     hipLaunchKernelGGL(k_pair_infer<double>, grid, dim3(kBlock), 0, s, n, (const double2 *)sums,
-                       (const double *)Sfix, (const double *)Hfz, xacc, marg, sticky);
+                       (const double *)Sfix, (const double *)Hfz, xacc, marg, (double *)means,
+                       sticky);
   return hipGetLastError();
 }
 

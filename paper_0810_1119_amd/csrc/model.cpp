@@ -116,6 +116,7 @@ const uint16_t *model_weights(const gabp_model *m) { return m ? m->wbf : nullptr
 extern "C" {
 
 int gabp_model_create(uint64_t seed, gabp_model **out, hipStream_t s) {
+  clear_stale_error();
   if (!out) return GABP_ERR_ARG;
   *out = nullptr;
   auto *m = new (std::nothrow) gabp_model();
@@ -147,6 +148,7 @@ int gabp_model_create(uint64_t seed, gabp_model **out, hipStream_t s) {
 }
 
 int gabp_model_destroy(gabp_model *m) {
+  clear_stale_error();
   if (!m) return GABP_ERR_ARG;
   (void)hipDeviceSynchronize();
   delete m;
@@ -154,6 +156,7 @@ int gabp_model_destroy(gabp_model *m) {
 }
 
 int gabp_model_get_params(const gabp_model *m, float *params, hipStream_t s) {
+  clear_stale_error();
   if (!m || !params) return GABP_ERR_ARG;
   float *tmp = nullptr;
   TRY_HIP(dalloc(&tmp, mlp_params(), sizeof(float)));
@@ -166,6 +169,7 @@ int gabp_model_get_params(const gabp_model *m, float *params, hipStream_t s) {
 }
 
 int gabp_model_set_params(gabp_model *m, const float *params, hipStream_t s) {
+  clear_stale_error();
   if (!m || !params) return GABP_ERR_ARG;
   for (int p = 0; p < mlp_params(); ++p)
     if (!std::isfinite(params[p])) return GABP_ERR_ARG;
@@ -174,6 +178,7 @@ int gabp_model_set_params(gabp_model *m, const float *params, hipStream_t s) {
 
 int gabp_model_forward(const gabp_model *m, const float *U, int64_t count, float *out,
                        hipStream_t s) {
+  clear_stale_error();
   if (!m || count < 0 || (count > 0 && (!U || !out))) return GABP_ERR_ARG;
   TRY_HIP(launch_mlp_forward(m->wbf, U, count, out, s));
   TRY_HIP(hipStreamSynchronize(s));
@@ -182,16 +187,19 @@ int gabp_model_forward(const gabp_model *m, const float *U, int64_t count, float
 
 int gabp_model_grad(gabp_model *m, const float *U, const float *T, int64_t count, float *grad,
                     double *loss, hipStream_t s) {
+  clear_stale_error();
   return run(m, U, T, count, grad, false, 0.0, loss, s);
 }
 
 int gabp_model_train_step(gabp_model *m, const float *U, const float *T, int64_t count,
                           double lr, double *loss, hipStream_t s) {
+  clear_stale_error();
   return run(m, U, T, count, nullptr, true, lr, loss, s);
 }
 
 int gabp_model_grid_features(const gabp_grid *A, const double *b, const int64_t *nodes,
                              int64_t count, float *U, hipStream_t s) {
+  clear_stale_error();
   GridGeom g{};
   int st;
   if ((st = check_grid(A, &g))) return st;
@@ -204,6 +212,7 @@ int gabp_model_grid_features(const gabp_grid *A, const double *b, const int64_t 
 
 int gabp_model_grid_targets(const gabp_grid *A, const double *P, const double *h,
                             const int64_t *nodes, int64_t count, float *T, hipStream_t s) {
+  clear_stale_error();
   GridGeom g{};
   int st;
   if ((st = check_grid(A, &g))) return st;
@@ -216,6 +225,7 @@ int gabp_model_grid_targets(const gabp_grid *A, const double *P, const double *h
 
 int gabp_plan_solve_warm(gabp_plan *p, const gabp_model *m, const double *b, double *x,
                          double *marg_prec, gabp_stats *st, hipStream_t s) {
+  clear_stale_error();
   if (!p || !m) return GABP_ERR_ARG;
   if (!p->eng || !p->eng->has_warm_start()) return GABP_ERR_UNSUPPORTED;  // grid plans only
   gabp_stats a{};
