@@ -166,22 +166,23 @@ __global__ __launch_bounds__(kBlock) void k_grid_frozen(
   for (int base = tile0 * kBlock; base < N; base += gridDim.x * kBlock) {
     const int i = base + threadIdx.x;
     if (i >= N) continue;
+    // Edges from the geometry alone: the freeze stored zero coefficients and
+    // zero informations on faces whose coupling is zero, so those carry zeros
+    // both ways and the couplings need not be read in this phase.
     Nbr nb;
     neighbours(g, i, nb);
-    T a[6];
-    couplings<T, VARC>(g, k, i, nb, a);
     T hin[6];
     T H = rhs[i];
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
       hin[d] = T(0);
-      if (a[d] != T(0)) hin[d] = hin_arr[(size_t)(d ^ 1) * N + nb.j[d]];
+      if (nb.ok[d]) hin[d] = hin_arr[(size_t)(d ^ 1) * N + nb.j[d]];
       H += hin[d];
     }
     if (MODE != 2) {
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
-        if (a[d] == T(0)) continue;
+        if (!nb.ok[d]) continue;
         T h = coef[(size_t)d * N + i] * (H - hin[d]);
         if (DAMP) h = alpha * hin_arr[(size_t)d * N + i] + (T(1) - alpha) * h;
         hout_arr[(size_t)d * N + i] = h;
