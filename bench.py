@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--layout", type=int, default=0, help="0 pair, 1 gather")
     ap.add_argument("--freeze", type=int, default=1)
+    ap.add_argument("--freeze-tol", type=float, default=0.0,
+                    help="settled-precision threshold (0 = library default)")
     ap.add_argument("--grid", type=int, default=0, help="sweep grid cap (0 = library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte "
@@ -169,6 +171,7 @@ def run_c2(args, G, W, torch, dev):
         opts.group = args.group
     opts.layout = args.layout
     opts.freeze = args.freeze
+    opts.freeze_tol = args.freeze_tol
     opts.grid_blocks = args.grid
     rc, plan = G.gabp_plan_create(A, opts)
     if rc != G.GABP_OK:
@@ -318,6 +321,14 @@ def bench_c4(args, G, W, torch, dev):
         torch.cuda.synchronize()
         res[kind] = (time.perf_counter() - t0, runs)
     G.gabp_plan_destroy(plan)
+    # each grid's own FP64 residual (the stop rule is the stack's), outside the timing
+    nn = n ** 3
+    worst_grid = 0.0
+    for t in range(count):
+        sl = slice(t * nn, (t + 1) * nn)
+        At = G.DeviceGrid(n, n, n, 1, diag=A.diag[sl], cx=A.cx[sl], cy=A.cy[sl], cz=A.cz[sl])
+        rc, rel = G.gabp_residual_grid(At, b[sl], x[sl])
+        worst_grid = max(worst_grid, rel)
     dt, runs = res["plain"]
     sweeps = sum(st.sweeps for st in runs)
     frozen = sum(st.frozen_sweeps for st in runs)
@@ -344,6 +355,8 @@ def bench_c4(args, G, W, torch, dev):
             "sweeps_plain": sweeps / args.steps,
             "sweeps_warm": sum(st.sweeps for st in wruns) / args.steps,
             "warm_start_status": wruns[-1].warm_start,
+            "rel_residual_stack": runs[-1].rel_residual,
+            "rel_residual_worst_grid_after_warm": worst_grid,
             "warm_speedup": dt / wdt,
             "warm_model": {k: meta[k] for k in ("grids", "samples", "steps", "final_loss")},
         },

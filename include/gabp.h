@@ -101,6 +101,8 @@ typedef struct {
                           refinement absorbs the last-ulp difference.  0: never */
   int32_t batch_waves; /* batched solves: wavefronts (64 lanes) per workgroup,
                           4, 8 or 16; 0 = chosen by the plan's autotuner */
+  double freeze_tol;    /* the settled-precision threshold (see freeze); 0 = the
+                          default, 1e-6 for FP32 messages and 1e-14 for FP64 */
   int32_t adapt_damping; /* batched solves, 1 (default): an instance whose means
                           stop contracting (ratio of successive changes >= 0.95
                           at 8 checks in a row after the first 32 sweeps of a

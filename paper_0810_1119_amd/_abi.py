@@ -63,7 +63,7 @@ class Opts(C.Structure):
                 ("check_every", C.c_int32), ("damping", C.c_double), ("inner_tol", C.c_double),
                 ("max_restarts", C.c_int32), ("group", C.c_int32), ("layout", C.c_int32),
                 ("grid_blocks", C.c_int32), ("freeze", C.c_int32), ("batch_waves", C.c_int32),
-                ("adapt_damping", C.c_int32)]
+                ("freeze_tol", C.c_double), ("adapt_damping", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -111,7 +111,8 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   // settling in between; 1e-6 leaves them at FP32 resolution by then on the
   // workloads measured, and the FP64 refinement absorbs any remainder.
   const bool freezing = o.freeze && p->can_freeze();
-  const double freeze_tol = freezing ? (p->fp32 ? 1e-6 : 1e-14) : -1.0;
+  const double freeze_tol =
+      freezing ? (o.freeze_tol > 0.0 ? o.freeze_tol : (p->fp32 ? 1e-6 : 1e-14)) : -1.0;
   auto target_for = [&](double rel) {
     if (o.inner_tol > 0) return o.inner_tol;
     return std::min(0.5, std::max(0.3 * o.tol / rel, p->fp32 ? 1e-7 : 1e-15));

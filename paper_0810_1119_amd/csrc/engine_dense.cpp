@@ -69,7 +69,7 @@ struct BatchEngine {
     a.alpha = o.damping;
     a.inner_tol = o.inner_tol;
     a.freeze = o.freeze != 0 && fcoef != nullptr;
-    a.freeze_tol = a.freeze ? (fp32 ? 1e-6 : 1e-14) : -1.0;
+    a.freeze_tol = a.freeze ? (o.freeze_tol > 0.0 ? o.freeze_tol : (fp32 ? 1e-6 : 1e-14)) : -1.0;
     a.floor = fp32 ? 1e-6 : 1e-14;
     a.max_sweeps = o.max_sweeps;
     a.max_restarts = o.max_restarts;
