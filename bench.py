@@ -90,10 +90,11 @@ def grid_bytes_per_sweep(N: int, E: int, frozen: bool, damped: bool, check_every
     return per_edge * E + 4.0 * N + 8.0 * N / check_every
 
 
-def measured_traffic(kernel_key: str):
-    """HBM bytes per launch of a kernel from the committed PMC summary
-    (profiles/traffic.json): the average over its sweep and check variants,
-    or None when the kernel's source changed since the counters were taken."""
+def measured_traffic(kernel_key: str, workload: str):
+    """HBM bytes per launch of a kernel on a workload from the committed PMC
+    summary (profiles/traffic.json): the average over its sweep and check
+    variants, or None when no counters were taken for that workload or the
+    kernel's source changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -101,7 +102,7 @@ def measured_traffic(kernel_key: str):
     t = json.load(open(path))
     vals = []
     for name, rec in t["kernels"].items():
-        if not name.startswith(kernel_key):
+        if not name.startswith(kernel_key) or rec.get("workload") != workload:
             continue
         src = os.path.join(ROOT, "paper_0810_1119_amd", "csrc", rec["source"])
         if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
@@ -272,7 +273,7 @@ def bench_c3(args, G, W, torch, dev):
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("gabp::(anonymous namespace)::k_dense_batch<float, 4, 0>"),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("gabp::(anonymous namespace)::k_dense_batch<float, 4, 0>", "c3"),
             "kernel": "k_dense_batch<float,4,bipartite> (persistent: A1-A4 for every instance)",
             "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": algo / args.steps,
             "launches_timed": args.steps,
@@ -363,7 +364,7 @@ def bench_c4(args, G, W, torch, dev):
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("gabp::k_grid_frozen<float, "),
+            "traffic": measured_traffic("gabp::k_grid_frozen<float, ", "c4"),
             "kernel": "k_grid_frozen<float,*,undamped,varcoef> (settled-precision sweep)",
             "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bps,
             "launches_timed": frozen,
@@ -500,7 +501,7 @@ def main():
     else:
         kname, bps, launches, kms = w["kfull"], w["bytes_full"], full_sweeps, full_ms
         tkey = w.get("tkey_full")
-    traffic = measured_traffic(tkey) if tkey else None
+    traffic = measured_traffic(tkey, args.workload) if tkey else None
     avg_s = kms * 1e-3 / max(launches, 1)
     achieved = bps / avg_s / 1e9
     out = {
