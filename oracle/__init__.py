@@ -59,6 +59,9 @@ def _load():
         lib.orc_alg1_round.restype = i64
         lib.orc_alg2_round.argtypes = lib.orc_alg1_round.argtypes
         lib.orc_alg2_round.restype = i64
+        lib.orc_alg2_color_round.argtypes = [C.POINTER(_Csr), vp, vp, vp, vp, vp, vp, C.c_int,
+                                             f64, C.c_int]
+        lib.orc_alg2_color_round.restype = i64
         lib.orc_marginals.argtypes = [C.POINTER(_Csr), vp, vp, vp, vp, vp, vp, vp, C.c_int]
         lib.orc_residual.argtypes = [C.POINTER(_Csr), vp, vp, vp]
         lib.orc_residual.restype = f64
@@ -111,22 +114,49 @@ def reverse(m):
     return st, rev, diag
 
 
-class Rounds:
-    """Round-by-round access for trajectory comparisons (P, mu per CSR slot)."""
+def is_proper_colouring(m, colors) -> bool:
+    """True when no off-diagonal nonzero joins two nodes of the same colour."""
+    colors = np.asarray(colors)
+    rows = np.repeat(np.arange(m.n), np.diff(np.asarray(m.row_ptr)))
+    cols = np.asarray(m.col)
+    off = rows != cols
+    return bool(np.all(colors[rows[off]] != colors[cols[off]]))
 
-    def __init__(self, m, b, algorithm: int = 2, damping: float = 0.0, nthreads: int = 0):
+
+class Rounds:
+    """Round-by-round access for trajectory comparisons (P, mu per CSR slot).
+
+    colors=None: the synchronous schedule of Algorithm 1 / 2 (one step = one
+    round).  colors = a proper node colouring 0..C-1: the coloured schedule
+    (one step = every class sending once, class 0 first)."""
+
+    def __init__(self, m, b, algorithm: int = 2, damping: float = 0.0, nthreads: int = 0,
+                 colors=None):
         self.M = Matrix(m)
         self.b = _f64(b, self.M.n)
         st, self.rev, self.diag = reverse(m)
         if st != OK:
             raise ValueError(f"oracle rejected the matrix: status {st}")
         self.algorithm, self.damping, self.nthreads = algorithm, damping, nthreads
+        self.colors = None
+        if colors is not None:
+            if not is_proper_colouring(m, colors):
+                raise ValueError("the colouring puts both ends of an edge in one class")
+            self.colors = np.ascontiguousarray(colors, dtype=np.int8)
         self.P = np.zeros(self.M.nnz)
         self.Mu = np.zeros(self.M.nnz)
         self.zero_cavities = 0
 
     def step(self, count: int = 1):
         lib = _load()
+        if self.colors is not None:
+            ncol = int(self.colors.max()) + 1 if self.colors.size else 0
+            for _ in range(count):
+                for c in range(ncol):
+                    self.zero_cavities += lib.orc_alg2_color_round(
+                        C.byref(self.M.c), _p(self.b), _p(self.rev), _p(self.diag), _p(self.P),
+                        _p(self.Mu), _p(self.colors), c, self.damping, self.nthreads)
+            return self
         fn = lib.orc_alg1_round if self.algorithm == 1 else lib.orc_alg2_round
         for _ in range(count):
             P2, M2 = np.empty_like(self.P), np.empty_like(self.Mu)

@@ -196,6 +196,53 @@ int64_t orc_alg2_round(const orc_csr *A, const double *b, const int64_t *rev,
   return zeros;
 }
 
+/* A coloured (serial-like) schedule: one class of a proper node colouring
+ * sends all of its messages, computed as in Algorithm 2 from the messages as
+ * they are now, and the classes take turns within a sweep.  The update is in
+ * place: with a proper colouring no edge joins two nodes of the class, so
+ * none of the messages a node of the class reads is written in its round.
+ * Damping mixes in the node's own previous message, as in the synchronous
+ * round.  Returns the number of zero cavity precisions met. */
+int64_t orc_alg2_color_round(const orc_csr *A, const double *b, const int64_t *rev,
+                             const double *diag, double *P, double *M, const int8_t *color,
+                             int c, double damping, int nthreads) {
+  int64_t zeros = 0;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(static) reduction(+ : zeros)
+  for (int32_t i = 0; i < A->n; ++i) {
+    if (color[i] != c) continue;
+    const double Pii = diag[i];
+    const double muii = b[i] / diag[i];
+    double Pt = Pii;
+    double num = Pii * muii;
+    for (int64_t f = A->row_ptr[i]; f < A->row_ptr[i + 1]; ++f) {
+      if (A->col[f] == i) continue;
+      const int64_t in = rev[f];
+      Pt += P[in];
+      num += P[in] * M[in];
+    }
+    const double mut = num / Pt;
+    for (int64_t e = A->row_ptr[i]; e < A->row_ptr[i + 1]; ++e) {
+      if (A->col[e] == i) continue;
+      const int64_t in = rev[e]; /* message j -> i, not written in this round */
+      const double cav = Pt - P[in];
+      if (cav == 0.0) ++zeros;
+      const double Aij = A->val[e];
+      double Pn = -Aij * Aij / cav;
+      double mu = (Pt * mut - P[in] * M[in]) / Aij;
+      if (damping > 0.0) {
+        const double Pd = damping * P[e] + (1.0 - damping) * Pn;
+        const double hd = damping * P[e] * M[e] + (1.0 - damping) * Pn * mu;
+        Pn = Pd;
+        mu = hd / Pd;
+      }
+      P[e] = Pn;
+      M[e] = mu;
+    }
+  }
+  return zeros;
+}
+
 /* Algorithm 1 step 4: marginal means and (optionally) marginal precisions
  *   P_i = P_ii + sum_{k in N(i)} P_ki,
  *   mu_i = (P_ii mu_ii + sum_{k in N(i)} P_ki mu_ki) / P_i. */

@@ -321,3 +321,80 @@ def test_poisson3d_row_order_construction():
         b = W.csr_from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
         assert np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col, b.col)
         assert np.array_equal(a.val, b.val)
+
+
+# ---------------------------------------------------------------------------
+# Coloured (serial-like) schedule.  On a bipartite graph the synchronous
+# rounds split into two independent chains (messages of one class at odd
+# rounds feed the other class at even rounds), and a two-colour schedule runs
+# one of them: after k coloured sweeps class 0 holds the synchronous messages
+# of round 2k - 1 and class 1 those of round 2k, exactly.
+# ---------------------------------------------------------------------------
+def _grid_colours(nx, ny, nz=1):
+    i = np.arange(nx * ny * nz)
+    return ((i % nx) + (i // nx) % ny + i // (nx * ny)) % 2
+
+
+def _class_slots(m, colors, c):
+    rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+    return (colors[rows] == c) & (rows != m.col)
+
+
+@pytest.mark.parametrize("case", ["grid2d", "grid3d", "tree", "bipartite"])
+def test_two_colour_schedule_runs_one_synchronous_chain(case):
+    if case == "grid2d":
+        m = W.poisson2d_rect(7, 5, 0.1); col = _grid_colours(7, 5)
+    elif case == "grid3d":
+        m = W.poisson3d(4, 3, 5, 0.2); col = _grid_colours(4, 3, 5)
+    elif case == "tree":
+        m = W.random_tree(40, 3)
+        # two-colour a tree by depth parity
+        A = W.dense_from_csr(m) != 0
+        col = -np.ones(m.n, dtype=int); col[0] = 0; todo = [0]
+        while todo:
+            i = todo.pop()
+            for j in np.nonzero(A[i])[0]:
+                if j != i and col[j] < 0:
+                    col[j] = 1 - col[i]; todo.append(j)
+    else:
+        db = W.detection_sizes([6], [12], seed=4)
+        S, y, _, s2 = db.instance(0)
+        m, b = oracle.bipartite_system(S, y, s2)
+        col = np.r_[np.ones(6, dtype=int), np.zeros(12, dtype=int)]  # chips send first
+    b = W.uniform_b(m.n, 7) if case != "bipartite" else b
+    assert oracle.is_proper_colouring(m, col)
+    sync = oracle.Rounds(m, b)
+    colr = oracle.Rounds(m, b, colors=col)
+    s0, s1 = _class_slots(m, col, 0), _class_slots(m, col, 1)
+    hist = {}
+    for t in range(1, 13):
+        sync.step()
+        hist[t] = (sync.P.copy(), sync.Mu.copy())
+    for k in range(1, 7):
+        colr.step()
+        P1, M1 = hist[2 * k - 1]
+        P2, M2 = hist[2 * k]
+        assert np.array_equal(colr.P[s0], P1[s0]) and np.array_equal(colr.Mu[s0], M1[s0])
+        assert np.array_equal(colr.P[s1], P2[s1]) and np.array_equal(colr.Mu[s1], M2[s1])
+
+
+def test_coloured_schedule_reaches_the_solution_in_about_half_the_sweeps():
+    m = W.poisson2d(16)
+    b = W.uniform_b(m.n, 3)
+    x = np.linalg.solve(W.dense_from_csr(m), b)
+    def sweeps(colors):
+        R = oracle.Rounds(m, b, colors=colors)
+        for t in range(1, 5000):
+            R.step()
+            mean, _ = R.marginals()
+            if np.abs(mean - x).max() <= 1e-10 * np.abs(x).max():
+                return t
+        raise AssertionError("no convergence")
+    s_sync, s_col = sweeps(None), sweeps(_grid_colours(16, 16))
+    assert s_col <= 0.6 * s_sync, (s_sync, s_col)
+
+
+def test_colouring_must_be_proper():
+    m = W.poisson2d(4)
+    with pytest.raises(ValueError):
+        oracle.Rounds(m, np.ones(m.n), colors=np.zeros(m.n, dtype=int))
