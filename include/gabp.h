@@ -109,9 +109,19 @@ typedef struct {
                           pass) or turn non-finite runs that pass again from
                           zero messages with the damping raised to 0.3, then
                           0.5, then 0.7 (damping as in section VI-D); 0 = never */
+  int32_t schedule;     /* GABP_SCHEDULE_SYNC (default): every message of a sweep
+                          from the previous sweep's messages (the parallel
+                          scheme of section III-C); GABP_SCHEDULE_COLORED: grid
+                          plans only, the serial scheme of section III-C in
+                          checkerboard order: one sweep lets every node of
+                          colour 0 ((x + y + z) even, z counted over the whole
+                          stack) send from the newest messages, then every node
+                          of colour 1.  Other plans return
+                          GABP_ERR_UNSUPPORTED */
 } gabp_opts;
 
 enum { GABP_LAYOUT_PAIR = 0, GABP_LAYOUT_GATHER = 1 };
+enum { GABP_SCHEDULE_SYNC = 0, GABP_SCHEDULE_COLORED = 1 };
 
 typedef struct {
   int32_t status;          /* gabp_status of the solve */

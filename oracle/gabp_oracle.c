@@ -196,9 +196,10 @@ int64_t orc_alg2_round(const orc_csr *A, const double *b, const int64_t *rev,
   return zeros;
 }
 
-/* A coloured (serial-like) schedule: one class of a proper node colouring
- * sends all of its messages, computed as in Algorithm 2 from the messages as
- * they are now, and the classes take turns within a sweep.  The update is in
+/* A coloured (serial-like) schedule, section III-C's serial scheme in an
+ * order fixed by a proper node colouring: one class sends all of its
+ * messages, computed as in Algorithm 2 from the messages as they are now,
+ * and the classes take turns within a sweep.  The update is in
  * place: with a proper colouring no edge joins two nodes of the class, so
  * none of the messages a node of the class reads is written in its round.
  * Damping mixes in the node's own previous message, as in the synchronous

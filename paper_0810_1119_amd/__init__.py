@@ -10,7 +10,7 @@ fails if the library has not been built.
 from ._abi import (  # noqa: F401
     GABP_OK, GABP_NOT_CONVERGED, GABP_ERR_ARG, GABP_ERR_NOT_SYMMETRIC, GABP_ERR_ZERO_DIAG,
     GABP_ERR_BREAKDOWN, GABP_ERR_DIVERGED, GABP_ERR_HIP, GABP_ERR_NOMEM, GABP_ERR_UNSUPPORTED,
-    GABP_LAYOUT_PAIR, GABP_LAYOUT_GATHER,
+    GABP_LAYOUT_PAIR, GABP_LAYOUT_GATHER, GABP_SCHEDULE_SYNC, GABP_SCHEDULE_COLORED,
     LIB_PATH, DeviceCSR, GabpError, Opts, Stats, lib, status_name,
     gabp_default_opts, gabp_solve, gabp_residual, gabp_plan_create, gabp_plan_destroy,
     gabp_plan_solve, gabp_plan_reset, gabp_plan_sweeps, gabp_plan_marginals,

@@ -24,6 +24,8 @@ GABP_ERR_NOMEM = -7
 GABP_ERR_UNSUPPORTED = -8
 GABP_LAYOUT_PAIR = 0
 GABP_LAYOUT_GATHER = 1
+GABP_SCHEDULE_SYNC = 0
+GABP_SCHEDULE_COLORED = 1
 GABP_BATCH_BIPARTITE = 0
 GABP_BATCH_DENSE = 1
 
@@ -63,7 +65,8 @@ class Opts(C.Structure):
                 ("check_every", C.c_int32), ("damping", C.c_double), ("inner_tol", C.c_double),
                 ("max_restarts", C.c_int32), ("group", C.c_int32), ("layout", C.c_int32),
                 ("grid_blocks", C.c_int32), ("freeze", C.c_int32), ("batch_waves", C.c_int32),
-                ("freeze_tol", C.c_double), ("adapt_damping", C.c_int32)]
+                ("freeze_tol", C.c_double), ("adapt_damping", C.c_int32),
+                ("schedule", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -53,7 +53,7 @@ int Engine::init_common(hipStream_t s) {
       (st = from_hip(dalloc(&sumpart, nsum, sizeof(double)))) ||
       (st = from_hip(dalloc(&sticky, 1, sizeof(uint32_t)))) ||
       (st = from_hip(dalloc(&ctl, 1, sizeof(Ctl)))) ||
-      (st = from_hip(dalloc(&xprev, n, tsz))))
+      (st = from_hip(dalloc(&xprev, means_slots(), tsz))))
     return st;
   if ((st = from_hip(hipHostMalloc((void **)&host, kRing * sizeof(HostReadout), hipHostMallocDefault))))
     return st;
@@ -120,8 +120,8 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   if (freezing) TRY_HIP(p->ensure_frozen_buffers());
   TRY_HIP(launch_fill_zero4(p->sticky, 1, s));
   TRY_HIP(p->reset(b, s));  // also computes ||b||^2 into the residual partials
-  if (p->fp32) TRY_HIP(launch_fill_zero4(p->xprev, p->n, s));
-  else TRY_HIP(launch_fill_zero(p->xprev, p->n, s));
+  if (p->fp32) TRY_HIP(launch_fill_zero4(p->xprev, p->means_slots(), s));
+  else TRY_HIP(launch_fill_zero(p->xprev, p->means_slots(), s));
   TRY_HIP(launch_fill_zero(x, p->n, s));
   TRY_HIP(launch_ctl_reset(p->ctl, target_for(1.0), floor, freeze_tol, true, 0, s));
   HostReadout r0;
@@ -271,6 +271,7 @@ void gabp_default_opts(gabp_opts *o) {
   o->freeze = 1;
   o->batch_waves = 0;
   o->adapt_damping = 1;
+  o->schedule = GABP_SCHEDULE_SYNC;
 }
 
 int gabp_plan_destroy(gabp_plan *p) {

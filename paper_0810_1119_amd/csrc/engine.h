@@ -68,12 +68,15 @@ struct Engine {
   virtual ~Engine();
   // allocate the controller plumbing (after n, nparts, nsum are known)
   int init_common(hipStream_t s);
+  // entries of xprev (the means of the last check, in the engine's order)
+  virtual int64_t means_slots() const { return n; }
 
-  // one synchronous sweep from buffer cur into cur ^ 1 (mode 0: sweep,
-  // 1: sweep + check of the means); c = controller or NULL
+  // one sweep (mode 0: sweep, 1: sweep + check of the means); c = controller
+  // or NULL.  Synchronous: from buffer cur into cur ^ 1; coloured: every
+  // colour class in turn, in place.
   virtual hipError_t sweep(int mode, const Ctl *c, hipStream_t s) = 0;
   // x += H/S (FP64), marginal precisions and/or the means in working
-  // precision (into `means`, n entries), from the current messages
+  // precision (into `means`, means_slots() entries), from the current messages
   virtual hipError_t infer(double *xacc, double *marg, void *means, hipStream_t s) = 0;
   // zero every information message, keep the precisions (rhs already holds r)
   virtual hipError_t restart(hipStream_t s) = 0;

@@ -43,7 +43,8 @@ int check_opts(const gabp_opts *o) {
       !(o->damping < 1.0) || !(o->inner_tol >= 0.0) || o->max_restarts < 0 ||
       !(o->freeze_tol >= 0.0) || !(o->freeze_tol < 1.0) ||
       (o->group != 0 && !valid_group(o->group)) || o->grid_blocks < 0 ||
-      (o->layout != GABP_LAYOUT_PAIR && o->layout != GABP_LAYOUT_GATHER))
+      (o->layout != GABP_LAYOUT_PAIR && o->layout != GABP_LAYOUT_GATHER) ||
+      (o->schedule != GABP_SCHEDULE_SYNC && o->schedule != GABP_SCHEDULE_COLORED))
     return GABP_ERR_ARG;
   return GABP_OK;
 }
@@ -251,6 +252,7 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
   int st = check_csr(A);
   if (st) return st;
   if ((st = check_opts(&opts))) return st;
+  if (opts.schedule != GABP_SCHEDULE_SYNC) return GABP_ERR_UNSUPPORTED;
   CsrEngine *e = new (std::nothrow) CsrEngine();
   if (!e) return GABP_ERR_NOMEM;
   e->A = *A;

@@ -192,6 +192,7 @@ int batch_create(const gabp_batch *B, const gabp_opts *o, BatchEngine **out, hip
   int st = check_batch(B);
   if (st) return st;
   if (o && (st = check_opts(o))) return st;
+  if (o && o->schedule != GABP_SCHEDULE_SYNC) return GABP_ERR_UNSUPPORTED;
   if (o && o->batch_waves != 0 && o->batch_waves != 4 && o->batch_waves != 8 &&
       o->batch_waves != 16)
     return GABP_ERR_ARG;

@@ -206,6 +206,110 @@ struct GridEngine : Engine {
   }
 };
 
+// Two-colour schedule: one message buffer, colour-major storage
+// (kernels_grid_rb.hip); a sweep is a launch per colour.
+struct RbGridEngine : GridEngine {
+  int hx = 1, Nc = 0;
+  int rgrid = 1;  // blocks of a one-colour launch
+
+  int64_t means_slots() const override { return 2 * (int64_t)Nc; }
+  int64_t rb_slots() const { return 12 * (int64_t)Nc; }
+
+  RbArgs rargs(int mode, int colour, const Ctl *c) const {
+    RbArgs a{};
+    a.g = g; a.hx = hx; a.Nc = Nc; a.grid = rgrid; a.colour = colour;
+    a.fp32 = fp32; a.varc = varc; a.damp = o.damping > 0.0 && mode != 2;
+    a.frozen = frozen; a.mode = mode;
+    a.diag = wdiag; a.cx = wcx; a.cy = wcy; a.cz = wcz;
+    a.dconst = A.diag_value; a.aconst = A.off_value;
+    a.rhs = rhs; a.msg = frozen ? hh[0] : msg[0]; a.coef = coef; a.Sfix = Sfix;
+    a.alpha = o.damping; a.xprev = xprev;
+    a.part = part + (size_t)colour * rgrid; a.sticky = sticky; a.ctl = c;
+    return a;
+  }
+
+  hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
+    for (int colour = 0; colour < 2; ++colour) {
+      hipError_t err = launch_rb_sweep(rargs(mode, colour, c), s);
+      if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+  }
+
+  hipError_t infer(double *xacc, double *marg, void *means, hipStream_t s) override {
+    for (int colour = 0; colour < 2; ++colour) {
+      RbArgs a = rargs(2, colour, nullptr);
+      a.xacc = xacc;
+      a.marg = marg;
+      a.xprev = means;
+      hipError_t err = launch_rb_sweep(a, s);
+      if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+  }
+
+  hipError_t restart(hipStream_t s) override {
+    if (frozen) return fp32 ? launch_fill_zero4(hh[0], rb_slots(), s) : launch_fill_zero(hh[0], rb_slots(), s);
+    return launch_grid_zero_h(fp32, rb_slots(), msg[0], s);
+  }
+
+  hipError_t reset(const double *b, hipStream_t s) override {
+    frozen = false;
+    hipError_t err = launch_fill_zero(msg[0], rb_slots() * (int64_t)(2 * tsz) / 8, s);
+    if (err != hipSuccess) return err;
+    return launch_grid_residual(g, k64, varc, nsum, b, nullptr, rhs, fp32, nullptr, sumpart, s, hx);
+  }
+
+  hipError_t residual(const double *b, const double *x, double *r64, hipStream_t s) override {
+    return launch_grid_residual(g, k64, varc, nsum, b, x, rhs, fp32, r64, sumpart, s, hx);
+  }
+
+  hipError_t warm_start(const uint16_t *w, hipStream_t s) override {
+    frozen = false;
+    // slots of unused positions and of faces without a coupling stay zero
+    hipError_t err = launch_fill_zero(msg[0], rb_slots() * (int64_t)(2 * tsz) / 8, s);
+    if (err != hipSuccess) return err;
+    return launch_grid_warm(fp32, g, varc ? wdiag : nullptr, varc ? wcx : nullptr,
+                            varc ? wcy : nullptr, varc ? wcz : nullptr, A.diag_value, A.off_value,
+                            rhs, w, msg[0], s, hx);
+  }
+
+  hipError_t ensure_frozen_buffers() override {
+    struct { void **p; size_t count; } need[] = {
+        {&coef, (size_t)rb_slots()}, {&hh[0], (size_t)rb_slots()}, {&Sfix, 2 * (size_t)Nc}};
+    for (auto &b : need)
+      if (!*b.p) {
+        hipError_t err = dalloc(b.p, b.count, tsz);
+        if (err != hipSuccess) return err;
+      }
+    return hipSuccess;
+  }
+
+  bool frozen_ready() const override { return coef && hh[0] && Sfix; }
+
+  hipError_t freeze(hipStream_t s) override {
+    RbArgs a = rargs(0, 0, nullptr);
+    a.msg = msg[0];
+    hipError_t err = launch_rb_freeze(a, hh[0], s);
+    frozen = true;
+    return err;
+  }
+
+  int get_messages(double *P, double *h, hipStream_t s) override {
+    if (!P || !h) return GABP_ERR_ARG;
+    TRY_HIP(launch_rb_io(fp32, true, g, hx, Nc, msg[0], P, h, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    return GABP_OK;
+  }
+
+  int set_messages(const double *P, const double *h, hipStream_t s) override {
+    if (!P || !h) return GABP_ERR_ARG;
+    TRY_HIP(launch_rb_io(fp32, false, g, hx, Nc, msg[0], (double *)P, (double *)h, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    return GABP_OK;
+  }
+};
+
 }  // namespace gabp
 
 using namespace gabp;
@@ -223,7 +327,9 @@ int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **pl
   if ((st = check_opts(&opts))) return st;
   GridGeom g{};
   if ((st = check_grid(A, &g))) return st;
-  GridEngine *e = new (std::nothrow) GridEngine();
+  const bool coloured = opts.schedule == GABP_SCHEDULE_COLORED;
+  RbGridEngine *rb = coloured ? new (std::nothrow) RbGridEngine() : nullptr;
+  GridEngine *e = coloured ? rb : new (std::nothrow) GridEngine();
   if (!e) return GABP_ERR_NOMEM;
   e->A = *A;
   e->g = g;
@@ -237,15 +343,26 @@ int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **pl
   e->grid = need < cap ? need : cap;
   e->nparts = e->grid;
   e->nsum = e->grid;
+  if (rb) {
+    rb->hx = rb_row_slots(g);
+    rb->Nc = rb->hx * (g.N / g.nx);
+    const int rneed = (rb->Nc + kBlock - 1) / kBlock;
+    rb->rgrid = rneed < cap ? rneed : cap;
+    e->nparts = 2 * rb->rgrid;  // a check sweep publishes one partial per block and colour
+  }
   auto fail = [&](int code) {
     delete e;
     return code;
   };
   if ((st = e->init_common(s))) return fail(st);
   if ((st = e->build(s))) return fail(st);
-  if ((st = from_hip(dalloc(&e->msg[0], e->slots(), 2 * e->tsz))) ||
-      (st = from_hip(dalloc(&e->msg[1], e->slots(), 2 * e->tsz))) ||
-      (st = from_hip(dalloc(&e->rhs, g.N, e->tsz))))
+  if (rb) {
+    if ((st = from_hip(dalloc(&e->msg[0], rb->rb_slots(), 2 * e->tsz))) ||
+        (st = from_hip(dalloc(&e->rhs, 2 * (size_t)rb->Nc, e->tsz))))
+      return fail(st);
+  } else if ((st = from_hip(dalloc(&e->msg[0], e->slots(), 2 * e->tsz))) ||
+             (st = from_hip(dalloc(&e->msg[1], e->slots(), 2 * e->tsz))) ||
+             (st = from_hip(dalloc(&e->rhs, g.N, e->tsz))))
     return fail(st);
   gabp_plan *p = new (std::nothrow) gabp_plan();
   if (!p) return fail(GABP_ERR_NOMEM);

@@ -210,9 +210,52 @@ struct GridArgs {
 };
 hipError_t launch_grid_sweep(const GridArgs &a, hipStream_t s);
 hipError_t launch_grid_freeze(const GridArgs &a, hipStream_t s);
+// rT (the working-precision right-hand side) in natural order when hx == 0,
+// else in the two-colour order of a red-black plan with hx slots per row
 hipError_t launch_grid_residual(const GridGeom &g, const GridCoef<double> &k, bool varc, int grid,
                                 const double *b, const double *x, void *rT, bool rT32, double *r64,
-                                double *sumpart, hipStream_t s);
+                                double *sumpart, hipStream_t s, int hx = 0);
+
+// ---- two-colour (red-black) schedule on grids (kernels_grid_rb.hip) ----
+// Node (x, y, z) of a stack (z counted over the whole stack) has colour
+// (x + y + z) & 1; row r = y + ny z holds hx = (nx + 1) / 2 slots of each
+// colour and the node sits in slot r hx + x / 2 of its colour's arrays (with
+// nx odd, one slot per row and colour is never used).  Every per-node and
+// per-direction array of such a plan is colour-major: [2][Nc] or [2][6][Nc],
+// Nc = hx * ny * nz * batch.
+__host__ __device__ inline int rb_row_slots(const GridGeom &g) { return (g.nx + 1) / 2; }
+__host__ __device__ inline void rb_place(const GridGeom &g, int hx, int i, int &colour, int &slot) {
+  const int x = i % g.nx, r = i / g.nx;
+  colour = (x + r % g.ny + r / g.ny) & 1;
+  slot = r * hx + (x >> 1);
+}
+struct RbArgs {
+  GridGeom g;
+  int hx, Nc;          // slots per row and colour, slots per colour
+  int grid;            // blocks of a one-colour launch
+  int colour;          // the class a sweep launch updates
+  bool fp32, varc, damp, frozen;
+  int mode;            // 0 sweep, 1 sweep + check, 2 means / precisions only
+  const void *diag, *cx, *cy, *cz;  // working-precision coefficients, natural order (varc)
+  double dconst, aconst;
+  const void *rhs;     // [2][Nc]
+  void *msg;           // full: (P, h)[2][6][Nc]; frozen: h[2][6][Nc]
+  const void *coef, *Sfix;  // frozen: c[2][6][Nc], S[2][Nc]
+  double alpha;
+  void *xprev;         // [2][Nc]
+  double *xacc, *marg; // natural order
+  BlockPartial *part;  // this launch's partials (grid entries)
+  uint32_t *sticky;
+  const Ctl *ctl;
+};
+hipError_t launch_rb_sweep(const RbArgs &a, hipStream_t s);
+// coefficients, information messages and S of the settled phase from the
+// full state (both colours); hh receives the information messages
+hipError_t launch_rb_freeze(const RbArgs &a, void *hh, hipStream_t s);
+// export (get) / import of the messages in the natural direction-major FP64
+// order [6][N] of the synchronous plans
+hipError_t launch_rb_io(bool fp32, bool get, const GridGeom &g, int hx, int Nc, void *msg,
+                        double *P, double *h, hipStream_t s);
 hipError_t launch_grid_check(const GridGeom &g, const GridCoef<double> &k, bool varc, int grid,
                              uint32_t *flags, hipStream_t s);
 hipError_t launch_to_working(bool fp32, int64_t m, const double *in, void *out, hipStream_t s);
@@ -334,8 +377,10 @@ hipError_t launch_grid_features(const GridGeom &g, const GridCoef<double> &k, co
 hipError_t launch_grid_targets(const GridGeom &g, const GridCoef<double> &k, const double *P,
                                const double *h, const int64_t *nodes, int64_t count, float *T,
                                hipStream_t s);
+// msg and rhs in natural order when hx == 0, else in the two-colour order
 hipError_t launch_grid_warm(bool fp32, const GridGeom &g, const void *diag, const void *cx,
                             const void *cy, const void *cz, double dconst, double aconst,
-                            const void *rhs, const uint16_t *w, void *msg, hipStream_t s);
+                            const void *rhs, const uint16_t *w, void *msg, hipStream_t s,
+                            int hx = 0);
 
 }  // namespace gabp

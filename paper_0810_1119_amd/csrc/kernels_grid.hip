@@ -239,8 +239,9 @@ __global__ __launch_bounds__(kBlock) void k_grid_freeze(
 template <bool VARC>
 __global__ __launch_bounds__(kBlock) void k_grid_residual(
     GridGeom g, GridCoef<double> k, const double *__restrict__ b, const double *__restrict__ x,
-    void *__restrict__ rT, bool rT32, double *__restrict__ r64, double *__restrict__ sumpart) {
+    void *__restrict__ rT, bool rT32, double *__restrict__ r64, double *__restrict__ sumpart, int hx) {
   const int N = g.N;
+  const int Nc = hx * (N / g.nx);
   double sq = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
     double ri = b[i];
@@ -256,8 +257,14 @@ __global__ __launch_bounds__(kBlock) void k_grid_residual(
       ri -= ax;
     }
     if (rT) {
-      if (rT32) ((float *)rT)[i] = (float)ri;
-      else ((double *)rT)[i] = ri;
+      int at = i;
+      if (hx > 0) {
+        int c, slot;
+        rb_place(g, hx, i, c, slot);
+        at = c * Nc + slot;
+      }
+      if (rT32) ((float *)rT)[at] = (float)ri;
+      else ((double *)rT)[at] = ri;
     }
     if (r64) r64[i] = ri;
     sq += ri * ri;
@@ -379,12 +386,12 @@ hipError_t launch_grid_freeze(const GridArgs &a, hipStream_t s) {
 
 hipError_t launch_grid_residual(const GridGeom &g, const GridCoef<double> &k, bool varc, int grid,
                                 const double *b, const double *x, void *rT, bool rT32, double *r64,
-                                double *sumpart, hipStream_t s) {
+                                double *sumpart, hipStream_t s, int hx) {
   if (g.N <= 0) return hipSuccess;
   if (varc)
-    hipLaunchKernelGGL((k_grid_residual<true>), dim3(grid), dim3(kBlock), 0, s, g, k, b, x, rT, rT32, r64, sumpart);
+    hipLaunchKernelGGL((k_grid_residual<true>), dim3(grid), dim3(kBlock), 0, s, g, k, b, x, rT, rT32, r64, sumpart, hx);
   else
-    hipLaunchKernelGGL((k_grid_residual<false>), dim3(grid), dim3(kBlock), 0, s, g, k, b, x, rT, rT32, r64, sumpart);
+    hipLaunchKernelGGL((k_grid_residual<false>), dim3(grid), dim3(kBlock), 0, s, g, k, b, x, rT, rT32, r64, sumpart, hx);
   return hipGetLastError();
 }
 

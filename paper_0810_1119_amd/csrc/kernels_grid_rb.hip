@@ -1,0 +1,350 @@
+// Two-colour (red-black) schedule of GaBP on structured grids, gfx950.
+//
+// The serial scheme of section III-C updates messages one node at a time
+// from the newest messages; on a grid, whose graph is bipartite, the nodes of
+// one colour of the checkerboard colouring share no edge, so all of them can
+// send at once from the messages the other colour sent last.  One sweep is
+// two launches: colour 0 sends, then colour 1.  On a bipartite graph the
+// synchronous schedule runs two independent copies of this recursion (one
+// per parity of the round number) at twice the work; the coloured sweep runs
+// one of them, so it reaches a given accuracy in about half the sweeps at the
+// same bytes per sweep.
+//
+// Storage is colour-major (layout in gabp_internal.h): a launch for colour c
+// reads the in-messages of its nodes from colour 1 - c's arrays at shifted,
+// coalesced slots and updates its own out-messages in place (only one
+// message buffer exists).  No edge joins two nodes of colour c, so no thread
+// reads a message that another thread of the launch writes.  Per node and
+// colour-launch: six (P, h) in-messages read, six written, and the
+// right-hand side: the 16 bytes per edge of the synchronous sweep, in two
+// halves.  The update itself is the synchronous one (information form of
+// eq. prec_message / mean_message); damping mixes in the node's own previous
+// message, read from the slot it overwrites.
+#include "device_common.h"
+
+namespace gabp {
+
+namespace {
+
+// The node a thread of a colour-c launch owns and its neighbours' slots in
+// the other colour's arrays.
+struct RbNode {
+  int i;         // natural index (coefficients, x, marginals)
+  int x;         // x coordinate
+  int j[6];      // slot of the neighbour toward d (valid when ok[d])
+  bool ok[6];
+};
+
+__device__ __forceinline__ bool rb_node(const GridGeom &g, int hx, int c, int s, RbNode &n) {
+  const int r = s / hx;
+  const int kx = s - r * hx;
+  const int y = r % g.ny;
+  const int z = r / g.ny;  // over the whole stack
+  const int zl = z % g.nz;
+  const int x = 2 * kx + ((c + y + z) & 1);
+  if (x >= g.nx) return false;  // unused slot (nx odd)
+  n.i = r * g.nx + x;
+  n.x = x;
+  const int row = r * hx;
+  const int plane = g.ny * hx;
+  n.ok[0] = x < g.nx - 1;  n.j[0] = row + ((x + 1) >> 1);
+  n.ok[1] = x > 0;         n.j[1] = row + ((x - 1) >> 1);
+  n.ok[2] = y < g.ny - 1;  n.j[2] = s + hx;
+  n.ok[3] = y > 0;         n.j[3] = s - hx;
+  n.ok[4] = zl < g.nz - 1; n.j[4] = s + plane;
+  n.ok[5] = zl > 0;        n.j[5] = s - plane;
+  return true;
+}
+
+template <typename T, bool VARC>
+__device__ __forceinline__ void rb_couplings(const GridGeom &g, const GridCoef<T> &k, const RbNode &n,
+                                             T a[6]) {
+  const int i = n.i;
+  if (VARC) {
+    a[0] = n.ok[0] ? k.cx[i] : T(0);
+    a[1] = n.ok[1] ? k.cx[i - 1] : T(0);
+    a[2] = n.ok[2] ? k.cy[i] : T(0);
+    a[3] = n.ok[3] ? k.cy[i - g.nx] : T(0);
+    a[4] = n.ok[4] ? k.cz[i] : T(0);
+    a[5] = n.ok[5] ? k.cz[i - g.nx * g.ny] : T(0);
+  } else {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) a[d] = n.ok[d] ? k.aconst : T(0);
+  }
+}
+
+// XCD-aware tile order, as in the synchronous grid sweep
+__device__ __forceinline__ int rb_tile_of_block() {
+  const int nb = gridDim.x;
+  if (nb % 8 != 0) return blockIdx.x;
+  return (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+}
+
+}  // namespace
+
+// MODE 0 sweep, 1 sweep + check, 2 means / precisions only (no messages)
+template <typename T, int MODE, bool DAMP, bool VARC>
+__global__ __launch_bounds__(kBlock) void k_rb_sweep(
+    GridGeom g, int hx, int Nc, int c, GridCoef<T> k, typename Vec2<T>::type *__restrict__ msg,
+    const T *__restrict__ rhs, T alpha, T *__restrict__ xprev, double *__restrict__ xacc,
+    double *__restrict__ marg, BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky,
+    const Ctl *__restrict__ ctl) {
+  using V = typename Vec2<T>::type;
+  if (ctl != nullptr && ctl->stop != STOP_NONE) return;
+  const V *__restrict__ other = msg + (size_t)(1 - c) * 6 * Nc;
+  V *__restrict__ own = msg + (size_t)c * 6 * Nc;
+  double dmax = 0.0, xmax = 0.0, dpb = 0.0, pmb = 0.0;
+  uint32_t f = 0;
+  const int tile0 = rb_tile_of_block();
+  for (int base = tile0 * kBlock; base < Nc; base += gridDim.x * kBlock) {
+    const int s = base + threadIdx.x;
+    RbNode nd;
+    if (s >= Nc || !rb_node(g, hx, c, s, nd)) continue;
+    T a[6];
+    rb_couplings<T, VARC>(g, k, nd, a);
+    T Pin[6], hin[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      Pin[d] = T(0);
+      hin[d] = T(0);
+      if (a[d] != T(0)) {
+        const V m = other[(size_t)(d ^ 1) * Nc + nd.j[d]];
+        Pin[d] = m.x;
+        hin[d] = m.y;
+      }
+    }
+    T S = VARC ? k.diag[nd.i] : k.dconst, H = rhs[(size_t)c * Nc + s];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      S += Pin[d];
+      H += hin[d];
+    }
+    if (MODE != 2) {
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        if (a[d] == T(0)) continue;
+        const T cav = S - Pin[d];
+        if (cav == T(0)) f |= FLAG_BREAKDOWN;
+        const T inv = T(1) / cav;
+        T P = -(a[d] * a[d]) * inv;
+        T h = -(a[d] * (H - hin[d])) * inv;
+        V *slot = own + (size_t)d * Nc + s;
+        if (DAMP || MODE == 1) {
+          const V o = *slot;
+          if (DAMP) {
+            P = alpha * o.x + (T(1) - alpha) * P;
+            h = alpha * o.y + (T(1) - alpha) * h;
+          }
+          if (MODE == 1) {
+            dpb = fmax(dpb, (double)fabs(P - o.x));
+            pmb = fmax(pmb, (double)fabs(P));
+          }
+        }
+        V out;
+        out.x = P;
+        out.y = h;
+        *slot = out;
+      }
+    }
+    if (MODE >= 1) {
+      if (S == T(0)) f |= FLAG_BREAKDOWN;
+      const T x = H / S;
+      if (!isfinite(x)) f |= FLAG_NONFINITE;
+      T *xp = xprev ? xprev + (size_t)c * Nc + s : nullptr;
+      if (MODE == 1) {
+        dmax = fmax(dmax, (double)fabs(x - *xp));
+        *xp = x;
+      } else {
+        if (xacc) xacc[nd.i] += (double)H / (double)S;
+        if (marg) marg[nd.i] = (double)S;
+        if (xp) *xp = x;  // means of the current messages
+      }
+      xmax = fmax(xmax, (double)fabs(x));
+    }
+  }
+  if (f) atomicOr(sticky, f);
+  if (MODE == 1) block_publish(dmax, xmax, dpb, pmb, part);
+}
+
+// settled phase: information only, fixed coefficients coef[(6 c + d) Nc + s]
+template <typename T, int MODE, bool DAMP>
+__global__ __launch_bounds__(kBlock) void k_rb_frozen(
+    GridGeom g, int hx, int Nc, int c, const T *__restrict__ coef, const T *__restrict__ Sfix,
+    T *__restrict__ hh, const T *__restrict__ rhs, T alpha, T *__restrict__ xprev,
+    double *__restrict__ xacc, double *__restrict__ marg, BlockPartial *__restrict__ part,
+    uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+  if (ctl != nullptr && ctl->stop != STOP_NONE) return;
+  const T *__restrict__ other = hh + (size_t)(1 - c) * 6 * Nc;
+  T *__restrict__ own = hh + (size_t)c * 6 * Nc;
+  const T *__restrict__ cf = coef + (size_t)c * 6 * Nc;
+  double dmax = 0.0, xmax = 0.0;
+  uint32_t f = 0;
+  const int tile0 = rb_tile_of_block();
+  for (int base = tile0 * kBlock; base < Nc; base += gridDim.x * kBlock) {
+    const int s = base + threadIdx.x;
+    RbNode nd;
+    if (s >= Nc || !rb_node(g, hx, c, s, nd)) continue;
+    // faces with a zero coupling hold zero coefficients and zero
+    // informations on both sides since the freeze, so the geometry decides
+    T hin[6];
+    T H = rhs[(size_t)c * Nc + s];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      hin[d] = nd.ok[d] ? other[(size_t)(d ^ 1) * Nc + nd.j[d]] : T(0);
+      H += hin[d];
+    }
+    if (MODE != 2) {
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        if (!nd.ok[d]) continue;
+        const size_t o = (size_t)d * Nc + s;
+        T h = cf[o] * (H - hin[d]);
+        if (DAMP) h = alpha * own[o] + (T(1) - alpha) * h;
+        own[o] = h;
+      }
+    }
+    if (MODE >= 1) {
+      const T S = Sfix[(size_t)c * Nc + s];
+      const T x = H / S;
+      if (!isfinite(x)) f |= FLAG_NONFINITE;
+      T *xp = xprev ? xprev + (size_t)c * Nc + s : nullptr;
+      if (MODE == 1) {
+        dmax = fmax(dmax, (double)fabs(x - *xp));
+        *xp = x;
+      } else {
+        if (xacc) xacc[nd.i] += (double)H / (double)S;
+        if (marg) marg[nd.i] = (double)S;
+        if (xp) *xp = x;
+      }
+      xmax = fmax(xmax, (double)fabs(x));
+    }
+  }
+  if (f) atomicOr(sticky, f);
+  if (MODE == 1) block_publish(dmax, xmax, 0.0, 0.0, part);
+}
+
+// freeze: coefficients, S and information messages of both colours
+template <typename T, bool VARC>
+__global__ __launch_bounds__(kBlock) void k_rb_freeze(GridGeom g, int hx, int Nc, GridCoef<T> k,
+                                                      const typename Vec2<T>::type *__restrict__ msg,
+                                                      T *__restrict__ coef, T *__restrict__ hh,
+                                                      T *__restrict__ Sfix) {
+  const int total = 2 * Nc;
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock) {
+    const int c = t >= Nc ? 1 : 0;
+    const int s = t - c * Nc;
+    RbNode nd;
+    if (!rb_node(g, hx, c, s, nd)) continue;
+    T a[6];
+    rb_couplings<T, VARC>(g, k, nd, a);
+    const auto *other = msg + (size_t)(1 - c) * 6 * Nc;
+    const size_t own = (size_t)c * 6 * Nc;
+    T Pin[6];
+    T S = VARC ? k.diag[nd.i] : k.dconst;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      Pin[d] = a[d] != T(0) ? other[(size_t)(d ^ 1) * Nc + nd.j[d]].x : T(0);
+      S += Pin[d];
+    }
+    Sfix[(size_t)c * Nc + s] = S;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      const size_t o = own + (size_t)d * Nc + s;
+      coef[o] = a[d] != T(0) ? -a[d] / (S - Pin[d]) : T(0);
+      hh[o] = a[d] != T(0) ? msg[o].y : T(0);
+    }
+  }
+}
+
+// natural direction-major FP64 [6][N] <-> colour-major working precision
+template <typename T, bool GET>
+__global__ void k_rb_io(GridGeom g, int hx, int Nc, typename Vec2<T>::type *__restrict__ msg,
+                        double *__restrict__ P, double *__restrict__ h) {
+  const int64_t m = 6 * (int64_t)g.N;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  const int d = (int)(t / g.N);
+  const int i = (int)(t - (int64_t)d * g.N);
+  int c, slot;
+  rb_place(g, hx, i, c, slot);
+  const size_t at = ((size_t)c * 6 + d) * Nc + slot;
+  if (GET) {
+    P[t] = (double)msg[at].x;
+    h[t] = (double)msg[at].y;
+  } else {
+    msg[at].x = (T)P[t];
+    msg[at].y = (T)h[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T, int MODE, bool DAMP, bool VARC>
+void rb_one(const RbArgs &a, hipStream_t s) {
+  using V = typename Vec2<T>::type;
+  GridCoef<T> k;
+  k.diag = (const T *)a.diag; k.cx = (const T *)a.cx; k.cy = (const T *)a.cy; k.cz = (const T *)a.cz;
+  k.dconst = (T)a.dconst; k.aconst = (T)a.aconst;
+  if (a.frozen)
+    hipLaunchKernelGGL((k_rb_frozen<T, MODE, DAMP>), dim3(a.grid), dim3(kBlock), 0, s, a.g, a.hx,
+                       a.Nc, a.colour, (const T *)a.coef, (const T *)a.Sfix, (T *)a.msg,
+                       (const T *)a.rhs, (T)a.alpha, (T *)a.xprev, a.xacc, a.marg, a.part,
+                       a.sticky, a.ctl);
+  else
+    hipLaunchKernelGGL((k_rb_sweep<T, MODE, DAMP, VARC>), dim3(a.grid), dim3(kBlock), 0, s, a.g,
+                       a.hx, a.Nc, a.colour, k, (V *)a.msg, (const T *)a.rhs, (T)a.alpha,
+                       (T *)a.xprev, a.xacc, a.marg, a.part, a.sticky, a.ctl);
+}
+
+template <typename T, bool VARC>
+void rb_mode(const RbArgs &a, hipStream_t s) {
+  switch (a.mode) {
+    case 0: a.damp ? rb_one<T, 0, true, VARC>(a, s) : rb_one<T, 0, false, VARC>(a, s); break;
+    case 1: a.damp ? rb_one<T, 1, true, VARC>(a, s) : rb_one<T, 1, false, VARC>(a, s); break;
+    default: rb_one<T, 2, false, VARC>(a, s); break;
+  }
+}
+
+template <typename T, bool VARC>
+void rb_freeze(const RbArgs &a, void *hh, hipStream_t s) {
+  GridCoef<T> k{(const T *)a.diag, (const T *)a.cx, (const T *)a.cy, (const T *)a.cz,
+                (T)a.dconst, (T)a.aconst};
+  hipLaunchKernelGGL((k_rb_freeze<T, VARC>), dim3(a.grid), dim3(kBlock), 0, s, a.g, a.hx, a.Nc, k,
+                     (const typename Vec2<T>::type *)a.msg, (T *)a.coef, (T *)hh, (T *)a.Sfix);
+}
+
+}  // namespace
+
+hipError_t launch_rb_sweep(const RbArgs &a, hipStream_t s) {
+  if (a.Nc <= 0) return hipSuccess;
+  if (a.fp32) a.varc ? rb_mode<float, true>(a, s) : rb_mode<float, false>(a, s);
+  else a.varc ? rb_mode<double, true>(a, s) : rb_mode<double, false>(a, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_rb_freeze(const RbArgs &a, void *hh, hipStream_t s) {
+  if (a.Nc <= 0) return hipSuccess;
+  if (a.fp32) a.varc ? rb_freeze<float, true>(a, hh, s) : rb_freeze<float, false>(a, hh, s);
+  else a.varc ? rb_freeze<double, true>(a, hh, s) : rb_freeze<double, false>(a, hh, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_rb_io(bool fp32, bool get, const GridGeom &g, int hx, int Nc, void *msg,
+                        double *P, double *h, hipStream_t s) {
+  const int64_t m = 6 * (int64_t)g.N;
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((m + kBlock - 1) / kBlock));
+  if (fp32) {
+    if (get) hipLaunchKernelGGL((k_rb_io<float, true>), grid, dim3(kBlock), 0, s, g, hx, Nc, (float2 *)msg, P, h);
+    else hipLaunchKernelGGL((k_rb_io<float, false>), grid, dim3(kBlock), 0, s, g, hx, Nc, (float2 *)msg, P, h);
+  } else {
+    if (get) hipLaunchKernelGGL((k_rb_io<double, true>), grid, dim3(kBlock), 0, s, g, hx, Nc, (double2 *)msg, P, h);
+    else hipLaunchKernelGGL((k_rb_io<double, false>), grid, dim3(kBlock), 0, s, g, hx, Nc, (double2 *)msg, P, h);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gabp

@@ -399,22 +399,34 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_grid_warm(GridGeom g, GridCoef<T> k,
                                                         const T *__restrict__ rhs,
                                                         const uint16_t *__restrict__ w,
-                                                        typename Vec2<T>::type *__restrict__ msg) {
+                                                        typename Vec2<T>::type *__restrict__ msg,
+                                                        int hx) {
   using T2 = typename Vec2<T>::type;
   __shared__ float sp[kParams];
   stage_params(w, sp);
   const int64_t N = g.N;
+  // natural order: node i, direction d at d N + i; two-colour order (hx > 0):
+  // rhs at c Nc + slot, direction d at (6 c + d) Nc + slot
+  const int64_t Nc = hx > 0 ? (int64_t)hx * (N / g.nx) : 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t at = i, bat = i, stride = N;
+    if (hx > 0) {
+      int c, slot;
+      rb_place(g, hx, (int)i, c, slot);
+      at = 6 * c * Nc + slot;
+      bat = c * Nc + slot;
+      stride = Nc;
+    }
     T diag, a[6];
     node_couplings(g, k, grid_node(g, i), diag, a);
     float u[kIn], o[kOut];
-    node_features(diag, a, rhs[i], u);
+    node_features(diag, a, rhs[bat], u);
     forward<false>(sp, u, o, nullptr, nullptr, 0, 0);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
       const bool on = a[d] != T(0);
-      msg[d * N + i] = on ? T2{(T)o[2 * d] * diag, (T)o[2 * d + 1] * diag} : T2{T(0), T(0)};
+      msg[d * stride + at] = on ? T2{(T)o[2 * d] * diag, (T)o[2 * d + 1] * diag} : T2{T(0), T(0)};
     }
   }
 }
@@ -485,19 +497,19 @@ hipError_t launch_grid_targets(const GridGeom &g, const GridCoef<double> &k, con
 
 hipError_t launch_grid_warm(bool fp32, const GridGeom &g, const void *diag, const void *cx,
                             const void *cy, const void *cz, double dconst, double aconst,
-                            const void *rhs, const uint16_t *w, void *msg, hipStream_t s) {
+                            const void *rhs, const uint16_t *w, void *msg, hipStream_t s, int hx) {
   if (g.N <= 0) return hipSuccess;
   const dim3 grid(blocks_for(g.N, 2048));
   if (fp32) {
     GridCoef<float> k{(const float *)diag, (const float *)cx, (const float *)cy, (const float *)cz,
                       (float)dconst, (float)aconst};
     hipLaunchKernelGGL(k_grid_warm<float>, grid, dim3(kThreads), 0, s, g, k, (const float *)rhs, w,
-                       (float2 *)msg);
+                       (float2 *)msg, hx);
   } else {
     GridCoef<double> k{(const double *)diag, (const double *)cx, (const double *)cy,
                        (const double *)cz, dconst, aconst};
     hipLaunchKernelGGL(k_grid_warm<double>, grid, dim3(kThreads), 0, s, g, k, (const double *)rhs,
-                       w, (double2 *)msg);
+                       w, (double2 *)msg, hx);
   }
   return hipGetLastError();
 }
