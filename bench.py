@@ -343,7 +343,8 @@ def bench_c4(args, G, W, torch, dev):
         torch.cuda.synchronize()
         res[kind] = (time.perf_counter() - t0, runs)
     G.gabp_plan_destroy(plan)
-    # each grid's own FP64 residual (the stop rule is the stack's), outside the timing
+    # each grid's own FP64 residual, recomputed one grid at a time outside the timing
+    # (the library's stop rule already requires every grid to meet the tolerance)
     nn = n ** 3
     worst_grid = 0.0
     for t in range(count):
@@ -378,8 +379,8 @@ def bench_c4(args, G, W, torch, dev):
             "sweeps_plain": sweeps / args.steps,
             "sweeps_warm": sum(st.sweeps for st in wruns) / args.steps,
             "warm_start_status": wruns[-1].warm_start,
-            "rel_residual_stack": runs[-1].rel_residual,
-            "rel_residual_worst_grid_after_warm": worst_grid,
+            "rel_residual_worst_grid_plain": runs[-1].rel_residual,
+            "rel_residual_worst_grid_warm": worst_grid,
             "warm_speedup": dt / wdt,
             "warm_model": {k: meta[k] for k in ("grids", "samples", "steps", "final_loss")},
         },

@@ -69,7 +69,9 @@ typedef struct {
   int32_t msg_fp32;    /* 1: messages and node sums in FP32, with the residual
                           b - A x and the correction restarts in FP64;
                           0: everything in FP64 */
-  double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol (FP64) */
+  double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol (FP64); for a
+                          stack of grids (batch > 1) every grid's own
+                          ||b_t - A_t x_t|| / ||b_t|| must meet it */
   int32_t max_sweeps;  /* budget of synchronous sweeps over all restarts */
   int32_t check_every; /* sweeps between checks of the marginal means */
   double damping;      /* alpha in [0,1): P <- alpha P_old + (1-alpha) P_new
@@ -129,7 +131,8 @@ typedef struct {
   int32_t frozen_sweeps;   /* of which with settled (fixed) precisions */
   int32_t restarts;        /* refinement restarts taken */
   int32_t checks;          /* mean checks read back by the host */
-  double rel_residual;     /* final ||b - A x||_2 / ||b||_2, FP64 */
+  double rel_residual;     /* final ||b - A x||_2 / ||b||_2, FP64 (a grid stack:
+                              the largest over its grids) */
   double residual_per_eq;  /* ||b - A x||_2 / n (section II-A norm) */
   double seconds;          /* host wall time of the solve */
   double sweep_ms;         /* summed device time of the sweep launches */

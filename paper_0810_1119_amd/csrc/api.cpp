@@ -34,7 +34,7 @@ void report_hip(hipError_t e, const char *file, int line) {
 }
 
 Engine::~Engine() {
-  void *bufs[] = {part, sumpart, sticky, ctl, xprev};
+  void *bufs[] = {part, sumpart, sticky, ctl, xprev, segb2};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (host) (void)hipHostFree(host);
@@ -55,6 +55,7 @@ int Engine::init_common(hipStream_t s) {
       (st = from_hip(dalloc(&ctl, 1, sizeof(Ctl)))) ||
       (st = from_hip(dalloc(&xprev, means_slots(), tsz))))
     return st;
+  if (nseg > 1 && (st = from_hip(dalloc(&segb2, nseg, sizeof(double))))) return st;
   if ((st = from_hip(hipHostMalloc((void **)&host, kRing * sizeof(HostReadout), hipHostMallocDefault))))
     return st;
   for (int k = 0; k < kRing; ++k) {
@@ -73,9 +74,11 @@ int Engine::init_common(hipStream_t s) {
   return GABP_OK;
 }
 
-int Engine::read_sum(hipStream_t s, HostReadout *outv) {
+int Engine::read_sum(hipStream_t s, HostReadout *outv, int seg_mode, double bnorm) {
   const int slot = 0;
   TRY_HIP(launch_readout(nullptr, 0, sumpart, nsum, sticky, ctl, 0, ++seq, &host[slot], s));
+  if (nseg > 1 && seg_mode > 0)
+    TRY_HIP(launch_seg_norms(sumpart, nseg, segb, segb2, seg_mode == 1, bnorm, &host[slot], s));
   TRY_HIP(hipEventRecord(ev_done[slot], s));
   TRY_HIP(hipEventSynchronize(ev_done[slot]));
   *outv = host[slot];
@@ -125,7 +128,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   TRY_HIP(launch_fill_zero(x, p->n, s));
   TRY_HIP(launch_ctl_reset(p->ctl, target_for(1.0), floor, freeze_tol, true, 0, s));
   HostReadout r0;
-  int rc = p->read_sum(s, &r0);
+  int rc = p->read_sum(s, &r0, 1);
   if (rc) return finish(rc);
   if (!std::isfinite(r0.sum)) return finish(GABP_ERR_ARG);
   const double bn = std::sqrt(r0.sum);
@@ -220,8 +223,11 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
     TRY_HIP(p->infer(x, nullptr, nullptr, s));
     TRY_HIP(p->residual(b, x, nullptr, s));
     HostReadout rr;
-    if ((rc = p->read_sum(s, &rr))) return finish(rc);
-    const double rel = std::sqrt(rr.sum) / bn;
+    if ((rc = p->read_sum(s, &rr, 2, bn))) return finish(rc);
+    // independent systems: the worst one decides (the whole-system norm still
+    // catches non-finite values)
+    const double rel_all = std::sqrt(rr.sum) / bn;
+    const double rel = (p->nseg > 1 && std::isfinite(rel_all)) ? rr.segrel : rel_all;
     if (std::getenv("GABP_VERBOSE"))
       std::fprintf(stderr, "gabp: pass %d: %d sweeps (%d settled), rel. residual %.3e\n", pass,
                    sweeps_done, stats.frozen_sweeps, rel);

@@ -60,6 +60,11 @@ struct Engine {
   uint32_t *sticky = nullptr;
   Ctl *ctl = nullptr;
   void *xprev = nullptr;
+  // independent systems in one plan (a stack of grids): the residual
+  // partials come in nseg runs of segb, and a solve stops when every
+  // segment's relative residual meets the tolerance
+  int nseg = 1, segb = 0;
+  double *segb2 = nullptr;  // ||b_t||^2 per segment
   HostReadout *host = nullptr;
   hipEvent_t ev_beg[kRing] = {}, ev_end[kRing] = {}, ev_done[kRing] = {};
   bool events = false;
@@ -96,8 +101,10 @@ struct Engine {
   virtual int get_messages(double *P, double *h, hipStream_t s) = 0;
   virtual int set_messages(const double *P, const double *h, hipStream_t s) = 0;
 
-  // readout of the residual partials only; waits for it
-  int read_sum(hipStream_t s, HostReadout *outv);
+  // readout of the residual partials only; waits for it.  seg_mode (nseg > 1):
+  // 1 keeps the per-segment squared norms as ||b_t||^2, 2 reports the largest
+  // per-segment relative residual in outv->segrel (bnorm = ||b||)
+  int read_sum(hipStream_t s, HostReadout *outv, int seg_mode = 0, double bnorm = 0.0);
 };
 
 // refinement loop around chunked sweeps (api.cpp)

@@ -120,11 +120,11 @@ struct GridEngine : Engine {
     hipError_t err;
     if ((err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
     if ((err = launch_fill_zero(msg[1], words, s)) != hipSuccess) return err;
-    return launch_grid_residual(g, k64, varc, nsum, b, nullptr, rhs, fp32, nullptr, sumpart, s);
+    return launch_grid_residual(g, k64, varc, nsum, b, nullptr, rhs, fp32, nullptr, sumpart, s, 0, nseg);
   }
 
   hipError_t residual(const double *b, const double *x, double *r64, hipStream_t s) override {
-    return launch_grid_residual(g, k64, varc, nsum, b, x, rhs, fp32, r64, sumpart, s);
+    return launch_grid_residual(g, k64, varc, nsum, b, x, rhs, fp32, r64, sumpart, s, 0, nseg);
   }
 
   bool has_warm_start() const override { return true; }
@@ -257,11 +257,11 @@ struct RbGridEngine : GridEngine {
     frozen = false;
     hipError_t err = launch_fill_zero(msg[0], rb_slots() * (int64_t)(2 * tsz) / 8, s);
     if (err != hipSuccess) return err;
-    return launch_grid_residual(g, k64, varc, nsum, b, nullptr, rhs, fp32, nullptr, sumpart, s, hx);
+    return launch_grid_residual(g, k64, varc, nsum, b, nullptr, rhs, fp32, nullptr, sumpart, s, hx, nseg);
   }
 
   hipError_t residual(const double *b, const double *x, double *r64, hipStream_t s) override {
-    return launch_grid_residual(g, k64, varc, nsum, b, x, rhs, fp32, r64, sumpart, s, hx);
+    return launch_grid_residual(g, k64, varc, nsum, b, x, rhs, fp32, r64, sumpart, s, hx, nseg);
   }
 
   hipError_t warm_start(const uint16_t *w, hipStream_t s) override {
@@ -343,6 +343,14 @@ int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **pl
   e->grid = need < cap ? need : cap;
   e->nparts = e->grid;
   e->nsum = e->grid;
+  if (g.batch > 1) {
+    // the grids of a stack are independent systems: each must meet the tolerance
+    const int per = (g.N / g.batch + kBlock - 1) / kBlock;
+    const int share = std::max(1, kMaxSweepBlocks / g.batch);
+    e->nseg = g.batch;
+    e->segb = std::min(per, share);
+    e->nsum = e->nseg * e->segb;
+  }
   if (rb) {
     rb->hx = rb_row_slots(g);
     rb->Nc = rb->hx * (g.N / g.nx);

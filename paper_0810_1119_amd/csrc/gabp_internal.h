@@ -74,6 +74,7 @@ struct HostReadout {
   int32_t seq;         // chunk sequence number (sanity check)
   int32_t freeze;      // precision messages settled
   int32_t pad;
+  double segrel;       // largest relative residual of a segment (independent systems)
 };
 
 template <typename T> struct Vec2;
@@ -211,10 +212,19 @@ struct GridArgs {
 hipError_t launch_grid_sweep(const GridArgs &a, hipStream_t s);
 hipError_t launch_grid_freeze(const GridArgs &a, hipStream_t s);
 // rT (the working-precision right-hand side) in natural order when hx == 0,
-// else in the two-colour order of a red-black plan with hx slots per row
+// else in the two-colour order of a red-black plan with hx slots per row.
+// With nseg > 1 the stack is cut into nseg equal segments (its grids) and
+// block k covers segment k / (grid / nseg) only, so the partials of a grid are
+// contiguous (grid must be a multiple of nseg).
 hipError_t launch_grid_residual(const GridGeom &g, const GridCoef<double> &k, bool varc, int grid,
                                 const double *b, const double *x, void *rT, bool rT32, double *r64,
-                                double *sumpart, hipStream_t s, int hx = 0);
+                                double *sumpart, hipStream_t s, int hx = 0, int nseg = 1);
+// Per-segment norms from residual partials (segb consecutive partials per
+// segment): store != 0 keeps the squared norms in segb2 (||b_t||^2);
+// otherwise host->segrel = max_t ||r_t|| / ||b_t|| (||b|| of the whole system
+// where ||b_t|| = 0, given as bnorm).
+hipError_t launch_seg_norms(const double *sumpart, int nseg, int segb, double *segb2, int store,
+                            double bnorm, HostReadout *host, hipStream_t s);
 
 // ---- two-colour (red-black) schedule on grids (kernels_grid_rb.hip) ----
 // Node (x, y, z) of a stack (z counted over the whole stack) has colour

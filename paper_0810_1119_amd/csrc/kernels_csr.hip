@@ -514,6 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_readout(
   host->stop = ctl ? ctl->stop : 0u;
   host->sweeps = ctl ? ctl->sweeps : 0;
   host->freeze = ctl ? ctl->freeze : 0;
+  host->segrel = -1.0;  // set by the per-segment norms when a plan has segments
   host->seq = seq;
   __threadfence_system();
 }

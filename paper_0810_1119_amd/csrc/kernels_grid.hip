@@ -239,11 +239,17 @@ __global__ __launch_bounds__(kBlock) void k_grid_freeze(
 template <bool VARC>
 __global__ __launch_bounds__(kBlock) void k_grid_residual(
     GridGeom g, GridCoef<double> k, const double *__restrict__ b, const double *__restrict__ x,
-    void *__restrict__ rT, bool rT32, double *__restrict__ r64, double *__restrict__ sumpart, int hx) {
+    void *__restrict__ rT, bool rT32, double *__restrict__ r64, double *__restrict__ sumpart, int hx,
+    int nseg) {
   const int N = g.N;
   const int Nc = hx * (N / g.nx);
+  const int segb = gridDim.x / nseg;          // blocks per segment
+  const int seg = blockIdx.x / segb;
+  const int len = N / nseg;
+  const int hi = (seg + 1) * len;
   double sq = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+  for (int i = seg * len + (blockIdx.x - seg * segb) * kBlock + threadIdx.x; i < hi;
+       i += segb * kBlock) {
     double ri = b[i];
     if (x != nullptr) {
       Nbr nb;
@@ -386,12 +392,48 @@ hipError_t launch_grid_freeze(const GridArgs &a, hipStream_t s) {
 
 hipError_t launch_grid_residual(const GridGeom &g, const GridCoef<double> &k, bool varc, int grid,
                                 const double *b, const double *x, void *rT, bool rT32, double *r64,
-                                double *sumpart, hipStream_t s, int hx) {
+                                double *sumpart, hipStream_t s, int hx, int nseg) {
   if (g.N <= 0) return hipSuccess;
+  if (nseg < 1 || grid % nseg != 0 || g.N % nseg != 0) return hipErrorInvalidValue;
   if (varc)
-    hipLaunchKernelGGL((k_grid_residual<true>), dim3(grid), dim3(kBlock), 0, s, g, k, b, x, rT, rT32, r64, sumpart, hx);
+    hipLaunchKernelGGL((k_grid_residual<true>), dim3(grid), dim3(kBlock), 0, s, g, k, b, x, rT, rT32, r64, sumpart, hx, nseg);
   else
-    hipLaunchKernelGGL((k_grid_residual<false>), dim3(grid), dim3(kBlock), 0, s, g, k, b, x, rT, rT32, r64, sumpart, hx);
+    hipLaunchKernelGGL((k_grid_residual<false>), dim3(grid), dim3(kBlock), 0, s, g, k, b, x, rT, rT32, r64, sumpart, hx, nseg);
+  return hipGetLastError();
+}
+
+// one thread per segment: sums its partials in a fixed order
+__global__ __launch_bounds__(kBlock) void k_seg_norms(const double *__restrict__ sumpart, int nseg,
+                                                      int segb, double *__restrict__ segb2, int store,
+                                                      double bnorm, HostReadout *__restrict__ host) {
+  __shared__ double sh[kBlock / 64];
+  double worst = 0.0;
+  for (int t = threadIdx.x; t < nseg; t += kBlock) {
+    double sq = 0.0;
+    for (int k = 0; k < segb; ++k) sq += sumpart[(size_t)t * segb + k];
+    if (store) {
+      segb2[t] = sq;
+    } else {
+      const double bn = segb2[t] > 0.0 ? sqrt(segb2[t]) : bnorm;
+      const double rel = bn > 0.0 ? sqrt(sq) / bn : sqrt(sq);
+      worst = fmax(worst, rel);  // non-finite sums are caught by the whole-system norm
+    }
+  }
+  if (store) return;
+  worst = wave_max(worst);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x / 64] = worst;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) worst = fmax(worst, sh[w]);
+    host->segrel = worst;
+    __threadfence_system();
+  }
+}
+
+hipError_t launch_seg_norms(const double *sumpart, int nseg, int segb, double *segb2, int store,
+                            double bnorm, HostReadout *host, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_norms, dim3(1), dim3(kBlock), 0, s, sumpart, nseg, segb, segb2, store,
+                     bnorm, host);
   return hipGetLastError();
 }
 

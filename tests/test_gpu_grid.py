@@ -236,3 +236,30 @@ def test_c5_full_size_256cubed(G):
     assert rc == G.GABP_OK, G.status_name(rc)
     rel = _grid_rel(nx, ny, nz, 1, coef, b, x)
     assert rel <= 1e-8 and st.rel_residual == pytest.approx(rel, rel=1e-6)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_stack_every_grid_meets_the_tolerance(G, schedule):
+    """The grids of a stack are independent systems: the solve stops only when
+    each one's own relative residual is at most tol, also when their
+    right-hand sides differ by orders of magnitude; a grid with b_t = 0 gets
+    x_t = 0."""
+    nx, ny, nz, bt = 12, 11, 10, 4
+    _, coef = W.grid_stack(nx, ny, nz, bt, varcoef=True, seed=9, with_csr=False)
+    n1 = nx * ny * nz
+    b = W.normal_b(n1 * bt, 4)
+    b[n1:2 * n1] *= 1e-6
+    b[2 * n1:3 * n1] = 0.0
+    rc, st, x = _solve(G, nx, ny, nz, bt, coef, b, tol=1e-8, schedule=schedule)
+    assert rc == G.GABP_OK, G.status_name(rc)
+    rels = []
+    for t in range(bt):
+        sl = slice(t * n1, (t + 1) * n1)
+        c1 = {k: (coef[k][sl] if coef[k] is not None else None) for k in ("diag", "cx", "cy", "cz")}
+        c1.update(dval=coef["dval"], off=coef["off"])
+        if t == 2:
+            assert np.all(x[sl] == 0.0)
+            continue
+        rels.append(_grid_rel(nx, ny, nz, 1, c1, b[sl], x[sl]))
+    assert max(rels) <= 1e-8, rels
+    assert st.rel_residual == pytest.approx(max(rels), rel=1e-6)
