@@ -44,10 +44,10 @@ def parse():
                     help="settled-precision threshold (0 = library default)")
     ap.add_argument("--grid", type=int, default=0, help="sweep grid cap (0 = library default)")
     ap.add_argument("--schedule", choices=["sync", "colored"], default=None,
-                    help="grid workloads: message schedule; default colored for c4 (undamped: "
-                         "half the sweeps) and sync for c5 (with damping 0.5 the coloured "
-                         "schedule saves only a quarter of the sweeps and loses the cache reuse "
-                         "of the damping reads); c2 and c3 have the synchronous schedule only")
+                    help="message schedule of the two-colourable workloads; default colored "
+                         "for c3 and c4 (undamped: half the sweeps) and sync for c5 (with "
+                         "damping 0.5 the coloured schedule saves only a quarter of the sweeps "
+                         "and loses the cache reuse of the damping reads); c2 is synchronous")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte "
                          "counters) and print its bandwidth")
@@ -210,17 +210,28 @@ def run_c2(args, G, W, torch, dev):
                 kfrozen="k_pair_frozen<float,G,*>" if pair else None)
 
 
-def dense_batch_bytes(rows, cols, per, fp32=True):
-    """Algorithmic bytes of a batched solve: per matrix entry (one undirected
-    edge, both messages) a full sweep reads the message pair (16) and the
-    FP32 coupling (4) and writes the pair (16); a settled sweep reads the
-    coefficient pair (8) and the information pair (8) and writes the latter
-    (8); every FP64 residual reads the entry twice (S x and S^T u, 16)."""
+def dense_batch_bytes(rows, cols, per, colored=False, check_every=2):
+    """Algorithmic bytes of a batched solve per matrix entry (one undirected
+    edge, both messages).  Synchronous: a full sweep reads the message pair
+    (16) and the FP32 coupling (4) and writes the pair (16); a settled sweep
+    reads the coefficient pair (8) and the information pair (8) and writes the
+    latter (8).  Coloured (two halves, each sending one direction): a full
+    sweep reads per half the received message (8) and the coupling (4) and
+    writes the sent one (8), plus the sent one's previous value (8) on check
+    sweeps and in damped instances; a settled sweep reads per half the
+    coefficient (4) and the received information (4) and writes the sent one
+    (4), plus its previous value (4) when damped.  Every FP64 residual reads
+    the entry twice (S x and S^T u, 16)."""
     pairs = np.asarray(rows, dtype=np.float64) * np.asarray(cols, dtype=np.float64)
     sweeps = np.array([p.sweeps for p in per], dtype=np.float64)
     frozen = np.array([p.frozen_sweeps for p in per], dtype=np.float64)
     resid = np.array([p.restarts + 2 for p in per], dtype=np.float64)
     full = sweeps - frozen
+    if colored:
+        damped = np.array([p.damping > 0 for p in per], dtype=np.float64)
+        per_full = 40.0 + 16.0 * (damped + (1.0 - damped) / check_every)
+        per_frozen = 24.0 + 8.0 * damped
+        return float(np.sum(pairs * (per_full * full + per_frozen * frozen + 16.0 * resid)))
     return float(np.sum(pairs * (36.0 * full + 24.0 * frozen + 16.0 * resid)))
 
 
@@ -235,6 +246,9 @@ def bench_c3(args, G, W, torch, dev):
         opts.check_every = args.check_every
     opts.freeze = args.freeze
     opts.grid_blocks = args.grid
+    colored = (args.schedule or "colored") == "colored"
+    opts.schedule = G.GABP_SCHEDULE_COLORED if colored else G.GABP_SCHEDULE_SYNC
+    ce = max(2, opts.check_every + (opts.check_every & 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc, plan = G.gabp_plan_create_batched(B, opts)
@@ -263,7 +277,7 @@ def bench_c3(args, G, W, torch, dev):
         work += float(np.sum(np.array([p.edges for p in per], dtype=np.float64) *
                              np.array([p.sweeps for p in per], dtype=np.float64)))
         kms += summ.sweep_ms
-        algo += dense_batch_bytes(db.N, db.K, per)
+        algo += dense_batch_bytes(db.N, db.K, per, colored, ce)
         sweeps_max = max(sweeps_max, summ.sweeps)
         sweeps_sum += sum(p.sweeps for p in per)
         damped += sum(1 for p in per if p.damping > 0)
@@ -282,7 +296,8 @@ def bench_c3(args, G, W, torch, dev):
             "workload": "batched linear detection (section VII bipartite GaBP): 4096 instances, "
                         "K ~ U{16..256} users, N = 2K chips, S = +-1/sqrt(N), x in {+-1}^K, "
                         "SNR 10 dB (sigma2 = 0.1); (S^T S + sigma2 I) x = S^T y per instance, "
-                        "FP32 messages + FP64 refinement to 1e-8, one persistent launch",
+                        "FP32 messages + FP64 refinement to 1e-8, one persistent launch; "
+                        f"{'two-colour (chips, then users)' if colored else 'synchronous'} schedule",
             "instances": 4096, "directed_edges": int(np.sum(2 * db.K * db.N)), "seed": args.seed,
             "time_to_1e-8_ms": dt * 1e3 / args.steps,
             "sweeps_mean": sweeps_sum / args.steps / 4096, "sweeps_max": sweeps_max,
@@ -292,8 +307,11 @@ def bench_c3(args, G, W, torch, dev):
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("gabp::(anonymous namespace)::k_dense_batch<float, 4, 0>", "c3"),
-            "kernel": "k_dense_batch<float,4,bipartite> (persistent: A1-A4 for every instance)",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic("gabp::(anonymous namespace)::k_dense_batch<float, 4, 0, "
+                                        f"{'true' if colored else 'false'}>", "c3"),
+            "kernel": f"k_dense_batch<float,4,bipartite,{'coloured' if colored else 'sync'}> "
+                      "(persistent: every sweep, check and refinement of every instance)",
             "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": algo / args.steps,
             "launches_timed": args.steps,
         },
@@ -455,8 +473,9 @@ def main():
               "(a single graph would shard by node partition with one halo exchange "
               "per sweep; see the design notes)", file=sys.stderr)
         sys.exit(2)
-    if args.schedule == "colored" and args.workload in ("c2", "c3"):
-        print("the coloured schedule is implemented for grid plans only (c4, c5)", file=sys.stderr)
+    if args.schedule == "colored" and args.workload == "c2":
+        print("the random graph of c2 is not two-colourable: synchronous schedule only",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 

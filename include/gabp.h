@@ -113,13 +113,14 @@ typedef struct {
                           0.5, then 0.7 (damping as in section VI-D); 0 = never */
   int32_t schedule;     /* GABP_SCHEDULE_SYNC (default): every message of a sweep
                           from the previous sweep's messages (the parallel
-                          scheme of section III-C); GABP_SCHEDULE_COLORED: grid
-                          plans only, the serial scheme of section III-C in
-                          checkerboard order: one sweep lets every node of
-                          colour 0 ((x + y + z) even, z counted over the whole
-                          stack) send from the newest messages, then every node
-                          of colour 1.  Other plans return
-                          GABP_ERR_UNSUPPORTED */
+                          scheme of section III-C); GABP_SCHEDULE_COLORED: the
+                          serial scheme of section III-C in the order of a
+                          two-colouring, for grid plans (checkerboard: one sweep
+                          lets every node of colour 0, (x + y + z) even with z
+                          counted over the whole stack, send from the newest
+                          messages, then every node of colour 1) and bipartite
+                          batches (chips send, then users).  Other plans
+                          return GABP_ERR_UNSUPPORTED */
 } gabp_opts;
 
 enum { GABP_LAYOUT_PAIR = 0, GABP_LAYOUT_GATHER = 1 };

@@ -62,6 +62,7 @@ struct BatchEngine {
     a.state = state;
     a.fcoef = fcoef;
     a.fh = fh;
+    a.colored = o.schedule == GABP_SCHEDULE_COLORED;
     a.tot = tot;
     a.nb = nb;
     a.stat = dstat;
@@ -121,7 +122,8 @@ std::map<std::tuple<int, int, int, int, int, int64_t>, int> tune_cache;
 
 int autotune(BatchEngine *e, hipStream_t s) {
   const int64_t bucket = e->entries > 0 ? (int64_t)std::log2((double)e->entries) : 0;
-  const auto key = std::make_tuple(e->kind, (int)e->fp32, e->nr, e->nc, e->count, bucket);
+  const auto key = std::make_tuple(e->kind * 2 + (e->o.schedule == GABP_SCHEDULE_COLORED ? 1 : 0),
+                                   (int)e->fp32, e->nr, e->nc, e->count, bucket);
   {
     std::lock_guard<std::mutex> g(tune_mu);
     auto it = tune_cache.find(key);
@@ -192,7 +194,9 @@ int batch_create(const gabp_batch *B, const gabp_opts *o, BatchEngine **out, hip
   int st = check_batch(B);
   if (st) return st;
   if (o && (st = check_opts(o))) return st;
-  if (o && o->schedule != GABP_SCHEDULE_SYNC) return GABP_ERR_UNSUPPORTED;
+  // the two-colour schedule needs a two-colourable graph: the bipartite kind
+  if (o && o->schedule != GABP_SCHEDULE_SYNC && B->kind != GABP_BATCH_BIPARTITE)
+    return GABP_ERR_UNSUPPORTED;
   if (o && o->batch_waves != 0 && o->batch_waves != 4 && o->batch_waves != 8 &&
       o->batch_waves != 16)
     return GABP_ERR_ARG;

@@ -317,8 +317,11 @@ struct DenseArgs {
   const void *matT;      // couplings in the message precision
   const double *b;
   double *x;
-  void *state;           // (P_rc, h_rc, P_cr, h_cr) per entry
-  void *fcoef, *fh;      // settled phase: (c_rc, c_cr) and (h_rc, h_cr) per entry
+  void *state;           // (P_rc, h_rc, P_cr, h_cr) per entry; coloured: per
+                         // instance all (P_rc, h_rc), then all (P_cr, h_cr)
+  void *fcoef, *fh;      // settled phase: (c_rc, c_cr) and (h_rc, h_cr) per entry;
+                         // coloured: all c_rc then all c_cr, the same for h
+  bool colored;          // bipartite: two-colour schedule (rows send, then columns)
   void *tot, *nb;        // per node: (S, H) totals and right-hand side
   DenseStat *stat;
   double tol, alpha, inner_tol, freeze_tol, floor;

@@ -268,6 +268,199 @@ __device__ void sweep(const Inst<T> &in, const Lds<T> &L, bool fresh, bool zero_
   __syncthreads();
 }
 
+// One half of a coloured sweep of a bipartite instance (all threads call).
+// Rows (chips) and columns (users) are the two colour classes of the
+// section VII graph: PH 1 lets every row send, PH 2 every column, each from
+// the newest messages of the other class, so one sweep (PH 1 then PH 2) is
+// the serial scheme of section III-C in this order.  Storage of an instance
+// with entry e = r C + c in the coloured layout:
+//   full state:  rc[e] = (P_rc, h_rc), then cr[e] = (P_cr, h_cr)  (T2 arrays)
+//   settled:     k_rc[e], then k_cr[e] (coefficients); h_rc[e], then h_cr[e]
+// PH 1 rebuilds the column totals from the new row -> column messages and
+// PH 2 the row totals from the new column -> row messages.  want_dp: track
+// the largest precision change (a check sweep).
+template <typename T, int MAXM, int SK, int PH>
+__device__ void sweep_rb(const Inst<T> &in, const Lds<T> &L, bool fresh, bool zero_h, bool damp,
+                         bool want_dp, T alpha, T &dp, T &pm, bool &brk, int W) {
+  using T2 = typename Vec2<T>::type;
+  const int lane = thread_id() & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int R = in.R, C = in.C;
+  const size_t RC = (size_t)R * (size_t)C;
+  T2 *own2 = nullptr, *rev2 = nullptr;  // full state: the sent and the received direction
+  T *kown = nullptr, *hown = nullptr, *hrev = nullptr;
+  if constexpr (SK == SK_FULL || SK == SK_FREEZE) {
+    T2 *const rc = (T2 *)in.st;
+    own2 = PH == 1 ? rc : rc + RC;
+    rev2 = PH == 1 ? rc + RC : rc;
+  }
+  if constexpr (SK != SK_FULL) {
+    T *const k = (T *)in.fc;
+    T *const h = (T *)in.fh;
+    kown = PH == 1 ? k : k + RC;
+    hown = PH == 1 ? h : h + RC;
+    hrev = PH == 1 ? h + RC : h;
+  }
+  T cS[MAXM], cH[MAXM], aP[MAXM], aH[MAXM];
+#pragma unroll
+  for (int m = 0; m < MAXM; ++m) {
+    const int c = lane + 64 * m;
+    cS[m] = T(0);
+    cH[m] = T(0);
+    if (PH == 2 && c < C) {
+      const T2 v = L.tot_col[c];
+      cS[m] = v.x;
+      cH[m] = v.y;
+    }
+    aP[m] = T(0);
+    aH[m] = T(0);
+  }
+  const T beta = T(1) - alpha;
+  const bool read_old = damp || (SK == SK_FULL && want_dp);
+  // Two rows per wavefront and iteration, with the loads of both in flight
+  // together: a half sweep moves half the bytes per entry of a synchronous
+  // sweep, and one row at a time would leave the memory pipeline half idle.
+  // Wavefront w still visits rows w, w + W, w + 2W, ... in that order, so
+  // every sum keeps its order.  Wide rows hold enough loads in flight alone
+  // (and two of them would not fit the registers).
+  constexpr int NR = MAXM * (int)sizeof(T) > 16 ? 1 : (SK == SK_FROZEN ? 4 : 2);
+#pragma unroll 1
+  for (int r0 = wave; r0 < R; r0 += NR * W) {
+    T2 rt[NR];
+    T av[NR][MAXM];
+    T2 rv[NR][MAXM], ov[NR][MAXM];  // received (reverse) message, own previous message
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int r = r0 + q * W;
+      const bool rok = r < R;  // uniform
+      const size_t base = (size_t)r * (size_t)C;
+      rt[q] = T2{T(0), T(0)};
+      if (PH == 1 && rok) rt[q] = L.tot_row[r];
+#pragma unroll
+      for (int m = 0; m < MAXM; ++m) {
+        const int c = lane + 64 * m;
+        const bool act = rok && c < C;
+        rv[q][m] = T2{T(0), T(0)};
+        ov[q][m] = T2{T(0), T(0)};
+        if constexpr (SK == SK_FROZEN) {
+          av[q][m] = act ? kown[base + c] : T(0);  // the settled coefficient
+          // informations zeroed by a restart are those not rewritten since:
+          // the received ones in PH 1, the own ones in both halves
+          if (act && !(PH == 1 && zero_h)) rv[q][m].y = hrev[base + c];
+          if (act && damp && !zero_h) ov[q][m].y = hown[base + c];
+        } else {
+          av[q][m] = act ? in.M[base + c] : T(0);
+          if (act && (PH == 2 || !fresh)) rv[q][m] = rev2[base + c];
+          if (SK == SK_FREEZE && PH == 2 && act) rv[q][m].y = hrev[base + c];  // new, settled array
+          if (PH == 1 && zero_h) rv[q][m].y = T(0);
+          if (act && read_old && !fresh) ov[q][m] = own2[base + c];
+          if (zero_h) ov[q][m].y = T(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int r = r0 + q * W;
+      if (r >= R) break;  // uniform
+      const size_t base = (size_t)r * (size_t)C;
+      T sP = T(0), sH = T(0);
+#pragma unroll
+      for (int m = 0; m < MAXM; ++m) {
+        const int c = lane + 64 * m;
+        if (c >= C) continue;
+        const T tS = PH == 1 ? rt[q].x : cS[m];
+        const T tH = PH == 1 ? rt[q].y : cH[m];
+        if constexpr (SK == SK_FROZEN) {
+          T h = av[q][m] * (tH - rv[q][m].y);
+          if (damp) h = alpha * ov[q][m].y + beta * h;
+          hown[base + c] = h;
+          if (PH == 1) aH[m] += h;
+          else sH += h;
+          continue;
+        }
+        const T a = av[q][m];
+        if (a == T(0)) {  // no edge: nothing is sent
+          if constexpr (SK == SK_FREEZE) {
+            kown[base + c] = T(0);
+            hown[base + c] = T(0);
+          }
+          continue;
+        }
+        const T cav = tS - rv[q][m].x;  // precision of the sender without the receiver's message
+        if (cav == T(0)) brk = true;
+        const T inv = T(1) / cav;
+        if constexpr (SK == SK_FREEZE) {
+          const T k = -a * inv;
+          T h = k * (tH - rv[q][m].y);
+          if (damp) h = alpha * ov[q][m].y + beta * h;
+          kown[base + c] = k;
+          hown[base + c] = h;
+          if (PH == 1) aH[m] += h;
+          else sH += h;
+        } else {
+          T P = -(a * a) * inv;
+          T h = -(a * (tH - rv[q][m].y)) * inv;
+          if (damp) {
+            P = alpha * ov[q][m].x + beta * P;
+            h = alpha * ov[q][m].y + beta * h;
+          }
+          if (want_dp) {
+            dp = fmax(dp, fabs(P - ov[q][m].x));
+            pm = fmax(pm, fabs(P));
+          }
+          own2[base + c] = T2{P, h};
+          if (PH == 1) {
+            aP[m] += P;
+            aH[m] += h;
+          } else {
+            sP += P;
+            sH += h;
+          }
+        }
+      }
+      if (PH == 2) {
+        sH = wsum64(sH);
+        if (SK == SK_FULL) sP = wsum64(sP);
+        if (lane == 0) {
+          if (SK == SK_FULL) L.tot_row[r] = T2{in.rdiag + sP, L.b_row[r] + sH};
+          else L.tot_row[r].y = L.b_row[r] + sH;
+        }
+      }
+    }
+  }
+  if (PH == 1) {
+#pragma unroll
+    for (int m = 0; m < MAXM; ++m) {
+      const int c = lane + 64 * m;
+      if (c < C) L.colpart[wave * C + c] = T2{aP[m], aH[m]};
+    }
+    __syncthreads();
+    for (int c = thread_id(); c < C; c += blockDim.x) {
+      T P = T(0), H = T(0);
+      for (int w = 0; w < W; ++w) {
+        const T2 v = L.colpart[w * C + c];
+        P += v.x;
+        H += v.y;
+      }
+      if (SK == SK_FULL) L.tot_col[c] = T2{T(1) + P, L.b_col[c] + H};
+      else L.tot_col[c].y = L.b_col[c] + H;
+    }
+  }
+  __syncthreads();
+}
+
+// One sweep of either schedule.
+template <typename T, int MAXM, int KIND, bool RB, int SK>
+__device__ __forceinline__ void any_sweep(const Inst<T> &in, const Lds<T> &L, bool fresh,
+                                          bool zero_h, bool damp, bool want_dp, T alpha, T &dp,
+                                          T &pm, bool &brk, int W) {
+  if constexpr (RB) {
+    sweep_rb<T, MAXM, SK, 1>(in, L, fresh, zero_h, damp, want_dp, alpha, dp, pm, brk, W);
+    sweep_rb<T, MAXM, SK, 2>(in, L, fresh, zero_h, damp, want_dp, alpha, dp, pm, brk, W);
+  } else {
+    sweep<T, MAXM, KIND, SK>(in, L, fresh, zero_h, damp, alpha, dp, pm, brk, W);
+  }
+}
+
 // A value every lane holds identically, moved to scalar registers so the
 // compiler treats it (and the control flow it decides) as uniform.
 __device__ __forceinline__ double uniform(double v) {
@@ -389,7 +582,7 @@ __device__ void init_totals(const Inst<T> &in, const Lds<T> &L) {
 // means or on stagnation at the arithmetic's floor, switch to settled
 // precisions, FP64 residual, restart with zeroed informations and kept
 // precisions).
-template <typename T, int MAXM, int KIND>
+template <typename T, int MAXM, int KIND, bool RB>
 __device__ DenseStat solve_instance(const DenseArgs &a, const DenseInst &I, const Inst<T> &in,
                                     const Lds<T> &L, int W) {
   using T2 = typename Vec2<T>::type;
@@ -431,15 +624,19 @@ __device__ DenseStat solve_instance(const DenseArgs &a, const DenseInst &I, cons
     }
     while (s.sweeps < a.max_sweeps) {
       T dp = T(0), pm = T(0);
+      const bool check = (in_pass + 1) % ce == 0;
       if (frozen) {
-        sweep<T, MAXM, KIND, SK_FROZEN>(in, L, fresh, zero_h, damp, alpha, dp, pm, brk, W);
+        any_sweep<T, MAXM, KIND, RB, SK_FROZEN>(in, L, fresh, zero_h, damp, check, alpha, dp, pm,
+                                                brk, W);
         ++s.frozen_sweeps;
       } else if (want_freeze && a.freeze) {
-        sweep<T, MAXM, KIND, SK_FREEZE>(in, L, fresh, zero_h, damp, alpha, dp, pm, brk, W);
+        any_sweep<T, MAXM, KIND, RB, SK_FREEZE>(in, L, fresh, zero_h, damp, check, alpha, dp, pm,
+                                                brk, W);
         frozen = true;
         ++s.frozen_sweeps;
       } else {
-        sweep<T, MAXM, KIND, SK_FULL>(in, L, fresh, zero_h, damp, alpha, dp, pm, brk, W);
+        any_sweep<T, MAXM, KIND, RB, SK_FULL>(in, L, fresh, zero_h, damp, check, alpha, dp, pm,
+                                              brk, W);
       }
       fresh = false;
       zero_h = false;
@@ -550,7 +747,7 @@ __device__ DenseStat solve_instance(const DenseArgs &a, const DenseInst &I, cons
   return s;
 }
 
-template <typename T, int MAXM, int KIND>
+template <typename T, int MAXM, int KIND, bool RB>
 __global__ __launch_bounds__(1024) void k_dense_batch(DenseArgs a) {
   using T2 = typename Vec2<T>::type;
   using T4 = typename V4<T>::type;
@@ -630,10 +827,10 @@ __global__ __launch_bounds__(1024) void k_dense_batch(DenseArgs a) {
       T dp = T(0), pm = T(0);
       bool brk = false;
       for (int k = 0; k < a.nsweeps; ++k)
-        sweep<T, MAXM, KIND, SK_FULL>(in, L, a.fresh && k == 0, false, a.alpha > 0.0, (T)a.alpha, dp,
-                                      pm, brk, W);
+        any_sweep<T, MAXM, KIND, RB, SK_FULL>(in, L, a.fresh && k == 0, false, a.alpha > 0.0, false,
+                                              (T)a.alpha, dp, pm, brk, W);
     } else if (a.mode == DENSE_SOLVE) {
-      const DenseStat s = solve_instance<T, MAXM, KIND>(a, I, in, L, W);
+      const DenseStat s = solve_instance<T, MAXM, KIND, RB>(a, I, in, L, W);
       if (threadIdx.x == 0) a.stat[t] = s;
     }
 
@@ -727,24 +924,26 @@ __global__ __launch_bounds__(256) void k_dense_marginals(int count, int kind,
   }
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, bool RB>
 const void *pick_m(int maxm) {
   switch (maxm) {
-    case 1: return (const void *)k_dense_batch<T, 1, KIND>;
-    case 2: return (const void *)k_dense_batch<T, 2, KIND>;
-    case 4: return (const void *)k_dense_batch<T, 4, KIND>;
-    case 8: return (const void *)k_dense_batch<T, 8, KIND>;
+    case 1: return (const void *)k_dense_batch<T, 1, KIND, RB>;
+    case 2: return (const void *)k_dense_batch<T, 2, KIND, RB>;
+    case 4: return (const void *)k_dense_batch<T, 4, KIND, RB>;
+    case 8: return (const void *)k_dense_batch<T, 8, KIND, RB>;
     default: return nullptr;
   }
 }
 
-const void *pick(const DenseArgs &a) {
-  if (a.fp32)
-    return a.kind == GABP_BATCH_BIPARTITE ? pick_m<float, GABP_BATCH_BIPARTITE>(a.maxm)
-                                          : pick_m<float, GABP_BATCH_DENSE>(a.maxm);
-  return a.kind == GABP_BATCH_BIPARTITE ? pick_m<double, GABP_BATCH_BIPARTITE>(a.maxm)
-                                        : pick_m<double, GABP_BATCH_DENSE>(a.maxm);
+template <typename T>
+const void *pick_t(const DenseArgs &a) {
+  if (a.kind == GABP_BATCH_DENSE)  // not two-colourable: synchronous only
+    return a.colored ? nullptr : pick_m<T, GABP_BATCH_DENSE, false>(a.maxm);
+  return a.colored ? pick_m<T, GABP_BATCH_BIPARTITE, true>(a.maxm)
+                   : pick_m<T, GABP_BATCH_BIPARTITE, false>(a.maxm);
 }
+
+const void *pick(const DenseArgs &a) { return a.fp32 ? pick_t<float>(a) : pick_t<double>(a); }
 
 size_t lds_bytes(const DenseArgs &a) {
   return (size_t)dense_lds(a.nr, a.nc, a.waves, a.fp32 ? 4 : 8).total;

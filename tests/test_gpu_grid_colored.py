@@ -230,7 +230,7 @@ def test_colored_warm_start_matches_synchronous_placement(G):
     assert _grid_rel(nx, nx, nx, bt, coef, host(b), host(x)) <= 1e-8
 
 
-def test_colored_schedule_is_grid_only(G):
+def test_colored_schedule_needs_a_two_colourable_plan(G):
     m = W.sdd_random(64, 1)
     rc, plan = G.gabp_plan_create(G.DeviceCSR.from_host(m), opts(G))
     assert rc == G.GABP_ERR_UNSUPPORTED and plan is None
