@@ -312,6 +312,43 @@ int gabp_plan_solve_batched(gabp_plan *plan, const double *b, double *x,
 int gabp_solve_batched(const gabp_batch *B, const double *b, double *x, const gabp_opts *o,
                        gabp_stats *per_instance, gabp_stats *summary, hipStream_t stream);
 
+/* ---- Any sparse matrix: regularised least squares (section VII) ---------
+ * For an m x k matrix S (any shape; square and nonsymmetric included) and
+ * psi > 0, section VII builds the symmetric (k + m) x (k + m) system
+ *     [[I_k, S^T], [S, -psi I_m]] [x; z] = [0; y]
+ * whose first k unknowns are x = (S^T S + psi I)^{-1} S^T y (psi -> 0: the
+ * Moore-Penrose solution S^+ y, which GaBP cannot reach: a zero diagonal).
+ * The plan assembles that system on the device (unknowns x first, then z;
+ * rows sorted) and solves it as a CSR plan in the pair layout, so every
+ * option and trajectory call of CSR plans applies to it with vectors of
+ * length k + m. */
+typedef struct {
+  int32_t m, k;              /* rows and columns of S, >= 0 */
+  int64_t nnz;
+  const int64_t *row_ptr;    /* device [m + 1], row_ptr[0] = 0, row_ptr[m] = nnz */
+  const int32_t *col;        /* device [nnz], strictly increasing within a row, in [0, k) */
+  const double *val;         /* device [nnz], finite */
+} gabp_rect;
+/* Validates S (GABP_ERR_ARG on a bad row_ptr, an out-of-range or unsorted
+ * column, a non-finite value, psi <= 0 or not finite; GABP_ERR_UNSUPPORTED if
+ * 2 nnz + k + m does not fit in 31 bits) and keeps the assembled system; S
+ * itself is not read after this call. */
+int gabp_plan_create_lsq(const gabp_rect *S, double psi, const gabp_opts *o, gabp_plan **plan,
+                         hipStream_t stream);
+/* x (device, k, FP64) from y (device, m, FP64).  The stop rule and
+ * st->rel_residual are those of the assembled system,
+ * ||[0; y] - R [x; z]||_2 / ||y||_2 <= tol; the least-squares residual of x
+ * is gabp_plan_residual_lsq's. */
+int gabp_plan_solve_lsq(gabp_plan *plan, const double *y, double *x, gabp_stats *st,
+                        hipStream_t stream);
+int gabp_solve_lsq(const gabp_rect *S, double psi, const double *y, double *x,
+                   const gabp_opts *o, gabp_stats *st, hipStream_t stream);
+/* FP64 residual of the regularised normal equations of an lsq plan:
+ * r = S^T y - (S^T S + psi I) x (device, k, or NULL) and
+ * *rel_norm = ||r||_2 / ||S^T y||_2 (||r||_2 when S^T y = 0). */
+int gabp_plan_residual_lsq(gabp_plan *plan, const double *y, const double *x, double *r,
+                           double *rel_norm, hipStream_t stream);
+
 /* ---- Learned warm start for grid solves (not part of the paper) ----------
  * A per-node network proposes the initial messages of a structured-grid solve
  * in place of the zero messages of Algorithm 1 step 1; the iteration, its

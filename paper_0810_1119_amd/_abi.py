@@ -60,6 +60,11 @@ class _Csr(C.Structure):
                 ("col", C.c_void_p), ("val", C.c_void_p)]
 
 
+class _Rect(C.Structure):
+    _fields_ = [("m", C.c_int32), ("k", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
 class Opts(C.Structure):
     _fields_ = [("msg_fp32", C.c_int32), ("tol", C.c_double), ("max_sweeps", C.c_int32),
                 ("check_every", C.c_int32), ("damping", C.c_double), ("inner_tol", C.c_double),
@@ -89,6 +94,12 @@ _sig = {
     "gabp_solve": (C.c_int, [C.POINTER(_Csr), _vp, _vp, _vp, C.POINTER(Opts), C.POINTER(Stats), _vp]),
     "gabp_residual": (C.c_int, [C.POINTER(_Csr), _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
     "gabp_plan_create": (C.c_int, [C.POINTER(_Csr), C.POINTER(Opts), C.POINTER(_vp), _vp]),
+    "gabp_plan_create_lsq": (C.c_int, [C.POINTER(_Rect), C.c_double, C.POINTER(Opts),
+                                       C.POINTER(_vp), _vp]),
+    "gabp_plan_solve_lsq": (C.c_int, [_vp, _vp, _vp, C.POINTER(Stats), _vp]),
+    "gabp_solve_lsq": (C.c_int, [C.POINTER(_Rect), C.c_double, _vp, _vp, C.POINTER(Opts),
+                                 C.POINTER(Stats), _vp]),
+    "gabp_plan_residual_lsq": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
     "gabp_plan_destroy": (C.c_int, [_vp]),
     "gabp_plan_solve": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(Stats), _vp]),
     "gabp_plan_reset": (C.c_int, [_vp, _vp, _vp]),
@@ -165,6 +176,47 @@ class DeviceCSR:
 
     def c(self) -> _Csr:
         return _Csr(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val))
+
+
+@dataclass
+class DeviceRect:
+    """Any sparse m x k matrix S resident on the GPU in CSR form (int64
+    row_ptr, int32 col, float64 val), for the section VII least-squares plans."""
+    m: int
+    k: int
+    row_ptr: object
+    col: object
+    val: object
+
+    @classmethod
+    def from_host(cls, row_ptr, col, val, shape, device="cuda"):
+        import numpy as np
+        import torch
+        rp = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.int64)).to(device)
+        cc = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).to(device)
+        vv = torch.from_numpy(np.ascontiguousarray(val, dtype=np.float64)).to(device)
+        return cls(int(shape[0]), int(shape[1]), rp, cc, vv)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def c(self) -> _Rect:
+        return _Rect(self.m, self.k, self.nnz, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val))
+
+
+@dataclass
+class _LsqShape:
+    """Array lengths of an lsq plan's assembled system (unknowns x then z)."""
+    S: DeviceRect
+
+    @property
+    def n(self) -> int:
+        return self.S.k + self.S.m
+
+    @property
+    def nnz(self) -> int:
+        return 2 * self.S.nnz + self.S.k + self.S.m
 
 
 def gabp_default_opts(**overrides) -> Opts:
@@ -262,6 +314,44 @@ def gabp_plan_get_messages(plan, P, h, stream=None) -> int:
 def gabp_plan_set_messages(plan, P, h, stream=None) -> int:
     _check_f64(P, plan.A.nnz, "P"); _check_f64(h, plan.A.nnz, "h")
     return lib.gabp_plan_set_messages(plan.ptr, _ptr(P), _ptr(h), _stream(stream))
+
+
+def gabp_plan_create_lsq(S: DeviceRect, psi: float, opts: Opts | None = None, stream=None):
+    """Returns (status, plan handle) of the section VII system of S."""
+    h = C.c_void_p()
+    a = S.c()
+    rc = lib.gabp_plan_create_lsq(C.byref(a), float(psi),
+                                  C.byref(opts) if opts is not None else None, C.byref(h),
+                                  _stream(stream))
+    return rc, (_PlanHandle(h.value, _LsqShape(S)) if rc == GABP_OK else None)
+
+
+def gabp_plan_solve_lsq(plan, y, x, stream=None):
+    S = plan.A.S
+    _check_f64(y, S.m, "y"); _check_f64(x, S.k, "x")
+    st = Stats()
+    rc = lib.gabp_plan_solve_lsq(plan.ptr, _ptr(y), _ptr(x), C.byref(st), _stream(stream))
+    return rc, st
+
+
+def gabp_solve_lsq(S: DeviceRect, psi: float, y, x, opts: Opts | None = None, stream=None):
+    _check_f64(y, S.m, "y"); _check_f64(x, S.k, "x")
+    st = Stats()
+    a = S.c()
+    rc = lib.gabp_solve_lsq(C.byref(a), float(psi), _ptr(y), _ptr(x),
+                            C.byref(opts) if opts is not None else None, C.byref(st),
+                            _stream(stream))
+    return rc, st
+
+
+def gabp_plan_residual_lsq(plan, y, x, r=None, stream=None):
+    """Returns (status, ||S^T y - (S^T S + psi I) x|| / ||S^T y||)."""
+    S = plan.A.S
+    _check_f64(y, S.m, "y"); _check_f64(x, S.k, "x"); _check_f64(r, S.k, "r")
+    rel = C.c_double(0.0)
+    rc = lib.gabp_plan_residual_lsq(plan.ptr, _ptr(y), _ptr(x), _ptr(r), C.byref(rel),
+                                    _stream(stream))
+    return rc, rel.value
 
 
 class _Grid(C.Structure):

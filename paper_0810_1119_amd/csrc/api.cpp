@@ -286,6 +286,7 @@ int gabp_plan_destroy(gabp_plan *p) {
   (void)hipDeviceSynchronize();
   delete p->eng;
   if (p->bat) batch_destroy(p->bat);
+  if (p->lsq) lsq_destroy(p->lsq);  // after the engine that reads its matrix
   delete p;
   return GABP_OK;
 }

@@ -126,8 +126,16 @@ int batch_marginals(BatchEngine *e, double *mean, double *prec, hipStream_t s);
 
 }  // namespace gabp
 
-// the opaque plan of the C ABI: one system (eng) or a batch of dense instances (bat)
+namespace gabp {
+// the assembled section VII system of an lsq plan (engine_lsq.cpp)
+struct LsqSystem;
+void lsq_destroy(LsqSystem *q);
+}  // namespace gabp
+
+// the opaque plan of the C ABI: one system (eng), a batch of dense instances
+// (bat); an lsq plan is a CSR system (eng) over its own assembled matrix (lsq)
 struct gabp_plan {
   gabp::Engine *eng = nullptr;
   gabp::BatchEngine *bat = nullptr;
+  gabp::LsqSystem *lsq = nullptr;
 };

@@ -273,6 +273,26 @@ hipError_t launch_grid_zero_h(bool fp32, int64_t m, void *msg, hipStream_t s);
 hipError_t launch_grid_io(bool fp32, bool get, int64_t m, void *msg, double *P, double *h,
                           hipStream_t s);
 
+// ---- section VII for any sparse S (kernels_lsq.hip) ----
+// validation of S, row lengths of R (k + m, int64), column counts, the row
+// of each nonzero and the identity permutation
+hipError_t launch_lsq_rows(int m, int k, int64_t nnz, const int64_t *rp, const int32_t *col,
+                           const double *val, uint32_t *colcnt, int64_t *rowlen, int32_t *rowof,
+                           int32_t *idx, uint32_t *flags, hipStream_t s);
+hipError_t launch_lsq_sort(int k, int64_t nnz, const int32_t *col, uint32_t *keys_out,
+                           const int32_t *idx, int32_t *perm, void *tmp, size_t *tmp_bytes,
+                           hipStream_t s);
+hipError_t launch_lsq_fill(int m, int k, double psi, const int64_t *rp, const int32_t *col,
+                           const double *val, const int64_t *Arp, const int32_t *perm,
+                           const int32_t *rowof, int32_t *Acol, double *Aval, hipStream_t s);
+hipError_t launch_lsq_embed(int k, int m, const double *y, double *bt, hipStream_t s);
+// r = S^T (y - S x) - psi x (x == NULL: S^T y) with the assembled R, u scratch
+// [m]; ||r||^2 as lsq_normal_blocks(k) block partials
+int lsq_normal_blocks(int k);
+hipError_t launch_lsq_normal(int m, int k, double psi, const int64_t *Arp, const int32_t *Acol,
+                             const double *Aval, const double *y, const double *x, double *u,
+                             double *r, double *part, hipStream_t s);
+
 // ---- batches of dense instances (kernels_dense.hip) ----
 // One instance of a batch.  Its couplings form a rows x cols row-major block
 // of the packed matrix array; entry (r, c) is one undirected edge between the

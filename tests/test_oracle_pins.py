@@ -398,3 +398,23 @@ def test_colouring_must_be_proper():
     m = W.poisson2d(4)
     with pytest.raises(ValueError):
         oracle.Rounds(m, np.ones(m.n), colors=np.zeros(m.n, dtype=int))
+
+
+# ---------------------------------------------------------------------------
+# Section VII for any sparse matrix: the first k unknowns of the symmetric
+# bipartite system are the regularised least-squares solution, for tall,
+# wide and square nonsymmetric S (pinned against a direct solve of the normal
+# equations, an independent route).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,k,per_row,psi", [(120, 40, 5, 0.1), (40, 90, 6, 0.5), (60, 60, 4, 0.3)])
+def test_bipartite_system_gives_regularised_least_squares(m, k, per_row, psi):
+    S = W.sparse_rect(m, k, per_row, seed=m + k).dense()
+    assert not np.allclose(S[:min(m, k), :min(m, k)], S[:min(m, k), :min(m, k)].T)
+    y = W.normal_b(m, 3)
+    mb, rhs = oracle.bipartite_system(S, y, psi)
+    r = oracle.solve(mb, rhs, tol=1e-12, max_rounds=20000)
+    assert r.status == oracle.OK
+    x = np.linalg.solve(S.T @ S + psi * np.eye(k), S.T @ y)
+    np.testing.assert_allclose(r.x[:k], x, rtol=0, atol=1e-9 * np.abs(x).max())
+    # the auxiliary unknowns are the scaled residual z = (S x - y) / psi
+    np.testing.assert_allclose(r.x[k:], (S @ x - y) / psi, rtol=0, atol=1e-8 * np.abs(y).max() / psi)

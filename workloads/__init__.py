@@ -491,3 +491,47 @@ def mlp_batch(count: int, seed: int, n_in: int = 8, n_out: int = 12, p_mask: flo
     U[:, 1:1 + n_out // 2] *= on  # a direction without a neighbour has coupling 0
     M = np.repeat(on, 2, axis=1).astype(np.float64)
     return U, T * M, M
+
+
+class SparseRect:
+    """A sparse m x k matrix (any shape) in CSR form: int64 row_ptr, int32
+    col (strictly increasing within a row), float64 val (no explicit zeros)."""
+
+    def __init__(self, m, k, row_ptr, col, val):
+        self.m, self.k = int(m), int(k)
+        self.row_ptr, self.col, self.val = row_ptr, col, val
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.size)
+
+    def dense(self) -> np.ndarray:
+        a = np.zeros((self.m, self.k))
+        rows = np.repeat(np.arange(self.m), np.diff(self.row_ptr))
+        a[rows, self.col] = self.val
+        return a
+
+
+def sparse_rect(m: int, k: int, per_row: int, seed: int, signs: bool = False,
+                empty_rows=(), empty_cols=()) -> SparseRect:
+    """Row j holds min(per_row, k) distinct random columns with N(0,1) values
+    (or +-1 when `signs`) scaled by 1/sqrt(per_row); rows in `empty_rows` are
+    empty and no entry falls in a column of `empty_cols`."""
+    rng = np.random.default_rng([seed, 0x5EC7])
+    allowed = np.setdiff1d(np.arange(k), np.asarray(empty_cols, dtype=np.int64))
+    skip = set(int(j) for j in empty_rows)
+    rp = np.zeros(m + 1, dtype=np.int64)
+    cols, vals = [], []
+    for j in range(m):
+        if j in skip or allowed.size == 0:
+            rp[j + 1] = rp[j]
+            continue
+        c = np.sort(rng.choice(allowed, size=min(per_row, allowed.size), replace=False))
+        v = rng.choice([-1.0, 1.0], c.size) if signs else rng.standard_normal(c.size)
+        v = np.where(v == 0.0, 1.0, v) / np.sqrt(per_row)
+        cols.append(c)
+        vals.append(v)
+        rp[j + 1] = rp[j] + c.size
+    col = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
+    val = np.concatenate(vals) if vals else np.zeros(0)
+    return SparseRect(m, k, rp, col, val)
