@@ -270,6 +270,26 @@ class _CSRLike:
         self.n, self.row_ptr, self.col, self.val = n, row_ptr, col, val
 
 
+def bipartite_system_sparse(m: int, k: int, row_ptr, col, val, y, sigma2: float):
+    """The same system for S given in CSR form (m x k, no explicit zeros), for
+    sizes where S cannot be dense: rows of x first (diagonal 1, then column i
+    of S), then rows of z (row j of S, then the diagonal -sigma2)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    val = np.asarray(val, dtype=np.float64)
+    srow = np.repeat(np.arange(m, dtype=np.int64), np.diff(row_ptr))
+    n = k + m
+    rows = np.concatenate([np.arange(k), srow + k, col, np.arange(k, n)])
+    cols = np.concatenate([np.arange(k), col, srow + k, np.arange(k, n)])
+    vals = np.concatenate([np.ones(k), val, val, np.full(m, -float(sigma2))])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    row_ptr_b = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr_b[1:])
+    rhs = np.concatenate([np.zeros(k), np.asarray(y, dtype=np.float64)])
+    return _CSRLike(n, row_ptr_b, cols.astype(np.int32), vals), rhs
+
+
 def bipartite_system(S: np.ndarray, y: np.ndarray, sigma2: float):
     """CSR of [[I_K, S^T], [S, -sigma2 I_N]] (zero entries of S dropped) and [0; y]."""
     S = np.asarray(S, dtype=np.float64)

@@ -33,9 +33,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Block-wide maxima of four values (every thread of the block must call);
-// thread 0 writes them to part[blockIdx.x].
+// thread 0 writes them to part[blockIdx.x], or, with combine, the maxima of
+// them and what part[blockIdx.x] already holds (a later launch of the same
+// check adding its nodes; launches on one stream run in order).
 __device__ __forceinline__ void block_publish(double d, double x, double dp, double pm,
-                                              BlockPartial *part) {
+                                              BlockPartial *part, bool combine = false) {
   __shared__ double sh[4][kBlock / 64];
   d = wave_max(d);
   x = wave_max(x);
@@ -50,6 +52,10 @@ __device__ __forceinline__ void block_publish(double d, double x, double dp, dou
     d = sh[0][0]; x = sh[1][0]; dp = sh[2][0]; pm = sh[3][0];
     for (int k = 1; k < kBlock / 64; ++k) {
       d = fmax(d, sh[0][k]); x = fmax(x, sh[1][k]); dp = fmax(dp, sh[2][k]); pm = fmax(pm, sh[3][k]);
+    }
+    if (combine) {
+      const BlockPartial o = part[blockIdx.x];
+      d = fmax(d, o.dmax); x = fmax(x, o.xmax); dp = fmax(dp, o.dpmax); pm = fmax(pm, o.pmax);
     }
     BlockPartial b;
     b.dmax = d; b.xmax = x; b.dpmax = dp; b.pmax = pm;

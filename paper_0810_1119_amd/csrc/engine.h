@@ -6,6 +6,7 @@
 #pragma once
 
 #include <algorithm>
+#include <vector>
 
 #include "gabp_internal.h"
 
@@ -112,6 +113,10 @@ int engine_solve(Engine *e, const double *b, double *x, double *marg, gabp_stats
                  hipStream_t s, const uint16_t *warm = nullptr);
 
 int check_opts(const gabp_opts *o);  // engine_csr.cpp
+// a CSR plan; classes = row offsets of colour classes (coloured schedule) or
+// NULL (engine_csr.cpp)
+int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int> *classes,
+                    gabp_plan **plan, hipStream_t s);
 int check_grid(const gabp_grid *A, GridGeom *g);  // engine_grid.cpp
 
 // batches of dense instances (engine_dense.cpp)

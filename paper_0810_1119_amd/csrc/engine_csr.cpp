@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "engine.h"
 
@@ -62,6 +63,11 @@ struct CsrEngine : Engine {
   void *sums[2] = {nullptr, nullptr};  // pair: (S, H) per node
   // settled-precision phase (pair layout, allocated on first use)
   void *coef = nullptr, *hp[2] = {nullptr, nullptr}, *Sfix = nullptr, *Hfz[2] = {nullptr, nullptr};
+  // coloured schedule (pair layout): class c is rows [cls[c], cls[c + 1]);
+  // one buffer (index 0), updated in place by one launch per class
+  std::vector<int> cls;
+  int cgrid = 1;
+  bool first = true;  // no sweep since the messages were set (reset, restart, import)
 
   ~CsrEngine() override {
     void *bufs[] = {oprt, ocol, rev, diagpos, acoef, diag, rhs, msg[0], msg[1], sums[0],
@@ -72,8 +78,29 @@ struct CsrEngine : Engine {
 
   size_t msg_bytes() const { return (pair ? 4 : 2) * tsz; }
 
+  bool colored() const { return !cls.empty(); }
+
   hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
     hipError_t err;
+    if (colored()) {
+      for (size_t k = 0; k + 1 < cls.size(); ++k) {
+        PairArgs a{};
+        a.grid = cgrid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
+        a.frozen = frozen; a.n = n; a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
+        a.rhs = rhs; a.alpha = o.damping; a.xprev = xprev; a.part = part; a.sticky = sticky;
+        a.ctl = c; a.colored = true; a.combine = k > 0; a.row0 = cls[k]; a.row1 = cls[k + 1];
+        a.first = first;
+        if (frozen) {
+          a.coef = coef; a.Sfix = Sfix; a.msg_out = hp[0]; a.sums_out = Hfz[0];
+        } else {
+          a.msg_out = msg[0]; a.sums_out = sums[0];
+        }
+        a.msg_in = a.msg_out; a.sums_in = a.sums_out;
+        if ((err = launch_pair_sweep(a, s)) != hipSuccess) return err;
+      }
+      first = false;
+      return hipSuccess;
+    }
     if (!pair) {
       SweepArgs a{};
       a.grid = grid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
@@ -107,22 +134,45 @@ struct CsrEngine : Engine {
       a.xacc = xacc; a.marg = marg; a.xprev = means; a.sticky = sticky;
       return launch_sweep(a, s);
     }
+    if (colored() && !first) {
+      // the broadcasts of earlier classes predate the later classes' messages
+      PairArgs a{};
+      a.grid = grid; a.fp32 = fp32; a.group = group; a.damp = o.damping > 0.0; a.frozen = frozen;
+      a.n = n; a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag; a.rhs = rhs;
+      a.alpha = o.damping; a.sticky = sticky; a.coef = coef; a.Sfix = Sfix;
+      a.msg_in = frozen ? hp[0] : msg[0];
+      a.sums_in = frozen ? Hfz[0] : sums[0];
+      for (size_t k = 0; k + 1 < cls.size(); ++k) {
+        a.row0 = cls[k];
+        a.row1 = cls[k + 1];
+        a.grid = sweep_blocks(std::max(a.row1 - a.row0, 1), group, grid);
+        hipError_t err = launch_pair_col_infer(a, xacc, marg, means, s);
+        if (err != hipSuccess) return err;
+      }
+      return hipSuccess;
+    }
     if (frozen)
       return launch_pair_infer(fp32, n, nullptr, Sfix, Hfz[cur], xacc, marg, means, sticky, s);
     return launch_pair_infer(fp32, n, sums[cur], nullptr, nullptr, xacc, marg, means, sticky, s);
   }
 
   hipError_t restart(hipStream_t s) override {
+    first = true;
     if (!pair) return launch_zero_h(fp32, E, msg[cur], s);
     if (frozen) return launch_frozen_restart(fp32, E, n, hp[cur], rhs, Hfz[cur], s);
     hipError_t err = launch_pair_zero_h(fp32, E, msg[cur], s);
     if (err != hipSuccess) return err;
+    // coloured: a row's stored copy of a later class's precision message is
+    // one half sweep old; make every copy the sender's current message
+    if (colored() && (err = launch_pair_sync_in(fp32, E, rev, msg[cur], s)) != hipSuccess)
+      return err;
     return launch_pair_aggregate(fp32, group, grid, n, oprt, diag, rhs, msg[cur], sums[cur], s);
   }
 
   hipError_t reset(const double *b, hipStream_t s) override {
     cur = 0;
     frozen = false;
+    first = true;
     const int64_t words = E * (int64_t)msg_bytes() / 8;
     hipError_t err;
     if ((err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
@@ -176,6 +226,7 @@ struct CsrEngine : Engine {
 
   int set_messages(const double *P, const double *h, hipStream_t s) override {
     if (A.nnz > 0 && (!P || !h)) return GABP_ERR_ARG;
+    first = true;
     if (pair) {
       TRY_HIP(launch_pair_io(fp32, false, n, A.row_ptr, diagpos, oprt, rev, msg[cur], (double *)P,
                              (double *)h, s));
@@ -236,14 +287,10 @@ struct CsrEngine : Engine {
   }
 };
 
-}  // namespace gabp
-
-using namespace gabp;
-
-extern "C" {
-
-int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
-  clear_stale_error();
+// A CSR plan; `classes` (row offsets of the colour classes, classes[0] = 0,
+// last = n) selects the coloured schedule, NULL the synchronous one.
+int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int> *classes,
+                    gabp_plan **plan, hipStream_t s) {
   if (!plan) return GABP_ERR_ARG;
   *plan = nullptr;
   gabp_opts opts;
@@ -252,7 +299,8 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
   int st = check_csr(A);
   if (st) return st;
   if ((st = check_opts(&opts))) return st;
-  if (opts.schedule != GABP_SCHEDULE_SYNC) return GABP_ERR_UNSUPPORTED;
+  if ((opts.schedule != GABP_SCHEDULE_SYNC) != (classes != nullptr)) return GABP_ERR_UNSUPPORTED;
+  if (classes && opts.layout != GABP_LAYOUT_PAIR) return GABP_ERR_UNSUPPORTED;
   CsrEngine *e = new (std::nothrow) CsrEngine();
   if (!e) return GABP_ERR_NOMEM;
   e->A = *A;
@@ -270,6 +318,15 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
   const int cap = opts.grid_blocks > 0 ? opts.grid_blocks : kMaxSweepBlocks;
   e->grid = sweep_blocks(std::max(e->n, 1), e->group, cap);
   e->nparts = e->grid;
+  if (classes) {
+    // every class launch has the same blocks, so a check's partials line up
+    e->cls = *classes;
+    int most = 1;
+    for (size_t k = 0; k + 1 < e->cls.size(); ++k)
+      most = std::max(most, e->cls[k + 1] - e->cls[k]);
+    e->cgrid = sweep_blocks(most, e->group, cap);
+    e->nparts = e->cgrid;
+  }
   e->nsum = residual_blocks(std::max(e->n, 1), e->group, cap);
   if ((st = e->init_common(s))) return fail(st);
   if ((st = from_hip(dalloc(&e->msg[0], e->E, e->msg_bytes()))) ||
@@ -284,6 +341,18 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
   p->eng = e;
   *plan = p;
   return GABP_OK;
+}
+
+}  // namespace gabp
+
+using namespace gabp;
+
+extern "C" {
+
+int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
+  clear_stale_error();
+  if (o && o->schedule == GABP_SCHEDULE_COLORED) return GABP_ERR_UNSUPPORTED;
+  return csr_plan_create(A, o, nullptr, plan, s);
 }
 
 int gabp_solve(const gabp_csr *A, const double *b, double *x, double *marg_prec,

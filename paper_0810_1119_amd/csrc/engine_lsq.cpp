@@ -144,8 +144,11 @@ int gabp_plan_create_lsq(const gabp_rect *S, double psi, const gabp_opts *o, gab
   A.row_ptr = q->Arp;
   A.col = q->Acol;
   A.val = q->Aval;
+  // the two classes of the bipartite graph: the x rows, then the z rows
+  const std::vector<int> classes = {0, S->k, (int)n};
+  const bool coloured = o && o->schedule == GABP_SCHEDULE_COLORED;
   gabp_plan *p = nullptr;
-  if ((rc = gabp_plan_create(&A, o, &p, s))) {
+  if ((rc = csr_plan_create(&A, o, coloured ? &classes : nullptr, &p, s))) {
     delete q;
     return rc;
   }

@@ -165,8 +165,22 @@ struct PairArgs {
   BlockPartial *part;
   uint32_t *sticky;
   const Ctl *ctl;
+  // coloured schedule: one colour class, rows [row0, row1), updated in place
+  // (msg_in == msg_out, sums_in == sums_out); combine: add to the partials
+  // of the check's earlier class launches
+  bool colored, combine;
+  int row0, row1;
+  bool first;  // first sweep since the messages were set, not sent
 };
 hipError_t launch_pair_sweep(const PairArgs &a, hipStream_t s);
+// marginals of one class (rows [row0, row1)) of a coloured pair plan from its
+// current messages after a complete sweep (msg_in / sums_in: the full state,
+// or in the settled state the information pairs and H broadcasts, with coef
+// and Sfix)
+hipError_t launch_pair_col_infer(const PairArgs &a, double *xacc, double *marg, void *means,
+                                 hipStream_t s);
+// msg[e].P_ji := msg[rev[e]].P_ij for every slot (pair layout)
+hipError_t launch_pair_sync_in(bool fp32, int64_t E, const int32_t *rev, void *msg, hipStream_t s);
 hipError_t launch_pair_aggregate(bool fp32, int group, int grid, int n, const int32_t *oprt, const void *diag,
                                  const void *rhs, const void *msg, void *sums, hipStream_t s);
 hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s);

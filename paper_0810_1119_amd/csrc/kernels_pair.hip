@@ -295,6 +295,306 @@ __global__ void k_frozen_restart(int64_t E, int n, typename Vec2<T>::type *__res
 }
 
 // ---------------------------------------------------------------------------
+// coloured schedule: the rows of one colour class send, in place
+// ---------------------------------------------------------------------------
+// Row i of the class first rebuilds its in-messages from the neighbours'
+// current broadcasts (every neighbour is of another class, so these are the
+// newest messages it sent, recomputed from the same operands it used), sums
+// them into its new totals (S_i, H_i), and only then computes its
+// out-messages from those totals: the serial scheme of section III-C, one
+// colour class at a time.  No row of the class reads a slot or broadcast
+// another row of the class writes, so one buffer suffices.  A row with at most
+// G slots keeps its slot in registers between the two steps; longer rows read
+// their slots twice (the second read comes from the cache).
+//
+// The rebuilt in-message equals the stored one only if its sender computed it
+// from its broadcast.  Messages that were set rather than sent (zeroed by a
+// reset or a restart, or imported) are not; `first` marks the first sweep
+// after such a change, in which the classes that have not sent yet (rows at
+// or beyond row1: classes run in row order) pass their stored in-messages
+// instead, which the engine keeps equal to the senders' out-messages.
+template <typename T, int G, int MODE, bool DAMP>
+__global__ __launch_bounds__(kBlock) void k_pair_col(
+    int row0, int row1, bool first, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ ocol, const T *__restrict__ acoef, const T *__restrict__ diag,
+    const T *__restrict__ rhs, typename Vec4<T>::type *msg, typename Vec2<T>::type *sums, T alpha,
+    T *__restrict__ xprev, BlockPartial *__restrict__ part, bool combine,
+    uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+#pragma clang fp contract(off)
+  using V4 = typename Vec4<T>::type;
+  using V2 = typename Vec2<T>::type;
+  constexpr int RPB = kBlock / G;
+  if (ctl != nullptr && ctl->stop != STOP_NONE) return;
+  const int lane = threadIdx.x % G;
+  const T b1 = T(1) - alpha;
+  double d = 0.0, ax = 0.0, dpb = 0.0, pmb = 0.0;
+  bool zero = false;
+  uint32_t f = 0;
+  for (int base = row0 + blockIdx.x * RPB; base < row1; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    const bool active = row < row1;
+    const int beg = active ? oprt[row] : 0, end = active ? oprt[row + 1] : 0;
+    // step 1: the in-messages j -> i from j's broadcast, and the new totals
+    T S = T(0), H = T(0);
+    V4 m0;
+    T Pin0 = T(0), hin0 = T(0), a0 = T(0);
+    const bool one = end - beg <= G;  // uniform over the row's lanes
+    for (int e = beg + lane; e < end; e += G) {
+      const T a = acoef[e];
+      const V4 m = msg[e];  // (P_ij, h_ij, P_ji, h_ji) as last written
+      const int j = ocol[e];
+      T Pin = m.z, hin = m.w;
+      if (!(first && j >= row1)) {
+        const V2 sj = sums[j];  // broadcast of node j, written when j last sent
+        const T cj = sj.x - m.x;
+        zero |= cj == T(0);
+        const T ij = T(1) / cj;
+        Pin = -(a * a) * ij;
+        hin = -(a * (sj.y - m.y)) * ij;
+        if (DAMP) {
+          Pin = alpha * m.z + b1 * Pin;
+          hin = alpha * m.w + b1 * hin;
+        }
+      }
+      S += Pin;
+      H += hin;
+      m0 = m;
+      Pin0 = Pin;
+      hin0 = hin;
+      a0 = a;
+    }
+    S = gsum<G>(S);
+    H = gsum<G>(H);
+    if (active) {
+      S += diag[row];
+      H += rhs[row];
+    }
+    // step 2: the out-messages i -> j from the new totals
+    T dp = T(0), pm = T(0);
+    for (int e = beg + lane; e < end; e += G) {
+      V4 m;
+      T Pin, hin, a;
+      if (one) {
+        m = m0;
+        Pin = Pin0;
+        hin = hin0;
+        a = a0;
+      } else {  // recompute this slot's in-message exactly as in step 1
+        a = acoef[e];
+        m = msg[e];
+        const int j = ocol[e];
+        Pin = m.z;
+        hin = m.w;
+        if (!(first && j >= row1)) {
+          const V2 sj = sums[j];
+          const T ij = T(1) / (sj.x - m.x);
+          Pin = -(a * a) * ij;
+          hin = -(a * (sj.y - m.y)) * ij;
+          if (DAMP) {
+            Pin = alpha * m.z + b1 * Pin;
+            hin = alpha * m.w + b1 * hin;
+          }
+        }
+      }
+      const T ci = S - Pin;
+      zero |= ci == T(0);
+      const T ii = T(1) / ci;
+      T Pout = -(a * a) * ii, hout = -(a * (H - hin)) * ii;
+      if (DAMP) {
+        Pout = alpha * m.x + b1 * Pout;
+        hout = alpha * m.y + b1 * hout;
+      }
+      if (MODE == 1) {
+        dp = fmax(dp, fabs(Pout - m.x));
+        pm = fmax(pm, fabs(Pout));
+      }
+      V4 o;
+      o.x = Pout; o.y = hout; o.z = Pin; o.w = hin;
+      msg[e] = o;
+    }
+    if (active && lane == 0) {
+      V2 o;
+      o.x = S;
+      o.y = H;
+      sums[row] = o;
+      if (MODE == 1) {
+        if (S == T(0)) f |= FLAG_BREAKDOWN;
+        const T x = H / S;
+        if (!isfinite(x)) f |= FLAG_NONFINITE;
+        d = fmax(d, (double)fabs(x - xprev[row]));
+        xprev[row] = x;
+        ax = fmax(ax, (double)fabs(x));
+      }
+    }
+    if (MODE == 1) {
+      dpb = fmax(dpb, (double)dp);
+      pmb = fmax(pmb, (double)pm);
+    }
+  }
+  if (zero) f |= FLAG_BREAKDOWN;
+  if (f) atomicOr(sticky, f);
+  if (MODE == 1) block_publish(d, ax, dpb, pmb, part, combine);
+}
+
+// settled precisions, coloured: h_ji from H_j's broadcast, then H_i, then h_ij
+template <typename T, int G, int MODE, bool DAMP>
+__global__ __launch_bounds__(kBlock) void k_pair_frozen_col(
+    int row0, int row1, bool first, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ ocol,
+    const typename Vec2<T>::type *__restrict__ coef, const T *__restrict__ rhs,
+    const T *__restrict__ Sfix, typename Vec2<T>::type *hp, T *Hb, T alpha,
+    T *__restrict__ xprev, BlockPartial *__restrict__ part, bool combine,
+    uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+#pragma clang fp contract(off)
+  using V2 = typename Vec2<T>::type;
+  constexpr int RPB = kBlock / G;
+  if (ctl != nullptr && ctl->stop != STOP_NONE) return;
+  const int lane = threadIdx.x % G;
+  const T b1 = T(1) - alpha;
+  double d = 0.0, ax = 0.0;
+  uint32_t f = 0;
+  for (int base = row0 + blockIdx.x * RPB; base < row1; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    const bool active = row < row1;
+    const int beg = active ? oprt[row] : 0, end = active ? oprt[row + 1] : 0;
+    const bool one = end - beg <= G;
+    T H = T(0);
+    V2 c0, h0;
+    T hin0 = T(0);
+    for (int e = beg + lane; e < end; e += G) {
+      const V2 c = coef[e];
+      const V2 h = hp[e];  // (h_ij, h_ji) as last written
+      const int j = ocol[e];
+      T hin = h.y;
+      if (!(first && j >= row1)) {
+        hin = c.y * (Hb[j] - h.x);
+        if (DAMP) hin = alpha * h.y + b1 * hin;
+      }
+      H += hin;
+      c0 = c;
+      h0 = h;
+      hin0 = hin;
+    }
+    H = gsum<G>(H);
+    if (active) H += rhs[row];
+    for (int e = beg + lane; e < end; e += G) {
+      V2 c, h;
+      T hin;
+      if (one) {
+        c = c0;
+        h = h0;
+        hin = hin0;
+      } else {
+        c = coef[e];
+        h = hp[e];
+        const int j = ocol[e];
+        hin = h.y;
+        if (!(first && j >= row1)) {
+          hin = c.y * (Hb[j] - h.x);
+          if (DAMP) hin = alpha * h.y + b1 * hin;
+        }
+      }
+      T hout = c.x * (H - hin);
+      if (DAMP) hout = alpha * h.x + b1 * hout;
+      V2 o;
+      o.x = hout;
+      o.y = hin;
+      hp[e] = o;
+    }
+    if (active && lane == 0) {
+      Hb[row] = H;
+      if (MODE == 1) {
+        const T x = H / Sfix[row];
+        if (!isfinite(x)) f |= FLAG_NONFINITE;
+        d = fmax(d, (double)fabs(x - xprev[row]));
+        xprev[row] = x;
+        ax = fmax(ax, (double)fabs(x));
+      }
+    }
+  }
+  if (f) atomicOr(sticky, f);
+  if (MODE == 1) block_publish(d, ax, 0.0, 0.0, part, combine);
+}
+
+// Marginals of a coloured plan from its current messages, one class (rows
+// [row0, row1)) per launch, after a complete sweep.  A row's broadcast
+// predates the messages of the classes that sent after it, so the totals are
+// rebuilt: in-messages from earlier classes are the stored copies (made in
+// this row's phase, and their senders have not sent since), those from later
+// classes are rebuilt from the senders' broadcasts (they were computed from
+// this row's current out-messages).  Full state: (S, H) from the in-messages;
+// settled: S fixed, H rebuilt.
+template <typename T, int G, bool DAMP, bool FROZEN>
+__global__ __launch_bounds__(kBlock) void k_pair_col_infer(
+    int row0, int row1, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
+    const T *__restrict__ acoef, const T *__restrict__ diag, const T *__restrict__ rhs,
+    const typename Vec4<T>::type *__restrict__ msg, const typename Vec2<T>::type *__restrict__ sums,
+    const typename Vec2<T>::type *__restrict__ coef, const typename Vec2<T>::type *__restrict__ hp,
+    const T *__restrict__ Sfix, const T *__restrict__ Hb, T alpha, double *__restrict__ xacc,
+    double *__restrict__ marg, T *__restrict__ means, uint32_t *__restrict__ sticky) {
+#pragma clang fp contract(off)
+  using V2 = typename Vec2<T>::type;
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G;
+  const T b1 = T(1) - alpha;
+  uint32_t f = 0;
+  for (int base = row0 + blockIdx.x * RPB; base < row1; base += gridDim.x * RPB) {
+    const int row = base + threadIdx.x / G;
+    const bool active = row < row1;
+    const int beg = active ? oprt[row] : 0, end = active ? oprt[row + 1] : 0;
+    T S = T(0), H = T(0);
+    for (int e = beg + lane; e < end; e += G) {
+      const int j = ocol[e];
+      if (FROZEN) {
+        const V2 h = hp[e];
+        T hin = h.y;
+        if (j >= row1) {
+          hin = coef[e].y * (Hb[j] - h.x);
+          if (DAMP) hin = alpha * h.y + b1 * hin;
+        }
+        H += hin;
+      } else {
+        const auto m = msg[e];
+        T Pin = m.z, hin = m.w;
+        if (j >= row1) {
+          const T a = acoef[e];
+          const V2 sj = sums[j];
+          const T ij = T(1) / (sj.x - m.x);
+          Pin = -(a * a) * ij;
+          hin = -(a * (sj.y - m.y)) * ij;
+          if (DAMP) {
+            Pin = alpha * m.z + b1 * Pin;
+            hin = alpha * m.w + b1 * hin;
+          }
+        }
+        S += Pin;
+        H += hin;
+      }
+    }
+    S = gsum<G>(S);
+    H = gsum<G>(H);
+    if (active && lane == 0) {
+      S = FROZEN ? Sfix[row] : S + diag[row];
+      H += rhs[row];
+      if (S == T(0)) f |= FLAG_BREAKDOWN;
+      if (xacc) xacc[row] += (double)H / (double)S;
+      if (marg) marg[row] = (double)S;
+      if (means) means[row] = H / S;
+    }
+  }
+  if (f) atomicOr(sticky, f);
+}
+
+// Stored in-messages := the senders' out-messages (P only; the coloured
+// schedule's restart, after the informations were zeroed).
+template <typename T>
+__global__ void k_pair_sync_in(int64_t E, const int32_t *__restrict__ rev,
+                               typename Vec4<T>::type *__restrict__ msg) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) msg[e].z = msg[rev[e]].x;
+}
+
+// ---------------------------------------------------------------------------
 // export / import in CSR slot order (pair layout holds the out-message at .xy)
 // ---------------------------------------------------------------------------
 template <typename T, bool GET>
@@ -332,6 +632,19 @@ static void pair_one(const PairArgs &a, hipStream_t s) {
   using V4 = typename Vec4<T>::type;
   using V2 = typename Vec2<T>::type;
   const dim3 grid(a.grid);
+  if (a.colored) {
+    if (a.frozen)
+      hipLaunchKernelGGL((k_pair_frozen_col<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.row0,
+                         a.row1, a.first, a.oprt, a.ocol, (const V2 *)a.coef, (const T *)a.rhs,
+                         (const T *)a.Sfix, (V2 *)a.msg_out, (T *)a.sums_out, (T)a.alpha,
+                         (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
+    else
+      hipLaunchKernelGGL((k_pair_col<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.row0, a.row1,
+                         a.first, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,
+                         (V4 *)a.msg_out, (V2 *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part,
+                         a.combine, a.sticky, a.ctl);
+    return;
+  }
   if (a.frozen)
     hipLaunchKernelGGL((k_pair_frozen<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.n, a.oprt,
                        a.ocol, (const V2 *)a.coef, (const T *)a.rhs, (const T *)a.Sfix,
@@ -475,4 +788,55 @@ hipError_t launch_pair_io(bool fp32, bool get, int n, const int64_t *rp, const i
   return hipGetLastError();
 }
 
+}  // namespace gabp
+
+namespace gabp {
+hipError_t launch_pair_sync_in(bool fp32, int64_t E, const int32_t *rev, void *msg, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((E + kBlock - 1) / kBlock));
+  if (fp32) hipLaunchKernelGGL(k_pair_sync_in<float>, grid, dim3(kBlock), 0, s, E, rev, (float4 *)msg);
+  else hipLaunchKernelGGL(k_pair_sync_in<double>, grid, dim3(kBlock), 0, s, E, rev, (double4 *)msg);
+  return hipGetLastError();
+}
+}  // namespace gabp
+
+namespace gabp {
+template <typename T, int G>
+static void col_infer_g(const PairArgs &a, double *xacc, double *marg, void *means, hipStream_t s) {
+  using V4 = typename Vec4<T>::type;
+  using V2 = typename Vec2<T>::type;
+#define COL_INFER(D, F)                                                                          \
+  hipLaunchKernelGGL((k_pair_col_infer<T, G, D, F>), dim3(a.grid), dim3(kBlock), 0, s, a.row0,  \
+                     a.row1, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,      \
+                     (const V4 *)a.msg_in, (const V2 *)a.sums_in, (const V2 *)a.coef,            \
+                     (const V2 *)a.msg_in, (const T *)a.Sfix, (const T *)a.sums_in, (T)a.alpha,   \
+                     xacc, marg, (T *)means, a.sticky)
+  if (a.frozen) {
+    if (a.damp) COL_INFER(true, true); else COL_INFER(false, true);
+  } else {
+    if (a.damp) COL_INFER(true, false); else COL_INFER(false, false);
+  }
+#undef COL_INFER
+}
+
+template <typename T>
+static hipError_t col_infer_t(const PairArgs &a, double *xacc, double *marg, void *means,
+                              hipStream_t s) {
+  switch (a.group) {
+    case 4: col_infer_g<T, 4>(a, xacc, marg, means, s); break;
+    case 8: col_infer_g<T, 8>(a, xacc, marg, means, s); break;
+    case 16: col_infer_g<T, 16>(a, xacc, marg, means, s); break;
+    case 32: col_infer_g<T, 32>(a, xacc, marg, means, s); break;
+    case 64: col_infer_g<T, 64>(a, xacc, marg, means, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_col_infer(const PairArgs &a, double *xacc, double *marg, void *means,
+                                 hipStream_t s) {
+  if (a.row1 <= a.row0) return hipSuccess;
+  return a.fp32 ? col_infer_t<float>(a, xacc, marg, means, s)
+                : col_infer_t<double>(a, xacc, marg, means, s);
+}
 }  // namespace gabp

@@ -79,6 +79,62 @@ def test_lsq_fp64_trajectory_matches_oracle(G, case):
         G.gabp_plan_destroy(plan)
 
 
+@pytest.mark.parametrize("case", sorted(SHAPES))
+@pytest.mark.parametrize("damping", [0.0, 0.4])
+def test_lsq_colored_fp64_trajectory_matches_oracle(G, case, damping):
+    """Two-colour schedule: the x rows send, then the z rows; oracle coloured
+    rounds with colour 0 on x."""
+    m, k, pr, psi = SHAPES[case]
+    S = W.sparse_rect(m, k, pr, seed=m * 7 + k)
+    y = W.normal_b(m, 5)
+    rc, plan = G.gabp_plan_create_lsq(_rect(G, S), psi, G.gabp_default_opts(
+        msg_fp32=0, freeze=0, damping=damping, schedule=G.GABP_SCHEDULE_COLORED))
+    assert rc == G.GABP_OK, G.status_name(rc)
+    try:
+        mb, rhs = oracle.bipartite_system(S.dense(), y, psi)
+        assert G.gabp_plan_reset(plan, dev(rhs)) == G.GABP_OK
+        R = oracle.Rounds(mb, rhs, damping=damping, colors=np.r_[np.zeros(k, int), np.ones(m, int)])
+        n, nnz = m + k, 2 * S.nnz + m + k
+        for t in range(1, 7):
+            R.step()
+            assert G.gabp_plan_sweeps(plan, 1) == G.GABP_OK
+            P = torch.zeros(nnz, dtype=torch.float64, device="cuda")
+            h = torch.zeros(nnz, dtype=torch.float64, device="cuda")
+            assert G.gabp_plan_get_messages(plan, P, h) == G.GABP_OK
+            np.testing.assert_allclose(host(P), R.P, rtol=1e-11, atol=1e-13 * np.abs(R.P).max())
+            ho = R.information()
+            np.testing.assert_allclose(host(h), ho, rtol=1e-10, atol=1e-12 * np.abs(ho).max())
+            mean = torch.zeros(n, dtype=torch.float64, device="cuda")
+            prec = torch.zeros(n, dtype=torch.float64, device="cuda")
+            assert G.gabp_plan_marginals(plan, mean, prec) == G.GABP_OK
+            mo, po = R.marginals()
+            np.testing.assert_allclose(host(mean), mo, rtol=1e-10, atol=1e-12 * np.abs(mo).max())
+            np.testing.assert_allclose(host(prec), po, rtol=1e-10)
+    finally:
+        G.gabp_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("fp32,tol", [(1, 1e-8), (0, 1e-11)])
+def test_lsq_colored_solve_in_about_half_the_sweeps(G, fp32, tol):
+    m, k, pr, psi = SHAPES["tall_240x80"]
+    S = W.sparse_rect(m, k, pr, seed=13)
+    y = dev(W.normal_b(m, 14))
+    res = {}
+    for sched in (G.GABP_SCHEDULE_SYNC, G.GABP_SCHEDULE_COLORED):
+        x = torch.zeros(k, dtype=torch.float64, device="cuda")
+        rc, st = G.gabp_solve_lsq(_rect(G, S), psi, y, x,
+                                  G.gabp_default_opts(msg_fp32=fp32, tol=tol, schedule=sched))
+        assert rc == G.GABP_OK, G.status_name(rc)
+        assert st.rel_residual <= tol
+        res[sched] = (host(x), st.sweeps)
+    ref = _normal_solution(S, host(y), psi)
+    for xs, _ in res.values():
+        np.testing.assert_allclose(xs, ref, rtol=0, atol=100 * tol * np.abs(ref).max())
+    s_sync, s_col = res[G.GABP_SCHEDULE_SYNC][1], res[G.GABP_SCHEDULE_COLORED][1]
+    print(f"sweeps: synchronous {s_sync}, coloured {s_col}", flush=True)
+    assert s_col <= 0.65 * s_sync
+
+
 @pytest.mark.parametrize("case", ["tall_240x80", "wide_70x150", "square_nonsym_130"])
 @pytest.mark.parametrize("fp32,tol", [(1, 1e-8), (0, 1e-11)])
 def test_lsq_solve_matches_the_normal_equations(G, case, fp32, tol):
@@ -158,7 +214,8 @@ def test_lsq_error_paths(G):
     bad.row_ptr = bad.row_ptr.copy()
     bad.row_ptr[-1] -= 1  # last entry not covered
     assert G.gabp_solve_lsq(_rect(G, bad), 0.5, y, x)[0] == G.GABP_ERR_ARG
-    rc, plan = G.gabp_plan_create_lsq(R, 0.5, G.gabp_default_opts(schedule=G.GABP_SCHEDULE_COLORED))
+    rc, plan = G.gabp_plan_create_lsq(R, 0.5, G.gabp_default_opts(
+        schedule=G.GABP_SCHEDULE_COLORED, layout=G.GABP_LAYOUT_GATHER))
     assert rc == G.GABP_ERR_UNSUPPORTED and plan is None
     # a CSR plan is not an lsq plan
     rc, csr = G.gabp_plan_create(G.DeviceCSR.from_host(W.sdd_random(16, 1)))

@@ -418,3 +418,15 @@ def test_bipartite_system_gives_regularised_least_squares(m, k, per_row, psi):
     np.testing.assert_allclose(r.x[:k], x, rtol=0, atol=1e-9 * np.abs(x).max())
     # the auxiliary unknowns are the scaled residual z = (S x - y) / psi
     np.testing.assert_allclose(r.x[k:], (S @ x - y) / psi, rtol=0, atol=1e-8 * np.abs(y).max() / psi)
+
+
+def test_sparse_bipartite_construction_equals_the_dense_one():
+    S = W.sparse_rect(37, 23, 4, seed=5, empty_rows=[3], empty_cols=[7])
+    y = W.normal_b(37, 2)
+    a, ra = oracle.bipartite_system(S.dense(), y, 0.25)
+    b, rb = oracle.bipartite_system_sparse(S.m, S.k, S.row_ptr, S.col, S.val, y, 0.25)
+    assert a.n == b.n
+    np.testing.assert_array_equal(a.row_ptr, b.row_ptr)
+    np.testing.assert_array_equal(a.col, b.col)
+    np.testing.assert_array_equal(a.val, b.val)
+    np.testing.assert_array_equal(ra, rb)
