@@ -115,12 +115,14 @@ typedef struct {
                           from the previous sweep's messages (the parallel
                           scheme of section III-C); GABP_SCHEDULE_COLORED: the
                           serial scheme of section III-C in the order of a
-                          two-colouring, for grid plans (checkerboard: one sweep
+                          node colouring: grid plans (checkerboard: one sweep
                           lets every node of colour 0, (x + y + z) even with z
                           counted over the whole stack, send from the newest
-                          messages, then every node of colour 1) and bipartite
-                          batches (chips send, then users).  Other plans
-                          return GABP_ERR_UNSUPPORTED */
+                          messages, then every node of colour 1), bipartite
+                          batches (chips send, then users), lsq plans (x, then
+                          z) and CSR plans in the pair layout (a colouring the
+                          plan computes, see gabp_plan_colors).  Dense batches
+                          and the gather layout return GABP_ERR_UNSUPPORTED */
 } gabp_opts;
 
 enum { GABP_LAYOUT_PAIR = 0, GABP_LAYOUT_GATHER = 1 };
@@ -197,18 +199,33 @@ int gabp_plan_solve(gabp_plan *plan, const double *b, double *x, double *marg_pr
 
 /* Trajectory access (parity checks, checkpoint and resume).
  * reset:     zero all messages and take b (device [n]) as the right-hand side.
- * sweeps:    run exactly `count` synchronous sweeps (no checks, no restarts).
+ * sweeps:    run exactly `count` sweeps of the plan's schedule (no checks, no
+ *            restarts).
  * marginals: mean (device [n]) and precision (device [n] or NULL) from the
  *            current messages.
  * get/set_messages: P and h = P * mu of every directed message i->j at the
  *            CSR slot of A_ij (device [nnz] each, FP64; diagonal slots read
- *            as 0 and are ignored on set). */
+ *            as 0 and are ignored on set).  Coloured CSR plans run on a
+ *            renumbering of A and return GABP_ERR_UNSUPPORTED here.
+ * A coloured CSR plan (gabp_plan_create with GABP_SCHEDULE_COLORED, pair
+ * layout) colours the graph of A on the device (Jones-Plassmann rounds with
+ * fixed pseudo-random priorities and first-fit colours, deterministic; at
+ * most 256 colours, else GABP_ERR_UNSUPPORTED), renumbers the nodes so each
+ * colour is a contiguous range of rows, and lets one colour send per launch:
+ * each node first rebuilds its in-messages from its neighbours' broadcast
+ * totals, then sends from its new totals (the serial scheme of section III-C
+ * in colour order).  b, x and the marginals stay in the caller's order. */
 int gabp_plan_reset(gabp_plan *plan, const double *b, hipStream_t stream);
 int gabp_plan_sweeps(gabp_plan *plan, int32_t count, hipStream_t stream);
 int gabp_plan_marginals(gabp_plan *plan, double *mean, double *prec, hipStream_t stream);
 int gabp_plan_get_messages(gabp_plan *plan, double *P, double *h, hipStream_t stream);
 int gabp_plan_set_messages(gabp_plan *plan, const double *P, const double *h,
                            hipStream_t stream);
+/* The colour of every node under the coloured schedule (device [n], int32, the
+ * caller's node order) and the number of colours (host); colours are
+ * processed in increasing order within a sweep.  Coloured CSR plans and
+ * coloured lsq plans (x: 0, z: 1); GABP_ERR_UNSUPPORTED for other plans. */
+int gabp_plan_colors(gabp_plan *plan, int32_t *colors, int32_t *ncolors, hipStream_t stream);
 
 /* ---- Structured grids: the finite-difference Poisson operators of ----------
  * section IX (5-point in 2-D, 7-point in 3-D), with constant or variable

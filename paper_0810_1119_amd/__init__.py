@@ -22,5 +22,6 @@ from ._abi import (  # noqa: F401
     gabp_model_create, gabp_model_get_params, gabp_model_set_params, gabp_model_forward,
     gabp_model_grad, gabp_model_train_step, gabp_model_grid_features, gabp_model_grid_targets,
     gabp_plan_solve_warm,
-    DeviceRect, gabp_plan_create_lsq, gabp_plan_solve_lsq, gabp_solve_lsq, gabp_plan_residual_lsq,
+    gabp_plan_colors, DeviceRect, gabp_plan_create_lsq, gabp_plan_solve_lsq, gabp_solve_lsq,
+    gabp_plan_residual_lsq,
 )

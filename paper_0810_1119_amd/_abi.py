@@ -30,7 +30,8 @@ GABP_BATCH_BIPARTITE = 0
 GABP_BATCH_DENSE = 1
 
 _NAMES = {v: k for k, v in dict(globals()).items()
-          if k.startswith("GABP_") and not k.startswith(("GABP_LAYOUT", "GABP_BATCH"))
+          if k.startswith("GABP_")
+          and not k.startswith(("GABP_LAYOUT", "GABP_BATCH", "GABP_SCHEDULE"))
           and isinstance(v, int)}
 
 
@@ -94,6 +95,7 @@ _sig = {
     "gabp_solve": (C.c_int, [C.POINTER(_Csr), _vp, _vp, _vp, C.POINTER(Opts), C.POINTER(Stats), _vp]),
     "gabp_residual": (C.c_int, [C.POINTER(_Csr), _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
     "gabp_plan_create": (C.c_int, [C.POINTER(_Csr), C.POINTER(Opts), C.POINTER(_vp), _vp]),
+    "gabp_plan_colors": (C.c_int, [_vp, _vp, C.POINTER(C.c_int32), _vp]),
     "gabp_plan_create_lsq": (C.c_int, [C.POINTER(_Rect), C.c_double, C.POINTER(Opts),
                                        C.POINTER(_vp), _vp]),
     "gabp_plan_solve_lsq": (C.c_int, [_vp, _vp, _vp, C.POINTER(Stats), _vp]),
@@ -314,6 +316,16 @@ def gabp_plan_get_messages(plan, P, h, stream=None) -> int:
 def gabp_plan_set_messages(plan, P, h, stream=None) -> int:
     _check_f64(P, plan.A.nnz, "P"); _check_f64(h, plan.A.nnz, "h")
     return lib.gabp_plan_set_messages(plan.ptr, _ptr(P), _ptr(h), _stream(stream))
+
+
+def gabp_plan_colors(plan, stream=None):
+    """Returns (status, int32 CUDA tensor of node colours or None, colour count)."""
+    import torch
+    n = _lens(plan)[2]
+    colors = torch.empty(n, dtype=torch.int32, device="cuda")
+    nc = C.c_int32(0)
+    rc = lib.gabp_plan_colors(plan.ptr, _ptr(colors), C.byref(nc), _stream(stream))
+    return rc, (colors if rc == GABP_OK else None), nc.value
 
 
 def gabp_plan_create_lsq(S: DeviceRect, psi: float, opts: Opts | None = None, stream=None):

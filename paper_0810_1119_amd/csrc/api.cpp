@@ -287,6 +287,7 @@ int gabp_plan_destroy(gabp_plan *p) {
   delete p->eng;
   if (p->bat) batch_destroy(p->bat);
   if (p->lsq) lsq_destroy(p->lsq);  // after the engine that reads its matrix
+  if (p->perm) perm_destroy(p->perm);
   delete p;
   return GABP_OK;
 }
@@ -296,6 +297,7 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
   clear_stale_error();
   if (p && p->bat) return batch_solve(p->bat, b, x, marg_prec, nullptr, st, s);
   if (!p || !p->eng) return GABP_ERR_ARG;
+  if (p->perm) return perm_solve(p->perm, p->eng, b, x, marg_prec, st, s);
   return engine_solve(p->eng, b, x, marg_prec, st, s);
 }
 
@@ -304,6 +306,7 @@ int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
   if (p && p->bat) return batch_reset(p->bat, b, s);
   if (!p || !p->eng || (p->eng->n > 0 && !b)) return GABP_ERR_ARG;
   if (p->eng->n == 0) return GABP_OK;
+  if (p->perm && !(b = perm_in(p->perm, b, s))) return GABP_ERR_HIP;
   TRY_HIP(launch_fill_zero4(p->eng->sticky, 1, s));
   TRY_HIP(p->eng->reset(b, s));
   TRY_HIP(hipStreamSynchronize(s));
@@ -326,6 +329,7 @@ int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s)
   if (p && p->bat) return batch_marginals(p->bat, mean, prec, s);
   if (!p || !p->eng || (p->eng->n > 0 && !mean)) return GABP_ERR_ARG;
   if (p->eng->n == 0) return GABP_OK;
+  if (p->perm) return perm_marginals(p->perm, p->eng, mean, prec, s);
   TRY_HIP(launch_fill_zero(mean, p->eng->n, s));
   TRY_HIP(p->eng->infer(mean, prec, nullptr, s));
   TRY_HIP(hipStreamSynchronize(s));
@@ -334,16 +338,24 @@ int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s)
 
 int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
   clear_stale_error();
-  if (p && p->bat) return GABP_ERR_UNSUPPORTED;
+  if (p && (p->bat || p->perm)) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
   return p->eng->get_messages(P, h, s);
 }
 
 int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipStream_t s) {
   clear_stale_error();
-  if (p && p->bat) return GABP_ERR_UNSUPPORTED;
+  if (p && (p->bat || p->perm)) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
   return p->eng->set_messages(P, h, s);
+}
+
+int gabp_plan_colors(gabp_plan *p, int32_t *colors, int32_t *ncolors, hipStream_t s) {
+  clear_stale_error();
+  if (!p || !p->eng) return GABP_ERR_ARG;
+  if (p->perm) return perm_colors(p->perm, colors, ncolors, s);
+  if (p->lsq && lsq_coloured(p->lsq)) return lsq_colors(p->lsq, colors, ncolors, s);
+  return GABP_ERR_UNSUPPORTED;
 }
 
 }  // extern "C"

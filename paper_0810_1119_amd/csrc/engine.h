@@ -113,6 +113,7 @@ int engine_solve(Engine *e, const double *b, double *x, double *marg, gabp_stats
                  hipStream_t s, const uint16_t *warm = nullptr);
 
 int check_opts(const gabp_opts *o);  // engine_csr.cpp
+int check_csr(const gabp_csr *A);    // engine_csr.cpp: sizes, pointers, row_ptr ends
 // a CSR plan; classes = row offsets of colour classes (coloured schedule) or
 // NULL (engine_csr.cpp)
 int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int> *classes,
@@ -135,12 +136,29 @@ namespace gabp {
 // the assembled section VII system of an lsq plan (engine_lsq.cpp)
 struct LsqSystem;
 void lsq_destroy(LsqSystem *q);
+bool lsq_coloured(const LsqSystem *q);
+int lsq_colors(const LsqSystem *q, int32_t *colors, int32_t *ncolors, hipStream_t s);
+// the colour-sorted renumbering of a coloured CSR plan (engine_color.cpp)
+struct CsrPerm;
+void perm_destroy(CsrPerm *q);
+int coloured_csr_plan(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s);
+// a coloured CSR plan's vectors in and out of its renumbered order
+// (engine_color.cpp): b into the plan's own buffer (returned), and x / the
+// marginal precisions back from them
+const double *perm_in(CsrPerm *q, const double *b, hipStream_t s);
+int perm_solve(CsrPerm *q, Engine *e, const double *b, double *x, double *marg, gabp_stats *st,
+               hipStream_t s);
+int perm_marginals(CsrPerm *q, Engine *e, double *mean, double *prec, hipStream_t s);
+int perm_colors(const CsrPerm *q, int32_t *colors, int32_t *ncolors, hipStream_t s);
 }  // namespace gabp
 
 // the opaque plan of the C ABI: one system (eng), a batch of dense instances
-// (bat); an lsq plan is a CSR system (eng) over its own assembled matrix (lsq)
+// (bat); an lsq plan is a CSR system (eng) over its own assembled matrix (lsq);
+// a coloured CSR plan runs on a colour-sorted renumbering of the caller's
+// matrix (perm)
 struct gabp_plan {
   gabp::Engine *eng = nullptr;
   gabp::BatchEngine *bat = nullptr;
   gabp::LsqSystem *lsq = nullptr;
+  gabp::CsrPerm *perm = nullptr;
 };

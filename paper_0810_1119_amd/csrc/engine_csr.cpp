@@ -25,6 +25,8 @@ int choose_group(int64_t n, int64_t E) {
 
 bool valid_group(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
 
+}  // namespace
+
 int check_csr(const gabp_csr *A) {
   if (!A || A->n < 0 || A->nnz < 0) return GABP_ERR_ARG;
   if (A->n > 0 && (!A->row_ptr || !A->col || !A->val)) return GABP_ERR_ARG;
@@ -36,8 +38,6 @@ int check_csr(const gabp_csr *A) {
   if (ends[0] != 0 || ends[1] != A->nnz) return GABP_ERR_ARG;
   return GABP_OK;
 }
-
-}  // namespace
 
 int check_opts(const gabp_opts *o) {
   if (!(o->tol >= 0.0) || o->max_sweeps < 0 || o->check_every < 1 || !(o->damping >= 0.0) ||
@@ -208,8 +208,8 @@ struct CsrEngine : Engine {
   }
 
   hipError_t freeze(hipStream_t s) override {
-    hipError_t err = launch_pair_freeze(fp32, group, grid, n, oprt, ocol, acoef, msg[cur],
-                                        sums[cur], coef, hp[cur], Sfix, Hfz[cur], s);
+    hipError_t err = launch_pair_freeze(fp32, group, grid, n, oprt, ocol, colored() ? rev : nullptr,
+                                        acoef, msg[cur], sums[cur], coef, hp[cur], Sfix, Hfz[cur], s);
     frozen = true;
     return err;
   }
@@ -351,7 +351,12 @@ extern "C" {
 
 int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
   clear_stale_error();
-  if (o && o->schedule == GABP_SCHEDULE_COLORED) return GABP_ERR_UNSUPPORTED;
+  if (!plan) return GABP_ERR_ARG;
+  if (o && o->schedule == GABP_SCHEDULE_COLORED) {
+    if (o->layout != GABP_LAYOUT_PAIR) return GABP_ERR_UNSUPPORTED;
+    int st = check_opts(o);
+    return st ? st : coloured_csr_plan(A, o, plan, s);
+  }
   return csr_plan_create(A, o, nullptr, plan, s);
 }
 

@@ -1,6 +1,7 @@
 // Section VII for any sparse matrix: the plan assembles the symmetric
 // bipartite system R = [[I_k, S^T], [S, -psi I_m]] on the device
 // (kernels_lsq.hip) and solves R [x; z] = [0; y] as an ordinary CSR plan.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -20,6 +21,7 @@ struct LsqSystem {
   double *bt = nullptr, *xt = nullptr;  // [0; y] and [x; z] of a solve
   double *u = nullptr, *part = nullptr; // normal-equations residual scratch
   int nparts = 1;
+  bool coloured = false;
 
   ~LsqSystem() {
     void *bufs[] = {Arp, Acol, Aval, bt, xt, u, part};
@@ -29,6 +31,21 @@ struct LsqSystem {
 };
 
 void lsq_destroy(LsqSystem *q) { delete q; }
+
+bool lsq_coloured(const LsqSystem *q) { return q->coloured; }
+
+// x rows colour 0, z rows colour 1
+int lsq_colors(const LsqSystem *q, int32_t *colors, int32_t *ncolors, hipStream_t s) {
+  if (ncolors) *ncolors = (q->k > 0) + (q->m > 0);
+  const int64_t n = (int64_t)q->k + q->m;
+  if (colors && n > 0) {
+    std::vector<int32_t> h((size_t)n, 1);
+    std::fill(h.begin(), h.begin() + q->k, 0);
+    TRY_HIP(hipMemcpyAsync(colors, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    TRY_HIP(hipStreamSynchronize(s));
+  }
+  return GABP_OK;
+}
 
 namespace {
 
@@ -152,6 +169,7 @@ int gabp_plan_create_lsq(const gabp_rect *S, double psi, const gabp_opts *o, gab
     delete q;
     return rc;
   }
+  q->coloured = coloured;
   p->lsq = q;
   *plan = p;
   return GABP_OK;

@@ -17,6 +17,7 @@ enum : uint32_t {
   FLAG_ASYM = 4u,        // pattern or value asymmetry (plan build)
   FLAG_ZERO_DIAG = 8u,   // missing or zero diagonal (plan build)
   FLAG_ARG = 16u,        // malformed CSR or non-finite value (plan build)
+  FLAG_UNSUPPORTED = 32u, // a limit of the implementation (plan build)
 };
 
 // Why an inner solve stopped (written by the device-side controller).
@@ -187,9 +188,11 @@ hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s);
 hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfix, const void *Hfz,
                              double *xacc, double *marg, void *means, uint32_t *sticky,
                              hipStream_t s);
-hipError_t launch_pair_freeze(bool fp32, int group, int grid, int n, const int32_t *oprt, const int32_t *ocol,
-                              const void *acoef, const void *msg, const void *sums, void *coef,
-                              void *hp, void *Sfix, void *Hfz, hipStream_t s);
+// rev: NULL, or the reverse-slot index (coloured plans; see k_pair_freeze)
+hipError_t launch_pair_freeze(bool fp32, int group, int grid, int n, const int32_t *oprt,
+                              const int32_t *ocol, const int32_t *rev, const void *acoef,
+                              const void *msg, const void *sums, void *coef, void *hp, void *Sfix,
+                              void *Hfz, hipStream_t s);
 hipError_t launch_frozen_restart(bool fp32, int64_t E, int n, void *hp, const void *rhs, void *Hfz,
                                  hipStream_t s);
 hipError_t launch_pair_io(bool fp32, bool get, int n, const int64_t *rp, const int64_t *diagpos,
@@ -286,6 +289,33 @@ hipError_t launch_to_working(bool fp32, int64_t m, const double *in, void *out, 
 hipError_t launch_grid_zero_h(bool fp32, int64_t m, void *msg, hipStream_t s);
 hipError_t launch_grid_io(bool fp32, bool get, int64_t m, void *msg, double *P, double *h,
                           hipStream_t s);
+
+// ---- colouring and renumbering for coloured CSR plans (kernels_color.hip) ----
+constexpr int kMaxColors = 256;
+// one Jones-Plassmann round (color < 0: not yet coloured); *left += nodes
+// still uncoloured after it; FLAG_UNSUPPORTED if a node needs more colours
+hipError_t launch_jp_round(int n, const int64_t *rp, const int32_t *col, int32_t *color,
+                           uint32_t *left, uint32_t *flags, hipStream_t s);
+hipError_t launch_color_max(int n, const int32_t *color, int32_t *out, hipStream_t s);
+hipError_t launch_iota(int n, int32_t *v, hipStream_t s);
+// stable sort of the nodes by colour: new2old (tmp == NULL: only *bytes)
+hipError_t launch_color_sort(int n, int ncolors, const int32_t *color, uint32_t *keys_out,
+                             const int32_t *idx, int32_t *new2old, void *tmp, size_t *bytes,
+                             hipStream_t s);
+// old2new and the first new row of each colour present (first[] preset to -1)
+hipError_t launch_perm_finish(int n, const uint32_t *keys, const int32_t *new2old,
+                              int32_t *old2new, int32_t *first, hipStream_t s);
+hipError_t launch_perm_rowlen(int n, const int64_t *rp, const int32_t *new2old, int64_t *len,
+                              hipStream_t s);
+hipError_t launch_perm_fill(int n, const int64_t *rp, const int32_t *col, const double *val,
+                            const int32_t *new2old, const int32_t *old2new, const int64_t *rp2,
+                            int32_t *col2, double *val2, hipStream_t s);
+hipError_t launch_rows_sort(int n, int64_t nnz, const int64_t *rp, const int32_t *col_in,
+                            int32_t *col_out, const double *val_in, double *val_out, void *tmp,
+                            size_t *bytes, hipStream_t s);
+// to_new: out[r] = in[new2old[r]]; else out[new2old[r]] = in[r]
+hipError_t launch_permute(int n, const int32_t *new2old, const double *in, double *out,
+                          bool to_new, hipStream_t s);
 
 // ---- section VII for any sparse S (kernels_lsq.hip) ----
 // validation of S, row lengths of R (k + m, int64), column counts, the row

@@ -18,7 +18,9 @@
 //
 // Once every precision message has stopped changing (it never depends on b),
 // the "frozen" kernels keep P fixed and iterate the information only, with
-// per-slot coefficients c_ij = -A_ij / (S_i - P_ji):
+// per-slot coefficients c_ij = -A_ij / (S_i - P_ji) (formed as -A_ij times the
+// reciprocal, exactly as the full sweeps form the factor of h, so that a
+// message computed before and after the switch rounds the same way):
 //   h_ij' = c_ij (H_i - h_ji),  h_ji' = c_ji (H_j - h_ij),  H_i' = b_i + sum h_ji'.
 // The gather then reads H_j alone (4 bytes per node).
 #include "device_common.h"
@@ -73,8 +75,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
       const T ci = si.x - m.z;  // S_i - P_ji: cavity of i toward j
       zero |= (cj == T(0)) | (ci == T(0));
       const T ij = T(1) / cj, ii = T(1) / ci;
-      T Pin = -(a * a) * ij, hin = -(a * (sj.y - m.y)) * ij;
-      T Pout = -(a * a) * ii, hout = -(a * (si.y - m.w)) * ii;
+      T Pin = -(a * a) * ij, hin = (-a * ij) * (sj.y - m.y);
+      T Pout = -(a * a) * ii, hout = (-a * ii) * (si.y - m.w);
       if (DAMP) {
         const T b1 = T(1) - alpha;
         Pin = alpha * m.z + b1 * Pin;
@@ -187,10 +189,16 @@ __global__ void k_pair_infer(int n, const typename Vec2<T>::type *__restrict__ s
 // ---------------------------------------------------------------------------
 // freeze: P has stopped changing; derive the fixed coefficients
 // ---------------------------------------------------------------------------
+// rev != NULL (coloured plans): the in-message coefficient c_ji is computed
+// from the sender's own copy of P_ij (its slot's received part), the operands
+// the sender uses for its out-coefficient.  In a synchronous state every pair
+// of copies is equal; in a coloured one a row that sent after j holds a newer
+// P_ij than the one j used, and the two copies of c_ji must still agree.
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_pair_freeze(
     int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
-    const T *__restrict__ acoef, const typename Vec4<T>::type *__restrict__ msg,
+    const int32_t *__restrict__ rev, const T *__restrict__ acoef,
+    const typename Vec4<T>::type *__restrict__ msg,
     const typename Vec2<T>::type *__restrict__ sums, typename Vec2<T>::type *__restrict__ coef,
     typename Vec2<T>::type *__restrict__ hp, T *__restrict__ Sfix, T *__restrict__ Hfz) {
 #pragma clang fp contract(off)
@@ -205,8 +213,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_freeze(
       const T a = acoef[e];
       const auto m = msg[e];
       typename Vec2<T>::type c, h;
-      c.x = -a / (Si - m.z);          // c_ij: out-message coefficient
-      c.y = -a / (sums[j].x - m.x);   // c_ji: in-message coefficient
+      c.x = -a * (T(1) / (Si - m.z));  // c_ij: out-message coefficient
+      const T Pij = rev ? msg[rev[e]].z : m.x;  // P_ij as the sender j holds it
+      c.y = -a * (T(1) / (sums[j].x - Pij));  // c_ji: in-message coefficient
       h.x = m.y;
       h.y = m.w;
       coef[e] = c;
@@ -350,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_col(
         zero |= cj == T(0);
         const T ij = T(1) / cj;
         Pin = -(a * a) * ij;
-        hin = -(a * (sj.y - m.y)) * ij;
+        hin = (-a * ij) * (sj.y - m.y);
         if (DAMP) {
           Pin = alpha * m.z + b1 * Pin;
           hin = alpha * m.w + b1 * hin;
@@ -389,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_col(
           const V2 sj = sums[j];
           const T ij = T(1) / (sj.x - m.x);
           Pin = -(a * a) * ij;
-          hin = -(a * (sj.y - m.y)) * ij;
+          hin = (-a * ij) * (sj.y - m.y);
           if (DAMP) {
             Pin = alpha * m.z + b1 * Pin;
             hin = alpha * m.w + b1 * hin;
@@ -399,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_col(
       const T ci = S - Pin;
       zero |= ci == T(0);
       const T ii = T(1) / ci;
-      T Pout = -(a * a) * ii, hout = -(a * (H - hin)) * ii;
+      T Pout = -(a * a) * ii, hout = (-a * ii) * (H - hin);
       if (DAMP) {
         Pout = alpha * m.x + b1 * Pout;
         hout = alpha * m.y + b1 * hout;
@@ -561,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_col_infer(
           const V2 sj = sums[j];
           const T ij = T(1) / (sj.x - m.x);
           Pin = -(a * a) * ij;
-          hin = -(a * (sj.y - m.y)) * ij;
+          hin = (-a * ij) * (sj.y - m.y);
           if (DAMP) {
             Pin = alpha * m.z + b1 * Pin;
             hin = alpha * m.w + b1 * hin;
@@ -731,14 +740,15 @@ hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfi
 
 template <typename T>
 static hipError_t freeze_t(int group, int nblk, int n, const int32_t *oprt, const int32_t *ocol,
-                           const void *acoef, const void *msg, const void *sums, void *coef,
-                           void *hp, void *Sfix, void *Hfz, hipStream_t s) {
+                           const int32_t *rev, const void *acoef, const void *msg,
+                           const void *sums, void *coef, void *hp, void *Sfix, void *Hfz,
+                           hipStream_t s) {
   using V4 = typename Vec4<T>::type;
   using V2 = typename Vec2<T>::type;
   const dim3 grid(nblk);
 #define FREEZE_CASE(GG)                                                                          \
   case GG:                                                                                       \
-    hipLaunchKernelGGL((k_pair_freeze<T, GG>), grid, dim3(kBlock), 0, s, n, oprt, ocol,        \
+    hipLaunchKernelGGL((k_pair_freeze<T, GG>), grid, dim3(kBlock), 0, s, n, oprt, ocol, rev,   \
                        (const T *)acoef, (const V4 *)msg, (const V2 *)sums, (V2 *)coef, (V2 *)hp, \
                        (T *)Sfix, (T *)Hfz);                                                     \
     break;
@@ -751,12 +761,14 @@ static hipError_t freeze_t(int group, int nblk, int n, const int32_t *oprt, cons
 }
 
 hipError_t launch_pair_freeze(bool fp32, int group, int grid, int n, const int32_t *oprt,
-                              const int32_t *ocol, const void *acoef, const void *msg,
-                              const void *sums, void *coef, void *hp, void *Sfix, void *Hfz,
-                              hipStream_t s) {
+                              const int32_t *ocol, const int32_t *rev, const void *acoef,
+                              const void *msg, const void *sums, void *coef, void *hp, void *Sfix,
+                              void *Hfz, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  return fp32 ? freeze_t<float>(group, grid, n, oprt, ocol, acoef, msg, sums, coef, hp, Sfix, Hfz, s)
-              : freeze_t<double>(group, grid, n, oprt, ocol, acoef, msg, sums, coef, hp, Sfix, Hfz, s);
+  return fp32 ? freeze_t<float>(group, grid, n, oprt, ocol, rev, acoef, msg, sums, coef, hp, Sfix,
+                                Hfz, s)
+              : freeze_t<double>(group, grid, n, oprt, ocol, rev, acoef, msg, sums, coef, hp, Sfix,
+                                 Hfz, s);
 }
 
 hipError_t launch_frozen_restart(bool fp32, int64_t E, int n, void *hp, const void *rhs, void *Hfz,

@@ -251,3 +251,22 @@ def test_lsq_large_sparse_tall(G):
               f"normal-equations residual {rel:.1e}", flush=True)
     finally:
         G.gabp_plan_destroy(plan)
+
+
+def test_coloured_settled_phase_stays_consistent(G):
+    """Regression: the coloured schedule rebuilds in-messages from the senders'
+    broadcasts, which is exact only while every rebuilt value rounds like the
+    sent one; an inconsistency (the settled-phase coefficients once rounded
+    differently from the full sweeps' factors) is not damped by the iteration
+    and grew from FP32 rounding to overflow within ~30 settled sweeps.  One
+    long FP32 pass must stay at the message precision's floor."""
+    m, k = 1 << 18, 1 << 16
+    S = W.sparse_rect(m, k, 8, seed=0)
+    y = dev(W.normal_b(m, 0))
+    R = _rect(G, S)
+    for sweeps in (24, 64):
+        x = torch.zeros(k, dtype=torch.float64, device="cuda")
+        rc, st = G.gabp_solve_lsq(R, 0.1, y, x, G.gabp_default_opts(
+            schedule=G.GABP_SCHEDULE_COLORED, max_restarts=0, max_sweeps=sweeps, inner_tol=1e-30))
+        assert rc in (G.GABP_OK, G.GABP_NOT_CONVERGED), G.status_name(rc)
+        assert st.frozen_sweeps > 0 and st.rel_residual < 1e-5, (sweeps, st.rel_residual)
