@@ -44,10 +44,11 @@ def parse():
                     help="settled-precision threshold (0 = library default)")
     ap.add_argument("--grid", type=int, default=0, help="sweep grid cap (0 = library default)")
     ap.add_argument("--schedule", choices=["sync", "colored"], default=None,
-                    help="message schedule of the two-colourable workloads; default colored "
-                         "for c3 and c4 (undamped: half the sweeps) and sync for c5 (with "
-                         "damping 0.5 the coloured schedule saves only a quarter of the sweeps "
-                         "and loses the cache reuse of the damping reads); c2 is synchronous")
+                    help="message schedule; default colored for c3, c4 and lsq (two-colourable, "
+                         "undamped: about half the sweeps), sync for c5 (with damping 0.5 the "
+                         "coloured schedule saves only a quarter of the sweeps and loses the "
+                         "cache reuse of the damping reads) and c2 (its colouring needs 8 "
+                         "colours, one launch each: 14 instead of 20 sweeps at the same time)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte "
                          "counters) and print its bandwidth")
