@@ -430,3 +430,22 @@ def test_sparse_bipartite_construction_equals_the_dense_one():
     np.testing.assert_array_equal(a.col, b.col)
     np.testing.assert_array_equal(a.val, b.val)
     np.testing.assert_array_equal(ra, rb)
+
+
+@pytest.mark.parametrize("m,k,per_row", [(50, 10, 8), (64, 3, 5), (30, 200, 7), (0, 5, 2), (9, 0, 3)])
+def test_sparse_rect_generator_structure(m, k, per_row):
+    # rows hold distinct sorted columns in range, nothing lands in an empty
+    # row or column, and the values are finite and nonzero
+    er = [r for r in (0, 4) if r < m]
+    ec = [c for c in (1,) if c < k]
+    S = W.sparse_rect(m, k, per_row, seed=11, empty_rows=er, empty_cols=ec)
+    assert S.row_ptr[0] == 0 and S.row_ptr[-1] == S.col.size == S.val.size
+    allowed = max(k - len(ec), 0)
+    for j in range(m):
+        c = S.col[S.row_ptr[j]:S.row_ptr[j + 1]]
+        want = 0 if j in er else min(per_row, allowed)
+        assert c.size == want
+        assert np.all(np.diff(c) > 0)
+        assert np.all((c >= 0) & (c < k))
+        assert not np.isin(c, ec).any()
+    assert np.all(np.isfinite(S.val)) and np.all(S.val != 0.0)

@@ -519,19 +519,25 @@ def sparse_rect(m: int, k: int, per_row: int, seed: int, signs: bool = False,
     empty and no entry falls in a column of `empty_cols`."""
     rng = np.random.default_rng([seed, 0x5EC7])
     allowed = np.setdiff1d(np.arange(k), np.asarray(empty_cols, dtype=np.int64))
-    skip = set(int(j) for j in empty_rows)
+    p = min(per_row, allowed.size)
+    keep = np.ones(m, dtype=bool)
+    keep[np.asarray(list(empty_rows), dtype=np.int64)] = False
+    if p == 0:
+        keep[:] = False
+    if p == allowed.size:
+        idx = np.tile(np.arange(p), (m, 1))
+    else:
+        idx = np.sort(rng.integers(0, allowed.size, size=(m, p)), axis=1)
+        bad = np.nonzero((np.diff(idx, axis=1) == 0).any(axis=1))[0] if p > 1 else np.zeros(0, int)
+        while bad.size:  # redraw rows with a repeated column
+            idx[bad] = np.sort(rng.integers(0, allowed.size, size=(bad.size, p)), axis=1)
+            sub = (np.diff(idx[bad], axis=1) == 0).any(axis=1)
+            bad = bad[sub]
+    v = rng.choice([-1.0, 1.0], size=(m, p)) if signs else rng.standard_normal((m, p))
+    v = np.where(v == 0.0, 1.0, v) / np.sqrt(max(per_row, 1))
+    counts = np.where(keep, p, 0)
     rp = np.zeros(m + 1, dtype=np.int64)
-    cols, vals = [], []
-    for j in range(m):
-        if j in skip or allowed.size == 0:
-            rp[j + 1] = rp[j]
-            continue
-        c = np.sort(rng.choice(allowed, size=min(per_row, allowed.size), replace=False))
-        v = rng.choice([-1.0, 1.0], c.size) if signs else rng.standard_normal(c.size)
-        v = np.where(v == 0.0, 1.0, v) / np.sqrt(per_row)
-        cols.append(c)
-        vals.append(v)
-        rp[j + 1] = rp[j] + c.size
-    col = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
-    val = np.concatenate(vals) if vals else np.zeros(0)
+    np.cumsum(counts, out=rp[1:])
+    col = allowed[idx[keep]].reshape(-1).astype(np.int32)
+    val = v[keep].reshape(-1)
     return SparseRect(m, k, rp, col, val)
