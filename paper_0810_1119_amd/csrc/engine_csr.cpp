@@ -55,6 +55,7 @@ struct CsrEngine : Engine {
   bool pair = true;
   int group = 8;
   int grid = 1;       // blocks of a row-kernel launch
+  int sgrid = 1;      // blocks of a synchronous pair sweep
   int32_t *oprt = nullptr, *ocol = nullptr, *rev = nullptr;
   int64_t *diagpos = nullptr;
   void *acoef = nullptr, *diag = nullptr, *rhs = nullptr;
@@ -79,6 +80,9 @@ struct CsrEngine : Engine {
   size_t msg_bytes() const { return (pair ? 4 : 2) * tsz; }
 
   bool colored() const { return !cls.empty(); }
+
+  // lane group of the aggregation: the sweeps' summation order (0: slot order)
+  int agg_group() const { return colored() ? group : 0; }
 
   hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
     hipError_t err;
@@ -110,7 +114,7 @@ struct CsrEngine : Engine {
       err = launch_sweep(a, s);
     } else {
       PairArgs a{};
-      a.grid = grid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
+      a.grid = sgrid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
       a.frozen = frozen; a.n = n; a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
       a.rhs = rhs; a.alpha = o.damping; a.xprev = xprev; a.part = part; a.sticky = sticky;
       a.ctl = c;
@@ -166,7 +170,7 @@ struct CsrEngine : Engine {
     // one half sweep old; make every copy the sender's current message
     if (colored() && (err = launch_pair_sync_in(fp32, E, rev, msg[cur], s)) != hipSuccess)
       return err;
-    return launch_pair_aggregate(fp32, group, grid, n, oprt, diag, rhs, msg[cur], sums[cur], s);
+    return launch_pair_aggregate(fp32, agg_group(), grid, n, oprt, diag, rhs, msg[cur], sums[cur], s);
   }
 
   hipError_t reset(const double *b, hipStream_t s) override {
@@ -180,7 +184,7 @@ struct CsrEngine : Engine {
     if ((err = launch_residual(fp32, group, nsum, n, A.row_ptr, A.col, A.val, b, nullptr, rhs,
                                nullptr, sumpart, s)) != hipSuccess)
       return err;
-    if (pair) return launch_pair_aggregate(fp32, group, grid, n, oprt, diag, rhs, msg[0], sums[0], s);
+    if (pair) return launch_pair_aggregate(fp32, agg_group(), grid, n, oprt, diag, rhs, msg[0], sums[0], s);
     return hipSuccess;
   }
 
@@ -230,7 +234,7 @@ struct CsrEngine : Engine {
     if (pair) {
       TRY_HIP(launch_pair_io(fp32, false, n, A.row_ptr, diagpos, oprt, rev, msg[cur], (double *)P,
                              (double *)h, s));
-      TRY_HIP(launch_pair_aggregate(fp32, group, grid, n, oprt, diag, rhs, msg[cur], sums[cur], s));
+      TRY_HIP(launch_pair_aggregate(fp32, agg_group(), grid, n, oprt, diag, rhs, msg[cur], sums[cur], s));
     } else {
       TRY_HIP(launch_set_msgs(fp32, n, A.row_ptr, diagpos, oprt, msg[cur], P, h, s));
     }
@@ -269,7 +273,8 @@ struct CsrEngine : Engine {
     if ((st = from_hip(hipMemcpyAsync(&e, oprt64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s))) ||
         (st = from_hip(hipStreamSynchronize(s))))
       return fail(st);
-    if (e >= (int64_t)INT32_MAX) return fail(GABP_ERR_UNSUPPORTED);
+    // slot indices stay in int32 with a chunk of headroom
+    if (e >= (int64_t)INT32_MAX - 4096) return fail(GABP_ERR_UNSUPPORTED);
     E = e;
     if ((st = from_hip(dalloc(&oprt, n + 1, sizeof(int32_t)))) ||
         (st = from_hip(dalloc(&ocol, E, sizeof(int32_t)))) ||
@@ -317,7 +322,8 @@ int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int
   e->group = opts.group ? opts.group : choose_group(e->n, e->E);
   const int cap = opts.grid_blocks > 0 ? opts.grid_blocks : kMaxSweepBlocks;
   e->grid = sweep_blocks(std::max(e->n, 1), e->group, cap);
-  e->nparts = e->grid;
+  e->sgrid = pair_sweep_blocks(std::max(e->n, 1), cap);
+  e->nparts = e->pair ? e->sgrid : e->grid;
   if (classes) {
     // every class launch has the same blocks, so a check's partials line up
     e->cls = *classes;

@@ -147,7 +147,7 @@ hipError_t launch_set_msgs(bool fp32, int n, const int64_t *rp, const int64_t *d
 
 // ---- pair layout (kernels_pair.hip) ----
 struct PairArgs {
-  int grid;            // blocks of the launch (sweep_blocks)
+  int grid;            // blocks of the launch (synchronous: pair_sweep_blocks; coloured: sweep_blocks)
   bool fp32;
   int group;
   int mode;            // 0 sweep, 1 sweep + check
@@ -174,6 +174,8 @@ struct PairArgs {
   bool first;  // first sweep since the messages were set, not sent
 };
 hipError_t launch_pair_sweep(const PairArgs &a, hipStream_t s);
+// blocks of a synchronous pair sweep over n rows (row blocks of fixed size)
+int pair_sweep_blocks(int n, int cap = kMaxSweepBlocks);
 // marginals of one class (rows [row0, row1)) of a coloured pair plan from its
 // current messages after a complete sweep (msg_in / sums_in: the full state,
 // or in the settled state the information pairs and H broadcasts, with coef
@@ -182,6 +184,8 @@ hipError_t launch_pair_col_infer(const PairArgs &a, double *xacc, double *marg, 
                                  hipStream_t s);
 // msg[e].P_ji := msg[rev[e]].P_ij for every slot (pair layout)
 hipError_t launch_pair_sync_in(bool fp32, int64_t E, const int32_t *rev, void *msg, hipStream_t s);
+// (S, H) from the stored in-messages; group 0: a row's in-messages added in
+// slot order (the synchronous sweeps' order), else in that lane group's order
 hipError_t launch_pair_aggregate(bool fp32, int group, int grid, int n, const int32_t *oprt, const void *diag,
                                  const void *rhs, const void *msg, void *sums, hipStream_t s);
 hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s);

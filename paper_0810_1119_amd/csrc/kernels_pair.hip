@@ -32,13 +32,35 @@ template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 
 // ---------------------------------------------------------------------------
-// full sweep (P and h), MODE 0 = sweep, 1 = sweep + check
+// synchronous sweeps: row blocks, slots streamed in chunks
 // ---------------------------------------------------------------------------
-template <typename T, int G, int MODE, bool DAMP>
+// A block takes kSegRows consecutive rows and streams their slots in chunks of
+// kSegChunk: thread t handles slots c + t, c + t + kBlock, ... of the chunk
+// (coalesced, every lane busy whatever the row lengths, kSegK independent
+// gathers in flight per thread), finds each slot's row by a binary search of
+// the block's row offsets in LDS, writes the slot and leaves its in-message
+// in LDS; then the row's own thread adds its in-messages in slot order.
+constexpr int kSegRows = 128;
+constexpr int kSegK = 4;
+constexpr int kSegChunk = kBlock * kSegK;
+
+// the row of slot e: the last r with rp[r] <= e (rp[0] <= e < rp[nr])
+__device__ __forceinline__ int seg_row(const int *rp, int nr, int e) {
+  int lo = 0, hi = nr;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rp[mid] <= e) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// full sweep (P and h), MODE 0 = sweep, 1 = sweep + check
+template <typename T, int MODE, bool DAMP>
 __global__ __launch_bounds__(kBlock) void k_pair_sweep(
     int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
     const T *__restrict__ acoef, const T *__restrict__ diag, const T *__restrict__ rhs,
-    const typename Vec4<T>::type *__restrict__ min, typename Vec4<T>::type *__restrict__ mout,
+    const typename Vec4<T>::type *__restrict__ mi, typename Vec4<T>::type *__restrict__ mo,
     const typename Vec2<T>::type *__restrict__ sin, typename Vec2<T>::type *__restrict__ sout,
     T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky,
     const Ctl *__restrict__ ctl) {
@@ -47,85 +69,133 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
 #pragma clang fp contract(off)
   using V4 = typename Vec4<T>::type;
   using V2 = typename Vec2<T>::type;
-  constexpr int RPB = kBlock / G;  // rows per block per iteration
+  __shared__ int rp[kSegRows + 1];
+  __shared__ V2 own[kSegRows];   // the block's rows' broadcasts of round t
+  __shared__ V2 in[kSegChunk];   // the chunk's new in-messages (P_ji, h_ji)
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
-  const int lane = threadIdx.x % G;
-  double d = 0.0, ax = 0.0, dpb = 0.0, pmb = 0.0;
+  const int t = threadIdx.x;
+  const T b1 = T(1) - alpha;
+  double d = 0.0, ax = 0.0;
+  T dp = T(0), pm = T(0);
   bool zero = false;
   uint32_t f = 0;
-  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
-    const int row = base + threadIdx.x / G;
-    const bool active = row < n;
-    int beg = 0, end = 0;
-    V2 si;
-    si.x = T(0);
-    si.y = T(0);
-    if (active) {
-      beg = oprt[row];
-      end = oprt[row + 1];
-      si = sin[row];
-    }
-    T S = T(0), H = T(0), dp = T(0), pm = T(0);
-    for (int e = beg + lane; e < end; e += G) {
-      const int j = ocol[e];
-      const T a = acoef[e];
-      const V4 m = min[e];      // (P_ij, h_ij, P_ji, h_ji) of round t
-      const V2 sj = sin[j];     // broadcast of node j, round t
-      const T cj = sj.x - m.x;  // S_j - P_ij: cavity of j toward i
-      const T ci = si.x - m.z;  // S_i - P_ji: cavity of i toward j
-      zero |= (cj == T(0)) | (ci == T(0));
-      const T ij = T(1) / cj, ii = T(1) / ci;
-      T Pin = -(a * a) * ij, hin = (-a * ij) * (sj.y - m.y);
-      T Pout = -(a * a) * ii, hout = (-a * ii) * (si.y - m.w);
-      if (DAMP) {
-        const T b1 = T(1) - alpha;
-        Pin = alpha * m.z + b1 * Pin;
-        hin = alpha * m.w + b1 * hin;
-        Pout = alpha * m.x + b1 * Pout;
-        hout = alpha * m.y + b1 * hout;
-      }
-      if (MODE == 1) {
-        dp = fmax(dp, fabs(Pout - m.x));
-        pm = fmax(pm, fabs(Pout));
-      }
-      V4 o;
-      o.x = Pout; o.y = hout; o.z = Pin; o.w = hin;
-      mout[e] = o;
-      S += Pin;
-      H += hin;
-    }
-    S = gsum<G>(S);
-    H = gsum<G>(H);
-    if (active) {
-      S += diag[row];
-      H += rhs[row];
-      if (lane == 0) {
-        V2 o;
-        o.x = S;
-        o.y = H;
-        sout[row] = o;
-        if (MODE == 1) {
-          if (S == T(0)) f |= FLAG_BREAKDOWN;
-          const T x = H / S;
-          if (!isfinite(x)) f |= FLAG_NONFINITE;
-          d = fmax(d, (double)fabs(x - xprev[row]));
-          xprev[row] = x;
-          ax = fmax(ax, (double)fabs(x));
+  for (int r0 = blockIdx.x * kSegRows; r0 < n; r0 += gridDim.x * kSegRows) {
+    const int nr = min(kSegRows, n - r0);
+    __syncthreads();  // the previous rows' readers are done with the LDS
+    for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
+    for (int k = t; k < nr; k += kBlock) own[k] = sin[r0 + k];
+    __syncthreads();
+    const int e0 = rp[0], e1 = rp[nr];
+    T S = T(0), H = T(0);
+    for (int c = e0; c < e1; c += kSegChunk) {
+      int j[kSegK];
+      T a[kSegK];
+      V4 m[kSegK];
+      V2 sj[kSegK];
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        j[k] = 0;
+        a[k] = T(0);
+        m[k] = V4{};
+        if (e < e1) {
+          j[k] = ocol[e];
+          a[k] = acoef[e];
+          m[k] = mi[e];  // (P_ij, h_ij, P_ji, h_ji) of round t
         }
       }
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        sj[k] = V2{};
+        if (c + k * kBlock + t < e1) sj[k] = sin[j[k]];  // broadcast of node j, round t
+      }
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        if (e >= e1) continue;
+        const V2 si = own[seg_row(rp, nr, e)];
+        const T cj = sj[k].x - m[k].x;  // S_j - P_ij: cavity of j toward i
+        const T ci = si.x - m[k].z;     // S_i - P_ji: cavity of i toward j
+        zero |= (cj == T(0)) | (ci == T(0));
+        const T ij = T(1) / cj, ii = T(1) / ci;
+        const T aa = a[k];
+        T Pin = -(aa * aa) * ij, hin = (-aa * ij) * (sj[k].y - m[k].y);
+        T Pout = -(aa * aa) * ii, hout = (-aa * ii) * (si.y - m[k].w);
+        if (DAMP) {
+          Pin = alpha * m[k].z + b1 * Pin;
+          hin = alpha * m[k].w + b1 * hin;
+          Pout = alpha * m[k].x + b1 * Pout;
+          hout = alpha * m[k].y + b1 * hout;
+        }
+        if (MODE == 1) {
+          dp = fmax(dp, fabs(Pout - m[k].x));
+          pm = fmax(pm, fabs(Pout));
+        }
+        V4 o;
+        o.x = Pout; o.y = hout; o.z = Pin; o.w = hin;
+        mo[e] = o;
+        V2 v;
+        v.x = Pin;
+        v.y = hin;
+        in[e - c] = v;
+      }
+      __syncthreads();
+      if (t < nr) {
+        const int lo = max(rp[t], c), hi = min(rp[t + 1], c + kSegChunk);
+        for (int e = lo; e < hi; ++e) {
+          S += in[e - c].x;
+          H += in[e - c].y;
+        }
+      }
+      __syncthreads();
     }
-    if (MODE == 1) {
-      dpb = fmax(dpb, (double)dp);
-      pmb = fmax(pmb, (double)pm);
+    if (t < nr) {
+      const int row = r0 + t;
+      S += diag[row];
+      H += rhs[row];
+      V2 o;
+      o.x = S;
+      o.y = H;
+      sout[row] = o;
+      if (MODE == 1) {
+        if (S == T(0)) f |= FLAG_BREAKDOWN;
+        const T x = H / S;
+        if (!isfinite(x)) f |= FLAG_NONFINITE;
+        d = fmax(d, (double)fabs(x - xprev[row]));
+        xprev[row] = x;
+        ax = fmax(ax, (double)fabs(x));
+      }
     }
   }
   if (zero) f |= FLAG_BREAKDOWN;
   if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(d, ax, dpb, pmb, part);
+  if (MODE == 1) block_publish(d, ax, (double)dp, (double)pm, part);
 }
 
 // Aggregate (S, H) from the slots' incoming messages: used after reset,
-// message import and restarts.
+// message import and restarts.  Synchronous plans add a row's in-messages in
+// slot order, one thread per row (k_pair_aggregate_seq), exactly as their
+// sweeps do, so that imported messages resume a solve bit for bit; coloured
+// plans use the lane-group order of their sweeps.
+template <typename T>
+__global__ void k_pair_aggregate_seq(int n, const int32_t *__restrict__ oprt,
+                                     const T *__restrict__ diag, const T *__restrict__ rhs,
+                                     const typename Vec4<T>::type *__restrict__ msg,
+                                     typename Vec2<T>::type *__restrict__ sums) {
+#pragma clang fp contract(off)
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  T S = T(0), H = T(0);
+  for (int e = oprt[row]; e < oprt[row + 1]; ++e) {
+    S += msg[e].z;
+    H += msg[e].w;
+  }
+  typename Vec2<T>::type o;
+  o.x = S + diag[row];
+  o.y = H + rhs[row];
+  sums[row] = o;
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_pair_aggregate(
     int n, const int32_t *__restrict__ oprt, const T *__restrict__ diag, const T *__restrict__ rhs,
@@ -228,8 +298,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_freeze(
   }
 }
 
-// frozen sweep: information only.  MODE 0 = sweep, 1 = sweep + check.
-template <typename T, int G, int MODE, bool DAMP>
+// frozen sweep: information only, row blocks as in the full sweep.
+// MODE 0 = sweep, 1 = sweep + check.
+template <typename T, int MODE, bool DAMP>
 __global__ __launch_bounds__(kBlock) void k_pair_frozen(
     int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
     const typename Vec2<T>::type *__restrict__ coef, const T *__restrict__ rhs,
@@ -239,51 +310,77 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen(
     const Ctl *__restrict__ ctl) {
 #pragma clang fp contract(off)
   using V2 = typename Vec2<T>::type;
-  constexpr int RPB = kBlock / G;
+  __shared__ int rp[kSegRows + 1];
+  __shared__ T own[kSegRows];
+  __shared__ T in[kSegChunk];
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
-  const int lane = threadIdx.x % G;
+  const int t = threadIdx.x;
+  const T b1 = T(1) - alpha;
   double d = 0.0, ax = 0.0;
   uint32_t f = 0;
-  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
-    const int row = base + threadIdx.x / G;
-    const bool active = row < n;
-    int beg = 0, end = 0;
-    T Hi = T(0);
-    if (active) {
-      beg = oprt[row];
-      end = oprt[row + 1];
-      Hi = Hin[row];
-    }
+  for (int r0 = blockIdx.x * kSegRows; r0 < n; r0 += gridDim.x * kSegRows) {
+    const int nr = min(kSegRows, n - r0);
+    __syncthreads();
+    for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
+    for (int k = t; k < nr; k += kBlock) own[k] = Hin[r0 + k];
+    __syncthreads();
+    const int e0 = rp[0], e1 = rp[nr];
     T H = T(0);
-    for (int e = beg + lane; e < end; e += G) {
-      const V2 c = coef[e];
-      const V2 h = hin[e];               // (h_ij, h_ji)
-      const T Hj = Hin[ocol[e]];
-      T ho = c.x * (Hi - h.y);
-      T hi = c.y * (Hj - h.x);
-      if (DAMP) {
-        const T b1 = T(1) - alpha;
-        ho = alpha * h.x + b1 * ho;
-        hi = alpha * h.y + b1 * hi;
-      }
-      V2 o;
-      o.x = ho;
-      o.y = hi;
-      hout[e] = o;
-      H += hi;
-    }
-    H = gsum<G>(H);
-    if (active) {
-      H += rhs[row];
-      if (lane == 0) {
-        Hout[row] = H;
-        if (MODE == 1) {
-          const T x = H / Sfix[row];
-          if (!isfinite(x)) f |= FLAG_NONFINITE;
-          d = fmax(d, (double)fabs(x - xprev[row]));
-          xprev[row] = x;
-          ax = fmax(ax, (double)fabs(x));
+    for (int c = e0; c < e1; c += kSegChunk) {
+      int j[kSegK];
+      V2 cf[kSegK], h[kSegK];
+      T Hj[kSegK];
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        j[k] = 0;
+        cf[k] = V2{};
+        h[k] = V2{};
+        if (e < e1) {
+          j[k] = ocol[e];
+          cf[k] = coef[e];
+          h[k] = hin[e];  // (h_ij, h_ji)
         }
+      }
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        Hj[k] = T(0);
+        if (c + k * kBlock + t < e1) Hj[k] = Hin[j[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        if (e >= e1) continue;
+        const T Hi = own[seg_row(rp, nr, e)];
+        T ho = cf[k].x * (Hi - h[k].y);
+        T hi = cf[k].y * (Hj[k] - h[k].x);
+        if (DAMP) {
+          ho = alpha * h[k].x + b1 * ho;
+          hi = alpha * h[k].y + b1 * hi;
+        }
+        V2 o;
+        o.x = ho;
+        o.y = hi;
+        hout[e] = o;
+        in[e - c] = hi;
+      }
+      __syncthreads();
+      if (t < nr) {
+        const int lo = max(rp[t], c), hi = min(rp[t + 1], c + kSegChunk);
+        for (int e = lo; e < hi; ++e) H += in[e - c];
+      }
+      __syncthreads();
+    }
+    if (t < nr) {
+      const int row = r0 + t;
+      H += rhs[row];
+      Hout[row] = H;
+      if (MODE == 1) {
+        const T x = H / Sfix[row];
+        if (!isfinite(x)) f |= FLAG_NONFINITE;
+        d = fmax(d, (double)fabs(x - xprev[row]));
+        xprev[row] = x;
+        ax = fmax(ax, (double)fabs(x));
       }
     }
   }
@@ -641,29 +738,45 @@ static void pair_one(const PairArgs &a, hipStream_t s) {
   using V4 = typename Vec4<T>::type;
   using V2 = typename Vec2<T>::type;
   const dim3 grid(a.grid);
-  if (a.colored) {
-    if (a.frozen)
-      hipLaunchKernelGGL((k_pair_frozen_col<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.row0,
-                         a.row1, a.first, a.oprt, a.ocol, (const V2 *)a.coef, (const T *)a.rhs,
-                         (const T *)a.Sfix, (V2 *)a.msg_out, (T *)a.sums_out, (T)a.alpha,
-                         (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
-    else
-      hipLaunchKernelGGL((k_pair_col<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.row0, a.row1,
-                         a.first, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,
-                         (V4 *)a.msg_out, (V2 *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part,
-                         a.combine, a.sticky, a.ctl);
-    return;
-  }
   if (a.frozen)
-    hipLaunchKernelGGL((k_pair_frozen<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.n, a.oprt,
+    hipLaunchKernelGGL((k_pair_frozen_col<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.row0,
+                       a.row1, a.first, a.oprt, a.ocol, (const V2 *)a.coef, (const T *)a.rhs,
+                       (const T *)a.Sfix, (V2 *)a.msg_out, (T *)a.sums_out, (T)a.alpha,
+                       (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
+  else
+    hipLaunchKernelGGL((k_pair_col<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.row0, a.row1,
+                       a.first, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,
+                       (V4 *)a.msg_out, (V2 *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part,
+                       a.combine, a.sticky, a.ctl);
+}
+
+template <typename T, int MODE, bool DAMP>
+static void pair_sync(const PairArgs &a, hipStream_t s) {
+  using V4 = typename Vec4<T>::type;
+  using V2 = typename Vec2<T>::type;
+  const dim3 grid(a.grid);
+  if (a.frozen)
+    hipLaunchKernelGGL((k_pair_frozen<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.n, a.oprt,
                        a.ocol, (const V2 *)a.coef, (const T *)a.rhs, (const T *)a.Sfix,
                        (const V2 *)a.msg_in, (V2 *)a.msg_out, (const T *)a.sums_in,
                        (T *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part, a.sticky, a.ctl);
   else
-    hipLaunchKernelGGL((k_pair_sweep<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.n, a.oprt,
+    hipLaunchKernelGGL((k_pair_sweep<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.n, a.oprt,
                        a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,
                        (const V4 *)a.msg_in, (V4 *)a.msg_out, (const V2 *)a.sums_in,
                        (V2 *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part, a.sticky, a.ctl);
+}
+
+template <typename T>
+static hipError_t pair_sync_t(const PairArgs &a, hipStream_t s) {
+  if (a.mode == 1) a.damp ? pair_sync<T, 1, true>(a, s) : pair_sync<T, 1, false>(a, s);
+  else a.damp ? pair_sync<T, 0, true>(a, s) : pair_sync<T, 0, false>(a, s);
+  return hipGetLastError();
+}
+
+int pair_sweep_blocks(int n, int cap) {
+  const int need = (n + kSegRows - 1) / kSegRows;
+  return need < cap ? (need > 0 ? need : 1) : cap;
 }
 
 template <typename T, int G>
@@ -687,6 +800,7 @@ static hipError_t pair_group(const PairArgs &a, hipStream_t s) {
 
 hipError_t launch_pair_sweep(const PairArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
+  if (!a.colored) return a.fp32 ? pair_sync_t<float>(a, s) : pair_sync_t<double>(a, s);
   return a.fp32 ? pair_group<float>(a, s) : pair_group<double>(a, s);
 }
 
@@ -711,6 +825,18 @@ hipError_t launch_pair_aggregate(bool fp32, int group, int grid, int n, const in
                                  const void *diag, const void *rhs, const void *msg, void *sums,
                                  hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  if (group == 0) {  // slot order (synchronous plans)
+    const dim3 g((n + kBlock - 1) / kBlock);
+    if (fp32)
+      hipLaunchKernelGGL(k_pair_aggregate_seq<float>, g, dim3(kBlock), 0, s, n, oprt,
+                         (const float *)diag, (const float *)rhs, (const float4 *)msg,
+                         (float2 *)sums);
+    else
+      hipLaunchKernelGGL(k_pair_aggregate_seq<double>, g, dim3(kBlock), 0, s, n, oprt,
+                         (const double *)diag, (const double *)rhs, (const double4 *)msg,
+                         (double2 *)sums);
+    return hipGetLastError();
+  }
   return fp32 ? aggregate_t<float>(group, grid, n, oprt, diag, rhs, msg, sums, s)
               : aggregate_t<double>(group, grid, n, oprt, diag, rhs, msg, sums, s);
 }

@@ -174,6 +174,66 @@ def test_damped_trajectory_matches_oracle(G, layout):
     G.gabp_plan_destroy(plan)
 
 
+def _hub_chain(leaves, seed):
+    """A hub joined to every leaf and the leaves joined in a chain, diagonally
+    dominant: the hub's row holds more slots than two chunks of a row block
+    (1024 slots each) of the pair sweeps."""
+    rng = np.random.default_rng(seed)
+    r = np.concatenate([np.zeros(leaves, dtype=np.int64), np.arange(1, leaves)])
+    c = np.concatenate([np.arange(1, leaves + 1), np.arange(2, leaves + 1)])
+    v = rng.standard_normal(r.size)
+    n = leaves + 1
+    rows, cols, vals = np.concatenate([r, c]), np.concatenate([c, r]), np.concatenate([v, v])
+    d = np.zeros(n)
+    np.add.at(d, rows, np.abs(vals))
+    return W.csr_from_coo(n, np.concatenate([rows, np.arange(n)]),
+                          np.concatenate([cols, np.arange(n)]),
+                          np.concatenate([vals, 1.1 * d + 0.1]))
+
+
+@pytest.mark.parametrize("case", ["hub_2600", "sdd_ragged"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_pair_row_blocks_long_rows_and_grid_stride(G, case, fp32):
+    """Synchronous pair sweeps with a two-block grid, so every block walks many
+    row blocks, and (hub) one row spread over three slot chunks: the messages
+    follow Algorithm 2 of the oracle round by round."""
+    m = _hub_chain(2600, 4) if case == "hub_2600" else CASES[case]()
+    b = W.uniform_b(m.n, 6)
+    Ad, plan = _plan(G, m, fp32=fp32, grid_blocks=2)
+    assert G.gabp_plan_reset(plan, dev(b)) == G.GABP_OK
+    R = oracle.Rounds(m, b, algorithm=2)
+    # FP32: the hub sums 2600 in-messages in sequence; the worst-case bound of
+    # such a sum is about count * 2^-24 = 1.5e-4 of the summed magnitudes
+    rtol = (1e-4 if case == "hub_2600" else 2e-5) if fp32 else 1e-10
+    for t in range(1, 5):
+        R.step()
+        assert G.gabp_plan_sweeps(plan, 1) == G.GABP_OK
+        P, h = _messages(G, plan, m.nnz)
+        ho = R.information()
+        np.testing.assert_allclose(P, R.P, rtol=rtol, atol=rtol * 0.1 * np.abs(R.P).max(),
+                                   err_msg=f"P round {t}")
+        np.testing.assert_allclose(h, ho, rtol=rtol, atol=rtol * np.abs(ho).max(),
+                                   err_msg=f"h round {t}")
+        mean, prec = _marginals(G, plan, m.n)
+        mo, po = R.marginals()
+        np.testing.assert_allclose(prec, po, rtol=rtol, atol=rtol * 0.1 * np.abs(po).max())
+        np.testing.assert_allclose(mean, mo, rtol=rtol, atol=rtol * np.abs(mo).max())
+    G.gabp_plan_destroy(plan)
+
+
+def test_pair_hub_solve_settled_phase_small_grid(G):
+    """FP32 solve of the hub graph to 1e-8 with a two-block grid: the check
+    sweeps' block maxima and the settled-precision kernel walk many row
+    blocks, the hub's row spans several chunks."""
+    m = _hub_chain(2600, 5)
+    b = W.normal_b(m.n, 5)
+    rc, st, x = _solve(G, m, b, msg_fp32=1, tol=1e-8, grid_blocks=2)
+    assert rc == G.GABP_OK, G.status_name(rc)
+    assert st.frozen_sweeps > 0
+    _, rn = oracle.residual(m, b, x)
+    assert rn / np.linalg.norm(b) <= 1e-8
+
+
 def test_tree_exact_after_diameter_on_gpu(G):
     """Trees: exact means and precisions after diameter sweeps (section IV)."""
     m = W.random_tree(300, 8, dominant=False)
