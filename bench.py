@@ -216,11 +216,11 @@ def run_c2(args, G, W, torch, dev):
                           if pair else None,
                 tkey_frozen=("gabp::k_pair_frozen_col<float, " if colored
                              else "gabp::k_pair_frozen<float, ") if pair else None,
-                kfull=(("k_pair_col<float,G,*> (one colour class: in-messages, totals, "
+                kfull=(("k_pair_col<float,*> (one colour class: in-messages, totals, "
                         "out-messages)" if colored else
                         "k_pair_sweep<float,*> (A1 node broadcast + A2 edge update + A3 check)")
                        if pair else "k_csr_sweep<float,G,*> (A1+A2+A3, reverse-index gather)"),
-                kfrozen=("k_pair_frozen_col<float,G,*>" if colored else "k_pair_frozen<float,*>")
+                kfrozen=("k_pair_frozen_col<float,*>" if colored else "k_pair_frozen<float,*>")
                         if pair else None)
 
 
@@ -262,9 +262,9 @@ def run_lsq(args, G, W, torch, dev):
                 tkey_full="gabp::k_pair_col<float, " if colored else "gabp::k_pair_sweep<float, ",
                 tkey_frozen=("gabp::k_pair_frozen_col<float, " if colored
                              else "gabp::k_pair_frozen<float, "),
-                kfull=("k_pair_col<float,G,*> (one colour class)" if colored else
+                kfull=("k_pair_col<float,*> (one colour class)" if colored else
                        "k_pair_sweep<float,*> (A1 node broadcast + A2 edge update + A3 check)"),
-                kfrozen="k_pair_frozen_col<float,G,*>" if colored else "k_pair_frozen<float,*>")
+                kfrozen="k_pair_frozen_col<float,*>" if colored else "k_pair_frozen<float,*>")
 
 
 def cpu_baseline_lsq(w, E, budget_s=12.0):

@@ -55,7 +55,12 @@ struct CsrEngine : Engine {
   bool pair = true;
   int group = 8;
   int grid = 1;       // blocks of a row-kernel launch
-  int sgrid = 1;      // blocks of a synchronous pair sweep
+  // pair sweeps: row blocks (offsets rblk, pair_row_blocks), the first block
+  // of every colour class (or of the one range) and the workgroups a sweep
+  // launch walks them with
+  int32_t *rblk = nullptr;
+  std::vector<int> bfirst;
+  int sgrid = 1;
   int32_t *oprt = nullptr, *ocol = nullptr, *rev = nullptr;
   int64_t *diagpos = nullptr;
   void *acoef = nullptr, *diag = nullptr, *rhs = nullptr;
@@ -67,12 +72,11 @@ struct CsrEngine : Engine {
   // coloured schedule (pair layout): class c is rows [cls[c], cls[c + 1]);
   // one buffer (index 0), updated in place by one launch per class
   std::vector<int> cls;
-  int cgrid = 1;
   bool first = true;  // no sweep since the messages were set (reset, restart, import)
 
   ~CsrEngine() override {
     void *bufs[] = {oprt, ocol, rev, diagpos, acoef, diag, rhs, msg[0], msg[1], sums[0],
-                    sums[1], coef, hp[0], hp[1], Sfix, Hfz[0], Hfz[1]};
+                    sums[1], coef, hp[0], hp[1], Sfix, Hfz[0], Hfz[1], rblk};
     for (void *b : bufs)
       if (b) (void)hipFree(b);
   }
@@ -81,18 +85,16 @@ struct CsrEngine : Engine {
 
   bool colored() const { return !cls.empty(); }
 
-  // lane group of the aggregation: the sweeps' summation order (0: slot order)
-  int agg_group() const { return colored() ? group : 0; }
-
   hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
     hipError_t err;
     if (colored()) {
       for (size_t k = 0; k + 1 < cls.size(); ++k) {
         PairArgs a{};
-        a.grid = cgrid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
+        a.grid = sgrid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
         a.frozen = frozen; a.n = n; a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
         a.rhs = rhs; a.alpha = o.damping; a.xprev = xprev; a.part = part; a.sticky = sticky;
         a.ctl = c; a.colored = true; a.combine = k > 0; a.row0 = cls[k]; a.row1 = cls[k + 1];
+        a.rb = rblk; a.b0 = bfirst[k]; a.b1 = bfirst[k + 1];
         a.first = first;
         if (frozen) {
           a.coef = coef; a.Sfix = Sfix; a.msg_out = hp[0]; a.sums_out = Hfz[0];
@@ -115,7 +117,7 @@ struct CsrEngine : Engine {
     } else {
       PairArgs a{};
       a.grid = sgrid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
-      a.frozen = frozen; a.n = n; a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
+      a.frozen = frozen; a.n = n; a.rb = rblk; a.b0 = 0; a.b1 = bfirst.back(); a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
       a.rhs = rhs; a.alpha = o.damping; a.xprev = xprev; a.part = part; a.sticky = sticky;
       a.ctl = c;
       if (frozen) {
@@ -170,7 +172,7 @@ struct CsrEngine : Engine {
     // one half sweep old; make every copy the sender's current message
     if (colored() && (err = launch_pair_sync_in(fp32, E, rev, msg[cur], s)) != hipSuccess)
       return err;
-    return launch_pair_aggregate(fp32, agg_group(), grid, n, oprt, diag, rhs, msg[cur], sums[cur], s);
+    return launch_pair_aggregate(fp32, n, oprt, diag, rhs, msg[cur], sums[cur], s);
   }
 
   hipError_t reset(const double *b, hipStream_t s) override {
@@ -184,7 +186,7 @@ struct CsrEngine : Engine {
     if ((err = launch_residual(fp32, group, nsum, n, A.row_ptr, A.col, A.val, b, nullptr, rhs,
                                nullptr, sumpart, s)) != hipSuccess)
       return err;
-    if (pair) return launch_pair_aggregate(fp32, agg_group(), grid, n, oprt, diag, rhs, msg[0], sums[0], s);
+    if (pair) return launch_pair_aggregate(fp32, n, oprt, diag, rhs, msg[0], sums[0], s);
     return hipSuccess;
   }
 
@@ -234,10 +236,32 @@ struct CsrEngine : Engine {
     if (pair) {
       TRY_HIP(launch_pair_io(fp32, false, n, A.row_ptr, diagpos, oprt, rev, msg[cur], (double *)P,
                              (double *)h, s));
-      TRY_HIP(launch_pair_aggregate(fp32, agg_group(), grid, n, oprt, diag, rhs, msg[cur], sums[cur], s));
+      TRY_HIP(launch_pair_aggregate(fp32, n, oprt, diag, rhs, msg[cur], sums[cur], s));
     } else {
       TRY_HIP(launch_set_msgs(fp32, n, A.row_ptr, diagpos, oprt, msg[cur], P, h, s));
     }
+    TRY_HIP(hipStreamSynchronize(s));
+    return GABP_OK;
+  }
+
+  // Row blocks of the pair sweeps from a host copy of the slot offsets; every
+  // class launch of a coloured sweep has the same workgroups, so a check's
+  // partials line up.
+  int row_blocks(int cap, hipStream_t s) {
+    std::vector<int32_t> hrp((size_t)n + 1, 0);
+    if (n > 0) {
+      TRY_HIP(hipMemcpyAsync(hrp.data(), oprt, hrp.size() * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      TRY_HIP(hipStreamSynchronize(s));
+    }
+    const std::vector<int> bounds = colored() ? cls : std::vector<int>{0, n};
+    const std::vector<int32_t> rb = pair_row_blocks(hrp.data(), bounds, &bfirst);
+    int most = 1;
+    for (size_t k = 0; k + 1 < bfirst.size(); ++k) most = std::max(most, bfirst[k + 1] - bfirst[k]);
+    sgrid = std::min(most, cap);
+    nparts = sgrid;
+    TRY_HIP(dalloc(&rblk, rb.size(), sizeof(int32_t)));
+    TRY_HIP(hipMemcpyAsync(rblk, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     TRY_HIP(hipStreamSynchronize(s));
     return GABP_OK;
   }
@@ -322,17 +346,9 @@ int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int
   e->group = opts.group ? opts.group : choose_group(e->n, e->E);
   const int cap = opts.grid_blocks > 0 ? opts.grid_blocks : kMaxSweepBlocks;
   e->grid = sweep_blocks(std::max(e->n, 1), e->group, cap);
-  e->sgrid = pair_sweep_blocks(std::max(e->n, 1), cap);
-  e->nparts = e->pair ? e->sgrid : e->grid;
-  if (classes) {
-    // every class launch has the same blocks, so a check's partials line up
-    e->cls = *classes;
-    int most = 1;
-    for (size_t k = 0; k + 1 < e->cls.size(); ++k)
-      most = std::max(most, e->cls[k + 1] - e->cls[k]);
-    e->cgrid = sweep_blocks(most, e->group, cap);
-    e->nparts = e->cgrid;
-  }
+  e->nparts = e->grid;
+  if (classes) e->cls = *classes;
+  if (e->pair && (st = e->row_blocks(cap, s))) return fail(st);
   e->nsum = residual_blocks(std::max(e->n, 1), e->group, cap);
   if ((st = e->init_common(s))) return fail(st);
   if ((st = from_hip(dalloc(&e->msg[0], e->E, e->msg_bytes()))) ||

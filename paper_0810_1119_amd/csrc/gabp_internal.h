@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "gabp.h"
 
@@ -84,6 +85,10 @@ template <> struct Vec2<double> { using type = double2; };
 
 constexpr int kBlock = 256;       // threads per block of the row kernels
 constexpr int kMaxSweepBlocks = 2048;  // row kernels loop over row groups beyond this
+// row blocks of the pair-layout sweeps: at most kSegRows rows and kSegChunk
+// slots each (a longer row alone); slots are streamed in chunks of kSegChunk
+constexpr int kSegRows = 128;
+constexpr int kSegChunk = 1024;
 
 // ---- launchers (kernels_csr.hip) ----
 hipError_t launch_plan_rows(int n, int64_t nnz, const int64_t *rp, const int32_t *col,
@@ -147,7 +152,7 @@ hipError_t launch_set_msgs(bool fp32, int n, const int64_t *rp, const int64_t *d
 
 // ---- pair layout (kernels_pair.hip) ----
 struct PairArgs {
-  int grid;            // blocks of the launch (synchronous: pair_sweep_blocks; coloured: sweep_blocks)
+  int grid;            // workgroups of the launch (each walks row blocks b0 + k * grid)
   bool fp32;
   int group;
   int mode;            // 0 sweep, 1 sweep + check
@@ -166,6 +171,9 @@ struct PairArgs {
   BlockPartial *part;
   uint32_t *sticky;
   const Ctl *ctl;
+  // sweeps: the row blocks [b0, b1) of rb (pair_row_blocks)
+  const int32_t *rb;
+  int b0, b1;
   // coloured schedule: one colour class, rows [row0, row1), updated in place
   // (msg_in == msg_out, sums_in == sums_out); combine: add to the partials
   // of the check's earlier class launches
@@ -174,8 +182,13 @@ struct PairArgs {
   bool first;  // first sweep since the messages were set, not sent
 };
 hipError_t launch_pair_sweep(const PairArgs &a, hipStream_t s);
-// blocks of a synchronous pair sweep over n rows (row blocks of fixed size)
-int pair_sweep_blocks(int n, int cap = kMaxSweepBlocks);
+// Row blocks of the pair sweeps for the row ranges [bounds[k], bounds[k+1])
+// (colour classes, or one range): consecutive rows, at most kSegRows rows and
+// kSegChunk slots per block unless one row has more; rp is the slot offset of
+// every row (host copy).  Returns the block offsets (rows); first_block[k] is
+// the first block of range k (first_block.back() = the number of blocks).
+std::vector<int32_t> pair_row_blocks(const int32_t *rp, const std::vector<int> &bounds,
+                                     std::vector<int> *first_block);
 // marginals of one class (rows [row0, row1)) of a coloured pair plan from its
 // current messages after a complete sweep (msg_in / sums_in: the full state,
 // or in the settled state the information pairs and H broadcasts, with coef
@@ -184,9 +197,9 @@ hipError_t launch_pair_col_infer(const PairArgs &a, double *xacc, double *marg, 
                                  hipStream_t s);
 // msg[e].P_ji := msg[rev[e]].P_ij for every slot (pair layout)
 hipError_t launch_pair_sync_in(bool fp32, int64_t E, const int32_t *rev, void *msg, hipStream_t s);
-// (S, H) from the stored in-messages; group 0: a row's in-messages added in
-// slot order (the synchronous sweeps' order), else in that lane group's order
-hipError_t launch_pair_aggregate(bool fp32, int group, int grid, int n, const int32_t *oprt, const void *diag,
+// (S, H) from the stored in-messages, a row's added in slot order (the sweeps'
+// order)
+hipError_t launch_pair_aggregate(bool fp32, int n, const int32_t *oprt, const void *diag,
                                  const void *rhs, const void *msg, void *sums, hipStream_t s);
 hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s);
 hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfix, const void *Hfz,

@@ -23,6 +23,8 @@
 // message computed before and after the switch rounds the same way):
 //   h_ij' = c_ij (H_i - h_ji),  h_ji' = c_ji (H_j - h_ij),  H_i' = b_i + sum h_ji'.
 // The gather then reads H_j alone (4 bytes per node).
+#include <vector>
+
 #include "device_common.h"
 
 namespace gabp {
@@ -32,17 +34,19 @@ template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 
 // ---------------------------------------------------------------------------
-// synchronous sweeps: row blocks, slots streamed in chunks
+// row blocks: the unit of work of every sweep kernel
 // ---------------------------------------------------------------------------
-// A block takes kSegRows consecutive rows and streams their slots in chunks of
-// kSegChunk: thread t handles slots c + t, c + t + kBlock, ... of the chunk
-// (coalesced, every lane busy whatever the row lengths, kSegK independent
-// gathers in flight per thread), finds each slot's row by a binary search of
-// the block's row offsets in LDS, writes the slot and leaves its in-message
-// in LDS; then the row's own thread adds its in-messages in slot order.
-constexpr int kSegRows = 128;
-constexpr int kSegK = 4;
-constexpr int kSegChunk = kBlock * kSegK;
+// The plan cuts the rows into blocks of consecutive rows, at most kSegRows rows
+// and kSegChunk slots each (a longer row forms a block of its own), never
+// across a colour class.  A workgroup takes a block: it loads the rows'
+// offsets into LDS and streams their slots in chunks of kSegChunk, thread t
+// handling slots c + t, c + t + kBlock, ... (coalesced, every lane busy
+// whatever the row lengths, kSegK independent gathers in flight per thread);
+// it finds each slot's row by a binary search of the offsets, leaves the
+// slot's in-message in LDS, and the row's own thread then adds its
+// in-messages in slot order.
+constexpr int kSegK = kSegChunk / kBlock;
+static_assert(kSegChunk % kBlock == 0 && kSegRows <= kBlock, "row block shape");
 
 // the row of slot e: the last r with rp[r] <= e (rp[0] <= e < rp[nr])
 __device__ __forceinline__ int seg_row(const int *rp, int nr, int e) {
@@ -55,15 +59,17 @@ __device__ __forceinline__ int seg_row(const int *rp, int nr, int e) {
   return lo;
 }
 
-// full sweep (P and h), MODE 0 = sweep, 1 = sweep + check
+// ---------------------------------------------------------------------------
+// synchronous full sweep (P and h), MODE 0 = sweep, 1 = sweep + check
+// ---------------------------------------------------------------------------
 template <typename T, int MODE, bool DAMP>
 __global__ __launch_bounds__(kBlock) void k_pair_sweep(
-    int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
-    const T *__restrict__ acoef, const T *__restrict__ diag, const T *__restrict__ rhs,
-    const typename Vec4<T>::type *__restrict__ mi, typename Vec4<T>::type *__restrict__ mo,
-    const typename Vec2<T>::type *__restrict__ sin, typename Vec2<T>::type *__restrict__ sout,
-    T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky,
-    const Ctl *__restrict__ ctl) {
+    const int32_t *__restrict__ rb, int b0, int b1, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ ocol, const T *__restrict__ acoef, const T *__restrict__ diag,
+    const T *__restrict__ rhs, const typename Vec4<T>::type *__restrict__ mi,
+    typename Vec4<T>::type *__restrict__ mo, const typename Vec2<T>::type *__restrict__ sin,
+    typename Vec2<T>::type *__restrict__ sout, T alpha, T *__restrict__ xprev,
+    BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
   // no FMA contraction: both stored copies of a message, and the node sums
   // rebuilt from stored values, must round exactly like this sweep does
 #pragma clang fp contract(off)
@@ -74,14 +80,14 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
   __shared__ V2 in[kSegChunk];   // the chunk's new in-messages (P_ji, h_ji)
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
   const int t = threadIdx.x;
-  const T b1 = T(1) - alpha;
+  const T b1m = T(1) - alpha;
   double d = 0.0, ax = 0.0;
   T dp = T(0), pm = T(0);
   bool zero = false;
   uint32_t f = 0;
-  for (int r0 = blockIdx.x * kSegRows; r0 < n; r0 += gridDim.x * kSegRows) {
-    const int nr = min(kSegRows, n - r0);
-    __syncthreads();  // the previous rows' readers are done with the LDS
+  for (int b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
+    const int r0 = rb[b], nr = rb[b + 1] - r0;
+    __syncthreads();  // the previous block's readers are done with the LDS
     for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
     for (int k = t; k < nr; k += kBlock) own[k] = sin[r0 + k];
     __syncthreads();
@@ -122,10 +128,10 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
         T Pin = -(aa * aa) * ij, hin = (-aa * ij) * (sj[k].y - m[k].y);
         T Pout = -(aa * aa) * ii, hout = (-aa * ii) * (si.y - m[k].w);
         if (DAMP) {
-          Pin = alpha * m[k].z + b1 * Pin;
-          hin = alpha * m[k].w + b1 * hin;
-          Pout = alpha * m[k].x + b1 * Pout;
-          hout = alpha * m[k].y + b1 * hout;
+          Pin = alpha * m[k].z + b1m * Pin;
+          hin = alpha * m[k].w + b1m * hin;
+          Pout = alpha * m[k].x + b1m * Pout;
+          hout = alpha * m[k].y + b1m * hout;
         }
         if (MODE == 1) {
           dp = fmax(dp, fabs(Pout - m[k].x));
@@ -173,12 +179,11 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
 }
 
 // Aggregate (S, H) from the slots' incoming messages: used after reset,
-// message import and restarts.  Synchronous plans add a row's in-messages in
-// slot order, one thread per row (k_pair_aggregate_seq), exactly as their
-// sweeps do, so that imported messages resume a solve bit for bit; coloured
-// plans use the lane-group order of their sweeps.
+// message import and restarts.  A row's in-messages are added in slot order,
+// one thread per row, exactly as the sweeps add them, so that imported
+// messages resume a solve bit for bit.
 template <typename T>
-__global__ void k_pair_aggregate_seq(int n, const int32_t *__restrict__ oprt,
+__global__ void k_pair_aggregate(int n, const int32_t *__restrict__ oprt,
                                      const T *__restrict__ diag, const T *__restrict__ rhs,
                                      const typename Vec4<T>::type *__restrict__ msg,
                                      typename Vec2<T>::type *__restrict__ sums) {
@@ -194,33 +199,6 @@ __global__ void k_pair_aggregate_seq(int n, const int32_t *__restrict__ oprt,
   o.x = S + diag[row];
   o.y = H + rhs[row];
   sums[row] = o;
-}
-
-template <typename T, int G>
-__global__ __launch_bounds__(kBlock) void k_pair_aggregate(
-    int n, const int32_t *__restrict__ oprt, const T *__restrict__ diag, const T *__restrict__ rhs,
-    const typename Vec4<T>::type *__restrict__ msg, typename Vec2<T>::type *__restrict__ sums) {
-#pragma clang fp contract(off)
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G;
-  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
-    const int row = base + threadIdx.x / G;
-    const bool active = row < n;
-    T S = T(0), H = T(0);
-    if (active)
-      for (int e = oprt[row] + lane; e < oprt[row + 1]; e += G) {
-        S += msg[e].z;
-        H += msg[e].w;
-      }
-    S = gsum<G>(S);
-    H = gsum<G>(H);
-    if (active && lane == 0) {
-      typename Vec2<T>::type o;
-      o.x = S + diag[row];
-      o.y = H + rhs[row];
-      sums[row] = o;
-    }
-  }
 }
 
 // Zero every information field (restart) and re-aggregate H = rhs.
@@ -298,16 +276,16 @@ __global__ __launch_bounds__(kBlock) void k_pair_freeze(
   }
 }
 
-// frozen sweep: information only, row blocks as in the full sweep.
+// synchronous settled-precision sweep: information only.
 // MODE 0 = sweep, 1 = sweep + check.
 template <typename T, int MODE, bool DAMP>
 __global__ __launch_bounds__(kBlock) void k_pair_frozen(
-    int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
-    const typename Vec2<T>::type *__restrict__ coef, const T *__restrict__ rhs,
-    const T *__restrict__ Sfix, const typename Vec2<T>::type *__restrict__ hin,
-    typename Vec2<T>::type *__restrict__ hout, const T *__restrict__ Hin, T *__restrict__ Hout,
-    T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky,
-    const Ctl *__restrict__ ctl) {
+    const int32_t *__restrict__ rb, int b0, int b1, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ ocol, const typename Vec2<T>::type *__restrict__ coef,
+    const T *__restrict__ rhs, const T *__restrict__ Sfix,
+    const typename Vec2<T>::type *__restrict__ hin, typename Vec2<T>::type *__restrict__ hout,
+    const T *__restrict__ Hin, T *__restrict__ Hout, T alpha, T *__restrict__ xprev,
+    BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
 #pragma clang fp contract(off)
   using V2 = typename Vec2<T>::type;
   __shared__ int rp[kSegRows + 1];
@@ -315,11 +293,11 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen(
   __shared__ T in[kSegChunk];
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
   const int t = threadIdx.x;
-  const T b1 = T(1) - alpha;
+  const T b1m = T(1) - alpha;
   double d = 0.0, ax = 0.0;
   uint32_t f = 0;
-  for (int r0 = blockIdx.x * kSegRows; r0 < n; r0 += gridDim.x * kSegRows) {
-    const int nr = min(kSegRows, n - r0);
+  for (int b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
+    const int r0 = rb[b], nr = rb[b + 1] - r0;
     __syncthreads();
     for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
     for (int k = t; k < nr; k += kBlock) own[k] = Hin[r0 + k];
@@ -355,8 +333,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen(
         T ho = cf[k].x * (Hi - h[k].y);
         T hi = cf[k].y * (Hj[k] - h[k].x);
         if (DAMP) {
-          ho = alpha * h[k].x + b1 * ho;
-          hi = alpha * h[k].y + b1 * hi;
+          ho = alpha * h[k].x + b1m * ho;
+          hi = alpha * h[k].y + b1m * hi;
         }
         V2 o;
         o.x = ho;
@@ -409,9 +387,10 @@ __global__ void k_frozen_restart(int64_t E, int n, typename Vec2<T>::type *__res
 // them into its new totals (S_i, H_i), and only then computes its
 // out-messages from those totals: the serial scheme of section III-C, one
 // colour class at a time.  No row of the class reads a slot or broadcast
-// another row of the class writes, so one buffer suffices.  A row with at most
-// G slots keeps its slot in registers between the two steps; longer rows read
-// their slots twice (the second read comes from the cache).
+// another row of the class writes, so one buffer suffices.  The launch walks
+// the class's row blocks [b0, b1); a block within one chunk keeps its slots in
+// registers between the two steps, a longer one (a single long row) reads
+// them again and recomputes its in-messages with the same operands.
 //
 // The rebuilt in-message equals the stored one only if its sender computed it
 // from its broadcast.  Messages that were set rather than sent (zeroed by a
@@ -419,109 +398,109 @@ __global__ void k_frozen_restart(int64_t E, int n, typename Vec2<T>::type *__res
 // after such a change, in which the classes that have not sent yet (rows at
 // or beyond row1: classes run in row order) pass their stored in-messages
 // instead, which the engine keeps equal to the senders' out-messages.
-template <typename T, int G, int MODE, bool DAMP>
+template <typename T, bool DAMP>
+__device__ __forceinline__ void col_in(bool rebuild, T a, const typename Vec4<T>::type &m,
+                                       const typename Vec2<T>::type &sj, T alpha, T b1m, T &Pin,
+                                       T &hin, bool &zero) {
+#pragma clang fp contract(off)
+  Pin = m.z;
+  hin = m.w;
+  if (rebuild) {
+    const T cj = sj.x - m.x;
+    zero |= cj == T(0);
+    const T ij = T(1) / cj;
+    Pin = -(a * a) * ij;
+    hin = (-a * ij) * (sj.y - m.y);
+    if (DAMP) {
+      Pin = alpha * m.z + b1m * Pin;
+      hin = alpha * m.w + b1m * hin;
+    }
+  }
+}
+
+template <typename T, int MODE, bool DAMP>
 __global__ __launch_bounds__(kBlock) void k_pair_col(
-    int row0, int row1, bool first, const int32_t *__restrict__ oprt,
-    const int32_t *__restrict__ ocol, const T *__restrict__ acoef, const T *__restrict__ diag,
-    const T *__restrict__ rhs, typename Vec4<T>::type *msg, typename Vec2<T>::type *sums, T alpha,
-    T *__restrict__ xprev, BlockPartial *__restrict__ part, bool combine,
-    uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+    const int32_t *__restrict__ rb, int b0, int b1, int row1, bool first,
+    const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
+    const T *__restrict__ acoef, const T *__restrict__ diag, const T *__restrict__ rhs,
+    typename Vec4<T>::type *msg, typename Vec2<T>::type *sums, T alpha, T *__restrict__ xprev,
+    BlockPartial *__restrict__ part, bool combine, uint32_t *__restrict__ sticky,
+    const Ctl *__restrict__ ctl) {
 #pragma clang fp contract(off)
   using V4 = typename Vec4<T>::type;
   using V2 = typename Vec2<T>::type;
-  constexpr int RPB = kBlock / G;
+  __shared__ int rp[kSegRows + 1];
+  __shared__ V2 tot[kSegRows];  // the rows' new totals (S_i, H_i)
+  __shared__ V2 in[kSegChunk];
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
-  const int lane = threadIdx.x % G;
-  const T b1 = T(1) - alpha;
-  double d = 0.0, ax = 0.0, dpb = 0.0, pmb = 0.0;
+  const int t = threadIdx.x;
+  const T b1m = T(1) - alpha;
+  double d = 0.0, ax = 0.0;
+  T dp = T(0), pm = T(0);
   bool zero = false;
   uint32_t f = 0;
-  for (int base = row0 + blockIdx.x * RPB; base < row1; base += gridDim.x * RPB) {
-    const int row = base + threadIdx.x / G;
-    const bool active = row < row1;
-    const int beg = active ? oprt[row] : 0, end = active ? oprt[row + 1] : 0;
+  for (int b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
+    const int r0 = rb[b], nr = rb[b + 1] - r0;
+    __syncthreads();
+    for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
+    __syncthreads();
+    const int e0 = rp[0], e1 = rp[nr];
+    const bool one = e1 - e0 <= kSegChunk;  // uniform over the workgroup
+    T a[kSegK], Pin[kSegK], hin[kSegK];
+    V4 m[kSegK];
     // step 1: the in-messages j -> i from j's broadcast, and the new totals
     T S = T(0), H = T(0);
-    V4 m0;
-    T Pin0 = T(0), hin0 = T(0), a0 = T(0);
-    const bool one = end - beg <= G;  // uniform over the row's lanes
-    for (int e = beg + lane; e < end; e += G) {
-      const T a = acoef[e];
-      const V4 m = msg[e];  // (P_ij, h_ij, P_ji, h_ji) as last written
-      const int j = ocol[e];
-      T Pin = m.z, hin = m.w;
-      if (!(first && j >= row1)) {
-        const V2 sj = sums[j];  // broadcast of node j, written when j last sent
-        const T cj = sj.x - m.x;
-        zero |= cj == T(0);
-        const T ij = T(1) / cj;
-        Pin = -(a * a) * ij;
-        hin = (-a * ij) * (sj.y - m.y);
-        if (DAMP) {
-          Pin = alpha * m.z + b1 * Pin;
-          hin = alpha * m.w + b1 * hin;
+    for (int c = e0; c < e1; c += kSegChunk) {
+      int j[kSegK];
+      V2 sj[kSegK];
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        j[k] = 0;
+        a[k] = T(0);
+        m[k] = V4{};
+        if (e < e1) {
+          j[k] = ocol[e];
+          a[k] = acoef[e];
+          m[k] = msg[e];  // (P_ij, h_ij, P_ji, h_ji) as last written
         }
       }
-      S += Pin;
-      H += hin;
-      m0 = m;
-      Pin0 = Pin;
-      hin0 = hin;
-      a0 = a;
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        sj[k] = V2{};
+        if (c + k * kBlock + t < e1 && !(first && j[k] >= row1)) sj[k] = sums[j[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        Pin[k] = T(0);
+        hin[k] = T(0);
+        if (e >= e1) continue;
+        col_in<T, DAMP>(!(first && j[k] >= row1), a[k], m[k], sj[k], alpha, b1m, Pin[k], hin[k],
+                        zero);
+        V2 v;
+        v.x = Pin[k];
+        v.y = hin[k];
+        in[e - c] = v;
+      }
+      __syncthreads();
+      if (t < nr) {
+        const int lo = max(rp[t], c), hi = min(rp[t + 1], c + kSegChunk);
+        for (int e = lo; e < hi; ++e) {
+          S += in[e - c].x;
+          H += in[e - c].y;
+        }
+      }
+      __syncthreads();
     }
-    S = gsum<G>(S);
-    H = gsum<G>(H);
-    if (active) {
+    if (t < nr) {
+      const int row = r0 + t;
       S += diag[row];
       H += rhs[row];
-    }
-    // step 2: the out-messages i -> j from the new totals
-    T dp = T(0), pm = T(0);
-    for (int e = beg + lane; e < end; e += G) {
-      V4 m;
-      T Pin, hin, a;
-      if (one) {
-        m = m0;
-        Pin = Pin0;
-        hin = hin0;
-        a = a0;
-      } else {  // recompute this slot's in-message exactly as in step 1
-        a = acoef[e];
-        m = msg[e];
-        const int j = ocol[e];
-        Pin = m.z;
-        hin = m.w;
-        if (!(first && j >= row1)) {
-          const V2 sj = sums[j];
-          const T ij = T(1) / (sj.x - m.x);
-          Pin = -(a * a) * ij;
-          hin = (-a * ij) * (sj.y - m.y);
-          if (DAMP) {
-            Pin = alpha * m.z + b1 * Pin;
-            hin = alpha * m.w + b1 * hin;
-          }
-        }
-      }
-      const T ci = S - Pin;
-      zero |= ci == T(0);
-      const T ii = T(1) / ci;
-      T Pout = -(a * a) * ii, hout = (-a * ii) * (H - hin);
-      if (DAMP) {
-        Pout = alpha * m.x + b1 * Pout;
-        hout = alpha * m.y + b1 * hout;
-      }
-      if (MODE == 1) {
-        dp = fmax(dp, fabs(Pout - m.x));
-        pm = fmax(pm, fabs(Pout));
-      }
-      V4 o;
-      o.x = Pout; o.y = hout; o.z = Pin; o.w = hin;
-      msg[e] = o;
-    }
-    if (active && lane == 0) {
       V2 o;
       o.x = S;
       o.y = H;
+      tot[t] = o;
       sums[row] = o;
       if (MODE == 1) {
         if (S == T(0)) f |= FLAG_BREAKDOWN;
@@ -532,82 +511,147 @@ __global__ __launch_bounds__(kBlock) void k_pair_col(
         ax = fmax(ax, (double)fabs(x));
       }
     }
-    if (MODE == 1) {
-      dpb = fmax(dpb, (double)dp);
-      pmb = fmax(pmb, (double)pm);
+    __syncthreads();
+    // step 2: the out-messages i -> j from the new totals
+    for (int c = e0; c < e1; c += kSegChunk) {
+      if (!one) {  // recompute this chunk's in-messages exactly as in step 1
+        int j[kSegK];
+        V2 sj[kSegK];
+#pragma unroll
+        for (int k = 0; k < kSegK; ++k) {
+          const int e = c + k * kBlock + t;
+          j[k] = 0;
+          a[k] = T(0);
+          m[k] = V4{};
+          if (e < e1) {
+            j[k] = ocol[e];
+            a[k] = acoef[e];
+            m[k] = msg[e];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kSegK; ++k) {
+          sj[k] = V2{};
+          if (c + k * kBlock + t < e1 && !(first && j[k] >= row1)) sj[k] = sums[j[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kSegK; ++k) {
+          Pin[k] = T(0);
+          hin[k] = T(0);
+          if (c + k * kBlock + t < e1)
+            col_in<T, DAMP>(!(first && j[k] >= row1), a[k], m[k], sj[k], alpha, b1m, Pin[k],
+                            hin[k], zero);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        if (e >= e1) continue;
+        const V2 ti = tot[seg_row(rp, nr, e)];
+        const T ci = ti.x - Pin[k];
+        zero |= ci == T(0);
+        const T ii = T(1) / ci;
+        const T aa = a[k];
+        T Pout = -(aa * aa) * ii, hout = (-aa * ii) * (ti.y - hin[k]);
+        if (DAMP) {
+          Pout = alpha * m[k].x + b1m * Pout;
+          hout = alpha * m[k].y + b1m * hout;
+        }
+        if (MODE == 1) {
+          dp = fmax(dp, fabs(Pout - m[k].x));
+          pm = fmax(pm, fabs(Pout));
+        }
+        V4 o;
+        o.x = Pout; o.y = hout; o.z = Pin[k]; o.w = hin[k];
+        msg[e] = o;
+      }
     }
   }
   if (zero) f |= FLAG_BREAKDOWN;
   if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(d, ax, dpb, pmb, part, combine);
+  if (MODE == 1) block_publish(d, ax, (double)dp, (double)pm, part, combine);
 }
 
 // settled precisions, coloured: h_ji from H_j's broadcast, then H_i, then h_ij
-template <typename T, int G, int MODE, bool DAMP>
+template <typename T, bool DAMP>
+__device__ __forceinline__ T col_hin(bool rebuild, const typename Vec2<T>::type &c,
+                                     const typename Vec2<T>::type &h, T Hj, T alpha, T b1m) {
+#pragma clang fp contract(off)
+  T hin = h.y;
+  if (rebuild) {
+    hin = c.y * (Hj - h.x);
+    if (DAMP) hin = alpha * h.y + b1m * hin;
+  }
+  return hin;
+}
+
+template <typename T, int MODE, bool DAMP>
 __global__ __launch_bounds__(kBlock) void k_pair_frozen_col(
-    int row0, int row1, bool first, const int32_t *__restrict__ oprt,
-    const int32_t *__restrict__ ocol,
+    const int32_t *__restrict__ rb, int b0, int b1, int row1, bool first,
+    const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
     const typename Vec2<T>::type *__restrict__ coef, const T *__restrict__ rhs,
     const T *__restrict__ Sfix, typename Vec2<T>::type *hp, T *Hb, T alpha,
     T *__restrict__ xprev, BlockPartial *__restrict__ part, bool combine,
     uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
 #pragma clang fp contract(off)
   using V2 = typename Vec2<T>::type;
-  constexpr int RPB = kBlock / G;
+  __shared__ int rp[kSegRows + 1];
+  __shared__ T tot[kSegRows];
+  __shared__ T in[kSegChunk];
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
-  const int lane = threadIdx.x % G;
-  const T b1 = T(1) - alpha;
+  const int t = threadIdx.x;
+  const T b1m = T(1) - alpha;
   double d = 0.0, ax = 0.0;
   uint32_t f = 0;
-  for (int base = row0 + blockIdx.x * RPB; base < row1; base += gridDim.x * RPB) {
-    const int row = base + threadIdx.x / G;
-    const bool active = row < row1;
-    const int beg = active ? oprt[row] : 0, end = active ? oprt[row + 1] : 0;
-    const bool one = end - beg <= G;
+  for (int b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
+    const int r0 = rb[b], nr = rb[b + 1] - r0;
+    __syncthreads();
+    for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
+    __syncthreads();
+    const int e0 = rp[0], e1 = rp[nr];
+    const bool one = e1 - e0 <= kSegChunk;
+    V2 cf[kSegK], h[kSegK];
+    T hin[kSegK];
     T H = T(0);
-    V2 c0, h0;
-    T hin0 = T(0);
-    for (int e = beg + lane; e < end; e += G) {
-      const V2 c = coef[e];
-      const V2 h = hp[e];  // (h_ij, h_ji) as last written
-      const int j = ocol[e];
-      T hin = h.y;
-      if (!(first && j >= row1)) {
-        hin = c.y * (Hb[j] - h.x);
-        if (DAMP) hin = alpha * h.y + b1 * hin;
-      }
-      H += hin;
-      c0 = c;
-      h0 = h;
-      hin0 = hin;
-    }
-    H = gsum<G>(H);
-    if (active) H += rhs[row];
-    for (int e = beg + lane; e < end; e += G) {
-      V2 c, h;
-      T hin;
-      if (one) {
-        c = c0;
-        h = h0;
-        hin = hin0;
-      } else {
-        c = coef[e];
-        h = hp[e];
-        const int j = ocol[e];
-        hin = h.y;
-        if (!(first && j >= row1)) {
-          hin = c.y * (Hb[j] - h.x);
-          if (DAMP) hin = alpha * h.y + b1 * hin;
+    for (int c = e0; c < e1; c += kSegChunk) {
+      int j[kSegK];
+      T Hj[kSegK];
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        j[k] = 0;
+        cf[k] = V2{};
+        h[k] = V2{};
+        if (e < e1) {
+          j[k] = ocol[e];
+          cf[k] = coef[e];
+          h[k] = hp[e];  // (h_ij, h_ji) as last written
         }
       }
-      T hout = c.x * (H - hin);
-      if (DAMP) hout = alpha * h.x + b1 * hout;
-      V2 o;
-      o.x = hout;
-      o.y = hin;
-      hp[e] = o;
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        Hj[k] = T(0);
+        if (c + k * kBlock + t < e1 && !(first && j[k] >= row1)) Hj[k] = Hb[j[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        hin[k] = T(0);
+        if (e >= e1) continue;
+        hin[k] = col_hin<T, DAMP>(!(first && j[k] >= row1), cf[k], h[k], Hj[k], alpha, b1m);
+        in[e - c] = hin[k];
+      }
+      __syncthreads();
+      if (t < nr) {
+        const int lo = max(rp[t], c), hi = min(rp[t + 1], c + kSegChunk);
+        for (int e = lo; e < hi; ++e) H += in[e - c];
+      }
+      __syncthreads();
     }
-    if (active && lane == 0) {
+    if (t < nr) {
+      const int row = r0 + t;
+      H += rhs[row];
+      tot[t] = H;
       Hb[row] = H;
       if (MODE == 1) {
         const T x = H / Sfix[row];
@@ -615,6 +659,48 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen_col(
         d = fmax(d, (double)fabs(x - xprev[row]));
         xprev[row] = x;
         ax = fmax(ax, (double)fabs(x));
+      }
+    }
+    __syncthreads();
+    for (int c = e0; c < e1; c += kSegChunk) {
+      if (!one) {
+        int j[kSegK];
+        T Hj[kSegK];
+#pragma unroll
+        for (int k = 0; k < kSegK; ++k) {
+          const int e = c + k * kBlock + t;
+          j[k] = 0;
+          cf[k] = V2{};
+          h[k] = V2{};
+          if (e < e1) {
+            j[k] = ocol[e];
+            cf[k] = coef[e];
+            h[k] = hp[e];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kSegK; ++k) {
+          Hj[k] = T(0);
+          if (c + k * kBlock + t < e1 && !(first && j[k] >= row1)) Hj[k] = Hb[j[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kSegK; ++k) {
+          hin[k] = T(0);
+          if (c + k * kBlock + t < e1)
+            hin[k] = col_hin<T, DAMP>(!(first && j[k] >= row1), cf[k], h[k], Hj[k], alpha, b1m);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kSegK; ++k) {
+        const int e = c + k * kBlock + t;
+        if (e >= e1) continue;
+        const T Hi = tot[seg_row(rp, nr, e)];
+        T hout = cf[k].x * (Hi - hin[k]);
+        if (DAMP) hout = alpha * h[k].x + b1m * hout;
+        V2 o;
+        o.x = hout;
+        o.y = hin[k];
+        hp[e] = o;
       }
     }
   }
@@ -733,112 +819,85 @@ __global__ void k_pair_io(int n, const int64_t *__restrict__ rp, const int64_t *
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T, int G, int MODE, bool DAMP>
+template <typename T, int MODE, bool DAMP>
 static void pair_one(const PairArgs &a, hipStream_t s) {
   using V4 = typename Vec4<T>::type;
   using V2 = typename Vec2<T>::type;
   const dim3 grid(a.grid);
+  if (a.colored) {
+    if (a.frozen)
+      hipLaunchKernelGGL((k_pair_frozen_col<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.rb, a.b0,
+                         a.b1, a.row1, a.first, a.oprt, a.ocol, (const V2 *)a.coef,
+                         (const T *)a.rhs, (const T *)a.Sfix, (V2 *)a.msg_out, (T *)a.sums_out,
+                         (T)a.alpha, (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
+    else
+      hipLaunchKernelGGL((k_pair_col<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.rb, a.b0, a.b1,
+                         a.row1, a.first, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag,
+                         (const T *)a.rhs, (V4 *)a.msg_out, (V2 *)a.sums_out, (T)a.alpha,
+                         (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
+    return;
+  }
   if (a.frozen)
-    hipLaunchKernelGGL((k_pair_frozen_col<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.row0,
-                       a.row1, a.first, a.oprt, a.ocol, (const V2 *)a.coef, (const T *)a.rhs,
-                       (const T *)a.Sfix, (V2 *)a.msg_out, (T *)a.sums_out, (T)a.alpha,
-                       (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
-  else
-    hipLaunchKernelGGL((k_pair_col<T, G, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.row0, a.row1,
-                       a.first, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,
-                       (V4 *)a.msg_out, (V2 *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part,
-                       a.combine, a.sticky, a.ctl);
-}
-
-template <typename T, int MODE, bool DAMP>
-static void pair_sync(const PairArgs &a, hipStream_t s) {
-  using V4 = typename Vec4<T>::type;
-  using V2 = typename Vec2<T>::type;
-  const dim3 grid(a.grid);
-  if (a.frozen)
-    hipLaunchKernelGGL((k_pair_frozen<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.n, a.oprt,
-                       a.ocol, (const V2 *)a.coef, (const T *)a.rhs, (const T *)a.Sfix,
+    hipLaunchKernelGGL((k_pair_frozen<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.rb, a.b0, a.b1,
+                       a.oprt, a.ocol, (const V2 *)a.coef, (const T *)a.rhs, (const T *)a.Sfix,
                        (const V2 *)a.msg_in, (V2 *)a.msg_out, (const T *)a.sums_in,
                        (T *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part, a.sticky, a.ctl);
   else
-    hipLaunchKernelGGL((k_pair_sweep<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.n, a.oprt,
-                       a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,
+    hipLaunchKernelGGL((k_pair_sweep<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.rb, a.b0, a.b1,
+                       a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,
                        (const V4 *)a.msg_in, (V4 *)a.msg_out, (const V2 *)a.sums_in,
                        (V2 *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part, a.sticky, a.ctl);
 }
 
 template <typename T>
-static hipError_t pair_sync_t(const PairArgs &a, hipStream_t s) {
-  if (a.mode == 1) a.damp ? pair_sync<T, 1, true>(a, s) : pair_sync<T, 1, false>(a, s);
-  else a.damp ? pair_sync<T, 0, true>(a, s) : pair_sync<T, 0, false>(a, s);
-  return hipGetLastError();
-}
-
-int pair_sweep_blocks(int n, int cap) {
-  const int need = (n + kSegRows - 1) / kSegRows;
-  return need < cap ? (need > 0 ? need : 1) : cap;
-}
-
-template <typename T, int G>
-static void pair_mode(const PairArgs &a, hipStream_t s) {
-  if (a.mode == 1) a.damp ? pair_one<T, G, 1, true>(a, s) : pair_one<T, G, 1, false>(a, s);
-  else a.damp ? pair_one<T, G, 0, true>(a, s) : pair_one<T, G, 0, false>(a, s);
-}
-
-template <typename T>
-static hipError_t pair_group(const PairArgs &a, hipStream_t s) {
-  switch (a.group) {
-    case 4: pair_mode<T, 4>(a, s); break;
-    case 8: pair_mode<T, 8>(a, s); break;
-    case 16: pair_mode<T, 16>(a, s); break;
-    case 32: pair_mode<T, 32>(a, s); break;
-    case 64: pair_mode<T, 64>(a, s); break;
-    default: return hipErrorInvalidValue;
-  }
+static hipError_t pair_t(const PairArgs &a, hipStream_t s) {
+  if (a.mode == 1) a.damp ? pair_one<T, 1, true>(a, s) : pair_one<T, 1, false>(a, s);
+  else a.damp ? pair_one<T, 0, true>(a, s) : pair_one<T, 0, false>(a, s);
   return hipGetLastError();
 }
 
 hipError_t launch_pair_sweep(const PairArgs &a, hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
-  if (!a.colored) return a.fp32 ? pair_sync_t<float>(a, s) : pair_sync_t<double>(a, s);
-  return a.fp32 ? pair_group<float>(a, s) : pair_group<double>(a, s);
+  if (a.b1 <= a.b0 && !(a.colored && a.mode == 1)) return hipSuccess;
+  return a.fp32 ? pair_t<float>(a, s) : pair_t<double>(a, s);
 }
 
-template <typename T>
-static hipError_t aggregate_t(int group, int nblk, int n, const int32_t *oprt, const void *diag,
-                              const void *rhs, const void *msg, void *sums, hipStream_t s) {
-  using V4 = typename Vec4<T>::type;
-  using V2 = typename Vec2<T>::type;
-  const dim3 grid(nblk);
-  switch (group) {
-    case 4: hipLaunchKernelGGL((k_pair_aggregate<T, 4>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
-    case 8: hipLaunchKernelGGL((k_pair_aggregate<T, 8>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
-    case 16: hipLaunchKernelGGL((k_pair_aggregate<T, 16>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
-    case 32: hipLaunchKernelGGL((k_pair_aggregate<T, 32>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
-    case 64: hipLaunchKernelGGL((k_pair_aggregate<T, 64>), grid, dim3(kBlock), 0, s, n, oprt, (const T *)diag, (const T *)rhs, (const V4 *)msg, (V2 *)sums); break;
-    default: return hipErrorInvalidValue;
+std::vector<int32_t> pair_row_blocks(const int32_t *rp, const std::vector<int> &bounds,
+                                     std::vector<int> *first_block) {
+  std::vector<int32_t> rb;
+  first_block->clear();
+  rb.push_back(bounds.empty() ? 0 : bounds[0]);
+  for (size_t k = 0; k + 1 < bounds.size(); ++k) {
+    first_block->push_back((int)rb.size() - 1);
+    int r = bounds[k];
+    while (r < bounds[k + 1]) {
+      const int start = r;
+      int64_t slots = 0;
+      while (r < bounds[k + 1] && r - start < kSegRows) {
+        const int64_t len = (int64_t)rp[r + 1] - rp[r];
+        if (r > start && slots + len > kSegChunk) break;
+        slots += len;
+        ++r;
+      }
+      rb.push_back(r);
+    }
   }
-  return hipGetLastError();
+  first_block->push_back((int)rb.size() - 1);
+  return rb;
 }
 
-hipError_t launch_pair_aggregate(bool fp32, int group, int grid, int n, const int32_t *oprt,
-                                 const void *diag, const void *rhs, const void *msg, void *sums,
-                                 hipStream_t s) {
+hipError_t launch_pair_aggregate(bool fp32, int n, const int32_t *oprt, const void *diag,
+                                 const void *rhs, const void *msg, void *sums, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (group == 0) {  // slot order (synchronous plans)
-    const dim3 g((n + kBlock - 1) / kBlock);
-    if (fp32)
-      hipLaunchKernelGGL(k_pair_aggregate_seq<float>, g, dim3(kBlock), 0, s, n, oprt,
-                         (const float *)diag, (const float *)rhs, (const float4 *)msg,
-                         (float2 *)sums);
-    else
-      hipLaunchKernelGGL(k_pair_aggregate_seq<double>, g, dim3(kBlock), 0, s, n, oprt,
-                         (const double *)diag, (const double *)rhs, (const double4 *)msg,
-                         (double2 *)sums);
-    return hipGetLastError();
-  }
-  return fp32 ? aggregate_t<float>(group, grid, n, oprt, diag, rhs, msg, sums, s)
-              : aggregate_t<double>(group, grid, n, oprt, diag, rhs, msg, sums, s);
+  const dim3 g((n + kBlock - 1) / kBlock);
+  if (fp32)
+    hipLaunchKernelGGL(k_pair_aggregate<float>, g, dim3(kBlock), 0, s, n, oprt,
+                       (const float *)diag, (const float *)rhs, (const float4 *)msg,
+                       (float2 *)sums);
+  else
+    hipLaunchKernelGGL(k_pair_aggregate<double>, g, dim3(kBlock), 0, s, n, oprt,
+                       (const double *)diag, (const double *)rhs, (const double4 *)msg,
+                       (double2 *)sums);
+  return hipGetLastError();
 }
 
 hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s) {
