@@ -183,7 +183,7 @@ struct CsrEngine : Engine {
     hipError_t err;
     if ((err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
     if ((err = launch_fill_zero(msg[1], words, s)) != hipSuccess) return err;
-    if ((err = launch_residual(fp32, group, nsum, n, A.row_ptr, A.col, A.val, b, nullptr, rhs,
+    if ((err = launch_residual(fp32, nsum, n, A.row_ptr, A.col, A.val, b, nullptr, rhs,
                                nullptr, sumpart, s)) != hipSuccess)
       return err;
     if (pair) return launch_pair_aggregate(fp32, n, oprt, diag, rhs, msg[0], sums[0], s);
@@ -191,7 +191,7 @@ struct CsrEngine : Engine {
   }
 
   hipError_t residual(const double *b, const double *x, double *r64, hipStream_t s) override {
-    return launch_residual(fp32, group, nsum, n, A.row_ptr, A.col, A.val, b, x, rhs, r64,
+    return launch_residual(fp32, nsum, n, A.row_ptr, A.col, A.val, b, x, rhs, r64,
                            sumpart, s);
   }
 
@@ -214,8 +214,10 @@ struct CsrEngine : Engine {
   }
 
   hipError_t freeze(hipStream_t s) override {
-    hipError_t err = launch_pair_freeze(fp32, group, grid, n, oprt, ocol, colored() ? rev : nullptr,
-                                        acoef, msg[cur], sums[cur], coef, hp[cur], Sfix, Hfz[cur], s);
+    const int nblk = bfirst.back();
+    hipError_t err = launch_pair_freeze(fp32, std::min(nblk, kMaxSweepBlocks), rblk, nblk, oprt, ocol,
+                                        colored() ? rev : nullptr, acoef, msg[cur], sums[cur], coef,
+                                        hp[cur], Sfix, Hfz[cur], s);
     frozen = true;
     return err;
   }
@@ -349,7 +351,7 @@ int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int
   e->nparts = e->grid;
   if (classes) e->cls = *classes;
   if (e->pair && (st = e->row_blocks(cap, s))) return fail(st);
-  e->nsum = residual_blocks(std::max(e->n, 1), e->group, cap);
+  e->nsum = residual_blocks(std::max(e->n, 1), cap);
   if ((st = e->init_common(s))) return fail(st);
   if ((st = from_hip(dalloc(&e->msg[0], e->E, e->msg_bytes()))) ||
       (st = from_hip(dalloc(&e->msg[1], e->E, e->msg_bytes()))) ||
@@ -403,9 +405,7 @@ int gabp_residual(const gabp_csr *A, const double *b, const double *x, double *r
   if (rc) return rc;
   if (!rel_norm || (A->n > 0 && (!b || !x))) return GABP_ERR_ARG;
   if (A->n == 0) { *rel_norm = 0.0; return GABP_OK; }
-  const int64_t nnzE = A->nnz - A->n;
-  const int g = choose_group(A->n, std::max<int64_t>(0, nnzE));
-  const int nb = residual_blocks(A->n, g);
+  const int nb = residual_blocks(A->n);
   double *sum = nullptr;
   int64_t *deg = nullptr, *dpos = nullptr;
   uint32_t *flags = nullptr;
@@ -434,10 +434,10 @@ int gabp_residual(const gabp_csr *A, const double *b, const double *x, double *r
       (rc = from_hip(hipStreamSynchronize(s))))
     return cleanup(rc);
   if (hflags & FLAG_ARG) return cleanup(GABP_ERR_ARG);
-  if ((rc = from_hip(launch_residual(false, g, nb, A->n, A->row_ptr, A->col, A->val, b, nullptr,
+  if ((rc = from_hip(launch_residual(false, nb, A->n, A->row_ptr, A->col, A->val, b, nullptr,
                                      nullptr, nullptr, sum, s))) ||
       (rc = from_hip(launch_readout(nullptr, 0, sum, nb, nullptr, nullptr, 0, 0, &host[0], s))) ||
-      (rc = from_hip(launch_residual(false, g, nb, A->n, A->row_ptr, A->col, A->val, b, x, nullptr,
+      (rc = from_hip(launch_residual(false, nb, A->n, A->row_ptr, A->col, A->val, b, x, nullptr,
                                      r, sum, s))) ||
       (rc = from_hip(launch_readout(nullptr, 0, sum, nb, nullptr, nullptr, 0, 1, &host[1], s))) ||
       (rc = from_hip(hipEventRecord(ev, s))) || (rc = from_hip(hipEventSynchronize(ev))))

@@ -127,10 +127,13 @@ struct SweepArgs {
 int sweep_blocks(int n, int group, int cap = kMaxSweepBlocks);
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t s);
 
-hipError_t launch_residual(bool fp32, int group, int grid, int n, const int64_t *rp, const int32_t *col,
+// FP64 r = b - A x (x == NULL: r = b) over a CSR matrix, optionally rounded
+// to the message type (rT), and one partial sum of r^2 per workgroup (grid =
+// residual_blocks(n))
+hipError_t launch_residual(bool fp32, int grid, int n, const int64_t *rp, const int32_t *col,
                            const double *val, const double *b, const double *x, void *rT,
                            double *r64, double *sumpart, hipStream_t s);
-int residual_blocks(int n, int group, int cap = kMaxSweepBlocks);
+int residual_blocks(int n, int cap = kMaxSweepBlocks);
 
 // Reduce residual partials and (nparts > 0) the check partials, update the
 // controller, write the host readout slot.
@@ -205,11 +208,12 @@ hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s);
 hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfix, const void *Hfz,
                              double *xacc, double *marg, void *means, uint32_t *sticky,
                              hipStream_t s);
-// rev: NULL, or the reverse-slot index (coloured plans; see k_pair_freeze)
-hipError_t launch_pair_freeze(bool fp32, int group, int grid, int n, const int32_t *oprt,
-                              const int32_t *ocol, const int32_t *rev, const void *acoef,
-                              const void *msg, const void *sums, void *coef, void *hp, void *Sfix,
-                              void *Hfz, hipStream_t s);
+// Settled-precision coefficients over the row blocks [0, nblk) of rb; rev:
+// NULL, or the reverse-slot index (coloured plans; see k_pair_freeze)
+hipError_t launch_pair_freeze(bool fp32, int grid, const int32_t *rb, int nblk,
+                              const int32_t *oprt, const int32_t *ocol, const int32_t *rev,
+                              const void *acoef, const void *msg, const void *sums, void *coef,
+                              void *hp, void *Sfix, void *Hfz, hipStream_t s);
 hipError_t launch_frozen_restart(bool fp32, int64_t E, int n, void *hp, const void *rhs, void *Hfz,
                                  hipStream_t s);
 hipError_t launch_pair_io(bool fp32, bool get, int n, const int64_t *rp, const int64_t *diagpos,

@@ -381,65 +381,97 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // FP64 residual r = b - A x over the caller's CSR, with per-block sums of r^2
 // ---------------------------------------------------------------------------
-template <typename T, int G>
+// A workgroup takes kResRows consecutive rows and streams their entries in
+// chunks of kResChunk (thread t: entries c + t, c + t + kBlock, ...; all lanes
+// busy, four gathers of x in flight per thread); the products go to LDS and
+// the row's own thread adds them in entry order.
+constexpr int kResRows = 64;
+constexpr int kResK = 4;
+constexpr int kResChunk = kBlock * kResK;
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_csr_residual(
     int n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
     T *__restrict__ rT, double *__restrict__ r64, double *__restrict__ sumpart) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G;
+  __shared__ int64_t rps[kResRows + 1];
+  __shared__ double prod[kResChunk];
+  __shared__ double sh[kBlock / 64];
+  const int t = threadIdx.x;
   double sq = 0.0;
-  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
-    const int row = base + threadIdx.x / G;
-    const bool active = row < n;
+  for (int r0 = blockIdx.x * kResRows; r0 < n; r0 += gridDim.x * kResRows) {
+    const int nr = min(kResRows, n - r0);
+    __syncthreads();
+    for (int k = t; k <= nr; k += kBlock) rps[k] = rp[r0 + k];
+    __syncthreads();
+    const int64_t e0 = rps[0], e1 = rps[nr];
     double acc = 0.0;
-    if (active && x != nullptr)
-      for (int64_t k = rp[row] + lane; k < rp[row + 1]; k += G) acc += val[k] * x[col[k]];
-    acc = gsum<G>(acc);
-    if (active && lane == 0) {
+    if (x != nullptr) {
+      for (int64_t c = e0; c < e1; c += kResChunk) {
+        int j[kResK];
+        double v[kResK], xv[kResK];
+#pragma unroll
+        for (int k = 0; k < kResK; ++k) {
+          const int64_t e = c + k * kBlock + t;
+          j[k] = 0;
+          v[k] = 0.0;
+          if (e < e1) {
+            j[k] = col[e];
+            v[k] = val[e];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kResK; ++k) {
+          xv[k] = 0.0;
+          if (c + k * kBlock + t < e1) xv[k] = x[j[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kResK; ++k)
+          if (c + k * kBlock + t < e1) prod[k * kBlock + t] = v[k] * xv[k];
+        __syncthreads();
+        if (t < nr) {
+          const int64_t lo = rps[t] > c ? rps[t] : c;
+          const int64_t hi = rps[t + 1] < c + kResChunk ? rps[t + 1] : c + kResChunk;
+          for (int64_t e = lo; e < hi; ++e) acc += prod[e - c];
+        }
+        __syncthreads();
+      }
+    }
+    if (t < nr) {
+      const int row = r0 + t;
       const double ri = b[row] - acc;
       if (rT) rT[row] = (T)ri;
       if (r64) r64[row] = ri;
       sq += ri * ri;
     }
   }
-  __shared__ double sh[kBlock / 64];
   sq = wave_sum(sq);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x / 64] = sq;
+  if ((t & 63) == 0) sh[t / 64] = sq;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = sh[0];
+  if (t == 0) {
+    double tot = sh[0];
 #pragma unroll
-    for (int k = 1; k < kBlock / 64; ++k) t += sh[k];
-    sumpart[blockIdx.x] = t;
+    for (int k = 1; k < kBlock / 64; ++k) tot += sh[k];
+    sumpart[blockIdx.x] = tot;
   }
 }
 
-int residual_blocks(int n, int group, int cap) { return sweep_blocks(n, group, cap); }
-
-template <typename T>
-static hipError_t residual_group(int group, int nblk, int n, const int64_t *rp,
-                                 const int32_t *col, const double *val, const double *b,
-                                 const double *x, T *rT, double *r64, double *sumpart,
-                                 hipStream_t s) {
-  const dim3 grid(nblk);
-  switch (group) {
-    case 4: hipLaunchKernelGGL((k_csr_residual<T, 4>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
-    case 8: hipLaunchKernelGGL((k_csr_residual<T, 8>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
-    case 16: hipLaunchKernelGGL((k_csr_residual<T, 16>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
-    case 32: hipLaunchKernelGGL((k_csr_residual<T, 32>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
-    case 64: hipLaunchKernelGGL((k_csr_residual<T, 64>), grid, dim3(kBlock), 0, s, n, rp, col, val, b, x, rT, r64, sumpart); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+int residual_blocks(int n, int cap) {
+  const int need = (n + kResRows - 1) / kResRows;
+  return need < cap ? (need > 0 ? need : 1) : cap;
 }
 
-hipError_t launch_residual(bool fp32, int group, int grid, int n, const int64_t *rp,
-                           const int32_t *col, const double *val, const double *b, const double *x,
-                           void *rT, double *r64, double *sumpart, hipStream_t s) {
+hipError_t launch_residual(bool fp32, int grid, int n, const int64_t *rp, const int32_t *col,
+                           const double *val, const double *b, const double *x, void *rT,
+                           double *r64, double *sumpart, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  return fp32 ? residual_group<float>(group, grid, n, rp, col, val, b, x, (float *)rT, r64, sumpart, s)
-              : residual_group<double>(group, grid, n, rp, col, val, b, x, (double *)rT, r64, sumpart, s);
+  if (fp32)
+    hipLaunchKernelGGL(k_csr_residual<float>, dim3(grid), dim3(kBlock), 0, s, n, rp, col, val, b,
+                       x, (float *)rT, r64, sumpart);
+  else
+    hipLaunchKernelGGL(k_csr_residual<double>, dim3(grid), dim3(kBlock), 0, s, n, rp, col, val, b,
+                       x, (double *)rT, r64, sumpart);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

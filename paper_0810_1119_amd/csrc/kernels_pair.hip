@@ -242,36 +242,43 @@ __global__ void k_pair_infer(int n, const typename Vec2<T>::type *__restrict__ s
 // the sender uses for its out-coefficient.  In a synchronous state every pair
 // of copies is equal; in a coloured one a row that sent after j holds a newer
 // P_ij than the one j used, and the two copies of c_ji must still agree.
-template <typename T, int G>
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pair_freeze(
-    int n, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
-    const int32_t *__restrict__ rev, const T *__restrict__ acoef,
+    const int32_t *__restrict__ rb, int nblk, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ ocol, const int32_t *__restrict__ rev, const T *__restrict__ acoef,
     const typename Vec4<T>::type *__restrict__ msg,
     const typename Vec2<T>::type *__restrict__ sums, typename Vec2<T>::type *__restrict__ coef,
     typename Vec2<T>::type *__restrict__ hp, T *__restrict__ Sfix, T *__restrict__ Hfz) {
 #pragma clang fp contract(off)
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G;
-  for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
-    const int row = base + threadIdx.x / G;
-    if (row >= n) continue;
-    const T Si = sums[row].x;
-    for (int e = oprt[row] + lane; e < oprt[row + 1]; e += G) {
+  using V2 = typename Vec2<T>::type;
+  __shared__ int rp[kSegRows + 1];
+  __shared__ T own[kSegRows];
+  const int t = threadIdx.x;
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int r0 = rb[b], nr = rb[b + 1] - r0;
+    __syncthreads();
+    for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
+    for (int k = t; k < nr; k += kBlock) {
+      const V2 si = sums[r0 + k];
+      own[k] = si.x;
+      Sfix[r0 + k] = si.x;
+      Hfz[r0 + k] = si.y;
+    }
+    __syncthreads();
+    const int e1 = rp[nr];
+    for (int e = rp[0] + t; e < e1; e += kBlock) {
       const int j = ocol[e];
       const T a = acoef[e];
       const auto m = msg[e];
-      typename Vec2<T>::type c, h;
-      c.x = -a * (T(1) / (Si - m.z));  // c_ij: out-message coefficient
+      const T Si = own[seg_row(rp, nr, e)];
+      V2 c, h;
+      c.x = -a * (T(1) / (Si - m.z));           // c_ij: out-message coefficient
       const T Pij = rev ? msg[rev[e]].z : m.x;  // P_ij as the sender j holds it
-      c.y = -a * (T(1) / (sums[j].x - Pij));  // c_ji: in-message coefficient
+      c.y = -a * (T(1) / (sums[j].x - Pij));    // c_ji: in-message coefficient
       h.x = m.y;
       h.y = m.w;
       coef[e] = c;
       hp[e] = h;
-    }
-    if (lane == 0) {
-      Sfix[row] = Si;
-      Hfz[row] = sums[row].y;
     }
   }
 }
@@ -923,37 +930,20 @@ hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfi
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t freeze_t(int group, int nblk, int n, const int32_t *oprt, const int32_t *ocol,
-                           const int32_t *rev, const void *acoef, const void *msg,
-                           const void *sums, void *coef, void *hp, void *Sfix, void *Hfz,
-                           hipStream_t s) {
-  using V4 = typename Vec4<T>::type;
-  using V2 = typename Vec2<T>::type;
-  const dim3 grid(nblk);
-#define FREEZE_CASE(GG)                                                                          \
-  case GG:                                                                                       \
-    hipLaunchKernelGGL((k_pair_freeze<T, GG>), grid, dim3(kBlock), 0, s, n, oprt, ocol, rev,   \
-                       (const T *)acoef, (const V4 *)msg, (const V2 *)sums, (V2 *)coef, (V2 *)hp, \
-                       (T *)Sfix, (T *)Hfz);                                                     \
-    break;
-  switch (group) {
-    FREEZE_CASE(4) FREEZE_CASE(8) FREEZE_CASE(16) FREEZE_CASE(32) FREEZE_CASE(64)
-    default: return hipErrorInvalidValue;
-  }
-#undef FREEZE_CASE
+hipError_t launch_pair_freeze(bool fp32, int grid, const int32_t *rb, int nblk,
+                              const int32_t *oprt, const int32_t *ocol, const int32_t *rev,
+                              const void *acoef, const void *msg, const void *sums, void *coef,
+                              void *hp, void *Sfix, void *Hfz, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_pair_freeze<float>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, oprt, ocol,
+                       rev, (const float *)acoef, (const float4 *)msg, (const float2 *)sums,
+                       (float2 *)coef, (float2 *)hp, (float *)Sfix, (float *)Hfz);
+  else
+    hipLaunchKernelGGL(k_pair_freeze<double>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, oprt, ocol,
+                       rev, (const double *)acoef, (const double4 *)msg, (const double2 *)sums,
+                       (double2 *)coef, (double2 *)hp, (double *)Sfix, (double *)Hfz);
   return hipGetLastError();
-}
-
-hipError_t launch_pair_freeze(bool fp32, int group, int grid, int n, const int32_t *oprt,
-                              const int32_t *ocol, const int32_t *rev, const void *acoef,
-                              const void *msg, const void *sums, void *coef, void *hp, void *Sfix,
-                              void *Hfz, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  return fp32 ? freeze_t<float>(group, grid, n, oprt, ocol, rev, acoef, msg, sums, coef, hp, Sfix,
-                                Hfz, s)
-              : freeze_t<double>(group, grid, n, oprt, ocol, rev, acoef, msg, sums, coef, hp, Sfix,
-                                 Hfz, s);
 }
 
 hipError_t launch_frozen_restart(bool fp32, int64_t E, int n, void *hp, const void *rhs, void *Hfz,

@@ -230,10 +230,16 @@ def test_colored_warm_start_matches_synchronous_placement(G):
     assert _grid_rel(nx, nx, nx, bt, coef, host(b), host(x)) <= 1e-8
 
 
-def test_colored_schedule_needs_a_two_colourable_plan(G):
+def test_colored_schedule_support_per_plan_kind(G):
+    """General CSR plans colour their graph in the pair layout (the gather
+    layout has no coloured sweep); dense batches of instances that are not
+    bipartite are refused; an unknown schedule is an argument error."""
     m = W.sdd_random(64, 1)
-    rc, plan = G.gabp_plan_create(G.DeviceCSR.from_host(m), opts(G))
+    rc, plan = G.gabp_plan_create(G.DeviceCSR.from_host(m), opts(G, layout=1))
     assert rc == G.GABP_ERR_UNSUPPORTED and plan is None
+    rc, plan = G.gabp_plan_create(G.DeviceCSR.from_host(m), opts(G))
+    assert rc == G.GABP_OK
+    G.gabp_plan_destroy(plan)
     B = G.DeviceBatch.dense([3], (2.0 * np.eye(3)).ravel())
     rc, plan = G.gabp_plan_create_batched(B, opts(G))
     assert rc == G.GABP_ERR_UNSUPPORTED
