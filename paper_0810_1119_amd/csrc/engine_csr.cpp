@@ -85,6 +85,9 @@ struct CsrEngine : Engine {
 
   bool colored() const { return !cls.empty(); }
 
+  // workgroups of a launch over all row blocks
+  int bgrid() const { return std::max(1, std::min(bfirst.back(), kMaxSweepBlocks)); }
+
   hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
     hipError_t err;
     if (colored()) {
@@ -172,7 +175,7 @@ struct CsrEngine : Engine {
     // one half sweep old; make every copy the sender's current message
     if (colored() && (err = launch_pair_sync_in(fp32, E, rev, msg[cur], s)) != hipSuccess)
       return err;
-    return launch_pair_aggregate(fp32, n, oprt, diag, rhs, msg[cur], sums[cur], s);
+    return launch_pair_aggregate(fp32, bgrid(), rblk, bfirst.back(), oprt, diag, rhs, msg[cur], sums[cur], s);
   }
 
   hipError_t reset(const double *b, hipStream_t s) override {
@@ -186,7 +189,7 @@ struct CsrEngine : Engine {
     if ((err = launch_residual(fp32, nsum, n, A.row_ptr, A.col, A.val, b, nullptr, rhs,
                                nullptr, sumpart, s)) != hipSuccess)
       return err;
-    if (pair) return launch_pair_aggregate(fp32, n, oprt, diag, rhs, msg[0], sums[0], s);
+    if (pair) return launch_pair_aggregate(fp32, bgrid(), rblk, bfirst.back(), oprt, diag, rhs, msg[0], sums[0], s);
     return hipSuccess;
   }
 
@@ -214,8 +217,7 @@ struct CsrEngine : Engine {
   }
 
   hipError_t freeze(hipStream_t s) override {
-    const int nblk = bfirst.back();
-    hipError_t err = launch_pair_freeze(fp32, std::min(nblk, kMaxSweepBlocks), rblk, nblk, oprt, ocol,
+    hipError_t err = launch_pair_freeze(fp32, bgrid(), rblk, bfirst.back(), oprt, ocol,
                                         colored() ? rev : nullptr, acoef, msg[cur], sums[cur], coef,
                                         hp[cur], Sfix, Hfz[cur], s);
     frozen = true;
@@ -238,7 +240,7 @@ struct CsrEngine : Engine {
     if (pair) {
       TRY_HIP(launch_pair_io(fp32, false, n, A.row_ptr, diagpos, oprt, rev, msg[cur], (double *)P,
                              (double *)h, s));
-      TRY_HIP(launch_pair_aggregate(fp32, n, oprt, diag, rhs, msg[cur], sums[cur], s));
+      TRY_HIP(launch_pair_aggregate(fp32, bgrid(), rblk, bfirst.back(), oprt, diag, rhs, msg[cur], sums[cur], s));
     } else {
       TRY_HIP(launch_set_msgs(fp32, n, A.row_ptr, diagpos, oprt, msg[cur], P, h, s));
     }

@@ -200,10 +200,11 @@ hipError_t launch_pair_col_infer(const PairArgs &a, double *xacc, double *marg, 
                                  hipStream_t s);
 // msg[e].P_ji := msg[rev[e]].P_ij for every slot (pair layout)
 hipError_t launch_pair_sync_in(bool fp32, int64_t E, const int32_t *rev, void *msg, hipStream_t s);
-// (S, H) from the stored in-messages, a row's added in slot order (the sweeps'
-// order)
-hipError_t launch_pair_aggregate(bool fp32, int n, const int32_t *oprt, const void *diag,
-                                 const void *rhs, const void *msg, void *sums, hipStream_t s);
+// (S, H) from the stored in-messages over the row blocks [0, nblk) of rb, a
+// row's added in slot order (the sweeps' order)
+hipError_t launch_pair_aggregate(bool fp32, int grid, const int32_t *rb, int nblk,
+                                 const int32_t *oprt, const void *diag, const void *rhs,
+                                 const void *msg, void *sums, hipStream_t s);
 hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s);
 hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfix, const void *Hfz,
                              double *xacc, double *marg, void *means, uint32_t *sticky,

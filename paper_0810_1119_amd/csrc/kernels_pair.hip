@@ -179,26 +179,51 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
 }
 
 // Aggregate (S, H) from the slots' incoming messages: used after reset,
-// message import and restarts.  A row's in-messages are added in slot order,
-// one thread per row, exactly as the sweeps add them, so that imported
-// messages resume a solve bit for bit.
+// message import and restarts.  Row blocks as in the sweeps; a row's
+// in-messages are added in slot order, exactly as the sweeps add them, so that
+// imported messages resume a solve bit for bit.
 template <typename T>
-__global__ void k_pair_aggregate(int n, const int32_t *__restrict__ oprt,
-                                     const T *__restrict__ diag, const T *__restrict__ rhs,
-                                     const typename Vec4<T>::type *__restrict__ msg,
-                                     typename Vec2<T>::type *__restrict__ sums) {
+__global__ __launch_bounds__(kBlock) void k_pair_aggregate(
+    const int32_t *__restrict__ rb, int nblk, const int32_t *__restrict__ oprt,
+    const T *__restrict__ diag, const T *__restrict__ rhs,
+    const typename Vec4<T>::type *__restrict__ msg, typename Vec2<T>::type *__restrict__ sums) {
 #pragma clang fp contract(off)
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  T S = T(0), H = T(0);
-  for (int e = oprt[row]; e < oprt[row + 1]; ++e) {
-    S += msg[e].z;
-    H += msg[e].w;
+  using V2 = typename Vec2<T>::type;
+  __shared__ int rp[kSegRows + 1];
+  __shared__ V2 in[kSegChunk];
+  const int t = threadIdx.x;
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int r0 = rb[b], nr = rb[b + 1] - r0;
+    __syncthreads();
+    for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
+    __syncthreads();
+    const int e0 = rp[0], e1 = rp[nr];
+    T S = T(0), H = T(0);
+    for (int c = e0; c < e1; c += kSegChunk) {
+      for (int e = c + t; e < e1 && e < c + kSegChunk; e += kBlock) {
+        const auto m = msg[e];
+        V2 v;
+        v.x = m.z;
+        v.y = m.w;
+        in[e - c] = v;
+      }
+      __syncthreads();
+      if (t < nr) {
+        const int lo = max(rp[t], c), hi = min(rp[t + 1], c + kSegChunk);
+        for (int e = lo; e < hi; ++e) {
+          S += in[e - c].x;
+          H += in[e - c].y;
+        }
+      }
+      __syncthreads();
+    }
+    if (t < nr) {
+      V2 o;
+      o.x = S + diag[r0 + t];
+      o.y = H + rhs[r0 + t];
+      sums[r0 + t] = o;
+    }
   }
-  typename Vec2<T>::type o;
-  o.x = S + diag[row];
-  o.y = H + rhs[row];
-  sums[row] = o;
 }
 
 // Zero every information field (restart) and re-aggregate H = rhs.
@@ -892,16 +917,16 @@ std::vector<int32_t> pair_row_blocks(const int32_t *rp, const std::vector<int> &
   return rb;
 }
 
-hipError_t launch_pair_aggregate(bool fp32, int n, const int32_t *oprt, const void *diag,
-                                 const void *rhs, const void *msg, void *sums, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const dim3 g((n + kBlock - 1) / kBlock);
+hipError_t launch_pair_aggregate(bool fp32, int grid, const int32_t *rb, int nblk,
+                                 const int32_t *oprt, const void *diag, const void *rhs,
+                                 const void *msg, void *sums, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL(k_pair_aggregate<float>, g, dim3(kBlock), 0, s, n, oprt,
+    hipLaunchKernelGGL(k_pair_aggregate<float>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, oprt,
                        (const float *)diag, (const float *)rhs, (const float4 *)msg,
                        (float2 *)sums);
   else
-    hipLaunchKernelGGL(k_pair_aggregate<double>, g, dim3(kBlock), 0, s, n, oprt,
+    hipLaunchKernelGGL(k_pair_aggregate<double>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, oprt,
                        (const double *)diag, (const double *)rhs, (const double4 *)msg,
                        (double2 *)sums);
   return hipGetLastError();
