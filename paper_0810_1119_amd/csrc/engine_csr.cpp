@@ -154,7 +154,10 @@ struct CsrEngine : Engine {
       for (size_t k = 0; k + 1 < cls.size(); ++k) {
         a.row0 = cls[k];
         a.row1 = cls[k + 1];
-        a.grid = sweep_blocks(std::max(a.row1 - a.row0, 1), group, grid);
+        a.rb = rblk;
+        a.b0 = bfirst[k];
+        a.b1 = bfirst[k + 1];
+        a.grid = std::max(1, std::min(a.b1 - a.b0, kMaxSweepBlocks));
         hipError_t err = launch_pair_col_infer(a, xacc, marg, means, s);
         if (err != hipSuccess) return err;
       }

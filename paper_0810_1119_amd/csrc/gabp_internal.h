@@ -192,10 +192,10 @@ hipError_t launch_pair_sweep(const PairArgs &a, hipStream_t s);
 // the first block of range k (first_block.back() = the number of blocks).
 std::vector<int32_t> pair_row_blocks(const int32_t *rp, const std::vector<int> &bounds,
                                      std::vector<int> *first_block);
-// marginals of one class (rows [row0, row1)) of a coloured pair plan from its
-// current messages after a complete sweep (msg_in / sums_in: the full state,
-// or in the settled state the information pairs and H broadcasts, with coef
-// and Sfix)
+// marginals of one class (rows [row0, row1), row blocks [b0, b1) of rb) of a
+// coloured pair plan from its current messages after a complete sweep
+// (msg_in / sums_in: the full state, or in the settled state the information
+// pairs and H broadcasts, with coef and Sfix)
 hipError_t launch_pair_col_infer(const PairArgs &a, double *xacc, double *marg, void *means,
                                  hipStream_t s);
 // msg[e].P_ji := msg[rev[e]].P_ij for every slot (pair layout)

@@ -748,56 +748,73 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen_col(
 // classes are rebuilt from the senders' broadcasts (they were computed from
 // this row's current out-messages).  Full state: (S, H) from the in-messages;
 // settled: S fixed, H rebuilt.
-template <typename T, int G, bool DAMP, bool FROZEN>
+template <typename T, bool DAMP, bool FROZEN>
 __global__ __launch_bounds__(kBlock) void k_pair_col_infer(
-    int row0, int row1, const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
-    const T *__restrict__ acoef, const T *__restrict__ diag, const T *__restrict__ rhs,
-    const typename Vec4<T>::type *__restrict__ msg, const typename Vec2<T>::type *__restrict__ sums,
-    const typename Vec2<T>::type *__restrict__ coef, const typename Vec2<T>::type *__restrict__ hp,
-    const T *__restrict__ Sfix, const T *__restrict__ Hb, T alpha, double *__restrict__ xacc,
-    double *__restrict__ marg, T *__restrict__ means, uint32_t *__restrict__ sticky) {
+    const int32_t *__restrict__ rb, int b0, int b1, int row1, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ ocol, const T *__restrict__ acoef, const T *__restrict__ diag,
+    const T *__restrict__ rhs, const typename Vec4<T>::type *__restrict__ msg,
+    const typename Vec2<T>::type *__restrict__ sums, const typename Vec2<T>::type *__restrict__ coef,
+    const typename Vec2<T>::type *__restrict__ hp, const T *__restrict__ Sfix,
+    const T *__restrict__ Hb, T alpha, double *__restrict__ xacc, double *__restrict__ marg,
+    T *__restrict__ means, uint32_t *__restrict__ sticky) {
 #pragma clang fp contract(off)
   using V2 = typename Vec2<T>::type;
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G;
-  const T b1 = T(1) - alpha;
+  __shared__ int rp[kSegRows + 1];
+  __shared__ V2 in[kSegChunk];
+  const int t = threadIdx.x;
+  const T b1m = T(1) - alpha;
   uint32_t f = 0;
-  for (int base = row0 + blockIdx.x * RPB; base < row1; base += gridDim.x * RPB) {
-    const int row = base + threadIdx.x / G;
-    const bool active = row < row1;
-    const int beg = active ? oprt[row] : 0, end = active ? oprt[row + 1] : 0;
+  for (int b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
+    const int r0 = rb[b], nr = rb[b + 1] - r0;
+    __syncthreads();
+    for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
+    __syncthreads();
+    const int e0 = rp[0], e1 = rp[nr];
     T S = T(0), H = T(0);
-    for (int e = beg + lane; e < end; e += G) {
-      const int j = ocol[e];
-      if (FROZEN) {
-        const V2 h = hp[e];
-        T hin = h.y;
-        if (j >= row1) {
-          hin = coef[e].y * (Hb[j] - h.x);
-          if (DAMP) hin = alpha * h.y + b1 * hin;
-        }
-        H += hin;
-      } else {
-        const auto m = msg[e];
-        T Pin = m.z, hin = m.w;
-        if (j >= row1) {
-          const T a = acoef[e];
-          const V2 sj = sums[j];
-          const T ij = T(1) / (sj.x - m.x);
-          Pin = -(a * a) * ij;
-          hin = (-a * ij) * (sj.y - m.y);
-          if (DAMP) {
-            Pin = alpha * m.z + b1 * Pin;
-            hin = alpha * m.w + b1 * hin;
+    for (int c = e0; c < e1; c += kSegChunk) {
+      for (int e = c + t; e < e1 && e < c + kSegChunk; e += kBlock) {
+        const int j = ocol[e];
+        V2 v;
+        if (FROZEN) {
+          const V2 h = hp[e];
+          T hin = h.y;
+          if (j >= row1) {
+            hin = coef[e].y * (Hb[j] - h.x);
+            if (DAMP) hin = alpha * h.y + b1m * hin;
           }
+          v.x = T(0);
+          v.y = hin;
+        } else {
+          const auto m = msg[e];
+          T Pin = m.z, hin = m.w;
+          if (j >= row1) {
+            const T a = acoef[e];
+            const V2 sj = sums[j];
+            const T ij = T(1) / (sj.x - m.x);
+            Pin = -(a * a) * ij;
+            hin = (-a * ij) * (sj.y - m.y);
+            if (DAMP) {
+              Pin = alpha * m.z + b1m * Pin;
+              hin = alpha * m.w + b1m * hin;
+            }
+          }
+          v.x = Pin;
+          v.y = hin;
         }
-        S += Pin;
-        H += hin;
+        in[e - c] = v;
       }
+      __syncthreads();
+      if (t < nr) {
+        const int lo = max(rp[t], c), hi = min(rp[t + 1], c + kSegChunk);
+        for (int e = lo; e < hi; ++e) {
+          S += in[e - c].x;
+          H += in[e - c].y;
+        }
+      }
+      __syncthreads();
     }
-    S = gsum<G>(S);
-    H = gsum<G>(H);
-    if (active && lane == 0) {
+    if (t < nr) {
+      const int row = r0 + t;
       S = FROZEN ? Sfix[row] : S + diag[row];
       H += rhs[row];
       if (S == T(0)) f |= FLAG_BREAKDOWN;
@@ -1013,41 +1030,31 @@ hipError_t launch_pair_sync_in(bool fp32, int64_t E, const int32_t *rev, void *m
 }  // namespace gabp
 
 namespace gabp {
-template <typename T, int G>
-static void col_infer_g(const PairArgs &a, double *xacc, double *marg, void *means, hipStream_t s) {
+template <typename T, bool DAMP, bool FROZEN>
+static void col_infer_one(const PairArgs &a, double *xacc, double *marg, void *means,
+                          hipStream_t s) {
   using V4 = typename Vec4<T>::type;
   using V2 = typename Vec2<T>::type;
-#define COL_INFER(D, F)                                                                          \
-  hipLaunchKernelGGL((k_pair_col_infer<T, G, D, F>), dim3(a.grid), dim3(kBlock), 0, s, a.row0,  \
-                     a.row1, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,      \
-                     (const V4 *)a.msg_in, (const V2 *)a.sums_in, (const V2 *)a.coef,            \
-                     (const V2 *)a.msg_in, (const T *)a.Sfix, (const T *)a.sums_in, (T)a.alpha,   \
-                     xacc, marg, (T *)means, a.sticky)
-  if (a.frozen) {
-    if (a.damp) COL_INFER(true, true); else COL_INFER(false, true);
-  } else {
-    if (a.damp) COL_INFER(true, false); else COL_INFER(false, false);
-  }
-#undef COL_INFER
+  hipLaunchKernelGGL((k_pair_col_infer<T, DAMP, FROZEN>), dim3(a.grid), dim3(kBlock), 0, s, a.rb,
+                     a.b0, a.b1, a.row1, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag,
+                     (const T *)a.rhs, (const V4 *)a.msg_in, (const V2 *)a.sums_in,
+                     (const V2 *)a.coef, (const V2 *)a.msg_in, (const T *)a.Sfix,
+                     (const T *)a.sums_in, (T)a.alpha, xacc, marg, (T *)means, a.sticky);
 }
 
 template <typename T>
 static hipError_t col_infer_t(const PairArgs &a, double *xacc, double *marg, void *means,
                               hipStream_t s) {
-  switch (a.group) {
-    case 4: col_infer_g<T, 4>(a, xacc, marg, means, s); break;
-    case 8: col_infer_g<T, 8>(a, xacc, marg, means, s); break;
-    case 16: col_infer_g<T, 16>(a, xacc, marg, means, s); break;
-    case 32: col_infer_g<T, 32>(a, xacc, marg, means, s); break;
-    case 64: col_infer_g<T, 64>(a, xacc, marg, means, s); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (a.frozen) a.damp ? col_infer_one<T, true, true>(a, xacc, marg, means, s)
+                       : col_infer_one<T, false, true>(a, xacc, marg, means, s);
+  else a.damp ? col_infer_one<T, true, false>(a, xacc, marg, means, s)
+              : col_infer_one<T, false, false>(a, xacc, marg, means, s);
   return hipGetLastError();
 }
 
 hipError_t launch_pair_col_infer(const PairArgs &a, double *xacc, double *marg, void *means,
                                  hipStream_t s) {
-  if (a.row1 <= a.row0) return hipSuccess;
+  if (a.b1 <= a.b0) return hipSuccess;
   return a.fp32 ? col_infer_t<float>(a, xacc, marg, means, s)
                 : col_infer_t<double>(a, xacc, marg, means, s);
 }
