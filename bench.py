@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--freeze-tol", type=float, default=0.0,
                     help="settled-precision threshold (0 = library default)")
     ap.add_argument("--grid", type=int, default=0, help="sweep grid cap (0 = library default)")
+    ap.add_argument("--col-blocks", type=int, default=0,
+                    help="column ranges of the synchronous pair layout (0 = library's choice)")
     ap.add_argument("--schedule", choices=["sync", "colored"], default=None,
                     help="message schedule; default colored for c3, c4 and lsq (two-colourable, "
                          "undamped: about half the sweeps), sync for c5 (with damping 0.5 the "
@@ -197,6 +199,8 @@ def run_c2(args, G, W, torch, dev):
     colored = args.schedule == "colored"
     if colored:
         opts.schedule = G.GABP_SCHEDULE_COLORED
+    else:
+        opts.col_blocks = args.col_blocks
     rc, plan = G.gabp_plan_create(A, opts)
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create: {G.status_name(rc)}")
@@ -242,6 +246,8 @@ def run_lsq(args, G, W, torch, dev):
     colored = (args.schedule or "colored") == "colored"
     if colored:
         opts.schedule = G.GABP_SCHEDULE_COLORED
+    else:
+        opts.col_blocks = args.col_blocks
     rc, plan = G.gabp_plan_create_lsq(R, psi, opts)
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create_lsq: {G.status_name(rc)}")
@@ -594,6 +600,7 @@ def main():
     sweeps = restarts = frozen = 0
     sweep_ms = frozen_ms = 0.0
     worst_rel = 0.0
+    lps = 1
     for _ in range(args.steps):
         rc, st = solve()
         if rc != G.GABP_OK:
@@ -604,6 +611,7 @@ def main():
         sweep_ms += st.sweep_ms
         frozen_ms += st.frozen_sweep_ms
         worst_rel = max(worst_rel, st.rel_residual)
+        lps = max(1, st.sweep_launches)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lsq_rel = G.gabp_plan_residual_lsq(plan, b, x)[1] if args.workload == "lsq" else None
@@ -622,7 +630,10 @@ def main():
         kname, bps, launches, kms = w["kfull"], w["bytes_full"], full_sweeps, full_ms
         tkey = w.get("tkey_full")
     traffic = measured_traffic(tkey, args.workload) if tkey else None
-    launches *= w.get("per_sweep", 1)
+    # the workload's bytes are per launch at its own count of launches per
+    # sweep; the plan reports how many it ran (column ranges, colour classes)
+    bps = bps * w.get("per_sweep", 1) / lps
+    launches *= lps
     avg_s = kms * 1e-3 / max(launches, 1)
     achieved = bps / avg_s / 1e9
     out = {
@@ -652,7 +663,7 @@ def main():
             "launches_timed": launches,
             "full_sweep_avg_us": (full_ms * 1e3 / full_sweeps) if full_sweeps else None,
             "settled_sweep_avg_us": (frozen_ms * 1e3 / frozen) if frozen else None,
-            "launches_per_sweep": w.get("per_sweep", 1),
+            "launches_per_sweep": lps,
         },
     }
     if lsq_rel is not None:  # the least-squares residual of the answer, outside the timing

@@ -123,6 +123,20 @@ typedef struct {
                           z) and CSR plans in the pair layout (a colouring the
                           plan computes, see gabp_plan_colors).  Dense batches
                           and the gather layout return GABP_ERR_UNSUPPORTED */
+  int32_t col_blocks;   /* CSR plans, pair layout, synchronous schedule: 1 or 2
+                          column ranges.  With 2 the slots of every row are
+                          ordered by neighbour range (node indices below
+                          (n + 1) / 2 first) and a sweep runs one launch per
+                          range, so each launch gathers node broadcasts from
+                          half of the node table, which then fits the L2 cache
+                          of an XCD better.  0 (default): 2 when the node table
+                          (8 B per node in FP32, 16 B in FP64) exceeds 4 MiB
+                          and at least half of the edges join nodes n / 4 or
+                          more apart in index, else 1.  The two differ only in
+                          the order of the node sums.  2 with the coloured
+                          schedule or the gather layout: GABP_ERR_UNSUPPORTED;
+                          other values: GABP_ERR_ARG.  Other plan kinds ignore
+                          it. */
 } gabp_opts;
 
 enum { GABP_LAYOUT_PAIR = 0, GABP_LAYOUT_GATHER = 1 };
@@ -152,7 +166,9 @@ typedef struct {
                               they imply fit b worse than x = 0); -2 the warm
                               solve did not converge and was redone from zero
                               messages; 0 no warm start */
-  int32_t pad_;
+  int32_t sweep_launches;  /* kernel launches per sweep: column ranges of a CSR
+                              plan, colour classes of a coloured plan, 1 else;
+                              0 for batched solves (one launch runs the solve) */
   double warm_rel0;        /* ||b - A x0|| / ||b|| of the warm start's means */
 } gabp_stats;
 

@@ -72,7 +72,7 @@ class Opts(C.Structure):
                 ("max_restarts", C.c_int32), ("group", C.c_int32), ("layout", C.c_int32),
                 ("grid_blocks", C.c_int32), ("freeze", C.c_int32), ("batch_waves", C.c_int32),
                 ("freeze_tol", C.c_double), ("adapt_damping", C.c_int32),
-                ("schedule", C.c_int32)]
+                ("schedule", C.c_int32), ("col_blocks", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -83,7 +83,8 @@ class Stats(C.Structure):
                 ("sweep_ms", C.c_double), ("frozen_sweep_ms", C.c_double), ("edges", C.c_int64),
                 ("edge_updates_per_s", C.c_double), ("damping", C.c_double),
                 ("batch_waves", C.c_int32), ("batch_groups", C.c_int32),
-                ("warm_start", C.c_int32), ("pad_", C.c_int32), ("warm_rel0", C.c_double)]
+                ("warm_start", C.c_int32), ("sweep_launches", C.c_int32),
+                ("warm_rel0", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

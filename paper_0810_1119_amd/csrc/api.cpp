@@ -91,6 +91,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   if (!p || (p->n > 0 && (!b || !x))) return GABP_ERR_ARG;
   gabp_stats stats{};
   stats.edges = p->E;
+  stats.sweep_launches = p->sweep_launches();
   stats.damping = p->o.damping;
   stats.status = GABP_OK;
   const gabp_opts &o = p->o;
@@ -278,6 +279,7 @@ void gabp_default_opts(gabp_opts *o) {
   o->batch_waves = 0;
   o->adapt_damping = 1;
   o->schedule = GABP_SCHEDULE_SYNC;
+  o->col_blocks = 0;
 }
 
 int gabp_plan_destroy(gabp_plan *p) {

@@ -76,6 +76,8 @@ struct Engine {
   int init_common(hipStream_t s);
   // entries of xprev (the means of the last check, in the engine's order)
   virtual int64_t means_slots() const { return n; }
+  // kernel launches of one sweep
+  virtual int sweep_launches() const { return 1; }
 
   // one sweep (mode 0: sweep, 1: sweep + check of the means); c = controller
   // or NULL.  Synchronous: from buffer cur into cur ^ 1; coloured: every

@@ -45,7 +45,8 @@ int check_opts(const gabp_opts *o) {
       !(o->freeze_tol >= 0.0) || !(o->freeze_tol < 1.0) ||
       (o->group != 0 && !valid_group(o->group)) || o->grid_blocks < 0 ||
       (o->layout != GABP_LAYOUT_PAIR && o->layout != GABP_LAYOUT_GATHER) ||
-      (o->schedule != GABP_SCHEDULE_SYNC && o->schedule != GABP_SCHEDULE_COLORED))
+      (o->schedule != GABP_SCHEDULE_SYNC && o->schedule != GABP_SCHEDULE_COLORED) ||
+      o->col_blocks < 0 || o->col_blocks > 2)
     return GABP_ERR_ARG;
   return GABP_OK;
 }
@@ -61,6 +62,12 @@ struct CsrEngine : Engine {
   int32_t *rblk = nullptr;
   std::vector<int> bfirst;
   int sgrid = 1;
+  // column ranges of the synchronous pair layout (1 or 2): range p of row i
+  // is virtual row p * n + i (oprt has nb * n + 1 offsets); with 2, a sweep's
+  // first launch leaves the first range's node sums in `carry` and the second
+  // continues from them
+  int nb = 1;
+  void *carry = nullptr;
   int32_t *oprt = nullptr, *ocol = nullptr, *rev = nullptr;
   int64_t *diagpos = nullptr;
   void *acoef = nullptr, *diag = nullptr, *rhs = nullptr;
@@ -76,7 +83,7 @@ struct CsrEngine : Engine {
 
   ~CsrEngine() override {
     void *bufs[] = {oprt, ocol, rev, diagpos, acoef, diag, rhs, msg[0], msg[1], sums[0],
-                    sums[1], coef, hp[0], hp[1], Sfix, Hfz[0], Hfz[1], rblk};
+                    sums[1], coef, hp[0], hp[1], Sfix, Hfz[0], Hfz[1], rblk, carry};
     for (void *b : bufs)
       if (b) (void)hipFree(b);
   }
@@ -85,8 +92,26 @@ struct CsrEngine : Engine {
 
   bool colored() const { return !cls.empty(); }
 
+  int sweep_launches() const override { return colored() ? (int)cls.size() - 1 : (pair ? nb : 1); }
+
   // workgroups of a launch over all row blocks
   int bgrid() const { return std::max(1, std::min(bfirst.back(), kMaxSweepBlocks)); }
+
+  // node sums from the stored in-messages, range by range as the sweeps add
+  // them (one range: every row block, colour classes included)
+  hipError_t aggregate(const void *m, void *out, hipStream_t s) {
+    if (nb == 1)
+      return launch_pair_aggregate(fp32, bgrid(), rblk, 0, bfirst.back(), 0, oprt, diag, rhs, m,
+                                   nullptr, out, true, s);
+    for (int p = 0; p < nb; ++p) {
+      const bool last = p == nb - 1;
+      hipError_t err = launch_pair_aggregate(fp32, sgrid, rblk, bfirst[p], bfirst[p + 1], p * n,
+                                             oprt, diag, rhs, m, p > 0 ? carry : nullptr,
+                                             last ? out : carry, last, s);
+      if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+  }
 
   hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
     hipError_t err;
@@ -120,7 +145,8 @@ struct CsrEngine : Engine {
     } else {
       PairArgs a{};
       a.grid = sgrid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
-      a.frozen = frozen; a.n = n; a.rb = rblk; a.b0 = 0; a.b1 = bfirst.back(); a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
+      a.frozen = frozen; a.n = n; a.rb = rblk;
+      a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
       a.rhs = rhs; a.alpha = o.damping; a.xprev = xprev; a.part = part; a.sticky = sticky;
       a.ctl = c;
       if (frozen) {
@@ -129,7 +155,18 @@ struct CsrEngine : Engine {
       } else {
         a.msg_in = msg[cur]; a.msg_out = msg[cur ^ 1]; a.sums_in = sums[cur]; a.sums_out = sums[cur ^ 1];
       }
-      err = launch_pair_sweep(a, s);
+      void *final_out = a.sums_out;
+      err = hipSuccess;
+      for (int p = 0; p < nb && err == hipSuccess; ++p) {
+        a.b0 = bfirst[p];
+        a.b1 = bfirst[p + 1];
+        a.vbase = p * n;
+        a.carry = p > 0 ? carry : nullptr;
+        a.last = p == nb - 1;
+        a.sums_out = a.last ? final_out : carry;
+        a.combine = p > 0;
+        err = launch_pair_sweep(a, s);
+      }
     }
     cur ^= 1;
     return err;
@@ -178,7 +215,7 @@ struct CsrEngine : Engine {
     // one half sweep old; make every copy the sender's current message
     if (colored() && (err = launch_pair_sync_in(fp32, E, rev, msg[cur], s)) != hipSuccess)
       return err;
-    return launch_pair_aggregate(fp32, bgrid(), rblk, bfirst.back(), oprt, diag, rhs, msg[cur], sums[cur], s);
+    return aggregate(msg[cur], sums[cur], s);
   }
 
   hipError_t reset(const double *b, hipStream_t s) override {
@@ -192,7 +229,7 @@ struct CsrEngine : Engine {
     if ((err = launch_residual(fp32, nsum, n, A.row_ptr, A.col, A.val, b, nullptr, rhs,
                                nullptr, sumpart, s)) != hipSuccess)
       return err;
-    if (pair) return launch_pair_aggregate(fp32, bgrid(), rblk, bfirst.back(), oprt, diag, rhs, msg[0], sums[0], s);
+    if (pair) return aggregate(msg[0], sums[0], s);
     return hipSuccess;
   }
 
@@ -220,7 +257,7 @@ struct CsrEngine : Engine {
   }
 
   hipError_t freeze(hipStream_t s) override {
-    hipError_t err = launch_pair_freeze(fp32, bgrid(), rblk, bfirst.back(), oprt, ocol,
+    hipError_t err = launch_pair_freeze(fp32, bgrid(), rblk, bfirst.back(), n, oprt, ocol,
                                         colored() ? rev : nullptr, acoef, msg[cur], sums[cur], coef,
                                         hp[cur], Sfix, Hfz[cur], s);
     frozen = true;
@@ -230,7 +267,7 @@ struct CsrEngine : Engine {
   int get_messages(double *P, double *h, hipStream_t s) override {
     if (A.nnz > 0 && (!P || !h)) return GABP_ERR_ARG;
     if (pair)
-      TRY_HIP(launch_pair_io(fp32, true, n, A.row_ptr, diagpos, oprt, rev, msg[cur], P, h, s));
+      TRY_HIP(launch_pair_io(fp32, true, n, nb, A.row_ptr, diagpos, oprt, rev, msg[cur], P, h, s));
     else
       TRY_HIP(launch_get_msgs(fp32, n, A.row_ptr, diagpos, oprt, msg[cur], P, h, s));
     TRY_HIP(hipStreamSynchronize(s));
@@ -241,9 +278,9 @@ struct CsrEngine : Engine {
     if (A.nnz > 0 && (!P || !h)) return GABP_ERR_ARG;
     first = true;
     if (pair) {
-      TRY_HIP(launch_pair_io(fp32, false, n, A.row_ptr, diagpos, oprt, rev, msg[cur], (double *)P,
+      TRY_HIP(launch_pair_io(fp32, false, n, nb, A.row_ptr, diagpos, oprt, rev, msg[cur], (double *)P,
                              (double *)h, s));
-      TRY_HIP(launch_pair_aggregate(fp32, bgrid(), rblk, bfirst.back(), oprt, diag, rhs, msg[cur], sums[cur], s));
+      TRY_HIP(aggregate(msg[cur], sums[cur], s));
     } else {
       TRY_HIP(launch_set_msgs(fp32, n, A.row_ptr, diagpos, oprt, msg[cur], P, h, s));
     }
@@ -255,19 +292,21 @@ struct CsrEngine : Engine {
   // class launch of a coloured sweep has the same workgroups, so a check's
   // partials line up.
   int row_blocks(int cap, hipStream_t s) {
-    std::vector<int32_t> hrp((size_t)n + 1, 0);
+    std::vector<int32_t> hrp((size_t)nb * n + 1, 0);
     if (n > 0) {
       TRY_HIP(hipMemcpyAsync(hrp.data(), oprt, hrp.size() * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
       TRY_HIP(hipStreamSynchronize(s));
     }
-    const std::vector<int> bounds = colored() ? cls : std::vector<int>{0, n};
+    std::vector<int> bounds = colored() ? cls : std::vector<int>{0, n};
+    if (nb == 2) bounds.push_back(2 * n);
     const std::vector<int32_t> rb = pair_row_blocks(hrp.data(), bounds, &bfirst);
     int most = 1;
     for (size_t k = 0; k + 1 < bfirst.size(); ++k) most = std::max(most, bfirst[k + 1] - bfirst[k]);
     sgrid = std::min(most, cap);
     nparts = sgrid;
     TRY_HIP(dalloc(&rblk, rb.size(), sizeof(int32_t)));
+    if (nb > 1) TRY_HIP(dalloc(&carry, n, 2 * tsz));
     TRY_HIP(hipMemcpyAsync(rblk, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     TRY_HIP(hipStreamSynchronize(s));
     return GABP_OK;
@@ -275,19 +314,18 @@ struct CsrEngine : Engine {
 
   // validate A on the device and build the edge arrays and reverse index
   int build(hipStream_t s) {
-    int64_t *deg = nullptr, *oprt64 = nullptr, *tmp = nullptr;
+    int64_t *deg = nullptr, *vo = nullptr, *tmp = nullptr, *L = nullptr;
     uint32_t *flags = nullptr;
+    unsigned long long *far = nullptr;
     int st = GABP_OK;
     auto fail = [&](int code) {
-      void *bufs[] = {deg, oprt64, tmp, flags};
+      void *bufs[] = {deg, vo, tmp, L, flags, far};
       for (void *b : bufs)
         if (b) (void)hipFree(b);
       return code;
     };
     if ((st = from_hip(dalloc(&deg, n, sizeof(int64_t)))) ||
         (st = from_hip(dalloc(&diagpos, n, sizeof(int64_t)))) ||
-        (st = from_hip(dalloc(&oprt64, n + 1, sizeof(int64_t)))) ||
-        (st = from_hip(dalloc(&tmp, scan_tmp_elems(n), sizeof(int64_t)))) ||
         (st = from_hip(dalloc(&flags, 1, sizeof(uint32_t)))))
       return fail(st);
     if ((st = from_hip(launch_fill_zero4(flags, 1, s))) ||
@@ -299,20 +337,41 @@ struct CsrEngine : Engine {
       return fail(st);
     if (hflags & FLAG_ARG) return fail(GABP_ERR_ARG);
     if (hflags & FLAG_ZERO_DIAG) return fail(GABP_ERR_ZERO_DIAG);
-    if ((st = from_hip(launch_scan(deg, oprt64, n, tmp, s)))) return fail(st);
+    // column ranges (pair layout, synchronous schedule)
+    nb = 1;
+    if (pair && !colored() && o.col_blocks != 1) {
+      const int split = (n + 1) / 2;
+      if ((st = from_hip(dalloc(&L, 2 * (size_t)n, sizeof(int64_t)))) ||
+          (st = from_hip(dalloc(&far, 1, sizeof(unsigned long long)))) ||
+          (st = from_hip(hipMemsetAsync(far, 0, sizeof(unsigned long long), s))) ||
+          (st = from_hip(launch_plan_split(n, A.row_ptr, A.col, diagpos, split, L, far, s))))
+        return fail(st);
+      unsigned long long hfar = 0;
+      if ((st = from_hip(hipMemcpyAsync(&hfar, far, sizeof(hfar), hipMemcpyDeviceToHost, s))) ||
+          (st = from_hip(hipStreamSynchronize(s))))
+        return fail(st);
+      const int64_t offdiag = A.nnz - n;
+      const bool big = (int64_t)n * 2 * (int64_t)tsz > ((int64_t)4 << 20);
+      nb = (o.col_blocks == 2 || (big && offdiag > 0 && 2 * (int64_t)hfar >= offdiag)) ? 2 : 1;
+    }
+    const int64_t vrows = (int64_t)nb * n;
+    if ((st = from_hip(dalloc(&vo, vrows + 1, sizeof(int64_t)))) ||
+        (st = from_hip(dalloc(&tmp, scan_tmp_elems(vrows), sizeof(int64_t)))) ||
+        (st = from_hip(launch_scan(nb == 2 ? L : deg, vo, vrows, tmp, s))))
+      return fail(st);
     int64_t e = 0;
-    if ((st = from_hip(hipMemcpyAsync(&e, oprt64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s))) ||
+    if ((st = from_hip(hipMemcpyAsync(&e, vo + vrows, sizeof(int64_t), hipMemcpyDeviceToHost, s))) ||
         (st = from_hip(hipStreamSynchronize(s))))
       return fail(st);
     // slot indices stay in int32 with a chunk of headroom
     if (e >= (int64_t)INT32_MAX - 4096) return fail(GABP_ERR_UNSUPPORTED);
     E = e;
-    if ((st = from_hip(dalloc(&oprt, n + 1, sizeof(int32_t)))) ||
+    if ((st = from_hip(dalloc(&oprt, vrows + 1, sizeof(int32_t)))) ||
         (st = from_hip(dalloc(&ocol, E, sizeof(int32_t)))) ||
         (st = from_hip(dalloc(&rev, E, sizeof(int32_t)))) ||
         (st = from_hip(dalloc(&acoef, E, tsz))) || (st = from_hip(dalloc(&diag, n, tsz))))
       return fail(st);
-    if ((st = from_hip(launch_plan_edges(fp32, n, A.row_ptr, A.col, A.val, diagpos, oprt64, oprt,
+    if ((st = from_hip(launch_plan_edges(fp32, n, nb, A.row_ptr, A.col, A.val, diagpos, vo, oprt,
                                          ocol, rev, acoef, diag, flags, s))))
       return fail(st);
     if ((st = from_hip(hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s))) ||
@@ -337,6 +396,8 @@ int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int
   if ((st = check_opts(&opts))) return st;
   if ((opts.schedule != GABP_SCHEDULE_SYNC) != (classes != nullptr)) return GABP_ERR_UNSUPPORTED;
   if (classes && opts.layout != GABP_LAYOUT_PAIR) return GABP_ERR_UNSUPPORTED;
+  if (opts.col_blocks == 2 && (classes || opts.layout != GABP_LAYOUT_PAIR))
+    return GABP_ERR_UNSUPPORTED;
   CsrEngine *e = new (std::nothrow) CsrEngine();
   if (!e) return GABP_ERR_NOMEM;
   e->A = *A;
@@ -349,12 +410,12 @@ int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int
     delete e;
     return code;
   };
+  if (classes) e->cls = *classes;
   if (e->n > 0 && (st = e->build(s))) return fail(st);
   e->group = opts.group ? opts.group : choose_group(e->n, e->E);
   const int cap = opts.grid_blocks > 0 ? opts.grid_blocks : kMaxSweepBlocks;
   e->grid = sweep_blocks(std::max(e->n, 1), e->group, cap);
   e->nparts = e->grid;
-  if (classes) e->cls = *classes;
   if (e->pair && (st = e->row_blocks(cap, s))) return fail(st);
   e->nsum = residual_blocks(std::max(e->n, 1), cap);
   if ((st = e->init_common(s))) return fail(st);
@@ -384,6 +445,7 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
   if (o && o->schedule == GABP_SCHEDULE_COLORED) {
     if (o->layout != GABP_LAYOUT_PAIR) return GABP_ERR_UNSUPPORTED;
     int st = check_opts(o);
+    if (!st && o->col_blocks == 2) st = GABP_ERR_UNSUPPORTED;
     return st ? st : coloured_csr_plan(A, o, plan, s);
   }
   return csr_plan_create(A, o, nullptr, plan, s);

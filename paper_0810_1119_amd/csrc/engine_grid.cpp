@@ -213,6 +213,7 @@ struct RbGridEngine : GridEngine {
   int rgrid = 1;  // blocks of a one-colour launch
 
   int64_t means_slots() const override { return 2 * (int64_t)Nc; }
+  int sweep_launches() const override { return 2; }
   int64_t rb_slots() const { return 12 * (int64_t)Nc; }
 
   RbArgs rargs(int mode, int colour, const Ctl *c) const {

@@ -98,8 +98,15 @@ hipError_t launch_plan_rows(int n, int64_t nnz, const int64_t *rp, const int32_t
 // scan_tmp_elems(n) int64 values.
 size_t scan_tmp_elems(int64_t n);
 hipError_t launch_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
-hipError_t launch_plan_edges(bool fp32, int n, const int64_t *rp, const int32_t *col,
-                             const double *val, const int64_t *diagpos, const int64_t *oprt64,
+// L[i] / L[n + i]: off-diagonal entries of row i with column below / at or
+// above split; *far += the entries joining nodes n / 4 or more apart
+hipError_t launch_plan_split(int n, const int64_t *rp, const int32_t *col, const int64_t *diagpos,
+                             int split, int64_t *L, unsigned long long *far, hipStream_t s);
+// Edge arrays of the pair / gather layouts with nb (1 or 2) column ranges: vo
+// holds the nb * n + 1 slot offsets of the virtual rows (range p of row i is
+// virtual row p * n + i), copied to oprt; ocol, rev, acoef per slot
+hipError_t launch_plan_edges(bool fp32, int n, int nb, const int64_t *rp, const int32_t *col,
+                             const double *val, const int64_t *diagpos, const int64_t *vo,
                              int32_t *oprt, int32_t *ocol, int32_t *rev, void *acoef, void *diag,
                              uint32_t *flags, hipStream_t s);
 
@@ -177,6 +184,14 @@ struct PairArgs {
   // sweeps: the row blocks [b0, b1) of rb (pair_row_blocks)
   const int32_t *rb;
   int b0, b1;
+  // synchronous sweeps with column ranges: the blocks are virtual rows
+  // [vbase, vbase + n) of one range; carry (nullable) holds the earlier
+  // ranges' node sums; last: the final range (adds A_ii, b_i, checks; sums_out
+  // is the broadcast array, else the carry); combine: check partials are
+  // added to those of the earlier ranges' launches
+  int vbase;
+  const void *carry;
+  bool last;
   // coloured schedule: one colour class, rows [row0, row1), updated in place
   // (msg_in == msg_out, sums_in == sums_out); combine: add to the partials
   // of the check's earlier class launches
@@ -200,26 +215,30 @@ hipError_t launch_pair_col_infer(const PairArgs &a, double *xacc, double *marg, 
                                  hipStream_t s);
 // msg[e].P_ji := msg[rev[e]].P_ij for every slot (pair layout)
 hipError_t launch_pair_sync_in(bool fp32, int64_t E, const int32_t *rev, void *msg, hipStream_t s);
-// (S, H) from the stored in-messages over the row blocks [0, nblk) of rb, a
-// row's added in slot order (the sweeps' order)
-hipError_t launch_pair_aggregate(bool fp32, int grid, const int32_t *rb, int nblk,
-                                 const int32_t *oprt, const void *diag, const void *rhs,
-                                 const void *msg, void *sums, hipStream_t s);
+// (S, H) from the stored in-messages over the row blocks [b0, b1) of rb (one
+// column range, virtual rows from vbase), a row's added in slot order after
+// carry (nullable) as the sweeps add them; last: add A_ii and b_i
+hipError_t launch_pair_aggregate(bool fp32, int grid, const int32_t *rb, int b0, int b1,
+                                 int vbase, const int32_t *oprt, const void *diag, const void *rhs,
+                                 const void *msg, const void *carry, void *sums, bool last,
+                                 hipStream_t s);
 hipError_t launch_pair_zero_h(bool fp32, int64_t E, void *msg, hipStream_t s);
 hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfix, const void *Hfz,
                              double *xacc, double *marg, void *means, uint32_t *sticky,
                              hipStream_t s);
-// Settled-precision coefficients over the row blocks [0, nblk) of rb; rev:
-// NULL, or the reverse-slot index (coloured plans; see k_pair_freeze)
-hipError_t launch_pair_freeze(bool fp32, int grid, const int32_t *rb, int nblk,
+// Settled-precision coefficients over the row blocks [0, nblk) of rb (n nodes;
+// with two column ranges the blocks span both); rev: NULL, or the
+// reverse-slot index (coloured plans; see k_pair_freeze)
+hipError_t launch_pair_freeze(bool fp32, int grid, const int32_t *rb, int nblk, int n,
                               const int32_t *oprt, const int32_t *ocol, const int32_t *rev,
                               const void *acoef, const void *msg, const void *sums, void *coef,
                               void *hp, void *Sfix, void *Hfz, hipStream_t s);
 hipError_t launch_frozen_restart(bool fp32, int64_t E, int n, void *hp, const void *rhs, void *Hfz,
                                  hipStream_t s);
-hipError_t launch_pair_io(bool fp32, bool get, int n, const int64_t *rp, const int64_t *diagpos,
-                          const int32_t *oprt, const int32_t *rev, void *msg, double *P, double *h,
-                          hipStream_t s);
+// messages in CSR entry order (get) or into the slots (set); nb column ranges
+hipError_t launch_pair_io(bool fp32, bool get, int n, int nb, const int64_t *rp,
+                          const int64_t *diagpos, const int32_t *oprt, const int32_t *rev,
+                          void *msg, double *P, double *h, hipStream_t s);
 
 // ---- structured grids (kernels_grid.hip) ----
 struct GridGeom {

@@ -154,24 +154,71 @@ hipError_t launch_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp,
   return scan_rec(pad, out, n + 1, work, s);
 }
 
-template <typename T>
-__global__ void k_plan_edges(int n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
-                             const double *__restrict__ val, const int64_t *__restrict__ diagpos,
-                             const int64_t *__restrict__ oprt64, int32_t *__restrict__ oprt,
-                             int32_t *__restrict__ ocol, int32_t *__restrict__ rev,
-                             T *__restrict__ acoef,
-                             T *__restrict__ diag, uint32_t *__restrict__ flags) {
+// Column ranges of the pair layout: L[i] = off-diagonal entries of row i with
+// column < split, L[n + i] = the others; far += the entries joining nodes n / 4
+// or more apart in index (one atomic per wavefront).
+__global__ __launch_bounds__(kBlock) void k_plan_split(int n, const int64_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       const int64_t *__restrict__ diagpos,
+                                                       int split, int64_t *__restrict__ L,
+                                                       unsigned long long *__restrict__ far) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > n) return;
-  oprt[i] = (int32_t)oprt64[i];
-  if (i == n) return;
+  double fr = 0.0;
+  if (i < n) {
+    const int64_t dp = diagpos[i];
+    const int64_t q = n / 4;
+    int64_t c0 = 0, d = 0;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      if (k == dp) continue;
+      const int32_t j = col[k];
+      ++d;
+      c0 += j < split;
+      const int64_t gap = j > i ? (int64_t)j - i : (int64_t)i - j;
+      fr += gap >= q ? 1.0 : 0.0;
+    }
+    L[i] = c0;
+    L[n + i] = d - c0;
+  }
+  fr = wave_sum(fr);
+  if ((threadIdx.x & 63) == 0 && fr > 0.0) atomicAdd(far, (unsigned long long)fr);
+}
+
+hipError_t launch_plan_split(int n, const int64_t *rp, const int32_t *col, const int64_t *diagpos,
+                             int split, int64_t *L, unsigned long long *far, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan_split, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, rp, col,
+                     diagpos, split, L, far);
+  return hipGetLastError();
+}
+
+// Slot of the off-diagonal entry of rank `rank` in row i.  One column range:
+// vo[i] + rank.  Two: row i's entries below the split (its first
+// vo[i + 1] - vo[i]) at vo[i] + rank, the others at vo[n + i] + the rest.
+__device__ __forceinline__ int64_t pair_slot(const int64_t *vo, int n, int nb, int i,
+                                             int64_t rank) {
+  if (nb == 2) {
+    const int64_t c0 = vo[i + 1] - vo[i];
+    if (rank >= c0) return vo[n + i] + (rank - c0);
+  }
+  return vo[i] + rank;
+}
+
+template <typename T>
+__global__ void k_plan_edges(int n, int nb, const int64_t *__restrict__ rp,
+                             const int32_t *__restrict__ col, const double *__restrict__ val,
+                             const int64_t *__restrict__ diagpos, const int64_t *__restrict__ vo,
+                             int32_t *__restrict__ ocol, int32_t *__restrict__ rev,
+                             T *__restrict__ acoef, T *__restrict__ diag,
+                             uint32_t *__restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
   const int64_t b = rp[i], e = rp[i + 1], dp = diagpos[i];
   diag[i] = (T)val[dp];
-  int64_t o = oprt64[i];
   uint32_t f = 0;
   for (int64_t k = b; k < e; ++k) {
     if (k == dp) continue;
     const int32_t j = col[k];
+    const int64_t o = pair_slot(vo, n, nb, i, (k - b) - (k > dp ? 1 : 0));
     // binary search for column i in row j (columns sorted)
     int64_t lo = rp[j], hi = rp[j + 1] - 1, found = -1;
     while (lo <= hi) {
@@ -185,27 +232,35 @@ __global__ void k_plan_edges(int n, const int64_t *__restrict__ rp, const int32_
     if (found < 0 || val[found] != val[k]) {
       f |= FLAG_ASYM;
     } else {
-      r = (int32_t)(oprt64[j] + (found - rp[j]) - (found > diagpos[j] ? 1 : 0));
+      r = (int32_t)pair_slot(vo, n, nb, j, (found - rp[j]) - (found > diagpos[j] ? 1 : 0));
     }
     rev[o] = r;
     ocol[o] = j;
     acoef[o] = (T)val[k];
-    ++o;
   }
   if (f) atomicOr(flags, f);
 }
 
-hipError_t launch_plan_edges(bool fp32, int n, const int64_t *rp, const int32_t *col,
-                             const double *val, const int64_t *diagpos, const int64_t *oprt64,
+__global__ void k_narrow_offsets(int64_t m, const int64_t *__restrict__ in, int32_t *__restrict__ out) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < m) out[v] = (int32_t)in[v];
+}
+
+hipError_t launch_plan_edges(bool fp32, int n, int nb, const int64_t *rp, const int32_t *col,
+                             const double *val, const int64_t *diagpos, const int64_t *vo,
                              int32_t *oprt, int32_t *ocol, int32_t *rev, void *acoef, void *diag,
                              uint32_t *flags, hipStream_t s) {
-  const dim3 grid((n + 1 + kBlock - 1) / kBlock);
+  const int64_t m = (int64_t)nb * n + 1;
+  hipLaunchKernelGGL(k_narrow_offsets, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, m, vo, oprt);
+  if (n <= 0) return hipGetLastError();
+  const dim3 grid((n + kBlock - 1) / kBlock);
   if (fp32)
-    hipLaunchKernelGGL(k_plan_edges<float>, grid, dim3(kBlock), 0, s, n, rp, col, val, diagpos,
-                       oprt64, oprt, ocol, rev, (float *)acoef, (float *)diag, flags);
+    hipLaunchKernelGGL(k_plan_edges<float>, grid, dim3(kBlock), 0, s, n, nb, rp, col, val, diagpos,
+                       vo, ocol, rev, (float *)acoef, (float *)diag, flags);
   else
-    hipLaunchKernelGGL(k_plan_edges<double>, grid, dim3(kBlock), 0, s, n, rp, col, val, diagpos,
-                       oprt64, oprt, ocol, rev, (double *)acoef, (double *)diag, flags);
+    hipLaunchKernelGGL(k_plan_edges<double>, grid, dim3(kBlock), 0, s, n, nb, rp, col, val, diagpos,
+                       vo, ocol, rev, (double *)acoef, (double *)diag, flags);
   return hipGetLastError();
 }
 

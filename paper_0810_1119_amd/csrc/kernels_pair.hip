@@ -62,14 +62,19 @@ __device__ __forceinline__ int seg_row(const int *rp, int nr, int e) {
 // ---------------------------------------------------------------------------
 // synchronous full sweep (P and h), MODE 0 = sweep, 1 = sweep + check
 // ---------------------------------------------------------------------------
+// Rows are the virtual rows [vbase, vbase + n) of one column range (node
+// v - vbase); carry (nullable) holds the node sums of the ranges before it.
+// The last range adds A_ii and b_i, writes the broadcasts and checks the
+// means; an earlier one writes its partial sums to sout (the carry).
 template <typename T, int MODE, bool DAMP>
 __global__ __launch_bounds__(kBlock) void k_pair_sweep(
-    const int32_t *__restrict__ rb, int b0, int b1, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ rb, int b0, int b1, int vbase, const int32_t *__restrict__ oprt,
     const int32_t *__restrict__ ocol, const T *__restrict__ acoef, const T *__restrict__ diag,
     const T *__restrict__ rhs, const typename Vec4<T>::type *__restrict__ mi,
     typename Vec4<T>::type *__restrict__ mo, const typename Vec2<T>::type *__restrict__ sin,
-    typename Vec2<T>::type *__restrict__ sout, T alpha, T *__restrict__ xprev,
-    BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+    const typename Vec2<T>::type *__restrict__ carry, typename Vec2<T>::type *__restrict__ sout,
+    bool last, T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, bool combine,
+    uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
   // no FMA contraction: both stored copies of a message, and the node sums
   // rebuilt from stored values, must round exactly like this sweep does
 #pragma clang fp contract(off)
@@ -87,12 +92,17 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
   uint32_t f = 0;
   for (int b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
     const int r0 = rb[b], nr = rb[b + 1] - r0;
+    const int n0 = r0 - vbase;  // node of the block's first row
     __syncthreads();  // the previous block's readers are done with the LDS
     for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
-    for (int k = t; k < nr; k += kBlock) own[k] = sin[r0 + k];
+    for (int k = t; k < nr; k += kBlock) own[k] = sin[n0 + k];
     __syncthreads();
     const int e0 = rp[0], e1 = rp[nr];
     T S = T(0), H = T(0);
+    if (carry != nullptr && t < nr) {
+      S = carry[n0 + t].x;
+      H = carry[n0 + t].y;
+    }
     for (int c = e0; c < e1; c += kSegChunk) {
       int j[kSegK];
       T a[kSegK];
@@ -156,14 +166,16 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
       __syncthreads();
     }
     if (t < nr) {
-      const int row = r0 + t;
-      S += diag[row];
-      H += rhs[row];
+      const int row = n0 + t;
+      if (last) {
+        S += diag[row];
+        H += rhs[row];
+      }
       V2 o;
       o.x = S;
       o.y = H;
       sout[row] = o;
-      if (MODE == 1) {
+      if (MODE == 1 && last) {
         if (S == T(0)) f |= FLAG_BREAKDOWN;
         const T x = H / S;
         if (!isfinite(x)) f |= FLAG_NONFINITE;
@@ -175,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
   }
   if (zero) f |= FLAG_BREAKDOWN;
   if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(d, ax, (double)dp, (double)pm, part);
+  if (MODE == 1) block_publish(d, ax, (double)dp, (double)pm, part, combine);
 }
 
 // Aggregate (S, H) from the slots' incoming messages: used after reset,
@@ -184,21 +196,27 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
 // imported messages resume a solve bit for bit.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pair_aggregate(
-    const int32_t *__restrict__ rb, int nblk, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ rb, int b0, int b1, int vbase, const int32_t *__restrict__ oprt,
     const T *__restrict__ diag, const T *__restrict__ rhs,
-    const typename Vec4<T>::type *__restrict__ msg, typename Vec2<T>::type *__restrict__ sums) {
+    const typename Vec4<T>::type *__restrict__ msg, const typename Vec2<T>::type *__restrict__ carry,
+    typename Vec2<T>::type *__restrict__ sums, bool last) {
 #pragma clang fp contract(off)
   using V2 = typename Vec2<T>::type;
   __shared__ int rp[kSegRows + 1];
   __shared__ V2 in[kSegChunk];
   const int t = threadIdx.x;
-  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+  for (int b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
     const int r0 = rb[b], nr = rb[b + 1] - r0;
+    const int n0 = r0 - vbase;
     __syncthreads();
     for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
     __syncthreads();
     const int e0 = rp[0], e1 = rp[nr];
     T S = T(0), H = T(0);
+    if (carry != nullptr && t < nr) {
+      S = carry[n0 + t].x;
+      H = carry[n0 + t].y;
+    }
     for (int c = e0; c < e1; c += kSegChunk) {
       for (int e = c + t; e < e1 && e < c + kSegChunk; e += kBlock) {
         const auto m = msg[e];
@@ -219,9 +237,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_aggregate(
     }
     if (t < nr) {
       V2 o;
-      o.x = S + diag[r0 + t];
-      o.y = H + rhs[r0 + t];
-      sums[r0 + t] = o;
+      o.x = last ? S + diag[n0 + t] : S;
+      o.y = last ? H + rhs[n0 + t] : H;
+      sums[n0 + t] = o;
     }
   }
 }
@@ -269,7 +287,7 @@ __global__ void k_pair_infer(int n, const typename Vec2<T>::type *__restrict__ s
 // P_ij than the one j used, and the two copies of c_ji must still agree.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pair_freeze(
-    const int32_t *__restrict__ rb, int nblk, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ rb, int nblk, int n, const int32_t *__restrict__ oprt,
     const int32_t *__restrict__ ocol, const int32_t *__restrict__ rev, const T *__restrict__ acoef,
     const typename Vec4<T>::type *__restrict__ msg,
     const typename Vec2<T>::type *__restrict__ sums, typename Vec2<T>::type *__restrict__ coef,
@@ -281,13 +299,18 @@ __global__ __launch_bounds__(kBlock) void k_pair_freeze(
   const int t = threadIdx.x;
   for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
     const int r0 = rb[b], nr = rb[b + 1] - r0;
+    // virtual rows of the second column range are nodes r0 - n, ...; the
+    // first range lists every node once
+    const int n0 = r0 >= n ? r0 - n : r0;
     __syncthreads();
     for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
     for (int k = t; k < nr; k += kBlock) {
-      const V2 si = sums[r0 + k];
+      const V2 si = sums[n0 + k];
       own[k] = si.x;
-      Sfix[r0 + k] = si.x;
-      Hfz[r0 + k] = si.y;
+      if (r0 < n) {
+        Sfix[n0 + k] = si.x;
+        Hfz[n0 + k] = si.y;
+      }
     }
     __syncthreads();
     const int e1 = rp[nr];
@@ -310,14 +333,16 @@ __global__ __launch_bounds__(kBlock) void k_pair_freeze(
 
 // synchronous settled-precision sweep: information only.
 // MODE 0 = sweep, 1 = sweep + check.
+// Column ranges as in k_pair_sweep (carry: the earlier ranges' H sums).
 template <typename T, int MODE, bool DAMP>
 __global__ __launch_bounds__(kBlock) void k_pair_frozen(
-    const int32_t *__restrict__ rb, int b0, int b1, const int32_t *__restrict__ oprt,
+    const int32_t *__restrict__ rb, int b0, int b1, int vbase, const int32_t *__restrict__ oprt,
     const int32_t *__restrict__ ocol, const typename Vec2<T>::type *__restrict__ coef,
     const T *__restrict__ rhs, const T *__restrict__ Sfix,
     const typename Vec2<T>::type *__restrict__ hin, typename Vec2<T>::type *__restrict__ hout,
-    const T *__restrict__ Hin, T *__restrict__ Hout, T alpha, T *__restrict__ xprev,
-    BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+    const T *__restrict__ Hin, const T *__restrict__ carry, T *__restrict__ Hout, bool last,
+    T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, bool combine,
+    uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
 #pragma clang fp contract(off)
   using V2 = typename Vec2<T>::type;
   __shared__ int rp[kSegRows + 1];
@@ -330,12 +355,13 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen(
   uint32_t f = 0;
   for (int b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
     const int r0 = rb[b], nr = rb[b + 1] - r0;
+    const int n0 = r0 - vbase;
     __syncthreads();
     for (int k = t; k <= nr; k += kBlock) rp[k] = oprt[r0 + k];
-    for (int k = t; k < nr; k += kBlock) own[k] = Hin[r0 + k];
+    for (int k = t; k < nr; k += kBlock) own[k] = Hin[n0 + k];
     __syncthreads();
     const int e0 = rp[0], e1 = rp[nr];
-    T H = T(0);
+    T H = (carry != nullptr && t < nr) ? carry[n0 + t] : T(0);
     for (int c = e0; c < e1; c += kSegChunk) {
       int j[kSegK];
       V2 cf[kSegK], h[kSegK];
@@ -382,10 +408,10 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen(
       __syncthreads();
     }
     if (t < nr) {
-      const int row = r0 + t;
-      H += rhs[row];
+      const int row = n0 + t;
+      if (last) H += rhs[row];
       Hout[row] = H;
-      if (MODE == 1) {
+      if (MODE == 1 && last) {
         const T x = H / Sfix[row];
         if (!isfinite(x)) f |= FLAG_NONFINITE;
         d = fmax(d, (double)fabs(x - xprev[row]));
@@ -395,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen(
     }
   }
   if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(d, ax, 0.0, 0.0, part);
+  if (MODE == 1) block_publish(d, ax, 0.0, 0.0, part, combine);
 }
 
 // restart in the frozen state: h = 0, H = rhs
@@ -838,20 +864,24 @@ __global__ void k_pair_sync_in(int64_t E, const int32_t *__restrict__ rev,
 // ---------------------------------------------------------------------------
 // export / import in CSR slot order (pair layout holds the out-message at .xy)
 // ---------------------------------------------------------------------------
+// nb column ranges: row i's entries below the split sit at oprt[i] + rank,
+// the others (nb == 2) at oprt[n + i] + the rest
 template <typename T, bool GET>
-__global__ void k_pair_io(int n, const int64_t *__restrict__ rp, const int64_t *__restrict__ diagpos,
-                          const int32_t *__restrict__ oprt, const int32_t *__restrict__ rev,
-                          typename Vec4<T>::type *__restrict__ msg, double *__restrict__ P,
-                          double *__restrict__ h) {
+__global__ void k_pair_io(int n, int nb, const int64_t *__restrict__ rp,
+                          const int64_t *__restrict__ diagpos, const int32_t *__restrict__ oprt,
+                          const int32_t *__restrict__ rev, typename Vec4<T>::type *__restrict__ msg,
+                          double *__restrict__ P, double *__restrict__ h) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t b = rp[i], e = rp[i + 1], dp = diagpos[i];
+  const int64_t c0 = oprt[i + 1] - oprt[i];
   for (int64_t k = b; k < e; ++k) {
     if (k == dp) {
       if (GET) { P[k] = 0.0; h[k] = 0.0; }
       continue;
     }
-    const int64_t o = oprt[i] + (k - b) - (k > dp ? 1 : 0);
+    const int64_t rank = (k - b) - (k > dp ? 1 : 0);
+    const int64_t o = (nb == 2 && rank >= c0) ? oprt[n + i] + (rank - c0) : oprt[i] + rank;
     if (GET) {
       P[k] = (double)msg[o].x;
       h[k] = (double)msg[o].y;
@@ -888,14 +918,16 @@ static void pair_one(const PairArgs &a, hipStream_t s) {
   }
   if (a.frozen)
     hipLaunchKernelGGL((k_pair_frozen<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.rb, a.b0, a.b1,
-                       a.oprt, a.ocol, (const V2 *)a.coef, (const T *)a.rhs, (const T *)a.Sfix,
-                       (const V2 *)a.msg_in, (V2 *)a.msg_out, (const T *)a.sums_in,
-                       (T *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part, a.sticky, a.ctl);
+                       a.vbase, a.oprt, a.ocol, (const V2 *)a.coef, (const T *)a.rhs,
+                       (const T *)a.Sfix, (const V2 *)a.msg_in, (V2 *)a.msg_out,
+                       (const T *)a.sums_in, (const T *)a.carry, (T *)a.sums_out, a.last,
+                       (T)a.alpha, (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
   else
     hipLaunchKernelGGL((k_pair_sweep<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.rb, a.b0, a.b1,
-                       a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag, (const T *)a.rhs,
-                       (const V4 *)a.msg_in, (V4 *)a.msg_out, (const V2 *)a.sums_in,
-                       (V2 *)a.sums_out, (T)a.alpha, (T *)a.xprev, a.part, a.sticky, a.ctl);
+                       a.vbase, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag,
+                       (const T *)a.rhs, (const V4 *)a.msg_in, (V4 *)a.msg_out,
+                       (const V2 *)a.sums_in, (const V2 *)a.carry, (V2 *)a.sums_out, a.last,
+                       (T)a.alpha, (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
 }
 
 template <typename T>
@@ -934,18 +966,19 @@ std::vector<int32_t> pair_row_blocks(const int32_t *rp, const std::vector<int> &
   return rb;
 }
 
-hipError_t launch_pair_aggregate(bool fp32, int grid, const int32_t *rb, int nblk,
-                                 const int32_t *oprt, const void *diag, const void *rhs,
-                                 const void *msg, void *sums, hipStream_t s) {
-  if (nblk <= 0) return hipSuccess;
+hipError_t launch_pair_aggregate(bool fp32, int grid, const int32_t *rb, int b0, int b1,
+                                 int vbase, const int32_t *oprt, const void *diag, const void *rhs,
+                                 const void *msg, const void *carry, void *sums, bool last,
+                                 hipStream_t s) {
+  if (b1 <= b0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL(k_pair_aggregate<float>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, oprt,
-                       (const float *)diag, (const float *)rhs, (const float4 *)msg,
-                       (float2 *)sums);
+    hipLaunchKernelGGL(k_pair_aggregate<float>, dim3(grid), dim3(kBlock), 0, s, rb, b0, b1, vbase,
+                       oprt, (const float *)diag, (const float *)rhs, (const float4 *)msg,
+                       (const float2 *)carry, (float2 *)sums, last);
   else
-    hipLaunchKernelGGL(k_pair_aggregate<double>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, oprt,
-                       (const double *)diag, (const double *)rhs, (const double4 *)msg,
-                       (double2 *)sums);
+    hipLaunchKernelGGL(k_pair_aggregate<double>, dim3(grid), dim3(kBlock), 0, s, rb, b0, b1, vbase,
+                       oprt, (const double *)diag, (const double *)rhs, (const double4 *)msg,
+                       (const double2 *)carry, (double2 *)sums, last);
   return hipGetLastError();
 }
 
@@ -972,17 +1005,17 @@ hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfi
   return hipGetLastError();
 }
 
-hipError_t launch_pair_freeze(bool fp32, int grid, const int32_t *rb, int nblk,
+hipError_t launch_pair_freeze(bool fp32, int grid, const int32_t *rb, int nblk, int n,
                               const int32_t *oprt, const int32_t *ocol, const int32_t *rev,
                               const void *acoef, const void *msg, const void *sums, void *coef,
                               void *hp, void *Sfix, void *Hfz, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL(k_pair_freeze<float>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, oprt, ocol,
+    hipLaunchKernelGGL(k_pair_freeze<float>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, n, oprt, ocol,
                        rev, (const float *)acoef, (const float4 *)msg, (const float2 *)sums,
                        (float2 *)coef, (float2 *)hp, (float *)Sfix, (float *)Hfz);
   else
-    hipLaunchKernelGGL(k_pair_freeze<double>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, oprt, ocol,
+    hipLaunchKernelGGL(k_pair_freeze<double>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, n, oprt, ocol,
                        rev, (const double *)acoef, (const double4 *)msg, (const double2 *)sums,
                        (double2 *)coef, (double2 *)hp, (double *)Sfix, (double *)Hfz);
   return hipGetLastError();
@@ -1002,17 +1035,17 @@ hipError_t launch_frozen_restart(bool fp32, int64_t E, int n, void *hp, const vo
   return hipGetLastError();
 }
 
-hipError_t launch_pair_io(bool fp32, bool get, int n, const int64_t *rp, const int64_t *diagpos,
-                          const int32_t *oprt, const int32_t *rev, void *msg, double *P, double *h,
-                          hipStream_t s) {
+hipError_t launch_pair_io(bool fp32, bool get, int n, int nb, const int64_t *rp,
+                          const int64_t *diagpos, const int32_t *oprt, const int32_t *rev,
+                          void *msg, double *P, double *h, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const dim3 grid((n + kBlock - 1) / kBlock);
   if (fp32) {
-    if (get) hipLaunchKernelGGL((k_pair_io<float, true>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, rev, (float4 *)msg, P, h);
-    else hipLaunchKernelGGL((k_pair_io<float, false>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, rev, (float4 *)msg, P, h);
+    if (get) hipLaunchKernelGGL((k_pair_io<float, true>), grid, dim3(kBlock), 0, s, n, nb, rp, diagpos, oprt, rev, (float4 *)msg, P, h);
+    else hipLaunchKernelGGL((k_pair_io<float, false>), grid, dim3(kBlock), 0, s, n, nb, rp, diagpos, oprt, rev, (float4 *)msg, P, h);
   } else {
-    if (get) hipLaunchKernelGGL((k_pair_io<double, true>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, rev, (double4 *)msg, P, h);
-    else hipLaunchKernelGGL((k_pair_io<double, false>), grid, dim3(kBlock), 0, s, n, rp, diagpos, oprt, rev, (double4 *)msg, P, h);
+    if (get) hipLaunchKernelGGL((k_pair_io<double, true>), grid, dim3(kBlock), 0, s, n, nb, rp, diagpos, oprt, rev, (double4 *)msg, P, h);
+    else hipLaunchKernelGGL((k_pair_io<double, false>), grid, dim3(kBlock), 0, s, n, nb, rp, diagpos, oprt, rev, (double4 *)msg, P, h);
   }
   return hipGetLastError();
 }

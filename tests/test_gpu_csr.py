@@ -221,6 +221,111 @@ def test_pair_row_blocks_long_rows_and_grid_stride(G, case, fp32):
     G.gabp_plan_destroy(plan)
 
 
+# FP32 on the diagonally dominant cases only, as for one range: the trees and
+# dense rows here are not dominant, and their small cavities amplify FP32
+# rounding beyond a fixed tolerance
+@pytest.mark.parametrize("case,fp32", [(c, False) for c in sorted(CASES)] +
+                         [(c, True) for c in ("sdd_ragged", "poisson3d_13x11x7", "varcoef_9x7x5")])
+def test_two_column_ranges_trajectory_matches_oracle(G, case, fp32):
+    """Pair layout with two column ranges (each sweep one launch per range,
+    node sums carried from the first to the second): round-by-round messages
+    and marginals follow Algorithm 2 of the oracle."""
+    m = CASES[case]()
+    b = W.uniform_b(m.n, 7)
+    Ad, plan = _plan(G, m, fp32=fp32, col_blocks=2)
+    assert G.gabp_plan_reset(plan, dev(b)) == G.GABP_OK
+    R = oracle.Rounds(m, b, algorithm=2)
+    rtol = 2e-5 if fp32 else 1e-10
+    for t in range(1, 5):
+        R.step()
+        assert G.gabp_plan_sweeps(plan, 1) == G.GABP_OK
+        P, h = _messages(G, plan, m.nnz)
+        ho = R.information()
+        np.testing.assert_allclose(P, R.P, rtol=rtol, atol=rtol * 0.1 * np.abs(R.P).max(),
+                                   err_msg=f"P round {t}")
+        np.testing.assert_allclose(h, ho, rtol=rtol, atol=rtol * np.abs(ho).max(),
+                                   err_msg=f"h round {t}")
+        mean, prec = _marginals(G, plan, m.n)
+        mo, po = R.marginals()
+        np.testing.assert_allclose(prec, po, rtol=rtol, atol=rtol * 0.1 * np.abs(po).max())
+        np.testing.assert_allclose(mean, mo, rtol=rtol, atol=rtol * np.abs(mo).max())
+    G.gabp_plan_destroy(plan)
+
+
+def test_two_column_ranges_damped_and_resumed_bitwise(G):
+    """Two column ranges: damped rounds follow the oracle, and exported
+    messages resume a plan bit for bit (5 + 5 sweeps == 10 sweeps)."""
+    m = W.poisson3d(10, 9, 8, 0.01)
+    b = W.uniform_b(m.n, 3)
+    Ad, plan = _plan(G, m, fp32=False, damping=0.5, col_blocks=2)
+    assert G.gabp_plan_reset(plan, dev(b)) == G.GABP_OK
+    R = oracle.Rounds(m, b, algorithm=2, damping=0.5)
+    for t in range(1, 5):
+        R.step()
+        assert G.gabp_plan_sweeps(plan, 1) == G.GABP_OK
+        P, h = _messages(G, plan, m.nnz)
+        np.testing.assert_allclose(P, R.P, rtol=1e-12, atol=1e-14)
+        ho = R.information()
+        np.testing.assert_allclose(h, ho, rtol=1e-10, atol=1e-12 * np.abs(ho).max())
+    G.gabp_plan_destroy(plan)
+    m = W.sdd_random(4001, 9)
+    b = W.normal_b(m.n, 9)
+    _, p1 = _plan(G, m, fp32=True, col_blocks=2)
+    G.gabp_plan_reset(p1, dev(b)); G.gabp_plan_sweeps(p1, 10)
+    P10, h10 = _messages(G, p1, m.nnz)
+    _, p2 = _plan(G, m, fp32=True, col_blocks=2)
+    G.gabp_plan_reset(p2, dev(b)); G.gabp_plan_sweeps(p2, 5)
+    P5, h5 = _messages(G, p2, m.nnz)
+    _, p3 = _plan(G, m, fp32=True, col_blocks=2)
+    G.gabp_plan_reset(p3, dev(b))
+    assert G.gabp_plan_set_messages(p3, dev(P5), dev(h5)) == G.GABP_OK
+    G.gabp_plan_sweeps(p3, 5)
+    P, h = _messages(G, p3, m.nnz)
+    assert np.array_equal(P, P10) and np.array_equal(h, h10)
+    for p in (p1, p2, p3):
+        G.gabp_plan_destroy(p)
+
+
+@pytest.mark.parametrize("col_blocks", [1, 2])
+def test_column_ranges_solve_refined_with_settled_phase(G, col_blocks):
+    """FP32 + FP64 refinement to 1e-8 with one or two column ranges, through
+    the settled-precision phase; the plan reports its launches per sweep."""
+    m = W.sdd_random(20011, 4)
+    b = W.normal_b(m.n, 4)
+    rc, st, x = _solve(G, m, b, msg_fp32=1, tol=1e-8, col_blocks=col_blocks)
+    assert rc == G.GABP_OK, G.status_name(rc)
+    assert st.frozen_sweeps > 0 and st.sweep_launches == col_blocks
+    _, rn = oracle.residual(m, b, x)
+    assert rn / np.linalg.norm(b) <= 1e-8
+
+
+def test_column_ranges_automatic_choice(G):
+    """Default choice: two ranges for a random graph whose FP32 node table
+    exceeds 4 MiB, one for a naturally ordered grid of the same size (its
+    edges join nearby indices) and for small graphs; either way the solve
+    meets 1e-8."""
+    for m, want in ((W.sdd_random(600_000, 2), 2), (W.poisson3d(90, 90, 80, 0.01), 1),
+                    (W.sdd_random(3001, 5), 1)):
+        b = W.normal_b(m.n, 1)
+        rc, st, x = _solve(G, m, b, msg_fp32=1, tol=1e-8)
+        assert rc == G.GABP_OK, G.status_name(rc)
+        assert st.sweep_launches == want, (m.n, st.sweep_launches)
+        _, rn = oracle.residual(m, b, x)
+        assert rn / np.linalg.norm(b) <= 1e-8
+
+
+def test_column_ranges_option_checks(G):
+    m = W.sdd_random(200, 1)
+    A = G.DeviceCSR.from_host(m)
+    rc, plan = G.gabp_plan_create(A, G.gabp_default_opts(col_blocks=3))
+    assert rc == G.GABP_ERR_ARG and plan is None
+    rc, plan = G.gabp_plan_create(A, G.gabp_default_opts(col_blocks=2, layout=1))
+    assert rc == G.GABP_ERR_UNSUPPORTED and plan is None
+    rc, plan = G.gabp_plan_create(A, G.gabp_default_opts(col_blocks=2,
+                                                         schedule=G.GABP_SCHEDULE_COLORED))
+    assert rc == G.GABP_ERR_UNSUPPORTED and plan is None
+
+
 def test_pair_hub_solve_settled_phase_small_grid(G):
     """FP32 solve of the hub graph to 1e-8 with a two-block grid: the check
     sweeps' block maxima and the settled-precision kernel walk many row
