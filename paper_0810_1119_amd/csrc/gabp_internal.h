@@ -89,6 +89,10 @@ constexpr int kMaxSweepBlocks = 2048;  // row kernels loop over row groups beyon
 // slots each (a longer row alone); slots are streamed in chunks of kSegChunk
 constexpr int kSegRows = 128;
 constexpr int kSegChunk = 1024;
+// workgroups of a pair-layout launch: one per row block up to this many
+// (a random graph of 2^20 rows has 8192 blocks), so that blocks overlap
+// through the hardware scheduler rather than queue inside a workgroup
+constexpr int kMaxPairBlocks = 16384;
 
 // ---- launchers (kernels_csr.hip) ----
 hipError_t launch_plan_rows(int n, int64_t nnz, const int64_t *rp, const int32_t *col,
