@@ -87,7 +87,7 @@ constexpr int kBlock = 256;       // threads per block of the row kernels
 constexpr int kMaxSweepBlocks = 2048;  // row kernels loop over row groups beyond this
 // row blocks of the pair-layout sweeps: at most kSegRows rows and kSegChunk
 // slots each (a longer row alone); slots are streamed in chunks of kSegChunk
-constexpr int kSegRows = 128;
+constexpr int kSegRows = 256;
 constexpr int kSegChunk = 1024;
 // workgroups of a pair-layout launch: one per row block up to this many
 // (a random graph of 2^20 rows has 8192 blocks), so that blocks overlap
