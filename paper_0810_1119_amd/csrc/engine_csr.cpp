@@ -95,7 +95,7 @@ struct CsrEngine : Engine {
   int sweep_launches() const override { return colored() ? (int)cls.size() - 1 : (pair ? nb : 1); }
 
   // workgroups of a launch over all row blocks
-  int bgrid() const { return std::max(1, std::min(bfirst.back(), kMaxPairBlocks)); }
+  int bgrid() const { return std::max(1, std::min(bfirst.back(), pair_max_blocks())); }
 
   // node sums from the stored in-messages, range by range as the sweeps add
   // them (one range: every row block, colour classes included)
@@ -194,7 +194,7 @@ struct CsrEngine : Engine {
         a.rb = rblk;
         a.b0 = bfirst[k];
         a.b1 = bfirst[k + 1];
-        a.grid = std::max(1, std::min(a.b1 - a.b0, kMaxPairBlocks));
+        a.grid = std::max(1, std::min(a.b1 - a.b0, pair_max_blocks()));
         hipError_t err = launch_pair_col_infer(a, xacc, marg, means, s);
         if (err != hipSuccess) return err;
       }
@@ -416,7 +416,7 @@ int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int
   const int cap = opts.grid_blocks > 0 ? opts.grid_blocks : kMaxSweepBlocks;
   e->grid = sweep_blocks(std::max(e->n, 1), e->group, cap);
   e->nparts = e->grid;
-  if (e->pair && (st = e->row_blocks(opts.grid_blocks > 0 ? opts.grid_blocks : kMaxPairBlocks, s)))
+  if (e->pair && (st = e->row_blocks(opts.grid_blocks > 0 ? opts.grid_blocks : pair_max_blocks(), s)))
     return fail(st);
   e->nsum = residual_blocks(std::max(e->n, 1), cap);
   if ((st = e->init_common(s))) return fail(st);

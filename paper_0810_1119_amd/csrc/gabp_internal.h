@@ -85,14 +85,6 @@ template <> struct Vec2<double> { using type = double2; };
 
 constexpr int kBlock = 256;       // threads per block of the row kernels
 constexpr int kMaxSweepBlocks = 2048;  // row kernels loop over row groups beyond this
-// row blocks of the pair-layout sweeps: at most kSegRows rows and kSegChunk
-// slots each (a longer row alone); slots are streamed in chunks of kSegChunk
-constexpr int kSegRows = 256;
-constexpr int kSegChunk = 1024;
-// workgroups of a pair-layout launch: one per row block up to this many
-// (a random graph of 2^20 rows has 8192 blocks), so that blocks overlap
-// through the hardware scheduler rather than queue inside a workgroup
-constexpr int kMaxPairBlocks = 16384;
 
 // ---- launchers (kernels_csr.hip) ----
 hipError_t launch_plan_rows(int n, int64_t nnz, const int64_t *rp, const int32_t *col,
@@ -205,12 +197,16 @@ struct PairArgs {
 };
 hipError_t launch_pair_sweep(const PairArgs &a, hipStream_t s);
 // Row blocks of the pair sweeps for the row ranges [bounds[k], bounds[k+1])
-// (colour classes, or one range): consecutive rows, at most kSegRows rows and
-// kSegChunk slots per block unless one row has more; rp is the slot offset of
-// every row (host copy).  Returns the block offsets (rows); first_block[k] is
-// the first block of range k (first_block.back() = the number of blocks).
+// (colour classes, or one range): consecutive rows, at most 256 rows and 1024
+// slots per block unless one row has more; rp is the slot offset of every row
+// (host copy).  Returns the block offsets (rows); first_block[k] is the first
+// block of range k (first_block.back() = the number of blocks).
 std::vector<int32_t> pair_row_blocks(const int32_t *rp, const std::vector<int> &bounds,
                                      std::vector<int> *first_block);
+// workgroups of a pair-layout launch at most: one per row block up to this
+// many, so that blocks overlap through the hardware scheduler rather than
+// queue inside a workgroup
+int pair_max_blocks();
 // marginals of one class (rows [row0, row1), row blocks [b0, b1) of rb) of a
 // coloured pair plan from its current messages after a complete sweep
 // (msg_in / sums_in: the full state, or in the settled state the information

@@ -45,6 +45,9 @@ template <> struct Vec4<double> { using type = double4; };
 // it finds each slot's row by a binary search of the offsets, leaves the
 // slot's in-message in LDS, and the row's own thread then adds its
 // in-messages in slot order.
+constexpr int kSegRows = 256;    // rows of a block at most
+constexpr int kSegChunk = 1024;  // slots of a block (a longer row alone), streamed per chunk
+constexpr int kMaxPairBlocks = 16384;  // a random graph of 2^20 rows has 8192 blocks
 constexpr int kSegK = kSegChunk / kBlock;
 static_assert(kSegChunk % kBlock == 0 && kSegRows <= kBlock, "row block shape");
 
@@ -941,6 +944,8 @@ hipError_t launch_pair_sweep(const PairArgs &a, hipStream_t s) {
   if (a.b1 <= a.b0 && !(a.colored && a.mode == 1)) return hipSuccess;
   return a.fp32 ? pair_t<float>(a, s) : pair_t<double>(a, s);
 }
+
+int pair_max_blocks() { return kMaxPairBlocks; }
 
 std::vector<int32_t> pair_row_blocks(const int32_t *rp, const std::vector<int> &bounds,
                                      std::vector<int> *first_block) {
