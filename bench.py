@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "lsq"])
+    ap.add_argument("--log2n", type=int, default=20,
+                    help="c2: log2 of the unknowns (20 is the configuration; 23 puts the "
+                         "working set beyond the 256 MB last-level cache)")
     ap.add_argument("--waves", type=int, default=0, help="c3: wavefronts per workgroup (0 = autotuned)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -180,7 +183,7 @@ def run_c5(args, G, W, torch, dev):
 
 
 def run_c2(args, G, W, torch, dev):
-    n = 1 << 20
+    n = 1 << args.log2n
     m = W.sdd_random(n, args.seed)
     b_h = W.normal_b(n, args.seed)
     E = int(m.nnz - n)
@@ -210,7 +213,7 @@ def run_c2(args, G, W, torch, dev):
     # coloured: one launch per colour class, each over its rows and their slots;
     # the bytes of a sweep are those of a synchronous pair sweep
     return dict(plan=plan, b=b, x=x, E=E, n=n, m=m, b_h=b_h, A=A, per_sweep=ncol,
-                workload="random sparse SDD A (n=2^20, ~8 off-diagonals/row, N(0,1) couplings, "
+                workload=f"random sparse SDD A (n=2^{args.log2n}, ~8 off-diagonals/row, N(0,1) couplings, "
                          "A_ii=1.1 sum|A_ij|), b~N(0,1); FP32 messages + FP64 refinement to 1e-8; "
                          + (f"coloured schedule ({ncol} colours)" if colored
                             else "synchronous schedule"),
