@@ -51,6 +51,29 @@ constexpr int kMaxPairBlocks = 16384;  // a random graph of 2^20 rows has 8192 b
 constexpr int kSegK = kSegChunk / kBlock;
 static_assert(kSegChunk % kBlock == 0 && kSegRows <= kBlock, "row block shape");
 
+
+// non-temporal (streaming) access to slot data: read or written once per
+// sweep, kept out of the way of the gathered node tables
+template <typename V>
+__device__ __forceinline__ V nt_load(const V *p) {
+  using E = decltype(p->x);
+  constexpr int N = sizeof(V) / sizeof(E);
+  typedef E vec __attribute__((ext_vector_type(N)));
+  const vec v = __builtin_nontemporal_load((const vec *)p);
+  V out;
+  __builtin_memcpy(&out, &v, sizeof(V));
+  return out;
+}
+template <typename V>
+__device__ __forceinline__ void nt_store(V *p, const V &x) {
+  using E = decltype(p->x);
+  constexpr int N = sizeof(V) / sizeof(E);
+  typedef E vec __attribute__((ext_vector_type(N)));
+  vec v;
+  __builtin_memcpy(&v, &x, sizeof(V));
+  __builtin_nontemporal_store(v, (vec *)p);
+}
+
 // the row of slot e: the last r with rp[r] <= e (rp[0] <= e < rp[nr])
 __device__ __forceinline__ int seg_row(const int *rp, int nr, int e) {
   int lo = 0, hi = nr;
@@ -118,9 +141,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
         a[k] = T(0);
         m[k] = V4{};
         if (e < e1) {
-          j[k] = ocol[e];
-          a[k] = acoef[e];
-          m[k] = mi[e];  // (P_ij, h_ij, P_ji, h_ji) of round t
+          j[k] = __builtin_nontemporal_load(&ocol[e]);
+          a[k] = __builtin_nontemporal_load(&acoef[e]);
+          m[k] = nt_load(&mi[e]);  // (P_ij, h_ij, P_ji, h_ji) of round t
         }
       }
 #pragma unroll
@@ -152,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
         }
         V4 o;
         o.x = Pout; o.y = hout; o.z = Pin; o.w = hin;
-        mo[e] = o;
+        nt_store(&mo[e], o);
         V2 v;
         v.x = Pin;
         v.y = hin;
@@ -400,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen(
         V2 o;
         o.x = ho;
         o.y = hi;
-        hout[e] = o;
+        nt_store(&hout[e], o);
         in[e - c] = hi;
       }
       __syncthreads();
@@ -523,7 +546,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_col(
         if (e < e1) {
           j[k] = ocol[e];
           a[k] = acoef[e];
-          m[k] = msg[e];  // (P_ij, h_ij, P_ji, h_ji) as last written
+          m[k] = nt_load(&msg[e]);  // (P_ij, h_ij, P_ji, h_ji) as last written
         }
       }
 #pragma unroll
@@ -624,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_col(
         }
         V4 o;
         o.x = Pout; o.y = hout; o.z = Pin[k]; o.w = hin[k];
-        msg[e] = o;
+        nt_store(&msg[e], o);
       }
     }
   }
@@ -761,7 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen_col(
         V2 o;
         o.x = hout;
         o.y = hin[k];
-        hp[e] = o;
+        nt_store(&hp[e], o);
       }
     }
   }
