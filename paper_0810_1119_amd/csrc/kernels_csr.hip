@@ -470,9 +470,9 @@ __global__ __launch_bounds__(kBlock) void k_csr_residual(
           const int64_t e = c + k * kBlock + t;
           j[k] = 0;
           v[k] = 0.0;
-          if (e < e1) {
-            j[k] = col[e];
-            v[k] = val[e];
+          if (e < e1) {  // streamed once: kept out of the L2 that the x gather uses
+            j[k] = __builtin_nontemporal_load(&col[e]);
+            v[k] = __builtin_nontemporal_load(&val[e]);
           }
         }
 #pragma unroll

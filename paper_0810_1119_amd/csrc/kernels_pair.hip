@@ -341,9 +341,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_freeze(
     __syncthreads();
     const int e1 = rp[nr];
     for (int e = rp[0] + t; e < e1; e += kBlock) {
-      const int j = ocol[e];
-      const T a = acoef[e];
-      const auto m = msg[e];
+      const int j = __builtin_nontemporal_load(&ocol[e]);
+      const T a = __builtin_nontemporal_load(&acoef[e]);
+      const auto m = nt_load(&msg[e]);
       const T Si = own[seg_row(rp, nr, e)];
       V2 c, h;
       c.x = -a * (T(1) / (Si - m.z));           // c_ij: out-message coefficient
@@ -351,8 +351,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_freeze(
       c.y = -a * (T(1) / (sums[j].x - Pij));    // c_ji: in-message coefficient
       h.x = m.y;
       h.y = m.w;
-      coef[e] = c;
-      hp[e] = h;
+      nt_store(&coef[e], c);
+      nt_store(&hp[e], h);
     }
   }
 }
