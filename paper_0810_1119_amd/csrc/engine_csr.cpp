@@ -224,8 +224,9 @@ struct CsrEngine : Engine {
     first = true;
     const int64_t words = E * (int64_t)msg_bytes() / 8;
     hipError_t err;
+    // msg[1] needs no clearing: a synchronous sweep writes every slot of it
+    // before anything reads it, and coloured sweeps work in msg[0]
     if ((err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
-    if ((err = launch_fill_zero(msg[1], words, s)) != hipSuccess) return err;
     if ((err = launch_residual(fp32, nsum, n, A.row_ptr, A.col, A.val, b, nullptr, rhs,
                                nullptr, sumpart, s)) != hipSuccess)
       return err;

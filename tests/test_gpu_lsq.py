@@ -48,11 +48,15 @@ SHAPES = {
 
 
 @pytest.mark.parametrize("case", sorted(SHAPES))
-def test_lsq_fp64_trajectory_matches_oracle(G, case):
+@pytest.mark.parametrize("col_blocks", [1, 2])
+def test_lsq_fp64_trajectory_matches_oracle(G, case, col_blocks):
+    """Synchronous rounds of the assembled system against the oracle, with one
+    and with two column ranges of the pair layout."""
     m, k, pr, psi = SHAPES[case]
     S = W.sparse_rect(m, k, pr, seed=m * 7 + k)
     y = W.normal_b(m, 5)
-    rc, plan = G.gabp_plan_create_lsq(_rect(G, S), psi, G.gabp_default_opts(msg_fp32=0, freeze=0))
+    rc, plan = G.gabp_plan_create_lsq(_rect(G, S), psi, G.gabp_default_opts(
+        msg_fp32=0, freeze=0, col_blocks=col_blocks))
     assert rc == G.GABP_OK, G.status_name(rc)
     try:
         mb, rhs = oracle.bipartite_system(S.dense(), y, psi)
