@@ -44,6 +44,7 @@ Engine::~Engine() {
       (void)hipEventDestroy(ev_end[k]);
       (void)hipEventDestroy(ev_done[k]);
     }
+  if (ev_sum) (void)hipEventDestroy(ev_sum);
 }
 
 int Engine::init_common(hipStream_t s) {
@@ -56,7 +57,10 @@ int Engine::init_common(hipStream_t s) {
       (st = from_hip(dalloc(&xprev, means_slots(), tsz))))
     return st;
   if (nseg > 1 && (st = from_hip(dalloc(&segb2, nseg, sizeof(double))))) return st;
-  if ((st = from_hip(hipHostMalloc((void **)&host, kRing * sizeof(HostReadout), hipHostMallocDefault))))
+  // kRing chunk readouts and one slot for the residual sums
+  if ((st = from_hip(hipHostMalloc((void **)&host, (kRing + 1) * sizeof(HostReadout),
+                                   hipHostMallocDefault))) ||
+      (st = from_hip(hipEventCreateWithFlags(&ev_sum, hipEventDisableTiming))))
     return st;
   for (int k = 0; k < kRing; ++k) {
     if ((st = from_hip(hipEventCreate(&ev_beg[k]))) || (st = from_hip(hipEventCreate(&ev_end[k]))) ||
@@ -74,15 +78,23 @@ int Engine::init_common(hipStream_t s) {
   return GABP_OK;
 }
 
-int Engine::read_sum(hipStream_t s, HostReadout *outv, int seg_mode, double bnorm) {
-  const int slot = 0;
-  TRY_HIP(launch_readout(nullptr, 0, sumpart, nsum, sticky, ctl, 0, ++seq, &host[slot], s));
+int Engine::post_sum(hipStream_t s, int seg_mode, double bnorm) {
+  TRY_HIP(launch_readout(nullptr, 0, sumpart, nsum, sticky, ctl, 0, ++seq, &host[kRing], s));
   if (nseg > 1 && seg_mode > 0)
-    TRY_HIP(launch_seg_norms(sumpart, nseg, segb, segb2, seg_mode == 1, bnorm, &host[slot], s));
-  TRY_HIP(hipEventRecord(ev_done[slot], s));
-  TRY_HIP(hipEventSynchronize(ev_done[slot]));
-  *outv = host[slot];
+    TRY_HIP(launch_seg_norms(sumpart, nseg, segb, segb2, seg_mode == 1, bnorm, &host[kRing], s));
+  TRY_HIP(hipEventRecord(ev_sum, s));
   return GABP_OK;
+}
+
+int Engine::wait_sum(HostReadout *outv) {
+  TRY_HIP(hipEventSynchronize(ev_sum));
+  *outv = host[kRing];
+  return GABP_OK;
+}
+
+int Engine::read_sum(hipStream_t s, HostReadout *outv, int seg_mode, double bnorm) {
+  const int rc = post_sum(s, seg_mode, bnorm);
+  return rc ? rc : wait_sum(outv);
 }
 
 int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
@@ -128,18 +140,32 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   else TRY_HIP(launch_fill_zero(p->xprev, p->means_slots(), s));
   TRY_HIP(launch_fill_zero(x, p->n, s));
   TRY_HIP(launch_ctl_reset(p->ctl, target_for(1.0), floor, freeze_tol, true, 0, s));
-  HostReadout r0;
-  int rc = p->read_sum(s, &r0, 1);
+  // ||b||: a plain solve reads it back after the first pass's sweeps, which
+  // then need not wait for it (x is untouched until then; a zero b converges
+  // at the first check, a non-finite one stops it); a warm start and the
+  // marginals of a zero b need it now
+  int rc = p->post_sum(s, 1);
   if (rc) return finish(rc);
-  if (!std::isfinite(r0.sum)) return finish(GABP_ERR_ARG);
-  const double bn = std::sqrt(r0.sum);
-  if (bn == 0.0) {
+  double bn = -1.0;
+  auto take_bn = [&]() -> int {
+    HostReadout r0;
+    const int e = p->wait_sum(&r0);
+    if (e) return e;
+    if (!std::isfinite(r0.sum)) return GABP_ERR_ARG;
+    bn = std::sqrt(r0.sum);
+    return GABP_OK;
+  };
+  auto zero_b = [&]() {
     stats.rel_residual = 0.0;
     if (marg_prec) {
       TRY_HIP(p->infer(nullptr, marg_prec, nullptr, s));
       TRY_HIP(hipStreamSynchronize(s));
     }
     return finish(GABP_OK);
+  };
+  if (warm || marg_prec) {
+    if ((rc = take_bn())) return finish(rc);
+    if (bn == 0.0) return zero_b();
   }
 
   if (warm) {
@@ -213,13 +239,18 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
       ++rd;
       if (h.stop != STOP_NONE) stopped = true;
       if (stopped && rd < enq) {
-        // drain: the remaining queued chunks are no-ops on the device
-        TRY_HIP(hipEventSynchronize(p->ev_done[(enq - 1) % kRing]));
+        // the remaining queued chunks are no-ops on the device; the work
+        // enqueued next runs after them in stream order, and the host's next
+        // wait covers them, so there is nothing to wait for here
         rd = enq;
       }
     }
     sweeps_done = last_sweeps;
     stats.sweeps = sweeps_done;
+    if (bn < 0.0) {
+      if ((rc = take_bn())) return finish(rc);
+      if (bn == 0.0) return zero_b();
+    }
     // ---- x += H/S, r = b - A x (FP64), ||r|| ----
     TRY_HIP(p->infer(x, nullptr, nullptr, s));
     TRY_HIP(p->residual(b, x, nullptr, s));

@@ -67,7 +67,7 @@ struct Engine {
   int nseg = 1, segb = 0;
   double *segb2 = nullptr;  // ||b_t||^2 per segment
   HostReadout *host = nullptr;
-  hipEvent_t ev_beg[kRing] = {}, ev_end[kRing] = {}, ev_done[kRing] = {};
+  hipEvent_t ev_beg[kRing] = {}, ev_end[kRing] = {}, ev_done[kRing] = {}, ev_sum = nullptr;
   bool events = false;
   int seq = 0;
 
@@ -108,6 +108,10 @@ struct Engine {
   // 1 keeps the per-segment squared norms as ||b_t||^2, 2 reports the largest
   // per-segment relative residual in outv->segrel (bnorm = ||b||)
   int read_sum(hipStream_t s, HostReadout *outv, int seg_mode = 0, double bnorm = 0.0);
+  // read_sum in two halves: post_sum enqueues the reduction into its own host
+  // slot, wait_sum waits for it and copies the readout
+  int post_sum(hipStream_t s, int seg_mode = 0, double bnorm = 0.0);
+  int wait_sum(HostReadout *outv);
 };
 
 // refinement loop around chunked sweeps (api.cpp)
