@@ -258,9 +258,9 @@ struct CsrEngine : Engine {
   }
 
   hipError_t freeze(hipStream_t s) override {
-    hipError_t err = launch_pair_freeze(fp32, bgrid(), rblk, bfirst.back(), n, oprt, ocol,
-                                        colored() ? rev : nullptr, acoef, msg[cur], sums[cur], coef,
-                                        hp[cur], Sfix, Hfz[cur], s);
+    hipError_t err = launch_pair_freeze(fp32, bgrid(), rblk, bfirst.back(), n, oprt, ocol, rev,
+                                        colored(), acoef, msg[cur], sums[cur], coef, hp[cur], Sfix,
+                                        Hfz[cur], s);
     frozen = true;
     return err;
   }

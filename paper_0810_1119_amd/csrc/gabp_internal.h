@@ -227,12 +227,14 @@ hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfi
                              double *xacc, double *marg, void *means, uint32_t *sticky,
                              hipStream_t s);
 // Settled-precision coefficients over the row blocks [0, nblk) of rb (n nodes;
-// with two column ranges the blocks span both); rev: NULL, or the
-// reverse-slot index (coloured plans; see k_pair_freeze)
+// with two column ranges the blocks span both).  scatter (coloured plans):
+// every slot stores its out-coefficient and, through rev, the in-coefficient
+// of its reverse slot; otherwise each slot recomputes its in-coefficient from
+// its copy of the message and the gathered total (ocol)
 hipError_t launch_pair_freeze(bool fp32, int grid, const int32_t *rb, int nblk, int n,
                               const int32_t *oprt, const int32_t *ocol, const int32_t *rev,
-                              const void *acoef, const void *msg, const void *sums, void *coef,
-                              void *hp, void *Sfix, void *Hfz, hipStream_t s);
+                              bool scatter, const void *acoef, const void *msg, const void *sums,
+                              void *coef, void *hp, void *Sfix, void *Hfz, hipStream_t s);
 hipError_t launch_frozen_restart(bool fp32, int64_t E, int n, void *hp, const void *rhs, void *Hfz,
                                  hipStream_t s);
 // messages in CSR entry order (get) or into the slots (set); nb column ranges

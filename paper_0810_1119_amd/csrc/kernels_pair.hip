@@ -306,12 +306,20 @@ __global__ void k_pair_infer(int n, const typename Vec2<T>::type *__restrict__ s
 // ---------------------------------------------------------------------------
 // freeze: P has stopped changing; derive the fixed coefficients
 // ---------------------------------------------------------------------------
-// rev != NULL (coloured plans): the in-message coefficient c_ji is computed
-// from the sender's own copy of P_ij (its slot's received part), the operands
-// the sender uses for its out-coefficient.  In a synchronous state every pair
-// of copies is equal; in a coloured one a row that sent after j holds a newer
-// P_ij than the one j used, and the two copies of c_ji must still agree.
-template <typename T>
+// Each slot (i, j) computes its out-message coefficient c_ij = -A_ij / (S_i -
+// P_ji) and the in-message coefficient c_ji of the message it receives.  The
+// two copies of every coefficient (the sender's and the receiver's) must be
+// the same number.  In a synchronous state both copies of every message are
+// equal, so the receiver recomputes c_ji = -A_ij / (S_j - P_ij) from its own
+// copy of P_ij and the gathered S_j.  In a coloured state a row that sent
+// after j holds a newer P_ij than the one j used, so the receiver's copy would
+// not match: there (SCATTER) each slot stores its c_ij twice instead, as its
+// own out-coefficient and, through the reverse-slot index, as the
+// in-coefficient of slot (j, i).  A scattered 4-byte store costs more than the
+// gather on the random graph (180 against 117 us) but less than the two
+// gathers a coloured receiver would need (374 against 607 us on the
+// least-squares system).
+template <typename T, bool SCATTER>
 __global__ __launch_bounds__(kBlock) void k_pair_freeze(
     const int32_t *__restrict__ rb, int nblk, int n, const int32_t *__restrict__ oprt,
     const int32_t *__restrict__ ocol, const int32_t *__restrict__ rev, const T *__restrict__ acoef,
@@ -341,17 +349,24 @@ __global__ __launch_bounds__(kBlock) void k_pair_freeze(
     __syncthreads();
     const int e1 = rp[nr];
     for (int e = rp[0] + t; e < e1; e += kBlock) {
-      const int j = __builtin_nontemporal_load(&ocol[e]);
       const T a = __builtin_nontemporal_load(&acoef[e]);
       const auto m = nt_load(&msg[e]);
       const T Si = own[seg_row(rp, nr, e)];
-      V2 c, h;
-      c.x = -a * (T(1) / (Si - m.z));           // c_ij: out-message coefficient
-      const T Pij = rev ? msg[rev[e]].z : m.x;  // P_ij as the sender j holds it
-      c.y = -a * (T(1) / (sums[j].x - Pij));    // c_ji: in-message coefficient
+      const T cij = -a * (T(1) / (Si - m.z));  // out-message coefficient
+      if (SCATTER) {
+        const int r = __builtin_nontemporal_load(&rev[e]);
+        coef[e].x = cij;
+        coef[r].y = cij;  // in-message coefficient of (j, i)
+      } else {
+        const int j = __builtin_nontemporal_load(&ocol[e]);
+        V2 c;
+        c.x = cij;
+        c.y = -a * (T(1) / (sums[j].x - m.x));  // c_ji from this slot's copy of P_ij
+        nt_store(&coef[e], c);
+      }
+      V2 h;
       h.x = m.y;
       h.y = m.w;
-      nt_store(&coef[e], c);
       nt_store(&hp[e], h);
     }
   }
@@ -1035,17 +1050,21 @@ hipError_t launch_pair_infer(bool fp32, int n, const void *sums, const void *Sfi
 
 hipError_t launch_pair_freeze(bool fp32, int grid, const int32_t *rb, int nblk, int n,
                               const int32_t *oprt, const int32_t *ocol, const int32_t *rev,
-                              const void *acoef, const void *msg, const void *sums, void *coef,
-                              void *hp, void *Sfix, void *Hfz, hipStream_t s) {
+                              bool scatter, const void *acoef, const void *msg, const void *sums,
+                              void *coef, void *hp, void *Sfix, void *Hfz, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
-  if (fp32)
-    hipLaunchKernelGGL(k_pair_freeze<float>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, n, oprt, ocol,
-                       rev, (const float *)acoef, (const float4 *)msg, (const float2 *)sums,
-                       (float2 *)coef, (float2 *)hp, (float *)Sfix, (float *)Hfz);
-  else
-    hipLaunchKernelGGL(k_pair_freeze<double>, dim3(grid), dim3(kBlock), 0, s, rb, nblk, n, oprt, ocol,
-                       rev, (const double *)acoef, (const double4 *)msg, (const double2 *)sums,
-                       (double2 *)coef, (double2 *)hp, (double *)Sfix, (double *)Hfz);
+#define FREEZE_LAUNCH(T, V4, V2, SC)                                                             \
+  hipLaunchKernelGGL((k_pair_freeze<T, SC>), dim3(grid), dim3(kBlock), 0, s, rb, nblk, n, oprt,   \
+                     ocol, rev, (const T *)acoef, (const V4 *)msg, (const V2 *)sums, (V2 *)coef, \
+                     (V2 *)hp, (T *)Sfix, (T *)Hfz)
+  if (fp32) {
+    if (scatter) FREEZE_LAUNCH(float, float4, float2, true);
+    else FREEZE_LAUNCH(float, float4, float2, false);
+  } else {
+    if (scatter) FREEZE_LAUNCH(double, double4, double2, true);
+    else FREEZE_LAUNCH(double, double4, double2, false);
+  }
+#undef FREEZE_LAUNCH
   return hipGetLastError();
 }
 
