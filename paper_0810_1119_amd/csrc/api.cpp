@@ -48,9 +48,11 @@ Engine::~Engine() {
 }
 
 int Engine::init_common(hipStream_t s) {
-  (void)s;
   int st;
+  // check partials start cleared (slot_publish raises them atomically; the
+  // readout clears them again)
   if ((st = from_hip(dalloc(&part, nparts, sizeof(BlockPartial)))) ||
+      (st = from_hip(launch_fill_zero(part, (int64_t)std::max(nparts, 1) * 4, s))) ||
       (st = from_hip(dalloc(&sumpart, nsum, sizeof(double)))) ||
       (st = from_hip(dalloc(&sticky, 1, sizeof(uint32_t)))) ||
       (st = from_hip(dalloc(&ctl, 1, sizeof(Ctl)))) ||
@@ -135,6 +137,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   };
   if (freezing) TRY_HIP(p->ensure_frozen_buffers());
   TRY_HIP(launch_fill_zero4(p->sticky, 1, s));
+  TRY_HIP(launch_fill_zero(p->part, (int64_t)std::max(p->nparts, 1) * 4, s));  // no stale check maxima
   TRY_HIP(p->reset(b, s));  // also computes ||b||^2 into the residual partials
   if (p->fp32) TRY_HIP(launch_fill_zero4(p->xprev, p->means_slots(), s));
   else TRY_HIP(launch_fill_zero(p->xprev, p->means_slots(), s));

@@ -32,12 +32,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block-wide maxima of four values (every thread of the block must call);
-// thread 0 writes them to part[blockIdx.x], or, with combine, the maxima of
-// them and what part[blockIdx.x] already holds (a later launch of the same
-// check adding its nodes; launches on one stream run in order).
-__device__ __forceinline__ void block_publish(double d, double x, double dp, double pm,
-                                              BlockPartial *part, bool combine = false) {
+// Block-wide maxima of four values (every thread of the block must call, once
+// per kernel); thread 0 ends with them.
+__device__ __forceinline__ void block_max4(double &d, double &x, double &dp, double &pm) {
   __shared__ double sh[4][kBlock / 64];
   d = wave_max(d);
   x = wave_max(x);
@@ -53,13 +50,39 @@ __device__ __forceinline__ void block_publish(double d, double x, double dp, dou
     for (int k = 1; k < kBlock / 64; ++k) {
       d = fmax(d, sh[0][k]); x = fmax(x, sh[1][k]); dp = fmax(dp, sh[2][k]); pm = fmax(pm, sh[3][k]);
     }
-    if (combine) {
-      const BlockPartial o = part[blockIdx.x];
-      d = fmax(d, o.dmax); x = fmax(x, o.xmax); dp = fmax(dp, o.dpmax); pm = fmax(pm, o.pmax);
-    }
+  }
+}
+
+// thread 0 writes the block maxima to part[blockIdx.x]
+__device__ __forceinline__ void block_publish(double d, double x, double dp, double pm,
+                                              BlockPartial *part) {
+  block_max4(d, x, dp, pm);
+  if (threadIdx.x == 0) {
     BlockPartial b;
     b.dmax = d; b.xmax = x; b.dpmax = dp; b.pmax = pm;
     part[blockIdx.x] = b;
+  }
+}
+
+// As block_publish, but for launches with more workgroups than partial slots
+// and for checks split over several launches: thread 0 raises slot
+// blockIdx.x % nslots to the maxima with integer atomics (non-negative
+// doubles order like their bit patterns; NaN and -0 count as 0, as fmax would
+// drop them).  The slots start at zero and the readout clears them.
+__device__ __forceinline__ void atomic_max_nonneg(double *p, double v) {
+  v = v > 0.0 ? v : 0.0;
+  atomicMax((unsigned long long *)p, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ void slot_publish(double d, double x, double dp, double pm,
+                                             BlockPartial *part, int nslots) {
+  block_max4(d, x, dp, pm);
+  if (threadIdx.x == 0) {
+    BlockPartial *q = part + (blockIdx.x % nslots);
+    atomic_max_nonneg(&q->dmax, d);
+    atomic_max_nonneg(&q->xmax, x);
+    atomic_max_nonneg(&q->dpmax, dp);
+    atomic_max_nonneg(&q->pmax, pm);
   }
 }
 

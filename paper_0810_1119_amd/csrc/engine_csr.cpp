@@ -121,7 +121,7 @@ struct CsrEngine : Engine {
         a.grid = sgrid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
         a.frozen = frozen; a.n = n; a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
         a.rhs = rhs; a.alpha = o.damping; a.xprev = xprev; a.part = part; a.sticky = sticky;
-        a.ctl = c; a.colored = true; a.combine = k > 0; a.row0 = cls[k]; a.row1 = cls[k + 1];
+        a.ctl = c; a.colored = true; a.nslots = nparts; a.row0 = cls[k]; a.row1 = cls[k + 1];
         a.rb = rblk; a.b0 = bfirst[k]; a.b1 = bfirst[k + 1];
         a.first = first;
         if (frozen) {
@@ -145,7 +145,7 @@ struct CsrEngine : Engine {
     } else {
       PairArgs a{};
       a.grid = sgrid; a.fp32 = fp32; a.group = group; a.mode = mode; a.damp = o.damping > 0.0;
-      a.frozen = frozen; a.n = n; a.rb = rblk;
+      a.frozen = frozen; a.n = n; a.rb = rblk; a.nslots = nparts;
       a.oprt = oprt; a.ocol = ocol; a.acoef = acoef; a.diag = diag;
       a.rhs = rhs; a.alpha = o.damping; a.xprev = xprev; a.part = part; a.sticky = sticky;
       a.ctl = c;
@@ -164,7 +164,6 @@ struct CsrEngine : Engine {
         a.carry = p > 0 ? carry : nullptr;
         a.last = p == nb - 1;
         a.sums_out = a.last ? final_out : carry;
-        a.combine = p > 0;
         err = launch_pair_sweep(a, s);
       }
     }
@@ -305,7 +304,7 @@ struct CsrEngine : Engine {
     int most = 1;
     for (size_t k = 0; k + 1 < bfirst.size(); ++k) most = std::max(most, bfirst[k + 1] - bfirst[k]);
     sgrid = std::min(most, cap);
-    nparts = sgrid;
+    nparts = std::min(sgrid, 1024);  // check partial slots (slot_publish)
     TRY_HIP(dalloc(&rblk, rb.size(), sizeof(int32_t)));
     if (nb > 1) TRY_HIP(dalloc(&carry, n, 2 * tsz));
     TRY_HIP(hipMemcpyAsync(rblk, rb.data(), rb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));

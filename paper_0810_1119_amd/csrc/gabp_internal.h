@@ -140,7 +140,7 @@ int residual_blocks(int n, int cap = kMaxSweepBlocks);
 
 // Reduce residual partials and (nparts > 0) the check partials, update the
 // controller, write the host readout slot.
-hipError_t launch_readout(const BlockPartial *part, int nparts, const double *sumpart, int nsum,
+hipError_t launch_readout(BlockPartial *part, int nparts, const double *sumpart, int nsum,
                           const uint32_t *sticky, Ctl *ctl, int sweeps_in_chunk, int seq,
                           HostReadout *host, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl *ctl, double target, double floor, double freeze_tol, bool full,
@@ -183,15 +183,16 @@ struct PairArgs {
   // synchronous sweeps with column ranges: the blocks are virtual rows
   // [vbase, vbase + n) of one range; carry (nullable) holds the earlier
   // ranges' node sums; last: the final range (adds A_ii, b_i, checks; sums_out
-  // is the broadcast array, else the carry); combine: check partials are
-  // added to those of the earlier ranges' launches
+  // is the broadcast array, else the carry)
   int vbase;
   const void *carry;
   bool last;
+  // check partials: nslots slots raised with atomics (slot_publish), so the
+  // launches of one check (colour classes, column ranges) add up
+  int nslots;
   // coloured schedule: one colour class, rows [row0, row1), updated in place
-  // (msg_in == msg_out, sums_in == sums_out); combine: add to the partials
-  // of the check's earlier class launches
-  bool colored, combine;
+  // (msg_in == msg_out, sums_in == sums_out)
+  bool colored;
   int row0, row1;
   bool first;  // first sweep since the messages were set, not sent
 };

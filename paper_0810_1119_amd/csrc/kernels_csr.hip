@@ -534,7 +534,7 @@ hipError_t launch_residual(bool fp32, int grid, int n, const int64_t *rp, const 
 // publish to pinned host memory
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_readout(
-    const BlockPartial *__restrict__ part, int nparts, const double *__restrict__ sumpart, int nsum,
+    BlockPartial *__restrict__ part, int nparts, const double *__restrict__ sumpart, int nsum,
     const uint32_t *__restrict__ sticky, Ctl *__restrict__ ctl, int sweeps_in_chunk, int seq,
     HostReadout *__restrict__ host) {
   __shared__ double sh[5][kBlock / 64];
@@ -546,6 +546,7 @@ __global__ __launch_bounds__(kBlock) void k_readout(
     x = fmax(x, b.xmax);
     dp = fmax(dp, b.dpmax);
     pm = fmax(pm, b.pmax);
+    part[k] = BlockPartial{};  // cleared for atomically raised slots (slot_publish)
   }
   s = wave_sum(s);
   d = wave_max(d);
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void k_readout(
   __threadfence_system();
 }
 
-hipError_t launch_readout(const BlockPartial *part, int nparts, const double *sumpart, int nsum,
+hipError_t launch_readout(BlockPartial *part, int nparts, const double *sumpart, int nsum,
                           const uint32_t *sticky, Ctl *ctl, int sweeps_in_chunk, int seq,
                           HostReadout *host, hipStream_t s) {
   hipLaunchKernelGGL(k_readout, dim3(1), dim3(kBlock), 0, s, part, nparts, sumpart, nsum, sticky,

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
     const T *__restrict__ rhs, const typename Vec4<T>::type *__restrict__ mi,
     typename Vec4<T>::type *__restrict__ mo, const typename Vec2<T>::type *__restrict__ sin,
     const typename Vec2<T>::type *__restrict__ carry, typename Vec2<T>::type *__restrict__ sout,
-    bool last, T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, bool combine,
+    bool last, T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, int nslots,
     uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
   // no FMA contraction: both stored copies of a message, and the node sums
   // rebuilt from stored values, must round exactly like this sweep does
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
   }
   if (zero) f |= FLAG_BREAKDOWN;
   if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(d, ax, (double)dp, (double)pm, part, combine);
+  if (MODE == 1) slot_publish(d, ax, (double)dp, (double)pm, part, nslots);
 }
 
 // Aggregate (S, H) from the slots' incoming messages: used after reset,
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen(
     const T *__restrict__ rhs, const T *__restrict__ Sfix,
     const typename Vec2<T>::type *__restrict__ hin, typename Vec2<T>::type *__restrict__ hout,
     const T *__restrict__ Hin, const T *__restrict__ carry, T *__restrict__ Hout, bool last,
-    T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, bool combine,
+    T alpha, T *__restrict__ xprev, BlockPartial *__restrict__ part, int nslots,
     uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
 #pragma clang fp contract(off)
   using V2 = typename Vec2<T>::type;
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen(
     }
   }
   if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(d, ax, 0.0, 0.0, part, combine);
+  if (MODE == 1) slot_publish(d, ax, 0.0, 0.0, part, nslots);
 }
 
 // restart in the frozen state: h = 0, H = rhs
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_col(
     const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
     const T *__restrict__ acoef, const T *__restrict__ diag, const T *__restrict__ rhs,
     typename Vec4<T>::type *msg, typename Vec2<T>::type *sums, T alpha, T *__restrict__ xprev,
-    BlockPartial *__restrict__ part, bool combine, uint32_t *__restrict__ sticky,
+    BlockPartial *__restrict__ part, int nslots, uint32_t *__restrict__ sticky,
     const Ctl *__restrict__ ctl) {
 #pragma clang fp contract(off)
   using V4 = typename Vec4<T>::type;
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_col(
   }
   if (zero) f |= FLAG_BREAKDOWN;
   if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(d, ax, (double)dp, (double)pm, part, combine);
+  if (MODE == 1) slot_publish(d, ax, (double)dp, (double)pm, part, nslots);
 }
 
 // settled precisions, coloured: h_ji from H_j's broadcast, then H_i, then h_ij
@@ -690,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen_col(
     const int32_t *__restrict__ oprt, const int32_t *__restrict__ ocol,
     const typename Vec2<T>::type *__restrict__ coef, const T *__restrict__ rhs,
     const T *__restrict__ Sfix, typename Vec2<T>::type *hp, T *Hb, T alpha,
-    T *__restrict__ xprev, BlockPartial *__restrict__ part, bool combine,
+    T *__restrict__ xprev, BlockPartial *__restrict__ part, int nslots,
     uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
 #pragma clang fp contract(off)
   using V2 = typename Vec2<T>::type;
@@ -804,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_frozen_col(
     }
   }
   if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(d, ax, 0.0, 0.0, part, combine);
+  if (MODE == 1) slot_publish(d, ax, 0.0, 0.0, part, nslots);
 }
 
 // Marginals of a coloured plan from its current messages, one class (rows
@@ -949,12 +949,12 @@ static void pair_one(const PairArgs &a, hipStream_t s) {
       hipLaunchKernelGGL((k_pair_frozen_col<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.rb, a.b0,
                          a.b1, a.row1, a.first, a.oprt, a.ocol, (const V2 *)a.coef,
                          (const T *)a.rhs, (const T *)a.Sfix, (V2 *)a.msg_out, (T *)a.sums_out,
-                         (T)a.alpha, (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
+                         (T)a.alpha, (T *)a.xprev, a.part, a.nslots, a.sticky, a.ctl);
     else
       hipLaunchKernelGGL((k_pair_col<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.rb, a.b0, a.b1,
                          a.row1, a.first, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag,
                          (const T *)a.rhs, (V4 *)a.msg_out, (V2 *)a.sums_out, (T)a.alpha,
-                         (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
+                         (T *)a.xprev, a.part, a.nslots, a.sticky, a.ctl);
     return;
   }
   if (a.frozen)
@@ -962,13 +962,13 @@ static void pair_one(const PairArgs &a, hipStream_t s) {
                        a.vbase, a.oprt, a.ocol, (const V2 *)a.coef, (const T *)a.rhs,
                        (const T *)a.Sfix, (const V2 *)a.msg_in, (V2 *)a.msg_out,
                        (const T *)a.sums_in, (const T *)a.carry, (T *)a.sums_out, a.last,
-                       (T)a.alpha, (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
+                       (T)a.alpha, (T *)a.xprev, a.part, a.nslots, a.sticky, a.ctl);
   else
     hipLaunchKernelGGL((k_pair_sweep<T, MODE, DAMP>), grid, dim3(kBlock), 0, s, a.rb, a.b0, a.b1,
                        a.vbase, a.oprt, a.ocol, (const T *)a.acoef, (const T *)a.diag,
                        (const T *)a.rhs, (const V4 *)a.msg_in, (V4 *)a.msg_out,
                        (const V2 *)a.sums_in, (const V2 *)a.carry, (V2 *)a.sums_out, a.last,
-                       (T)a.alpha, (T *)a.xprev, a.part, a.combine, a.sticky, a.ctl);
+                       (T)a.alpha, (T *)a.xprev, a.part, a.nslots, a.sticky, a.ctl);
 }
 
 template <typename T>
