@@ -80,6 +80,9 @@ struct CsrEngine : Engine {
   // one buffer (index 0), updated in place by one launch per class
   std::vector<int> cls;
   bool first = true;  // no sweep since the messages were set (reset, restart, import)
+  // synchronous pair plans after a reset: every message is zero and msg[cur]
+  // has not been written (the first sweep reads no slot state)
+  bool zero_msgs = false;
 
   ~CsrEngine() override {
     void *bufs[] = {oprt, ocol, rev, diagpos, acoef, diag, rhs, msg[0], msg[1], sums[0],
@@ -153,7 +156,9 @@ struct CsrEngine : Engine {
         a.coef = coef; a.Sfix = Sfix;
         a.msg_in = hp[cur]; a.msg_out = hp[cur ^ 1]; a.sums_in = Hfz[cur]; a.sums_out = Hfz[cur ^ 1];
       } else {
-        a.msg_in = msg[cur]; a.msg_out = msg[cur ^ 1]; a.sums_in = sums[cur]; a.sums_out = sums[cur ^ 1];
+        a.msg_in = zero_msgs ? nullptr : msg[cur]; a.msg_out = msg[cur ^ 1];
+        a.sums_in = sums[cur]; a.sums_out = sums[cur ^ 1];
+        zero_msgs = false;
       }
       void *final_out = a.sums_out;
       err = hipSuccess;
@@ -208,6 +213,7 @@ struct CsrEngine : Engine {
     first = true;
     if (!pair) return launch_zero_h(fp32, E, msg[cur], s);
     if (frozen) return launch_frozen_restart(fp32, E, n, hp[cur], rhs, Hfz[cur], s);
+    if (zero_msgs) return aggregate(nullptr, sums[cur], s);  // nothing sent yet
     hipError_t err = launch_pair_zero_h(fp32, E, msg[cur], s);
     if (err != hipSuccess) return err;
     // coloured: a row's stored copy of a later class's precision message is
@@ -223,13 +229,15 @@ struct CsrEngine : Engine {
     first = true;
     const int64_t words = E * (int64_t)msg_bytes() / 8;
     hipError_t err;
-    // msg[1] needs no clearing: a synchronous sweep writes every slot of it
-    // before anything reads it, and coloured sweeps work in msg[0]
-    if ((err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
+    // No slot state needs clearing for a synchronous pair plan: its first
+    // sweep takes every message as zero and writes every slot of msg[1].
+    // Coloured sweeps work in msg[0] and the gather layout reads it.
+    zero_msgs = pair && !colored();
+    if (!zero_msgs && (err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
     if ((err = launch_residual(fp32, nsum, n, A.row_ptr, A.col, A.val, b, nullptr, rhs,
                                nullptr, sumpart, s)) != hipSuccess)
       return err;
-    if (pair) return aggregate(msg[0], sums[0], s);
+    if (pair) return aggregate(zero_msgs ? nullptr : msg[0], sums[0], s);
     return hipSuccess;
   }
 
@@ -257,6 +265,11 @@ struct CsrEngine : Engine {
   }
 
   hipError_t freeze(hipStream_t s) override {
+    if (zero_msgs) {  // not reached by a solve (it freezes after sweeps); kept well defined
+      hipError_t err = launch_fill_zero(msg[cur], E * (int64_t)msg_bytes() / 8, s);
+      if (err != hipSuccess) return err;
+      zero_msgs = false;
+    }
     hipError_t err = launch_pair_freeze(fp32, bgrid(), rblk, bfirst.back(), n, oprt, ocol, rev,
                                         colored(), acoef, msg[cur], sums[cur], coef, hp[cur], Sfix,
                                         Hfz[cur], s);
@@ -266,7 +279,10 @@ struct CsrEngine : Engine {
 
   int get_messages(double *P, double *h, hipStream_t s) override {
     if (A.nnz > 0 && (!P || !h)) return GABP_ERR_ARG;
-    if (pair)
+    if (zero_msgs) {
+      TRY_HIP(launch_fill_zero(P, A.nnz, s));
+      TRY_HIP(launch_fill_zero(h, A.nnz, s));
+    } else if (pair)
       TRY_HIP(launch_pair_io(fp32, true, n, nb, A.row_ptr, diagpos, oprt, rev, msg[cur], P, h, s));
     else
       TRY_HIP(launch_get_msgs(fp32, n, A.row_ptr, diagpos, oprt, msg[cur], P, h, s));
@@ -277,6 +293,7 @@ struct CsrEngine : Engine {
   int set_messages(const double *P, const double *h, hipStream_t s) override {
     if (A.nnz > 0 && (!P || !h)) return GABP_ERR_ARG;
     first = true;
+    zero_msgs = false;  // every slot is written
     if (pair) {
       TRY_HIP(launch_pair_io(fp32, false, n, nb, A.row_ptr, diagpos, oprt, rev, msg[cur], (double *)P,
                              (double *)h, s));

@@ -218,7 +218,8 @@ hipError_t launch_pair_col_infer(const PairArgs &a, double *xacc, double *marg, 
 hipError_t launch_pair_sync_in(bool fp32, int64_t E, const int32_t *rev, void *msg, hipStream_t s);
 // (S, H) from the stored in-messages over the row blocks [b0, b1) of rb (one
 // column range, virtual rows from vbase), a row's added in slot order after
-// carry (nullable) as the sweeps add them; last: add A_ii and b_i
+// carry (nullable) as the sweeps add them; last: add A_ii and b_i.  msg ==
+// NULL: every message is zero (S = A_ii, H = b_i)
 hipError_t launch_pair_aggregate(bool fp32, int grid, const int32_t *rb, int b0, int b1,
                                  int vbase, const int32_t *oprt, const void *diag, const void *rhs,
                                  const void *msg, const void *carry, void *sums, bool last,

@@ -90,6 +90,8 @@ __device__ __forceinline__ int seg_row(const int *rp, int nr, int e) {
 // ---------------------------------------------------------------------------
 // Rows are the virtual rows [vbase, vbase + n) of one column range (node
 // v - vbase); carry (nullable) holds the node sums of the ranges before it.
+// mi == NULL: every message of round t is zero (the first sweep after a
+// reset, which then reads no slot state).
 // The last range adds A_ii and b_i, writes the broadcasts and checks the
 // means; an earlier one writes its partial sums to sout (the carry).
 template <typename T, int MODE, bool DAMP>
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_sweep(
         if (e < e1) {
           j[k] = __builtin_nontemporal_load(&ocol[e]);
           a[k] = __builtin_nontemporal_load(&acoef[e]);
-          m[k] = nt_load(&mi[e]);  // (P_ij, h_ij, P_ji, h_ji) of round t
+          if (mi != nullptr) m[k] = nt_load(&mi[e]);  // (P_ij, h_ij, P_ji, h_ji) of round t
         }
       }
 #pragma unroll
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_aggregate(
       S = carry[n0 + t].x;
       H = carry[n0 + t].y;
     }
-    for (int c = e0; c < e1; c += kSegChunk) {
+    for (int c = msg != nullptr ? e0 : e1; c < e1; c += kSegChunk) {  // NULL: no messages yet
       for (int e = c + t; e < e1 && e < c + kSegChunk; e += kBlock) {
         const auto m = msg[e];
         V2 v;
