@@ -42,7 +42,6 @@ Engine::~Engine() {
     for (int k = 0; k < kRing; ++k) {
       (void)hipEventDestroy(ev_beg[k]);
       (void)hipEventDestroy(ev_end[k]);
-      (void)hipEventDestroy(ev_done[k]);
     }
   if (ev_sum) (void)hipEventDestroy(ev_sum);
 }
@@ -60,18 +59,17 @@ int Engine::init_common(hipStream_t s) {
     return st;
   if (nseg > 1 && (st = from_hip(dalloc(&segb2, nseg, sizeof(double))))) return st;
   // kRing chunk readouts and one slot for the residual sums
+  // coherent, so that the host can watch a readout's sequence number arrive
   if ((st = from_hip(hipHostMalloc((void **)&host, (kRing + 1) * sizeof(HostReadout),
-                                   hipHostMallocDefault))) ||
+                                   hipHostMallocCoherent))) ||
       (st = from_hip(hipEventCreateWithFlags(&ev_sum, hipEventDisableTiming))))
     return st;
   for (int k = 0; k < kRing; ++k) {
-    if ((st = from_hip(hipEventCreate(&ev_beg[k]))) || (st = from_hip(hipEventCreate(&ev_end[k]))) ||
-        (st = from_hip(hipEventCreateWithFlags(&ev_done[k], hipEventDisableTiming)))) {
+    if ((st = from_hip(hipEventCreate(&ev_beg[k]))) || (st = from_hip(hipEventCreate(&ev_end[k])))) {
       for (int j = 0; j <= k; ++j) {
         if (ev_beg[j]) (void)hipEventDestroy(ev_beg[j]);
         if (ev_end[j]) (void)hipEventDestroy(ev_end[j]);
-        if (ev_done[j]) (void)hipEventDestroy(ev_done[j]);
-        ev_beg[j] = ev_end[j] = ev_done[j] = nullptr;
+        ev_beg[j] = ev_end[j] = nullptr;
       }
       return st;
     }
@@ -92,6 +90,22 @@ int Engine::wait_sum(HostReadout *outv) {
   TRY_HIP(hipEventSynchronize(ev_sum));
   *outv = host[kRing];
   return GABP_OK;
+}
+
+// Wait until the readout with sequence number `want` has arrived in slot h:
+// watch its sequence number (written last by the readout kernel), asking the
+// stream now and then whether it failed or went idle without delivering it.
+static int wait_readout(const HostReadout *h, int want, hipStream_t s) {
+  for (uint32_t k = 1;; ++k) {
+    if (__atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) == want) return GABP_OK;
+    if ((k & 1023u) == 0) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {  // idle: the readout has run
+        return __atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) == want ? GABP_OK : GABP_ERR_HIP;
+      }
+      if (e != hipErrorNotReady) return from_hip(e);
+    }
+  }
 }
 
 int Engine::read_sum(hipStream_t s, HostReadout *outv, int seg_mode, double bnorm) {
@@ -206,6 +220,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
     int enq = 0, rd = 0, enq_sweeps = 0, last_sweeps = sweeps_done;
     bool stopped = false, want_freeze = false;
     bool chunk_frozen[kRing] = {};
+    int slot_seq[kRing] = {};
     while (true) {
       while (!stopped && enq - rd < kLookahead && enq_sweeps < budget) {
         const int slot = enq % kRing;
@@ -216,20 +231,23 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
           TRY_HIP(p->sweep(k == c - 1 ? 1 : 0, p->ctl, s));
         }
         TRY_HIP(hipEventRecord(p->ev_end[slot], s));
-        TRY_HIP(launch_readout(p->part, p->nparts, nullptr, 0, p->sticky, p->ctl, c, enq,
-                               &p->host[slot], s));
-        TRY_HIP(hipEventRecord(p->ev_done[slot], s));
+        // a pinned buffer may come back from the allocator with an earlier
+        // plan's readouts in it: mark the slot unwritten before the readout
+        __atomic_store_n(&p->host[slot].seq, -1, __ATOMIC_RELEASE);
+        slot_seq[slot] = ++p->seq;
+        TRY_HIP(launch_readout(p->part, p->nparts, nullptr, 0, p->sticky, p->ctl, c,
+                               slot_seq[slot], &p->host[slot], s));
         ++enq;
         enq_sweeps += c;
       }
       if (rd == enq) break;
       const int slot = rd % kRing;
-      TRY_HIP(hipEventSynchronize(p->ev_done[slot]));
+      if ((rc = wait_readout(&p->host[slot], slot_seq[slot], s))) return finish(rc);
       const HostReadout h = p->host[slot];
-      if (h.seq != rd) return finish(GABP_ERR_HIP);
       stats.checks += 1;
       if (h.sweeps > last_sweeps) {  // this chunk ran (not skipped)
         float ms = 0.f;
+        TRY_HIP(hipEventSynchronize(p->ev_end[slot]));  // done: the readout after it has run
         TRY_HIP(hipEventElapsedTime(&ms, p->ev_beg[slot], p->ev_end[slot]));
         stats.sweep_ms += ms;
         if (chunk_frozen[slot]) {

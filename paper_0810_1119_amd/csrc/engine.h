@@ -67,7 +67,9 @@ struct Engine {
   int nseg = 1, segb = 0;
   double *segb2 = nullptr;  // ||b_t||^2 per segment
   HostReadout *host = nullptr;
-  hipEvent_t ev_beg[kRing] = {}, ev_end[kRing] = {}, ev_done[kRing] = {}, ev_sum = nullptr;
+  // per chunk: the sweeps' timing events; the readout itself is watched in
+  // its host slot (sequence number); ev_sum marks the residual sums' readout
+  hipEvent_t ev_beg[kRing] = {}, ev_end[kRing] = {}, ev_sum = nullptr;
   bool events = false;
   int seq = 0;
 

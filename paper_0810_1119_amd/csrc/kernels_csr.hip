@@ -603,7 +603,9 @@ __global__ __launch_bounds__(kBlock) void k_readout(
   host->sweeps = ctl ? ctl->sweeps : 0;
   host->freeze = ctl ? ctl->freeze : 0;
   host->segrel = -1.0;  // set by the per-segment norms when a plan has segments
-  host->seq = seq;
+  // the sequence number last: a host that sees it sees the fields
+  __threadfence_system();
+  __hip_atomic_store(&host->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   __threadfence_system();
 }
 
