@@ -155,7 +155,9 @@ typedef struct {
   double sweep_ms;         /* summed device time of the sweep launches */
   double frozen_sweep_ms;  /* of which in sweeps with settled precisions */
   int64_t edges;           /* directed off-diagonal messages per sweep */
-  double edge_updates_per_s; /* edges * sweeps / seconds */
+  double edge_updates_per_s; /* messages computed per second: edges *
+                                mean_sweeps / seconds (batched: each
+                                instance's edges times its own sweeps) */
   double damping;          /* damping factor in use at the end (batched
                               instances may have raised it) */
   int32_t batch_waves;     /* batched solves: wavefronts per workgroup of the
@@ -170,6 +172,14 @@ typedef struct {
                               plan, colour classes of a coloured plan, 1 else;
                               0 for batched solves (one launch runs the solve) */
   double warm_rel0;        /* ||b - A x0|| / ||b|| of the warm start's means */
+  double mean_sweeps;      /* sweeps per independent system, averaged over them:
+                              a grid stack under the coloured schedule lets each
+                              grid leave the sweeps once it meets its own inner
+                              target, so this is below `sweeps` (the slowest
+                              grid's); batched solves: the instances' mean;
+                              otherwise equal to sweeps */
+  double mean_frozen_sweeps; /* of which with settled precisions (frozen_sweeps
+                              counted the same way) */
 } gabp_stats;
 
 /* Fills o with the defaults: FP32 messages, tol 1e-8, 20000 sweeps, checks

@@ -84,7 +84,8 @@ class Stats(C.Structure):
                 ("edge_updates_per_s", C.c_double), ("damping", C.c_double),
                 ("batch_waves", C.c_int32), ("batch_groups", C.c_int32),
                 ("warm_start", C.c_int32), ("sweep_launches", C.c_int32),
-                ("warm_rel0", C.c_double)]
+                ("warm_rel0", C.c_double), ("mean_sweeps", C.c_double),
+                ("mean_frozen_sweeps", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -34,7 +34,7 @@ void report_hip(hipError_t e, const char *file, int line) {
 }
 
 Engine::~Engine() {
-  void *bufs[] = {part, sumpart, sticky, ctl, xprev, segb2};
+  void *bufs[] = {part, sumpart, sticky, ctl, xprev, segb2, segctl, segact};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (host) (void)hipHostFree(host);
@@ -58,6 +58,12 @@ int Engine::init_common(hipStream_t s) {
       (st = from_hip(dalloc(&xprev, means_slots(), tsz))))
     return st;
   if (nseg > 1 && (st = from_hip(dalloc(&segb2, nseg, sizeof(double))))) return st;
+  // zeroed: an empty list of sweeping segments until a solve fills it
+  if (segctl_wanted && ((st = from_hip(dalloc(&segctl, nseg, sizeof(SegCtl)))) ||
+                        (st = from_hip(dalloc(&segact, nseg + 1, sizeof(int32_t)))) ||
+                        (st = from_hip(launch_fill_zero(segctl, nseg * (int64_t)sizeof(SegCtl) / 8, s))) ||
+                        (st = from_hip(launch_fill_zero4(segact, nseg + 1, s)))))
+    return st;
   // kRing chunk readouts and one slot for the residual sums
   // coherent, so that the host can watch a readout's sequence number arrive
   if ((st = from_hip(hipHostMalloc((void **)&host, (kRing + 1) * sizeof(HostReadout),
@@ -81,7 +87,8 @@ int Engine::init_common(hipStream_t s) {
 int Engine::post_sum(hipStream_t s, int seg_mode, double bnorm) {
   TRY_HIP(launch_readout(nullptr, 0, sumpart, nsum, sticky, ctl, 0, ++seq, &host[kRing], s));
   if (nseg > 1 && seg_mode > 0)
-    TRY_HIP(launch_seg_norms(sumpart, nseg, segb, segb2, seg_mode == 1, bnorm, &host[kRing], s));
+    TRY_HIP(launch_seg_norms(sumpart, nseg, segb, segb2, seg_mode == 1, bnorm, &host[kRing], s,
+                             segctl, segact, o.tol, inner_floor(), o.inner_tol));
   TRY_HIP(hipEventRecord(ev_sum, s));
   return GABP_OK;
 }
@@ -118,6 +125,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   const auto t0 = std::chrono::steady_clock::now();
   if (!p || (p->n > 0 && (!b || !x))) return GABP_ERR_ARG;
   gabp_stats stats{};
+  int64_t seg_sweeps = 0, frozen_seg_sweeps = 0;  // sweeps summed over the segments that ran them
   stats.edges = p->E;
   stats.sweep_launches = p->sweep_launches();
   stats.damping = p->o.damping;
@@ -126,8 +134,11 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   auto finish = [&](int status) {
     stats.status = status;
     stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats.mean_sweeps = p->segctl ? (double)seg_sweeps / p->nseg : (double)stats.sweeps;
+    stats.mean_frozen_sweeps =
+        p->segctl ? (double)frozen_seg_sweeps / p->nseg : (double)stats.frozen_sweeps;
     stats.edge_updates_per_s =
-        stats.seconds > 0 ? (double)stats.edges * stats.sweeps / stats.seconds : 0.0;
+        stats.seconds > 0 ? (double)stats.edges * stats.mean_sweeps / stats.seconds : 0.0;
     if (st) *st = stats;
     return status;
   };
@@ -147,7 +158,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
       freezing ? (o.freeze_tol > 0.0 ? o.freeze_tol : (p->fp32 ? 1e-6 : 1e-14)) : -1.0;
   auto target_for = [&](double rel) {
     if (o.inner_tol > 0) return o.inner_tol;
-    return std::min(0.5, std::max(0.3 * o.tol / rel, p->fp32 ? 1e-7 : 1e-15));
+    return std::min(0.5, std::max(0.3 * o.tol / rel, p->inner_floor()));
   };
   if (freezing) TRY_HIP(p->ensure_frozen_buffers());
   TRY_HIP(launch_fill_zero4(p->sticky, 1, s));
@@ -236,7 +247,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
         __atomic_store_n(&p->host[slot].seq, -1, __ATOMIC_RELEASE);
         slot_seq[slot] = ++p->seq;
         TRY_HIP(launch_readout(p->part, p->nparts, nullptr, 0, p->sticky, p->ctl, c,
-                               slot_seq[slot], &p->host[slot], s));
+                               slot_seq[slot], &p->host[slot], s, p->segctl, p->segact));
         ++enq;
         enq_sweeps += c;
       }
@@ -246,6 +257,8 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
       const HostReadout h = p->host[slot];
       stats.checks += 1;
       if (h.sweeps > last_sweeps) {  // this chunk ran (not skipped)
+        if (chunk_frozen[slot]) frozen_seg_sweeps += h.seg_sweeps - seg_sweeps;
+        seg_sweeps = h.seg_sweeps;
         float ms = 0.f;
         TRY_HIP(hipEventSynchronize(p->ev_end[slot]));  // done: the readout after it has run
         TRY_HIP(hipEventElapsedTime(&ms, p->ev_beg[slot], p->ev_end[slot]));
@@ -273,7 +286,10 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
       if (bn == 0.0) return zero_b();
     }
     // ---- x += H/S, r = b - A x (FP64), ||r|| ----
-    TRY_HIP(p->infer(x, nullptr, nullptr, s));
+    p->infer_skips = true;  // segments that sat the pass out add nothing
+    const hipError_t ie = p->infer(x, nullptr, nullptr, s);
+    p->infer_skips = false;
+    TRY_HIP(ie);
     TRY_HIP(p->residual(b, x, nullptr, s));
     HostReadout rr;
     if ((rc = p->read_sum(s, &rr, 2, bn))) return finish(rc);

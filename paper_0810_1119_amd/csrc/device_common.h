@@ -86,4 +86,45 @@ __device__ __forceinline__ void slot_publish(double d, double x, double dp, doub
   }
 }
 
+// The block's maxima raised into one given entry (a segment's); callable
+// several times per kernel by every thread of the block.
+__device__ __forceinline__ void entry_publish(double d, double x, double dp, double pm,
+                                              BlockPartial *q) {
+  block_max4(d, x, dp, pm);
+  if (threadIdx.x == 0) {
+    atomic_max_nonneg(&q->dmax, d);
+    atomic_max_nonneg(&q->xmax, x);
+    atomic_max_nonneg(&q->dpmax, dp);
+    atomic_max_nonneg(&q->pmax, pm);
+  }
+  __syncthreads();  // block_max4's buffer is free again
+}
+
+// act[0] = number of segments with done == 0, act[1..] = their indices in
+// increasing order.  Every thread of the (kBlock-thread) block must call;
+// thread k % kBlock must be the one that last wrote seg[k].done, or a barrier
+// must separate the writes from the call.
+__device__ __forceinline__ void seg_compact(const SegCtl *seg, int nseg, int32_t *act) {
+  __shared__ int wcount[kBlock / 64];
+  __shared__ int base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int k0 = 0; k0 < nseg; k0 += kBlock) {
+    const int k = k0 + threadIdx.x;
+    const bool on = k < nseg && seg[k].done == 0;
+    const unsigned long long m = __ballot(on);
+    if (lane == 0) wcount[w] = __popcll(m);
+    __syncthreads();
+    int at = base + __popcll(m & ((1ull << lane) - 1ull));
+    for (int v = 0; v < w; ++v) at += wcount[v];
+    if (on) act[1 + at] = k;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int v = 0; v < kBlock / 64; ++v) base += wcount[v];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) act[0] = base;
+}
+
 }  // namespace gabp

@@ -66,6 +66,14 @@ struct Engine {
   // segment's relative residual meets the tolerance
   int nseg = 1, segb = 0;
   double *segb2 = nullptr;  // ||b_t||^2 per segment
+  // per-segment control (engines whose sweeps can skip segments): the check
+  // partials are then one entry per segment (nparts == nseg)
+  SegCtl *segctl = nullptr;
+  int32_t *segact = nullptr;  // [nseg + 1]: count, then the segments still sweeping
+  bool segctl_wanted = false;  // set before init_common
+  // set by the solve around the pass's x update only: x of a segment with
+  // done == 2 stays as it is
+  bool infer_skips = false;
   HostReadout *host = nullptr;
   // per chunk: the sweeps' timing events; the readout itself is watched in
   // its host slot (sequence number); ev_sum marks the residual sums' readout
@@ -80,6 +88,8 @@ struct Engine {
   virtual int64_t means_slots() const { return n; }
   // kernel launches of one sweep
   virtual int sweep_launches() const { return 1; }
+  // lowest automatic inner target: the message precision's resolution
+  double inner_floor() const { return fp32 ? 1e-7 : 1e-15; }
 
   // one sweep (mode 0: sweep, 1: sweep + check of the means); c = controller
   // or NULL.  Synchronous: from buffer cur into cur ^ 1; coloured: every

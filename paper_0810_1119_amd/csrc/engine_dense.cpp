@@ -351,6 +351,8 @@ int batch_solve(BatchEngine *e, const double *b, double *x, double *marg_prec,
         p.rel_residual = d.rel;
         p.residual_per_eq = I.cols > 0 ? d.rnorm / I.cols : 0.0;
         p.edges = I.edges;
+        p.mean_sweeps = d.sweeps;
+        p.mean_frozen_sweeps = d.frozen_sweeps;
         p.damping = d.damping;
         p.batch_waves = e->waves;
         p.batch_groups = e->grid;
@@ -359,6 +361,12 @@ int batch_solve(BatchEngine *e, const double *b, double *x, double *marg_prec,
     }
     sum.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     sum.edge_updates_per_s = sum.seconds > 0 ? work / sum.seconds : 0.0;
+    double swept = 0.0;
+    for (int t = 0; t < e->count; ++t) swept += hs[t].sweeps;
+    sum.mean_sweeps = swept / e->count;
+    double settled = 0.0;
+    for (int t = 0; t < e->count; ++t) settled += hs[t].frozen_sweeps;
+    sum.mean_frozen_sweeps = settled / e->count;
     if (per)
       for (int t = 0; t < e->count; ++t) {
         per[t].seconds = sum.seconds;

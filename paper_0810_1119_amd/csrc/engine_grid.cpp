@@ -225,7 +225,12 @@ struct RbGridEngine : GridEngine {
     a.dconst = A.diag_value; a.aconst = A.off_value;
     a.rhs = rhs; a.msg = frozen ? hh[0] : msg[0]; a.coef = coef; a.Sfix = Sfix;
     a.alpha = o.damping; a.xprev = xprev;
-    a.part = part + (size_t)colour * rgrid; a.sticky = sticky; a.ctl = c;
+    // a stack's grids stop one by one: their check maxima go to one entry per grid
+    a.part = segctl ? part : part + (size_t)colour * rgrid; a.sticky = sticky; a.ctl = c;
+    // segments only inside a solve: sweeps under the controller, and the
+    // pass's x update; trajectory sweeps and marginals cover every grid
+    const bool segs = segctl && ((mode < 2 && c) || (mode == 2 && infer_skips));
+    a.nseg = nseg; a.seg = segs ? segctl : nullptr; a.act = segs ? segact : nullptr;
     return a;
   }
 
@@ -358,6 +363,11 @@ int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **pl
     const int rneed = (rb->Nc + kBlock - 1) / kBlock;
     rb->rgrid = rneed < cap ? rneed : cap;
     e->nparts = 2 * rb->rgrid;  // a check sweep publishes one partial per block and colour
+    if (e->nseg > 1) {
+      // each grid of the stack leaves the sweeps once it meets its own target
+      e->segctl_wanted = true;
+      e->nparts = e->nseg;
+    }
   }
   auto fail = [&](int code) {
     delete e;

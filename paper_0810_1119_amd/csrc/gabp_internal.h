@@ -61,6 +61,24 @@ struct Ctl {
                        // first check of a pass compares against means of
                        // another right-hand side (or zeros), so its change is
                        // no measure of this pass's convergence
+  int32_t pad;
+  int64_t seg_sweeps;  // sweeps summed over the segments that ran them
+};
+
+// Per-segment control of a plan made of independent systems (a stack of
+// grids under the two-colour schedule): each segment applies the stop rule
+// above to its own maxima and leaves the sweeps once it meets its own target;
+// the inner solve ends when no segment is left.  The readout and the
+// segment-norm kernels (one block each) write these, in stream order, and
+// keep the list of segments still sweeping: act[0] = count, act[1..] = their
+// indices in increasing order.
+struct SegCtl {
+  double last_d;       // the segment's d at its previous check (0 before the first)
+  double target;       // the segment's inner target (0: the controller's)
+  int32_t done;        // 0 sweeping; 1 met its target in this pass; 2 sits the
+                       // pass out (its residual already met the tolerance), so
+                       // the pass adds nothing to its x
+  int32_t stall;       // consecutive stagnant checks below the floor
 };
 
 // What the host reads back (pinned, written by the readout kernel).
@@ -77,6 +95,7 @@ struct HostReadout {
   int32_t freeze;      // precision messages settled
   int32_t pad;
   double segrel;       // largest relative residual of a segment (independent systems)
+  int64_t seg_sweeps;  // Ctl::seg_sweeps
 };
 
 template <typename T> struct Vec2;
@@ -140,9 +159,12 @@ int residual_blocks(int n, int cap = kMaxSweepBlocks);
 
 // Reduce residual partials and (nparts > 0) the check partials, update the
 // controller, write the host readout slot.
+// With seg (nparts == nseg): part holds one entry per segment, each segment
+// runs the stop rule on its own entry and act is rebuilt.
 hipError_t launch_readout(BlockPartial *part, int nparts, const double *sumpart, int nsum,
                           const uint32_t *sticky, Ctl *ctl, int sweeps_in_chunk, int seq,
-                          HostReadout *host, hipStream_t s);
+                          HostReadout *host, hipStream_t s, SegCtl *seg = nullptr,
+                          int32_t *act = nullptr);
 hipError_t launch_ctl_reset(Ctl *ctl, double target, double floor, double freeze_tol, bool full,
                             int warmup, hipStream_t s);
 
@@ -285,8 +307,14 @@ hipError_t launch_grid_residual(const GridGeom &g, const GridCoef<double> &k, bo
 // segment): store != 0 keeps the squared norms in segb2 (||b_t||^2);
 // otherwise host->segrel = max_t ||r_t|| / ||b_t|| (||b|| of the whole system
 // where ||b_t|| = 0, given as bnorm).
+// With seg: store != 0 also starts every segment sweeping (a new solve);
+// otherwise a segment whose residual meets tol sits the next pass out and the
+// others get the inner target of their own residual (inner_tol if > 0, else
+// 0.3 tol / rel clamped to [tfloor, 0.5]); act is rebuilt either way.
 hipError_t launch_seg_norms(const double *sumpart, int nseg, int segb, double *segb2, int store,
-                            double bnorm, HostReadout *host, hipStream_t s);
+                            double bnorm, HostReadout *host, hipStream_t s, SegCtl *seg = nullptr,
+                            int32_t *act = nullptr, double tol = 0.0, double tfloor = 0.0,
+                            double inner_tol = 0.0);
 
 // ---- two-colour (red-black) schedule on grids (kernels_grid_rb.hip) ----
 // Node (x, y, z) of a stack (z counted over the whole stack) has colour
@@ -316,9 +344,15 @@ struct RbArgs {
   double alpha;
   void *xprev;         // [2][Nc]
   double *xacc, *marg; // natural order
-  BlockPartial *part;  // this launch's partials (grid entries)
+  BlockPartial *part;  // this launch's partials (grid entries; with seg one per segment)
   uint32_t *sticky;
   const Ctl *ctl;
+  // segments (nseg > 1, the grids of a stack, Nc / nseg slots each): sweeps
+  // cover the segments listed in act only; infer adds nothing to xacc for a
+  // segment with done == 2
+  int nseg;
+  const SegCtl *seg;
+  const int32_t *act;
 };
 hipError_t launch_rb_sweep(const RbArgs &a, hipStream_t s);
 // coefficients, information messages and S of the settled phase from the

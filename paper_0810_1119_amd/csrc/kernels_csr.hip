@@ -536,9 +536,14 @@ hipError_t launch_residual(bool fp32, int grid, int n, const int64_t *rp, const 
 __global__ __launch_bounds__(kBlock) void k_readout(
     BlockPartial *__restrict__ part, int nparts, const double *__restrict__ sumpart, int nsum,
     const uint32_t *__restrict__ sticky, Ctl *__restrict__ ctl, int sweeps_in_chunk, int seq,
-    HostReadout *__restrict__ host) {
-  __shared__ double sh[5][kBlock / 64];
-  double s = 0.0, d = 0.0, x = 0.0, dp = 0.0, pm = 0.0;
+    HostReadout *__restrict__ host, SegCtl *__restrict__ seg, int32_t *__restrict__ act) {
+  __shared__ double sh[6][kBlock / 64];
+  // every thread takes these before thread 0 updates the controller below
+  const bool live = nparts > 0 && ctl != nullptr && ctl->stop == STOP_NONE;
+  const bool segs = live && seg != nullptr;
+  const int swept = segs ? act[0] : 0;  // segments the chunk's sweeps covered
+  const bool warm = live && ctl->warmup > 0;
+  double s = 0.0, d = 0.0, x = 0.0, dp = 0.0, pm = 0.0, e = 0.0;
   for (int k = threadIdx.x; k < nsum; k += kBlock) s += sumpart[k];
   for (int k = threadIdx.x; k < nparts; k += kBlock) {
     const BlockPartial b = part[k];
@@ -547,36 +552,66 @@ __global__ __launch_bounds__(kBlock) void k_readout(
     dp = fmax(dp, b.dpmax);
     pm = fmax(pm, b.pmax);
     part[k] = BlockPartial{};  // cleared for atomically raised slots (slot_publish)
+    if (segs && seg[k].done == 0) {
+      // the controller's stop rule on segment k's own maxima
+      SegCtl &q = seg[k];
+      if (warm) {
+        q.last_d = 0.0;
+        continue;
+      }
+      const double rel = b.dmax / fmax(b.xmax, 1e-300);
+      const double r = q.last_d > 0.0 ? b.dmax / q.last_d : 1.0;
+      const double est = (r < 1.0) ? rel * r / (1.0 - r) : 1e300;
+      q.last_d = b.dmax;
+      e = fmax(e, est);
+      if (rel == 0.0 || est <= (q.target > 0.0 ? q.target : ctl->target)) {
+        q.done = 1;
+      } else {
+        q.stall = (rel < ctl->floor && r > 0.7) ? q.stall + 1 : 0;
+        if (q.stall >= 2) q.done = 1;
+      }
+    }
   }
   s = wave_sum(s);
   d = wave_max(d);
   x = wave_max(x);
   dp = wave_max(dp);
   pm = wave_max(pm);
+  e = wave_max(e);
   const int w = threadIdx.x / 64;
   if ((threadIdx.x & 63) == 0) {
-    sh[0][w] = s; sh[1][w] = d; sh[2][w] = x; sh[3][w] = dp; sh[4][w] = pm;
+    sh[0][w] = s; sh[1][w] = d; sh[2][w] = x; sh[3][w] = dp; sh[4][w] = pm; sh[5][w] = e;
   }
   __syncthreads();
+  if (segs) seg_compact(seg, nparts, act);
   if (threadIdx.x != 0) return;
-  s = sh[0][0]; d = sh[1][0]; x = sh[2][0]; dp = sh[3][0]; pm = sh[4][0];
+  s = sh[0][0]; d = sh[1][0]; x = sh[2][0]; dp = sh[3][0]; pm = sh[4][0]; e = sh[5][0];
   for (int k = 1; k < kBlock / 64; ++k) {
     s += sh[0][k];
     d = fmax(d, sh[1][k]);
     x = fmax(x, sh[2][k]);
     dp = fmax(dp, sh[3][k]);
     pm = fmax(pm, sh[4][k]);
+    e = fmax(e, sh[5][k]);
   }
   const uint32_t flags = sticky ? *sticky : 0u;
-  if (nparts > 0 && ctl->stop == STOP_NONE && ctl->warmup > 0) {
+  if (live) {
     ctl->sweeps += sweeps_in_chunk;
     ctl->checks += 1;
+    ctl->seg_sweeps += (int64_t)sweeps_in_chunk * (segs ? swept : 1);
+  }
+  if (warm) {
     ctl->warmup -= 1;
     ctl->last_d = 0.0;
     if (flags & (FLAG_NONFINITE | FLAG_BREAKDOWN)) ctl->stop = STOP_NONFINITE;
-  } else if (nparts > 0 && ctl->stop == STOP_NONE) {
-    ctl->sweeps += sweeps_in_chunk;
-    ctl->checks += 1;
+  } else if (segs) {
+    ctl->est = e;
+    ctl->last_d = d;
+    ctl->last_x = x;
+    if (ctl->freeze_tol > 0.0 && dp <= ctl->freeze_tol * pm) ctl->freeze = 1;
+    if (flags & (FLAG_NONFINITE | FLAG_BREAKDOWN)) ctl->stop = STOP_NONFINITE;
+    else if (act[0] == 0) ctl->stop = STOP_CONVERGED;
+  } else if (live) {
     const double rel = d / fmax(x, 1e-300);
     const double q = ctl->last_d > 0.0 ? d / ctl->last_d : 1.0;
     const double est = (q < 1.0) ? rel * q / (1.0 - q) : 1e300;
@@ -602,6 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_readout(
   host->stop = ctl ? ctl->stop : 0u;
   host->sweeps = ctl ? ctl->sweeps : 0;
   host->freeze = ctl ? ctl->freeze : 0;
+  host->seg_sweeps = ctl ? ctl->seg_sweeps : 0;
   host->segrel = -1.0;  // set by the per-segment norms when a plan has segments
   // the sequence number last: a host that sees it sees the fields
   __threadfence_system();
@@ -611,9 +647,9 @@ __global__ __launch_bounds__(kBlock) void k_readout(
 
 hipError_t launch_readout(BlockPartial *part, int nparts, const double *sumpart, int nsum,
                           const uint32_t *sticky, Ctl *ctl, int sweeps_in_chunk, int seq,
-                          HostReadout *host, hipStream_t s) {
+                          HostReadout *host, hipStream_t s, SegCtl *seg, int32_t *act) {
   hipLaunchKernelGGL(k_readout, dim3(1), dim3(kBlock), 0, s, part, nparts, sumpart, nsum, sticky,
-                     ctl, sweeps_in_chunk, seq, host);
+                     ctl, sweeps_in_chunk, seq, host, seg, act);
   return hipGetLastError();
 }
 
@@ -630,6 +666,7 @@ __global__ void k_ctl_reset(Ctl *ctl, double target, double floor, double freeze
   ctl->est = 1e300;
   ctl->warmup = warmup;
   if (full) {
+    ctl->seg_sweeps = 0;
     ctl->sweeps = 0;
     ctl->checks = 0;
     ctl->freeze = 0;

@@ -403,9 +403,10 @@ hipError_t launch_grid_residual(const GridGeom &g, const GridCoef<double> &k, bo
 }
 
 // one thread per segment: sums its partials in a fixed order
-__global__ __launch_bounds__(kBlock) void k_seg_norms(const double *__restrict__ sumpart, int nseg,
-                                                      int segb, double *__restrict__ segb2, int store,
-                                                      double bnorm, HostReadout *__restrict__ host) {
+__global__ __launch_bounds__(kBlock) void k_seg_norms(
+    const double *__restrict__ sumpart, int nseg, int segb, double *__restrict__ segb2, int store,
+    double bnorm, HostReadout *__restrict__ host, SegCtl *__restrict__ seg,
+    int32_t *__restrict__ act, double tol, double tfloor, double inner_tol) {
   __shared__ double sh[kBlock / 64];
   double worst = 0.0;
   for (int t = threadIdx.x; t < nseg; t += kBlock) {
@@ -413,12 +414,20 @@ __global__ __launch_bounds__(kBlock) void k_seg_norms(const double *__restrict__
     for (int k = 0; k < segb; ++k) sq += sumpart[(size_t)t * segb + k];
     if (store) {
       segb2[t] = sq;
+      if (seg) seg[t] = SegCtl{0.0, 0.0, 0, 0};
     } else {
       const double bn = segb2[t] > 0.0 ? sqrt(segb2[t]) : bnorm;
       const double rel = bn > 0.0 ? sqrt(sq) / bn : sqrt(sq);
       worst = fmax(worst, rel);  // non-finite sums are caught by the whole-system norm
+      if (seg) {
+        // the next pass: a segment within the tolerance sits it out, the
+        // others aim at the factor their own residual still needs
+        const double tg = inner_tol > 0.0 ? inner_tol : fmin(0.5, fmax(0.3 * tol / rel, tfloor));
+        seg[t] = SegCtl{0.0, tg, rel <= tol ? 2 : 0, 0};
+      }
     }
   }
+  if (seg) seg_compact(seg, nseg, act);
   if (store) return;
   worst = wave_max(worst);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x / 64] = worst;
@@ -431,9 +440,10 @@ __global__ __launch_bounds__(kBlock) void k_seg_norms(const double *__restrict__
 }
 
 hipError_t launch_seg_norms(const double *sumpart, int nseg, int segb, double *segb2, int store,
-                            double bnorm, HostReadout *host, hipStream_t s) {
+                            double bnorm, HostReadout *host, hipStream_t s, SegCtl *seg,
+                            int32_t *act, double tol, double tfloor, double inner_tol) {
   hipLaunchKernelGGL(k_seg_norms, dim3(1), dim3(kBlock), 0, s, sumpart, nseg, segb, segb2, store,
-                     bnorm, host);
+                     bnorm, host, seg, act, tol, tfloor, inner_tol);
   return hipGetLastError();
 }
 

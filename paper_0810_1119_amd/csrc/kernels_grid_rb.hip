@@ -82,24 +82,69 @@ __device__ __forceinline__ int rb_tile_of_block() {
 
 }  // namespace
 
+// Check maxima and flags of one block's slots.
+struct RbAcc {
+  double dmax = 0.0, xmax = 0.0, dpb = 0.0, pmb = 0.0;
+  uint32_t f = 0;
+};
+
+// The slots a block of a colour launch covers.  Without segments: tiles of
+// kBlock slots, strided by the grid.  With segments (the grids of a stack,
+// ncs = Nc / nseg slots each) and MODE < 2: the tiles of the segments listed
+// in act, numbered segment by segment and cut into one contiguous run per
+// block, so a block meets few segments and publishes its check maxima to a
+// segment's entry when it leaves it.  fn(s, acc) updates slot s.
+template <int MODE, bool SEG, typename F>
+__device__ __forceinline__ void rb_cover(int Nc, int nseg, const int32_t *__restrict__ act,
+                                         BlockPartial *__restrict__ part, RbAcc &acc, F fn) {
+  const int tile0 = rb_tile_of_block();
+  if (SEG && MODE != 2) {
+    const int ncs = Nc / nseg;
+    const int tps = (ncs + kBlock - 1) / kBlock;
+    const int64_t total = (int64_t)act[0] * tps;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)tile0 * per;
+    const int64_t v1 = v0 + per < total ? v0 + per : total;
+    int cur = -1;
+    for (int64_t v = v0; v < v1; ++v) {
+      const int a = (int)(v / tps);
+      const int sg = act[1 + a];
+      if (MODE == 1 && sg != cur) {
+        if (cur >= 0) {
+          entry_publish(acc.dmax, acc.xmax, acc.dpb, acc.pmb, part + cur);
+          acc.dmax = acc.xmax = acc.dpb = acc.pmb = 0.0;
+        }
+        cur = sg;
+      }
+      const int off = (int)(v - (int64_t)a * tps) * kBlock + threadIdx.x;
+      if (off < ncs) fn(sg * ncs + off, acc);
+    }
+    if (MODE == 1 && cur >= 0) entry_publish(acc.dmax, acc.xmax, acc.dpb, acc.pmb, part + cur);
+  } else {
+    for (int base = tile0 * kBlock; base < Nc; base += gridDim.x * kBlock) {
+      const int s = base + threadIdx.x;
+      if (s < Nc) fn(s, acc);
+    }
+    if (MODE == 1) block_publish(acc.dmax, acc.xmax, acc.dpb, acc.pmb, part);
+  }
+}
+
 // MODE 0 sweep, 1 sweep + check, 2 means / precisions only (no messages)
-template <typename T, int MODE, bool DAMP, bool VARC>
+template <typename T, int MODE, bool DAMP, bool VARC, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_rb_sweep(
     GridGeom g, int hx, int Nc, int c, GridCoef<T> k, typename Vec2<T>::type *__restrict__ msg,
     const T *__restrict__ rhs, T alpha, T *__restrict__ xprev, double *__restrict__ xacc,
     double *__restrict__ marg, BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky,
-    const Ctl *__restrict__ ctl) {
+    const Ctl *__restrict__ ctl, int nseg, const SegCtl *__restrict__ seg,
+    const int32_t *__restrict__ act) {
   using V = typename Vec2<T>::type;
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
   const V *__restrict__ other = msg + (size_t)(1 - c) * 6 * Nc;
   V *__restrict__ own = msg + (size_t)c * 6 * Nc;
-  double dmax = 0.0, xmax = 0.0, dpb = 0.0, pmb = 0.0;
-  uint32_t f = 0;
-  const int tile0 = rb_tile_of_block();
-  for (int base = tile0 * kBlock; base < Nc; base += gridDim.x * kBlock) {
-    const int s = base + threadIdx.x;
+  RbAcc acc;
+  rb_cover<MODE, SEG>(Nc, nseg, act, part, acc, [&](int s, RbAcc &q) {
     RbNode nd;
-    if (s >= Nc || !rb_node(g, hx, c, s, nd)) continue;
+    if (!rb_node(g, hx, c, s, nd)) return;
     T a[6];
     rb_couplings<T, VARC>(g, k, nd, a);
     T Pin[6], hin[6];
@@ -124,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
       for (int d = 0; d < 6; ++d) {
         if (a[d] == T(0)) continue;
         const T cav = S - Pin[d];
-        if (cav == T(0)) f |= FLAG_BREAKDOWN;
+        if (cav == T(0)) q.f |= FLAG_BREAKDOWN;
         const T inv = T(1) / cav;
         T P = -(a[d] * a[d]) * inv;
         T h = -(a[d] * (H - hin[d])) * inv;
@@ -136,8 +181,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
             h = alpha * o.y + (T(1) - alpha) * h;
           }
           if (MODE == 1) {
-            dpb = fmax(dpb, (double)fabs(P - o.x));
-            pmb = fmax(pmb, (double)fabs(P));
+            q.dpb = fmax(q.dpb, (double)fabs(P - o.x));
+            q.pmb = fmax(q.pmb, (double)fabs(P));
           }
         }
         V out;
@@ -147,43 +192,41 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
       }
     }
     if (MODE >= 1) {
-      if (S == T(0)) f |= FLAG_BREAKDOWN;
+      if (S == T(0)) q.f |= FLAG_BREAKDOWN;
       const T x = H / S;
-      if (!isfinite(x)) f |= FLAG_NONFINITE;
+      if (!isfinite(x)) q.f |= FLAG_NONFINITE;
       T *xp = xprev ? xprev + (size_t)c * Nc + s : nullptr;
       if (MODE == 1) {
-        dmax = fmax(dmax, (double)fabs(x - *xp));
+        q.dmax = fmax(q.dmax, (double)fabs(x - *xp));
         *xp = x;
       } else {
-        if (xacc) xacc[nd.i] += (double)H / (double)S;
+        // a segment sitting the pass out gets no correction
+        if (xacc && !(SEG && seg[s / (Nc / nseg)].done == 2)) xacc[nd.i] += (double)H / (double)S;
         if (marg) marg[nd.i] = (double)S;
         if (xp) *xp = x;  // means of the current messages
       }
-      xmax = fmax(xmax, (double)fabs(x));
+      q.xmax = fmax(q.xmax, (double)fabs(x));
     }
-  }
-  if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(dmax, xmax, dpb, pmb, part);
+  });
+  if (acc.f) atomicOr(sticky, acc.f);
 }
 
 // settled phase: information only, fixed coefficients coef[(6 c + d) Nc + s]
-template <typename T, int MODE, bool DAMP>
+template <typename T, int MODE, bool DAMP, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_rb_frozen(
     GridGeom g, int hx, int Nc, int c, const T *__restrict__ coef, const T *__restrict__ Sfix,
     T *__restrict__ hh, const T *__restrict__ rhs, T alpha, T *__restrict__ xprev,
     double *__restrict__ xacc, double *__restrict__ marg, BlockPartial *__restrict__ part,
-    uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+    uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl, int nseg,
+    const SegCtl *__restrict__ seg, const int32_t *__restrict__ act) {
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
   const T *__restrict__ other = hh + (size_t)(1 - c) * 6 * Nc;
   T *__restrict__ own = hh + (size_t)c * 6 * Nc;
   const T *__restrict__ cf = coef + (size_t)c * 6 * Nc;
-  double dmax = 0.0, xmax = 0.0;
-  uint32_t f = 0;
-  const int tile0 = rb_tile_of_block();
-  for (int base = tile0 * kBlock; base < Nc; base += gridDim.x * kBlock) {
-    const int s = base + threadIdx.x;
+  RbAcc acc;
+  rb_cover<MODE, SEG>(Nc, nseg, act, part, acc, [&](int s, RbAcc &q) {
     RbNode nd;
-    if (s >= Nc || !rb_node(g, hx, c, s, nd)) continue;
+    if (!rb_node(g, hx, c, s, nd)) return;
     // faces with a zero coupling hold zero coefficients and zero
     // informations on both sides since the freeze, so the geometry decides
     T hin[6];
@@ -206,21 +249,20 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
     if (MODE >= 1) {
       const T S = Sfix[(size_t)c * Nc + s];
       const T x = H / S;
-      if (!isfinite(x)) f |= FLAG_NONFINITE;
+      if (!isfinite(x)) q.f |= FLAG_NONFINITE;
       T *xp = xprev ? xprev + (size_t)c * Nc + s : nullptr;
       if (MODE == 1) {
-        dmax = fmax(dmax, (double)fabs(x - *xp));
+        q.dmax = fmax(q.dmax, (double)fabs(x - *xp));
         *xp = x;
       } else {
-        if (xacc) xacc[nd.i] += (double)H / (double)S;
+        if (xacc && !(SEG && seg[s / (Nc / nseg)].done == 2)) xacc[nd.i] += (double)H / (double)S;
         if (marg) marg[nd.i] = (double)S;
         if (xp) *xp = x;
       }
-      xmax = fmax(xmax, (double)fabs(x));
+      q.xmax = fmax(q.xmax, (double)fabs(x));
     }
-  }
-  if (f) atomicOr(sticky, f);
-  if (MODE == 1) block_publish(dmax, xmax, 0.0, 0.0, part);
+  });
+  if (acc.f) atomicOr(sticky, acc.f);
 }
 
 // freeze: coefficients, S and information messages of both colours
@@ -282,30 +324,36 @@ __global__ void k_rb_io(GridGeom g, int hx, int Nc, typename Vec2<T>::type *__re
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename T, int MODE, bool DAMP, bool VARC>
+template <typename T, int MODE, bool DAMP, bool VARC, bool SEG>
 void rb_one(const RbArgs &a, hipStream_t s) {
   using V = typename Vec2<T>::type;
   GridCoef<T> k;
   k.diag = (const T *)a.diag; k.cx = (const T *)a.cx; k.cy = (const T *)a.cy; k.cz = (const T *)a.cz;
   k.dconst = (T)a.dconst; k.aconst = (T)a.aconst;
+  const int nseg = a.seg ? a.nseg : 1;
   if (a.frozen)
-    hipLaunchKernelGGL((k_rb_frozen<T, MODE, DAMP>), dim3(a.grid), dim3(kBlock), 0, s, a.g, a.hx,
-                       a.Nc, a.colour, (const T *)a.coef, (const T *)a.Sfix, (T *)a.msg,
+    hipLaunchKernelGGL((k_rb_frozen<T, MODE, DAMP, SEG>), dim3(a.grid), dim3(kBlock), 0, s, a.g,
+                       a.hx, a.Nc, a.colour, (const T *)a.coef, (const T *)a.Sfix, (T *)a.msg,
                        (const T *)a.rhs, (T)a.alpha, (T *)a.xprev, a.xacc, a.marg, a.part,
-                       a.sticky, a.ctl);
+                       a.sticky, a.ctl, nseg, a.seg, a.act);
   else
-    hipLaunchKernelGGL((k_rb_sweep<T, MODE, DAMP, VARC>), dim3(a.grid), dim3(kBlock), 0, s, a.g,
-                       a.hx, a.Nc, a.colour, k, (V *)a.msg, (const T *)a.rhs, (T)a.alpha,
-                       (T *)a.xprev, a.xacc, a.marg, a.part, a.sticky, a.ctl);
+    hipLaunchKernelGGL((k_rb_sweep<T, MODE, DAMP, VARC, SEG>), dim3(a.grid), dim3(kBlock), 0, s,
+                       a.g, a.hx, a.Nc, a.colour, k, (V *)a.msg, (const T *)a.rhs, (T)a.alpha,
+                       (T *)a.xprev, a.xacc, a.marg, a.part, a.sticky, a.ctl, nseg, a.seg, a.act);
+}
+
+template <typename T, bool VARC, bool SEG>
+void rb_mode_seg(const RbArgs &a, hipStream_t s) {
+  switch (a.mode) {
+    case 0: a.damp ? rb_one<T, 0, true, VARC, SEG>(a, s) : rb_one<T, 0, false, VARC, SEG>(a, s); break;
+    case 1: a.damp ? rb_one<T, 1, true, VARC, SEG>(a, s) : rb_one<T, 1, false, VARC, SEG>(a, s); break;
+    default: rb_one<T, 2, false, VARC, SEG>(a, s); break;
+  }
 }
 
 template <typename T, bool VARC>
 void rb_mode(const RbArgs &a, hipStream_t s) {
-  switch (a.mode) {
-    case 0: a.damp ? rb_one<T, 0, true, VARC>(a, s) : rb_one<T, 0, false, VARC>(a, s); break;
-    case 1: a.damp ? rb_one<T, 1, true, VARC>(a, s) : rb_one<T, 1, false, VARC>(a, s); break;
-    default: rb_one<T, 2, false, VARC>(a, s); break;
-  }
+  a.seg ? rb_mode_seg<T, VARC, true>(a, s) : rb_mode_seg<T, VARC, false>(a, s);
 }
 
 template <typename T, bool VARC>
@@ -320,6 +368,7 @@ void rb_freeze(const RbArgs &a, void *hh, hipStream_t s) {
 
 hipError_t launch_rb_sweep(const RbArgs &a, hipStream_t s) {
   if (a.Nc <= 0) return hipSuccess;
+  if (a.seg && (a.nseg < 1 || a.Nc % a.nseg != 0 || !a.act)) return hipErrorInvalidValue;
   if (a.fp32) a.varc ? rb_mode<float, true>(a, s) : rb_mode<float, false>(a, s);
   else a.varc ? rb_mode<double, true>(a, s) : rb_mode<double, false>(a, s);
   return hipGetLastError();

@@ -242,7 +242,9 @@ int gabp_plan_solve_warm(gabp_plan *p, const gabp_model *m, const double *b, dou
     z.seconds += a.seconds;
     z.sweep_ms += a.sweep_ms;
     z.frozen_sweep_ms += a.frozen_sweep_ms;
-    z.edge_updates_per_s = z.seconds > 0 ? (double)z.edges * z.sweeps / z.seconds : 0.0;
+    z.mean_sweeps += a.mean_sweeps;
+    z.mean_frozen_sweeps += a.mean_frozen_sweeps;
+    z.edge_updates_per_s = z.seconds > 0 ? (double)z.edges * z.mean_sweeps / z.seconds : 0.0;
     z.warm_start = -2;
     z.warm_rel0 = a.warm_rel0;
     a = z;

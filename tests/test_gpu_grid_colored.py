@@ -262,3 +262,106 @@ def test_c5_full_size_colored(G):
     rel = _grid_rel(nx, ny, nz, 1, coef, b, x)
     assert rel <= 1e-8 and st.rel_residual == pytest.approx(rel, rel=1e-6)
     print(f"coloured 256^3: {st.sweeps} sweeps, {st.seconds:.2f} s", flush=True)
+
+
+def _spread_stack(nx, ny, nz, shifts, seed=11):
+    """Variable-coefficient grids whose diagonals carry per-grid shifts, so
+    that the grids of one stack converge at very different rates."""
+    bt = len(shifts)
+    m, coef = W.grid_stack(nx, ny, nz, bt, varcoef=True, seed=seed)
+    n = nx * ny * nz
+    add = np.repeat(np.asarray(shifts, dtype=np.float64), n)
+    coef["diag"] = coef["diag"] + add
+    rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+    val = m.val.copy()
+    on = rows == m.col
+    val[on] += add[rows[on]]
+    return W.CSR(m.n, m.row_ptr, m.col, val), coef
+
+
+def _per_grid_rel(nx, ny, nz, bt, coef, b, x):
+    r, _ = oracle.residual_grid(nx, ny, nz, bt, b, x, coef["diag"], coef["dval"], coef["cx"],
+                                coef["cy"], coef["cz"], coef["off"])
+    n = nx * ny * nz
+    out = []
+    for t in range(bt):
+        sl = slice(t * n, (t + 1) * n)
+        bn = np.linalg.norm(b[sl])
+        out.append(np.linalg.norm(r[sl]) / (bn if bn > 0 else np.linalg.norm(b)))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("fp32,freeze", [(1, 1), (1, 0), (0, 1)])
+def test_colored_stack_grids_stop_one_by_one(G, fp32, freeze):
+    """Each grid of a stack leaves the sweeps once it meets its own target:
+    every grid still meets the tolerance (the oracle's residual, grid by
+    grid), a grid with b_t = 0 keeps x_t = 0 exactly, each grid's x agrees
+    with the grid solved on its own, and the mean sweeps per grid fall well
+    below the slowest grid's."""
+    nx, ny, nz = 12, 11, 10
+    shifts = [0.0, 2.0, 0.02, 0.0, 6.0]
+    bt = len(shifts)
+    m, coef = _spread_stack(nx, ny, nz, shifts)
+    n = nx * ny * nz
+    b = W.normal_b(m.n, 9)
+    b[3 * n:4 * n] = 0.0  # grid 3: zero right-hand side
+    tol = 1e-8 if fp32 else 1e-10
+    rc, st, x = _solve(G, nx, ny, nz, bt, coef, b, tol=tol, msg_fp32=fp32, freeze=freeze,
+                       schedule=G.GABP_SCHEDULE_COLORED)
+    assert rc == G.GABP_OK, G.status_name(rc)
+    rel = _per_grid_rel(nx, ny, nz, bt, coef, b, x)
+    print(f"sweeps {st.sweeps}, mean per grid {st.mean_sweeps:.1f}, per-grid rel {rel}", flush=True)
+    assert rel.max() <= tol and st.rel_residual <= tol
+    assert np.all(x[3 * n:4 * n] == 0.0)
+    assert st.mean_sweeps < 0.8 * st.sweeps
+    assert st.edge_updates_per_s == pytest.approx(st.edges * st.mean_sweeps / st.seconds, rel=1e-9)
+    # each grid alone: the same system, so the same solution within what tol allows
+    for t in (0, 1, 2, 4):
+        sl = slice(t * n, (t + 1) * n)
+        one = {k: (v[sl] if isinstance(v, np.ndarray) else v) for k, v in coef.items()}
+        rc1, st1, x1 = _solve(G, nx, ny, nz, 1, one, b[sl], tol=tol, msg_fp32=fp32, freeze=freeze,
+                              schedule=G.GABP_SCHEDULE_COLORED)
+        assert rc1 == G.GABP_OK and st1.mean_sweeps == st1.sweeps
+        # ||x - x*|| <= ||A^-1|| ||r||, ||A^-1|| <= 1 / shift-free bound: compare loosely
+        np.testing.assert_allclose(x[sl], x1, rtol=0, atol=1e3 * tol * np.abs(x1).max())
+
+
+def test_colored_stack_trajectory_after_solve_covers_every_grid(G):
+    """After a solve in which the grids stopped one by one, trajectory sweeps
+    and marginals still update every grid: FP64 messages and marginals match
+    the oracle's coloured rounds."""
+    nx, ny, nz = 9, 7, 6
+    shifts = [0.0, 4.0, 0.1]
+    bt = len(shifts)
+    m, coef = _spread_stack(nx, ny, nz, shifts, seed=21)
+    A = device_grid(G, nx, ny, nz, bt, coef)
+    rc, plan = G.gabp_plan_create_grid(A, opts(G, msg_fp32=0, tol=1e-10))
+    assert rc == G.GABP_OK
+    b = W.normal_b(m.n, 4)
+    x = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    rc, st = G.gabp_plan_solve(plan, dev(b), x)
+    assert rc == G.GABP_OK and st.mean_sweeps < st.sweeps
+    dmap, col = direction_map(m, nx, ny, nz, bt), checkerboard(nx, ny, nz, bt)
+    b2 = W.uniform_b(m.n, 6)
+    assert G.gabp_plan_reset(plan, dev(b2)) == G.GABP_OK
+    R = oracle.Rounds(m, b2, colors=col)
+    for t in range(1, 4):
+        R.step()
+        assert G.gabp_plan_sweeps(plan, 1) == G.GABP_OK
+        P, h = _msgs(G, plan, A)
+        Po, ho = to_dirs(R.P, dmap), to_dirs(R.information(), dmap)
+        np.testing.assert_allclose(P, Po, rtol=1e-11, atol=1e-13 * np.abs(Po).max(), err_msg=f"P {t}")
+        np.testing.assert_allclose(h, ho, rtol=1e-10, atol=1e-12 * np.abs(ho).max(), err_msg=f"h {t}")
+    mean = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    prec = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    assert G.gabp_plan_marginals(plan, mean, prec) == G.GABP_OK
+    mo, po = R.marginals()
+    np.testing.assert_allclose(host(mean), mo, rtol=1e-10, atol=1e-12 * np.abs(mo).max())
+    np.testing.assert_allclose(host(prec), po, rtol=1e-10)
+    # and a second solve of the same plan starts every grid again
+    x2 = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    rc, st2 = G.gabp_plan_solve(plan, dev(b), x2)
+    assert rc == G.GABP_OK
+    np.testing.assert_array_equal(host(x2), host(x))
+    assert st2.sweeps == st.sweeps and st2.mean_sweeps == st.mean_sweeps
+    G.gabp_plan_destroy(plan)
