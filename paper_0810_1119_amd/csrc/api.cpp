@@ -247,7 +247,8 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
         __atomic_store_n(&p->host[slot].seq, -1, __ATOMIC_RELEASE);
         slot_seq[slot] = ++p->seq;
         TRY_HIP(launch_readout(p->part, p->nparts, nullptr, 0, p->sticky, p->ctl, c,
-                               slot_seq[slot], &p->host[slot], s, p->segctl, p->segact));
+                               slot_seq[slot], &p->host[slot], s, p->segctl, p->segact,
+                               p->nseg, p->seg_grid));
         ++enq;
         enq_sweeps += c;
       }

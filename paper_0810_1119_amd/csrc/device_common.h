@@ -86,16 +86,15 @@ __device__ __forceinline__ void slot_publish(double d, double x, double dp, doub
   }
 }
 
-// The block's maxima raised into one given entry (a segment's); callable
-// several times per kernel by every thread of the block.
-__device__ __forceinline__ void entry_publish(double d, double x, double dp, double pm,
-                                              BlockPartial *q) {
+// The block's maxima stored to one given entry; callable several times per
+// kernel by every thread of the block.
+__device__ __forceinline__ void entry_store(double d, double x, double dp, double pm,
+                                            BlockPartial *q) {
   block_max4(d, x, dp, pm);
   if (threadIdx.x == 0) {
-    atomic_max_nonneg(&q->dmax, d);
-    atomic_max_nonneg(&q->xmax, x);
-    atomic_max_nonneg(&q->dpmax, dp);
-    atomic_max_nonneg(&q->pmax, pm);
+    BlockPartial b;
+    b.dmax = d; b.xmax = x; b.dpmax = dp; b.pmax = pm;
+    *q = b;
   }
   __syncthreads();  // block_max4's buffer is free again
 }

@@ -67,10 +67,11 @@ struct Engine {
   int nseg = 1, segb = 0;
   double *segb2 = nullptr;  // ||b_t||^2 per segment
   // per-segment control (engines whose sweeps can skip segments): the check
-  // partials are then one entry per segment (nparts == nseg)
+  // partials are then laid out per segment (launch_readout)
   SegCtl *segctl = nullptr;
   int32_t *segact = nullptr;  // [nseg + 1]: count, then the segments still sweeping
   bool segctl_wanted = false;  // set before init_common
+  int seg_grid = 0;            // blocks of a segment sweep launch
   // set by the solve around the pass's x update only: x of a segment with
   // done == 2 stays as it is
   bool infer_skips = false;

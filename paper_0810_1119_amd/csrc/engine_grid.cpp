@@ -226,7 +226,7 @@ struct RbGridEngine : GridEngine {
     a.rhs = rhs; a.msg = frozen ? hh[0] : msg[0]; a.coef = coef; a.Sfix = Sfix;
     a.alpha = o.damping; a.xprev = xprev;
     // a stack's grids stop one by one: their check maxima go to one entry per grid
-    a.part = segctl ? part : part + (size_t)colour * rgrid; a.sticky = sticky; a.ctl = c;
+    a.part = part + (size_t)colour * (segctl ? nparts / 2 : rgrid); a.sticky = sticky; a.ctl = c;
     // segments only inside a solve: sweeps under the controller, and the
     // pass's x update; trajectory sweeps and marginals cover every grid
     const bool segs = segctl && ((mode < 2 && c) || (mode == 2 && infer_skips));
@@ -363,10 +363,15 @@ int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **pl
     const int rneed = (rb->Nc + kBlock - 1) / kBlock;
     rb->rgrid = rneed < cap ? rneed : cap;
     e->nparts = 2 * rb->rgrid;  // a check sweep publishes one partial per block and colour
-    if (e->nseg > 1) {
-      // each grid of the stack leaves the sweeps once it meets its own target
+    const int widest = std::min(cap, kMaxSweepBlocks);
+    if (e->nseg > 1 && e->nseg <= widest) {
+      // each grid of the stack leaves the sweeps once it meets its own
+      // target; the segment sweeps need a block per grid at least, and the
+      // readout's per-grid reduction bounds the launch
+      rb->rgrid = std::min(std::max(rb->rgrid, e->nseg), widest);
       e->segctl_wanted = true;
-      e->nparts = e->nseg;
+      e->seg_grid = rb->rgrid;
+      e->nparts = 2 * rb->rgrid;
     }
   }
   auto fail = [&](int code) {

@@ -159,12 +159,14 @@ int residual_blocks(int n, int cap = kMaxSweepBlocks);
 
 // Reduce residual partials and (nparts > 0) the check partials, update the
 // controller, write the host readout slot.
-// With seg (nparts == nseg): part holds one entry per segment, each segment
-// runs the stop rule on its own entry and act is rebuilt.
+// With seg (nseg segments, sweeps of nseg <= seg_grid <= kMaxSweepBlocks
+// blocks): part holds two colour halves of nparts / 2 >= seg_grid entries in
+// the layout of the segment sweeps (kernels_grid_rb.hip); each segment swept
+// runs the stop rule on its own maxima and act is rebuilt.
 hipError_t launch_readout(BlockPartial *part, int nparts, const double *sumpart, int nsum,
                           const uint32_t *sticky, Ctl *ctl, int sweeps_in_chunk, int seq,
                           HostReadout *host, hipStream_t s, SegCtl *seg = nullptr,
-                          int32_t *act = nullptr);
+                          int32_t *act = nullptr, int nseg = 0, int seg_grid = 0);
 hipError_t launch_ctl_reset(Ctl *ctl, double target, double floor, double freeze_tol, bool full,
                             int warmup, hipStream_t s);
 
@@ -347,9 +349,9 @@ struct RbArgs {
   BlockPartial *part;  // this launch's partials (grid entries; with seg one per segment)
   uint32_t *sticky;
   const Ctl *ctl;
-  // segments (nseg > 1, the grids of a stack, Nc / nseg slots each): sweeps
-  // cover the segments listed in act only; infer adds nothing to xacc for a
-  // segment with done == 2
+  // segments (1 < nseg <= grid, the grids of a stack, Nc / nseg slots each):
+  // sweeps cover the segments listed in act only; infer adds nothing to xacc
+  // for a segment with done == 2
   int nseg;
   const SegCtl *seg;
   const int32_t *act;

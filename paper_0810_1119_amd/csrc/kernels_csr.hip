@@ -533,11 +533,37 @@ hipError_t launch_residual(bool fp32, int grid, int n, const int64_t *rp, const 
 // readout: reduce partials in a fixed order, run the inner-solve controller,
 // publish to pinned host memory
 // ---------------------------------------------------------------------------
+// The stop rule of the controller on one segment's own maxima (d, x).
+__device__ __forceinline__ void seg_check(SegCtl &q, double d, double x, const Ctl *ctl,
+                                          double &e) {
+  const double rel = d / fmax(x, 1e-300);
+  const double r = q.last_d > 0.0 ? d / q.last_d : 1.0;
+  const double est = (r < 1.0) ? rel * r / (1.0 - r) : 1e300;
+  q.last_d = d;
+  e = fmax(e, est);
+  if (rel == 0.0 || est <= (q.target > 0.0 ? q.target : ctl->target)) {
+    q.done = 1;
+  } else {
+    q.stall = (rel < ctl->floor && r > 0.7) ? q.stall + 1 : 0;
+    if (q.stall >= 2) q.done = 1;
+  }
+}
+
+__device__ __forceinline__ unsigned long long max_bits(double v) {
+  return (unsigned long long)__double_as_longlong(v > 0.0 ? v : 0.0);
+}
+
+// Without seg: part holds nparts block entries.  With seg: two colour halves
+// of nparts / 2 entries, laid out as the segment sweeps publish them (see
+// rb_cover): with nact <= seg_grid segments swept by seg_grid blocks,
+// B = seg_grid / nact consecutive entries per segment.
 __global__ __launch_bounds__(kBlock) void k_readout(
     BlockPartial *__restrict__ part, int nparts, const double *__restrict__ sumpart, int nsum,
     const uint32_t *__restrict__ sticky, Ctl *__restrict__ ctl, int sweeps_in_chunk, int seq,
-    HostReadout *__restrict__ host, SegCtl *__restrict__ seg, int32_t *__restrict__ act) {
+    HostReadout *__restrict__ host, SegCtl *__restrict__ seg, int32_t *__restrict__ act,
+    int nseg, int seg_grid) {
   __shared__ double sh[6][kBlock / 64];
+  __shared__ unsigned long long accd[kMaxSweepBlocks / 2], accx[kMaxSweepBlocks / 2];
   // every thread takes these before thread 0 updates the controller below
   const bool live = nparts > 0 && ctl != nullptr && ctl->stop == STOP_NONE;
   const bool segs = live && seg != nullptr;
@@ -545,31 +571,49 @@ __global__ __launch_bounds__(kBlock) void k_readout(
   const bool warm = live && ctl->warmup > 0;
   double s = 0.0, d = 0.0, x = 0.0, dp = 0.0, pm = 0.0, e = 0.0;
   for (int k = threadIdx.x; k < nsum; k += kBlock) s += sumpart[k];
-  for (int k = threadIdx.x; k < nparts; k += kBlock) {
-    const BlockPartial b = part[k];
-    d = fmax(d, b.dmax);
-    x = fmax(x, b.xmax);
-    dp = fmax(dp, b.dpmax);
-    pm = fmax(pm, b.pmax);
-    part[k] = BlockPartial{};  // cleared for atomically raised slots (slot_publish)
-    if (segs && seg[k].done == 0) {
-      // the controller's stop rule on segment k's own maxima
-      SegCtl &q = seg[k];
-      if (warm) {
-        q.last_d = 0.0;
-        continue;
-      }
-      const double rel = b.dmax / fmax(b.xmax, 1e-300);
-      const double r = q.last_d > 0.0 ? b.dmax / q.last_d : 1.0;
-      const double est = (r < 1.0) ? rel * r / (1.0 - r) : 1e300;
-      q.last_d = b.dmax;
-      e = fmax(e, est);
-      if (rel == 0.0 || est <= (q.target > 0.0 ? q.target : ctl->target)) {
-        q.done = 1;
+  if (segs && swept > 0) {
+    const int half = nparts / 2;
+    const int B = seg_grid / swept;  // >= 1: swept <= nseg <= seg_grid
+    const int ne = swept * B;
+    if (B > 1) {
+      for (int a = threadIdx.x; a < swept; a += kBlock) accd[a] = accx[a] = 0ull;
+      __syncthreads();
+    }
+    for (int k = threadIdx.x; k < ne; k += kBlock) {
+      const BlockPartial b0 = part[k], b1 = part[half + k];
+      part[k] = BlockPartial{};
+      part[half + k] = BlockPartial{};
+      const double dk = fmax(b0.dmax, b1.dmax), xk = fmax(b0.xmax, b1.xmax);
+      d = fmax(d, dk);
+      x = fmax(x, xk);
+      dp = fmax(dp, fmax(b0.dpmax, b1.dpmax));
+      pm = fmax(pm, fmax(b0.pmax, b1.pmax));
+      if (B > 1) {
+        atomicMax(&accd[k / B], max_bits(dk));
+        atomicMax(&accx[k / B], max_bits(xk));
       } else {
-        q.stall = (rel < ctl->floor && r > 0.7) ? q.stall + 1 : 0;
-        if (q.stall >= 2) q.done = 1;
+        SegCtl &q = seg[act[1 + k]];
+        if (warm) q.last_d = 0.0;
+        else seg_check(q, dk, xk, ctl, e);
       }
+    }
+    if (B > 1) {
+      __syncthreads();
+      for (int a = threadIdx.x; a < swept; a += kBlock) {
+        SegCtl &q = seg[act[1 + a]];
+        if (warm) q.last_d = 0.0;
+        else seg_check(q, __longlong_as_double((long long)accd[a]),
+                       __longlong_as_double((long long)accx[a]), ctl, e);
+      }
+    }
+  } else if (!segs) {
+    for (int k = threadIdx.x; k < nparts; k += kBlock) {
+      const BlockPartial b = part[k];
+      d = fmax(d, b.dmax);
+      x = fmax(x, b.xmax);
+      dp = fmax(dp, b.dpmax);
+      pm = fmax(pm, b.pmax);
+      part[k] = BlockPartial{};  // cleared for atomically raised slots (slot_publish)
     }
   }
   s = wave_sum(s);
@@ -582,8 +626,8 @@ __global__ __launch_bounds__(kBlock) void k_readout(
   if ((threadIdx.x & 63) == 0) {
     sh[0][w] = s; sh[1][w] = d; sh[2][w] = x; sh[3][w] = dp; sh[4][w] = pm; sh[5][w] = e;
   }
-  __syncthreads();
-  if (segs) seg_compact(seg, nparts, act);
+  __syncthreads();  // also orders the segment updates above before the compaction
+  if (segs) seg_compact(seg, nseg, act);
   if (threadIdx.x != 0) return;
   s = sh[0][0]; d = sh[1][0]; x = sh[2][0]; dp = sh[3][0]; pm = sh[4][0]; e = sh[5][0];
   for (int k = 1; k < kBlock / 64; ++k) {
@@ -647,9 +691,12 @@ __global__ __launch_bounds__(kBlock) void k_readout(
 
 hipError_t launch_readout(BlockPartial *part, int nparts, const double *sumpart, int nsum,
                           const uint32_t *sticky, Ctl *ctl, int sweeps_in_chunk, int seq,
-                          HostReadout *host, hipStream_t s, SegCtl *seg, int32_t *act) {
+                          HostReadout *host, hipStream_t s, SegCtl *seg, int32_t *act, int nseg,
+                          int seg_grid) {
+  if (seg && (nseg < 1 || seg_grid < nseg || seg_grid > kMaxSweepBlocks || nparts < 2 * seg_grid))
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_readout, dim3(1), dim3(kBlock), 0, s, part, nparts, sumpart, nsum, sticky,
-                     ctl, sweeps_in_chunk, seq, host, seg, act);
+                     ctl, sweeps_in_chunk, seq, host, seg, act, nseg, seg_grid);
   return hipGetLastError();
 }
 

@@ -88,44 +88,47 @@ struct RbAcc {
   uint32_t f = 0;
 };
 
-// The slots a block of a colour launch covers.  Without segments: tiles of
-// kBlock slots, strided by the grid.  With segments (the grids of a stack,
-// ncs = Nc / nseg slots each) and MODE < 2: the tiles of the segments listed
-// in act, numbered segment by segment and cut into one contiguous run per
-// block, so a block meets few segments and publishes its check maxima to a
-// segment's entry when it leaves it.  fn(s, acc) updates slot s.
+// The slots a block of a colour launch covers.  Without segments (and for
+// MODE 2): tiles of kBlock slots, strided by the grid; a check publishes one
+// entry per block.  With segments (the grids of a stack, ncs = Nc / nseg
+// slots each, nseg <= grid) only the nact segments listed in act are covered:
+// B = grid / nact consecutive blocks share a segment, each taking every B-th
+// of its tiles, so that the B blocks sweep it as one window of B consecutive
+// tiles (few DRAM streams, the neighbouring planes in the XCD's L2) and a
+// block's check maxima belong to one segment: block L publishes entry L
+// without atomics, and the readout maps entry L to segment act[1 + L / B].
+// (A second loop for more segments than blocks, even unused, made the
+// compiled sweep about a third slower; such stacks run without segments.)
+// fn(s, acc) updates slot s.
 template <int MODE, bool SEG, typename F>
 __device__ __forceinline__ void rb_cover(int Nc, int nseg, const int32_t *__restrict__ act,
                                          BlockPartial *__restrict__ part, RbAcc &acc, F fn) {
   const int tile0 = rb_tile_of_block();
+  // one loop for both cases, which differ in its bounds only
+  int first = tile0 * kBlock, stride = gridDim.x * kBlock, end = Nc;
   if (SEG && MODE != 2) {
-    const int ncs = Nc / nseg;
-    const int tps = (ncs + kBlock - 1) / kBlock;
-    const int64_t total = (int64_t)act[0] * tps;
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    const int64_t v0 = (int64_t)tile0 * per;
-    const int64_t v1 = v0 + per < total ? v0 + per : total;
-    int cur = -1;
-    for (int64_t v = v0; v < v1; ++v) {
-      const int a = (int)(v / tps);
-      const int sg = act[1 + a];
-      if (MODE == 1 && sg != cur) {
-        if (cur >= 0) {
-          entry_publish(acc.dmax, acc.xmax, acc.dpb, acc.pmb, part + cur);
-          acc.dmax = acc.xmax = acc.dpb = acc.pmb = 0.0;
-        }
-        cur = sg;
-      }
-      const int off = (int)(v - (int64_t)a * tps) * kBlock + threadIdx.x;
-      if (off < ncs) fn(sg * ncs + off, acc);
+    const int nact = act[0];
+    const int B = nact > 0 ? gridDim.x / nact : 0;  // >= 1: nact <= nseg <= grid
+    const int a = B > 0 ? tile0 / B : 0;
+    if (B == 0 || a >= nact) {
+      end = 0;
+    } else {
+      const int ncs = Nc / nseg;
+      first = act[1 + a] * ncs + (tile0 - a * B) * kBlock;
+      stride = B * kBlock;
+      end = (act[1 + a] + 1) * ncs;
     }
-    if (MODE == 1 && cur >= 0) entry_publish(acc.dmax, acc.xmax, acc.dpb, acc.pmb, part + cur);
-  } else {
-    for (int base = tile0 * kBlock; base < Nc; base += gridDim.x * kBlock) {
-      const int s = base + threadIdx.x;
-      if (s < Nc) fn(s, acc);
+  }
+  for (int base = first; base < end; base += stride) {
+    const int s = base + threadIdx.x;
+    if (s < end) fn(s, acc);
+  }
+  if (MODE == 1) {
+    if (SEG) {
+      if (end > 0) entry_store(acc.dmax, acc.xmax, acc.dpb, acc.pmb, part + tile0);
+    } else {
+      block_publish(acc.dmax, acc.xmax, acc.dpb, acc.pmb, part);
     }
-    if (MODE == 1) block_publish(acc.dmax, acc.xmax, acc.dpb, acc.pmb, part);
   }
 }
 
@@ -368,7 +371,8 @@ void rb_freeze(const RbArgs &a, void *hh, hipStream_t s) {
 
 hipError_t launch_rb_sweep(const RbArgs &a, hipStream_t s) {
   if (a.Nc <= 0) return hipSuccess;
-  if (a.seg && (a.nseg < 1 || a.Nc % a.nseg != 0 || !a.act)) return hipErrorInvalidValue;
+  if (a.seg && (a.nseg < 1 || a.nseg > a.grid || a.Nc % a.nseg != 0 || !a.act))
+    return hipErrorInvalidValue;
   if (a.fp32) a.varc ? rb_mode<float, true>(a, s) : rb_mode<float, false>(a, s);
   else a.varc ? rb_mode<double, true>(a, s) : rb_mode<double, false>(a, s);
   return hipGetLastError();

@@ -365,3 +365,30 @@ def test_colored_stack_trajectory_after_solve_covers_every_grid(G):
     np.testing.assert_array_equal(host(x2), host(x))
     assert st2.sweeps == st.sweeps and st2.mean_sweeps == st.mean_sweeps
     G.gabp_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("grid_blocks", [3, 8, 16])
+def test_colored_stack_launch_width_does_not_change_the_solve(G, grid_blocks):
+    """Launches of a few blocks per grid (in XCD order for multiples of 8):
+    every slot's update and every grid's check maxima are the same, so the
+    solve is bitwise the one of the default launch width (37 blocks here).
+    With fewer blocks than grids the stack runs under one stop rule (every
+    grid sweeps until the last has met its target) and still meets the
+    tolerance grid by grid."""
+    nx, ny, nz = 16, 14, 12
+    shifts = [0.0, 3.0, 0.05, 1.0, 0.0, 8.0, 0.3]
+    bt = len(shifts)
+    m, coef = _spread_stack(nx, ny, nz, shifts, seed=31)
+    b = W.normal_b(m.n, 12)
+    ref = _solve(G, nx, ny, nz, bt, coef, b, tol=1e-8, schedule=G.GABP_SCHEDULE_COLORED)
+    got = _solve(G, nx, ny, nz, bt, coef, b, tol=1e-8, schedule=G.GABP_SCHEDULE_COLORED,
+                 grid_blocks=grid_blocks)
+    for rc, st, x in (ref, got):
+        assert rc == G.GABP_OK, G.status_name(rc)
+        assert _per_grid_rel(nx, ny, nz, bt, coef, b, x).max() <= 1e-8
+    assert ref[1].mean_sweeps < ref[1].sweeps
+    if grid_blocks < bt:
+        assert got[1].mean_sweeps == got[1].sweeps
+    else:
+        np.testing.assert_array_equal(got[2], ref[2])
+        assert got[1].sweeps == ref[1].sweeps and got[1].mean_sweeps == ref[1].mean_sweeps
