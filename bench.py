@@ -109,25 +109,33 @@ def grid_schedule(args, G):
     return (G.GABP_SCHEDULE_SYNC, "k_grid_sweep", "k_grid_frozen", 1)
 
 
-def measured_traffic(kernel_key: str, workload: str):
+def measured_traffic(kernel_key: str, workload: str, check_share: float = 0.5):
     """HBM bytes per launch of a kernel on a workload from the committed PMC
-    summary (profiles/traffic.json): the average over its sweep and check
-    variants, or None when no counters were taken for that workload or the
-    kernel's source changed since."""
+    summary (profiles/traffic.json): its plain (MODE 0) and check (MODE 1)
+    variants weighted by the share of check launches in the timed solves, or
+    None when no counters were taken for that workload or the kernel's source
+    changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    vals = []
+    by_mode = {}
     for name, rec in t["kernels"].items():
         if not name.startswith(kernel_key) or rec.get("workload") != workload:
             continue
         src = os.path.join(ROOT, "paper_0810_1119_amd", "csrc", rec["source"])
         if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
             return None
-        vals.append(rec["bytes_per_launch"])
-    return sum(vals) / len(vals) if vals else None
+        mode = name[len(kernel_key):].split(",")[0].strip()
+        by_mode.setdefault(mode, []).append(rec["bytes_per_launch"])
+    if not by_mode:
+        return None
+    if set(by_mode) == {"0", "1"}:
+        plain, check = (sum(v) / len(v) for v in (by_mode["0"], by_mode["1"]))
+        return (1.0 - check_share) * plain + check_share * check
+    vals = [x for v in by_mode.values() for x in v]
+    return sum(vals) / len(vals)
 
 
 def cpu_baseline(m, b, E, budget_s=12.0):
@@ -164,7 +172,6 @@ def run_c5(args, G, W, torch, dev):
     opts.grid_blocks = args.grid
     sched, kf, kz, per = grid_schedule(args, G)
     opts.schedule = sched
-    c = max(2, opts.check_every + (opts.check_every & 1))
     rc, plan = G.gabp_plan_create_grid(A, opts)
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create_grid: {G.status_name(rc)}")
@@ -176,8 +183,8 @@ def run_c5(args, G, W, torch, dev):
                          "edges, 117,047,296 nonzeros), A_ii = 6.01, A_ij = -1, Dirichlet 0, "
                          "b ~ U[-1,1]; FP32 messages, damping 0.5, FP64 refinement to 1e-8; "
                          f"{'red-black (serial-like)' if per == 2 else 'synchronous'} schedule",
-                bytes_full=grid_bytes_per_sweep(N, E, False, True, c) / per,
-                bytes_frozen=grid_bytes_per_sweep(N, E, True, True, c) / per,
+                bytes_full=lambda c: grid_bytes_per_sweep(N, E, False, True, c) / per,
+                bytes_frozen=lambda c: grid_bytes_per_sweep(N, E, True, True, c) / per,
                 kfull=f"{kf}<float,*,damped,const>", kfrozen=f"{kz}<float,*,damped,const>",
                 tkey_full=f"gabp::{kf}<float, ", tkey_frozen=f"gabp::{kz}<float, ")
 
@@ -207,7 +214,6 @@ def run_c2(args, G, W, torch, dev):
     rc, plan = G.gabp_plan_create(A, opts)
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create: {G.status_name(rc)}")
-    c = max(2, opts.check_every + (opts.check_every & 1))
     pair = args.layout == 0
     ncol = G.gabp_plan_colors(plan)[2] if colored else 1
     # coloured: one launch per colour class, each over its rows and their slots;
@@ -217,8 +223,8 @@ def run_c2(args, G, W, torch, dev):
                          "A_ii=1.1 sum|A_ij|), b~N(0,1); FP32 messages + FP64 refinement to 1e-8; "
                          + (f"coloured schedule ({ncol} colours)" if colored
                             else "synchronous schedule"),
-                bytes_full=(pair_bytes_per_sweep if pair else gather_bytes_per_sweep)(n, E, c) / ncol,
-                bytes_frozen=pair_frozen_bytes_per_sweep(n, E, c) / ncol if pair else None,
+                bytes_full=lambda c: (pair_bytes_per_sweep if pair else gather_bytes_per_sweep)(n, E, c) / ncol,
+                bytes_frozen=(lambda c: pair_frozen_bytes_per_sweep(n, E, c) / ncol) if pair else None,
                 tkey_full=("gabp::k_pair_col<float, " if colored else "gabp::k_pair_sweep<float, ")
                           if pair else None,
                 tkey_frozen=("gabp::k_pair_frozen_col<float, " if colored
@@ -257,7 +263,6 @@ def run_lsq(args, G, W, torch, dev):
     y = torch.from_numpy(y_h).to(dev)
     x = torch.zeros(k, dtype=torch.float64, device=dev)
     n, E = k + m, 2 * S.nnz
-    c = max(2, opts.check_every + (opts.check_every & 1))
     per = 2 if colored else 1
     return dict(plan=plan, b=y, x=x, E=E, n=n, S=S, y_h=y_h, psi=psi, R=R, per_sweep=per,
                 solve=lambda: G.gabp_plan_solve_lsq(plan, y, x),
@@ -266,8 +271,8 @@ def run_lsq(args, G, W, torch, dev):
                          "system of 1,310,720 nodes and 16,777,216 directed edges; FP32 messages "
                          "+ FP64 refinement to 1e-8 (residual of the bipartite system); "
                          + ("coloured schedule (x, then z)" if colored else "synchronous schedule"),
-                bytes_full=pair_bytes_per_sweep(n, E, c) / per,
-                bytes_frozen=pair_frozen_bytes_per_sweep(n, E, c) / per,
+                bytes_full=lambda c: pair_bytes_per_sweep(n, E, c) / per,
+                bytes_frozen=lambda c: pair_frozen_bytes_per_sweep(n, E, c) / per,
                 tkey_full="gabp::k_pair_col<float, " if colored else "gabp::k_pair_sweep<float, ",
                 tkey_frozen=("gabp::k_pair_frozen_col<float, " if colored
                              else "gabp::k_pair_frozen<float, "),
@@ -423,7 +428,6 @@ def bench_c4(args, G, W, torch, dev):
     opts.grid_blocks = args.grid
     sched, kf, kz, per = grid_schedule(args, G)
     opts.schedule = sched
-    c = max(2, opts.check_every + (opts.check_every & 1))
     rc, plan = G.gabp_plan_create_grid(A, opts)
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create_grid: {G.status_name(rc)}")
@@ -462,12 +466,13 @@ def bench_c4(args, G, W, torch, dev):
     grid_sweeps = sum(st.mean_sweeps for st in runs)
     frozen = sum(st.frozen_sweeps for st in runs)
     grid_frozen = sum(st.mean_frozen_sweeps for st in runs)
+    c_eff = sweeps / max(sum(st.checks for st in runs), 1)  # sweeps per check sweep as run
     fz_ms = sum(st.frozen_sweep_ms for st in runs)
     wdt, wruns = res["warm"]
     # launches of the settled phase cover the grids still sweeping: bytes per
     # launch averaged over the launches timed
     launches = max(per * frozen, 1)
-    bps = grid_bytes_per_sweep(N, E, True, False, c) / per * grid_frozen / max(frozen, 1)
+    bps = grid_bytes_per_sweep(N, E, True, False, c_eff) / per * grid_frozen / max(frozen, 1)
     avg_s = fz_ms * 1e-3 / launches
     achieved = bps / avg_s / 1e9
     out = {
@@ -488,6 +493,7 @@ def bench_c4(args, G, W, torch, dev):
             "time_to_1e-8_ms_warm": wdt * 1e3 / args.steps,
             "sweeps_plain": sweeps / args.steps,
             "mean_sweeps_per_grid_plain": grid_sweeps / args.steps,
+            "sweeps_per_check": c_eff,
             "sweeps_warm": sum(st.sweeps for st in wruns) / args.steps,
             "mean_sweeps_per_grid_warm": sum(st.mean_sweeps for st in wruns) / args.steps,
             "warm_start_status": wruns[-1].warm_start,
@@ -499,7 +505,7 @@ def bench_c4(args, G, W, torch, dev):
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(f"gabp::{kz}<float, ", "c4"),
+            "traffic": measured_traffic(f"gabp::{kz}<float, ", "c4", 1.0 / c_eff),
             "kernel": f"{kz}<float,*,undamped> (settled-precision sweep"
                       f"{', one launch per colour' if per == 2 else ''})",
             "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bps,
@@ -609,7 +615,7 @@ def main():
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sweeps = restarts = frozen = 0
+    sweeps = restarts = frozen = checks = 0
     sweep_ms = frozen_ms = 0.0
     worst_rel = 0.0
     lps = 1
@@ -618,6 +624,7 @@ def main():
         if rc != G.GABP_OK:
             raise SystemExit(f"timed solve: {G.status_name(rc)}")
         sweeps += st.sweeps
+        checks += st.checks
         restarts += st.restarts
         frozen += st.frozen_sweeps
         sweep_ms += st.sweep_ms
@@ -632,16 +639,18 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     value = E * sweeps / dt
     full_sweeps, full_ms = sweeps - frozen, sweep_ms - frozen_ms
+    # sweeps per check sweep as run (the interval grows with long passes)
+    c_eff = sweeps / max(checks, 1)
     # dominant kernel = the sweep kind with the larger share of device time,
     # timed with HIP events on the solve's stream
     use_frozen = frozen > 0 and frozen_ms >= full_ms and w["bytes_frozen"]
     if use_frozen:
-        kname, bps, launches, kms = w["kfrozen"], w["bytes_frozen"], frozen, frozen_ms
+        kname, bps, launches, kms = w["kfrozen"], w["bytes_frozen"](c_eff), frozen, frozen_ms
         tkey = w.get("tkey_frozen")
     else:
-        kname, bps, launches, kms = w["kfull"], w["bytes_full"], full_sweeps, full_ms
+        kname, bps, launches, kms = w["kfull"], w["bytes_full"](c_eff), full_sweeps, full_ms
         tkey = w.get("tkey_full")
-    traffic = measured_traffic(tkey, args.workload) if tkey else None
+    traffic = measured_traffic(tkey, args.workload, 1.0 / c_eff) if tkey else None
     # the workload's bytes are per launch at its own count of launches per
     # sweep; the plan reports how many it ran (column ranges, colour classes)
     bps = bps * w.get("per_sweep", 1) / lps
@@ -665,6 +674,7 @@ def main():
             "workload": w["workload"], "n": n, "directed_edges": E, "seed": args.seed,
             "sweeps_per_solve": sweeps / args.steps, "restarts_per_solve": restarts / args.steps,
             "settled_precision_sweeps_per_solve": frozen / args.steps,
+            "sweeps_per_check": c_eff,
             "time_to_1e-8_ms": ms_per_step, "worst_rel_residual": worst_rel,
             "plan_ms": plan_ms,
         },

@@ -73,7 +73,12 @@ typedef struct {
                           stack of grids (batch > 1) every grid's own
                           ||b_t - A_t x_t|| / ||b_t|| must meet it */
   int32_t max_sweeps;  /* budget of synchronous sweeps over all restarts */
-  int32_t check_every; /* sweeps between checks of the marginal means */
+  int32_t check_every; /* sweeps between checks of the marginal means, rounded
+                          up to an even count; 0 (default): 2 in the first 64
+                          sweeps of a refinement pass, 4 up to 256, then 8
+                          (a check sweep costs more than a plain one and adds
+                          a readout).  Batched solves: 0 means 2.  < 0:
+                          GABP_ERR_ARG */
   double damping;      /* alpha in [0,1): P <- alpha P_old + (1-alpha) P_new
                           and the same for the information h = P mu */
   double inner_tol;    /* an inner solve ends when the estimated relative
@@ -147,7 +152,7 @@ typedef struct {
   int32_t sweeps;          /* synchronous sweeps run (all restarts) */
   int32_t frozen_sweeps;   /* of which with settled (fixed) precisions */
   int32_t restarts;        /* refinement restarts taken */
-  int32_t checks;          /* mean checks read back by the host */
+  int32_t checks;          /* check sweeps run (one per chunk of sweeps) */
   double rel_residual;     /* final ||b - A x||_2 / ||b||_2, FP64 (a grid stack:
                               the largest over its grids) */
   double residual_per_eq;  /* ||b - A x||_2 / n (section II-A norm) */
@@ -182,11 +187,10 @@ typedef struct {
                               counted the same way) */
 } gabp_stats;
 
-/* Fills o with the defaults: FP32 messages, tol 1e-8, 20000 sweeps, checks
- * every 2 sweeps, no damping, automatic inner targets (inner_tol 0),
- * 30 restarts, group 0, pair layout, freeze on, batch_waves 0 (autotuned),
- * adapt_damping on.  check_every is rounded up to
- * an even count. */
+/* Fills o with the defaults: FP32 messages, tol 1e-8, 20000 sweeps,
+ * automatic check interval (check_every 0), no damping, automatic inner
+ * targets (inner_tol 0), 30 restarts, group 0, pair layout, freeze on,
+ * batch_waves 0 (autotuned), adapt_damping on. */
 void gabp_default_opts(gabp_opts *o);
 
 /* One-call solve (plan create + solve + destroy).

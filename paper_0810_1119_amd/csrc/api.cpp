@@ -9,8 +9,9 @@
 //           else zero every h (mean) message and keep every P message -- the
 //           precision messages do not depend on the right-hand side
 //           (Algorithm 1 never reads b in the P update).
-// Sweeps are issued in chunks of `check_every` (even) launches, the last one
-// also checking the means; a single-thread readout kernel decides on the
+// Sweeps are issued in chunks of `check_every` (even) sweeps, or of a length
+// that grows with the pass (check_every = 0), the last one also checking the
+// means; a single-thread readout kernel decides on the
 // device whether the inner solve is done and publishes its state to pinned
 // host memory.  The host keeps two chunks in flight, so the GPU never waits
 // for the host; chunks queued after the device decided to stop return at
@@ -71,7 +72,10 @@ int Engine::init_common(hipStream_t s) {
       (st = from_hip(hipEventCreateWithFlags(&ev_sum, hipEventDisableTiming))))
     return st;
   for (int k = 0; k < kRing; ++k) {
-    if ((st = from_hip(hipEventCreate(&ev_beg[k]))) || (st = from_hip(hipEventCreate(&ev_end[k])))) {
+    // timing only: no system-scope fence (cache writeback and invalidation)
+    // when these are recorded between the sweeps and the readout
+    if ((st = from_hip(hipEventCreateWithFlags(&ev_beg[k], hipEventDisableSystemFence))) ||
+        (st = from_hip(hipEventCreateWithFlags(&ev_end[k], hipEventDisableSystemFence)))) {
       for (int j = 0; j <= k; ++j) {
         if (ev_beg[j]) (void)hipEventDestroy(ev_beg[j]);
         if (ev_end[j]) (void)hipEventDestroy(ev_end[j]);
@@ -144,7 +148,16 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
   };
   if (p->n == 0) return finish(GABP_OK);
 
-  const int c = std::max(2, o.check_every + (o.check_every & 1));  // even: buffer parity kept
+  // Sweeps per chunk, even (the double buffers' parity is kept): the option
+  // rounded up, or with 0 a length that grows with the pass's sweeps: a check
+  // sweep costs more than a plain one (the previous means are read and
+  // written, the check maxima published) and each chunk adds a readout, so
+  // long passes check less often; 8 sweeps later than needed is little next
+  // to hundreds, while short passes keep checking every 2.
+  auto chunk_len = [&](int pass_sweeps) {
+    if (o.check_every > 0) return std::max(2, o.check_every + (o.check_every & 1));
+    return pass_sweeps < 64 ? 2 : pass_sweeps < 256 ? 4 : 8;
+  };
   // Inner targets: the first pass runs to the message precision's floor (or
   // to 0.3 tol if that is coarser); later passes only need the remaining
   // factor tol / rel, with the same margin.  inner_tol > 0 fixes the target.
@@ -235,6 +248,7 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
     while (true) {
       while (!stopped && enq - rd < kLookahead && enq_sweeps < budget) {
         const int slot = enq % kRing;
+        const int c = chunk_len(enq_sweeps);
         if (want_freeze && !p->frozen && freezing && p->frozen_ready()) TRY_HIP(p->freeze(s));
         chunk_frozen[slot] = p->frozen;
         for (int k = 0; k < c; ++k) {
@@ -256,8 +270,8 @@ int engine_solve(Engine *p, const double *b, double *x, double *marg_prec, gabp_
       const int slot = rd % kRing;
       if ((rc = wait_readout(&p->host[slot], slot_seq[slot], s))) return finish(rc);
       const HostReadout h = p->host[slot];
-      stats.checks += 1;
       if (h.sweeps > last_sweeps) {  // this chunk ran (not skipped)
+        stats.checks += 1;
         if (chunk_frozen[slot]) frozen_seg_sweeps += h.seg_sweeps - seg_sweeps;
         seg_sweeps = h.seg_sweeps;
         float ms = 0.f;
@@ -337,7 +351,7 @@ void gabp_default_opts(gabp_opts *o) {
   o->msg_fp32 = 1;
   o->tol = 1e-8;
   o->max_sweeps = 20000;
-  o->check_every = 2;
+  o->check_every = 0;
   o->damping = 0.0;
   o->inner_tol = 0.0;
   o->max_restarts = 30;

@@ -40,7 +40,7 @@ int check_csr(const gabp_csr *A) {
 }
 
 int check_opts(const gabp_opts *o) {
-  if (!(o->tol >= 0.0) || o->max_sweeps < 0 || o->check_every < 1 || !(o->damping >= 0.0) ||
+  if (!(o->tol >= 0.0) || o->max_sweeps < 0 || o->check_every < 0 || !(o->damping >= 0.0) ||
       !(o->damping < 1.0) || !(o->inner_tol >= 0.0) || o->max_restarts < 0 ||
       !(o->freeze_tol >= 0.0) || !(o->freeze_tol < 1.0) ||
       (o->group != 0 && !valid_group(o->group)) || o->grid_blocks < 0 ||
