@@ -79,6 +79,7 @@ struct SegCtl {
                        // pass out (its residual already met the tolerance), so
                        // the pass adds nothing to its x
   int32_t stall;       // consecutive stagnant checks below the floor
+  double rel;          // relative residual after the previous pass
 };
 
 // What the host reads back (pinned, written by the readout kernel).
@@ -312,7 +313,9 @@ hipError_t launch_grid_residual(const GridGeom &g, const GridCoef<double> &k, bo
 // With seg: store != 0 also starts every segment sweeping (a new solve);
 // otherwise a segment whose residual meets tol sits the next pass out and the
 // others get the inner target of their own residual (inner_tol if > 0, else
-// 0.3 tol / rel clamped to [tfloor, 0.5]); act is rebuilt either way.
+// 0.3 tol / rel clamped to [tfloor, 0.5]), at most a tenth of the previous
+// target (not below tfloor) where the residual grew over the pass; act is
+// rebuilt either way.
 hipError_t launch_seg_norms(const double *sumpart, int nseg, int segb, double *segb2, int store,
                             double bnorm, HostReadout *host, hipStream_t s, SegCtl *seg = nullptr,
                             int32_t *act = nullptr, double tol = 0.0, double tfloor = 0.0,

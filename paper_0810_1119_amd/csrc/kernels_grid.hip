@@ -414,16 +414,20 @@ __global__ __launch_bounds__(kBlock) void k_seg_norms(
     for (int k = 0; k < segb; ++k) sq += sumpart[(size_t)t * segb + k];
     if (store) {
       segb2[t] = sq;
-      if (seg) seg[t] = SegCtl{0.0, 0.0, 0, 0};
+      if (seg) seg[t] = SegCtl{0.0, 0.0, 0, 0, HUGE_VAL};
     } else {
       const double bn = segb2[t] > 0.0 ? sqrt(segb2[t]) : bnorm;
       const double rel = bn > 0.0 ? sqrt(sq) / bn : sqrt(sq);
       worst = fmax(worst, rel);  // non-finite sums are caught by the whole-system norm
       if (seg) {
         // the next pass: a segment within the tolerance sits it out, the
-        // others aim at the factor their own residual still needs
-        const double tg = inner_tol > 0.0 ? inner_tol : fmin(0.5, fmax(0.3 * tol / rel, tfloor));
-        seg[t] = SegCtl{0.0, tg, rel <= tol ? 2 : 0, 0};
+        // others aim at the factor their own residual still needs.  A pass
+        // stopped on an estimate made right after the restart can leave
+        // high-frequency error that raises the residual; a segment whose
+        // residual grew gets a ten times tighter target than it had.
+        double tg = inner_tol > 0.0 ? inner_tol : fmin(0.5, fmax(0.3 * tol / rel, tfloor));
+        if (rel > seg[t].rel && seg[t].target > 0.0) tg = fmax(tfloor, fmin(tg, 0.1 * seg[t].target));
+        seg[t] = SegCtl{0.0, tg, rel <= tol ? 2 : 0, 0, rel};
       }
     }
   }
