@@ -313,9 +313,9 @@ hipError_t launch_grid_residual(const GridGeom &g, const GridCoef<double> &k, bo
 // With seg: store != 0 also starts every segment sweeping (a new solve);
 // otherwise a segment whose residual meets tol sits the next pass out and the
 // others get the inner target of their own residual (inner_tol if > 0, else
-// 0.3 tol / rel clamped to [tfloor, 0.5]), at most a tenth of the previous
-// target (not below tfloor) where the residual grew over the pass; act is
-// rebuilt either way.
+// 0.3 tol / rel clamped to [tfloor, 0.5], and then at most a tenth of the
+// previous target, not below tfloor, where the residual grew over the pass);
+// act is rebuilt either way.
 hipError_t launch_seg_norms(const double *sumpart, int nseg, int segb, double *segb2, int store,
                             double bnorm, HostReadout *host, hipStream_t s, SegCtl *seg = nullptr,
                             int32_t *act = nullptr, double tol = 0.0, double tfloor = 0.0,

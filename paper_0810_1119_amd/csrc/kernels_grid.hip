@@ -426,7 +426,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_norms(
         // high-frequency error that raises the residual; a segment whose
         // residual grew gets a ten times tighter target than it had.
         double tg = inner_tol > 0.0 ? inner_tol : fmin(0.5, fmax(0.3 * tol / rel, tfloor));
-        if (rel > seg[t].rel && seg[t].target > 0.0) tg = fmax(tfloor, fmin(tg, 0.1 * seg[t].target));
+        if (inner_tol <= 0.0 && rel > seg[t].rel && seg[t].target > 0.0)
+          tg = fmax(tfloor, fmin(tg, 0.1 * seg[t].target));
         seg[t] = SegCtl{0.0, tg, rel <= tol ? 2 : 0, 0, rel};
       }
     }
