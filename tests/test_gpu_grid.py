@@ -263,3 +263,23 @@ def test_stack_every_grid_meets_the_tolerance(G, schedule):
         rels.append(_grid_rel(nx, ny, nz, 1, c1, b[sl], x[sl]))
     assert max(rels) <= 1e-8, rels
     assert st.rel_residual == pytest.approx(max(rels), rel=1e-6)
+
+
+def test_check_interval_grows_with_long_passes(G):
+    """check_every 0 (default) checks every 2 sweeps early in a pass and every
+    8 in long passes; an explicit 2 keeps one check per 2 sweeps.  Both meet
+    the tolerance (the oracle's residual)."""
+    nx, ny, nz = 32, 30, 28
+    m, coef = W.grid_stack(nx, ny, nz, 1, shift=0.001, with_csr=False)
+    b = W.uniform_b(nx * ny * nz, 3)
+    rc, auto, x = _solve(G, nx, ny, nz, 1, coef, b, tol=1e-8)
+    assert rc == G.GABP_OK, G.status_name(rc)
+    assert _grid_rel(nx, ny, nz, 1, coef, b, x) <= 1e-8
+    rc, fixed, x2 = _solve(G, nx, ny, nz, 1, coef, b, tol=1e-8, check_every=2)
+    assert rc == G.GABP_OK
+    assert _grid_rel(nx, ny, nz, 1, coef, b, x2) <= 1e-8
+    print(f"sweeps/checks: automatic {auto.sweeps}/{auto.checks}, fixed {fixed.sweeps}/{fixed.checks}",
+          flush=True)
+    assert auto.sweeps > 400
+    assert fixed.checks * 2 == fixed.sweeps
+    assert auto.checks * 4 < auto.sweeps
