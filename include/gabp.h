@@ -90,8 +90,10 @@ typedef struct {
                           remaining factor 0.3 tol / (current residual) */
   int32_t max_restarts;/* refinement restarts (mean messages zeroed,
                           precision messages kept) */
-  int32_t group;       /* lanes per row in the sweep: 0 = chosen from the
-                          degree profile, else 4, 8, 16, 32 or 64 */
+  int32_t group;       /* GABP_LAYOUT_GATHER only: lanes per row in the sweep,
+                          0 = chosen from the degree profile, else 4, 8, 16,
+                          32 or 64.  The pair layout streams rows in blocks
+                          of up to 256 rows and 1024 slots and ignores it */
   int32_t layout;      /* GABP_LAYOUT_PAIR (default): each edge slot holds both
                           directions of its edge and nodes broadcast their
                           aggregates (Algorithm 2, section V), so the only

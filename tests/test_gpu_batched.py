@@ -139,13 +139,14 @@ def test_bipartite_trajectory(G, fp32, checkpoints, rtol, floor):
         G.gabp_plan_destroy(plan)
 
 
-def test_bipartite_trajectory_damped(G):
+@pytest.mark.parametrize("alpha", [0.3, 0.5, 0.7])
+def test_bipartite_trajectory_damped(G, alpha):
     db = W.detection_sizes([5, 70, 129], [10, 140, 258], seed=12)
     B = _bip(G, db)
-    plan = _plan(G, B, msg_fp32=0, freeze=0, damping=0.5)
+    plan = _plan(G, B, msg_fp32=0, freeze=0, damping=alpha)
     try:
         assert G.gabp_plan_reset(plan, dev(db.y)) == G.GABP_OK
-        rounds = [_bip_oracle_rounds(db, t, damping=0.5) for t in range(db.batch)]
+        rounds = [_bip_oracle_rounds(db, t, damping=alpha) for t in range(db.batch)]
         _trajectory(G, plan, B, rounds, (1, 2, 6), 1e-10, 1e-12, _node_slices(db.K, db.N))
     finally:
         G.gabp_plan_destroy(plan)

@@ -73,7 +73,7 @@ def test_colouring_is_proper_and_deterministic(G, name):
 
 
 @pytest.mark.parametrize("name", sorted(MATRICES))
-@pytest.mark.parametrize("damping", [0.0, 0.5])
+@pytest.mark.parametrize("damping", [0.0, 0.3, 0.5])
 def test_colored_csr_fp64_trajectory_matches_oracle(G, name, damping):
     m = MATRICES[name]()
     b = W.uniform_b(m.n, 5)

@@ -86,7 +86,7 @@ def _msgs(G, plan, A):
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
-@pytest.mark.parametrize("damping", [0.0, 0.5])
+@pytest.mark.parametrize("damping", [0.0, 0.3, 0.5, 0.7])
 def test_grid_fp64_trajectory_matches_oracle(G, case, damping):
     m, A, plan, dmap = _plan(G, case, fp32=False, damping=damping)
     b = W.uniform_b(m.n, 3)

@@ -249,6 +249,74 @@ def test_damping_keeps_fixed_point():
     np.testing.assert_allclose(dmp.x, x, rtol=1e-10, atol=1e-11)
 
 
+def _toy_damped():
+    alpha, msgs, means = None, [], []
+    for t in lines("toy_tree_damped.txt"):
+        if t[0] == "alpha":
+            alpha = num(t[1])
+        elif t[0] == "dmsg":
+            msgs.append((t[1], int(t[2]), int(t[3]), int(t[4]), num(t[5]), num(t[6])))
+        elif t[0] == "dmean":
+            means.append((t[1], int(t[2]), np.array([num(v) for v in t[3:6]])))
+    return alpha, msgs, means
+
+
+@pytest.mark.parametrize("algorithm", [1, 2])
+def test_damped_rounds_on_the_toy_tree(algorithm):
+    """Section VI-D damping as read for GaBP (every message's P and h = P mu
+    mixed as alpha old + (1 - alpha) new): two damped rounds from zero
+    messages and one from the printed t = 1 messages of section VIII-A,
+    against values derived by hand (tests/golden/toy_tree_damped.txt) at
+    alpha = 3/10, where swapping alpha and 1 - alpha or damping mu instead of
+    h gives different numbers."""
+    A, rec = _toy()
+    alpha, msgs, means = _toy_damped()
+    m = W.csr_from_dense(A)
+    for case, rounds in (("zero", 2), ("t1", 1)):
+        R = oracle.Rounds(m, rec["b"], algorithm=algorithm, damping=alpha)
+        if case == "t1":
+            for kind, i, j, *vals in rec["msg"]:
+                e = _slot(m, int(i), int(j))
+                (R.P if kind == "P" else R.Mu)[e] = num(vals[1])
+        for t in range(1, rounds + 1):
+            R.step()
+            for c, tt, i, j, P, h in msgs:
+                if c != case or tt != t:
+                    continue
+                e = _slot(m, i, j)
+                assert R.P[e] == pytest.approx(P, rel=1e-14, abs=1e-15), (case, t, i, j)
+                assert R.information()[e] == pytest.approx(h, rel=1e-14, abs=1e-14), (case, t, i, j)
+            mean, _ = R.marginals()
+            exp = [v for c, tt, v in means if c == case and tt == t]
+            assert len(exp) == 1
+            np.testing.assert_allclose(mean, exp[0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("tol,rounds", [(10.0, 1), (5.0, 2), (1.0, 3), (1e-300, 3)])
+def test_stop_on_the_change_of_the_means(tol, rounds):
+    """The marginal-mean criterion (stop at the first round whose largest
+    change of a tentative mean is below tol) on the printed table of tentative
+    means of section VIII-A: changes 7, 2 and 0 at t = 1, 2, 3 (the tree is
+    exact after its diameter, 2 rounds, so round 3 repeats round 2)."""
+    A, rec = _toy()
+    r = oracle.solve(W.csr_from_dense(A), rec["b"], stop=oracle.STOP_MEANS, tol=tol,
+                     max_rounds=10)
+    assert r.status == oracle.OK and r.rounds == rounds
+    printed = np.array([[num(v) for v in row[1:]] for row in rec["mean"]])  # node x t
+    np.testing.assert_allclose(r.x, printed[:, rounds], rtol=1e-15, atol=1e-15)
+
+
+@pytest.mark.parametrize("tol,rounds", [(10.0, 1), (13.0, 1), (5.0, 3)])
+def test_stop_on_the_change_of_the_messages(tol, rounds):
+    """The criterion of section VIII (largest absolute change of any message,
+    precision or mean) on the printed message table of section VIII-A: changes
+    9, 12 and 0 at t = 1, 2, 3."""
+    A, rec = _toy()
+    r = oracle.solve(W.csr_from_dense(A), rec["b"], stop=oracle.STOP_MESSAGES, tol=tol,
+                     max_rounds=10)
+    assert r.status == oracle.OK and r.rounds == rounds
+
+
 def test_residual_definition():
     """Section II-A residual: r = b - A x (norm as the paper's Frobenius norm)."""
     m = W.sdd_random(500, 1)
