@@ -74,6 +74,11 @@ def _load():
         lib.orc_max_threads.restype = C.c_int
         lib.orc_residual_grid.argtypes = [i32, i32, i32, i32, vp, f64, vp, vp, vp, f64, vp, vp, vp]
         lib.orc_residual_grid.restype = f64
+        lib.orc_aitken.argtypes = [i64, vp, vp, vp, vp]
+        lib.orc_solve_aitken.argtypes = [C.POINTER(_Csr), vp, i32, f64, i32, f64, i32, vp,
+                                         C.POINTER(i32)]
+        lib.orc_solve_steffensen.argtypes = [C.POINTER(_Csr), vp, i32, i32, f64, i32, f64, i32,
+                                             vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(f64)]
         _lib = lib
     return _lib
 
@@ -218,6 +223,42 @@ def refine_solve(m, b, tol=1e-8, inner_tol=1e-5, inner_max=100000, max_restarts=
                                   damping, nthreads, _p(x), _p(P), _p(Mu), C.byref(rounds),
                                   C.byref(restarts), C.byref(rel))
     return st, x, int(rounds.value), int(restarts.value), float(rel.value)
+
+
+def aitken(x0, x1, x2):
+    """Section IV-A, Aitken's method per component (see orc_aitken): y from
+    three consecutive members of a sequence; a zero second difference keeps x2."""
+    x0, x1, x2 = (np.ascontiguousarray(a, dtype=np.float64) for a in (x0, x1, x2))
+    if not (x0.shape == x1.shape == x2.shape):
+        raise ValueError("shape mismatch")
+    y = np.empty_like(x0)
+    _load().orc_aitken(x0.size, _p(x0), _p(x1), _p(x2), _p(y))
+    return y
+
+
+def solve_aitken(m, b, stride=2, tol=1e-10, max_rounds=100000, damping=0.0, nthreads=0):
+    """Parallel GaBP + Aitken (orc_solve_aitken): returns (status, y, rounds)."""
+    M = Matrix(m)
+    b = _f64(b, M.n)
+    y = np.empty(M.n)
+    rounds = C.c_int32(0)
+    st = _load().orc_solve_aitken(C.byref(M.c), _p(b), stride, tol, max_rounds, damping,
+                                  nthreads, _p(y), C.byref(rounds))
+    return st, y, int(rounds.value)
+
+
+def solve_steffensen(m, b, stride=2, cycle=100, tol=1e-10, max_cycles=1000, damping=0.0,
+                     nthreads=0):
+    """GaBP + Steffensen (orc_solve_steffensen): returns
+    (status, x, rounds, cycles, rel_residual)."""
+    M = Matrix(m)
+    b = _f64(b, M.n)
+    x = np.empty(M.n)
+    rounds, cycles, rel = C.c_int32(0), C.c_int32(0), C.c_double(0)
+    st = _load().orc_solve_steffensen(C.byref(M.c), _p(b), stride, cycle, tol, max_cycles,
+                                      damping, nthreads, _p(x), C.byref(rounds),
+                                      C.byref(cycles), C.byref(rel))
+    return st, x, int(rounds.value), int(cycles.value), float(rel.value)
 
 
 def residual(m, b, x):

@@ -478,3 +478,137 @@ double orc_residual_grid(int32_t nx, int32_t ny, int32_t nz, int32_t batch, cons
         }
   return sqrt(ss);
 }
+
+/* Section IV-A, Aitken's method, per node on its own history: for three
+ * consecutive members x0 = x_n, x1 = x_{n+1}, x2 = x_{n+2} of a sequence
+ *   y_n = x_n - (x_{n+1} - x_n)^2 / (x_{n+2} - 2 x_{n+1} + x_n).
+ * The paper leaves a vanishing second difference open; then y = x_{n+2} (the
+ * sequence is already at rest or moves linearly, and nothing is extrapolated). */
+void orc_aitken(int64_t n, const double *x0, const double *x1, const double *x2, double *y) {
+  for (int64_t i = 0; i < n; ++i) {
+    const double d1 = x1[i] - x0[i];
+    const double d2 = x2[i] - 2.0 * x1[i] + x0[i];
+    y[i] = (d2 != 0.0) ? x0[i] - d1 * d1 / d2 : x2[i];
+  }
+}
+
+/* Parallel GaBP + Aitken (section IV-A): synchronous Algorithm 2 rounds from
+ * zero messages, unchanged by the extrapolation; the tentative means are
+ * sampled every `stride` rounds (x_0 = the means of the zero messages,
+ * b_i / A_ii) and, at sample k >= 2, every node extrapolates its own last
+ * three samples x_{(k-2)s}, x_{(k-1)s}, x_{ks} to y; at sample 1, y = x_s.
+ * The run stops at the first sample whose y has ||b - A y||_2 / ||b||_2 <= tol.
+ * y receives that extrapolated vector, *rounds the rounds run.  A stride of 2
+ * pairs rounds of equal parity, which matters where the iteration has
+ * eigenvalues of both signs (bipartite graphs under the parallel schedule). */
+int orc_solve_aitken(const orc_csr *A, const double *b, int32_t stride, double tol,
+                     int32_t max_rounds, double damping, int32_t nthreads, double *y,
+                     int32_t *rounds) {
+  const int32_t n = A->n;
+  const int64_t nnz = A->row_ptr[n];
+  *rounds = 0;
+  if (stride < 1 || max_rounds < 0 || !(damping >= 0.0 && damping < 1.0)) return ORC_ERR_ARG;
+  const size_t nb = sizeof(double) * (n ? n : 1), eb = sizeof(double) * (nnz ? nnz : 1);
+  int64_t *rev = (int64_t *)malloc(sizeof(int64_t) * (nnz ? nnz : 1));
+  double *diag = (double *)malloc(nb), *prec = (double *)malloc(nb);
+  double *P = (double *)calloc(nnz ? nnz : 1, sizeof(double));
+  double *M = (double *)calloc(nnz ? nnz : 1, sizeof(double));
+  double *P2 = (double *)malloc(eb), *M2 = (double *)malloc(eb);
+  double *h0 = (double *)malloc(nb), *h1 = (double *)malloc(nb), *h2 = (double *)malloc(nb);
+  int status = orc_build_reverse(A, rev, diag);
+  if (status != ORC_OK) goto done;
+  double bn = 0.0;
+  for (int32_t i = 0; i < n; ++i) bn += b[i] * b[i];
+  bn = sqrt(bn);
+  if (bn == 0.0) bn = 1.0;
+  orc_marginals(A, b, rev, diag, P, M, h2, prec, nthreads);  /* x_0 */
+  status = ORC_NOT_CONVERGED;
+  int32_t k = 0;
+  for (int32_t t = 1; t <= max_rounds; ++t) {
+    const int64_t zeros = orc_alg2_round(A, b, rev, diag, P, M, P2, M2, damping, nthreads);
+    memcpy(P, P2, eb);
+    memcpy(M, M2, eb);
+    *rounds = t;
+    if (zeros) { status = ORC_ERR_BREAKDOWN; break; }
+    if (t % stride) continue;
+    ++k;
+    double *tmp = h0; h0 = h1; h1 = h2; h2 = tmp;  /* h0 <- x_{(k-2)s}, h1 <- x_{(k-1)s} */
+    orc_marginals(A, b, rev, diag, P, M, h2, prec, nthreads);
+    int zero_marg = 0;
+    for (int32_t i = 0; i < n; ++i)
+      if (prec[i] == 0.0) zero_marg = 1;
+    if (zero_marg) { status = ORC_ERR_BREAKDOWN; break; }
+    if (k >= 2) orc_aitken(n, h0, h1, h2, y);
+    else memcpy(y, h2, nb);
+    if (!all_finite(y, n) || !all_finite(h2, n)) { status = ORC_ERR_DIVERGED; break; }
+    if (orc_residual(A, b, y, NULL) / bn <= tol) { status = ORC_OK; break; }
+  }
+done:
+  free(rev); free(diag); free(prec); free(P); free(M); free(P2); free(M2);
+  free(h0); free(h1); free(h2);
+  return status;
+}
+
+/* GaBP + Steffensen (section IV-A): a cycle runs `cycle` synchronous rounds,
+ * Aitken extrapolates every node's tentative means from rounds cycle - 2s,
+ * cycle - s and cycle (s = stride), and the extrapolated value replaces the
+ * iterate before GaBP runs again.  The paper does not say how a vector of
+ * means is put back into message form; here GaBP "runs again from y" on the
+ * correction system: x <- x + y_d (x = 0 before the first cycle, y_d the
+ * extrapolated correction), then the next cycle solves A d = b - A x starting
+ * from zero information messages P mu while keeping every precision message
+ * (they do not depend on the right-hand side: Algorithm 1 never reads b in the
+ * P update).  Stops after the first cycle with ||b - A x||_2 / ||b||_2 <= tol.
+ * Outputs x, the rounds and cycles run and the final relative residual. */
+int orc_solve_steffensen(const orc_csr *A, const double *b, int32_t stride, int32_t cycle,
+                         double tol, int32_t max_cycles, double damping, int32_t nthreads,
+                         double *x, int32_t *rounds, int32_t *cycles, double *rel) {
+  const int32_t n = A->n;
+  const int64_t nnz = A->row_ptr[n];
+  *rounds = 0; *cycles = 0; *rel = NAN;
+  if (stride < 1 || cycle < 2 * stride || max_cycles < 1 || !(damping >= 0.0 && damping < 1.0))
+    return ORC_ERR_ARG;
+  const size_t nb = sizeof(double) * (n ? n : 1), eb = sizeof(double) * (nnz ? nnz : 1);
+  int64_t *rev = (int64_t *)malloc(sizeof(int64_t) * (nnz ? nnz : 1));
+  double *diag = (double *)malloc(nb), *prec = (double *)malloc(nb);
+  double *P = (double *)calloc(nnz ? nnz : 1, sizeof(double));
+  double *M = (double *)calloc(nnz ? nnz : 1, sizeof(double));
+  double *P2 = (double *)malloc(eb), *M2 = (double *)malloc(eb);
+  double *r = (double *)malloc(nb), *yd = (double *)malloc(nb);
+  double *d0 = (double *)malloc(nb), *d1 = (double *)malloc(nb), *d2 = (double *)malloc(nb);
+  int status = orc_build_reverse(A, rev, diag);
+  if (status != ORC_OK) goto done;
+  double bn = 0.0;
+  for (int32_t i = 0; i < n; ++i) { bn += b[i] * b[i]; x[i] = 0.0; r[i] = b[i]; }
+  bn = sqrt(bn);
+  if (bn == 0.0) { *rel = 0.0; status = ORC_OK; goto done; }
+  status = ORC_NOT_CONVERGED;
+  for (int32_t c = 0; c < max_cycles; ++c) {
+    for (int64_t e = 0; e < nnz; ++e) M[e] = 0.0;  /* information restarts, precisions kept */
+    if (cycle == 2 * stride)  /* the first sample is the cycle's starting state */
+      orc_marginals(A, r, rev, diag, P, M, d0, prec, nthreads);
+    for (int32_t t = 1; t <= cycle; ++t) {
+      const int64_t zeros = orc_alg2_round(A, r, rev, diag, P, M, P2, M2, damping, nthreads);
+      memcpy(P, P2, eb);
+      memcpy(M, M2, eb);
+      ++*rounds;
+      if (zeros) { status = ORC_ERR_BREAKDOWN; goto done; }
+      double *dst = (t == cycle - 2 * stride) ? d0 : (t == cycle - stride) ? d1
+                  : (t == cycle) ? d2 : NULL;
+      if (!dst) continue;
+      orc_marginals(A, r, rev, diag, P, M, dst, prec, nthreads);
+      for (int32_t i = 0; i < n; ++i)
+        if (prec[i] == 0.0) { status = ORC_ERR_BREAKDOWN; goto done; }
+    }
+    orc_aitken(n, d0, d1, d2, yd);
+    for (int32_t i = 0; i < n; ++i) x[i] += yd[i];
+    ++*cycles;
+    if (!all_finite(x, n)) { status = ORC_ERR_DIVERGED; break; }
+    *rel = orc_residual(A, b, x, r) / bn;
+    if (*rel <= tol) { status = ORC_OK; break; }
+  }
+done:
+  free(rev); free(diag); free(prec); free(P); free(M); free(P2); free(M2);
+  free(r); free(yd); free(d0); free(d1); free(d2);
+  return status;
+}
