@@ -213,6 +213,21 @@ int gabp_solve(const gabp_csr *A, const double *b, double *x, double *marg_prec,
 int gabp_residual(const gabp_csr *A, const double *b, const double *x, double *r,
                   double *rel_norm, hipStream_t stream);
 
+/* gabp_residual without any allocation, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as gabp_residual (the same
+ * kernels in the same order: bitwise the same results).  Its scratch (32 KiB:
+ * validation flags, at most 2048 partial sums, two readout records) is one
+ * static device array per GPU, looked up on the first call with that device
+ * current and held until the process ends; no call allocates device or pinned
+ * memory.  Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (other streams or threads) race and must be serialised by the
+ * caller.  The stream must belong to the current device.  Any n is accepted
+ * (the residual uses at most 2048 workgroups); a partial count beyond the
+ * array would be GABP_ERR_UNSUPPORTED. */
+int gabp_residual_noalloc(const gabp_csr *A, const double *b, const double *x, double *r,
+                          double *rel_norm, hipStream_t stream);
+
 /* ---- Plans: reuse the validated graph, reverse-edge index and buffers. ---- */
 typedef struct gabp_plan gabp_plan;
 

@@ -12,7 +12,8 @@ from ._abi import (  # noqa: F401
     GABP_ERR_BREAKDOWN, GABP_ERR_DIVERGED, GABP_ERR_HIP, GABP_ERR_NOMEM, GABP_ERR_UNSUPPORTED,
     GABP_LAYOUT_PAIR, GABP_LAYOUT_GATHER, GABP_SCHEDULE_SYNC, GABP_SCHEDULE_COLORED,
     LIB_PATH, DeviceCSR, GabpError, Opts, Stats, lib, status_name,
-    gabp_default_opts, gabp_solve, gabp_residual, gabp_plan_create, gabp_plan_destroy,
+    gabp_default_opts, gabp_solve, gabp_residual, gabp_residual_noalloc, gabp_plan_create,
+    gabp_plan_destroy,
     gabp_plan_solve, gabp_plan_reset, gabp_plan_sweeps, gabp_plan_marginals,
     gabp_plan_get_messages, gabp_plan_set_messages, gabp_version,
     DeviceGrid, gabp_plan_create_grid, gabp_solve_grid, gabp_residual_grid,

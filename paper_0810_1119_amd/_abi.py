@@ -96,6 +96,8 @@ _sig = {
     "gabp_default_opts": (None, [C.POINTER(Opts)]),
     "gabp_solve": (C.c_int, [C.POINTER(_Csr), _vp, _vp, _vp, C.POINTER(Opts), C.POINTER(Stats), _vp]),
     "gabp_residual": (C.c_int, [C.POINTER(_Csr), _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
+    "gabp_residual_noalloc": (C.c_int, [C.POINTER(_Csr), _vp, _vp, _vp, C.POINTER(C.c_double),
+                                        _vp]),
     "gabp_plan_create": (C.c_int, [C.POINTER(_Csr), C.POINTER(Opts), C.POINTER(_vp), _vp]),
     "gabp_plan_colors": (C.c_int, [_vp, _vp, C.POINTER(C.c_int32), _vp]),
     "gabp_plan_create_lsq": (C.c_int, [C.POINTER(_Rect), C.c_double, C.POINTER(Opts),
@@ -253,6 +255,16 @@ def gabp_residual(A: DeviceCSR, b, x, r=None, stream=None):
     rel = C.c_double(0.0)
     a = A.c()
     rc = lib.gabp_residual(C.byref(a), _ptr(b), _ptr(x), _ptr(r), C.byref(rel), _stream(stream))
+    return rc, rel.value
+
+
+def gabp_residual_noalloc(A: DeviceCSR, b, x, r=None, stream=None):
+    """gabp_residual through the allocation-free entry point: (status, rel)."""
+    _check_f64(b, A.n, "b"); _check_f64(x, A.n, "x"); _check_f64(r, A.n, "r")
+    rel = C.c_double(0.0)
+    a = A.c()
+    rc = lib.gabp_residual_noalloc(C.byref(a), _ptr(b), _ptr(x), _ptr(r), C.byref(rel),
+                                   _stream(stream))
     return rc, rel.value
 
 

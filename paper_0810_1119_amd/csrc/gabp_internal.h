@@ -107,6 +107,7 @@ constexpr int kBlock = 256;       // threads per block of the row kernels
 constexpr int kMaxSweepBlocks = 2048;  // row kernels loop over row groups beyond this
 
 // ---- launchers (kernels_csr.hip) ----
+// deg and diagpos may both be NULL: the rows are then only validated (flags)
 hipError_t launch_plan_rows(int n, int64_t nnz, const int64_t *rp, const int32_t *col,
                             const double *val, int64_t *deg, int64_t *diagpos, uint32_t *flags,
                             hipStream_t s);

@@ -28,8 +28,10 @@ __global__ void k_plan_rows(int n, int64_t nnz, const int64_t *__restrict__ rp,
   if (i >= n) return;
   const int64_t b = rp[i], e = rp[i + 1];
   if (b < 0 || e < b || e > nnz) {
-    deg[i] = 0;
-    diagpos[i] = -1;
+    if (deg) {
+      deg[i] = 0;
+      diagpos[i] = -1;
+    }
     atomicOr(flags, FLAG_ARG);
     return;
   }
@@ -45,8 +47,10 @@ __global__ void k_plan_rows(int n, int64_t nnz, const int64_t *__restrict__ rp,
     else ++d;
   }
   if (dp < 0 || val[dp] == 0.0) f |= FLAG_ZERO_DIAG;
-  deg[i] = d;
-  diagpos[i] = dp;
+  if (deg) {  // NULL: validation only
+    deg[i] = d;
+    diagpos[i] = dp;
+  }
   if (f) atomicOr(flags, f);
 }
 
