@@ -1,15 +1,23 @@
-"""Benchmark: GaBP edge-updates/s and time to relative residual 1e-8 on one
-MI355X.
+"""Benchmark: GaBP time to relative residual 1e-8 (warm start vs plain) and
+edge-updates/s on one MI355X.
 
-Workload (default ``c2``): random sparse symmetric strictly diagonally
-dominant A, n = 2^20, each node drawing 4 distinct partners (union with the
-transpose, about 8 off-diagonals per row), off-diagonals N(0, 1),
-A_ii = 1.1 sum_j |A_ij|, b ~ N(0, 1); FP32 messages with FP64 residual
-refinement to ||b - A x|| / ||b|| <= 1e-8.  One step = one complete solve from
-zero messages (sweeps, mean checks, FP64 residuals, refinement restarts) with
-A and b already in HBM.  value = directed edges x sweeps / wall time.
+Workload (default ``c4``): 64 variable-coefficient 3-D Poisson grids of 64^3
+(7-point, conductivity exp(G) of a Gaussian random field, harmonic faces,
+Dirichlet 0), b ~ N(0, 1), held out from the warm-start network's training
+grids; FP32 messages with FP64 residual refinement until every grid meets
+||b_t - A_t x_t|| / ||b_t|| <= 1e-8; red-black schedule, each grid leaving the
+sweeps once it meets its own target.  One step = one solve of the stack from
+zero messages and one from the network's messages, with A and b already in
+HBM.  value = messages computed per second over both solves (every directed
+message of every grid still sweeping, each sweep); the split into full (P, h)
+sweeps and settled-precision sweeps is reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5]
+Other workloads (``--workload``): c2 random SDD n = 2^20, c3 4096 detection
+instances (one persistent launch), c5 3-D Poisson 256^3 with damping 0.5,
+lsq section VII least squares 2^20 x 2^18, c1 2-D Poisson 32^2 in FP64 to
+1e-10 (small systems in one workgroup).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2|c3|c5|lsq]
 """
 from __future__ import annotations
 
@@ -32,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "lsq"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "lsq"])
     ap.add_argument("--log2n", type=int, default=20,
                     help="c2: log2 of the unknowns (20 is the configuration; 23 puts the "
                          "working set beyond the 256 MB last-level cache)")
@@ -54,6 +62,8 @@ def parse():
                          "coloured schedule saves only a quarter of the sweeps and loses the "
                          "cache reuse of the damping reads) and c2 (its colouring needs 8 "
                          "colours, one launch each: 14 instead of 20 sweeps at the same time)")
+    ap.add_argument("--accel", choices=["none", "aitken", "steffensen"], default=None,
+                    help="c1: acceleration of the means (default aitken)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte "
                          "counters) and print its bandwidth")
@@ -172,13 +182,20 @@ def run_c5(args, G, W, torch, dev):
     opts.grid_blocks = args.grid
     sched, kf, kz, per = grid_schedule(args, G)
     opts.schedule = sched
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter()
     rc, plan = G.gabp_plan_create_grid(A, opts)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t_plan) * 1e3
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create_grid: {G.status_name(rc)}")
     # a coloured sweep is one launch per colour; each colour sends exactly
     # half of the directed edges (every edge joins the two colours) and owns
     # half of the nodes
-    return dict(plan=plan, b=b, x=x, E=E, n=N, b_h=b_h, coef=coef, per_sweep=per,
+    return dict(plan_ms=plan_ms, plan=plan, b=b, x=x, E=E, n=N, b_h=b_h, coef=coef, per_sweep=per,
+                algo_sweep=24.0 * E + 4.0 * N,
+                algo_model="24 B per directed edge (in-message 8, previous out-message 8 for "
+                           "the damping, new out-message 8) + 4 B per node (b_i) per sweep",
                 workload="3-D Poisson 7-point, 256^3 (16,777,216 unknowns, 100,270,080 directed "
                          "edges, 117,047,296 nonzeros), A_ii = 6.01, A_ij = -1, Dirichlet 0, "
                          "b ~ U[-1,1]; FP32 messages, damping 0.5, FP64 refinement to 1e-8; "
@@ -211,14 +228,22 @@ def run_c2(args, G, W, torch, dev):
         opts.schedule = G.GABP_SCHEDULE_COLORED
     else:
         opts.col_blocks = args.col_blocks
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter()
     rc, plan = G.gabp_plan_create(A, opts)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t_plan) * 1e3
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create: {G.status_name(rc)}")
     pair = args.layout == 0
     ncol = G.gabp_plan_colors(plan)[2] if colored else 1
     # coloured: one launch per colour class, each over its rows and their slots;
     # the bytes of a sweep are those of a synchronous pair sweep
-    return dict(plan=plan, b=b, x=x, E=E, n=n, m=m, b_h=b_h, A=A, per_sweep=ncol,
+    return dict(plan_ms=plan_ms, plan=plan, b=b, x=x, E=E, n=n, m=m, b_h=b_h, A=A, per_sweep=ncol,
+                algo_sweep=24.0 * E + 12.0 * n,
+                algo_model="24 B per directed edge (gathered in-message 8, reverse index 4, "
+                           "FP32 coupling 4, out-message 8) + 12 B per node (row offset, A_ii, "
+                           "b_i) per sweep",
                 workload=f"random sparse SDD A (n=2^{args.log2n}, ~8 off-diagonals/row, N(0,1) couplings, "
                          "A_ii=1.1 sum|A_ij|), b~N(0,1); FP32 messages + FP64 refinement to 1e-8; "
                          + (f"coloured schedule ({ncol} colours)" if colored
@@ -257,14 +282,21 @@ def run_lsq(args, G, W, torch, dev):
         opts.schedule = G.GABP_SCHEDULE_COLORED
     else:
         opts.col_blocks = args.col_blocks
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter()
     rc, plan = G.gabp_plan_create_lsq(R, psi, opts)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t_plan) * 1e3
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create_lsq: {G.status_name(rc)}")
     y = torch.from_numpy(y_h).to(dev)
     x = torch.zeros(k, dtype=torch.float64, device=dev)
     n, E = k + m, 2 * S.nnz
     per = 2 if colored else 1
-    return dict(plan=plan, b=y, x=x, E=E, n=n, S=S, y_h=y_h, psi=psi, R=R, per_sweep=per,
+    return dict(plan_ms=plan_ms, plan=plan, b=y, x=x, E=E, n=n, S=S, y_h=y_h, psi=psi, R=R, per_sweep=per,
+                algo_sweep=24.0 * E + 12.0 * n,
+                algo_model="the general sparse model: 24 B per directed edge + 12 B per node "
+                           "per sweep",
                 solve=lambda: G.gabp_plan_solve_lsq(plan, y, x),
                 workload="section VII regularised least squares: S sparse 2^20 x 2^18, 8 random "
                          "nonzeros per row N(0,1)/sqrt(8), psi = 0.1, y ~ N(0,1); bipartite "
@@ -373,7 +405,13 @@ def bench_c3(args, G, W, torch, dev):
         damped += sum(1 for p in per if p.damping > 0)
         worst = max(worst, summ.rel_residual)
     avg_s = kms * 1e-3 / args.steps
-    achieved = algo / args.steps / avg_s / 1e9
+    # the unit the measurement fixes for the bipartite batch: 16 B per directed
+    # edge per sweep (message in and out, FP32 (P, h)); the persistent launch
+    # runs every sweep of every instance, full and settled alike
+    algo16 = 16.0 * work / args.steps
+    achieved = algo16 / avg_s / 1e9
+    traffic = measured_traffic("gabp::(anonymous namespace)::k_dense_batch<float, 4, 0, "
+                               f"{'true' if colored else 'false'}>", "c3")
     out = {
         "metric": "GaBP edge-updates/s (solve to rel. residual 1e-8)",
         "value": work / dt,
@@ -397,13 +435,15 @@ def bench_c3(args, G, W, torch, dev):
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("gabp::(anonymous namespace)::k_dense_batch<float, 4, 0, "
-                                        f"{'true' if colored else 'false'}>", "c3"),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": f"k_dense_batch<float,4,bipartite,{'coloured' if colored else 'sync'}> "
                       "(persistent: every sweep, check and refinement of every instance)",
-            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": algo / args.steps,
+            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": algo16,
+            "bytes_model": "16 B per directed edge per sweep",
             "launches_timed": args.steps,
+            "layout_bytes_per_launch": algo / args.steps,
+            "layout_over_algorithmic": algo / args.steps / algo16,
+            "traffic_over_algorithmic": (traffic / algo16) if traffic else None,
         },
     }
     if not args.no_cpu_baseline:
@@ -411,12 +451,136 @@ def bench_c3(args, G, W, torch, dev):
     return out
 
 
+LDS_PEAK_CU_GBS = 128 * 2.4  # one compute unit's LDS: 128 B per clock at 2.4 GHz, GB/s
+
+
+def bench_c1(args, G, W, torch, dev):
+    """The 32 x 32 Poisson system in FP64 to rel. residual 1e-10: one instance
+    of the small-system batch path (one workgroup, messages in LDS, the stop
+    rule on the device), red-black schedule with Aitken's extrapolation of the
+    means by default.  One step = one solve."""
+    import oracle
+    m = W.poisson2d(32)
+    b_h = W.uniform_b(m.n, args.seed)
+    E = int(m.nnz - m.n)
+    B = G.DeviceBatch.sparse([m.n], m, device=dev)
+    b = torch.from_numpy(b_h).to(dev)
+    x = torch.zeros(m.n, dtype=torch.float64, device=dev)
+    accel = {"none": G.GABP_ACCEL_NONE, "aitken": G.GABP_ACCEL_AITKEN,
+             "steffensen": G.GABP_ACCEL_STEFFENSEN}[args.accel or "aitken"]
+    colored = (args.schedule or "colored") == "colored"
+    opts = G.gabp_default_opts(msg_fp32=0, tol=1e-10, max_sweeps=100000,
+                               schedule=G.GABP_SCHEDULE_COLORED if colored else G.GABP_SCHEDULE_SYNC,
+                               accel=accel, accel_stride=1 if colored else 2)
+    if args.check_every:
+        opts.check_every = args.check_every
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, plan = G.gabp_plan_create_batched(B, opts)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    if rc != G.GABP_OK:
+        raise SystemExit(f"plan_create_batched: {G.status_name(rc)}")
+    for _ in range(args.warmup):
+        rc, per, summ = G.gabp_plan_solve_batched(plan, b, x)
+        if rc != G.GABP_OK:
+            raise SystemExit(f"warmup solve: {G.status_name(rc)}")
+    kms, sweeps = 0.0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, per, summ = G.gabp_plan_solve_batched(plan, b, x)
+        if rc != G.GABP_OK:
+            raise SystemExit(f"timed solve: {G.status_name(rc)}")
+        kms += summ.sweep_ms
+        sweeps += per[0].sweeps
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    G.gabp_plan_destroy(plan)
+    K = args.steps
+    xh = x.cpu().numpy()
+    _, rn = oracle.residual(m, b_h, xh)
+    # the oracle beside it: synchronous FP64 Algorithm 2 from zero messages to
+    # the same tolerance, and its answer for the error of ours
+    t1 = time.perf_counter()
+    ref = oracle.solve(m, b_h, algorithm=2, tol=1e-10, max_rounds=50000)
+    ot = time.perf_counter() - t1
+    err = float(np.linalg.norm(xh - ref.x) / np.linalg.norm(ref.x))
+    avg_s = kms * 1e-3 / K
+    per_sweep = sweeps / K
+    lds_bytes = 32.0 * E + 8.0 * m.n  # FP64 in-message read 16 + write 16 per edge, b per node
+    achieved = lds_bytes * per_sweep / avg_s / 1e9
+    out = {
+        "metric": "GaBP time to rel. residual 1e-10 (small system, latency)",
+        "value": dt * 1e3 / K, "unit": "ms", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / K, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": "2-D Poisson 5-point 32 x 32 (n = 1024, 3,968 directed edges), "
+                        "b ~ U[-1,1], FP64 messages, zero messages, to rel. residual 1e-10; one "
+                        "workgroup with every message in LDS; "
+                        + ("red-black schedule" if colored else "synchronous schedule")
+                        + f", acceleration {args.accel or 'aitken'}",
+            "n": m.n, "directed_edges": E, "seed": args.seed,
+            "time_to_1e-10_ms": dt * 1e3 / K, "kernel_ms": avg_s * 1e3,
+            "sweeps": per_sweep, "rel_residual": rn / np.linalg.norm(b_h),
+            "err_vs_oracle": err, "oracle_rounds": ref.rounds, "plan_ms": plan_ms,
+            "edge_updates_per_s": E * per_sweep / (dt / K),
+        },
+        "roofline": {
+            "bound": "lds", "achieved": achieved, "peak": LDS_PEAK_CU_GBS, "unit": "GB/s",
+            "frac": achieved / LDS_PEAK_CU_GBS, "traffic": None,
+            "kernel": "k_small_batch<double,1,8,*> (whole solve in one workgroup)",
+            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": lds_bytes * per_sweep,
+            "bytes_model": "32 B per directed edge + 8 B per node per sweep, in LDS (one CU)",
+            "launches_timed": K,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = {
+            "value": ot * 1e3, "unit": "ms", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"the same system solved once by the FP64 oracle (synchronous Algorithm 2, "
+                      f"OpenMP over rows) to rel. residual 1e-10: {ref.rounds} rounds in "
+                      f"{ot * 1e3:.1f} ms"}
+    return out
+
+
+def c4_full_bytes_per_sweep(N: int, E: int) -> float:
+    """Algorithmic bytes of one full (P, h) sweep of a variable-coefficient
+    grid stack, per the unit the measurement fixes: per directed edge the
+    in-message (8) and the written out-message (8) in FP32 and the FP32 face
+    coupling shared by the edge's two directions (2); per node A_ii and b_i
+    (8).  The red-black schedule moves half of it per colour launch."""
+    return 18.0 * E + 8.0 * N
+
+
+def oracle_grid_reference(seed: int, t: int, n: int, b_stack, tol=1e-11, max_rounds=40000):
+    """The FP64 oracle (synchronous Algorithm 2 from zero messages, OpenMP over
+    rows) on grid t of the stack alone: its solution and how long it took.
+    Inputs come from the seeded generators (b_stack: the host right-hand side of
+    the whole stack)."""
+    import oracle
+    import workloads as W
+    csr, _ = W.grid_stack(n, n, n, 1, varcoef=True, seed=seed + t, with_csr=True)
+    nn = n ** 3
+    b = np.ascontiguousarray(b_stack[t * nn:(t + 1) * nn])
+    t0 = time.perf_counter()
+    r = oracle.solve(csr, b, algorithm=2, tol=tol, max_rounds=max_rounds)
+    dt = time.perf_counter() - t0
+    hit = np.nonzero(r.trace <= 1e-8)[0]
+    return {"x": r.x, "status": r.status, "rounds": r.rounds, "seconds": dt,
+            "rel_residual": float(r.trace[-1]), "edges": int(csr.nnz - csr.n),
+            "rounds_to_1e-8": int(hit[0]) if hit.size else None, "csr": csr, "b": b}
+
+
 def bench_c4(args, G, W, torch, dev):
     """64 variable-coefficient grids of 64^3 (held out from the warm start's
-    training grids) solved to 1e-8 from zero messages and from the trained
-    network's messages; both timed, the zero-message solve is the value."""
+    training grids) solved to 1e-8 from zero messages (plain) and from the
+    trained network's messages (warm).  One step = one plain and one warm
+    solve of the whole stack; value = messages computed per second over both."""
     from paper_0810_1119_amd import warmstart as WS
     n, count = 64, 64
+    nn = n ** 3
     A, b, coef = WS.grid_stack(args.seed, count, n)
     N = A.n
     E = 2 * 3 * (n - 1) * n * n * count
@@ -428,113 +592,151 @@ def bench_c4(args, G, W, torch, dev):
     opts.grid_blocks = args.grid
     sched, kf, kz, per = grid_schedule(args, G)
     opts.schedule = sched
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     rc, plan = G.gabp_plan_create_grid(A, opts)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3  # device plan only (inputs already resident)
     if rc != G.GABP_OK:
         raise SystemExit(f"plan_create_grid: {G.status_name(rc)}")
-    x = torch.zeros(N, dtype=torch.float64, device=dev)
+    xp = torch.zeros(N, dtype=torch.float64, device=dev)
+    xw = torch.zeros(N, dtype=torch.float64, device=dev)
+
+    def solve(kind):
+        if kind == "plain":
+            rc, st = G.gabp_plan_solve(plan, b, xp)
+        else:
+            rc, st = G.gabp_plan_solve_warm(plan, model, b, xw)
+        if rc != G.GABP_OK:
+            raise SystemExit(f"{kind} solve: {G.status_name(rc)}")
+        return st
+
     for _ in range(args.warmup):
-        G.gabp_plan_solve(plan, b, x)
-    res = {}
-    for kind in ("plain", "warm"):
-        runs = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            if kind == "plain":
-                rc, st = G.gabp_plan_solve(plan, b, x)
-            else:
-                rc, st = G.gabp_plan_solve_warm(plan, model, b, x)
-            if rc != G.GABP_OK:
-                raise SystemExit(f"{kind} solve: {G.status_name(rc)}")
-            runs.append(st)
-        torch.cuda.synchronize()
-        res[kind] = (time.perf_counter() - t0, runs)
+        solve("plain")
+        solve("warm")
+    res = {"plain": [], "warm": []}
+    wall = {"plain": 0.0, "warm": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for kind in ("plain", "warm"):
+            t1 = time.perf_counter()  # each solve returns once its results are complete
+            res[kind].append(solve(kind))
+            wall[kind] += time.perf_counter() - t1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
     G.gabp_plan_destroy(plan)
+    K = args.steps
     # each grid's own FP64 residual, recomputed one grid at a time outside the timing
-    # (the library's stop rule already requires every grid to meet the tolerance)
-    nn = n ** 3
-    worst_grid = 0.0
-    for t in range(count):
-        sl = slice(t * nn, (t + 1) * nn)
-        At = G.DeviceGrid(n, n, n, 1, diag=A.diag[sl], cx=A.cx[sl], cy=A.cy[sl], cz=A.cz[sl])
-        rc, rel = G.gabp_residual_grid(At, b[sl], x[sl])
-        worst_grid = max(worst_grid, rel)
-    dt, runs = res["plain"]
-    sweeps = sum(st.sweeps for st in runs)  # the slowest grid's
-    # with the coloured schedule each grid stops sweeping once it meets its own
-    # target: work is counted per grid
-    grid_sweeps = sum(st.mean_sweeps for st in runs)
+    worst = {}
+    for kind, xv in (("plain", xp), ("warm", xw)):
+        w = 0.0
+        for t in range(count):
+            sl = slice(t * nn, (t + 1) * nn)
+            At = G.DeviceGrid(n, n, n, 1, diag=A.diag[sl], cx=A.cx[sl], cy=A.cy[sl], cz=A.cz[sl])
+            w = max(w, G.gabp_residual_grid(At, b[sl], xv[sl])[1])
+        worst[kind] = w
+    runs, wruns = res["plain"], res["warm"]
+    # messages computed: with the red-black schedule each grid leaves the
+    # sweeps once it meets its own target, so sweeps are counted per grid
+    msgs = E * sum(st.mean_sweeps for st in runs + wruns)
+    full_grid = sum(st.mean_sweeps - st.mean_frozen_sweeps for st in runs + wruns)
+    settled_grid = sum(st.mean_frozen_sweeps for st in runs + wruns)
+    # full (P, h) sweep kernel: every grid sweeps (the precisions settle long
+    # before any grid meets its target), 2 launches per sweep, section 8(d)
+    # bytes; timed with HIP events on the solve's stream (plain solves)
+    full_sweeps = sum(st.sweeps - st.frozen_sweeps for st in runs)
+    full_ms = sum(st.sweep_ms - st.frozen_sweep_ms for st in runs)
+    full_launches = max(per * full_sweeps, 1)
+    full_bpl = c4_full_bytes_per_sweep(N, E) / per
+    full_avg_s = full_ms * 1e-3 / full_launches
+    full_gbs = full_bpl / full_avg_s / 1e9
+    # settled-precision kernel (most of the device time): its own bytes per
+    # launch, averaged over launches that cover fewer grids as grids stop
     frozen = sum(st.frozen_sweeps for st in runs)
     grid_frozen = sum(st.mean_frozen_sweeps for st in runs)
-    c_eff = sweeps / max(sum(st.checks for st in runs), 1)  # sweeps per check sweep as run
+    c_eff = sum(st.sweeps for st in runs) / max(sum(st.checks for st in runs), 1)
     fz_ms = sum(st.frozen_sweep_ms for st in runs)
-    wdt, wruns = res["warm"]
-    # launches of the settled phase cover the grids still sweeping: bytes per
-    # launch averaged over the launches timed
-    launches = max(per * frozen, 1)
-    bps = grid_bytes_per_sweep(N, E, True, False, c_eff) / per * grid_frozen / max(frozen, 1)
-    avg_s = fz_ms * 1e-3 / launches
-    achieved = bps / avg_s / 1e9
+    fz_launches = max(per * frozen, 1)
+    fz_bpl = grid_bytes_per_sweep(N, E, True, False, c_eff) / per * grid_frozen / max(frozen, 1)
+    fz_avg_s = fz_ms * 1e-3 / fz_launches
+    fz_gbs = fz_bpl / fz_avg_s / 1e9
+    tp, tw = wall["plain"] / K, wall["warm"] / K
     out = {
         "metric": "GaBP edge-updates/s; time to rel. residual 1e-8, warm start vs plain",
-        "value": E * grid_sweeps / dt, "unit": "edge-updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
+        "value": msgs / dt, "unit": "edge-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / K,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {
             "workload": "64 variable-coefficient 3-D Poisson grids of 64^3 (7-point, k = exp(G), "
                         "G Gaussian random field std 1, correlation length 8 cells, harmonic "
                         "faces, Dirichlet 0), b ~ N(0,1); FP32 messages + FP64 refinement to "
-                        "1e-8; grids held out from the warm start's 512 training grids; "
-                        f"{'red-black (serial-like)' if per == 2 else 'synchronous'} schedule",
+                        "1e-8 per grid; grids held out from the warm start's 512 training grids; "
+                        f"{'red-black (serial-like)' if per == 2 else 'synchronous'} schedule; "
+                        "one step = one plain and one warm-started solve of the stack",
             "grids": count, "n": N, "directed_edges": E, "seed": args.seed,
-            "time_to_1e-8_ms_plain": dt * 1e3 / args.steps,
-            "time_to_1e-8_ms_warm": wdt * 1e3 / args.steps,
-            "sweeps_plain": sweeps / args.steps,
-            "mean_sweeps_per_grid_plain": grid_sweeps / args.steps,
+            "time_to_1e-8_ms_plain": tp * 1e3,
+            "time_to_1e-8_ms_warm": tw * 1e3,
+            "warm_speedup": tp / tw,
+            "sweeps_slowest_grid_plain": sum(st.sweeps for st in runs) / K,
+            "sweeps_slowest_grid_warm": sum(st.sweeps for st in wruns) / K,
+            "mean_sweeps_per_grid_plain": sum(st.mean_sweeps for st in runs) / K,
+            "mean_sweeps_per_grid_warm": sum(st.mean_sweeps for st in wruns) / K,
+            "full_sweeps_per_grid": full_grid / (2 * K),
+            "settled_sweeps_per_grid": settled_grid / (2 * K),
+            "edge_updates_per_s_full_sweeps_only": E * full_grid / dt,
+            "edge_updates_per_s_settled_sweeps_only": E * settled_grid / dt,
             "sweeps_per_check": c_eff,
-            "sweeps_warm": sum(st.sweeps for st in wruns) / args.steps,
-            "mean_sweeps_per_grid_warm": sum(st.mean_sweeps for st in wruns) / args.steps,
             "warm_start_status": wruns[-1].warm_start,
-            "rel_residual_worst_grid_plain": runs[-1].rel_residual,
-            "rel_residual_worst_grid_warm": worst_grid,
-            "warm_speedup": dt / wdt,
+            "rel_residual_worst_grid_plain": worst["plain"],
+            "rel_residual_worst_grid_warm": worst["warm"],
+            "plan_ms": plan_ms,
             "warm_model": {k: meta[k] for k in ("grids", "samples", "steps", "final_loss")},
+            "settled_kernel": {
+                "kernel": f"{kz}<float,*,undamped> (settled precisions: information only"
+                          f"{', one launch per colour' if per == 2 else ''})",
+                "avg_launch_us": fz_avg_s * 1e6, "launches_timed": fz_launches,
+                "own_bytes_per_launch": fz_bpl, "achieved_GBps": fz_gbs,
+                "frac_of_hbm_peak": fz_gbs / HBM_PEAK_GBS,
+                "traffic": measured_traffic(f"gabp::{kz}<float, ", "c4", 1.0 / c_eff),
+                "device_time_share": fz_ms / max(sum(st.sweep_ms for st in runs), 1e-30),
+            },
         },
         "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(f"gabp::{kz}<float, ", "c4", 1.0 / c_eff),
-            "kernel": f"{kz}<float,*,undamped> (settled-precision sweep"
+            "bound": "hbm", "achieved": full_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": full_gbs / HBM_PEAK_GBS,
+            "traffic": measured_traffic(f"gabp::{kf}<float, ", "c4"),
+            "kernel": f"{kf}<float,*,undamped> (full (P, h) sweep: A1 + A2 + A3"
                       f"{', one launch per colour' if per == 2 else ''})",
-            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bps,
-            "launches_timed": launches,
+            "avg_launch_us": full_avg_s * 1e6, "algorithmic_bytes_per_launch": full_bpl,
+            "bytes_model": "18 B per directed edge + 8 B per node per sweep",
+            "launches_timed": full_launches,
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_c4(args.seed, E / count)
-    return out
-
-
-def cpu_baseline_c4(seed, edges_per_grid, budget_s=12.0):
-    """The oracle on 4 of the grids (their CSR built outside the timing),
-    Algorithm 2 rounds for a bounded time."""
-    import oracle
-    import workloads as W
-    csr, _ = W.grid_stack(64, 64, 64, 4, varcoef=True, seed=seed, with_csr=True)
-    b = W.normal_b(csr.n, seed)
-    R = oracle.Rounds(csr, b, algorithm=2)
-    t0 = time.perf_counter()
-    rounds = 0
-    while time.perf_counter() - t0 < budget_s and rounds < 200:
-        R.step()
-        rounds += 1
-    dt = time.perf_counter() - t0
-    return {"value": 4 * edges_per_grid * rounds / dt, "unit": "edge-updates/s",
+        ref = oracle_grid_reference(args.seed, 0, n, W.normal_b(N, args.seed))
+        errs = {}
+        for kind, xv in (("plain", xp), ("warm", xw)):
+            xg = xv[:nn].cpu().numpy()
+            errs[kind] = {"rel_l2": float(np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"])),
+                          "max_abs": float(np.abs(xg - ref["x"]).max())}
+        out["config"]["err_vs_oracle_grid0"] = {
+            **errs, "oracle_rounds": ref["rounds"], "oracle_rel_residual": ref["rel_residual"]}
+        import oracle
+        rt = ref["rounds_to_1e-8"]
+        out["cpu_baseline"] = {
+            "value": ref["edges"] * ref["rounds"] / ref["seconds"], "unit": "edge-updates/s",
             "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{rounds} FP64 oracle rounds (Algorithm 2, OpenMP over rows) on 4 of the "
-                      f"64 grids in {dt:.1f} s (a bounded slice of a solve)"}
+            "sample": f"grid 0 of the stack solved alone by the FP64 oracle (synchronous "
+                      f"Algorithm 2 from zero messages, OpenMP over rows): {ref['rounds']} rounds "
+                      f"to rel. residual {ref['rel_residual']:.1e} in {ref['seconds']:.1f} s"
+                      + (f"; 1e-8 after {rt} rounds, about "
+                         f"{ref['seconds'] * rt / ref['rounds']:.1f} s for one grid"
+                         if rt else ""),
+        }
+    return out
 
 
 def cpu_baseline_c3(db, budget_s=12.0):
@@ -594,17 +796,17 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.workload == "c1":
+        print(json.dumps(bench_c1(args, G, W, torch, dev)))
+        return
     if args.workload == "c3":
         print(json.dumps(bench_c3(args, G, W, torch, dev)))
         return
     if args.workload == "c4":
         print(json.dumps(bench_c4(args, G, W, torch, dev)))
         return
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     w = {"c2": run_c2, "c5": run_c5, "lsq": run_lsq}[args.workload](args, G, W, torch, dev)
-    torch.cuda.synchronize()
-    plan_ms = (time.perf_counter() - t0) * 1e3
+    plan_ms = w["plan_ms"]  # plan creation on the device only (inputs already resident)
     plan, b, x, E, n = w["plan"], w["b"], w["x"], w["E"], w["n"]
 
     solve = w.get("solve") or (lambda: G.gabp_plan_solve(plan, b, x))
@@ -637,26 +839,36 @@ def main():
     G.gabp_plan_destroy(plan)
 
     ms_per_step = dt * 1e3 / args.steps
-    value = E * sweeps / dt
+    value = E * sweeps / dt  # every message of every sweep (full or settled)
     full_sweeps, full_ms = sweeps - frozen, sweep_ms - frozen_ms
     # sweeps per check sweep as run (the interval grows with long passes)
     c_eff = sweeps / max(checks, 1)
-    # dominant kernel = the sweep kind with the larger share of device time,
-    # timed with HIP events on the solve's stream
-    use_frozen = frozen > 0 and frozen_ms >= full_ms and w["bytes_frozen"]
-    if use_frozen:
-        kname, bps, launches, kms = w["kfrozen"], w["bytes_frozen"](c_eff), frozen, frozen_ms
-        tkey = w.get("tkey_frozen")
-    else:
-        kname, bps, launches, kms = w["kfull"], w["bytes_full"](c_eff), full_sweeps, full_ms
-        tkey = w.get("tkey_full")
-    traffic = measured_traffic(tkey, args.workload, 1.0 / c_eff) if tkey else None
-    # the workload's bytes are per launch at its own count of launches per
-    # sweep; the plan reports how many it ran (column ranges, colour classes)
-    bps = bps * w.get("per_sweep", 1) / lps
-    launches *= lps
-    avg_s = kms * 1e-3 / max(launches, 1)
-    achieved = bps / avg_s / 1e9
+    per = w.get("per_sweep", 1)
+    # roofline: the full (P, h) sweep kernel, on the bytes the measurement
+    # fixes for one sweep of this workload, over its average launch time from
+    # HIP events on the solve's stream; the plan reports its launches per
+    # sweep (column ranges, colour classes)
+    full_launches = max(full_sweeps * lps, 1)
+    full_avg_s = full_ms * 1e-3 / full_launches
+    full_bpl = w["algo_sweep"] / lps
+    full_gbs = full_bpl / full_avg_s / 1e9
+    own_full = w["bytes_full"](c_eff) * per / lps
+    tk = w.get("tkey_full")
+    traffic_full = measured_traffic(tk, args.workload, 1.0 / c_eff) if tk else None
+    settled = None
+    if frozen and w.get("bytes_frozen"):
+        fz_launches = frozen * lps
+        fz_avg_s = frozen_ms * 1e-3 / fz_launches
+        own_fz = w["bytes_frozen"](c_eff) * per / lps
+        tkz = w.get("tkey_frozen")
+        settled = {
+            "kernel": w["kfrozen"], "avg_launch_us": fz_avg_s * 1e6,
+            "launches_timed": fz_launches, "own_bytes_per_launch": own_fz,
+            "achieved_GBps": own_fz / fz_avg_s / 1e9,
+            "frac_of_hbm_peak": own_fz / fz_avg_s / 1e9 / HBM_PEAK_GBS,
+            "traffic": measured_traffic(tkz, args.workload, 1.0 / c_eff) if tkz else None,
+            "device_time_share": frozen_ms / max(sweep_ms, 1e-30),
+        }
     out = {
         "metric": "GaBP edge-updates/s (solve to rel. residual 1e-8)",
         "value": value,
@@ -674,18 +886,22 @@ def main():
             "workload": w["workload"], "n": n, "directed_edges": E, "seed": args.seed,
             "sweeps_per_solve": sweeps / args.steps, "restarts_per_solve": restarts / args.steps,
             "settled_precision_sweeps_per_solve": frozen / args.steps,
+            "edge_updates_per_s_full_sweeps_only": E * full_sweeps / dt,
+            "edge_updates_per_s_settled_sweeps_only": E * frozen / dt,
             "sweeps_per_check": c_eff,
             "time_to_1e-8_ms": ms_per_step, "worst_rel_residual": worst_rel,
             "plan_ms": plan_ms,
+            "settled_kernel": settled,
         },
         "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": kname, "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bps,
-            "launches_timed": launches,
-            "full_sweep_avg_us": (full_ms * 1e3 / full_sweeps) if full_sweeps else None,
-            "settled_sweep_avg_us": (frozen_ms * 1e3 / frozen) if frozen else None,
-            "launches_per_sweep": lps,
+            "bound": "hbm", "achieved": full_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": full_gbs / HBM_PEAK_GBS, "traffic": traffic_full,
+            "kernel": w["kfull"], "avg_launch_us": full_avg_s * 1e6,
+            "algorithmic_bytes_per_launch": full_bpl, "bytes_model": w["algo_model"],
+            "launches_timed": full_launches, "launches_per_sweep": lps,
+            "layout_bytes_per_launch": own_full,
+            "layout_over_algorithmic": own_full / full_bpl,
+            "traffic_over_algorithmic": (traffic_full / full_bpl) if traffic_full else None,
         },
     }
     if lsq_rel is not None:  # the least-squares residual of the answer, outside the timing

@@ -144,10 +144,34 @@ typedef struct {
                           schedule or the gather layout: GABP_ERR_UNSUPPORTED;
                           other values: GABP_ERR_ARG.  Other plan kinds ignore
                           it. */
+  int32_t accel;        /* acceleration of the means, section IV-A (batches of
+                          small CSR instances only; other plans return
+                          GABP_ERR_UNSUPPORTED for a nonzero value):
+                          GABP_ACCEL_NONE (default);
+                          GABP_ACCEL_AITKEN: GaBP runs unchanged, the means are
+                          sampled every accel_stride sweeps (x_0 = the means of
+                          the messages a pass starts from) and each node
+                          extrapolates its last three samples x0, x1, x2 to
+                          y = x0 - (x1 - x0)^2 / (x2 - 2 x1 + x0) (y = x2 when
+                          the second difference is zero; at the first sample
+                          of a pass y is that sample); the stop rule and the
+                          answer use y;
+                          GABP_ACCEL_STEFFENSEN: cycles of accel_cycle sweeps;
+                          at the end of a cycle the samples of sweeps
+                          cycle - 2 stride, cycle - stride and cycle are
+                          extrapolated, x += y, and GaBP runs again on the
+                          residual b - A x from zero information messages with
+                          the precision messages kept (the paper does not say
+                          how a vector of means re-enters message form) */
+  int32_t accel_stride; /* sweeps between samples, >= 1; 0 = 2 (pairs sweeps of
+                          equal parity, which bipartite graphs need under the
+                          synchronous schedule) */
+  int32_t accel_cycle;  /* Steffensen: sweeps per cycle, >= 2 stride; 0 = 100 */
 } gabp_opts;
 
 enum { GABP_LAYOUT_PAIR = 0, GABP_LAYOUT_GATHER = 1 };
 enum { GABP_SCHEDULE_SYNC = 0, GABP_SCHEDULE_COLORED = 1 };
+enum { GABP_ACCEL_NONE = 0, GABP_ACCEL_AITKEN = 1, GABP_ACCEL_STEFFENSEN = 2 };
 
 typedef struct {
   int32_t status;          /* gabp_status of the solve */
@@ -335,16 +359,43 @@ int gabp_residual_grid(const gabp_grid *A, const double *b, const double *x, dou
  * to back in x (K_t entries each).  Limits: K_t <= 512 and the per-workgroup
  * state of the largest instance must fit the 160 KB LDS (about N_t <= 4096 for
  * FP32 messages); beyond: GABP_ERR_UNSUPPORTED. */
-enum { GABP_BATCH_BIPARTITE = 0, GABP_BATCH_DENSE = 1 };
+enum { GABP_BATCH_BIPARTITE = 0, GABP_BATCH_DENSE = 1, GABP_BATCH_CSR = 2 };
 typedef struct {
-  int32_t kind;          /* GABP_BATCH_BIPARTITE or GABP_BATCH_DENSE */
+  int32_t kind;          /* GABP_BATCH_BIPARTITE, GABP_BATCH_DENSE or GABP_BATCH_CSR */
   int32_t count;         /* instances, >= 0 */
   const int32_t *k;      /* host [count]: users K_t, or the order of A_t */
-  const int32_t *m;      /* host [count]: chips N_t (bipartite; NULL for dense) */
-  const double *sigma2;  /* host [count]: noise variance (bipartite; NULL for dense) */
+  const int32_t *m;      /* host [count]: chips N_t (bipartite; NULL otherwise) */
+  const double *sigma2;  /* host [count]: noise variance (bipartite; NULL otherwise) */
   const double *mat;     /* device: S_t (N_t x K_t) or A_t (K_t x K_t), packed; read
-                            by the plan until it is destroyed */
+                            by the plan until it is destroyed (NULL for CSR) */
+  const gabp_csr *csr;   /* GABP_BATCH_CSR: the instances as the diagonal blocks
+                            of one sparse symmetric matrix (host struct, device
+                            arrays as for gabp_solve): instance t owns rows
+                            [o_t, o_t + k_t), o_t = k_0 + ... + k_{t-1}, and no
+                            stored entry may join two instances (GABP_ERR_ARG);
+                            read by the plan until it is destroyed.  NULL for
+                            the dense kinds */
 } gabp_batch;
+/* GABP_BATCH_CSR: independent sparse symmetric systems A_t x_t = b_t of
+ * uneven sizes (section II-C each), one workgroup per instance in one
+ * persistent launch, every message of an instance in LDS, so no host round
+ * trip happens between sweeps and each instance stops on its own: at every
+ * check (every check_every sweeps, 0 = 2; with Aitken every accel_stride
+ * sweeps; with Steffensen at the end of each cycle) the FP64 residual
+ * ||b_t - A_t x_t|| / ||b_t|| of the instance's current answer is computed and
+ * the instance stops once it meets tol.  An inner solve that has converged to
+ * its own target or stagnated at the message precision restarts on the
+ * residual (refinement, as for gabp_solve).  Both schedules: synchronous, or
+ * the serial scheme in the order of a colouring the plan computes on the host
+ * (two colours where an instance's graph is bipartite, else greedy first-fit
+ * in row order; gabp_plan_colors reports it).  b and x are packed like the
+ * rows.  Limits (GABP_ERR_UNSUPPORTED beyond): k_t <= 4096 rows; the
+ * messages of the largest instance must fit the 160 KB LDS: directed edges x
+ * 16 bytes (FP32) or 32 bytes (FP64) under the synchronous schedule (two
+ * buffers), half that under the coloured one, plus 8 bytes per row; at most
+ * 2^31 - 1 directed edges in all.  gabp_plan_reset / sweeps / marginals /
+ * get_messages / set_messages work as for a CSR plan of the whole
+ * block-diagonal matrix (messages at the CSR slot of A_ij). */
 /* Validates every instance on the device (finite entries; dense: exactly
  * symmetric with nonzero diagonal; bipartite: sigma2 finite and > 0), keeps a
  * working-precision copy of the couplings and allocates the message state

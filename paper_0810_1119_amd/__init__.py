@@ -17,7 +17,8 @@ from ._abi import (  # noqa: F401
     gabp_plan_solve, gabp_plan_reset, gabp_plan_sweeps, gabp_plan_marginals,
     gabp_plan_get_messages, gabp_plan_set_messages, gabp_version,
     DeviceGrid, gabp_plan_create_grid, gabp_solve_grid, gabp_residual_grid,
-    GABP_BATCH_BIPARTITE, GABP_BATCH_DENSE, DeviceBatch,
+    GABP_BATCH_BIPARTITE, GABP_BATCH_DENSE, GABP_BATCH_CSR, DeviceBatch,
+    GABP_ACCEL_NONE, GABP_ACCEL_AITKEN, GABP_ACCEL_STEFFENSEN,
     gabp_plan_create_batched, gabp_plan_solve_batched, gabp_solve_batched,
     GABP_MODEL_INPUTS, GABP_MODEL_OUTPUTS, GABP_MODEL_PARAMS, Model,
     gabp_model_create, gabp_model_get_params, gabp_model_set_params, gabp_model_forward,

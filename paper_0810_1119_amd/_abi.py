@@ -28,6 +28,10 @@ GABP_SCHEDULE_SYNC = 0
 GABP_SCHEDULE_COLORED = 1
 GABP_BATCH_BIPARTITE = 0
 GABP_BATCH_DENSE = 1
+GABP_BATCH_CSR = 2
+GABP_ACCEL_NONE = 0
+GABP_ACCEL_AITKEN = 1
+GABP_ACCEL_STEFFENSEN = 2
 
 _NAMES = {v: k for k, v in dict(globals()).items()
           if k.startswith("GABP_")
@@ -72,7 +76,8 @@ class Opts(C.Structure):
                 ("max_restarts", C.c_int32), ("group", C.c_int32), ("layout", C.c_int32),
                 ("grid_blocks", C.c_int32), ("freeze", C.c_int32), ("batch_waves", C.c_int32),
                 ("freeze_tol", C.c_double), ("adapt_damping", C.c_int32),
-                ("schedule", C.c_int32), ("col_blocks", C.c_int32)]
+                ("schedule", C.c_int32), ("col_blocks", C.c_int32), ("accel", C.c_int32),
+                ("accel_stride", C.c_int32), ("accel_cycle", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -442,20 +447,33 @@ def gabp_residual_grid(A: DeviceGrid, b, x, r=None, stream=None):
 
 class _Batch(C.Structure):
     _fields_ = [("kind", C.c_int32), ("count", C.c_int32), ("k", C.c_void_p), ("m", C.c_void_p),
-                ("sigma2", C.c_void_p), ("mat", C.c_void_p)]
+                ("sigma2", C.c_void_p), ("mat", C.c_void_p), ("csr", C.c_void_p)]
 
 
 @dataclass
 class DeviceBatch:
-    """A batch of dense instances for gabp_solve_batched: per-instance sizes
-    and noise variances on the host, the packed row-major matrices (float64
-    CUDA tensor) on the device.  Bipartite: S_t (N_t x K_t), right-hand sides
-    y_t; dense: A_t (K_t x K_t), right-hand sides b_t."""
+    """A batch of instances for gabp_solve_batched: per-instance sizes and
+    noise variances on the host, the matrices on the device.  Bipartite: S_t
+    (N_t x K_t, packed row-major float64), right-hand sides y_t; dense: A_t
+    (K_t x K_t), right-hand sides b_t; CSR: the instances as the diagonal
+    blocks of one sparse symmetric matrix (a DeviceCSR), right-hand sides and
+    solutions packed like its rows."""
     kind: int
     k: object
     m: object = None
     sigma2: object = None
     mat: object = None
+    csr: object = None
+
+    @classmethod
+    def sparse(cls, K, A, device="cuda"):
+        """K: rows of each instance; A: host CSR (workloads.CSR) of the
+        block-diagonal matrix, or a DeviceCSR."""
+        import numpy as np
+        K = np.ascontiguousarray(K, dtype=np.int32)
+        if not isinstance(A, DeviceCSR):
+            A = DeviceCSR.from_host(A, device)
+        return cls(GABP_BATCH_CSR, K, None, None, None, A)
 
     @classmethod
     def bipartite(cls, K, N, sigma2, S, device="cuda"):
@@ -484,6 +502,14 @@ class DeviceBatch:
         return int(sum(int(v) for v in self.k))
 
     @property
+    def n(self) -> int:  # rows of the batch (trajectory calls)
+        return self.nodes
+
+    @property
+    def nnz(self) -> int:  # CSR kind: stored entries (get/set_messages)
+        return self.csr.nnz if self.csr is not None else 0
+
+    @property
     def rhslen(self) -> int:
         return int(sum(int(v) for v in (self.m if self.kind == GABP_BATCH_BIPARTITE else self.k)))
 
@@ -495,7 +521,12 @@ class DeviceBatch:
     def c(self) -> _Batch:
         def p(a):
             return None if a is None else a.ctypes.data_as(C.c_void_p)
-        return _Batch(self.kind, self.count, p(self.k), p(self.m), p(self.sigma2), _ptr(self.mat))
+        if self.csr is not None:
+            self._csr_c = self.csr.c()  # kept alive with the batch struct
+            cp = C.cast(C.pointer(self._csr_c), C.c_void_p)
+        else:
+            cp = None
+        return _Batch(self.kind, self.count, p(self.k), p(self.m), p(self.sigma2), _ptr(self.mat), cp)
 
 
 def _batch_stats(per_instance: bool, count: int):

@@ -363,6 +363,9 @@ void gabp_default_opts(gabp_opts *o) {
   o->adapt_damping = 1;
   o->schedule = GABP_SCHEDULE_SYNC;
   o->col_blocks = 0;
+  o->accel = GABP_ACCEL_NONE;
+  o->accel_stride = 0;
+  o->accel_cycle = 0;
 }
 
 int gabp_plan_destroy(gabp_plan *p) {
@@ -371,6 +374,7 @@ int gabp_plan_destroy(gabp_plan *p) {
   (void)hipDeviceSynchronize();
   delete p->eng;
   if (p->bat) batch_destroy(p->bat);
+  if (p->small) small_destroy(p->small);
   if (p->lsq) lsq_destroy(p->lsq);  // after the engine that reads its matrix
   if (p->perm) perm_destroy(p->perm);
   delete p;
@@ -381,6 +385,7 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
                     hipStream_t s) {
   clear_stale_error();
   if (p && p->bat) return batch_solve(p->bat, b, x, marg_prec, nullptr, st, s);
+  if (p && p->small) return small_solve(p->small, b, x, marg_prec, nullptr, st, s);
   if (!p || !p->eng) return GABP_ERR_ARG;
   if (p->perm) return perm_solve(p->perm, p->eng, b, x, marg_prec, st, s);
   return engine_solve(p->eng, b, x, marg_prec, st, s);
@@ -389,6 +394,7 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
 int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
   clear_stale_error();
   if (p && p->bat) return batch_reset(p->bat, b, s);
+  if (p && p->small) return small_reset(p->small, b, s);
   if (!p || !p->eng || (p->eng->n > 0 && !b)) return GABP_ERR_ARG;
   if (p->eng->n == 0) return GABP_OK;
   if (p->perm && !(b = perm_in(p->perm, b, s))) return GABP_ERR_HIP;
@@ -401,6 +407,7 @@ int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
 int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
   clear_stale_error();
   if (p && p->bat) return batch_sweeps(p->bat, count, s);
+  if (p && p->small) return small_sweeps(p->small, count, s);
   if (!p || !p->eng || count < 0) return GABP_ERR_ARG;
   Engine *e = p->eng;
   if (e->frozen) return GABP_ERR_ARG;  // trajectory access needs the full state (reset first)
@@ -412,6 +419,7 @@ int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
 int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s) {
   clear_stale_error();
   if (p && p->bat) return batch_marginals(p->bat, mean, prec, s);
+  if (p && p->small) return small_marginals(p->small, mean, prec, s);
   if (!p || !p->eng || (p->eng->n > 0 && !mean)) return GABP_ERR_ARG;
   if (p->eng->n == 0) return GABP_OK;
   if (p->perm) return perm_marginals(p->perm, p->eng, mean, prec, s);
@@ -423,6 +431,7 @@ int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s)
 
 int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
   clear_stale_error();
+  if (p && p->small) return small_messages(p->small, P, h, false, s);
   if (p && (p->bat || p->perm)) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
   return p->eng->get_messages(P, h, s);
@@ -430,6 +439,8 @@ int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
 
 int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipStream_t s) {
   clear_stale_error();
+  if (p && p->small)
+    return small_messages(p->small, const_cast<double *>(P), const_cast<double *>(h), true, s);
   if (p && (p->bat || p->perm)) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
   return p->eng->set_messages(P, h, s);
@@ -437,6 +448,7 @@ int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipSt
 
 int gabp_plan_colors(gabp_plan *p, int32_t *colors, int32_t *ncolors, hipStream_t s) {
   clear_stale_error();
+  if (p && p->small) return small_colors(p->small, colors, ncolors, s);
   if (!p || !p->eng) return GABP_ERR_ARG;
   if (p->perm) return perm_colors(p->perm, colors, ncolors, s);
   if (p->lsq && lsq_coloured(p->lsq)) return lsq_colors(p->lsq, colors, ncolors, s);

@@ -149,6 +149,18 @@ int batch_reset(BatchEngine *e, const double *b, hipStream_t s);
 int batch_sweeps(BatchEngine *e, int count, hipStream_t s);
 int batch_marginals(BatchEngine *e, double *mean, double *prec, hipStream_t s);
 
+// batches of small sparse instances, one workgroup each (engine_small.cpp)
+struct SmallEngine;
+int small_create(const gabp_batch *B, const gabp_opts *o, SmallEngine **out, hipStream_t s);
+void small_destroy(SmallEngine *e);
+int small_solve(SmallEngine *e, const double *b, double *x, double *marg_prec, gabp_stats *per,
+                gabp_stats *summary, hipStream_t s);
+int small_reset(SmallEngine *e, const double *b, hipStream_t s);
+int small_sweeps(SmallEngine *e, int count, hipStream_t s);
+int small_marginals(SmallEngine *e, double *mean, double *prec, hipStream_t s);
+int small_messages(SmallEngine *e, double *P, double *h, bool set, hipStream_t s);
+int small_colors(const SmallEngine *e, int32_t *colors, int32_t *ncolors, hipStream_t s);
+
 }  // namespace gabp
 
 namespace gabp {
@@ -172,12 +184,13 @@ int perm_colors(const CsrPerm *q, int32_t *colors, int32_t *ncolors, hipStream_t
 }  // namespace gabp
 
 // the opaque plan of the C ABI: one system (eng), a batch of dense instances
-// (bat); an lsq plan is a CSR system (eng) over its own assembled matrix (lsq);
+// (bat), a batch of small sparse instances (small); an lsq plan is a CSR system (eng) over its own assembled matrix (lsq);
 // a coloured CSR plan runs on a colour-sorted renumbering of the caller's
 // matrix (perm)
 struct gabp_plan {
   gabp::Engine *eng = nullptr;
   gabp::BatchEngine *bat = nullptr;
+  gabp::SmallEngine *small = nullptr;
   gabp::LsqSystem *lsq = nullptr;
   gabp::CsrPerm *perm = nullptr;
 };

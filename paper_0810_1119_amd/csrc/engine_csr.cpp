@@ -46,8 +46,14 @@ int check_opts(const gabp_opts *o) {
       (o->group != 0 && !valid_group(o->group)) || o->grid_blocks < 0 ||
       (o->layout != GABP_LAYOUT_PAIR && o->layout != GABP_LAYOUT_GATHER) ||
       (o->schedule != GABP_SCHEDULE_SYNC && o->schedule != GABP_SCHEDULE_COLORED) ||
-      o->col_blocks < 0 || o->col_blocks > 2)
+      o->col_blocks < 0 || o->col_blocks > 2 || o->accel < GABP_ACCEL_NONE ||
+      o->accel > GABP_ACCEL_STEFFENSEN || o->accel_stride < 0 || o->accel_cycle < 0)
     return GABP_ERR_ARG;
+  if (o->accel == GABP_ACCEL_STEFFENSEN) {
+    const int stride = o->accel_stride ? o->accel_stride : 2;
+    const int cycle = o->accel_cycle ? o->accel_cycle : 100;
+    if (cycle < 2 * stride) return GABP_ERR_ARG;
+  }
   return GABP_OK;
 }
 
@@ -411,6 +417,7 @@ int csr_plan_create(const gabp_csr *A, const gabp_opts *o, const std::vector<int
   int st = check_csr(A);
   if (st) return st;
   if ((st = check_opts(&opts))) return st;
+  if (opts.accel != GABP_ACCEL_NONE) return GABP_ERR_UNSUPPORTED;  // small CSR batches only
   if ((opts.schedule != GABP_SCHEDULE_SYNC) != (classes != nullptr)) return GABP_ERR_UNSUPPORTED;
   if (classes && opts.layout != GABP_LAYOUT_PAIR) return GABP_ERR_UNSUPPORTED;
   if (opts.col_blocks == 2 && (classes || opts.layout != GABP_LAYOUT_PAIR))

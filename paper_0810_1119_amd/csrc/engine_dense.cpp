@@ -194,6 +194,7 @@ int batch_create(const gabp_batch *B, const gabp_opts *o, BatchEngine **out, hip
   int st = check_batch(B);
   if (st) return st;
   if (o && (st = check_opts(o))) return st;
+  if (o && o->accel != GABP_ACCEL_NONE) return GABP_ERR_UNSUPPORTED;  // small CSR batches only
   // the two-colour schedule needs a two-colourable graph: the bipartite kind
   if (o && o->schedule != GABP_SCHEDULE_SYNC && B->kind != GABP_BATCH_BIPARTITE)
     return GABP_ERR_UNSUPPORTED;
@@ -429,6 +430,15 @@ int gabp_plan_create_batched(const gabp_batch *B, const gabp_opts *o, gabp_plan 
   clear_stale_error();
   if (!plan) return GABP_ERR_ARG;
   *plan = nullptr;
+  if (B && B->kind == GABP_BATCH_CSR) {
+    SmallEngine *q = nullptr;
+    const int st = small_create(B, o, &q, s);
+    if (st) return st;
+    auto *p = new gabp_plan();
+    p->small = q;
+    *plan = p;
+    return GABP_OK;
+  }
   BatchEngine *e = nullptr;
   const int st = batch_create(B, o, &e, s);
   if (st) return st;
@@ -441,6 +451,7 @@ int gabp_plan_create_batched(const gabp_batch *B, const gabp_opts *o, gabp_plan 
 int gabp_plan_solve_batched(gabp_plan *p, const double *b, double *x, gabp_stats *per,
                             gabp_stats *summary, hipStream_t s) {
   clear_stale_error();
+  if (p && p->small) return small_solve(p->small, b, x, nullptr, per, summary, s);
   if (!p || !p->bat) return GABP_ERR_ARG;
   return batch_solve(p->bat, b, x, nullptr, per, summary, s);
 }
@@ -448,6 +459,14 @@ int gabp_plan_solve_batched(gabp_plan *p, const double *b, double *x, gabp_stats
 int gabp_solve_batched(const gabp_batch *B, const double *b, double *x, const gabp_opts *o,
                        gabp_stats *per, gabp_stats *summary, hipStream_t s) {
   clear_stale_error();
+  if (B && B->kind == GABP_BATCH_CSR) {
+    SmallEngine *q = nullptr;
+    int st = small_create(B, o, &q, s);
+    if (st) return st;
+    st = small_solve(q, b, x, nullptr, per, summary, s);
+    small_destroy(q);
+    return st;
+  }
   BatchEngine *e = nullptr;
   int st = batch_create(B, o, &e, s);
   if (st) return st;

@@ -331,6 +331,7 @@ int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **pl
   else gabp_default_opts(&opts);
   int st;
   if ((st = check_opts(&opts))) return st;
+  if (opts.accel != GABP_ACCEL_NONE) return GABP_ERR_UNSUPPORTED;  // small CSR batches only
   GridGeom g{};
   if ((st = check_grid(A, &g))) return st;
   const bool coloured = opts.schedule == GABP_SCHEDULE_COLORED;

@@ -510,6 +510,65 @@ hipError_t launch_dense_prepare(const DenseArgs &a, uint32_t *flags, hipStream_t
 hipError_t launch_dense_marginals(const DenseArgs &a, double *mean, double *prec, bool all,
                                   hipStream_t s);
 
+// ---- small sparse systems, one workgroup each (kernels_small.hip) ----
+struct SmallInst {
+  int32_t n;      // rows of the instance
+  int32_t node0;  // its first row in the block-diagonal matrix
+  int32_t slot0;  // its first in-slot
+  int32_t E;      // in-slots (directed edges)
+  int32_t ncol;   // colours (coloured schedule)
+  int32_t pad;
+};
+struct SmallStat {
+  int32_t status, sweeps, restarts, checks;
+  double rel;    // final relative residual (FP64)
+  double rnorm;  // final ||r||_2
+};
+enum { SMALL_SOLVE = 0, SMALL_RESET = 1, SMALL_SWEEPS = 2 };
+struct SmallArgs {
+  int mode;              // SMALL_*
+  bool fp32;
+  bool colored;          // serial scheme in colour order
+  int rows_per_thread;   // 1 or 4
+  bool cache;            // rows_per_thread == 1 and degree <= 8: slot data in registers
+  int threads, grid;     // workgroup size and workgroups of the persistent launch
+  int count;
+  const SmallInst *inst;
+  const int32_t *order;  // queue: instance indices, largest first
+  uint32_t *queue;       // next queue position (zeroed before the launch)
+  int emax, nmax;        // LDS capacity: largest in-slot and row counts
+  const int64_t *rp;     // the caller's block-diagonal CSR (FP64 residual)
+  const int32_t *col;
+  const double *val;
+  const int32_t *soff;   // [N + 1] in-slot offsets of the rows
+  const int32_t *rev;    // [E] in-slot of the reverse message
+  const void *acoef;     // [E] coupling A_ij of in-slot (i <- j), message precision
+  const void *diagT;     // [N] A_ii, message precision
+  const int32_t *color;  // [N] colour of each row (coloured schedule) or NULL
+  const double *b;
+  double *x;
+  void *msg;             // [E] (P, h) per in-slot: the state after a kernel run
+  void *rhsT;            // [N] right-hand side of the current pass
+  SmallStat *stat;
+  double *hist;          // [6][nodes] FP64 sample history of the solve
+  int nodes;             // rows of the whole batch
+  double tol, alpha, inner_tol, floor;
+  int max_sweeps, max_restarts, check_every;
+  int accel, stride, cycle;  // GABP_ACCEL_*, samples every stride sweeps, Steffensen cycle
+  int nsweeps;           // SMALL_SWEEPS
+};
+size_t small_lds(const SmallArgs &a);
+int small_occupancy(const SmallArgs &a);  // workgroups per compute unit (0: cannot launch)
+hipError_t launch_small_batch(const SmallArgs &a, hipStream_t s);
+hipError_t launch_small_marginals(const SmallArgs &a, int N, double *mean, double *prec,
+                                  hipStream_t s);
+// P, h per CSR position of the caller's matrix (diagonal: 0); set: store them
+hipError_t launch_small_messages(const SmallArgs &a, int N, double *P, double *h, bool set,
+                                 hipStream_t s);
+// FLAG_ARG if a row has a column outside its instance (node_off: count + 1)
+hipError_t launch_small_blocks(int N, int count, const int32_t *node_off, const int64_t *rp,
+                               const int32_t *col, uint32_t *flags, hipStream_t s);
+
 // ---- warm-start network (kernels_mlp.hip) ----
 struct MlpTrainArgs {
   const uint16_t *w;            // bfloat16 parameters used by the passes

@@ -53,3 +53,14 @@ def test_committed_traffic_matches_the_sources():
         src = os.path.join(bench.ROOT, "paper_0810_1119_amd", "csrc", rec["source"])
         assert os.path.exists(src), name
         assert rec["bytes_per_launch"] > 0
+
+
+def test_headline_bytes_follow_the_measurement_unit():
+    """The C4 full sweep is priced at 18 B per directed edge + 8 B per node:
+    about 1.92 GB per sweep of the 64 grids of 64^3 (99,090,432 directed
+    edges, 16,777,216 nodes)."""
+    n, count = 64, 64
+    E = 2 * 3 * (n - 1) * n * n * count
+    N = n ** 3 * count
+    assert E == 99_090_432
+    assert bench.c4_full_bytes_per_sweep(N, E) == pytest.approx(1.9179e9, rel=1e-4)
