@@ -64,6 +64,8 @@ def parse():
                          "colours, one launch each: 14 instead of 20 sweeps at the same time)")
     ap.add_argument("--accel", choices=["none", "aitken", "steffensen"], default=None,
                     help="c1: acceleration of the means (default aitken)")
+    ap.add_argument("--stride", type=int, default=0,
+                    help="c1: sweeps between Aitken samples (0 = 2)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte "
                          "counters) and print its bandwidth")
@@ -471,7 +473,7 @@ def bench_c1(args, G, W, torch, dev):
     colored = (args.schedule or "colored") == "colored"
     opts = G.gabp_default_opts(msg_fp32=0, tol=1e-10, max_sweeps=100000,
                                schedule=G.GABP_SCHEDULE_COLORED if colored else G.GABP_SCHEDULE_SYNC,
-                               accel=accel, accel_stride=1 if colored else 2)
+                               accel=accel, accel_stride=args.stride or 2)
     if args.check_every:
         opts.check_every = args.check_every
     torch.cuda.synchronize()
@@ -554,30 +556,44 @@ def c4_full_bytes_per_sweep(N: int, E: int) -> float:
     return 18.0 * E + 8.0 * N
 
 
-def oracle_grid_reference(seed: int, t: int, n: int, b_stack, tol=1e-11, max_rounds=40000):
-    """The FP64 oracle (synchronous Algorithm 2 from zero messages, OpenMP over
-    rows) on grid t of the stack alone: its solution and how long it took.
-    Inputs come from the seeded generators (b_stack: the host right-hand side of
-    the whole stack)."""
+def oracle_grid_reference(seed: int, t: int, n: int, b_stack, tol=1e-9, max_rounds=20000,
+                          check=50):
+    """The FP64 oracle on grid t of the stack alone: its rounds in the
+    red-black order the GPU runs (the serial scheme, colour (x + y + z) & 1,
+    colour 0 first) from zero messages, the FP64 residual every `check`
+    rounds, until it is <= tol.  Inputs come from the seeded generators
+    (b_stack: the host right-hand side of the whole stack)."""
     import oracle
     import workloads as W
     csr, _ = W.grid_stack(n, n, n, 1, varcoef=True, seed=seed + t, with_csr=True)
     nn = n ** 3
     b = np.ascontiguousarray(b_stack[t * nn:(t + 1) * nn])
+    i = np.arange(nn)
+    colors = ((i % n + (i // n) % n + i // (n * n)) & 1).astype(np.int8)
+    bn = np.linalg.norm(b)
+    R = oracle.Rounds(csr, b, algorithm=2, colors=colors)
     t0 = time.perf_counter()
-    r = oracle.solve(csr, b, algorithm=2, tol=tol, max_rounds=max_rounds)
+    rounds, rel, hit = 0, np.inf, None
+    while rounds < max_rounds:
+        R.step(check)
+        rounds += check
+        x = R.marginals()[0]
+        rel = oracle.residual(csr, b, x)[1] / bn
+        if hit is None and rel <= 1e-8:
+            hit = rounds
+        if rel <= tol:
+            break
     dt = time.perf_counter() - t0
-    hit = np.nonzero(r.trace <= 1e-8)[0]
-    return {"x": r.x, "status": r.status, "rounds": r.rounds, "seconds": dt,
-            "rel_residual": float(r.trace[-1]), "edges": int(csr.nnz - csr.n),
-            "rounds_to_1e-8": int(hit[0]) if hit.size else None, "csr": csr, "b": b}
+    return {"x": x, "rounds": rounds, "seconds": dt, "rel_residual": float(rel),
+            "edges": int(csr.nnz - csr.n), "rounds_to_1e-8": hit}
 
 
 def bench_c4(args, G, W, torch, dev):
     """64 variable-coefficient grids of 64^3 (held out from the warm start's
-    training grids) solved to 1e-8 from zero messages (plain) and from the
-    trained network's messages (warm).  One step = one plain and one warm
-    solve of the whole stack; value = messages computed per second over both."""
+    training grids) solved to 1e-8 from zero messages (plain), from the
+    trained network's messages (warm) and with coarse-grid predicted
+    corrections (coarse).  One step = the three solves of the whole stack;
+    value = messages computed per second over them."""
     from paper_0810_1119_amd import warmstart as WS
     n, count = 64, 64
     nn = n ** 3
@@ -601,25 +617,29 @@ def bench_c4(args, G, W, torch, dev):
         raise SystemExit(f"plan_create_grid: {G.status_name(rc)}")
     xp = torch.zeros(N, dtype=torch.float64, device=dev)
     xw = torch.zeros(N, dtype=torch.float64, device=dev)
+    xc = torch.zeros(N, dtype=torch.float64, device=dev)
+    kinds = ("plain", "warm", "coarse")
 
     def solve(kind):
         if kind == "plain":
             rc, st = G.gabp_plan_solve(plan, b, xp)
-        else:
+        elif kind == "warm":
             rc, st = G.gabp_plan_solve_warm(plan, model, b, xw)
+        else:
+            rc, st = G.gabp_plan_solve_coarse(plan, b, xc)
         if rc != G.GABP_OK:
             raise SystemExit(f"{kind} solve: {G.status_name(rc)}")
         return st
 
     for _ in range(args.warmup):
-        solve("plain")
-        solve("warm")
-    res = {"plain": [], "warm": []}
-    wall = {"plain": 0.0, "warm": 0.0}
+        for kind in kinds:
+            solve(kind)
+    res = {k: [] for k in kinds}
+    wall = {k: 0.0 for k in kinds}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        for kind in ("plain", "warm"):
+        for kind in kinds:
             t1 = time.perf_counter()  # each solve returns once its results are complete
             res[kind].append(solve(kind))
             wall[kind] += time.perf_counter() - t1
@@ -629,17 +649,18 @@ def bench_c4(args, G, W, torch, dev):
     K = args.steps
     # each grid's own FP64 residual, recomputed one grid at a time outside the timing
     worst = {}
-    for kind, xv in (("plain", xp), ("warm", xw)):
+    for kind, xv in (("plain", xp), ("warm", xw), ("coarse", xc)):
         w = 0.0
         for t in range(count):
             sl = slice(t * nn, (t + 1) * nn)
             At = G.DeviceGrid(n, n, n, 1, diag=A.diag[sl], cx=A.cx[sl], cy=A.cy[sl], cz=A.cz[sl])
             w = max(w, G.gabp_residual_grid(At, b[sl], xv[sl])[1])
         worst[kind] = w
-    runs, wruns = res["plain"], res["warm"]
+    runs, wruns, cruns = res["plain"], res["warm"], res["coarse"]
     # messages computed: with the red-black schedule each grid leaves the
-    # sweeps once it meets its own target, so sweeps are counted per grid
-    msgs = E * sum(st.mean_sweeps for st in runs + wruns)
+    # sweeps once it meets its own target, so sweeps are counted per grid;
+    # the coarse solve's sweeps on the coarser grids add 1/7 at most
+    msgs = E * sum(st.mean_sweeps for st in runs + wruns + cruns)
     full_grid = sum(st.mean_sweeps - st.mean_frozen_sweeps for st in runs + wruns)
     settled_grid = sum(st.mean_frozen_sweeps for st in runs + wruns)
     # full (P, h) sweep kernel: every grid sweeps (the precisions settle long
@@ -661,7 +682,7 @@ def bench_c4(args, G, W, torch, dev):
     fz_bpl = grid_bytes_per_sweep(N, E, True, False, c_eff) / per * grid_frozen / max(frozen, 1)
     fz_avg_s = fz_ms * 1e-3 / fz_launches
     fz_gbs = fz_bpl / fz_avg_s / 1e9
-    tp, tw = wall["plain"] / K, wall["warm"] / K
+    tp, tw, tc = wall["plain"] / K, wall["warm"] / K, wall["coarse"] / K
     out = {
         "metric": "GaBP edge-updates/s; time to rel. residual 1e-8, warm start vs plain",
         "value": msgs / dt, "unit": "edge-updates/s",
@@ -675,11 +696,17 @@ def bench_c4(args, G, W, torch, dev):
                         "faces, Dirichlet 0), b ~ N(0,1); FP32 messages + FP64 refinement to "
                         "1e-8 per grid; grids held out from the warm start's 512 training grids; "
                         f"{'red-black (serial-like)' if per == 2 else 'synchronous'} schedule; "
-                        "one step = one plain and one warm-started solve of the stack",
+                        "one step = one plain solve, one started from the learned network's "
+                        "messages and one with coarse-grid predicted corrections",
             "grids": count, "n": N, "directed_edges": E, "seed": args.seed,
             "time_to_1e-8_ms_plain": tp * 1e3,
             "time_to_1e-8_ms_warm": tw * 1e3,
             "warm_speedup": tp / tw,
+            "time_to_1e-8_ms_coarse": tc * 1e3,
+            "coarse_speedup": tp / tc,
+            "coarse_corrections": sum(st.restarts for st in cruns) / K,
+            "coarse_sweeps_finest_grid": sum(st.sweeps for st in cruns) / K,
+            "rel_residual_worst_grid_coarse": worst["coarse"],
             "sweeps_slowest_grid_plain": sum(st.sweeps for st in runs) / K,
             "sweeps_slowest_grid_warm": sum(st.sweeps for st in wruns) / K,
             "mean_sweeps_per_grid_plain": sum(st.mean_sweeps for st in runs) / K,
@@ -718,7 +745,7 @@ def bench_c4(args, G, W, torch, dev):
     if not args.no_cpu_baseline:
         ref = oracle_grid_reference(args.seed, 0, n, W.normal_b(N, args.seed))
         errs = {}
-        for kind, xv in (("plain", xp), ("warm", xw)):
+        for kind, xv in (("plain", xp), ("warm", xw), ("coarse", xc)):
             xg = xv[:nn].cpu().numpy()
             errs[kind] = {"rel_l2": float(np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"])),
                           "max_abs": float(np.abs(xg - ref["x"]).max())}
@@ -729,9 +756,9 @@ def bench_c4(args, G, W, torch, dev):
         out["cpu_baseline"] = {
             "value": ref["edges"] * ref["rounds"] / ref["seconds"], "unit": "edge-updates/s",
             "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"grid 0 of the stack solved alone by the FP64 oracle (synchronous "
-                      f"Algorithm 2 from zero messages, OpenMP over rows): {ref['rounds']} rounds "
-                      f"to rel. residual {ref['rel_residual']:.1e} in {ref['seconds']:.1f} s"
+            "sample": f"grid 0 of the stack solved alone by the FP64 oracle (Algorithm 2 in "
+                      f"red-black order from zero messages, OpenMP over rows): {ref['rounds']} "
+                      f"rounds to rel. residual {ref['rel_residual']:.1e} in {ref['seconds']:.1f} s"
                       + (f"; 1e-8 after {rt} rounds, about "
                          f"{ref['seconds'] * rt / ref['rounds']:.1f} s for one grid"
                          if rt else ""),

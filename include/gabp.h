@@ -512,6 +512,35 @@ int gabp_model_grid_targets(const gabp_grid *A, const double *P, const double *h
 int gabp_plan_solve_warm(gabp_plan *plan, const gabp_model *model, const double *b, double *x,
                          double *marg_prec, gabp_stats *st, hipStream_t stream);
 
+/* ---- Coarse-grid predicted corrections for grid solves (not part of the
+ * paper; a predictor from beyond a node's neighbourhood) --------------------
+ * GaBP reduces the smooth part of the error slowly: on a Poisson operator it
+ * converges like a relaxation whose slowest modes are the smoothest, and the
+ * information messages that would remove them are globally determined, so no
+ * initial messages computed from a node's own neighbourhood can supply them.
+ * This solve predicts every correction of the refinement loop on coarser
+ * grids.  With r = b - A x (FP64), the correction d of A d = r is
+ *   d  = means of 4 GaBP sweeps on r (the plan's schedule and message
+ *        precision, zero information messages, the precision messages of the
+ *        level's previous sweeps kept);
+ *   d += 1.8 P d_c, where d_c is the same procedure applied on the next coarser
+ *        grid to the right-hand side P^T (r - A d), P the 2 x 2 x 2 block
+ *        indicator (an axis of extent 1 is not halved) and the coarse operator
+ *        the Galerkin product P^T A P (again a 5/7-point stencil), recursively
+ *        down to grids of at most 64 cells, where d_c is the means of 24 sweeps;
+ *   d += means of 4 GaBP sweeps on r - A d;
+ * then x += d, until every grid of the stack meets tol (each grid's own
+ * ||b_t - A_t x_t|| / ||b_t||).  The sweeps use the plan's damping, except
+ * that an undamped synchronous plan sweeps with damping 0.3 here: undamped
+ * synchronous sweeps leave the error mode that alternates between the two
+ * colours of a grid, and the cycle diverges.  The coarse levels are built on the first call
+ * and kept with the plan (about 1/7 of the plan's memory).  Grid plans only
+ * (GABP_ERR_UNSUPPORTED otherwise); st->restarts counts the corrections
+ * (at most opts.max_restarts), st->sweeps the sweeps on the plan's own grid.
+ * Arguments as for gabp_plan_solve. */
+int gabp_plan_solve_coarse(gabp_plan *plan, const double *b, double *x, double *marg_prec,
+                           gabp_stats *st, hipStream_t stream);
+
 /* Library version string. */
 const char *gabp_version(void);
 

@@ -23,7 +23,7 @@ from ._abi import (  # noqa: F401
     GABP_MODEL_INPUTS, GABP_MODEL_OUTPUTS, GABP_MODEL_PARAMS, Model,
     gabp_model_create, gabp_model_get_params, gabp_model_set_params, gabp_model_forward,
     gabp_model_grad, gabp_model_train_step, gabp_model_grid_features, gabp_model_grid_targets,
-    gabp_plan_solve_warm,
+    gabp_plan_solve_warm, gabp_plan_solve_coarse,
     gabp_plan_colors, DeviceRect, gabp_plan_create_lsq, gabp_plan_solve_lsq, gabp_solve_lsq,
     gabp_plan_residual_lsq,
 )

@@ -137,6 +137,7 @@ _sig = {
     "gabp_model_grid_features": (C.c_int, [C.c_void_p, _vp, _vp, C.c_int64, _vp, _vp]),
     "gabp_model_grid_targets": (C.c_int, [C.c_void_p, _vp, _vp, _vp, C.c_int64, _vp, _vp]),
     "gabp_plan_solve_warm": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.POINTER(Stats), _vp]),
+    "gabp_plan_solve_coarse": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(Stats), _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)
@@ -673,4 +674,15 @@ def gabp_plan_solve_warm(plan, model: Model, b, x, marg_prec=None, stream=None):
     st = Stats()
     rc = lib.gabp_plan_solve_warm(plan.ptr, model.ptr, _ptr(b), _ptr(x), _ptr(marg_prec),
                                   C.byref(st), _stream(stream))
+    return rc, st
+
+
+def gabp_plan_solve_coarse(plan, b, x, marg_prec=None, stream=None):
+    """Grid plans: the solve with coarse-grid predicted corrections.
+    Returns (status, Stats)."""
+    nb, nx, _ = _lens(plan)
+    _check_f64(b, nb, "b"); _check_f64(x, nx, "x"); _check_f64(marg_prec, nx, "marg_prec")
+    st = Stats()
+    rc = lib.gabp_plan_solve_coarse(plan.ptr, _ptr(b), _ptr(x), _ptr(marg_prec), C.byref(st),
+                                    _stream(stream))
     return rc, st

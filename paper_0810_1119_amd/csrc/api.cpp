@@ -372,6 +372,7 @@ int gabp_plan_destroy(gabp_plan *p) {
   clear_stale_error();
   if (!p) return GABP_ERR_ARG;
   (void)hipDeviceSynchronize();
+  if (p->coarse) coarse_destroy(p->coarse);  // its levels refer to the engine
   delete p->eng;
   if (p->bat) batch_destroy(p->bat);
   if (p->small) small_destroy(p->small);

@@ -149,6 +149,12 @@ int batch_reset(BatchEngine *e, const double *b, hipStream_t s);
 int batch_sweeps(BatchEngine *e, int count, hipStream_t s);
 int batch_marginals(BatchEngine *e, double *mean, double *prec, hipStream_t s);
 
+// coarse-grid predicted corrections of grid plans (engine_grid.cpp)
+struct CoarseHierarchy;
+void coarse_destroy(CoarseHierarchy *h);
+int coarse_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
+                 hipStream_t s);
+
 // batches of small sparse instances, one workgroup each (engine_small.cpp)
 struct SmallEngine;
 int small_create(const gabp_batch *B, const gabp_opts *o, SmallEngine **out, hipStream_t s);
@@ -191,6 +197,7 @@ struct gabp_plan {
   gabp::Engine *eng = nullptr;
   gabp::BatchEngine *bat = nullptr;
   gabp::SmallEngine *small = nullptr;
+  gabp::CoarseHierarchy *coarse = nullptr;  // grid plans: coarse levels, built on first use
   gabp::LsqSystem *lsq = nullptr;
   gabp::CsrPerm *perm = nullptr;
 };

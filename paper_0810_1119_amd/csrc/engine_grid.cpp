@@ -1,6 +1,7 @@
 // Structured grids: 5-point / 7-point stencils with constant or variable
 // coefficients, batched along z.  Messages live in six direction-major
 // arrays; see kernels_grid.hip.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -316,6 +317,220 @@ struct RbGridEngine : GridEngine {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Coarse-grid predicted corrections.  GaBP removes the smooth part of the
+// error slowly (it behaves like a relaxation on the low modes of a Poisson
+// operator), and no initial messages computed from a node's own neighbourhood
+// can supply it.  Here every correction d of A d = r (r = b - A x) is
+// predicted on coarser grids: a few GaBP sweeps on r (zero information
+// messages, precisions of the level's previous sweeps kept) give d; the
+// residual of d, summed over 2 x 2 x 2 blocks, is the right-hand side of the
+// same procedure on the Galerkin operator of the next coarser grid, down to a
+// grid of at most 64 cells; the coarse correction, injected back and scaled,
+// is added; a few more GaBP sweeps on the remaining residual finish d.  Then
+// x += d, until every grid of the stack meets the tolerance.
+// ---------------------------------------------------------------------------
+constexpr int kCoarsePre = 4, kCoarsePost = 4, kCoarseSweeps = 24, kCoarseMaxCells = 64;
+// Synchronous sweeps on a grid (a bipartite graph) do not damp the error mode
+// that alternates between the two colours, so as a smoother they need
+// damping: an undamped synchronous plan smooths with this factor (the FP64
+// oracle diverges without it and takes 11-13 corrections with it on
+// 16^3 - 24^3 grids); the coloured schedule smooths with the plan's own.
+constexpr double kCoarseSyncDamping = 0.3;
+// Injection of a block's correction into its cells under-corrects smooth
+// error (the coarse operator of piecewise constants is too stiff by about a
+// factor of two); the scale was chosen with the FP64 oracle on
+// variable-coefficient grids of 16^3 to 32^3.
+constexpr double kCoarseScale = 1.8;
+
+struct CoarseHierarchy {
+  struct Level {
+    gabp_plan *plan = nullptr;  // levels >= 1 (level 0 is the caller's plan)
+    Engine *eng = nullptr;
+    GridGeom g{};
+    double *dg = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;  // levels >= 1
+    double *v = nullptr, *d = nullptr, *t = nullptr;  // right-hand side, correction, residual
+    bool fresh = true;  // messages not yet set in this solve
+  };
+  std::vector<Level> lv;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  ~CoarseHierarchy() {
+    for (Level &L : lv) {
+      if (L.plan) gabp_plan_destroy(L.plan);
+      double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.t};
+      for (double *b : bufs)
+        if (b) (void)hipFree(b);
+    }
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+
+  double damping = 0.0;  // of every level's sweeps
+
+  int build(GridEngine *e0, hipStream_t s) {
+    damping = e0->o.damping;
+    if (e0->o.schedule == GABP_SCHEDULE_SYNC && damping == 0.0) damping = kCoarseSyncDamping;
+    TRY_HIP(hipEventCreate(&ev0));
+    TRY_HIP(hipEventCreate(&ev1));
+    Level L0;
+    L0.eng = e0;
+    L0.g = e0->g;
+    lv.push_back(L0);
+    GridCoef<double> k = e0->k64;
+    bool varc = e0->varc;
+    for (;;) {
+      Level &F = lv.back();
+      TRY_HIP(dalloc(&F.v, F.g.N, sizeof(double)));
+      TRY_HIP(dalloc(&F.d, F.g.N, sizeof(double)));
+      TRY_HIP(dalloc(&F.t, F.g.N, sizeof(double)));
+      if ((int64_t)F.g.nx * F.g.ny * F.g.nz <= kCoarseMaxCells) break;
+      Level C;
+      C.g = coarse_geom(F.g);
+      const GridGeom fg = F.g;  // F may move when lv grows
+      TRY_HIP(dalloc(&C.dg, C.g.N, sizeof(double)));
+      TRY_HIP(dalloc(&C.cx, C.g.N, sizeof(double)));
+      TRY_HIP(dalloc(&C.cy, C.g.N, sizeof(double)));
+      TRY_HIP(dalloc(&C.cz, C.g.N, sizeof(double)));
+      TRY_HIP(launch_coarse_coef(fg, k, varc, C.g, C.dg, C.cx, C.cy, C.cz, s));
+      gabp_grid Ag{};
+      Ag.nx = C.g.nx; Ag.ny = C.g.ny; Ag.nz = C.g.nz; Ag.batch = C.g.batch;
+      Ag.diag = C.dg; Ag.cx = C.cx; Ag.cy = C.cy; Ag.cz = C.cz;
+      gabp_opts o = e0->o;
+      o.damping = damping;
+      lv.push_back(C);  // owned from here on (freed by the destructor)
+      const int rc = gabp_plan_create_grid(&Ag, &o, &lv.back().plan, s);
+      if (rc) return rc;
+      lv.back().eng = lv.back().plan->eng;
+      k = GridCoef<double>{C.dg, C.cx, C.cy, C.cz, 0.0, 0.0};
+      varc = true;
+    }
+    TRY_HIP(hipStreamSynchronize(s));
+    return GABP_OK;
+  }
+
+  // d_l += the means of `sweeps` GaBP sweeps on right-hand side v (NULL: the
+  // engine already holds it), from zero information messages
+  int smooth(int l, const double *v, int sweeps, hipStream_t s) {
+    Level &L = lv[l];
+    if (v && L.fresh) {
+      TRY_HIP(L.eng->reset(v, s));
+      L.fresh = false;
+    } else {
+      if (v) TRY_HIP(L.eng->residual(v, nullptr, nullptr, s));
+      TRY_HIP(L.eng->restart(s));
+    }
+    for (int k = 0; k < sweeps; ++k) TRY_HIP(L.eng->sweep(0, nullptr, s));
+    TRY_HIP(L.eng->infer(L.d, nullptr, nullptr, s));
+    return GABP_OK;
+  }
+
+  // d_l from v_l: smoothing, coarse prediction, smoothing
+  int cycle(int l, hipStream_t s) {
+    Level &L = lv[l];
+    TRY_HIP(launch_fill_zero(L.d, L.g.N, s));
+    if (l + 1 == (int)lv.size()) return smooth(l, L.v, kCoarseSweeps, s);
+    int rc = smooth(l, L.v, kCoarsePre, s);
+    if (rc) return rc;
+    Level &C = lv[l + 1];
+    TRY_HIP(L.eng->residual(L.v, L.d, L.t, s));
+    TRY_HIP(launch_coarse_restrict(L.g, C.g, L.t, C.v, s));
+    if ((rc = cycle(l + 1, s))) return rc;
+    TRY_HIP(launch_coarse_prolong(L.g, C.g, C.d, kCoarseScale, L.d, s));
+    if (kCoarsePost > 0) {
+      TRY_HIP(L.eng->residual(L.v, L.d, L.t, s));
+      if ((rc = smooth(l, nullptr, kCoarsePost, s))) return rc;
+    }
+    return GABP_OK;
+  }
+};
+
+void coarse_destroy(CoarseHierarchy *h) { delete h; }
+
+int coarse_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
+                 hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  GridEngine *e0 = p ? dynamic_cast<GridEngine *>(p->eng) : nullptr;
+  if (!e0) return GABP_ERR_UNSUPPORTED;
+  if (e0->n > 0 && (!b || !x)) return GABP_ERR_ARG;
+  gabp_stats stats{};
+  stats.edges = e0->E;
+  stats.sweep_launches = e0->sweep_launches();
+  stats.damping = e0->o.damping;
+  auto finish = [&](int status) {
+    stats.status = status;
+    stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats.mean_sweeps = stats.sweeps;
+    stats.edge_updates_per_s =
+        stats.seconds > 0 ? (double)stats.edges * stats.sweeps / stats.seconds : 0.0;
+    if (st) *st = stats;
+    return status;
+  };
+  if (!p->coarse) {
+    auto *h = new (std::nothrow) CoarseHierarchy();
+    if (!h) return GABP_ERR_NOMEM;
+    const int rc = h->build(e0, s);
+    if (rc) {
+      delete h;
+      return finish(rc);
+    }
+    p->coarse = h;
+  }
+  CoarseHierarchy &H = *p->coarse;
+  for (auto &L : H.lv) L.fresh = true;
+  // the plan's own sweeps smooth with the hierarchy's damping for this call
+  struct Restore {
+    GridEngine *e;
+    double d;
+    ~Restore() { e->o.damping = d; }
+  } restore{e0, e0->o.damping};
+  e0->o.damping = H.damping;
+  stats.damping = H.damping;
+  TRY_HIP(launch_fill_zero4(e0->sticky, 1, s));
+  TRY_HIP(launch_fill_zero(x, e0->n, s));
+  // ||b_t|| of every grid of the stack (kept by the engine for the norms below)
+  TRY_HIP(e0->reset(b, s));
+  HostReadout r0;
+  int rc = e0->read_sum(s, &r0, 1);
+  if (rc) return finish(rc);
+  if (!std::isfinite(r0.sum)) return finish(GABP_ERR_ARG);
+  const double bn = std::sqrt(r0.sum);
+  if (bn == 0.0) {
+    stats.rel_residual = 0.0;
+    return finish(GABP_OK);
+  }
+  int status = GABP_NOT_CONVERGED;
+  TRY_HIP(hipEventRecord(H.ev0, s));
+  for (int cyc = 0;; ++cyc) {
+    // r = b - A x (FP64) and the worst grid's relative residual
+    TRY_HIP(e0->residual(b, x, H.lv[0].v, s));
+    HostReadout rr;
+    if ((rc = e0->read_sum(s, &rr, 2, bn))) return finish(rc);
+    const double rel_all = std::sqrt(rr.sum) / bn;
+    const double rel = (e0->nseg > 1 && std::isfinite(rel_all)) ? rr.segrel : rel_all;
+    stats.rel_residual = rel;
+    stats.residual_per_eq = std::sqrt(rr.sum) / e0->n;
+    if (rr.flags & FLAG_BREAKDOWN) { status = GABP_ERR_BREAKDOWN; break; }
+    if ((rr.flags & FLAG_NONFINITE) || !std::isfinite(rel) || rel > 1e6) {
+      status = GABP_ERR_DIVERGED;
+      break;
+    }
+    if (rel <= e0->o.tol) { status = GABP_OK; break; }
+    if (cyc >= e0->o.max_restarts || stats.sweeps >= e0->o.max_sweeps) break;
+    if ((rc = H.cycle(0, s))) return finish(rc);
+    TRY_HIP(launch_axpy(e0->n, H.lv[0].d, x, s));
+    stats.sweeps += kCoarsePre + kCoarsePost;
+    stats.restarts = cyc + 1;
+  }
+  TRY_HIP(hipEventRecord(H.ev1, s));
+  if (marg_prec) TRY_HIP(e0->infer(nullptr, marg_prec, nullptr, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  float ms = 0.f;
+  TRY_HIP(hipEventElapsedTime(&ms, H.ev0, H.ev1));
+  stats.sweep_ms = ms;
+  return finish(status);
+}
+
 }  // namespace gabp
 
 using namespace gabp;
@@ -449,6 +664,13 @@ int gabp_residual_grid(const gabp_grid *A, const double *b, const double *x, dou
   const double bn = std::sqrt(host[0].sum), rn = std::sqrt(host[1].sum);
   *rel_norm = bn > 0 ? rn / bn : rn;
   return cleanup(std::isfinite(*rel_norm) ? GABP_OK : GABP_ERR_ARG);
+}
+
+int gabp_plan_solve_coarse(gabp_plan *p, const double *b, double *x, double *marg_prec,
+                           gabp_stats *st, hipStream_t s) {
+  clear_stale_error();
+  if (!p || !p->eng) return GABP_ERR_ARG;
+  return coarse_solve(p, b, x, marg_prec, st, s);
 }
 
 }  // extern "C"

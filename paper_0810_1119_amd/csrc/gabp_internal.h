@@ -569,6 +569,18 @@ hipError_t launch_small_messages(const SmallArgs &a, int N, double *P, double *h
 hipError_t launch_small_blocks(int N, int count, const int32_t *node_off, const int64_t *rp,
                                const int32_t *col, uint32_t *flags, hipStream_t s);
 
+// ---- coarse grids of a grid stack (kernels_coarse.hip) ----
+GridGeom coarse_geom(const GridGeom &f);  // 2 x 2 x 2 blocks (an axis of extent 1 stays)
+// Galerkin operator P^T A P of the aggregation, FP64 arrays in the grid layout
+hipError_t launch_coarse_coef(const GridGeom &f, const GridCoef<double> &k, bool varc,
+                              const GridGeom &c, double *dg, double *cx, double *cy, double *cz,
+                              hipStream_t s);
+hipError_t launch_coarse_restrict(const GridGeom &f, const GridGeom &c, const double *r, double *rc,
+                                  hipStream_t s);
+hipError_t launch_coarse_prolong(const GridGeom &f, const GridGeom &c, const double *dc,
+                                 double scale, double *d, hipStream_t s);
+hipError_t launch_axpy(int n, const double *d, double *x, hipStream_t s);  // x += d
+
 // ---- warm-start network (kernels_mlp.hip) ----
 struct MlpTrainArgs {
   const uint16_t *w;            // bfloat16 parameters used by the passes

@@ -1,0 +1,148 @@
+"""GPU parity of the coarse-grid predicted corrections of grid solves
+(gabp_plan_solve_coarse) against the FP64 oracle (oracle/coarse.py).
+
+FP64 messages: the x after each of the first cycles equals the oracle's
+(same levels, Galerkin operators, smoothing sweeps and scale) to 1e-9
+relative -- the levels' GaBP rounds agree to ~1e-11 per sweep as on the plain
+grid path, and a cycle adds a handful of FP64 sums.  FP32 messages: every
+grid of the stack meets the tolerance (its residual recomputed by the
+oracle)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import coarse as OC
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import paper_0810_1119_amd as G
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return G
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _grid(G, nx, ny, nz, batch, seed, varcoef=True):
+    _, coef = W.grid_stack(nx, ny, nz, batch, varcoef=varcoef, seed=seed, ell=4.0, shift=0.01,
+                           with_csr=False)
+    if varcoef:
+        A = G.DeviceGrid(nx, ny, nz, batch, diag=dev(coef["diag"]), cx=dev(coef["cx"]),
+                         cy=dev(coef["cy"]), cz=dev(coef["cz"]) if nz > 1 else None)
+        arrs = (coef["diag"], coef["cx"], coef["cy"], coef["cz"] if nz > 1 else None)
+    else:
+        A = G.DeviceGrid(nx, ny, nz, batch, diag_value=coef["dval"], off_value=coef["off"])
+        N = nx * ny * nz * batch
+        arrs = (np.full(N, coef["dval"]), np.full(N, coef["off"]), np.full(N, coef["off"]),
+                np.full(N, coef["off"]) if nz > 1 else None)
+    return A, arrs
+
+
+CASES = {
+    "varcoef_16cubed_x2": (16, 16, 16, 2, True),
+    "varcoef_odd_13x9x7_x3": (13, 9, 7, 3, True),
+    "poisson2d_20x17": (20, 17, 1, 1, False),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("schedule", ["colored", "sync"])
+def test_cycles_match_oracle_fp64(G, case, schedule):
+    nx, ny, nz, batch, varc = CASES[case]
+    print(f"case: coarse-grid cycles FP64 {case} {schedule}", flush=True)
+    A, arrs = _grid(G, nx, ny, nz, batch, 3, varc)
+    b = W.normal_b(A.n, 4)
+    colored = schedule == "colored"
+    # an undamped synchronous plan smooths with damping 0.3 (the alternating
+    # mode of a bipartite graph is not damped otherwise)
+    ref_x, ref_c, ref_w, trail = OC.solve(nx, ny, nz, batch, *arrs, b, tol=0.0, max_cycles=3,
+                                          colored=colored, damping=0.0 if colored else 0.3)
+    for k in (1, 2, 3):
+        o = G.gabp_default_opts(msg_fp32=0, tol=0.0, max_restarts=k, freeze=0,
+                                schedule=G.GABP_SCHEDULE_COLORED if colored
+                                else G.GABP_SCHEDULE_SYNC)
+        rc, plan = G.gabp_plan_create_grid(A, o)
+        assert rc == G.GABP_OK
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
+        G.gabp_plan_destroy(plan)
+        assert rc == G.GABP_NOT_CONVERGED and st.restarts == k, (rc, st.restarts)
+        xh = x.cpu().numpy()
+        err = np.linalg.norm(xh - trail[k - 1]) / np.linalg.norm(trail[k - 1])
+        assert err < 1e-9, (k, err)
+
+
+def test_damped_sync_cycles_match_oracle(G):
+    print("case: coarse-grid cycles FP64, synchronous damped 0.5", flush=True)
+    nx, ny, nz, batch = 12, 10, 9, 1
+    A, arrs = _grid(G, nx, ny, nz, batch, 5, varcoef=False)
+    b = W.uniform_b(A.n, 6)
+    _, _, _, trail = OC.solve(nx, ny, nz, batch, *arrs, b, tol=0.0, max_cycles=2, colored=False,
+                              damping=0.5)
+    o = G.gabp_default_opts(msg_fp32=0, tol=0.0, max_restarts=2, freeze=0, damping=0.5)
+    rc, plan = G.gabp_plan_create_grid(A, o)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
+    G.gabp_plan_destroy(plan)
+    assert rc == G.GABP_NOT_CONVERGED
+    xh = x.cpu().numpy()
+    assert np.linalg.norm(xh - trail[1]) / np.linalg.norm(trail[1]) < 1e-9
+
+
+def test_fp32_stack_reaches_1e8_in_few_cycles(G):
+    print("case: coarse-grid solve FP32 to 1e-8, 4 grids of 32^3", flush=True)
+    nx = ny = nz = 32
+    batch = 4
+    A, arrs = _grid(G, nx, ny, nz, batch, 7)
+    b = W.normal_b(A.n, 8)
+    o = G.gabp_default_opts(schedule=G.GABP_SCHEDULE_COLORED)
+    rc, plan = G.gabp_plan_create_grid(A, o)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
+    xp = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    rc2, st2 = G.gabp_plan_solve(plan, dev(b), xp)
+    G.gabp_plan_destroy(plan)
+    assert rc == G.GABP_OK and rc2 == G.GABP_OK
+    n = nx * ny * nz
+    xh = x.cpu().numpy()
+    for t in range(batch):
+        sl = slice(t * n, (t + 1) * n)
+        _, rn = oracle.residual_grid(nx, ny, nz, 1, b[sl], xh[sl], diag=arrs[0][sl],
+                                     cx=arrs[1][sl], cy=arrs[2][sl], cz=arrs[3][sl])
+        assert rn / np.linalg.norm(b[sl]) <= 1e-8, t
+    print(f"coarse: {st.restarts} corrections, {st.sweeps} sweeps, {st.seconds * 1e3:.1f} ms; "
+          f"plain: {st2.sweeps} sweeps (slowest grid), {st2.seconds * 1e3:.1f} ms", flush=True)
+    assert st.restarts <= 20
+    assert st.sweeps < st2.mean_sweeps / 4
+    np.testing.assert_allclose(xh, xp.cpu().numpy(), rtol=0, atol=1e-6 * np.abs(xh).max())
+
+
+def test_zero_rhs_and_other_plans(G):
+    print("case: coarse-grid solve edge cases", flush=True)
+    A, arrs = _grid(G, 8, 8, 8, 1, 9)
+    rc, plan = G.gabp_plan_create_grid(A)
+    x = torch.full((A.n,), 5.0, dtype=torch.float64, device="cuda")
+    rc, st = G.gabp_plan_solve_coarse(plan, dev(np.zeros(A.n)), x)
+    assert rc == G.GABP_OK and float(x.abs().max()) == 0.0
+    # a grid small enough to be its own coarsest level: GaBP sweeps alone
+    A4, arrs4 = _grid(G, 4, 4, 4, 2, 10)
+    rc, p4 = G.gabp_plan_create_grid(A4, G.gabp_default_opts(msg_fp32=0, tol=1e-10,
+                                                              max_restarts=200))
+    b4 = W.normal_b(A4.n, 11)
+    x4 = torch.zeros(A4.n, dtype=torch.float64, device="cuda")
+    rc, st = G.gabp_plan_solve_coarse(p4, dev(b4), x4)
+    assert rc == G.GABP_OK
+    G.gabp_plan_destroy(p4)
+    G.gabp_plan_destroy(plan)
+    m = W.poisson2d(6)
+    rc, pc = G.gabp_plan_create(G.DeviceCSR.from_host(m))
+    rc, st = G.gabp_plan_solve_coarse(pc, dev(np.ones(m.n)),
+                                      torch.zeros(m.n, dtype=torch.float64, device="cuda"))
+    assert rc == G.GABP_ERR_UNSUPPORTED
+    G.gabp_plan_destroy(pc)
