@@ -64,8 +64,10 @@ def parse():
                          "colours, one launch each: 14 instead of 20 sweeps at the same time)")
     ap.add_argument("--accel", choices=["none", "aitken", "steffensen"], default=None,
                     help="c1: acceleration of the means (default aitken)")
+    ap.add_argument("--kinds", default="plain,warm,coarse",
+                    help="c4: the solves of a step (profiling a kind alone: e.g. plain)")
     ap.add_argument("--stride", type=int, default=0,
-                    help="c1: sweeps between Aitken samples (0 = 2)")
+                    help="c1: sweeps between Aitken samples (0 = 4)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte "
                          "counters) and print its bandwidth")
@@ -450,6 +452,23 @@ def bench_c3(args, G, W, torch, dev):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_c3(db)
+        # sampled instances against the oracle's solutions (outside the timing)
+        import oracle
+        xs = x.cpu().numpy()
+        worst_rel, worst_abs = 0.0, 0.0
+        for t in np.random.default_rng(11).choice(db.batch, 8, replace=False):
+            S, yv, _, s2 = db.instance(int(t))
+            mb, rhs = oracle.bipartite_system(S, yv, s2)
+            r = oracle.solve(mb, rhs, tol=1e-13, max_rounds=20000)
+            if r.status != oracle.OK:
+                r = oracle.solve(mb, rhs, tol=1e-13, max_rounds=60000, damping=0.3)
+            k0, k = int(db.x_off[t]), int(db.K[t])
+            xo = r.x[:k]
+            d = xs[k0:k0 + k] - xo
+            worst_rel = max(worst_rel, float(np.linalg.norm(d) / np.linalg.norm(xo)))
+            worst_abs = max(worst_abs, float(np.abs(d).max()))
+        out["config"]["err_vs_oracle"] = {"rel_l2_worst": worst_rel, "max_abs": worst_abs,
+                                          "note": "8 sampled instances, oracle to 1e-13"}
     return out
 
 
@@ -473,7 +492,7 @@ def bench_c1(args, G, W, torch, dev):
     colored = (args.schedule or "colored") == "colored"
     opts = G.gabp_default_opts(msg_fp32=0, tol=1e-10, max_sweeps=100000,
                                schedule=G.GABP_SCHEDULE_COLORED if colored else G.GABP_SCHEDULE_SYNC,
-                               accel=accel, accel_stride=args.stride or 2)
+                               accel=accel, accel_stride=args.stride or 4)
     if args.check_every:
         opts.check_every = args.check_every
     torch.cuda.synchronize()
@@ -618,7 +637,9 @@ def bench_c4(args, G, W, torch, dev):
     xp = torch.zeros(N, dtype=torch.float64, device=dev)
     xw = torch.zeros(N, dtype=torch.float64, device=dev)
     xc = torch.zeros(N, dtype=torch.float64, device=dev)
-    kinds = ("plain", "warm", "coarse")
+    kinds = tuple(k for k in ("plain", "warm", "coarse") if k in args.kinds.split(","))
+    if "plain" not in kinds:
+        raise SystemExit("--kinds must include plain (the roofline is taken on it)")
 
     def solve(kind):
         if kind == "plain":
@@ -634,8 +655,8 @@ def bench_c4(args, G, W, torch, dev):
     for _ in range(args.warmup):
         for kind in kinds:
             solve(kind)
-    res = {k: [] for k in kinds}
-    wall = {k: 0.0 for k in kinds}
+    res = {k: [] for k in ("plain", "warm", "coarse")}
+    wall = {k: 0.0 for k in ("plain", "warm", "coarse")}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -650,6 +671,9 @@ def bench_c4(args, G, W, torch, dev):
     # each grid's own FP64 residual, recomputed one grid at a time outside the timing
     worst = {}
     for kind, xv in (("plain", xp), ("warm", xw), ("coarse", xc)):
+        if kind not in kinds:
+            worst[kind] = None
+            continue
         w = 0.0
         for t in range(count):
             sl = slice(t * nn, (t + 1) * nn)
@@ -682,7 +706,9 @@ def bench_c4(args, G, W, torch, dev):
     fz_bpl = grid_bytes_per_sweep(N, E, True, False, c_eff) / per * grid_frozen / max(frozen, 1)
     fz_avg_s = fz_ms * 1e-3 / fz_launches
     fz_gbs = fz_bpl / fz_avg_s / 1e9
-    tp, tw, tc = wall["plain"] / K, wall["warm"] / K, wall["coarse"] / K
+    tp = wall["plain"] / K
+    tw = wall["warm"] / K if wruns else None
+    tc = wall["coarse"] / K if cruns else None
     out = {
         "metric": "GaBP edge-updates/s; time to rel. residual 1e-8, warm start vs plain",
         "value": msgs / dt, "unit": "edge-updates/s",
@@ -700,23 +726,24 @@ def bench_c4(args, G, W, torch, dev):
                         "messages and one with coarse-grid predicted corrections",
             "grids": count, "n": N, "directed_edges": E, "seed": args.seed,
             "time_to_1e-8_ms_plain": tp * 1e3,
-            "time_to_1e-8_ms_warm": tw * 1e3,
-            "warm_speedup": tp / tw,
-            "time_to_1e-8_ms_coarse": tc * 1e3,
-            "coarse_speedup": tp / tc,
-            "coarse_corrections": sum(st.restarts for st in cruns) / K,
-            "coarse_sweeps_finest_grid": sum(st.sweeps for st in cruns) / K,
+            "time_to_1e-8_ms_warm": tw * 1e3 if tw else None,
+            "warm_speedup": tp / tw if tw else None,
+            "time_to_1e-8_ms_coarse": tc * 1e3 if tc else None,
+            "coarse_speedup": tp / tc if tc else None,
+            "coarse_corrections": sum(st.restarts for st in cruns) / K if cruns else None,
+            "coarse_sweeps_finest_grid": sum(st.sweeps for st in cruns) / K if cruns else None,
             "rel_residual_worst_grid_coarse": worst["coarse"],
             "sweeps_slowest_grid_plain": sum(st.sweeps for st in runs) / K,
-            "sweeps_slowest_grid_warm": sum(st.sweeps for st in wruns) / K,
+            "sweeps_slowest_grid_warm": sum(st.sweeps for st in wruns) / K if wruns else None,
             "mean_sweeps_per_grid_plain": sum(st.mean_sweeps for st in runs) / K,
-            "mean_sweeps_per_grid_warm": sum(st.mean_sweeps for st in wruns) / K,
-            "full_sweeps_per_grid": full_grid / (2 * K),
-            "settled_sweeps_per_grid": settled_grid / (2 * K),
+            "mean_sweeps_per_grid_warm": (sum(st.mean_sweeps for st in wruns) / K
+                                          if wruns else None),
+            "full_sweeps_per_grid": full_grid / (K * (1 + bool(wruns))),
+            "settled_sweeps_per_grid": settled_grid / (K * (1 + bool(wruns))),
             "edge_updates_per_s_full_sweeps_only": E * full_grid / dt,
             "edge_updates_per_s_settled_sweeps_only": E * settled_grid / dt,
             "sweeps_per_check": c_eff,
-            "warm_start_status": wruns[-1].warm_start,
+            "warm_start_status": wruns[-1].warm_start if wruns else None,
             "rel_residual_worst_grid_plain": worst["plain"],
             "rel_residual_worst_grid_warm": worst["warm"],
             "plan_ms": plan_ms,
@@ -746,6 +773,8 @@ def bench_c4(args, G, W, torch, dev):
         ref = oracle_grid_reference(args.seed, 0, n, W.normal_b(N, args.seed))
         errs = {}
         for kind, xv in (("plain", xp), ("warm", xw), ("coarse", xc)):
+            if kind not in kinds:
+                continue
             xg = xv[:nn].cpu().numpy()
             errs[kind] = {"rel_l2": float(np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"])),
                           "max_abs": float(np.abs(xg - ref["x"]).max())}
@@ -863,6 +892,23 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lsq_rel = G.gabp_plan_residual_lsq(plan, b, x)[1] if args.workload == "lsq" else None
+    coarse = None
+    if args.workload == "c5":
+        # the same system with coarse-grid predicted corrections (outside the
+        # timed steps of the plain solve; timed on its own)
+        xc = torch.zeros_like(x)
+        rc, cst = G.gabp_plan_solve_coarse(plan, b, xc)  # builds the coarse levels
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            rc, cst = G.gabp_plan_solve_coarse(plan, b, xc)
+        torch.cuda.synchronize()
+        if rc != G.GABP_OK:
+            raise SystemExit(f"coarse solve: {G.status_name(rc)}")
+        coarse = {"time_to_1e-8_ms_coarse": (time.perf_counter() - t1) * 1e3 / reps,
+                  "coarse_corrections": cst.restarts, "coarse_sweeps_finest_grid": cst.sweeps,
+                  "rel_residual_coarse": cst.rel_residual}
     G.gabp_plan_destroy(plan)
 
     ms_per_step = dt * 1e3 / args.steps
@@ -931,6 +977,9 @@ def main():
             "traffic_over_algorithmic": (traffic_full / full_bpl) if traffic_full else None,
         },
     }
+    if coarse is not None:
+        out["config"].update(coarse)
+        out["config"]["coarse_speedup"] = ms_per_step / coarse["time_to_1e-8_ms_coarse"]
     if lsq_rel is not None:  # the least-squares residual of the answer, outside the timing
         out["config"]["normal_equations_rel_residual"] = lsq_rel
     if not args.no_cpu_baseline:
@@ -940,7 +989,34 @@ def main():
             out["cpu_baseline"] = cpu_baseline_lsq(w, E)
         else:
             out["cpu_baseline"] = cpu_baseline_grid(w, E)
+        out["config"]["err_vs_oracle"] = err_vs_oracle(args.workload, w, x)
     print(json.dumps(out))
+
+
+def err_vs_oracle(workload, w, x):
+    """The GPU answer against the FP64 oracle's own converged solution of the
+    same system (outside the timing): relative 2-norm and largest absolute
+    difference.  The 256^3 system is beyond what the oracle solves on the
+    host in minutes; its residual, recomputed in FP64 on the device, stands."""
+    import oracle
+    xh = x.cpu().numpy()
+    if workload == "c2":
+        ref = oracle.solve(w["m"], w["b_h"], algorithm=2, tol=1e-12, max_rounds=2000)
+        ok, xo, note = ref.status == oracle.OK, ref.x, f"oracle to 1e-12 ({ref.rounds} rounds)"
+    elif workload == "lsq":
+        S = w["S"]
+        mb, rhs = oracle.bipartite_system_sparse(S.m, S.k, S.row_ptr, S.col, S.val, w["y_h"],
+                                                 w["psi"])
+        ref = oracle.solve(mb, rhs, algorithm=2, tol=1e-11, max_rounds=4000)
+        ok, xo = ref.status == oracle.OK, ref.x[:S.k]
+        note = f"oracle on the section VII system to 1e-11 ({ref.rounds} rounds)"
+    else:
+        return {"rel_l2": None, "max_abs": None,
+                "note": "no oracle solution at this size (16.7M unknowns, ~9000 rounds)"}
+    if not ok:
+        return {"rel_l2": None, "max_abs": None, "note": note + ": not converged"}
+    return {"rel_l2": float(np.linalg.norm(xh - xo) / np.linalg.norm(xo)),
+            "max_abs": float(np.abs(xh - xo).max()), "note": note}
 
 
 def cpu_baseline_grid(w, E, budget_s=12.0):

@@ -523,11 +523,13 @@ int gabp_plan_solve_warm(gabp_plan *plan, const gabp_model *model, const double 
  *   d  = means of 4 GaBP sweeps on r (the plan's schedule and message
  *        precision, zero information messages, the precision messages of the
  *        level's previous sweeps kept);
- *   d += 1.8 P d_c, where d_c is the same procedure applied on the next coarser
- *        grid to the right-hand side P^T (r - A d), P the 2 x 2 x 2 block
- *        indicator (an axis of extent 1 is not halved) and the coarse operator
- *        the Galerkin product P^T A P (again a 5/7-point stencil), recursively
- *        down to grids of at most 64 cells, where d_c is the means of 24 sweeps;
+ *   d += 1.8 P e, where e solves the next coarser grid's system
+ *        P^T A P e = rc, rc = P^T (r - A d), by two applications of the same
+ *        procedure (e = the first's result, then e += the second's on
+ *        rc - P^T A P e: a W-cycle), P the 2 x 2 x 2 block indicator (an axis
+ *        of extent 1 is not halved) and P^T A P the Galerkin product (again a
+ *        5/7-point stencil), recursively down to grids of at most 64 cells,
+ *        where the procedure is the means of 24 sweeps;
  *   d += means of 4 GaBP sweeps on r - A d;
  * then x += d, until every grid of the stack meets tol (each grid's own
  * ||b_t - A_t x_t|| / ||b_t||).  The sweeps use the plan's damping, except

@@ -18,8 +18,10 @@ removes slowly.  Written plainly from the definitions below:
   precision messages of that level's previous smoothing kept (zero at the
   start of a solve), and the marginal means of the final messages;
 * a cycle on level l with right-hand side v: d = smooth(v, nu_pre); on the
-  coarsest level that is all (with nu_coarse sweeps); otherwise
-  d += scale * P cycle(l + 1, P^T (v - A d)), then d += smooth(v - A d, nu_post);
+  coarsest level that is all (with nu_coarse sweeps); otherwise, with
+  rc = P^T (v - A d), e = cycle(l + 1, rc) and then gamma - 1 more times
+  e += cycle(l + 1, rc - A_c e) (gamma = 2: a W-cycle), d += scale * P e, and
+  d += smooth(v - A d, nu_post);
 * the solve: x = 0, then x += cycle(0, b - A x) until every grid's
   ||b_t - A_t x_t|| / ||b_t|| <= tol.
 """
@@ -135,20 +137,27 @@ def smooth(lev, v, sweeps):
     return R.marginals()[0]
 
 
-def cycle(H, l, v, nu_pre, nu_post, nu_coarse, scale):
+def cycle(H, l, v, nu_pre, nu_post, nu_coarse, scale, gamma=2):
     lev = H.levels[l]
     if "P" not in lev:
         return smooth(lev, v, nu_coarse)
     d = smooth(lev, v, nu_pre)
     r = v - lev["A"] @ d
-    d = d + scale * (lev["P"] @ cycle(H, l + 1, lev["P"].T @ r, nu_pre, nu_post, nu_coarse, scale))
+    rc = lev["P"].T @ r
+    # the coarse system P^T A P e = rc: gamma cycles of the next level, each on
+    # the residual the previous ones left
+    e = cycle(H, l + 1, rc, nu_pre, nu_post, nu_coarse, scale, gamma)
+    for _ in range(gamma - 1):
+        e = e + cycle(H, l + 1, rc - H.levels[l + 1]["A"] @ e, nu_pre, nu_post, nu_coarse, scale,
+                      gamma)
+    d = d + scale * (lev["P"] @ e)
     if nu_post:
         d = d + smooth(lev, v - lev["A"] @ d, nu_post)
     return d
 
 
 def solve(nx, ny, nz, batch, diag, cx, cy, cz, b, tol=1e-8, nu_pre=4, nu_post=4, nu_coarse=24,
-          scale=1.8, max_cycles=100, colored=True, damping=0.0):
+          scale=1.8, max_cycles=100, colored=True, damping=0.0, gamma=2):
     """Returns (x, cycles, worst per-grid relative residual, list of the x
     after each cycle).  colored=False smooths with synchronous rounds; damping
     as in the rounds (section VI-D reading)."""
@@ -166,7 +175,7 @@ def solve(nx, ny, nz, batch, diag, cx, cy, cz, b, tol=1e-8, nu_pre=4, nu_post=4,
         worst = max(np.linalg.norm(r[t * n:(t + 1) * n]) / bn[t] for t in range(batch))
         if worst <= tol or k == max_cycles:
             return x, k, worst, trail
-        x = x + cycle(H, 0, r, nu_pre, nu_post, nu_coarse, scale)
+        x = x + cycle(H, 0, r, nu_pre, nu_post, nu_coarse, scale, gamma)
         trail.append(x.copy())
     return x, max_cycles, worst, trail
 

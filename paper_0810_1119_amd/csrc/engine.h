@@ -6,6 +6,7 @@
 #pragma once
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "gabp_internal.h"
@@ -130,6 +131,11 @@ struct Engine {
 // refinement loop around chunked sweeps (api.cpp)
 int engine_solve(Engine *e, const double *b, double *x, double *marg, gabp_stats *st,
                  hipStream_t s, const uint16_t *warm = nullptr);
+
+// persistent autotuning cache (tune_cache.cpp): key = arch | version | kernel | shape class
+std::string tune_key(const std::string &kernel, const std::string &shape);
+bool tune_lookup(const std::string &key, int *value);
+void tune_store(const std::string &key, int value);
 
 int check_opts(const gabp_opts *o);  // engine_csr.cpp
 int check_csr(const gabp_csr *A);    // engine_csr.cpp: sizes, pointers, row_ptr ends

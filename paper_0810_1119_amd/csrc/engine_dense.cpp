@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -114,20 +115,19 @@ int grid_for(BatchEngine *e) {
 }
 
 // Autotuner of the workgroup shape: time two full sweeps of the whole batch
-// for each shape that fits and keep the fastest.  Results are remembered per
-// shape class (kind, precision, largest instance, batch size, entries) for
-// the life of the process.
-std::mutex tune_mu;
-std::map<std::tuple<int, int, int, int, int, int64_t>, int> tune_cache;
-
+// for each shape that fits and keep the fastest.  The choice is remembered per
+// shape class (kind and schedule, precision, largest instance, batch size,
+// entries) in the persistent tuning cache (and so across processes).
 int autotune(BatchEngine *e, hipStream_t s) {
   const int64_t bucket = e->entries > 0 ? (int64_t)std::log2((double)e->entries) : 0;
-  const auto key = std::make_tuple(e->kind * 2 + (e->o.schedule == GABP_SCHEDULE_COLORED ? 1 : 0),
-                                   (int)e->fp32, e->nr, e->nc, e->count, bucket);
+  char shape[160];
+  std::snprintf(shape, sizeof shape, "kind=%d,colored=%d,fp32=%d,rows=%d,cols=%d,count=%d,log2e=%lld",
+                e->kind, e->o.schedule == GABP_SCHEDULE_COLORED ? 1 : 0, (int)e->fp32, e->nr,
+                e->nc, e->count, (long long)bucket);
+  const std::string key = tune_key("k_dense_batch.waves", shape);
   {
-    std::lock_guard<std::mutex> g(tune_mu);
-    auto it = tune_cache.find(key);
-    if (it != tune_cache.end()) return it->second;
+    int w = 0;
+    if (tune_lookup(key, &w) && (w == 4 || w == 8 || w == 16) && waves_fit(e, w)) return w;
   }
   const int cands[] = {4, 8, 16};
   int best = 0;
@@ -163,10 +163,7 @@ int autotune(BatchEngine *e, hipStream_t s) {
       best = w;
     }
   }
-  if (best != 0) {
-    std::lock_guard<std::mutex> g(tune_mu);
-    tune_cache[key] = best;
-  }
+  if (best != 0) tune_store(key, best);
   return best;
 }
 

@@ -337,11 +337,23 @@ constexpr int kCoarsePre = 4, kCoarsePost = 4, kCoarseSweeps = 24, kCoarseMaxCel
 // oracle diverges without it and takes 11-13 corrections with it on
 // 16^3 - 24^3 grids); the coloured schedule smooths with the plan's own.
 constexpr double kCoarseSyncDamping = 0.3;
+// The precision messages do not depend on the right-hand side and settle
+// within a few sweeps; after this many sweeps of a level in one solve (with
+// opts.freeze on) the level keeps them fixed and sweeps the information
+// messages only (the settled-precision sweeps of the plain solve).  The FP64
+// residual of every correction absorbs what is left of their change.
+constexpr int kCoarseFreezeAfter = 16;
 // Injection of a block's correction into its cells under-corrects smooth
 // error (the coarse operator of piecewise constants is too stiff by about a
 // factor of two); the scale was chosen with the FP64 oracle on
-// variable-coefficient grids of 16^3 to 32^3.
+// variable-coefficient grids of 16^3 to 64^3.
 constexpr double kCoarseScale = 1.8;
+// Cycles of the next level per coarse correction: 2 (a W-cycle).  With one
+// (a V-cycle) the correction loses accuracy with every level: in the FP64
+// oracle the shifted 64^3 Laplacian (5 levels) stalls near 3e-3 under damped
+// synchronous smoothing, while with two every tested grid (16^3 to 64^3,
+// constant and variable coefficients, both schedules) needs 7 to 13.
+constexpr int kCoarseGamma = 2;
 
 struct CoarseHierarchy {
   struct Level {
@@ -350,7 +362,9 @@ struct CoarseHierarchy {
     GridGeom g{};
     double *dg = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;  // levels >= 1
     double *v = nullptr, *d = nullptr, *t = nullptr;  // right-hand side, correction, residual
+    double *e = nullptr;  // levels >= 1: the coarse correction summed over the cycles
     bool fresh = true;  // messages not yet set in this solve
+    int swept = 0;      // sweeps of this level in this solve
   };
   std::vector<Level> lv;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -358,7 +372,7 @@ struct CoarseHierarchy {
   ~CoarseHierarchy() {
     for (Level &L : lv) {
       if (L.plan) gabp_plan_destroy(L.plan);
-      double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.t};
+      double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.t, L.e};
       for (double *b : bufs)
         if (b) (void)hipFree(b);
     }
@@ -367,9 +381,11 @@ struct CoarseHierarchy {
   }
 
   double damping = 0.0;  // of every level's sweeps
+  bool freeze = true;    // settle the precisions after kCoarseFreezeAfter sweeps
 
   int build(GridEngine *e0, hipStream_t s) {
     damping = e0->o.damping;
+    freeze = e0->o.freeze != 0;
     if (e0->o.schedule == GABP_SCHEDULE_SYNC && damping == 0.0) damping = kCoarseSyncDamping;
     TRY_HIP(hipEventCreate(&ev0));
     TRY_HIP(hipEventCreate(&ev1));
@@ -384,6 +400,7 @@ struct CoarseHierarchy {
       TRY_HIP(dalloc(&F.v, F.g.N, sizeof(double)));
       TRY_HIP(dalloc(&F.d, F.g.N, sizeof(double)));
       TRY_HIP(dalloc(&F.t, F.g.N, sizeof(double)));
+      if (lv.size() > 1) TRY_HIP(dalloc(&F.e, F.g.N, sizeof(double)));
       if ((int64_t)F.g.nx * F.g.ny * F.g.nz <= kCoarseMaxCells) break;
       Level C;
       C.g = coarse_geom(F.g);
@@ -416,11 +433,18 @@ struct CoarseHierarchy {
     if (v && L.fresh) {
       TRY_HIP(L.eng->reset(v, s));
       L.fresh = false;
+      L.swept = 0;
     } else {
       if (v) TRY_HIP(L.eng->residual(v, nullptr, nullptr, s));
+      TRY_HIP(L.eng->restart(s));  // zero informations (after a freeze: the settled ones)
+    }
+    if (freeze && !L.eng->frozen && L.swept >= kCoarseFreezeAfter) {
+      TRY_HIP(L.eng->ensure_frozen_buffers());
+      TRY_HIP(L.eng->freeze(s));
       TRY_HIP(L.eng->restart(s));
     }
     for (int k = 0; k < sweeps; ++k) TRY_HIP(L.eng->sweep(0, nullptr, s));
+    L.swept += sweeps;
     TRY_HIP(L.eng->infer(L.d, nullptr, nullptr, s));
     return GABP_OK;
   }
@@ -433,10 +457,20 @@ struct CoarseHierarchy {
     int rc = smooth(l, L.v, kCoarsePre, s);
     if (rc) return rc;
     Level &C = lv[l + 1];
+    const size_t cbytes = (size_t)C.g.N * sizeof(double);
     TRY_HIP(L.eng->residual(L.v, L.d, L.t, s));
     TRY_HIP(launch_coarse_restrict(L.g, C.g, L.t, C.v, s));
+    // the coarse system: kCoarseGamma cycles of the next level, each on the
+    // residual the previous ones left; their corrections summed in C.e
     if ((rc = cycle(l + 1, s))) return rc;
-    TRY_HIP(launch_coarse_prolong(L.g, C.g, C.d, kCoarseScale, L.d, s));
+    TRY_HIP(hipMemcpyAsync(C.e, C.d, cbytes, hipMemcpyDeviceToDevice, s));
+    for (int g = 1; g < kCoarseGamma; ++g) {
+      TRY_HIP(C.eng->residual(C.v, C.e, C.t, s));  // C.t = rc - A_c e
+      TRY_HIP(hipMemcpyAsync(C.v, C.t, cbytes, hipMemcpyDeviceToDevice, s));
+      if ((rc = cycle(l + 1, s))) return rc;
+      TRY_HIP(launch_axpy(C.g.N, C.d, C.e, s));
+    }
+    TRY_HIP(launch_coarse_prolong(L.g, C.g, C.e, kCoarseScale, L.d, s));
     if (kCoarsePost > 0) {
       TRY_HIP(L.eng->residual(L.v, L.d, L.t, s));
       if ((rc = smooth(l, nullptr, kCoarsePost, s))) return rc;

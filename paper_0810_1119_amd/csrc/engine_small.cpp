@@ -52,6 +52,7 @@ struct SmallEngine {
     a.colored = o.schedule == GABP_SCHEDULE_COLORED;
     a.rows_per_thread = rpt;
     a.cache = cache;
+    a.maxdeg = maxdeg;
     a.threads = threads;
     a.grid = grid;
     a.count = count;

@@ -531,6 +531,7 @@ struct SmallArgs {
   bool colored;          // serial scheme in colour order
   int rows_per_thread;   // 1 or 4
   bool cache;            // rows_per_thread == 1 and degree <= 8: slot data in registers
+  int maxdeg;            // largest row degree of the batch
   int threads, grid;     // workgroup size and workgroups of the persistent launch
   int count;
   const SmallInst *inst;

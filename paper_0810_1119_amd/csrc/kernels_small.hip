@@ -177,7 +177,35 @@ struct Rows {
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
       if (!ok[r] || (c >= 0 && colr[r] != c)) continue;
-      if (CACHE > 0 && deg[0] <= CACHE) {
+      if (CACHE > 0 && CACHE <= 4 && deg[0] <= CACHE) {
+        // all cavities and factors first, without branches, so the divisions
+        // of the row's slots overlap instead of running one after another
+        // (a slot beyond the row's degree divides 0 by 1 and stores nothing;
+        // with eight slots the three arrays would not fit the registers)
+        T pin[CS], hin[CS], f[CS];
+#pragma unroll
+        for (int k = 0; k < CS; ++k) {
+          const bool on = k < deg[0];
+          const T2 m = on ? B[s0[0] + k] : T2{T(0), T(0)};
+          pin[k] = m.x;
+          hin[k] = m.y;
+          const T cav = on ? S[0] - m.x : T(1);
+          if (on && cav == T(0)) brk = true;
+          f[k] = -av[k] / cav;
+        }
+#pragma unroll
+        for (int k = 0; k < CS; ++k)
+          if (k < deg[0]) {
+            T P = f[k] * av[k];
+            T h = f[k] * (H[0] - hin[k]);
+            if (damp) {
+              const T2 old = B[rv[k]];
+              P = alpha * old.x + (T(1) - alpha) * P;
+              h = alpha * old.y + (T(1) - alpha) * h;
+            }
+            O[rv[k]] = T2{P, h};
+          }
+      } else if (CACHE > 0 && deg[0] <= CACHE) {
 #pragma unroll
         for (int k = 0; k < CS; ++k)
           if (k < deg[0]) {
@@ -528,11 +556,16 @@ const void *small_kernel() {
 
 const void *pick_small(const SmallArgs &a) {
   const bool c = a.colored;
+  const bool d4 = a.cache && a.maxdeg <= 4;  // rows of degree <= 4: four slots in registers
   if (a.fp32) {
+    if (a.rows_per_thread == 1 && d4)
+      return c ? small_kernel<float, 1, 4, true>() : small_kernel<float, 1, 4, false>();
     if (a.rows_per_thread == 1)
       return c ? small_kernel<float, 1, 8, true>() : small_kernel<float, 1, 8, false>();
     return c ? small_kernel<float, 4, 0, true>() : small_kernel<float, 4, 0, false>();
   }
+  if (a.rows_per_thread == 1 && d4)
+    return c ? small_kernel<double, 1, 4, true>() : small_kernel<double, 1, 4, false>();
   if (a.rows_per_thread == 1)
     return c ? small_kernel<double, 1, 8, true>() : small_kernel<double, 1, 8, false>();
   return c ? small_kernel<double, 4, 0, true>() : small_kernel<double, 4, 0, false>();
