@@ -3,6 +3,8 @@
 // arrays; see kernels_grid.hip.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -368,8 +370,23 @@ struct CoarseHierarchy {
   };
   std::vector<Level> lv;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // Once every level has been set up in a solve and (with opts.freeze) has
+  // settled its precisions, a correction is the same sequence of launches on
+  // the same buffers every time (each visit of a level runs an even number of
+  // sweeps, so double-buffered engines start every correction from the same
+  // buffer): it is captured once into a graph and replayed, one launch per
+  // correction instead of a few hundred (most of them on the small grids,
+  // where the launches, not the sweeps, set the time).  GABP_COARSE_GRAPH=0
+  // at plan time keeps every correction eager.
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cs = nullptr;  // capture stream (the caller's may be the legacy NULL stream)
 
   ~CoarseHierarchy() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
     for (Level &L : lv) {
       if (L.plan) gabp_plan_destroy(L.plan);
       double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.t, L.e};
@@ -386,6 +403,7 @@ struct CoarseHierarchy {
   int build(GridEngine *e0, hipStream_t s) {
     damping = e0->o.damping;
     freeze = e0->o.freeze != 0;
+    if (const char *g = std::getenv("GABP_COARSE_GRAPH")) use_graph = std::strcmp(g, "0") != 0;
     if (e0->o.schedule == GABP_SCHEDULE_SYNC && damping == 0.0) damping = kCoarseSyncDamping;
     TRY_HIP(hipEventCreate(&ev0));
     TRY_HIP(hipEventCreate(&ev1));
@@ -449,6 +467,8 @@ struct CoarseHierarchy {
     return GABP_OK;
   }
 
+  int correction(hipStream_t s);
+
   // d_l from v_l: smoothing, coarse prediction, smoothing
   int cycle(int l, hipStream_t s) {
     Level &L = lv[l];
@@ -478,6 +498,38 @@ struct CoarseHierarchy {
     return GABP_OK;
   }
 };
+
+// One correction d_0 = cycle(0): eager until the hierarchy is in its steady
+// state, then from the captured graph.
+int CoarseHierarchy::correction(hipStream_t s) {
+  bool steady = use_graph;
+  for (const Level &L : lv) steady = steady && !L.fresh && (!freeze || L.eng->frozen);
+  if (!steady) return cycle(0, s);
+  if (!exec) {
+    // record on a stream of our own (nothing runs while capturing); the
+    // steady state's host bookkeeping (sweep counts, buffer parity) ends where
+    // it began, so a failed capture only means running this correction eagerly
+    hipGraph_t g = nullptr;
+    bool ok = (cs || hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess) &&
+              hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      const int rc = cycle(0, cs);
+      ok = hipStreamEndCapture(cs, &g) == hipSuccess && rc == GABP_OK && g &&
+           hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+    }
+    if (!ok) {
+      (void)hipGetLastError();
+      if (g) (void)hipGraphDestroy(g);
+      exec = nullptr;
+      use_graph = false;
+      if (std::getenv("GABP_VERBOSE")) std::fprintf(stderr, "gabp: coarse cycle not captured\n");
+      return cycle(0, s);
+    }
+    graph = g;
+  }
+  TRY_HIP(hipGraphLaunch(exec, s));
+  return GABP_OK;
+}
 
 void coarse_destroy(CoarseHierarchy *h) { delete h; }
 
@@ -551,7 +603,7 @@ int coarse_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, ga
     }
     if (rel <= e0->o.tol) { status = GABP_OK; break; }
     if (cyc >= e0->o.max_restarts || stats.sweeps >= e0->o.max_sweeps) break;
-    if ((rc = H.cycle(0, s))) return finish(rc);
+    if ((rc = H.correction(s))) return finish(rc);
     TRY_HIP(launch_axpy(e0->n, H.lv[0].d, x, s));
     stats.sweeps += kCoarsePre + kCoarsePost;
     stats.restarts = cyc + 1;

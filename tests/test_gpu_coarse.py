@@ -146,3 +146,37 @@ def test_zero_rhs_and_other_plans(G):
                                       torch.zeros(m.n, dtype=torch.float64, device="cuda"))
     assert rc == G.GABP_ERR_UNSUPPORTED
     G.gabp_plan_destroy(pc)
+
+
+def test_graph_replays_equal_eager_corrections(G):
+    """Steady-state corrections run from a captured graph: repeated solves on
+    one plan (the graph captured in the first, replayed in all) give bitwise
+    the answer of a plan that runs every correction eagerly, with other work
+    and synchronisations of the program between the replays."""
+    import os
+    print("case: coarse-grid corrections from a captured graph vs eager", flush=True)
+    nx = ny = nz = 24
+    batch = 3
+    A, arrs = _grid(G, nx, ny, nz, batch, 12)
+    b = dev(W.normal_b(A.n, 13))
+    o = G.gabp_default_opts(schedule=G.GABP_SCHEDULE_COLORED)
+    os.environ["GABP_COARSE_GRAPH"] = "0"
+    try:
+        rc, pe = G.gabp_plan_create_grid(A, o)
+        xe = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        rc, ste = G.gabp_plan_solve_coarse(pe, b, xe)  # the hierarchy is built here
+    finally:
+        del os.environ["GABP_COARSE_GRAPH"]
+    assert rc == G.GABP_OK and ste.restarts >= 5  # steady corrections exist
+    rc, pg = G.gabp_plan_create_grid(A, o)
+    for rep in range(3):
+        xg = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        rc, stg = G.gabp_plan_solve_coarse(pg, b, xg)
+        assert rc == G.GABP_OK and stg.restarts == ste.restarts
+        assert torch.equal(xg, xe), rep
+        # the program's own eager work between the replays
+        xp = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        assert G.gabp_plan_solve(pg, b, xp)[0] == G.GABP_OK
+        torch.cuda.synchronize()
+    G.gabp_plan_destroy(pg)
+    G.gabp_plan_destroy(pe)
