@@ -40,6 +40,15 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
     if (_e != hipSuccess) return from_hip(_e); \
   } while (0)
 
+// the most LDS one workgroup may use on the current device
+inline int max_lds_per_block() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 65536;
+  return v;
+}
+
 template <typename P>
 hipError_t dalloc(P **p, size_t count, size_t elem) {
   *p = nullptr;

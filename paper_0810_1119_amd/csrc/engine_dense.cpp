@@ -83,14 +83,6 @@ struct BatchEngine {
 
 namespace {
 
-int max_lds_per_block() {
-  int dev = 0, v = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 65536;
-  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-    return 65536;
-  return v;
-}
-
 int cu_count() {
   int dev = 0, v = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;

@@ -365,10 +365,17 @@ struct CoarseHierarchy {
     double *dg = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;  // levels >= 1
     double *v = nullptr, *d = nullptr, *t = nullptr;  // right-hand side, correction, residual
     double *e = nullptr;  // levels >= 1: the coarse correction summed over the cycles
+    double *Pt = nullptr; // tail levels: precision messages kept between tail launches
     bool fresh = true;  // messages not yet set in this solve
     int swept = 0;      // sweeps of this level in this solve
   };
   std::vector<Level> lv;
+  // Levels tail.. (when tail > 0) have at most kTailThreads cells per grid
+  // and run inside one k_coarse_tail launch per visit of level tail - 1
+  // instead of a few hundred launches of their own; they have no plans.
+  // GABP_COARSE_TAIL=0 at plan time runs them as plans too.
+  int tail = 0;
+  bool tail_fresh = true;  // the tail's precision messages not yet set in this solve
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // Once every level has been set up in a solve and (with opts.freeze) has
   // settled its precisions, a correction is the same sequence of launches on
@@ -389,7 +396,7 @@ struct CoarseHierarchy {
     if (cs) (void)hipStreamDestroy(cs);
     for (Level &L : lv) {
       if (L.plan) gabp_plan_destroy(L.plan);
-      double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.t, L.e};
+      double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.t, L.e, L.Pt};
       for (double *b : bufs)
         if (b) (void)hipFree(b);
     }
@@ -400,13 +407,60 @@ struct CoarseHierarchy {
   double damping = 0.0;  // of every level's sweeps
   bool freeze = true;    // settle the precisions after kCoarseFreezeAfter sweeps
 
+  TailArgs tail_args(const Level &top) const {
+    TailArgs a{};
+    a.nlev = (int)lv.size() - tail;
+    a.batch = top.g.batch;
+    for (int l = 0; l < a.nlev; ++l) {
+      const Level &L = lv[tail + l];
+      a.lv[l] = TailLevel{L.g.nx, L.g.ny, L.g.nz, L.dg, L.cx, L.cy, L.cz, L.Pt};
+    }
+    a.rc = top.v;
+    a.e = top.e;
+    a.damping = damping;
+    a.scale = kCoarseScale;
+    a.colored = colored ? 1 : 0;
+    a.pre = kCoarsePre;
+    a.post = kCoarsePost;
+    a.coarse = kCoarseSweeps;
+    a.gamma = kCoarseGamma;
+    return a;
+  }
+
+  // the first level the tail kernel can take with every level below it
+  // (0: none)
+  static int tail_start(const std::vector<GridGeom> &shapes) {
+    const int nl = (int)shapes.size();
+    for (int l = 1; l < nl; ++l) {
+      if (nl - l > kTailMaxLevels) continue;
+      TailArgs a{};
+      a.nlev = nl - l;
+      bool fits = true;
+      for (int m = l; m < nl; ++m) {
+        const GridGeom &g = shapes[m];
+        fits = fits && (int64_t)g.nx * g.ny * g.nz <= kTailThreads;
+        a.lv[m - l].nx = g.nx; a.lv[m - l].ny = g.ny; a.lv[m - l].nz = g.nz;
+      }
+      if (fits && coarse_tail_lds(a) <= (size_t)max_lds_per_block()) return l;
+    }
+    return 0;
+  }
+
+  bool colored = false;
+
   int build(GridEngine *e0, hipStream_t s) {
     damping = e0->o.damping;
     freeze = e0->o.freeze != 0;
+    colored = e0->o.schedule == GABP_SCHEDULE_COLORED;
     if (const char *g = std::getenv("GABP_COARSE_GRAPH")) use_graph = std::strcmp(g, "0") != 0;
     if (e0->o.schedule == GABP_SCHEDULE_SYNC && damping == 0.0) damping = kCoarseSyncDamping;
     TRY_HIP(hipEventCreate(&ev0));
     TRY_HIP(hipEventCreate(&ev1));
+    std::vector<GridGeom> shapes{e0->g};
+    while ((int64_t)shapes.back().nx * shapes.back().ny * shapes.back().nz > kCoarseMaxCells)
+      shapes.push_back(coarse_geom(shapes.back()));
+    const char *te = std::getenv("GABP_COARSE_TAIL");
+    tail = (te && std::strcmp(te, "0") == 0) ? 0 : tail_start(shapes);
     Level L0;
     L0.eng = e0;
     L0.g = e0->g;
@@ -434,9 +488,13 @@ struct CoarseHierarchy {
       gabp_opts o = e0->o;
       o.damping = damping;
       lv.push_back(C);  // owned from here on (freed by the destructor)
-      const int rc = gabp_plan_create_grid(&Ag, &o, &lv.back().plan, s);
-      if (rc) return rc;
-      lv.back().eng = lv.back().plan->eng;
+      if (tail > 0 && (int)lv.size() - 1 >= tail) {
+        TRY_HIP(dalloc(&lv.back().Pt, (size_t)6 * C.g.N, sizeof(double)));
+      } else {
+        const int rc = gabp_plan_create_grid(&Ag, &o, &lv.back().plan, s);
+        if (rc) return rc;
+        lv.back().eng = lv.back().plan->eng;
+      }
       k = GridCoef<double>{C.dg, C.cx, C.cy, C.cz, 0.0, 0.0};
       varc = true;
     }
@@ -482,13 +540,21 @@ struct CoarseHierarchy {
     TRY_HIP(launch_coarse_restrict(L.g, C.g, L.t, C.v, s));
     // the coarse system: kCoarseGamma cycles of the next level, each on the
     // residual the previous ones left; their corrections summed in C.e
-    if ((rc = cycle(l + 1, s))) return rc;
-    TRY_HIP(hipMemcpyAsync(C.e, C.d, cbytes, hipMemcpyDeviceToDevice, s));
-    for (int g = 1; g < kCoarseGamma; ++g) {
-      TRY_HIP(C.eng->residual(C.v, C.e, C.t, s));  // C.t = rc - A_c e
-      TRY_HIP(hipMemcpyAsync(C.v, C.t, cbytes, hipMemcpyDeviceToDevice, s));
+    if (tail > 0 && l + 1 == tail) {
+      TailArgs a = tail_args(C);
+      a.sticky = lv[0].eng->sticky;
+      a.fresh = tail_fresh ? 1 : 0;
+      TRY_HIP(launch_coarse_tail(a, s));
+      tail_fresh = false;
+    } else {
       if ((rc = cycle(l + 1, s))) return rc;
-      TRY_HIP(launch_axpy(C.g.N, C.d, C.e, s));
+      TRY_HIP(hipMemcpyAsync(C.e, C.d, cbytes, hipMemcpyDeviceToDevice, s));
+      for (int g = 1; g < kCoarseGamma; ++g) {
+        TRY_HIP(C.eng->residual(C.v, C.e, C.t, s));  // C.t = rc - A_c e
+        TRY_HIP(hipMemcpyAsync(C.v, C.t, cbytes, hipMemcpyDeviceToDevice, s));
+        if ((rc = cycle(l + 1, s))) return rc;
+        TRY_HIP(launch_axpy(C.g.N, C.d, C.e, s));
+      }
     }
     TRY_HIP(launch_coarse_prolong(L.g, C.g, C.e, kCoarseScale, L.d, s));
     if (kCoarsePost > 0) {
@@ -502,8 +568,9 @@ struct CoarseHierarchy {
 // One correction d_0 = cycle(0): eager until the hierarchy is in its steady
 // state, then from the captured graph.
 int CoarseHierarchy::correction(hipStream_t s) {
-  bool steady = use_graph;
-  for (const Level &L : lv) steady = steady && !L.fresh && (!freeze || L.eng->frozen);
+  bool steady = use_graph && !(tail > 0 && tail_fresh);
+  for (const Level &L : lv)
+    if (L.eng) steady = steady && !L.fresh && (!freeze || L.eng->frozen);
   if (!steady) return cycle(0, s);
   if (!exec) {
     // record on a stream of our own (nothing runs while capturing); the
@@ -564,6 +631,7 @@ int coarse_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, ga
   }
   CoarseHierarchy &H = *p->coarse;
   for (auto &L : H.lv) L.fresh = true;
+  H.tail_fresh = true;
   // the plan's own sweeps smooth with the hierarchy's damping for this call
   struct Restore {
     GridEngine *e;

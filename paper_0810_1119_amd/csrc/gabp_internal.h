@@ -582,6 +582,30 @@ hipError_t launch_coarse_prolong(const GridGeom &f, const GridGeom &c, const dou
                                  double scale, double *d, hipStream_t s);
 hipError_t launch_axpy(int n, const double *d, double *x, hipStream_t s);  // x += d
 
+// The coarsest levels of a hierarchy in one launch (one workgroup of
+// kTailThreads per grid of the stack, every vector and message of those
+// levels in LDS, FP64 throughout): what the level above asks of them --
+// `gamma` cycles on the restricted residual rc, each on the residual the
+// previous ones left -- summed into e.
+constexpr int kTailThreads = 512;   // also the most cells per grid of a tail level
+constexpr int kTailMaxLevels = 8;
+struct TailLevel {
+  int nx, ny, nz;                    // per grid
+  const double *dg, *cx, *cy, *cz;   // Galerkin operator, grid layout of the stack
+  double *P;                         // precision messages kept between calls, [batch][6][n]
+};
+struct TailArgs {
+  int nlev, batch;
+  TailLevel lv[kTailMaxLevels];
+  const double *rc;  // the first tail level's right-hand side (grid layout of the stack)
+  double *e;         // its correction summed over the gamma cycles
+  uint32_t *sticky;  // FLAG_* bits
+  double damping, scale;
+  int colored, fresh, pre, post, coarse, gamma;
+};
+size_t coarse_tail_lds(const TailArgs &a);  // bytes of LDS per workgroup
+hipError_t launch_coarse_tail(const TailArgs &a, hipStream_t s);
+
 // ---- warm-start network (kernels_mlp.hip) ----
 struct MlpTrainArgs {
   const uint16_t *w;            // bfloat16 parameters used by the passes

@@ -92,7 +92,331 @@ __global__ void k_axpy(int n, const double *__restrict__ d, double *__restrict__
 
 dim3 blocks_for(int n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
+// ---------------------------------------------------------------------------
+// The coarsest levels in one launch
+// ---------------------------------------------------------------------------
+// Below a few hundred cells per grid a level's launches last a few
+// microseconds each and the W-cycle visits the coarsest level 2^(levels - 1)
+// times per correction, so the small levels' launches, not their sweeps, set
+// the time of a correction.  k_coarse_tail does everything the level above
+// asks of them in one workgroup per grid: each thread owns one cell of every
+// tail level; the GaBP messages are kept per receiving cell (slot d of cell i:
+// the message from its neighbour in direction d = +x, -x, +y, -y, +z, -z), so
+// a sending cell reads its own in-slots and writes the in-slot d ^ 1 of each
+// neighbour.  Arithmetic is FP64 whatever the plan's message precision.
+
+// Dynamic LDS of the tail kernel; a level is a set of offsets into it, 21
+// doubles per cell (so that every access is an LDS access).
+extern __shared__ double tail_sm[];
+constexpr int kTailDoublesPerCell = 21;
+
+struct TL {
+  int nx, ny, nz, n, zpar;  // zpar: parity of the grid's first plane in the stack
+  int P, h;                 // in-messages [6][n]
+  int dg, cx, cy, cz;
+  int V, D, T, RC, E;  // rhs, cycle result, work, restricted residual, summed result
+};
+
+__device__ __forceinline__ int tail_cells(const TailLevel &L) { return L.nx * L.ny * L.nz; }
+
+__device__ __forceinline__ TL tail_level(const TailArgs &a, int l, int t) {
+  int p = 0;
+  for (int m = 0; m < l; ++m) p += kTailDoublesPerCell * tail_cells(a.lv[m]);
+  TL L;
+  L.nx = a.lv[l].nx; L.ny = a.lv[l].ny; L.nz = a.lv[l].nz;
+  const int n = L.nx * L.ny * L.nz;
+  L.n = n;
+  L.zpar = (t * L.nz) & 1;  // the checkerboard counts z over the whole stack
+  L.P = p; L.h = p + 6 * n;
+  p += 12 * n;
+  L.dg = p; L.cx = p + n; L.cy = p + 2 * n; L.cz = p + 3 * n;
+  p += 4 * n;
+  L.V = p; L.D = p + n; L.T = p + 2 * n; L.RC = p + 3 * n; L.E = p + 4 * n;
+  return L;
+}
+
+// neighbour of cell i in direction d and their coupling (0: no edge)
+__device__ __forceinline__ void tail_edges(const TL &L, int i, int j[6], double a[6]) {
+  const double *S = tail_sm;
+  const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+  const int sy = L.nx, sz = L.nx * L.ny;
+  j[0] = i + 1;  a[0] = x < L.nx - 1 ? S[L.cx + i] : 0.0;
+  j[1] = i - 1;  a[1] = x > 0 ? S[L.cx + i - 1] : 0.0;
+  j[2] = i + sy; a[2] = y < L.ny - 1 ? S[L.cy + i] : 0.0;
+  j[3] = i - sy; a[3] = y > 0 ? S[L.cy + i - sy] : 0.0;
+  j[4] = i + sz; a[4] = z < L.nz - 1 ? S[L.cz + i] : 0.0;
+  j[5] = i - sz; a[5] = z > 0 ? S[L.cz + i - sz] : 0.0;
+}
+
+// the k-th cell of colour c (in the order of the grid layout; -1: none):
+// row r = (y, z) holds the cells x = 2 kx + ((c + y + z + zpar) & 1)
+__device__ __forceinline__ int tail_colour_cell(const TL &L, int c, int k) {
+  const int hx = (L.nx + 1) >> 1;
+  const int r = k / hx;
+  if (r >= L.ny * L.nz) return -1;
+  const int kx = k - r * hx, y = r % L.ny, z = r / L.ny;
+  const int x = 2 * kx + ((c + y + z + L.zpar) & 1);
+  return x < L.nx ? x + L.nx * r : -1;
+}
+
+// The out-messages of cell i from its in-slots (slots of absent edges hold
+// zeros: no one writes them); av: its couplings (0: no edge).
+__device__ __forceinline__ void tail_out(const TL &L, int i, const double av[6], int R,
+                                         double Pn[6], double hn[6], uint32_t &flags) {
+  const double *S_ = tail_sm;
+  const int n = L.n;
+  double Pi[6], hi[6], S = S_[L.dg + i], H = S_[R + i];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    Pi[d] = S_[L.P + d * n + i];
+    hi[d] = S_[L.h + d * n + i];
+    S += Pi[d];
+    H += hi[d];
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const double cav = S - Pi[d];
+    if (av[d] != 0.0 && cav == 0.0) flags |= FLAG_BREAKDOWN;
+    const double inv = 1.0 / cav;
+    Pn[d] = -(av[d] * av[d]) * inv;
+    hn[d] = -(av[d] * (H - hi[d])) * inv;
+  }
+}
+
+// the out-messages into the neighbours' in-slots d ^ 1, damped with the old
+// message of the same directed edge
+__device__ __forceinline__ void tail_put(const TL &L, int i, const double av[6], double al,
+                                         const double Pn[6], const double hn[6]) {
+  double *S_ = tail_sm;
+  const int n = L.n;
+  const int step[6] = {1, -1, L.nx, -L.nx, L.nx * L.ny, -L.nx * L.ny};
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    if (av[d] == 0.0) continue;
+    const int o = (d ^ 1) * n + i + step[d];
+    double P = Pn[d], h = hn[d];
+    if (al > 0.0) {
+      P = al * S_[L.P + o] + (1.0 - al) * P;
+      h = al * S_[L.h + o] + (1.0 - al) * h;
+    }
+    S_[L.P + o] = P;
+    S_[L.h + o] = h;
+  }
+}
+
+// D (= or +=) the means of `sweeps` GaBP sweeps on right-hand side R (an
+// offset) from zero information messages, the level's precision messages
+// kept.  Coloured: a thread takes the k-th cell of each colour, so that only
+// as many waves as a class has cells do the work of a half sweep.
+__device__ __forceinline__ void tail_smooth(const TL &L, int R, int sweeps, bool add,
+                                            const TailArgs &a, uint32_t &flags) {
+  double *S_ = tail_sm;
+  const int t = threadIdx.x, n = L.n;
+  int i0, i1;
+  if (a.colored) {
+    i0 = tail_colour_cell(L, 0, t);
+    i1 = tail_colour_cell(L, 1, t);
+  } else {
+    i0 = t < n ? t : -1;
+    i1 = -1;
+  }
+  double a0[6], a1[6];
+  int jj[6];
+  if (i0 >= 0) tail_edges(L, i0, jj, a0);
+  if (i1 >= 0) tail_edges(L, i1, jj, a1);
+  if (t < n) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) S_[L.h + d * n + t] = 0.0;
+  }
+  __syncthreads();
+  const double al = a.damping;
+  double Pn[6], hn[6];
+  for (int s = 0; s < sweeps; ++s) {
+    if (a.colored) {
+      // a class writes only the other class's in-slots
+      if (i0 >= 0) {
+        tail_out(L, i0, a0, R, Pn, hn, flags);
+        tail_put(L, i0, a0, al, Pn, hn);
+      }
+      __syncthreads();
+      if (i1 >= 0) {
+        tail_out(L, i1, a1, R, Pn, hn, flags);
+        tail_put(L, i1, a1, al, Pn, hn);
+      }
+      __syncthreads();
+    } else {
+      // every cell reads its in-slots before any is written
+      if (i0 >= 0) tail_out(L, i0, a0, R, Pn, hn, flags);
+      __syncthreads();
+      if (i0 >= 0) tail_put(L, i0, a0, al, Pn, hn);
+      __syncthreads();
+    }
+  }
+  if (t < n) {
+    double S = S_[L.dg + t], H = S_[R + t];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      S += S_[L.P + d * n + t];
+      H += S_[L.h + d * n + t];
+    }
+    if (S == 0.0) flags |= FLAG_BREAKDOWN;
+    const double m = H / S;
+    if (!isfinite(m)) flags |= FLAG_NONFINITE;
+    S_[L.D + t] = add ? S_[L.D + t] + m : m;
+  }
+  __syncthreads();
+}
+
+// out = R - A X (offsets)
+__device__ __forceinline__ void tail_residual(const TL &L, int R, int X, int out) {
+  double *S_ = tail_sm;
+  const int i = threadIdx.x;
+  if (i < L.n) {
+    int j[6];
+    double av[6];
+    tail_edges(L, i, j, av);
+    double s = S_[L.dg + i] * S_[X + i];
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+      if (av[d] != 0.0) s += av[d] * S_[X + j[d]];
+    S_[out + i] = S_[R + i] - s;
+  }
+  __syncthreads();
+}
+
+// C.RC = C.V = block sums of F.T (fixed order: z, y, x)
+__device__ __forceinline__ void tail_restrict(const TL &F, const TL &C) {
+  double *S_ = tail_sm;
+  const int I = threadIdx.x;
+  if (I < C.n) {
+    const int X = I % C.nx, Y = (I / C.nx) % C.ny, Z = I / (C.nx * C.ny);
+    const int sx = F.nx > 1 ? 2 : 1, sy = F.ny > 1 ? 2 : 1, sz = F.nz > 1 ? 2 : 1;
+    const int x0 = X * sx, y0 = Y * sy, z0 = Z * sz;
+    const int x1 = min(x0 + sx, F.nx), y1 = min(y0 + sy, F.ny), z1 = min(z0 + sz, F.nz);
+    double s = 0.0;
+    for (int z = z0; z < z1; ++z)
+      for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x) s += S_[F.T + x + F.nx * (y + F.ny * z)];
+    S_[C.RC + I] = s;
+    S_[C.V + I] = s;
+  }
+  __syncthreads();
+}
+
+// F.D += scale * C.E[block of the cell]
+__device__ __forceinline__ void tail_prolong(const TL &F, const TL &C, double scale) {
+  double *S_ = tail_sm;
+  const int i = threadIdx.x;
+  if (i < F.n) {
+    const int x = i % F.nx, y = (i / F.nx) % F.ny, z = i / (F.nx * F.ny);
+    const int sx = F.nx > 1 ? 2 : 1, sy = F.ny > 1 ? 2 : 1, sz = F.nz > 1 ? 2 : 1;
+    S_[F.D + i] += scale * S_[C.E + x / sx + C.nx * (y / sy + C.ny * (z / sz))];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
+  double *S_ = tail_sm;
+  const int t = blockIdx.x, i = threadIdx.x;
+  // the operators, the kept precision messages (zero at the start of a
+  // solve) and the right-hand side
+  for (int l = 0; l < a.nlev; ++l) {
+    const TL L = tail_level(a, l, t);
+    const TailLevel &G = a.lv[l];
+    const int n = L.n;
+    if (i < n) {
+      const size_t g = (size_t)t * n + i;
+      S_[L.dg + i] = G.dg[g];
+      S_[L.cx + i] = G.cx[g];
+      S_[L.cy + i] = G.cy[g];
+      S_[L.cz + i] = G.cz[g];
+#pragma unroll
+      for (int d = 0; d < 6; ++d)
+        S_[L.P + d * n + i] = a.fresh ? 0.0 : G.P[((size_t)t * 6 + d) * n + i];
+      if (l == 0) {
+        const double r = a.rc[g];
+        S_[L.RC + i] = r;
+        S_[L.V + i] = r;
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t flags = 0;
+  // The W-cycle without recursion: l is the level being worked on (uniform
+  // over the workgroup); cnt holds, 4 bits per level, how many cycles of that
+  // level its parent has started; `entering`: a cycle of l begins.  Level 0
+  // is driven by the caller's level: gamma cycles, then done.
+  uint32_t cnt = 1u;
+  int l = 0;
+  bool entering = true;
+  for (;;) {
+    const TL L = tail_level(a, l, t);
+    if (entering) {
+      if (l == a.nlev - 1) {
+        tail_smooth(L, L.V, a.coarse, false, a, flags);
+        entering = false;
+        continue;
+      }
+      tail_smooth(L, L.V, a.pre, false, a, flags);
+      tail_residual(L, L.V, L.D, L.T);
+      tail_restrict(L, tail_level(a, l + 1, t));
+      cnt = (cnt & ~(15u << (4 * (l + 1)))) | (1u << (4 * (l + 1)));
+      ++l;
+      continue;
+    }
+    // a cycle of level l is done (its result in D): sum it for the parent
+    const int k = (int)((cnt >> (4 * l)) & 15u);
+    if (i < L.n) S_[L.E + i] = k == 1 ? S_[L.D + i] : S_[L.E + i] + S_[L.D + i];
+    __syncthreads();
+    if (k < a.gamma) {
+      tail_residual(L, L.RC, L.E, L.V);  // the next cycle's right-hand side
+      cnt += 1u << (4 * l);
+      entering = true;
+      continue;
+    }
+    if (l == 0) break;
+    --l;
+    const TL F = tail_level(a, l, t);
+    tail_prolong(F, L, a.scale);
+    if (a.post > 0) {
+      tail_residual(F, F.V, F.D, F.T);
+      tail_smooth(F, F.T, a.post, true, a, flags);
+    }
+  }
+  // the result and the precision messages for the next call
+  for (int m = 0; m < a.nlev; ++m) {
+    const TL L = tail_level(a, m, t);
+    const int n = L.n;
+    if (i < n) {
+      if (m == 0) a.e[(size_t)t * n + i] = S_[L.E + i];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) a.lv[m].P[((size_t)t * 6 + d) * n + i] = S_[L.P + d * n + i];
+    }
+  }
+  if (flags) atomicOr(a.sticky, flags);
+}
+
 }  // namespace
+
+size_t coarse_tail_lds(const TailArgs &a) {
+  size_t cells = 0;
+  for (int l = 0; l < a.nlev; ++l) cells += (size_t)a.lv[l].nx * a.lv[l].ny * a.lv[l].nz;
+  return cells * kTailDoublesPerCell * sizeof(double);
+}
+
+hipError_t launch_coarse_tail(const TailArgs &a, hipStream_t s) {
+  if (a.batch <= 0) return hipSuccess;
+  if (a.nlev < 1 || a.nlev > kTailMaxLevels || a.gamma < 1 || a.gamma > 15)
+    return hipErrorInvalidValue;
+  for (int l = 0; l < a.nlev; ++l)
+    if ((int64_t)a.lv[l].nx * a.lv[l].ny * a.lv[l].nz > kTailThreads) return hipErrorInvalidValue;
+  const size_t lds = coarse_tail_lds(a);
+  hipError_t e = hipFuncSetAttribute((const void *)k_coarse_tail,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_coarse_tail, dim3((unsigned)a.batch), dim3(kTailThreads), lds, s, a);
+  return hipGetLastError();
+}
 
 GridGeom coarse_geom(const GridGeom &f) {
   GridGeom c{};

@@ -4,9 +4,14 @@
 FP64 messages: the x after each of the first cycles equals the oracle's
 (same levels, Galerkin operators, smoothing sweeps and scale) to 1e-9
 relative -- the levels' GaBP rounds agree to ~1e-11 per sweep as on the plain
-grid path, and a cycle adds a handful of FP64 sums.  FP32 messages: every
-grid of the stack meets the tolerance (its residual recomputed by the
+grid path, and a cycle adds a handful of FP64 sums.  Both ways of running
+the smallest levels are checked: inside one tail launch per visit (the
+default) and as plans of their own (GABP_COARSE_TAIL=0).  FP32 messages:
+every grid of the stack meets the tolerance (its residual recomputed by the
 oracle)."""
+import os
+from contextlib import contextmanager
+
 import numpy as np
 import pytest
 
@@ -44,18 +49,37 @@ def _grid(G, nx, ny, nz, batch, seed, varcoef=True):
     return A, arrs
 
 
+@contextmanager
+def env(name, value):
+    old = os.environ.get(name)
+    if value is None:
+        os.environ.pop(name, None)
+    else:
+        os.environ[name] = value
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop(name, None)
+        else:
+            os.environ[name] = old
+
+
 CASES = {
     "varcoef_16cubed_x2": (16, 16, 16, 2, True),
     "varcoef_odd_13x9x7_x3": (13, 9, 7, 3, True),
     "poisson2d_20x17": (20, 17, 1, 1, False),
+    # four levels below the finest one (500, 250, 125, 63 cells), all in the tail
+    "varcoef_1d_1000_x2": (1000, 1, 1, 2, True),
 }
 
 
+@pytest.mark.parametrize("tail", ["tail", "plans"])
 @pytest.mark.parametrize("case", sorted(CASES))
 @pytest.mark.parametrize("schedule", ["colored", "sync"])
-def test_cycles_match_oracle_fp64(G, case, schedule):
+def test_cycles_match_oracle_fp64(G, case, schedule, tail):
     nx, ny, nz, batch, varc = CASES[case]
-    print(f"case: coarse-grid cycles FP64 {case} {schedule}", flush=True)
+    print(f"case: coarse-grid cycles FP64 {case} {schedule} {tail}", flush=True)
     A, arrs = _grid(G, nx, ny, nz, batch, 3, varc)
     b = W.normal_b(A.n, 4)
     colored = schedule == "colored"
@@ -70,7 +94,8 @@ def test_cycles_match_oracle_fp64(G, case, schedule):
         rc, plan = G.gabp_plan_create_grid(A, o)
         assert rc == G.GABP_OK
         x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-        rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
+        with env("GABP_COARSE_TAIL", None if tail == "tail" else "0"):
+            rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
         G.gabp_plan_destroy(plan)
         assert rc == G.GABP_NOT_CONVERGED and st.restarts == k, (rc, st.restarts)
         xh = x.cpu().numpy()
@@ -146,6 +171,30 @@ def test_zero_rhs_and_other_plans(G):
                                       torch.zeros(m.n, dtype=torch.float64, device="cuda"))
     assert rc == G.GABP_ERR_UNSUPPORTED
     G.gabp_plan_destroy(pc)
+
+
+def test_tail_equals_plans_fp64(G):
+    """The smallest levels inside one launch give the corrections of the same
+    levels run as plans, to FP64 rounding, over a whole solve (freeze off:
+    the tail never settles its precisions)."""
+    print("case: coarse-grid tail vs plans, FP64 solve, 3 grids of 24^3", flush=True)
+    A, arrs = _grid(G, 24, 24, 24, 3, 14)
+    b = dev(W.normal_b(A.n, 15))
+    o = G.gabp_default_opts(msg_fp32=0, freeze=0, tol=1e-10,
+                            schedule=G.GABP_SCHEDULE_COLORED)
+    out = {}
+    for tail in ("tail", "plans"):
+        rc, p = G.gabp_plan_create_grid(A, o)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        with env("GABP_COARSE_TAIL", None if tail == "tail" else "0"):
+            rc, st = G.gabp_plan_solve_coarse(p, b, x)
+        G.gabp_plan_destroy(p)
+        assert rc == G.GABP_OK, (tail, G.status_name(rc))
+        out[tail] = (x.cpu().numpy(), st)
+        print(f"{tail}: {st.restarts} corrections, {st.seconds * 1e3:.1f} ms", flush=True)
+    assert out["tail"][1].restarts == out["plans"][1].restarts
+    xt, xp = out["tail"][0], out["plans"][0]
+    assert np.abs(xt - xp).max() <= 1e-9 * np.abs(xp).max()
 
 
 def test_graph_replays_equal_eager_corrections(G):
