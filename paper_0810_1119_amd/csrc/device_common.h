@@ -126,4 +126,26 @@ __device__ __forceinline__ void seg_compact(const SegCtl *seg, int nseg, int32_t
   if (threadIdx.x == 0) act[0] = base;
 }
 
+// Non-temporal (streaming) access: data read or written once per launch,
+// kept from displacing what the launch reads more than once.
+template <typename V>
+__device__ __forceinline__ V nt_load(const V *p) {
+  using E = decltype(p->x);
+  constexpr int N = sizeof(V) / sizeof(E);
+  typedef E vec __attribute__((ext_vector_type(N)));
+  const vec v = __builtin_nontemporal_load((const vec *)p);
+  V out;
+  __builtin_memcpy(&out, &v, sizeof(V));
+  return out;
+}
+template <typename V>
+__device__ __forceinline__ void nt_store(V *p, const V &x) {
+  using E = decltype(p->x);
+  constexpr int N = sizeof(V) / sizeof(E);
+  typedef E vec __attribute__((ext_vector_type(N)));
+  vec v;
+  __builtin_memcpy(&v, &x, sizeof(V));
+  __builtin_nontemporal_store(v, (vec *)p);
+}
+
 }  // namespace gabp

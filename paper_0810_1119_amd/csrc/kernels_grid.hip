@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(
         V out;
         out.x = P;
         out.y = h;
-        mout[(size_t)d * N + i] = out;
+        nt_store(&mout[(size_t)d * N + i], out);
       }
     }
     if (MODE >= 1) {
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_frozen(
         if (!nb.ok[d]) continue;
         T h = coef[(size_t)d * N + i] * (H - hin[d]);
         if (DAMP) h = alpha * hin_arr[(size_t)d * N + i] + (T(1) - alpha) * h;
-        hout_arr[(size_t)d * N + i] = h;
+        __builtin_nontemporal_store(h, &hout_arr[(size_t)d * N + i]);
       }
     }
     if (MODE >= 1) {

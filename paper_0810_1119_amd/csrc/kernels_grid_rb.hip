@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
         V out;
         out.x = P;
         out.y = h;
-        *slot = out;
+        nt_store(slot, out);  // read by the other colour's next launch, not this one
       }
     }
     if (MODE >= 1) {
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
         const size_t o = (size_t)d * Nc + s;
         T h = cf[o] * (H - hin[d]);
         if (DAMP) h = alpha * own[o] + (T(1) - alpha) * h;
-        own[o] = h;
+        __builtin_nontemporal_store(h, &own[o]);
       }
     }
     if (MODE >= 1) {

@@ -52,28 +52,6 @@ constexpr int kSegK = kSegChunk / kBlock;
 static_assert(kSegChunk % kBlock == 0 && kSegRows <= kBlock, "row block shape");
 
 
-// non-temporal (streaming) access to slot data: read or written once per
-// sweep, kept out of the way of the gathered node tables
-template <typename V>
-__device__ __forceinline__ V nt_load(const V *p) {
-  using E = decltype(p->x);
-  constexpr int N = sizeof(V) / sizeof(E);
-  typedef E vec __attribute__((ext_vector_type(N)));
-  const vec v = __builtin_nontemporal_load((const vec *)p);
-  V out;
-  __builtin_memcpy(&out, &v, sizeof(V));
-  return out;
-}
-template <typename V>
-__device__ __forceinline__ void nt_store(V *p, const V &x) {
-  using E = decltype(p->x);
-  constexpr int N = sizeof(V) / sizeof(E);
-  typedef E vec __attribute__((ext_vector_type(N)));
-  vec v;
-  __builtin_memcpy(&v, &x, sizeof(V));
-  __builtin_nontemporal_store(v, (vec *)p);
-}
-
 // the row of slot e: the last r with rp[r] <= e (rp[0] <= e < rp[nr])
 __device__ __forceinline__ int seg_row(const int *rp, int nr, int e) {
   int lo = 0, hi = nr;
