@@ -17,8 +17,10 @@ removes slowly.  Written plainly from the definitions below:
   information messages, the
   precision messages of that level's previous smoothing kept (zero at the
   start of a solve), and the marginal means of the final messages;
-* a cycle on level l with right-hand side v: d = smooth(v, nu_pre); on the
-  coarsest level that is all (with nu_coarse sweeps); otherwise, with
+* a cycle on level l with right-hand side v: on the coarsest level below
+  the finest, the exact solution of its Galerkin system (a dense solve of at
+  most 64 unknowns per grid); on a finest level that is already the
+  coarsest, nu_coarse GaBP sweeps; otherwise d = smooth(v, nu_pre), and with
   rc = P^T (v - A d), e = cycle(l + 1, rc) and then gamma - 1 more times
   e += cycle(l + 1, rc - A_c e) (gamma = 2: a W-cycle), d += scale * P e, and
   d += smooth(v - A d, nu_post);
@@ -29,6 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from . import Rounds, residual
 
@@ -140,7 +143,9 @@ def smooth(lev, v, sweeps):
 def cycle(H, l, v, nu_pre, nu_post, nu_coarse, scale, gamma=2):
     lev = H.levels[l]
     if "P" not in lev:
-        return smooth(lev, v, nu_coarse)
+        if l == 0:  # the grid is its own coarsest level: GaBP sweeps alone
+            return smooth(lev, v, nu_coarse)
+        return spla.spsolve(lev["A"].tocsc(), v)
     d = smooth(lev, v, nu_pre)
     r = v - lev["A"] @ d
     rc = lev["P"].T @ r

@@ -328,11 +328,15 @@ struct RbGridEngine : GridEngine {
 // messages, precisions of the level's previous sweeps kept) give d; the
 // residual of d, summed over 2 x 2 x 2 blocks, is the right-hand side of the
 // same procedure on the Galerkin operator of the next coarser grid, down to a
-// grid of at most 64 cells; the coarse correction, injected back and scaled,
-// is added; a few more GaBP sweeps on the remaining residual finish d.  Then
-// x += d, until every grid of the stack meets the tolerance.
+// grid of at most 64 cells, where the correction is the exact solution of the
+// Galerkin system (its dense inverse per grid, built once); the coarse
+// correction, injected back and scaled, is added; a few more GaBP sweeps on
+// the remaining residual finish d.  Then x += d, until every grid of the
+// stack meets the tolerance.  (A grid that is itself at most 64 cells is
+// corrected by kCoarseSweeps GaBP sweeps alone.)
 // ---------------------------------------------------------------------------
-constexpr int kCoarsePre = 4, kCoarsePost = 4, kCoarseSweeps = 24, kCoarseMaxCells = 64;
+constexpr int kCoarsePre = 4, kCoarsePost = 4, kCoarseSweeps = 24;
+constexpr int kCoarseMaxCells = kCoarsestCells;
 // Synchronous sweeps on a grid (a bipartite graph) do not damp the error mode
 // that alternates between the two colours, so as a smoother they need
 // damping: an undamped synchronous plan smooths with this factor (the FP64
@@ -366,6 +370,8 @@ struct CoarseHierarchy {
     double *v = nullptr, *d = nullptr, *t = nullptr;  // right-hand side, correction, residual
     double *e = nullptr;  // levels >= 1: the coarse correction summed over the cycles
     double *Pt = nullptr; // tail levels: precision messages kept between tail launches
+    double *inv = nullptr;  // the coarsest level (below the finest): inverse per grid
+    double *part = nullptr; // ... and the residual partials of its plan-less residual
     bool fresh = true;  // messages not yet set in this solve
     int swept = 0;      // sweeps of this level in this solve
   };
@@ -396,7 +402,7 @@ struct CoarseHierarchy {
     if (cs) (void)hipStreamDestroy(cs);
     for (Level &L : lv) {
       if (L.plan) gabp_plan_destroy(L.plan);
-      double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.t, L.e, L.Pt};
+      double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.t, L.e, L.Pt, L.inv, L.part};
       for (double *b : bufs)
         if (b) (void)hipFree(b);
     }
@@ -415,6 +421,7 @@ struct CoarseHierarchy {
       const Level &L = lv[tail + l];
       a.lv[l] = TailLevel{L.g.nx, L.g.ny, L.g.nz, L.dg, L.cx, L.cy, L.cz, L.Pt};
     }
+    a.inv = lv.back().inv;
     a.rc = top.v;
     a.e = top.e;
     a.damping = damping;
@@ -422,7 +429,6 @@ struct CoarseHierarchy {
     a.colored = colored ? 1 : 0;
     a.pre = kCoarsePre;
     a.post = kCoarsePost;
-    a.coarse = kCoarseSweeps;
     a.gamma = kCoarseGamma;
     return a;
   }
@@ -488,7 +494,23 @@ struct CoarseHierarchy {
       gabp_opts o = e0->o;
       o.damping = damping;
       lv.push_back(C);  // owned from here on (freed by the destructor)
-      if (tail > 0 && (int)lv.size() - 1 >= tail) {
+      const int64_t cells = (int64_t)C.g.nx * C.g.ny * C.g.nz;
+      if (cells <= kCoarseMaxCells) {
+        // the coarsest level: its inverse per grid, no messages
+        Level &Z = lv.back();
+        uint32_t *bad = nullptr;
+        TRY_HIP(dalloc(&Z.inv, (size_t)cells * cells * C.g.batch, sizeof(double)));
+        TRY_HIP(dalloc(&Z.part, residual_blocks(C.g), sizeof(double)));
+        TRY_HIP(dalloc(&bad, 1, sizeof(uint32_t)));
+        uint32_t hb = 0;
+        hipError_t e = launch_fill_zero4(bad, 1, s);
+        if (e == hipSuccess) e = launch_coarse_inverse(C.g, C.dg, C.cx, C.cy, C.cz, Z.inv, bad, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(bad);
+        TRY_HIP(e);
+        if (hb & FLAG_BREAKDOWN) return GABP_ERR_BREAKDOWN;  // a singular coarse system
+      } else if (tail > 0 && (int)lv.size() - 1 >= tail) {
         TRY_HIP(dalloc(&lv.back().Pt, (size_t)6 * C.g.N, sizeof(double)));
       } else {
         const int rc = gabp_plan_create_grid(&Ag, &o, &lv.back().plan, s);
@@ -527,11 +549,26 @@ struct CoarseHierarchy {
 
   int correction(hipStream_t s);
 
+  static int residual_blocks(const GridGeom &g) { return std::max(1, (g.N + kBlock - 1) / kBlock); }
+
+  // t = v - A_l x on a level (the coarsest has no plan: its own coefficients)
+  hipError_t level_residual(const Level &L, const double *v, const double *x, double *t,
+                            hipStream_t s) {
+    if (L.eng) return L.eng->residual(v, x, t, s);
+    const GridCoef<double> k{L.dg, L.cx, L.cy, L.cz, 0.0, 0.0};
+    return launch_grid_residual(L.g, k, true, residual_blocks(L.g), v, x, nullptr, false, t, L.part,
+                                s);
+  }
+
   // d_l from v_l: smoothing, coarse prediction, smoothing
   int cycle(int l, hipStream_t s) {
     Level &L = lv[l];
     TRY_HIP(launch_fill_zero(L.d, L.g.N, s));
-    if (l + 1 == (int)lv.size()) return smooth(l, L.v, kCoarseSweeps, s);
+    if (l + 1 == (int)lv.size()) {
+      if (l == 0) return smooth(l, L.v, kCoarseSweeps, s);  // the grid is its own coarsest level
+      TRY_HIP(launch_coarse_dense_solve(L.g, L.inv, L.v, L.d, s));
+      return GABP_OK;
+    }
     int rc = smooth(l, L.v, kCoarsePre, s);
     if (rc) return rc;
     Level &C = lv[l + 1];
@@ -550,7 +587,7 @@ struct CoarseHierarchy {
       if ((rc = cycle(l + 1, s))) return rc;
       TRY_HIP(hipMemcpyAsync(C.e, C.d, cbytes, hipMemcpyDeviceToDevice, s));
       for (int g = 1; g < kCoarseGamma; ++g) {
-        TRY_HIP(C.eng->residual(C.v, C.e, C.t, s));  // C.t = rc - A_c e
+        TRY_HIP(level_residual(C, C.v, C.e, C.t, s));  // C.t = rc - A_c e
         TRY_HIP(hipMemcpyAsync(C.v, C.t, cbytes, hipMemcpyDeviceToDevice, s));
         if ((rc = cycle(l + 1, s))) return rc;
         TRY_HIP(launch_axpy(C.g.N, C.d, C.e, s));

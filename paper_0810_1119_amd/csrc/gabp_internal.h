@@ -596,15 +596,26 @@ struct TailLevel {
 };
 struct TailArgs {
   int nlev, batch;
-  TailLevel lv[kTailMaxLevels];
-  const double *rc;  // the first tail level's right-hand side (grid layout of the stack)
-  double *e;         // its correction summed over the gamma cycles
-  uint32_t *sticky;  // FLAG_* bits
+  TailLevel lv[kTailMaxLevels];  // the last one is the coarsest level
+  const double *inv;  // the coarsest level's inverse per grid, [batch][n][n]
+  const double *rc;   // the first tail level's right-hand side (grid layout of the stack)
+  double *e;          // its correction summed over the gamma cycles
+  uint32_t *sticky;   // FLAG_* bits
   double damping, scale;
-  int colored, fresh, pre, post, coarse, gamma;
+  int colored, fresh, pre, post, gamma;
 };
 size_t coarse_tail_lds(const TailArgs &a);  // bytes of LDS per workgroup
 hipError_t launch_coarse_tail(const TailArgs &a, hipStream_t s);
+// The coarsest level (at most kCoarsestCells cells per grid) is solved
+// exactly: its dense inverse per grid by Gauss-Jordan elimination with
+// partial pivoting (once per hierarchy; FLAG_BREAKDOWN on a zero pivot), and
+// d = inverse * v per grid.
+constexpr int kCoarsestCells = 64;
+hipError_t launch_coarse_inverse(const GridGeom &c, const double *dg, const double *cx,
+                                 const double *cy, const double *cz, double *inv,
+                                 uint32_t *flags, hipStream_t s);
+hipError_t launch_coarse_dense_solve(const GridGeom &c, const double *inv, const double *v,
+                                     double *d, hipStream_t s);
 
 // ---- warm-start network (kernels_mlp.hip) ----
 struct MlpTrainArgs {

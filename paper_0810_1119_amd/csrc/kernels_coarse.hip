@@ -135,6 +135,13 @@ __device__ __forceinline__ TL tail_level(const TailArgs &a, int l, int t) {
   return L;
 }
 
+// the coarsest level's inverse follows every level's arrays
+__device__ __forceinline__ int tail_inverse_offset(const TailArgs &a) {
+  int p = 0;
+  for (int m = 0; m < a.nlev; ++m) p += kTailDoublesPerCell * tail_cells(a.lv[m]);
+  return p;
+}
+
 // neighbour of cell i in direction d and their coupling (0: no edge)
 __device__ __forceinline__ void tail_edges(const TL &L, int i, int j[6], double a[6]) {
   const double *S = tail_sm;
@@ -319,7 +326,7 @@ __global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
   double *S_ = tail_sm;
   const int t = blockIdx.x, i = threadIdx.x;
   // the operators, the kept precision messages (zero at the start of a
-  // solve) and the right-hand side
+  // solve), the coarsest inverse and the right-hand side
   for (int l = 0; l < a.nlev; ++l) {
     const TL L = tail_level(a, l, t);
     const TailLevel &G = a.lv[l];
@@ -330,9 +337,11 @@ __global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
       S_[L.cx + i] = G.cx[g];
       S_[L.cy + i] = G.cy[g];
       S_[L.cz + i] = G.cz[g];
+      if (l < a.nlev - 1) {
 #pragma unroll
-      for (int d = 0; d < 6; ++d)
-        S_[L.P + d * n + i] = a.fresh ? 0.0 : G.P[((size_t)t * 6 + d) * n + i];
+        for (int d = 0; d < 6; ++d)
+          S_[L.P + d * n + i] = a.fresh ? 0.0 : G.P[((size_t)t * 6 + d) * n + i];
+      }
       if (l == 0) {
         const double r = a.rc[g];
         S_[L.RC + i] = r;
@@ -340,6 +349,10 @@ __global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
       }
     }
   }
+  const TL Lc = tail_level(a, a.nlev - 1, t);
+  const int inv = tail_inverse_offset(a);
+  for (int k = i; k < Lc.n * Lc.n; k += kTailThreads)
+    S_[inv + k] = a.inv[(size_t)t * Lc.n * Lc.n + k];
   __syncthreads();
   uint32_t flags = 0;
   // The W-cycle without recursion: l is the level being worked on (uniform
@@ -353,7 +366,14 @@ __global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
     const TL L = tail_level(a, l, t);
     if (entering) {
       if (l == a.nlev - 1) {
-        tail_smooth(L, L.V, a.coarse, false, a, flags);
+        // the coarsest level: its exact solution
+        if (i < L.n) {
+          double d = 0.0;
+          for (int j = 0; j < L.n; ++j) d += S_[inv + i * L.n + j] * S_[L.V + j];
+          if (!isfinite(d)) flags |= FLAG_NONFINITE;
+          S_[L.D + i] = d;
+        }
+        __syncthreads();
         entering = false;
         continue;
       }
@@ -389,11 +409,95 @@ __global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
     const int n = L.n;
     if (i < n) {
       if (m == 0) a.e[(size_t)t * n + i] = S_[L.E + i];
+      if (m < a.nlev - 1) {
 #pragma unroll
-      for (int d = 0; d < 6; ++d) a.lv[m].P[((size_t)t * 6 + d) * n + i] = S_[L.P + d * n + i];
+        for (int d = 0; d < 6; ++d) a.lv[m].P[((size_t)t * 6 + d) * n + i] = S_[L.P + d * n + i];
+      }
     }
   }
   if (flags) atomicOr(a.sticky, flags);
+}
+
+// The coarsest level's dense matrix per grid, inverted by Gauss-Jordan
+// elimination with partial pivoting on [M | I] in LDS: one workgroup per
+// grid, thread r owns row r.
+__global__ __launch_bounds__(kCoarsestCells) void k_coarse_inverse(
+    GridGeom c, const double *__restrict__ dg, const double *__restrict__ cx,
+    const double *__restrict__ cy, const double *__restrict__ cz, double *__restrict__ inv,
+    uint32_t *__restrict__ flags) {
+  extern __shared__ double gj[];
+  __shared__ int piv;
+  __shared__ double pval;
+  const int n = c.nx * c.ny * c.nz, w = 2 * n + 1;  // row stride (padded)
+  const int t = blockIdx.x, r = threadIdx.x;
+  if (r < n) {
+    for (int j = 0; j < 2 * n; ++j) gj[r * w + j] = 0.0;
+    const size_t g = (size_t)t * n + r;
+    const int x = r % c.nx, y = (r / c.nx) % c.ny, z = r / (c.nx * c.ny);
+    const int sy = c.nx, sz = c.nx * c.ny;
+    gj[r * w + r] = dg[g];
+    if (x < c.nx - 1) gj[r * w + r + 1] = cx[g];
+    if (x > 0) gj[r * w + r - 1] = cx[g - 1];
+    if (y < c.ny - 1) gj[r * w + r + sy] = cy[g];
+    if (y > 0) gj[r * w + r - sy] = cy[g - sy];
+    if (z < c.nz - 1) gj[r * w + r + sz] = cz[g];
+    if (z > 0) gj[r * w + r - sz] = cz[g - sz];
+    gj[r * w + n + r] = 1.0;
+  }
+  __syncthreads();
+  bool ok = true;
+  for (int k = 0; k < n; ++k) {
+    if (r == 0) {
+      int p = k;
+      double best = fabs(gj[k * w + k]);
+      for (int q = k + 1; q < n; ++q)
+        if (fabs(gj[q * w + k]) > best) {
+          best = fabs(gj[q * w + k]);
+          p = q;
+        }
+      piv = p;
+      pval = gj[p * w + k];
+    }
+    __syncthreads();
+    const int p = piv;
+    const double pv = pval;
+    if (pv == 0.0) {  // singular: the coarse system has no solution
+      ok = false;
+      break;
+    }
+    // swap rows k and p, scale the pivot row
+    for (int j = r; j < 2 * n; j += blockDim.x) {
+      const double a = gj[k * w + j], b = gj[p * w + j];
+      gj[k * w + j] = b / pv;
+      if (p != k) gj[p * w + j] = a;
+    }
+    __syncthreads();
+    if (r < n && r != k) {
+      const double f = gj[r * w + k];
+      if (f != 0.0)
+        for (int j = 0; j < 2 * n; ++j) gj[r * w + j] -= f * gj[k * w + j];
+    }
+    __syncthreads();
+  }
+  if (!ok) {
+    if (r == 0) atomicOr(flags, (uint32_t)FLAG_BREAKDOWN);
+    return;
+  }
+  for (int k = r; k < n * n; k += blockDim.x)
+    inv[(size_t)t * n * n + k] = gj[(k / n) * w + n + k % n];
+}
+
+// d = inverse * v on every grid of the coarsest level
+__global__ __launch_bounds__(kCoarsestCells) void k_coarse_dense_solve(
+    GridGeom c, const double *__restrict__ inv, const double *__restrict__ v,
+    double *__restrict__ d) {
+  const int n = c.nx * c.ny * c.nz, t = blockIdx.x, r = threadIdx.x;
+  if (r >= n) return;
+  const double *row = inv + ((size_t)t * n + r) * n;
+  const double *vt = v + (size_t)t * n;
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) s += row[j] * vt[j];
+  d[(size_t)t * n + r] = s;
 }
 
 }  // namespace
@@ -401,12 +505,40 @@ __global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
 size_t coarse_tail_lds(const TailArgs &a) {
   size_t cells = 0;
   for (int l = 0; l < a.nlev; ++l) cells += (size_t)a.lv[l].nx * a.lv[l].ny * a.lv[l].nz;
-  return cells * kTailDoublesPerCell * sizeof(double);
+  const size_t nc = (size_t)a.lv[a.nlev - 1].nx * a.lv[a.nlev - 1].ny * a.lv[a.nlev - 1].nz;
+  return (cells * kTailDoublesPerCell + nc * nc) * sizeof(double);
+}
+
+hipError_t launch_coarse_inverse(const GridGeom &c, const double *dg, const double *cx,
+                                 const double *cy, const double *cz, double *inv,
+                                 uint32_t *flags, hipStream_t s) {
+  const int n = c.nx * c.ny * c.nz;
+  if (c.batch <= 0 || n <= 0) return hipSuccess;
+  if (n > kCoarsestCells) return hipErrorInvalidValue;
+  const size_t lds = (size_t)n * (2 * n + 1) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void *)k_coarse_inverse,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_coarse_inverse, dim3((unsigned)c.batch), dim3(kCoarsestCells), lds, s, c,
+                     dg, cx, cy, cz, inv, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_dense_solve(const GridGeom &c, const double *inv, const double *v,
+                                     double *d, hipStream_t s) {
+  const int n = c.nx * c.ny * c.nz;
+  if (c.batch <= 0 || n <= 0) return hipSuccess;
+  if (n > kCoarsestCells) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_coarse_dense_solve, dim3((unsigned)c.batch), dim3(kCoarsestCells), 0, s, c,
+                     inv, v, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_coarse_tail(const TailArgs &a, hipStream_t s) {
   if (a.batch <= 0) return hipSuccess;
-  if (a.nlev < 1 || a.nlev > kTailMaxLevels || a.gamma < 1 || a.gamma > 15)
+  if (a.nlev < 1 || a.nlev > kTailMaxLevels || a.gamma < 1 || a.gamma > 15 || !a.inv)
+    return hipErrorInvalidValue;
+  if ((int64_t)a.lv[a.nlev - 1].nx * a.lv[a.nlev - 1].ny * a.lv[a.nlev - 1].nz > kCoarsestCells)
     return hipErrorInvalidValue;
   for (int l = 0; l < a.nlev; ++l)
     if ((int64_t)a.lv[l].nx * a.lv[l].ny * a.lv[l].nz > kTailThreads) return hipErrorInvalidValue;

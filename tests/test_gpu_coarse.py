@@ -69,7 +69,8 @@ CASES = {
     "varcoef_16cubed_x2": (16, 16, 16, 2, True),
     "varcoef_odd_13x9x7_x3": (13, 9, 7, 3, True),
     "poisson2d_20x17": (20, 17, 1, 1, False),
-    # four levels below the finest one (500, 250, 125, 63 cells), all in the tail
+    # four levels below the finest one (500, 250, 125, 63 cells), the last
+    # three in the tail (all four would not fit the LDS with the inverse)
     "varcoef_1d_1000_x2": (1000, 1, 1, 2, True),
 }
 

@@ -3,7 +3,9 @@
 The Galerkin coarse operator against a brute-force sum over the fine matrix's
 entries (pure Python on tiny grids with odd extents), its row sums and
 stencil shape (closed forms), the adjointness of restriction and
-prolongation, the level count, and the solve against a direct sparse solve."""
+prolongation, the level count, the coarsest correction as the exact solution
+of its system (its residual at rounding level), and the solve against a
+direct sparse solve."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spl
@@ -96,3 +98,20 @@ def test_solve_matches_direct_solution():
     # each cycle contracts the residual: a predicted correction, not a restart
     res = [np.linalg.norm(b - A @ xk) for xk in trail]
     assert all(r1 < 0.5 * r0 for r0, r1 in zip(res, res[1:]))
+
+
+def test_coarsest_correction_is_exact():
+    """Below the finest level the coarsest correction solves its Galerkin
+    system exactly: A_c e = rc to rounding, on every grid of the stack."""
+    nx, ny, nz, batch = 9, 7, 6, 3
+    coef = _stack(nx, ny, nz, batch, 8)
+    H = OC.Hierarchy(nx, ny, nz, batch, coef["diag"], coef["cx"], coef["cy"], coef["cz"])
+    assert len(H.levels) == 2
+    last = H.levels[-1]
+    rc = np.random.default_rng(3).standard_normal(last["A"].shape[0])
+    e = OC.cycle(H, 1, rc, 4, 4, 24, 1.8)
+    r = rc - last["A"] @ e
+    assert np.abs(r).max() <= 1e-12 * np.abs(rc).max()
+    # while 24 GaBP sweeps on the same system leave a visible residual
+    g = OC.smooth(dict(last, P_msg=None), rc, 24)
+    assert np.abs(rc - last["A"] @ g).max() > 1e3 * np.abs(r).max()
