@@ -34,6 +34,13 @@ inline int from_hip_at(hipError_t e, const char *file, int line) {
 // ABI starts by clearing it.
 inline void clear_stale_error() { (void)hipGetLastError(); }
 
+// inside functions that return hipError_t
+#define TRY_HIP_E(expr)                \
+  do {                                 \
+    hipError_t _e = (expr);            \
+    if (_e != hipSuccess) return _e;   \
+  } while (0)
+
 #define TRY_HIP(expr)                          \
   do {                                         \
     hipError_t _e = (expr);                    \
@@ -111,6 +118,15 @@ struct Engine {
   virtual hipError_t infer(double *xacc, double *marg, void *means, hipStream_t s) = 0;
   // zero every information message, keep the precisions (rhs already holds r)
   virtual hipError_t restart(hipStream_t s) = 0;
+  // the same, left to the next sweep where the engine can (that sweep takes
+  // the informations as zero); anything else that reads messages first
+  // carries the restart out
+  virtual hipError_t restart_lazy(hipStream_t s) { return restart(s); }
+  // x = H/S (FP64) from the current messages
+  virtual hipError_t infer_set(double *x, hipStream_t s) {
+    hipError_t e = launch_fill_zero(x, n, s);
+    return e != hipSuccess ? e : infer(x, nullptr, nullptr, s);
+  }
   // zero all messages, rhs = b, full state; ||b||^2 into the residual partials
   virtual hipError_t reset(const double *b, hipStream_t s) = 0;
   // rhs = b - A x (FP64, optionally r64 = the same), ||.||^2 into the partials

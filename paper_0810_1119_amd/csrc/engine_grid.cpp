@@ -72,6 +72,7 @@ struct GridEngine : Engine {
   void *rhs = nullptr;
   void *msg[2] = {nullptr, nullptr};  // (P, h)[6][N]
   void *coef = nullptr, *hh[2] = {nullptr, nullptr}, *Sfix = nullptr;  // frozen
+  bool hzero = false;  // a restart left to the next sweep (restart_lazy)
 
   ~GridEngine() override {
     void *bufs[] = {wdiag, wcx, wcy, wcz, rhs, msg[0], msg[1], coef, hh[0], hh[1], Sfix};
@@ -93,16 +94,28 @@ struct GridEngine : Engine {
     return a;
   }
 
+  // a pending restart, carried out before anything but a sweep reads messages
+  hipError_t settle_restart(hipStream_t s) { return hzero ? restart(s) : hipSuccess; }
+
+  hipError_t restart_lazy(hipStream_t) override {
+    hzero = true;
+    return hipSuccess;
+  }
+
   hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
     GridArgs a = args(mode, c);
     a.msg_in = frozen ? hh[cur] : msg[cur];
     a.msg_out = frozen ? hh[cur ^ 1] : msg[cur ^ 1];
+    // both the in-messages and a node's previous out-messages are in msg_in
+    a.fl = hzero ? (SWEEP_ZIN | SWEEP_ZOWN) : 0;
+    hzero = false;
     hipError_t err = launch_grid_sweep(a, s);
     cur ^= 1;
     return err;
   }
 
   hipError_t infer(double *xacc, double *marg, void *means, hipStream_t s) override {
+    TRY_HIP_E(settle_restart(s));
     GridArgs a = args(2, nullptr);
     a.msg_in = frozen ? hh[cur] : msg[cur];
     a.xacc = xacc;
@@ -111,7 +124,17 @@ struct GridEngine : Engine {
     return launch_grid_sweep(a, s);
   }
 
+  hipError_t infer_set(double *x, hipStream_t s) override {
+    TRY_HIP_E(settle_restart(s));
+    GridArgs a = args(2, nullptr);
+    a.msg_in = frozen ? hh[cur] : msg[cur];
+    a.xacc = x;
+    a.fl = SWEEP_XSET;
+    return launch_grid_sweep(a, s);
+  }
+
   hipError_t restart(hipStream_t s) override {
+    hzero = false;
     if (frozen) return fp32 ? launch_fill_zero4(hh[cur], slots(), s) : launch_fill_zero(hh[cur], slots(), s);
     return launch_grid_zero_h(fp32, slots(), msg[cur], s);
   }
@@ -119,6 +142,7 @@ struct GridEngine : Engine {
   hipError_t reset(const double *b, hipStream_t s) override {
     cur = 0;
     frozen = false;
+    hzero = false;
     const int64_t words = slots() * (int64_t)(2 * tsz) / 8;
     hipError_t err;
     if ((err = launch_fill_zero(msg[0], words, s)) != hipSuccess) return err;
@@ -134,6 +158,7 @@ struct GridEngine : Engine {
   hipError_t warm_start(const uint16_t *w, hipStream_t s) override {
     cur = 0;
     frozen = false;
+    hzero = false;
     return launch_grid_warm(fp32, g, varc ? wdiag : nullptr, varc ? wcx : nullptr,
                             varc ? wcy : nullptr, varc ? wcz : nullptr, A.diag_value, A.off_value,
                             rhs, w, msg[0], s);
@@ -156,6 +181,7 @@ struct GridEngine : Engine {
   bool frozen_ready() const override { return coef && hh[0] && hh[1] && Sfix; }
 
   hipError_t freeze(hipStream_t s) override {
+    TRY_HIP_E(settle_restart(s));
     GridArgs a = args(0, nullptr);
     a.msg_in = msg[cur];
     a.msg_out = hh[cur];
@@ -166,6 +192,7 @@ struct GridEngine : Engine {
 
   int get_messages(double *P, double *h, hipStream_t s) override {
     if (!P || !h) return GABP_ERR_ARG;
+    TRY_HIP(settle_restart(s));
     TRY_HIP(launch_grid_io(fp32, true, slots(), msg[cur], P, h, s));
     TRY_HIP(hipStreamSynchronize(s));
     return GABP_OK;
@@ -173,6 +200,7 @@ struct GridEngine : Engine {
 
   int set_messages(const double *P, const double *h, hipStream_t s) override {
     if (!P || !h) return GABP_ERR_ARG;
+    hzero = false;
     TRY_HIP(launch_grid_io(fp32, false, slots(), msg[cur], (double *)P, (double *)h, s));
     TRY_HIP(hipStreamSynchronize(s));
     return GABP_OK;
@@ -238,14 +266,33 @@ struct RbGridEngine : GridEngine {
   }
 
   hipError_t sweep(int mode, const Ctl *c, hipStream_t s) override {
+    // after a pending restart colour 0 reads zero informations of colour 1;
+    // colour 1 then reads colour 0's new ones; neither has old ones to damp with
+    const bool z = hzero;
+    hzero = false;
     for (int colour = 0; colour < 2; ++colour) {
-      hipError_t err = launch_rb_sweep(rargs(mode, colour, c), s);
+      RbArgs a = rargs(mode, colour, c);
+      a.fl = z ? (colour == 0 ? SWEEP_ZIN | SWEEP_ZOWN : SWEEP_ZOWN) : 0;
+      hipError_t err = launch_rb_sweep(a, s);
+      if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+  }
+
+  hipError_t infer_set(double *x, hipStream_t s) override {
+    TRY_HIP_E(settle_restart(s));
+    for (int colour = 0; colour < 2; ++colour) {
+      RbArgs a = rargs(2, colour, nullptr);
+      a.xacc = x;
+      a.fl = SWEEP_XSET;
+      hipError_t err = launch_rb_sweep(a, s);
       if (err != hipSuccess) return err;
     }
     return hipSuccess;
   }
 
   hipError_t infer(double *xacc, double *marg, void *means, hipStream_t s) override {
+    TRY_HIP_E(settle_restart(s));
     for (int colour = 0; colour < 2; ++colour) {
       RbArgs a = rargs(2, colour, nullptr);
       a.xacc = xacc;
@@ -258,12 +305,14 @@ struct RbGridEngine : GridEngine {
   }
 
   hipError_t restart(hipStream_t s) override {
+    hzero = false;
     if (frozen) return fp32 ? launch_fill_zero4(hh[0], rb_slots(), s) : launch_fill_zero(hh[0], rb_slots(), s);
     return launch_grid_zero_h(fp32, rb_slots(), msg[0], s);
   }
 
   hipError_t reset(const double *b, hipStream_t s) override {
     frozen = false;
+    hzero = false;
     hipError_t err = launch_fill_zero(msg[0], rb_slots() * (int64_t)(2 * tsz) / 8, s);
     if (err != hipSuccess) return err;
     return launch_grid_residual(g, k64, varc, nsum, b, nullptr, rhs, fp32, nullptr, sumpart, s, hx, nseg);
@@ -275,6 +324,7 @@ struct RbGridEngine : GridEngine {
 
   hipError_t warm_start(const uint16_t *w, hipStream_t s) override {
     frozen = false;
+    hzero = false;
     // slots of unused positions and of faces without a coupling stay zero
     hipError_t err = launch_fill_zero(msg[0], rb_slots() * (int64_t)(2 * tsz) / 8, s);
     if (err != hipSuccess) return err;
@@ -297,6 +347,7 @@ struct RbGridEngine : GridEngine {
   bool frozen_ready() const override { return coef && hh[0] && Sfix; }
 
   hipError_t freeze(hipStream_t s) override {
+    TRY_HIP_E(settle_restart(s));
     RbArgs a = rargs(0, 0, nullptr);
     a.msg = msg[0];
     hipError_t err = launch_rb_freeze(a, hh[0], s);
@@ -306,6 +357,7 @@ struct RbGridEngine : GridEngine {
 
   int get_messages(double *P, double *h, hipStream_t s) override {
     if (!P || !h) return GABP_ERR_ARG;
+    TRY_HIP(settle_restart(s));
     TRY_HIP(launch_rb_io(fp32, true, g, hx, Nc, msg[0], P, h, s));
     TRY_HIP(hipStreamSynchronize(s));
     return GABP_OK;
@@ -313,6 +365,7 @@ struct RbGridEngine : GridEngine {
 
   int set_messages(const double *P, const double *h, hipStream_t s) override {
     if (!P || !h) return GABP_ERR_ARG;
+    hzero = false;
     TRY_HIP(launch_rb_io(fp32, false, g, hx, Nc, msg[0], (double *)P, (double *)h, s));
     TRY_HIP(hipStreamSynchronize(s));
     return GABP_OK;
@@ -367,11 +420,12 @@ struct CoarseHierarchy {
     Engine *eng = nullptr;
     GridGeom g{};
     double *dg = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;  // levels >= 1
-    double *v = nullptr, *d = nullptr, *t = nullptr;  // right-hand side, correction, residual
+    double *v = nullptr, *d = nullptr;  // right-hand side, correction
     double *e = nullptr;  // levels >= 1: the coarse correction summed over the cycles
     double *Pt = nullptr; // tail levels: precision messages kept between tail launches
     double *inv = nullptr;  // the coarsest level (below the finest): inverse per grid
-    double *part = nullptr; // ... and the residual partials of its plan-less residual
+    GridCoef<double> k{};   // the level's FP64 operator
+    bool varc = true;
     bool fresh = true;  // messages not yet set in this solve
     int swept = 0;      // sweeps of this level in this solve
   };
@@ -402,7 +456,7 @@ struct CoarseHierarchy {
     if (cs) (void)hipStreamDestroy(cs);
     for (Level &L : lv) {
       if (L.plan) gabp_plan_destroy(L.plan);
-      double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.t, L.e, L.Pt, L.inv, L.part};
+      double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.e, L.Pt, L.inv};
       for (double *b : bufs)
         if (b) (void)hipFree(b);
     }
@@ -470,6 +524,8 @@ struct CoarseHierarchy {
     Level L0;
     L0.eng = e0;
     L0.g = e0->g;
+    L0.k = e0->k64;
+    L0.varc = e0->varc;
     lv.push_back(L0);
     GridCoef<double> k = e0->k64;
     bool varc = e0->varc;
@@ -477,7 +533,6 @@ struct CoarseHierarchy {
       Level &F = lv.back();
       TRY_HIP(dalloc(&F.v, F.g.N, sizeof(double)));
       TRY_HIP(dalloc(&F.d, F.g.N, sizeof(double)));
-      TRY_HIP(dalloc(&F.t, F.g.N, sizeof(double)));
       if (lv.size() > 1) TRY_HIP(dalloc(&F.e, F.g.N, sizeof(double)));
       if ((int64_t)F.g.nx * F.g.ny * F.g.nz <= kCoarseMaxCells) break;
       Level C;
@@ -493,6 +548,8 @@ struct CoarseHierarchy {
       Ag.diag = C.dg; Ag.cx = C.cx; Ag.cy = C.cy; Ag.cz = C.cz;
       gabp_opts o = e0->o;
       o.damping = damping;
+      C.k = GridCoef<double>{C.dg, C.cx, C.cy, C.cz, 0.0, 0.0};
+      C.varc = true;
       lv.push_back(C);  // owned from here on (freed by the destructor)
       const int64_t cells = (int64_t)C.g.nx * C.g.ny * C.g.nz;
       if (cells <= kCoarseMaxCells) {
@@ -500,7 +557,6 @@ struct CoarseHierarchy {
         Level &Z = lv.back();
         uint32_t *bad = nullptr;
         TRY_HIP(dalloc(&Z.inv, (size_t)cells * cells * C.g.batch, sizeof(double)));
-        TRY_HIP(dalloc(&Z.part, residual_blocks(C.g), sizeof(double)));
         TRY_HIP(dalloc(&bad, 1, sizeof(uint32_t)));
         uint32_t hb = 0;
         hipError_t e = launch_fill_zero4(bad, 1, s);
@@ -524,9 +580,10 @@ struct CoarseHierarchy {
     return GABP_OK;
   }
 
-  // d_l += the means of `sweeps` GaBP sweeps on right-hand side v (NULL: the
-  // engine already holds it), from zero information messages
-  int smooth(int l, const double *v, int sweeps, hipStream_t s) {
+  // d_l (set: =, else +=) the means of `sweeps` GaBP sweeps on right-hand
+  // side v (NULL: the engine already holds it), from zero information
+  // messages (zeroed by the first sweep itself)
+  int smooth(int l, const double *v, int sweeps, bool set, hipStream_t s) {
     Level &L = lv[l];
     if (v && L.fresh) {
       TRY_HIP(L.eng->reset(v, s));
@@ -534,47 +591,36 @@ struct CoarseHierarchy {
       L.swept = 0;
     } else {
       if (v) TRY_HIP(L.eng->residual(v, nullptr, nullptr, s));
-      TRY_HIP(L.eng->restart(s));  // zero informations (after a freeze: the settled ones)
+      TRY_HIP(L.eng->restart_lazy(s));  // zero informations (after a freeze: the settled ones)
     }
     if (freeze && !L.eng->frozen && L.swept >= kCoarseFreezeAfter) {
       TRY_HIP(L.eng->ensure_frozen_buffers());
       TRY_HIP(L.eng->freeze(s));
-      TRY_HIP(L.eng->restart(s));
+      TRY_HIP(L.eng->restart_lazy(s));
     }
     for (int k = 0; k < sweeps; ++k) TRY_HIP(L.eng->sweep(0, nullptr, s));
     L.swept += sweeps;
-    TRY_HIP(L.eng->infer(L.d, nullptr, nullptr, s));
+    if (set) TRY_HIP(L.eng->infer_set(L.d, s));
+    else TRY_HIP(L.eng->infer(L.d, nullptr, nullptr, s));
     return GABP_OK;
   }
 
   int correction(hipStream_t s);
 
-  static int residual_blocks(const GridGeom &g) { return std::max(1, (g.N + kBlock - 1) / kBlock); }
-
-  // t = v - A_l x on a level (the coarsest has no plan: its own coefficients)
-  hipError_t level_residual(const Level &L, const double *v, const double *x, double *t,
-                            hipStream_t s) {
-    if (L.eng) return L.eng->residual(v, x, t, s);
-    const GridCoef<double> k{L.dg, L.cx, L.cy, L.cz, 0.0, 0.0};
-    return launch_grid_residual(L.g, k, true, residual_blocks(L.g), v, x, nullptr, false, t, L.part,
-                                s);
-  }
 
   // d_l from v_l: smoothing, coarse prediction, smoothing
   int cycle(int l, hipStream_t s) {
     Level &L = lv[l];
-    TRY_HIP(launch_fill_zero(L.d, L.g.N, s));
     if (l + 1 == (int)lv.size()) {
-      if (l == 0) return smooth(l, L.v, kCoarseSweeps, s);  // the grid is its own coarsest level
+      if (l == 0) return smooth(l, L.v, kCoarseSweeps, true, s);  // its own coarsest level
       TRY_HIP(launch_coarse_dense_solve(L.g, L.inv, L.v, L.d, s));
       return GABP_OK;
     }
-    int rc = smooth(l, L.v, kCoarsePre, s);
+    int rc = smooth(l, L.v, kCoarsePre, true, s);
     if (rc) return rc;
     Level &C = lv[l + 1];
-    const size_t cbytes = (size_t)C.g.N * sizeof(double);
-    TRY_HIP(L.eng->residual(L.v, L.d, L.t, s));
-    TRY_HIP(launch_coarse_restrict(L.g, C.g, L.t, C.v, s));
+    // the next level's right-hand side P^T (v - A d)
+    TRY_HIP(launch_coarse_residual_restrict(L.g, L.k, L.varc, C.g, L.v, L.d, C.v, s));
     // the coarse system: kCoarseGamma cycles of the next level, each on the
     // residual the previous ones left; their corrections summed in C.e
     if (tail > 0 && l + 1 == tail) {
@@ -584,19 +630,17 @@ struct CoarseHierarchy {
       TRY_HIP(launch_coarse_tail(a, s));
       tail_fresh = false;
     } else {
+      static_assert(kCoarseGamma == 2, "the second cycle's right-hand side below assumes two");
       if ((rc = cycle(l + 1, s))) return rc;
-      TRY_HIP(hipMemcpyAsync(C.e, C.d, cbytes, hipMemcpyDeviceToDevice, s));
-      for (int g = 1; g < kCoarseGamma; ++g) {
-        TRY_HIP(level_residual(C, C.v, C.e, C.t, s));  // C.t = rc - A_c e
-        TRY_HIP(hipMemcpyAsync(C.v, C.t, cbytes, hipMemcpyDeviceToDevice, s));
-        if ((rc = cycle(l + 1, s))) return rc;
-        TRY_HIP(launch_axpy(C.g.N, C.d, C.e, s));
-      }
+      // e = d, and the second cycle on what the first left: v_c = rc - A_c e
+      TRY_HIP(launch_coarse_copy_residual(C.g, C.k, C.varc, C.d, C.e, C.v, s));
+      if ((rc = cycle(l + 1, s))) return rc;
+      TRY_HIP(launch_axpy(C.g.N, C.d, C.e, s));
     }
     TRY_HIP(launch_coarse_prolong(L.g, C.g, C.e, kCoarseScale, L.d, s));
     if (kCoarsePost > 0) {
-      TRY_HIP(L.eng->residual(L.v, L.d, L.t, s));
-      if ((rc = smooth(l, nullptr, kCoarsePost, s))) return rc;
+      TRY_HIP(L.eng->residual(L.v, L.d, nullptr, s));  // the engine's right-hand side only
+      if ((rc = smooth(l, nullptr, kCoarsePost, false, s))) return rc;
     }
     return GABP_OK;
   }

@@ -279,6 +279,13 @@ template <typename T> struct GridCoef {
   const T *diag, *cx, *cy, *cz;  // per node / per face (NULL when constant)
   T dconst, aconst;              // constant diagonal and coupling
 };
+// Per-launch options of the grid sweeps (GridArgs::fl, RbArgs::fl)
+enum : int {
+  SWEEP_ZIN = 1,   // the in-messages' informations count as zero (a pending restart)
+  SWEEP_ZOWN = 2,  // the launch's own previous informations count as zero (damping)
+  SWEEP_XSET = 4,  // means pass: xacc = H / S instead of xacc += H / S
+};
+
 struct GridArgs {
   GridGeom g;
   int grid;            // blocks of the launch
@@ -296,6 +303,7 @@ struct GridArgs {
   BlockPartial *part;
   uint32_t *sticky;
   const Ctl *ctl;
+  int fl;              // SWEEP_*
 };
 hipError_t launch_grid_sweep(const GridArgs &a, hipStream_t s);
 hipError_t launch_grid_freeze(const GridArgs &a, hipStream_t s);
@@ -359,6 +367,7 @@ struct RbArgs {
   int nseg;
   const SegCtl *seg;
   const int32_t *act;
+  int fl;              // SWEEP_*
 };
 hipError_t launch_rb_sweep(const RbArgs &a, hipStream_t s);
 // coefficients, information messages and S of the settled phase from the
@@ -581,6 +590,13 @@ hipError_t launch_coarse_restrict(const GridGeom &f, const GridGeom &c, const do
 hipError_t launch_coarse_prolong(const GridGeom &f, const GridGeom &c, const double *dc,
                                  double scale, double *d, hipStream_t s);
 hipError_t launch_axpy(int n, const double *d, double *x, hipStream_t s);  // x += d
+// rc = P^T (v - A d) in one pass (A: the fine level's FP64 coefficients)
+hipError_t launch_coarse_residual_restrict(const GridGeom &f, const GridCoef<double> &k, bool varc,
+                                           const GridGeom &c, const double *v, const double *d,
+                                           double *rc, hipStream_t s);
+// e = d, v = v - A d in one pass
+hipError_t launch_coarse_copy_residual(const GridGeom &g, const GridCoef<double> &k, bool varc,
+                                       const double *d, double *e, double *v, hipStream_t s);
 
 // The coarsest levels of a hierarchy in one launch (one workgroup of
 // kTailThreads per grid of the stack, every vector and message of those

@@ -85,6 +85,72 @@ __global__ void k_coarse_prolong(GridGeom f, GridGeom c, const double *__restric
   d[i] += scale * dc[t * nc + x / sx + c.nx * (y / sy + c.ny * (z / sz))];
 }
 
+// (A x)_i of a 5/7-point stack in FP64, terms in the order of the grid
+// residual (diagonal first, then +x, -x, +y, -y, +z, -z), so that the fused
+// kernels below give bitwise the results of residual + restriction
+template <bool VARC>
+__device__ __forceinline__ double stencil_ax(const GridGeom &g, const GridCoef<double> &k,
+                                             const double *__restrict__ x, int i) {
+  const int nxy = g.nx * g.ny;
+  const int xx = i % g.nx, y = (i / g.nx) % g.ny, zl = (i / nxy) % g.nz;
+  const bool ok[6] = {xx < g.nx - 1, xx > 0, y < g.ny - 1, y > 0, zl < g.nz - 1, zl > 0};
+  const int j[6] = {i + 1, i - 1, i + g.nx, i - g.nx, i + nxy, i - nxy};
+  double a[6];
+  if (VARC) {
+    a[0] = ok[0] ? k.cx[i] : 0.0;
+    a[1] = ok[1] ? k.cx[i - 1] : 0.0;
+    a[2] = ok[2] ? k.cy[i] : 0.0;
+    a[3] = ok[3] ? k.cy[i - g.nx] : 0.0;
+    a[4] = ok[4] ? k.cz[i] : 0.0;
+    a[5] = ok[5] ? k.cz[i - nxy] : 0.0;
+  } else {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) a[d] = ok[d] ? k.aconst : 0.0;
+  }
+  double ax = (VARC ? k.diag[i] : k.dconst) * x[i];
+#pragma unroll
+  for (int d = 0; d < 6; ++d)
+    if (a[d] != 0.0) ax += a[d] * x[j[d]];
+  return ax;
+}
+
+// rc[I] = sum over the cells i of block I of (v - A d)_i (fixed order: z, y, x)
+template <bool VARC>
+__global__ void k_coarse_residual_restrict(GridGeom f, GridCoef<double> k, GridGeom c,
+                                           const double *__restrict__ v,
+                                           const double *__restrict__ d, double *__restrict__ rc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= c.N) return;
+  const int nc = c.nx * c.ny * c.nz, nf = f.nx * f.ny * f.nz;
+  const int t = I / nc, j = I - t * nc;
+  const int X = j % c.nx, Y = (j / c.nx) % c.ny, Z = j / (c.nx * c.ny);
+  const int sx = f.nx > 1 ? 2 : 1, sy = f.ny > 1 ? 2 : 1, sz = f.nz > 1 ? 2 : 1;
+  const int x0 = X * sx, y0 = Y * sy, z0 = Z * sz;
+  const int x1 = min(x0 + sx, f.nx), y1 = min(y0 + sy, f.ny), z1 = min(z0 + sz, f.nz);
+  double s = 0.0;
+  for (int z = z0; z < z1; ++z)
+    for (int y = y0; y < y1; ++y)
+      for (int x = x0; x < x1; ++x) {
+        const int i = t * nf + x + f.nx * (y + f.ny * z);
+        double r = v[i];
+        r -= stencil_ax<VARC>(f, k, d, i);
+        s += r;
+      }
+  rc[I] = s;
+}
+
+// e = d and v = v - A d: the right-hand side of a level's next cycle
+template <bool VARC>
+__global__ void k_coarse_copy_residual(GridGeom g, GridCoef<double> k, const double *__restrict__ d,
+                                       double *__restrict__ e, double *__restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  e[i] = d[i];
+  double r = v[i];
+  r -= stencil_ax<VARC>(g, k, d, i);
+  v[i] = r;
+}
+
 __global__ void k_axpy(int n, const double *__restrict__ d, double *__restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] += d[i];
@@ -580,6 +646,31 @@ hipError_t launch_coarse_prolong(const GridGeom &f, const GridGeom &c, const dou
                                  double scale, double *d, hipStream_t s) {
   if (f.N <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_coarse_prolong, blocks_for(f.N), dim3(kBlock), 0, s, f, c, dc, scale, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_residual_restrict(const GridGeom &f, const GridCoef<double> &k, bool varc,
+                                           const GridGeom &c, const double *v, const double *d,
+                                           double *rc, hipStream_t s) {
+  if (c.N <= 0) return hipSuccess;
+  if (varc)
+    hipLaunchKernelGGL(k_coarse_residual_restrict<true>, blocks_for(c.N), dim3(kBlock), 0, s, f, k,
+                       c, v, d, rc);
+  else
+    hipLaunchKernelGGL(k_coarse_residual_restrict<false>, blocks_for(c.N), dim3(kBlock), 0, s, f, k,
+                       c, v, d, rc);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_copy_residual(const GridGeom &g, const GridCoef<double> &k, bool varc,
+                                       const double *d, double *e, double *v, hipStream_t s) {
+  if (g.N <= 0) return hipSuccess;
+  if (varc)
+    hipLaunchKernelGGL(k_coarse_copy_residual<true>, blocks_for(g.N), dim3(kBlock), 0, s, g, k, d,
+                       e, v);
+  else
+    hipLaunchKernelGGL(k_coarse_copy_residual<false>, blocks_for(g.N), dim3(kBlock), 0, s, g, k, d,
+                       e, v);
   return hipGetLastError();
 }
 

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(
     GridGeom g, GridCoef<T> k, const typename Vec2<T>::type *__restrict__ min,
     typename Vec2<T>::type *__restrict__ mout, const T *__restrict__ rhs, T alpha,
     T *__restrict__ xprev, double *__restrict__ xacc, double *__restrict__ marg,
-    BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+    BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl,
+    int fl) {
   using V = typename Vec2<T>::type;
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
   const int N = g.N;
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(
       if (a[d] != T(0)) {
         const V m = min[(size_t)(d ^ 1) * N + nb.j[d]];
         Pin[d] = m.x;
-        hin[d] = m.y;
+        hin[d] = (fl & SWEEP_ZIN) ? T(0) : m.y;
       }
     }
     T S = VARC ? k.diag[i] : k.dconst, H = rhs[i];
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(
           const V o = min[(size_t)d * N + i];
           if (DAMP) {
             P = alpha * o.x + (T(1) - alpha) * P;
-            h = alpha * o.y + (T(1) - alpha) * h;
+            h = alpha * ((fl & SWEEP_ZOWN) ? T(0) : o.y) + (T(1) - alpha) * h;
           }
           if (MODE == 1) {
             dpb = fmax(dpb, (double)fabs(P - o.x));
@@ -140,7 +141,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(
         dmax = fmax(dmax, (double)fabs(x - xprev[i]));
         xprev[i] = x;
       } else {
-        if (xacc) xacc[i] += (double)H / (double)S;
+        if (xacc) {
+          const double m = (double)H / (double)S;
+          xacc[i] = (fl & SWEEP_XSET) ? m : xacc[i] + m;
+        }
         if (marg) marg[i] = (double)S;
         if (xprev) xprev[i] = x;  // means of the current messages
       }
@@ -157,7 +161,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_frozen(
     GridGeom g, GridCoef<T> k, const T *__restrict__ coef, const T *__restrict__ Sfix,
     const T *__restrict__ hin_arr, T *__restrict__ hout_arr, const T *__restrict__ rhs, T alpha,
     T *__restrict__ xprev, double *__restrict__ xacc, double *__restrict__ marg,
-    BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl) {
+    BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl,
+    int fl) {
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
   const int N = g.N;
   double dmax = 0.0, xmax = 0.0;
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_frozen(
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
       hin[d] = T(0);
-      if (nb.ok[d]) hin[d] = hin_arr[(size_t)(d ^ 1) * N + nb.j[d]];
+      if (nb.ok[d] && !(fl & SWEEP_ZIN)) hin[d] = hin_arr[(size_t)(d ^ 1) * N + nb.j[d]];
       H += hin[d];
     }
     if (MODE != 2) {
@@ -184,7 +189,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_frozen(
       for (int d = 0; d < 6; ++d) {
         if (!nb.ok[d]) continue;
         T h = coef[(size_t)d * N + i] * (H - hin[d]);
-        if (DAMP) h = alpha * hin_arr[(size_t)d * N + i] + (T(1) - alpha) * h;
+        if (DAMP)
+          h = alpha * ((fl & SWEEP_ZOWN) ? T(0) : hin_arr[(size_t)d * N + i]) + (T(1) - alpha) * h;
         __builtin_nontemporal_store(h, &hout_arr[(size_t)d * N + i]);
       }
     }
@@ -196,7 +202,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_frozen(
         dmax = fmax(dmax, (double)fabs(x - xprev[i]));
         xprev[i] = x;
       } else {
-        if (xacc) xacc[i] += (double)H / (double)S;
+        if (xacc) {
+          const double m = (double)H / (double)S;
+          xacc[i] = (fl & SWEEP_XSET) ? m : xacc[i] + m;
+        }
         if (marg) marg[i] = (double)S;
         if (xprev) xprev[i] = x;  // means of the current messages
       }
@@ -343,11 +352,11 @@ static void grid_one(const GridArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_grid_frozen<T, MODE, DAMP, VARC>), dim3(a.grid), dim3(kBlock), 0, s,
                        a.g, k, (const T *)a.coef, (const T *)a.Sfix, (const T *)a.msg_in,
                        (T *)a.msg_out, (const T *)a.rhs, (T)a.alpha, (T *)a.xprev, a.xacc,
-                       a.marg, a.part, a.sticky, a.ctl);
+                       a.marg, a.part, a.sticky, a.ctl, a.fl);
   else
     hipLaunchKernelGGL((k_grid_sweep<T, MODE, DAMP, VARC>), dim3(a.grid), dim3(kBlock), 0, s, a.g,
                        k, (const V *)a.msg_in, (V *)a.msg_out, (const T *)a.rhs, (T)a.alpha,
-                       (T *)a.xprev, a.xacc, a.marg, a.part, a.sticky, a.ctl);
+                       (T *)a.xprev, a.xacc, a.marg, a.part, a.sticky, a.ctl, a.fl);
 }
 
 template <typename T, bool VARC>

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
     const T *__restrict__ rhs, T alpha, T *__restrict__ xprev, double *__restrict__ xacc,
     double *__restrict__ marg, BlockPartial *__restrict__ part, uint32_t *__restrict__ sticky,
     const Ctl *__restrict__ ctl, int nseg, const SegCtl *__restrict__ seg,
-    const int32_t *__restrict__ act) {
+    const int32_t *__restrict__ act, int fl) {
   using V = typename Vec2<T>::type;
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
   const V *__restrict__ other = msg + (size_t)(1 - c) * 6 * Nc;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
       if (a[d] != T(0)) {
         const V m = other[(size_t)(d ^ 1) * Nc + nd.j[d]];
         Pin[d] = m.x;
-        hin[d] = m.y;
+        hin[d] = (fl & SWEEP_ZIN) ? T(0) : m.y;
       }
     }
     T S = VARC ? k.diag[nd.i] : k.dconst, H = rhs[(size_t)c * Nc + s];
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
           const V o = *slot;
           if (DAMP) {
             P = alpha * o.x + (T(1) - alpha) * P;
-            h = alpha * o.y + (T(1) - alpha) * h;
+            h = alpha * ((fl & SWEEP_ZOWN) ? T(0) : o.y) + (T(1) - alpha) * h;
           }
           if (MODE == 1) {
             q.dpb = fmax(q.dpb, (double)fabs(P - o.x));
@@ -204,7 +204,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
         *xp = x;
       } else {
         // a segment sitting the pass out gets no correction
-        if (xacc && !(SEG && seg[s / (Nc / nseg)].done == 2)) xacc[nd.i] += (double)H / (double)S;
+        if (xacc && !(SEG && seg[s / (Nc / nseg)].done == 2)) {
+          const double m = (double)H / (double)S;
+          xacc[nd.i] = (fl & SWEEP_XSET) ? m : xacc[nd.i] + m;
+        }
         if (marg) marg[nd.i] = (double)S;
         if (xp) *xp = x;  // means of the current messages
       }
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
     T *__restrict__ hh, const T *__restrict__ rhs, T alpha, T *__restrict__ xprev,
     double *__restrict__ xacc, double *__restrict__ marg, BlockPartial *__restrict__ part,
     uint32_t *__restrict__ sticky, const Ctl *__restrict__ ctl, int nseg,
-    const SegCtl *__restrict__ seg, const int32_t *__restrict__ act) {
+    const SegCtl *__restrict__ seg, const int32_t *__restrict__ act, int fl) {
   if (ctl != nullptr && ctl->stop != STOP_NONE) return;
   const T *__restrict__ other = hh + (size_t)(1 - c) * 6 * Nc;
   T *__restrict__ own = hh + (size_t)c * 6 * Nc;
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
     T H = rhs[(size_t)c * Nc + s];
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
-      hin[d] = nd.ok[d] ? other[(size_t)(d ^ 1) * Nc + nd.j[d]] : T(0);
+      hin[d] = nd.ok[d] && !(fl & SWEEP_ZIN) ? other[(size_t)(d ^ 1) * Nc + nd.j[d]] : T(0);
       H += hin[d];
     }
     if (MODE != 2) {
@@ -245,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
         if (!nd.ok[d]) continue;
         const size_t o = (size_t)d * Nc + s;
         T h = cf[o] * (H - hin[d]);
-        if (DAMP) h = alpha * own[o] + (T(1) - alpha) * h;
+        if (DAMP) h = alpha * ((fl & SWEEP_ZOWN) ? T(0) : own[o]) + (T(1) - alpha) * h;
         __builtin_nontemporal_store(h, &own[o]);
       }
     }
@@ -258,7 +261,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
         q.dmax = fmax(q.dmax, (double)fabs(x - *xp));
         *xp = x;
       } else {
-        if (xacc && !(SEG && seg[s / (Nc / nseg)].done == 2)) xacc[nd.i] += (double)H / (double)S;
+        if (xacc && !(SEG && seg[s / (Nc / nseg)].done == 2)) {
+          const double m = (double)H / (double)S;
+          xacc[nd.i] = (fl & SWEEP_XSET) ? m : xacc[nd.i] + m;
+        }
         if (marg) marg[nd.i] = (double)S;
         if (xp) *xp = x;
       }
@@ -338,11 +344,12 @@ void rb_one(const RbArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_rb_frozen<T, MODE, DAMP, SEG>), dim3(a.grid), dim3(kBlock), 0, s, a.g,
                        a.hx, a.Nc, a.colour, (const T *)a.coef, (const T *)a.Sfix, (T *)a.msg,
                        (const T *)a.rhs, (T)a.alpha, (T *)a.xprev, a.xacc, a.marg, a.part,
-                       a.sticky, a.ctl, nseg, a.seg, a.act);
+                       a.sticky, a.ctl, nseg, a.seg, a.act, a.fl);
   else
     hipLaunchKernelGGL((k_rb_sweep<T, MODE, DAMP, VARC, SEG>), dim3(a.grid), dim3(kBlock), 0, s,
                        a.g, a.hx, a.Nc, a.colour, k, (V *)a.msg, (const T *)a.rhs, (T)a.alpha,
-                       (T *)a.xprev, a.xacc, a.marg, a.part, a.sticky, a.ctl, nseg, a.seg, a.act);
+                       (T *)a.xprev, a.xacc, a.marg, a.part, a.sticky, a.ctl, nseg, a.seg, a.act,
+                       a.fl);
 }
 
 template <typename T, bool VARC, bool SEG>
