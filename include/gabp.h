@@ -28,6 +28,7 @@
 #ifndef GABP_H
 #define GABP_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -297,6 +298,16 @@ int gabp_plan_set_messages(gabp_plan *plan, const double *P, const double *h,
  * processed in increasing order within a sweep.  Coloured CSR plans and
  * coloured lsq plans (x: 0, z: 1); GABP_ERR_UNSUPPORTED for other plans. */
 int gabp_plan_colors(gabp_plan *plan, int32_t *colors, int32_t *ncolors, hipStream_t stream);
+
+/* Device memory the plan holds (host *bytes): every buffer the library
+ * allocated for it and has not freed -- messages, index and coefficient
+ * arrays, working copies, controller state, and what solves added later
+ * (settled-precision buffers, the coarse levels of gabp_plan_solve_coarse
+ * with their own plans).  Memory the caller passes in is not counted.  A
+ * one-shot call (gabp_solve and the like) allocates what a plan for the same
+ * problem holds and frees it before returning.  No device work, no
+ * synchronisation; GABP_ERR_ARG for a NULL argument. */
+int gabp_plan_workspace_bytes(const gabp_plan *plan, size_t *bytes);
 
 /* ---- Structured grids: the finite-difference Poisson operators of ----------
  * section IX (5-point in 2-D, 7-point in 3-D), with constant or variable

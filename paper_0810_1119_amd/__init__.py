@@ -25,5 +25,5 @@ from ._abi import (  # noqa: F401
     gabp_model_grad, gabp_model_train_step, gabp_model_grid_features, gabp_model_grid_targets,
     gabp_plan_solve_warm, gabp_plan_solve_coarse,
     gabp_plan_colors, DeviceRect, gabp_plan_create_lsq, gabp_plan_solve_lsq, gabp_solve_lsq,
-    gabp_plan_residual_lsq,
+    gabp_plan_residual_lsq, gabp_plan_workspace_bytes,
 )

@@ -105,6 +105,7 @@ _sig = {
                                         _vp]),
     "gabp_plan_create": (C.c_int, [C.POINTER(_Csr), C.POINTER(Opts), C.POINTER(_vp), _vp]),
     "gabp_plan_colors": (C.c_int, [_vp, _vp, C.POINTER(C.c_int32), _vp]),
+    "gabp_plan_workspace_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "gabp_plan_create_lsq": (C.c_int, [C.POINTER(_Rect), C.c_double, C.POINTER(Opts),
                                        C.POINTER(_vp), _vp]),
     "gabp_plan_solve_lsq": (C.c_int, [_vp, _vp, _vp, C.POINTER(Stats), _vp]),
@@ -346,6 +347,13 @@ def gabp_plan_colors(plan, stream=None):
     nc = C.c_int32(0)
     rc = lib.gabp_plan_colors(plan.ptr, _ptr(colors), C.byref(nc), _stream(stream))
     return rc, (colors if rc == GABP_OK else None), nc.value
+
+
+def gabp_plan_workspace_bytes(plan):
+    """Returns (status, bytes of device memory the plan holds)."""
+    nb = C.c_size_t(0)
+    rc = lib.gabp_plan_workspace_bytes(plan.ptr, C.byref(nb))
+    return rc, nb.value
 
 
 def gabp_plan_create_lsq(S: DeviceRect, psi: float, opts: Opts | None = None, stream=None):

@@ -37,7 +37,7 @@ void report_hip(hipError_t e, const char *file, int line) {
 Engine::~Engine() {
   void *bufs[] = {part, sumpart, sticky, ctl, xprev, segb2, segctl, segact};
   for (void *b : bufs)
-    if (b) (void)hipFree(b);
+    if (b) dfree(b);
   if (host) (void)hipHostFree(host);
   if (events)
     for (int k = 0; k < kRing; ++k) {
@@ -368,6 +368,15 @@ void gabp_default_opts(gabp_opts *o) {
   o->accel_cycle = 0;
 }
 
+int gabp_plan_workspace_bytes(const gabp_plan *p, size_t *bytes) {
+  clear_stale_error();
+  if (!p || !bytes) return GABP_ERR_ARG;
+  int64_t b = p->acct ? p->acct->bytes.load() : 0;
+  if (p->coarse) b += coarse_bytes(p->coarse);
+  *bytes = (size_t)std::max<int64_t>(b, 0);
+  return GABP_OK;
+}
+
 int gabp_plan_destroy(gabp_plan *p) {
   clear_stale_error();
   if (!p) return GABP_ERR_ARG;
@@ -385,6 +394,7 @@ int gabp_plan_destroy(gabp_plan *p) {
 int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
                     hipStream_t s) {
   clear_stale_error();
+  GABP_PLAN_SCOPE(p);
   if (p && p->bat) return batch_solve(p->bat, b, x, marg_prec, nullptr, st, s);
   if (p && p->small) return small_solve(p->small, b, x, marg_prec, nullptr, st, s);
   if (!p || !p->eng) return GABP_ERR_ARG;
@@ -394,6 +404,7 @@ int gabp_plan_solve(gabp_plan *p, const double *b, double *x, double *marg_prec,
 
 int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
   clear_stale_error();
+  GABP_PLAN_SCOPE(p);
   if (p && p->bat) return batch_reset(p->bat, b, s);
   if (p && p->small) return small_reset(p->small, b, s);
   if (!p || !p->eng || (p->eng->n > 0 && !b)) return GABP_ERR_ARG;
@@ -406,6 +417,7 @@ int gabp_plan_reset(gabp_plan *p, const double *b, hipStream_t s) {
 }
 
 int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (p && p->bat) return batch_sweeps(p->bat, count, s);
   if (p && p->small) return small_sweeps(p->small, count, s);
@@ -418,6 +430,7 @@ int gabp_plan_sweeps(gabp_plan *p, int32_t count, hipStream_t s) {
 }
 
 int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (p && p->bat) return batch_marginals(p->bat, mean, prec, s);
   if (p && p->small) return small_marginals(p->small, mean, prec, s);
@@ -431,6 +444,7 @@ int gabp_plan_marginals(gabp_plan *p, double *mean, double *prec, hipStream_t s)
 }
 
 int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (p && p->small) return small_messages(p->small, P, h, false, s);
   if (p && (p->bat || p->perm)) return GABP_ERR_UNSUPPORTED;
@@ -439,6 +453,7 @@ int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
 }
 
 int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (p && p->small)
     return small_messages(p->small, const_cast<double *>(P), const_cast<double *>(h), true, s);
@@ -448,6 +463,7 @@ int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipSt
 }
 
 int gabp_plan_colors(gabp_plan *p, int32_t *colors, int32_t *ncolors, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (p && p->small) return small_colors(p->small, colors, ncolors, s);
   if (!p || !p->eng) return GABP_ERR_ARG;

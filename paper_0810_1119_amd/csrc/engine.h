@@ -6,6 +6,8 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -56,10 +58,30 @@ inline int max_lds_per_block() {
   return v;
 }
 
+// Device memory held by a plan (memory.cpp): every allocation made while an
+// AccountScope of the plan is open on the thread counts until it is freed.
+struct DevAccount {
+  std::atomic<int64_t> bytes{0};
+};
+struct AccountScope {
+  explicit AccountScope(DevAccount *a);
+  ~AccountScope();
+  AccountScope(const AccountScope &) = delete;
+  AccountScope &operator=(const AccountScope &) = delete;
+  DevAccount *prev;
+};
+hipError_t dalloc_bytes(void **p, size_t bytes);  // hipMalloc, recorded
+void dfree(void *p);                               // hipFree, unrecorded (NULL: nothing)
+
+// the plan's account for the duration of an entry point on an existing plan
+#define GABP_PLAN_SCOPE(p) gabp::AccountScope gabp_scope_((p) && (p)->acct ? (p)->acct.get() : nullptr)
+
 template <typename P>
 hipError_t dalloc(P **p, size_t count, size_t elem) {
-  *p = nullptr;
-  return hipMalloc((void **)p, std::max<size_t>(1, count) * elem);
+  void *q = nullptr;
+  const hipError_t e = dalloc_bytes(&q, std::max<size_t>(1, count) * elem);
+  *p = (P *)q;
+  return e;
 }
 
 struct Engine {
@@ -225,6 +247,8 @@ int perm_colors(const CsrPerm *q, int32_t *colors, int32_t *ncolors, hipStream_t
 // a coloured CSR plan runs on a colour-sorted renumbering of the caller's
 // matrix (perm)
 struct gabp_plan {
+  // the account its device allocations count against
+  std::shared_ptr<gabp::DevAccount> acct;
   gabp::Engine *eng = nullptr;
   gabp::BatchEngine *bat = nullptr;
   gabp::SmallEngine *small = nullptr;
@@ -232,3 +256,20 @@ struct gabp_plan {
   gabp::LsqSystem *lsq = nullptr;
   gabp::CsrPerm *perm = nullptr;
 };
+
+namespace gabp {
+// Runs a plan constructor f (which stores the new plan in *plan) with a fresh
+// account open, so that everything it allocates counts for the new plan.
+template <typename F>
+int with_account(gabp_plan **plan, F f) {
+  auto acct = std::make_shared<DevAccount>();
+  int rc;
+  {
+    AccountScope scope(acct.get());
+    rc = f();
+  }
+  if (rc == GABP_OK && plan && *plan) (*plan)->acct = acct;
+  return rc;
+}
+int64_t coarse_bytes(const CoarseHierarchy *h);  // the coarse levels' own plans
+}  // namespace gabp

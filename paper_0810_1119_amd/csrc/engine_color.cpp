@@ -21,7 +21,7 @@ struct CsrPerm {
   ~CsrPerm() {
     void *bufs[] = {new2old, old2new, color, rp, col, val, bp, xp, mp};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) dfree(b);
   }
 };
 
@@ -38,7 +38,7 @@ struct Scratch {
     return e;
   }
   ~Scratch() {
-    for (void *b : bufs) (void)hipFree(b);
+    for (void *b : bufs) dfree(b);
   }
 };
 

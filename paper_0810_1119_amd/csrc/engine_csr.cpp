@@ -94,7 +94,7 @@ struct CsrEngine : Engine {
     void *bufs[] = {oprt, ocol, rev, diagpos, acoef, diag, rhs, msg[0], msg[1], sums[0],
                     sums[1], coef, hp[0], hp[1], Sfix, Hfz[0], Hfz[1], rblk, carry};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) dfree(b);
   }
 
   size_t msg_bytes() const { return (pair ? 4 : 2) * tsz; }
@@ -344,7 +344,7 @@ struct CsrEngine : Engine {
     auto fail = [&](int code) {
       void *bufs[] = {deg, vo, tmp, L, flags, far};
       for (void *b : bufs)
-        if (b) (void)hipFree(b);
+        if (b) dfree(b);
       return code;
     };
     if ((st = from_hip(dalloc(&deg, n, sizeof(int64_t)))) ||
@@ -464,7 +464,7 @@ using namespace gabp;
 
 extern "C" {
 
-int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
+static int plan_create_impl(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
   clear_stale_error();
   if (!plan) return GABP_ERR_ARG;
   if (o && o->schedule == GABP_SCHEDULE_COLORED) {
@@ -474,6 +474,10 @@ int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hi
     return st ? st : coloured_csr_plan(A, o, plan, s);
   }
   return csr_plan_create(A, o, nullptr, plan, s);
+}
+
+int gabp_plan_create(const gabp_csr *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
+  return with_account(plan, [&] { return plan_create_impl(A, o, plan, s); });
 }
 
 int gabp_solve(const gabp_csr *A, const double *b, double *x, double *marg_prec,
@@ -506,7 +510,7 @@ int gabp_residual(const gabp_csr *A, const double *b, const double *x, double *r
   auto cleanup = [&](int code) {
     void *bufs[] = {sum, deg, dpos, flags};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) dfree(b);
     if (host) (void)hipHostFree(host);
     if (ev) (void)hipEventDestroy(ev);
     return code;

@@ -39,7 +39,7 @@ struct BatchEngine {
   ~BatchEngine() {
     void *bufs[] = {inst, order, queue, matT, state, fcoef, fh, tot, nb, dstat, vflags};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) dfree(b);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
   }
@@ -414,7 +414,7 @@ using namespace gabp;
 
 extern "C" {
 
-int gabp_plan_create_batched(const gabp_batch *B, const gabp_opts *o, gabp_plan **plan,
+static int plan_create_batched_impl(const gabp_batch *B, const gabp_opts *o, gabp_plan **plan,
                              hipStream_t s) {
   clear_stale_error();
   if (!plan) return GABP_ERR_ARG;
@@ -437,8 +437,14 @@ int gabp_plan_create_batched(const gabp_batch *B, const gabp_opts *o, gabp_plan 
   return GABP_OK;
 }
 
+int gabp_plan_create_batched(const gabp_batch *B, const gabp_opts *o, gabp_plan **plan,
+                             hipStream_t s) {
+  return with_account(plan, [&] { return plan_create_batched_impl(B, o, plan, s); });
+}
+
 int gabp_plan_solve_batched(gabp_plan *p, const double *b, double *x, gabp_stats *per,
                             gabp_stats *summary, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (p && p->small) return small_solve(p->small, b, x, nullptr, per, summary, s);
   if (!p || !p->bat) return GABP_ERR_ARG;

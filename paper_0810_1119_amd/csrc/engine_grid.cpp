@@ -77,8 +77,8 @@ struct GridEngine : Engine {
   ~GridEngine() override {
     void *bufs[] = {wdiag, wcx, wcy, wcz, rhs, msg[0], msg[1], coef, hh[0], hh[1], Sfix};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
-    for (double *b : owned) (void)hipFree(b);
+      if (b) dfree(b);
+    for (double *b : owned) dfree(b);
   }
 
   int64_t slots() const { return 6 * (int64_t)g.N; }
@@ -219,7 +219,7 @@ struct GridEngine : Engine {
     if (e1 == hipSuccess) e1 = launch_grid_check(g, k64, varc, nsum, flags, s);
     if (e1 == hipSuccess) e1 = hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
-    (void)hipFree(flags);
+    dfree(flags);
     if (e1 != hipSuccess) return from_hip(e1);
     if (hflags & FLAG_ARG) return GABP_ERR_ARG;
     if (hflags & FLAG_ZERO_DIAG) return GABP_ERR_ZERO_DIAG;
@@ -458,7 +458,7 @@ struct CoarseHierarchy {
       if (L.plan) gabp_plan_destroy(L.plan);
       double *bufs[] = {L.dg, L.cx, L.cy, L.cz, L.v, L.d, L.e, L.Pt, L.inv};
       for (double *b : bufs)
-        if (b) (void)hipFree(b);
+        if (b) dfree(b);
     }
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -563,7 +563,7 @@ struct CoarseHierarchy {
         if (e == hipSuccess) e = launch_coarse_inverse(C.g, C.dg, C.cx, C.cy, C.cz, Z.inv, bad, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        (void)hipFree(bad);
+        dfree(bad);
         TRY_HIP(e);
         if (hb & FLAG_BREAKDOWN) return GABP_ERR_BREAKDOWN;  // a singular coarse system
       } else if (tail > 0 && (int)lv.size() - 1 >= tail) {
@@ -681,6 +681,13 @@ int CoarseHierarchy::correction(hipStream_t s) {
 
 void coarse_destroy(CoarseHierarchy *h) { delete h; }
 
+int64_t coarse_bytes(const CoarseHierarchy *h) {
+  int64_t b = 0;
+  for (const auto &L : h->lv)
+    if (L.plan && L.plan->acct) b += L.plan->acct->bytes.load();
+  return b;
+}
+
 int coarse_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, gabp_stats *st,
                  hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -772,7 +779,7 @@ using namespace gabp;
 
 extern "C" {
 
-int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
+static int plan_create_grid_impl(const gabp_grid *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
   clear_stale_error();
   if (!plan) return GABP_ERR_ARG;
   *plan = nullptr;
@@ -846,6 +853,10 @@ int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **pl
   return GABP_OK;
 }
 
+int gabp_plan_create_grid(const gabp_grid *A, const gabp_opts *o, gabp_plan **plan, hipStream_t s) {
+  return with_account(plan, [&] { return plan_create_grid_impl(A, o, plan, s); });
+}
+
 int gabp_solve_grid(const gabp_grid *A, const double *b, double *x, double *marg_prec,
                     const gabp_opts *o, gabp_stats *st, hipStream_t s) {
   clear_stale_error();
@@ -871,7 +882,7 @@ int gabp_residual_grid(const gabp_grid *A, const double *b, const double *x, dou
   GridCoef<double> k{};
   std::vector<double *> owned;
   if ((rc = expand_coefficients(A, g.N, &k, &owned))) {
-    for (double *d : owned) (void)hipFree(d);
+    for (double *d : owned) dfree(d);
     return rc;
   }
   const int need = (g.N + kBlock - 1) / kBlock;
@@ -880,8 +891,8 @@ int gabp_residual_grid(const gabp_grid *A, const double *b, const double *x, dou
   HostReadout *host = nullptr;
   hipEvent_t ev = nullptr;
   auto cleanup = [&](int code) {
-    if (sum) (void)hipFree(sum);
-    for (double *d : owned) (void)hipFree(d);
+    if (sum) dfree(sum);
+    for (double *d : owned) dfree(d);
     if (host) (void)hipHostFree(host);
     if (ev) (void)hipEventDestroy(ev);
     return code;
@@ -903,6 +914,7 @@ int gabp_residual_grid(const gabp_grid *A, const double *b, const double *x, dou
 
 int gabp_plan_solve_coarse(gabp_plan *p, const double *b, double *x, double *marg_prec,
                            gabp_stats *st, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (!p || !p->eng) return GABP_ERR_ARG;
   return coarse_solve(p, b, x, marg_prec, st, s);

@@ -26,7 +26,7 @@ struct LsqSystem {
   ~LsqSystem() {
     void *bufs[] = {Arp, Acol, Aval, bt, xt, u, part};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) dfree(b);
   }
 };
 
@@ -58,7 +58,7 @@ struct LsqScratch {
   ~LsqScratch() {
     void *bufs[] = {colcnt, keys, flags, rowlen, scan, rowof, idx, perm, sort};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) dfree(b);
   }
 };
 
@@ -133,7 +133,7 @@ using namespace gabp;
 
 extern "C" {
 
-int gabp_plan_create_lsq(const gabp_rect *S, double psi, const gabp_opts *o, gabp_plan **plan,
+static int plan_create_lsq_impl(const gabp_rect *S, double psi, const gabp_opts *o, gabp_plan **plan,
                          hipStream_t s) {
   clear_stale_error();
   if (!plan) return GABP_ERR_ARG;
@@ -175,7 +175,13 @@ int gabp_plan_create_lsq(const gabp_rect *S, double psi, const gabp_opts *o, gab
   return GABP_OK;
 }
 
+int gabp_plan_create_lsq(const gabp_rect *S, double psi, const gabp_opts *o, gabp_plan **plan,
+                         hipStream_t s) {
+  return with_account(plan, [&] { return plan_create_lsq_impl(S, psi, o, plan, s); });
+}
+
 int gabp_plan_solve_lsq(gabp_plan *p, const double *y, double *x, gabp_stats *st, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (!p || !p->eng || !p->lsq) return GABP_ERR_ARG;
   LsqSystem *q = p->lsq;
@@ -207,6 +213,7 @@ int gabp_solve_lsq(const gabp_rect *S, double psi, const double *y, double *x,
 
 int gabp_plan_residual_lsq(gabp_plan *p, const double *y, const double *x, double *r,
                            double *rel_norm, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (!p || !p->lsq || !rel_norm) return GABP_ERR_ARG;
   LsqSystem *q = p->lsq;

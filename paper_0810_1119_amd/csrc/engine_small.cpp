@@ -40,7 +40,7 @@ struct SmallEngine {
   ~SmallEngine() {
     void *bufs[] = {inst, order, queue, soff, rev, color, acoef, diagT, msg, rhsT, hist, stat};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) dfree(b);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
   }
@@ -153,7 +153,7 @@ void colour_instances(const std::vector<SmallInst> &inst, const std::vector<int3
 struct Scratch {
   std::vector<void *> p;
   ~Scratch() {
-    for (void *q : p) (void)hipFree(q);
+    for (void *q : p) dfree(q);
   }
   template <typename P>
   hipError_t alloc(P **q, size_t count, size_t elem) {

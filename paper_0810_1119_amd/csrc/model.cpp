@@ -23,7 +23,7 @@ struct gabp_model {
   void free_scratch() {
     void *bufs[] = {H1, H2, R, D1, D2, part, gpart};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) dfree(b);
     H1 = H2 = R = D1 = D2 = nullptr;
     part = nullptr;
     gpart = nullptr;
@@ -33,7 +33,7 @@ struct gabp_model {
     free_scratch();
     void *bufs[] = {master, m1, m2, wbf, lossv};
     for (void *b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) dfree(b);
   }
   int ensure(int64_t S) {
     if (S <= cap) return GABP_OK;
@@ -73,7 +73,7 @@ int set_params(gabp_model *m, const float *host, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(tmp, host, mlp_params() * sizeof(float), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_mlp_set(tmp, m->master, m->wbf, m->m1, m->m2, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(tmp);
+  dfree(tmp);
   m->step = 0;
   return from_hip(e);
 }
@@ -164,7 +164,7 @@ int gabp_model_get_params(const gabp_model *m, float *params, hipStream_t s) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(params, tmp, mlp_params() * sizeof(float), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(tmp);
+  dfree(tmp);
   return from_hip(e);
 }
 
@@ -225,6 +225,7 @@ int gabp_model_grid_targets(const gabp_grid *A, const double *P, const double *h
 
 int gabp_plan_solve_warm(gabp_plan *p, const gabp_model *m, const double *b, double *x,
                          double *marg_prec, gabp_stats *st, hipStream_t s) {
+  GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (!p || !m) return GABP_ERR_ARG;
   if (!p->eng || !p->eng->has_warm_start()) return GABP_ERR_UNSUPPORTED;  // grid plans only
