@@ -233,32 +233,55 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
   rb_cover<MODE, SEG>(Nc, nseg, act, part, acc, [&](int s, RbAcc &q) {
     RbNode nd;
     if (!rb_node(g, hx, c, s, nd)) return;
-    // faces with a zero coupling hold zero coefficients and zero
-    // informations on both sides since the freeze, so the geometry decides
-    T hin[6];
-    T H = rhs[(size_t)c * Nc + s];
+    // Faces with a zero coupling hold zero coefficients and zero
+    // informations on both sides since the freeze, so the geometry decides.
+    // Load order, as measured: with segments (a stack whose grids stop one
+    // by one) every load before the first store; without, each direction's
+    // coefficient (and old information) next to its store.
+    T hin[6], kf[6], ho[6];
 #pragma unroll
-    for (int d = 0; d < 6; ++d) {
+    for (int d = 0; d < 6; ++d)
       hin[d] = nd.ok[d] && !(fl & SWEEP_ZIN) ? other[(size_t)(d ^ 1) * Nc + nd.j[d]] : T(0);
-      H += hin[d];
+    if (SEG && MODE != 2) {
+#pragma unroll
+      for (int d = 0; d < 6; ++d) kf[d] = nd.ok[d] ? cf[(size_t)d * Nc + s] : T(0);
+      if (DAMP) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d)
+          ho[d] = nd.ok[d] && !(fl & SWEEP_ZOWN) ? own[(size_t)d * Nc + s] : T(0);
+      }
     }
+    T H = rhs[(size_t)c * Nc + s];
+    T *xp = xprev ? xprev + (size_t)c * Nc + s : nullptr;
+    T S = T(1), xold = T(0);
+    if (SEG) {
+      if (MODE >= 1) S = Sfix[(size_t)c * Nc + s];
+      if (MODE == 1) xold = *xp;
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) H += hin[d];
     if (MODE != 2) {
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         if (!nd.ok[d]) continue;
         const size_t o = (size_t)d * Nc + s;
-        T h = cf[o] * (H - hin[d]);
-        if (DAMP) h = alpha * ((fl & SWEEP_ZOWN) ? T(0) : own[o]) + (T(1) - alpha) * h;
+        T h = (SEG ? kf[d] : cf[o]) * (H - hin[d]);
+        if (DAMP) {
+          const T old = SEG ? ho[d] : ((fl & SWEEP_ZOWN) ? T(0) : own[o]);
+          h = alpha * old + (T(1) - alpha) * h;
+        }
         __builtin_nontemporal_store(h, &own[o]);
       }
     }
     if (MODE >= 1) {
-      const T S = Sfix[(size_t)c * Nc + s];
+      if (!SEG) {
+        S = Sfix[(size_t)c * Nc + s];
+        if (MODE == 1) xold = *xp;
+      }
       const T x = H / S;
       if (!isfinite(x)) q.f |= FLAG_NONFINITE;
-      T *xp = xprev ? xprev + (size_t)c * Nc + s : nullptr;
       if (MODE == 1) {
-        q.dmax = fmax(q.dmax, (double)fabs(x - *xp));
+        q.dmax = fmax(q.dmax, (double)fabs(x - xold));
         *xp = x;
       } else {
         if (xacc && !(SEG && seg[s / (Nc / nseg)].done == 2)) {
