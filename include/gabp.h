@@ -531,7 +531,7 @@ int gabp_plan_solve_warm(gabp_plan *plan, const gabp_model *model, const double 
  * initial messages computed from a node's own neighbourhood can supply them.
  * This solve predicts every correction of the refinement loop on coarser
  * grids.  With r = b - A x (FP64), the correction d of A d = r is
- *   d  = means of 4 GaBP sweeps on r (the plan's schedule and message
+ *   d  = means of 3 GaBP sweeps on r (the plan's schedule and message
  *        precision, zero information messages, the precision messages of the
  *        level's previous sweeps kept);
  *   d += 1.8 P e, where e solves the next coarser grid's system
@@ -540,8 +540,10 @@ int gabp_plan_solve_warm(gabp_plan *plan, const gabp_model *model, const double 
  *        rc - P^T A P e: a W-cycle), P the 2 x 2 x 2 block indicator (an axis
  *        of extent 1 is not halved) and P^T A P the Galerkin product (again a
  *        5/7-point stencil), recursively down to grids of at most 64 cells,
- *        where the procedure is the means of 24 sweeps;
- *   d += means of 4 GaBP sweeps on r - A d;
+ *        whose systems are solved exactly (their dense inverses, built once;
+ *        a plan whose own grids have at most 64 cells is corrected by the
+ *        means of 24 sweeps instead);
+ *   d += means of 3 GaBP sweeps on r - A d;
  * then x += d, until every grid of the stack meets tol (each grid's own
  * ||b_t - A_t x_t|| / ||b_t||).  The sweeps use the plan's damping, except
  * that an undamped synchronous plan sweeps with damping 0.3 here: undamped

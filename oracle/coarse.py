@@ -161,7 +161,7 @@ def cycle(H, l, v, nu_pre, nu_post, nu_coarse, scale, gamma=2):
     return d
 
 
-def solve(nx, ny, nz, batch, diag, cx, cy, cz, b, tol=1e-8, nu_pre=4, nu_post=4, nu_coarse=24,
+def solve(nx, ny, nz, batch, diag, cx, cy, cz, b, tol=1e-8, nu_pre=3, nu_post=3, nu_coarse=24,
           scale=1.8, max_cycles=100, colored=True, damping=0.0, gamma=2):
     """Returns (x, cycles, worst per-grid relative residual, list of the x
     after each cycle).  colored=False smooths with synchronous rounds; damping

@@ -388,7 +388,11 @@ struct RbGridEngine : GridEngine {
 // stack meets the tolerance.  (A grid that is itself at most 64 cells is
 // corrected by kCoarseSweeps GaBP sweeps alone.)
 // ---------------------------------------------------------------------------
-constexpr int kCoarsePre = 4, kCoarsePost = 4, kCoarseSweeps = 24;
+// Sweeps per visit of a level: 3 before and 3 after the coarse prediction
+// (4 + 4 took the same number of corrections in the FP64 oracle on 32^3 to
+// 64^3 variable-coefficient stacks and damped synchronous grids, one more
+// on a few, at a quarter more sweeps).
+constexpr int kCoarsePre = 3, kCoarsePost = 3, kCoarseSweeps = 24;
 constexpr int kCoarseMaxCells = kCoarsestCells;
 // Synchronous sweeps on a grid (a bipartite graph) do not damp the error mode
 // that alternates between the two colours, so as a smoother they need
