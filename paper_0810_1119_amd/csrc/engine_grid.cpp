@@ -400,12 +400,16 @@ constexpr int kCoarseMaxCells = kCoarsestCells;
 // oracle diverges without it and takes 11-13 corrections with it on
 // 16^3 - 24^3 grids); the coloured schedule smooths with the plan's own.
 constexpr double kCoarseSyncDamping = 0.3;
-// The precision messages do not depend on the right-hand side and settle
-// within a few sweeps; after this many sweeps of a level in one solve (with
-// opts.freeze on) the level keeps them fixed and sweeps the information
-// messages only (the settled-precision sweeps of the plain solve).  The FP64
-// residual of every correction absorbs what is left of their change.
-constexpr int kCoarseFreezeAfter = 16;
+// The precision messages do not depend on the right-hand side; once a level
+// has swept this many times in one solve (with opts.freeze on: from its
+// second smoothing on) it keeps them fixed and sweeps the information
+// messages only (the settled-precision sweeps of the plain solve).  The
+// smoother is then GaBP with precisions of a few sweeps, and the FP64
+// residual of every correction absorbs the difference.  Measured with 3 + 3
+// sweeps (freeze after 16 / 9 / 6 / 3 sweeps of a level): 64 grids of 64^3
+// 37.8 / 35.0 / 33.6 / 32.7 ms, 7 corrections each; 256^3 damped 80.2 /
+// 78.4 / 78.1 / 72.3 ms, 14 corrections, 13 with the last.
+constexpr int kCoarseFreezeAfter = 2;
 // Injection of a block's correction into its cells under-corrects smooth
 // error (the coarse operator of piecewise constants is too stiff by about a
 // factor of two); the scale was chosen with the FP64 oracle on
