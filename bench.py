@@ -529,6 +529,27 @@ def bench_c1(args, G, W, torch, dev):
     err = float(np.linalg.norm(xh - ref.x) / np.linalg.norm(ref.x))
     avg_s = kms * 1e-3 / K
     per_sweep = sweeps / K
+    # the same system as a grid plan with coarse-grid predicted corrections
+    # (synchronous FP64 sweeps, the 16 x 16 and 8 x 8 levels in one launch
+    # per correction), timed on its own after the steps above
+    Ag = G.DeviceGrid(32, 32, 1, 1, diag_value=4.0, off_value=-1.0)
+    rc, gp = G.gabp_plan_create_grid(Ag, G.gabp_default_opts(msg_fp32=0, tol=1e-10,
+                                                             max_restarts=200))
+    if rc != G.GABP_OK:
+        raise SystemExit(f"plan_create_grid: {G.status_name(rc)}")
+    xc = torch.zeros(m.n, dtype=torch.float64, device=dev)
+    G.gabp_plan_solve_coarse(gp, b, xc)  # builds the coarse levels
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(K):
+        rc, cst = G.gabp_plan_solve_coarse(gp, b, xc)
+    torch.cuda.synchronize()
+    coarse_ms = (time.perf_counter() - t1) * 1e3 / K
+    G.gabp_plan_destroy(gp)
+    if rc != G.GABP_OK:
+        raise SystemExit(f"coarse solve: {G.status_name(rc)}")
+    xch = xc.cpu().numpy()
+    coarse_rel = oracle.residual(m, b_h, xch)[1] / np.linalg.norm(b_h)
     lds_bytes = 32.0 * E + 8.0 * m.n  # FP64 in-message read 16 + write 16 per edge, b per node
     achieved = lds_bytes * per_sweep / avg_s / 1e9
     out = {
@@ -547,6 +568,9 @@ def bench_c1(args, G, W, torch, dev):
             "sweeps": per_sweep, "rel_residual": rn / np.linalg.norm(b_h),
             "err_vs_oracle": err, "oracle_rounds": ref.rounds, "plan_ms": plan_ms,
             "edge_updates_per_s": E * per_sweep / (dt / K),
+            "time_to_1e-10_ms_coarse_grid_plan": coarse_ms,
+            "coarse_corrections": cst.restarts, "rel_residual_coarse": coarse_rel,
+            "err_vs_oracle_coarse": float(np.linalg.norm(xch - ref.x) / np.linalg.norm(ref.x)),
         },
         "roofline": {
             "bound": "lds", "achieved": achieved, "peak": LDS_PEAK_CU_GBS, "unit": "GB/s",

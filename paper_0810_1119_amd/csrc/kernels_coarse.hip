@@ -114,29 +114,35 @@ __device__ __forceinline__ double stencil_ax(const GridGeom &g, const GridCoef<d
   return ax;
 }
 
-// rc[I] = sum over the cells i of block I of (v - A d)_i (fixed order: z, y, x)
+// rc[I] = sum over the cells i of block I of (v - A d)_i.  Eight lanes per
+// coarse cell, lane k on the child (k & 1, (k >> 1) & 1, k >> 2) of the
+// 2 x 2 x 2 block (absent children add 0), summed by a fixed butterfly over
+// the eight lanes, so every lane holds the same sum; consecutive coarse
+// cells on consecutive lane groups keep the fine reads in runs along x.
 template <bool VARC>
-__global__ void k_coarse_residual_restrict(GridGeom f, GridCoef<double> k, GridGeom c,
-                                           const double *__restrict__ v,
-                                           const double *__restrict__ d, double *__restrict__ rc) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= c.N) return;
-  const int nc = c.nx * c.ny * c.nz, nf = f.nx * f.ny * f.nz;
-  const int t = I / nc, j = I - t * nc;
-  const int X = j % c.nx, Y = (j / c.nx) % c.ny, Z = j / (c.nx * c.ny);
-  const int sx = f.nx > 1 ? 2 : 1, sy = f.ny > 1 ? 2 : 1, sz = f.nz > 1 ? 2 : 1;
-  const int x0 = X * sx, y0 = Y * sy, z0 = Z * sz;
-  const int x1 = min(x0 + sx, f.nx), y1 = min(y0 + sy, f.ny), z1 = min(z0 + sz, f.nz);
-  double s = 0.0;
-  for (int z = z0; z < z1; ++z)
-    for (int y = y0; y < y1; ++y)
-      for (int x = x0; x < x1; ++x) {
-        const int i = t * nf + x + f.nx * (y + f.ny * z);
-        double r = v[i];
-        r -= stencil_ax<VARC>(f, k, d, i);
-        s += r;
-      }
-  rc[I] = s;
+__global__ __launch_bounds__(kBlock) void k_coarse_residual_restrict(
+    GridGeom f, GridCoef<double> k, GridGeom c, const double *__restrict__ v,
+    const double *__restrict__ d, double *__restrict__ rc) {
+  const int64_t t8 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int I = (int)(t8 >> 3), kid = threadIdx.x & 7;
+  double r = 0.0;
+  if (I < c.N) {
+    const int nc = c.nx * c.ny * c.nz, nf = f.nx * f.ny * f.nz;
+    const int t = I / nc, j = I - t * nc;
+    const int X = j % c.nx, Y = (j / c.nx) % c.ny, Z = j / (c.nx * c.ny);
+    const int sx = f.nx > 1 ? 2 : 1, sy = f.ny > 1 ? 2 : 1, sz = f.nz > 1 ? 2 : 1;
+    const int dx = kid & 1, dy = (kid >> 1) & 1, dz = kid >> 2;
+    const int x = X * sx + dx, y = Y * sy + dy, z = Z * sz + dz;
+    if (dx < sx && dy < sy && dz < sz && x < f.nx && y < f.ny && z < f.nz) {
+      const int i = t * nf + x + f.nx * (y + f.ny * z);
+      r = v[i];
+      r -= stencil_ax<VARC>(f, k, d, i);
+    }
+  }
+  r += __shfl_xor(r, 1, 8);
+  r += __shfl_xor(r, 2, 8);
+  r += __shfl_xor(r, 4, 8);
+  if (I < c.N && kid == 0) rc[I] = r;
 }
 
 // e = d and v = v - A d: the right-hand side of a level's next cycle
@@ -653,12 +659,13 @@ hipError_t launch_coarse_residual_restrict(const GridGeom &f, const GridCoef<dou
                                            const GridGeom &c, const double *v, const double *d,
                                            double *rc, hipStream_t s) {
   if (c.N <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((8 * (int64_t)c.N + kBlock - 1) / kBlock));
   if (varc)
-    hipLaunchKernelGGL(k_coarse_residual_restrict<true>, blocks_for(c.N), dim3(kBlock), 0, s, f, k,
-                       c, v, d, rc);
+    hipLaunchKernelGGL(k_coarse_residual_restrict<true>, grid, dim3(kBlock), 0, s, f, k, c, v, d,
+                       rc);
   else
-    hipLaunchKernelGGL(k_coarse_residual_restrict<false>, blocks_for(c.N), dim3(kBlock), 0, s, f, k,
-                       c, v, d, rc);
+    hipLaunchKernelGGL(k_coarse_residual_restrict<false>, grid, dim3(kBlock), 0, s, f, k, c, v, d,
+                       rc);
   return hipGetLastError();
 }
 
