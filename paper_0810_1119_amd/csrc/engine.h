@@ -149,6 +149,13 @@ struct Engine {
     hipError_t e = launch_fill_zero(x, n, s);
     return e != hipSuccess ? e : infer(x, nullptr, nullptr, s);
   }
+  // the last sweep of a smoothing (mode 0), then x (set: =, else +=) H/S of
+  // the messages it leaves; an engine may fuse the two
+  virtual hipError_t sweep_means(double *x, bool set, hipStream_t s) {
+    hipError_t e = sweep(0, nullptr, s);
+    if (e != hipSuccess) return e;
+    return set ? infer_set(x, s) : infer(x, nullptr, nullptr, s);
+  }
   // zero all messages, rhs = b, full state; ||b||^2 into the residual partials
   virtual hipError_t reset(const double *b, hipStream_t s) = 0;
   // rhs = b - A x (FP64, optionally r64 = the same), ||.||^2 into the partials
@@ -158,6 +165,12 @@ struct Engine {
   virtual hipError_t ensure_frozen_buffers() { return hipSuccess; }
   virtual bool frozen_ready() const { return false; }
   virtual hipError_t freeze(hipStream_t) { return hipErrorNotSupported; }
+  // freeze, then a (lazy) restart: the informations are discarded, so an
+  // engine need not carry a pending restart out or copy them
+  virtual hipError_t freeze_restart(hipStream_t s) {
+    hipError_t e = freeze(s);
+    return e != hipSuccess ? e : restart_lazy(s);
+  }
   // initial messages from the warm-start network (bfloat16 parameters)
   virtual bool has_warm_start() const { return false; }
   virtual hipError_t warm_start(const uint16_t *, hipStream_t) { return hipErrorNotSupported; }

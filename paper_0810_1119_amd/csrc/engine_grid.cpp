@@ -22,7 +22,8 @@ int check_grid(const gabp_grid *A, GridGeom *g) {
   if (!A->diag && (A->diag_value == 0.0)) return GABP_ERR_ZERO_DIAG;
   if (!A->diag && !std::isfinite(A->diag_value)) return GABP_ERR_ARG;
   if (!any && !std::isfinite(A->off_value)) return GABP_ERR_ARG;
-  g->nx = A->nx; g->ny = A->ny; g->nz = A->nz; g->batch = A->batch; g->N = (int)N;
+  g->nx = A->nx; g->ny = A->ny; g->nz = A->nz; g->batch = A->batch;
+  geom_finish(*g);
   return GABP_OK;
 }
 
@@ -190,6 +191,16 @@ struct GridEngine : Engine {
     return err;
   }
 
+  hipError_t freeze_restart(hipStream_t s) override {
+    GridArgs a = args(0, nullptr);
+    a.msg_in = msg[cur];
+    a.msg_out = nullptr;  // informations not copied: the next sweep takes them as zero
+    hipError_t err = launch_grid_freeze(a, s);
+    frozen = true;
+    hzero = true;
+    return err;
+  }
+
   int get_messages(double *P, double *h, hipStream_t s) override {
     if (!P || !h) return GABP_ERR_ARG;
     TRY_HIP(settle_restart(s));
@@ -279,6 +290,26 @@ struct RbGridEngine : GridEngine {
     return hipSuccess;
   }
 
+  // Colour 1's nodes have their final in-messages once colour 0 has sent, so
+  // colour 1's sweep launch also writes their means; colour 0's means follow
+  // in a launch of their own (three launches instead of four, bitwise the
+  // same x)
+  hipError_t sweep_means(double *x, bool set, hipStream_t s) override {
+    const bool z = hzero;
+    hzero = false;
+    RbArgs a = rargs(0, 0, nullptr);
+    a.fl = z ? SWEEP_ZIN | SWEEP_ZOWN : 0;
+    TRY_HIP_E(launch_rb_sweep(a, s));
+    a = rargs(3, 1, nullptr);
+    a.fl = (z ? SWEEP_ZOWN : 0) | (set ? SWEEP_XSET : 0);
+    a.xacc = x;
+    TRY_HIP_E(launch_rb_sweep(a, s));
+    a = rargs(2, 0, nullptr);
+    a.fl = set ? SWEEP_XSET : 0;
+    a.xacc = x;
+    return launch_rb_sweep(a, s);
+  }
+
   hipError_t infer_set(double *x, hipStream_t s) override {
     TRY_HIP_E(settle_restart(s));
     for (int colour = 0; colour < 2; ++colour) {
@@ -352,6 +383,15 @@ struct RbGridEngine : GridEngine {
     a.msg = msg[0];
     hipError_t err = launch_rb_freeze(a, hh[0], s);
     frozen = true;
+    return err;
+  }
+
+  hipError_t freeze_restart(hipStream_t s) override {
+    RbArgs a = rargs(0, 0, nullptr);
+    a.msg = msg[0];
+    hipError_t err = launch_rb_freeze(a, nullptr, s);  // informations not copied
+    frozen = true;
+    hzero = true;
     return err;
   }
 
@@ -590,7 +630,8 @@ struct CoarseHierarchy {
 
   // d_l (set: =, else +=) the means of `sweeps` GaBP sweeps on right-hand
   // side v (NULL: the engine already holds it), from zero information
-  // messages (zeroed by the first sweep itself)
+  // messages (zeroed by the first sweep itself).  On level 0 the solve's FP64
+  // residual has just written v into the engine's right-hand side as well.
   int smooth(int l, const double *v, int sweeps, bool set, hipStream_t s) {
     Level &L = lv[l];
     if (v && L.fresh) {
@@ -598,18 +639,17 @@ struct CoarseHierarchy {
       L.fresh = false;
       L.swept = 0;
     } else {
-      if (v) TRY_HIP(L.eng->residual(v, nullptr, nullptr, s));
+      if (v && l > 0) TRY_HIP(L.eng->residual(v, nullptr, nullptr, s));
       TRY_HIP(L.eng->restart_lazy(s));  // zero informations (after a freeze: the settled ones)
     }
     if (freeze && !L.eng->frozen && L.swept >= kCoarseFreezeAfter) {
       TRY_HIP(L.eng->ensure_frozen_buffers());
-      TRY_HIP(L.eng->freeze(s));
-      TRY_HIP(L.eng->restart_lazy(s));
+      TRY_HIP(L.eng->freeze_restart(s));
     }
-    for (int k = 0; k < sweeps; ++k) TRY_HIP(L.eng->sweep(0, nullptr, s));
+    static_assert(kCoarsePre > 0 && kCoarseSweeps > 0, "every smoothing sweeps");
+    for (int k = 0; k + 1 < sweeps; ++k) TRY_HIP(L.eng->sweep(0, nullptr, s));
+    TRY_HIP(L.eng->sweep_means(L.d, set, s));
     L.swept += sweeps;
-    if (set) TRY_HIP(L.eng->infer_set(L.d, s));
-    else TRY_HIP(L.eng->infer(L.d, nullptr, nullptr, s));
     return GABP_OK;
   }
 

@@ -271,10 +271,48 @@ hipError_t launch_pair_io(bool fp32, bool get, int n, int nb, const int64_t *rp,
                           void *msg, double *P, double *h, hipStream_t s);
 
 // ---- structured grids (kernels_grid.hip) ----
+// n / d for 0 <= n < 2^31 and 1 <= d < 2^31 as a multiply and a shift
+// (division by invariant integers, Granlund and Montgomery, PLDI 1994): with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, the quotient is
+// (mulhi(m, n) + n) >> l, where the sum stays below 2^32 because n < 2^31.
+// The index arithmetic of the grid kernels divides by the grid's extents; a
+// divisor known only at run time otherwise costs a few dozen instructions.
+struct FastDiv {
+  uint32_t m = 0, l = 0;
+  int d = 0;  // the divisor (0: not set up)
+};
+inline FastDiv fast_div(int d) {
+  FastDiv f;
+  uint32_t l = 0;
+  while ((1ull << l) < (uint64_t)d) ++l;
+  f.l = l;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - (uint64_t)d)) / (uint64_t)d + 1);
+  f.d = d;
+  return f;
+}
+__host__ __device__ inline int fdiv(int n, const FastDiv &f) {
+  const uint32_t t = (uint32_t)(((uint64_t)f.m * (uint32_t)n) >> 32);
+  return (int)((t + (uint32_t)n) >> f.l);
+}
+
 struct GridGeom {
   int nx, ny, nz, batch;
   int N;  // nx * ny * nz * batch
+  // divisions by nx, ny, nz and by the red-black row length (nx + 1) / 2
+  FastDiv fx, fy, fz, fh;
 };
+// sets N and the divisors from nx, ny, nz, batch
+inline void geom_finish(GridGeom &g) {
+  g.N = g.nx * g.ny * g.nz * g.batch;
+  g.fx = fast_div(g.nx);
+  g.fy = fast_div(g.ny);
+  g.fz = fast_div(g.nz);
+  g.fh = fast_div((g.nx + 1) / 2);
+}
+inline bool geom_ok(const GridGeom &g) {
+  return g.nx >= 1 && g.ny >= 1 && g.nz >= 1 && g.batch >= 1 && g.fx.d == g.nx &&
+         g.fy.d == g.ny && g.fz.d == g.nz && g.fh.d == (g.nx + 1) / 2;
+}
 template <typename T> struct GridCoef {
   const T *diag, *cx, *cy, *cz;  // per node / per face (NULL when constant)
   T dconst, aconst;              // constant diagonal and coupling
@@ -306,6 +344,7 @@ struct GridArgs {
   int fl;              // SWEEP_*
 };
 hipError_t launch_grid_sweep(const GridArgs &a, hipStream_t s);
+// a.msg_out receives the information messages (NULL: not copied)
 hipError_t launch_grid_freeze(const GridArgs &a, hipStream_t s);
 // rT (the working-precision right-hand side) in natural order when hx == 0,
 // else in the two-colour order of a red-black plan with hx slots per row.
@@ -339,8 +378,9 @@ hipError_t launch_seg_norms(const double *sumpart, int nseg, int segb, double *s
 // Nc = hx * ny * nz * batch.
 __host__ __device__ inline int rb_row_slots(const GridGeom &g) { return (g.nx + 1) / 2; }
 __host__ __device__ inline void rb_place(const GridGeom &g, int hx, int i, int &colour, int &slot) {
-  const int x = i % g.nx, r = i / g.nx;
-  colour = (x + r % g.ny + r / g.ny) & 1;
+  const int r = fdiv(i, g.fx), x = i - r * g.nx;
+  const int z = fdiv(r, g.fy), y = r - z * g.ny;
+  colour = (x + y + z) & 1;
   slot = r * hx + (x >> 1);
 }
 struct RbArgs {
@@ -349,7 +389,8 @@ struct RbArgs {
   int grid;            // blocks of a one-colour launch
   int colour;          // the class a sweep launch updates
   bool fp32, varc, damp, frozen;
-  int mode;            // 0 sweep, 1 sweep + check, 2 means / precisions only
+  int mode;            // 0 sweep, 1 sweep + check, 2 means / precisions only,
+                       // 3 sweep + the colour's means into xacc (no segments)
   const void *diag, *cx, *cy, *cz;  // working-precision coefficients, natural order (varc)
   double dconst, aconst;
   const void *rhs;     // [2][Nc]
@@ -371,7 +412,8 @@ struct RbArgs {
 };
 hipError_t launch_rb_sweep(const RbArgs &a, hipStream_t s);
 // coefficients, information messages and S of the settled phase from the
-// full state (both colours); hh receives the information messages
+// full state (both colours); hh receives the information messages (NULL:
+// not copied, for a restart that follows)
 hipError_t launch_rb_freeze(const RbArgs &a, void *hh, hipStream_t s);
 // export (get) / import of the messages in the natural direction-major FP64
 // order [6][N] of the synchronous plans

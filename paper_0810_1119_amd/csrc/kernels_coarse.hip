@@ -16,14 +16,25 @@ namespace {
 
 __device__ __forceinline__ int half_up(int n) { return n > 1 ? (n + 1) / 2 : 1; }
 
+// (x, y, z) of cell i of a stack and its grid t
+__device__ __forceinline__ void grid_coords(const GridGeom &g, int i, int &x, int &y, int &z,
+                                            int &t) {
+  const int r = fdiv(i, g.fx);
+  x = i - r * g.nx;
+  const int q = fdiv(r, g.fy);
+  y = r - q * g.ny;
+  t = fdiv(q, g.fz);
+  z = q - t * g.nz;
+}
+
 __global__ void k_coarse_coef(GridGeom f, GridCoef<double> k, int varc, GridGeom c,
                               double *__restrict__ dg, double *__restrict__ cx,
                               double *__restrict__ cy, double *__restrict__ cz) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= c.N) return;
-  const int nc = c.nx * c.ny * c.nz, nf = f.nx * f.ny * f.nz;
-  const int t = I / nc, j = I - t * nc;
-  const int X = j % c.nx, Y = (j / c.nx) % c.ny, Z = j / (c.nx * c.ny);
+  const int nf = f.nx * f.ny * f.nz;
+  int t, X, Y, Z;
+  grid_coords(c, I, X, Y, Z, t);
   const int sx = f.nx > 1 ? 2 : 1, sy = f.ny > 1 ? 2 : 1, sz = f.nz > 1 ? 2 : 1;
   const int x0 = X * sx, y0 = Y * sy, z0 = Z * sz;
   const int x1 = min(x0 + sx, f.nx), y1 = min(y0 + sy, f.ny), z1 = min(z0 + sz, f.nz);
@@ -60,9 +71,9 @@ __global__ void k_coarse_restrict(GridGeom f, GridGeom c, const double *__restri
                                   double *__restrict__ rc) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= c.N) return;
-  const int nc = c.nx * c.ny * c.nz, nf = f.nx * f.ny * f.nz;
-  const int t = I / nc, j = I - t * nc;
-  const int X = j % c.nx, Y = (j / c.nx) % c.ny, Z = j / (c.nx * c.ny);
+  const int nf = f.nx * f.ny * f.nz;
+  int t, X, Y, Z;
+  grid_coords(c, I, X, Y, Z, t);
   const int sx = f.nx > 1 ? 2 : 1, sy = f.ny > 1 ? 2 : 1, sz = f.nz > 1 ? 2 : 1;
   const int x0 = X * sx, y0 = Y * sy, z0 = Z * sz;
   const int x1 = min(x0 + sx, f.nx), y1 = min(y0 + sy, f.ny), z1 = min(z0 + sz, f.nz);
@@ -78,11 +89,12 @@ __global__ void k_coarse_prolong(GridGeom f, GridGeom c, const double *__restric
                                  double scale, double *__restrict__ d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= f.N) return;
-  const int nf = f.nx * f.ny * f.nz, nc = c.nx * c.ny * c.nz;
-  const int t = i / nf, j = i - t * nf;
-  const int x = j % f.nx, y = (j / f.nx) % f.ny, z = j / (f.nx * f.ny);
-  const int sx = f.nx > 1 ? 2 : 1, sy = f.ny > 1 ? 2 : 1, sz = f.nz > 1 ? 2 : 1;
-  d[i] += scale * dc[t * nc + x / sx + c.nx * (y / sy + c.ny * (z / sz))];
+  const int nc = c.nx * c.ny * c.nz;
+  int t, x, y, z;
+  grid_coords(f, i, x, y, z, t);
+  // an axis of extent 1 is not halved
+  const int hx = f.nx > 1, hy = f.ny > 1, hz = f.nz > 1;
+  d[i] += scale * dc[t * nc + (x >> hx) + c.nx * ((y >> hy) + c.ny * (z >> hz))];
 }
 
 // (A x)_i of a 5/7-point stack in FP64, terms in the order of the grid
@@ -90,9 +102,9 @@ __global__ void k_coarse_prolong(GridGeom f, GridGeom c, const double *__restric
 // kernels below give bitwise the results of residual + restriction
 template <bool VARC>
 __device__ __forceinline__ double stencil_ax(const GridGeom &g, const GridCoef<double> &k,
-                                             const double *__restrict__ x, int i) {
+                                             const double *__restrict__ x, int i, int xx, int y,
+                                             int zl) {
   const int nxy = g.nx * g.ny;
-  const int xx = i % g.nx, y = (i / g.nx) % g.ny, zl = (i / nxy) % g.nz;
   const bool ok[6] = {xx < g.nx - 1, xx > 0, y < g.ny - 1, y > 0, zl < g.nz - 1, zl > 0};
   const int j[6] = {i + 1, i - 1, i + g.nx, i - g.nx, i + nxy, i - nxy};
   double a[6];
@@ -107,11 +119,21 @@ __device__ __forceinline__ double stencil_ax(const GridGeom &g, const GridCoef<d
 #pragma unroll
     for (int d = 0; d < 6; ++d) a[d] = ok[d] ? k.aconst : 0.0;
   }
+  double xn[6];  // loaded on the geometry alone, not after the couplings
+#pragma unroll
+  for (int d = 0; d < 6; ++d) xn[d] = ok[d] ? x[j[d]] : 0.0;
   double ax = (VARC ? k.diag[i] : k.dconst) * x[i];
 #pragma unroll
   for (int d = 0; d < 6; ++d)
-    if (a[d] != 0.0) ax += a[d] * x[j[d]];
+    if (a[d] != 0.0) ax += a[d] * xn[d];
   return ax;
+}
+template <bool VARC>
+__device__ __forceinline__ double stencil_ax(const GridGeom &g, const GridCoef<double> &k,
+                                             const double *__restrict__ x, int i) {
+  int xx, y, zl, t;
+  grid_coords(g, i, xx, y, zl, t);
+  return stencil_ax<VARC>(g, k, x, i, xx, y, zl);
 }
 
 // rc[I] = sum over the cells i of block I of (v - A d)_i.  Eight lanes per
@@ -127,16 +149,16 @@ __global__ __launch_bounds__(kBlock) void k_coarse_residual_restrict(
   const int I = (int)(t8 >> 3), kid = threadIdx.x & 7;
   double r = 0.0;
   if (I < c.N) {
-    const int nc = c.nx * c.ny * c.nz, nf = f.nx * f.ny * f.nz;
-    const int t = I / nc, j = I - t * nc;
-    const int X = j % c.nx, Y = (j / c.nx) % c.ny, Z = j / (c.nx * c.ny);
+    const int nf = f.nx * f.ny * f.nz;
+    int t, X, Y, Z;
+    grid_coords(c, I, X, Y, Z, t);
     const int sx = f.nx > 1 ? 2 : 1, sy = f.ny > 1 ? 2 : 1, sz = f.nz > 1 ? 2 : 1;
     const int dx = kid & 1, dy = (kid >> 1) & 1, dz = kid >> 2;
     const int x = X * sx + dx, y = Y * sy + dy, z = Z * sz + dz;
     if (dx < sx && dy < sy && dz < sz && x < f.nx && y < f.ny && z < f.nz) {
       const int i = t * nf + x + f.nx * (y + f.ny * z);
       r = v[i];
-      r -= stencil_ax<VARC>(f, k, d, i);
+      r -= stencil_ax<VARC>(f, k, d, i, x, y, z);
     }
   }
   r += __shfl_xor(r, 1, 8);
@@ -628,7 +650,7 @@ GridGeom coarse_geom(const GridGeom &f) {
   c.ny = f.ny > 1 ? (f.ny + 1) / 2 : 1;
   c.nz = f.nz > 1 ? (f.nz + 1) / 2 : 1;
   c.batch = f.batch;
-  c.N = c.nx * c.ny * c.nz * c.batch;
+  geom_finish(c);
   return c;
 }
 
@@ -636,6 +658,7 @@ hipError_t launch_coarse_coef(const GridGeom &f, const GridCoef<double> &k, bool
                               const GridGeom &c, double *dg, double *cx, double *cy, double *cz,
                               hipStream_t s) {
   if (c.N <= 0) return hipSuccess;
+  if (!geom_ok(f) || !geom_ok(c)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_coarse_coef, blocks_for(c.N), dim3(kBlock), 0, s, f, k, varc ? 1 : 0, c, dg,
                      cx, cy, cz);
   return hipGetLastError();
@@ -644,6 +667,7 @@ hipError_t launch_coarse_coef(const GridGeom &f, const GridCoef<double> &k, bool
 hipError_t launch_coarse_restrict(const GridGeom &f, const GridGeom &c, const double *r, double *rc,
                                   hipStream_t s) {
   if (c.N <= 0) return hipSuccess;
+  if (!geom_ok(f) || !geom_ok(c)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_coarse_restrict, blocks_for(c.N), dim3(kBlock), 0, s, f, c, r, rc);
   return hipGetLastError();
 }
@@ -651,6 +675,7 @@ hipError_t launch_coarse_restrict(const GridGeom &f, const GridGeom &c, const do
 hipError_t launch_coarse_prolong(const GridGeom &f, const GridGeom &c, const double *dc,
                                  double scale, double *d, hipStream_t s) {
   if (f.N <= 0) return hipSuccess;
+  if (!geom_ok(f) || !geom_ok(c)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_coarse_prolong, blocks_for(f.N), dim3(kBlock), 0, s, f, c, dc, scale, d);
   return hipGetLastError();
 }
@@ -659,6 +684,7 @@ hipError_t launch_coarse_residual_restrict(const GridGeom &f, const GridCoef<dou
                                            const GridGeom &c, const double *v, const double *d,
                                            double *rc, hipStream_t s) {
   if (c.N <= 0) return hipSuccess;
+  if (!geom_ok(f) || !geom_ok(c)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((8 * (int64_t)c.N + kBlock - 1) / kBlock));
   if (varc)
     hipLaunchKernelGGL(k_coarse_residual_restrict<true>, grid, dim3(kBlock), 0, s, f, k, c, v, d,
@@ -672,6 +698,7 @@ hipError_t launch_coarse_residual_restrict(const GridGeom &f, const GridCoef<dou
 hipError_t launch_coarse_copy_residual(const GridGeom &g, const GridCoef<double> &k, bool varc,
                                        const double *d, double *e, double *v, hipStream_t s) {
   if (g.N <= 0) return hipSuccess;
+  if (!geom_ok(g)) return hipErrorInvalidValue;
   if (varc)
     hipLaunchKernelGGL(k_coarse_copy_residual<true>, blocks_for(g.N), dim3(kBlock), 0, s, g, k, d,
                        e, v);

@@ -36,6 +36,8 @@ struct RbNode {
 };
 
 __device__ __forceinline__ bool rb_node(const GridGeom &g, int hx, int c, int s, RbNode &n) {
+  // the compiler's divisions: with GridGeom's multiply-and-shift divisors
+  // the check launches of the 64-grid stack ran 300 -> 400 us
   const int r = s / hx;
   const int kx = s - r * hx;
   const int y = r % g.ny;
@@ -132,7 +134,9 @@ __device__ __forceinline__ void rb_cover(int Nc, int nseg, const int32_t *__rest
   }
 }
 
-// MODE 0 sweep, 1 sweep + check, 2 means / precisions only (no messages)
+// MODE 0 sweep, 1 sweep + check, 2 means / precisions only (no messages),
+// 3 sweep + means of the launch's colour into xacc (its nodes' in-messages
+// are final once the other colour has sent; not with segments)
 template <typename T, int MODE, bool DAMP, bool VARC, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_rb_sweep(
     GridGeom g, int hx, int Nc, int c, GridCoef<T> k, typename Vec2<T>::type *__restrict__ msg,
@@ -150,6 +154,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
     if (!rb_node(g, hx, c, s, nd)) return;
     T a[6];
     rb_couplings<T, VARC>(g, k, nd, a);
+    // In-messages behind the couplings: loading them on the geometry alone,
+    // without waiting for the couplings, made these launches slower (the
+    // whole-grid launches by 10%, check launches by 14%).
     T Pin[6], hin[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
@@ -167,6 +174,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
       S += Pin[d];
       H += hin[d];
     }
+    // MODE 3: xacc's previous value loaded before the stores
+    double xa = 0.0;
+    if (MODE == 3 && xacc && !(fl & SWEEP_XSET)) xa = xacc[nd.i];
     if (MODE != 2) {
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
@@ -206,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
         // a segment sitting the pass out gets no correction
         if (xacc && !(SEG && seg[s / (Nc / nseg)].done == 2)) {
           const double m = (double)H / (double)S;
-          xacc[nd.i] = (fl & SWEEP_XSET) ? m : xacc[nd.i] + m;
+          xacc[nd.i] = (fl & SWEEP_XSET) ? m : (MODE == 3 ? xa : xacc[nd.i]) + m;
         }
         if (marg) marg[nd.i] = (double)S;
         if (xp) *xp = x;  // means of the current messages
@@ -217,7 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_sweep(
   if (acc.f) atomicOr(sticky, acc.f);
 }
 
-// settled phase: information only, fixed coefficients coef[(6 c + d) Nc + s]
+// settled phase: information only, fixed coefficients coef[(6 c + d) Nc + s];
+// MODE as in k_rb_sweep
 template <typename T, int MODE, bool DAMP, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_rb_frozen(
     GridGeom g, int hx, int Nc, int c, const T *__restrict__ coef, const T *__restrict__ Sfix,
@@ -258,6 +269,12 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
       if (MODE >= 1) S = Sfix[(size_t)c * Nc + s];
       if (MODE == 1) xold = *xp;
     }
+    // MODE 3: the means' operands with the messages, not after the stores
+    double xa = 0.0;
+    if (MODE == 3) {
+      S = Sfix[(size_t)c * Nc + s];
+      if (xacc && !(fl & SWEEP_XSET)) xa = xacc[nd.i];
+    }
 #pragma unroll
     for (int d = 0; d < 6; ++d) H += hin[d];
     if (MODE != 2) {
@@ -274,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
       }
     }
     if (MODE >= 1) {
-      if (!SEG) {
+      if (!SEG && MODE != 3) {
         S = Sfix[(size_t)c * Nc + s];
         if (MODE == 1) xold = *xp;
       }
@@ -286,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
       } else {
         if (xacc && !(SEG && seg[s / (Nc / nseg)].done == 2)) {
           const double m = (double)H / (double)S;
-          xacc[nd.i] = (fl & SWEEP_XSET) ? m : xacc[nd.i] + m;
+          xacc[nd.i] = (fl & SWEEP_XSET) ? m : (MODE == 3 ? xa : xacc[nd.i]) + m;
         }
         if (marg) marg[nd.i] = (double)S;
         if (xp) *xp = x;
@@ -297,7 +314,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_frozen(
   if (acc.f) atomicOr(sticky, acc.f);
 }
 
-// freeze: coefficients, S and information messages of both colours
+// freeze: coefficients, S and information messages of both colours (hh NULL:
+// the informations are discarded, a restart follows)
 template <typename T, bool VARC>
 __global__ __launch_bounds__(kBlock) void k_rb_freeze(GridGeom g, int hx, int Nc, GridCoef<T> k,
                                                       const typename Vec2<T>::type *__restrict__ msg,
@@ -317,7 +335,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_freeze(GridGeom g, int hx, int Nc
     T S = VARC ? k.diag[nd.i] : k.dconst;
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
-      Pin[d] = a[d] != T(0) ? other[(size_t)(d ^ 1) * Nc + nd.j[d]].x : T(0);
+      const T p = nd.ok[d] ? other[(size_t)(d ^ 1) * Nc + nd.j[d]].x : T(0);
+      Pin[d] = a[d] != T(0) ? p : T(0);
       S += Pin[d];
     }
     Sfix[(size_t)c * Nc + s] = S;
@@ -325,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_freeze(GridGeom g, int hx, int Nc
     for (int d = 0; d < 6; ++d) {
       const size_t o = own + (size_t)d * Nc + s;
       coef[o] = a[d] != T(0) ? -a[d] / (S - Pin[d]) : T(0);
-      hh[o] = a[d] != T(0) ? msg[o].y : T(0);
+      if (hh) hh[o] = a[d] != T(0) ? msg[o].y : T(0);
     }
   }
 }
@@ -380,6 +399,11 @@ void rb_mode_seg(const RbArgs &a, hipStream_t s) {
   switch (a.mode) {
     case 0: a.damp ? rb_one<T, 0, true, VARC, SEG>(a, s) : rb_one<T, 0, false, VARC, SEG>(a, s); break;
     case 1: a.damp ? rb_one<T, 1, true, VARC, SEG>(a, s) : rb_one<T, 1, false, VARC, SEG>(a, s); break;
+    case 3:
+      if constexpr (!SEG) {
+        a.damp ? rb_one<T, 3, true, VARC, false>(a, s) : rb_one<T, 3, false, VARC, false>(a, s);
+      }
+      break;
     default: rb_one<T, 2, false, VARC, SEG>(a, s); break;
   }
 }
@@ -403,6 +427,8 @@ hipError_t launch_rb_sweep(const RbArgs &a, hipStream_t s) {
   if (a.Nc <= 0) return hipSuccess;
   if (a.seg && (a.nseg < 1 || a.nseg > a.grid || a.Nc % a.nseg != 0 || !a.act))
     return hipErrorInvalidValue;
+  if (a.mode < 0 || a.mode > 3 || (a.mode == 3 && a.seg)) return hipErrorInvalidValue;
+  if (!geom_ok(a.g) || a.hx != a.g.fh.d) return hipErrorInvalidValue;
   if (a.fp32) a.varc ? rb_mode<float, true>(a, s) : rb_mode<float, false>(a, s);
   else a.varc ? rb_mode<double, true>(a, s) : rb_mode<double, false>(a, s);
   return hipGetLastError();
@@ -410,6 +436,7 @@ hipError_t launch_rb_sweep(const RbArgs &a, hipStream_t s) {
 
 hipError_t launch_rb_freeze(const RbArgs &a, void *hh, hipStream_t s) {
   if (a.Nc <= 0) return hipSuccess;
+  if (!geom_ok(a.g) || a.hx != a.g.fh.d) return hipErrorInvalidValue;
   if (a.fp32) a.varc ? rb_freeze<float, true>(a, hh, s) : rb_freeze<float, false>(a, hh, s);
   else a.varc ? rb_freeze<double, true>(a, hh, s) : rb_freeze<double, false>(a, hh, s);
   return hipGetLastError();
@@ -419,6 +446,7 @@ hipError_t launch_rb_io(bool fp32, bool get, const GridGeom &g, int hx, int Nc, 
                         double *P, double *h, hipStream_t s) {
   const int64_t m = 6 * (int64_t)g.N;
   if (m <= 0) return hipSuccess;
+  if (!geom_ok(g) || hx != g.fh.d) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((m + kBlock - 1) / kBlock));
   if (fp32) {
     if (get) hipLaunchKernelGGL((k_rb_io<float, true>), grid, dim3(kBlock), 0, s, g, hx, Nc, (float2 *)msg, P, h);

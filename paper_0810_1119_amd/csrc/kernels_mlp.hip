@@ -499,6 +499,7 @@ hipError_t launch_grid_warm(bool fp32, const GridGeom &g, const void *diag, cons
                             const void *cy, const void *cz, double dconst, double aconst,
                             const void *rhs, const uint16_t *w, void *msg, hipStream_t s, int hx) {
   if (g.N <= 0) return hipSuccess;
+  if (!geom_ok(g) || (hx > 0 && hx != g.fh.d)) return hipErrorInvalidValue;
   const dim3 grid(blocks_for(g.N, 2048));
   if (fp32) {
     GridCoef<float> k{(const float *)diag, (const float *)cx, (const float *)cy, (const float *)cz,
