@@ -124,32 +124,47 @@ def grid_schedule(args, G):
 
 
 def measured_traffic(kernel_key: str, workload: str, check_share: float = 0.5):
-    """HBM bytes per launch of a kernel on a workload from the committed PMC
-    summary (profiles/traffic.json): its plain (MODE 0) and check (MODE 1)
-    variants weighted by the share of check launches in the timed solves, or
-    None when no counters were taken for that workload or the kernel's source
-    changed since."""
+    """HBM bytes per launch of a kernel instantiation on a workload from the
+    committed PMC summary (profiles/traffic.json).  kernel_key is the record's
+    name; with "{m}" in place of the mode argument, its plain (mode 0) and
+    check (mode 1) records are weighted by the share of check launches in the
+    timed solves.  None when no counters were taken for that workload or the
+    kernel's source changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    t = json.load(open(path))
-    by_mode = {}
-    for name, rec in t["kernels"].items():
-        if not name.startswith(kernel_key) or rec.get("workload") != workload:
+    recs = json.load(open(path))["kernels"]
+    names = [kernel_key.replace("{m}", m) for m in ("0", "1")] if "{m}" in kernel_key \
+        else [kernel_key]
+    vals = []
+    for name in names:
+        rec = recs.get(name)
+        if rec is None or rec.get("workload") != workload:
+            vals.append(None)
             continue
         src = os.path.join(ROOT, "paper_0810_1119_amd", "csrc", rec["source"])
         if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
             return None
-        mode = name[len(kernel_key):].split(",")[0].strip()
-        by_mode.setdefault(mode, []).append(rec["bytes_per_launch"])
-    if not by_mode:
-        return None
-    if set(by_mode) == {"0", "1"}:
-        plain, check = (sum(v) / len(v) for v in (by_mode["0"], by_mode["1"]))
-        return (1.0 - check_share) * plain + check_share * check
-    vals = [x for v in by_mode.values() for x in v]
-    return sum(vals) / len(vals)
+        vals.append(rec["bytes_per_launch"])
+    if len(vals) == 2 and None not in vals:
+        return (1.0 - check_share) * vals[0] + check_share * vals[1]
+    got = [v for v in vals if v is not None]
+    return got[0] if got else None
+
+
+def grid_tkey(kernel: str, damp: bool, varc: bool, seg: bool) -> str:
+    """traffic record name of a grid sweep instantiation, mode left as {m}
+    (k_rb_sweep<T, MODE, DAMP, VARC, SEG>, k_rb_frozen<T, MODE, DAMP, SEG>,
+    k_grid_sweep / k_grid_frozen<T, MODE, DAMP, VARC>)"""
+    b = lambda v: "true" if v else "false"
+    if kernel == "k_rb_sweep":
+        parts = [b(damp), b(varc), b(seg)]
+    elif kernel == "k_rb_frozen":
+        parts = [b(damp), b(seg)]
+    else:
+        parts = [b(damp), b(varc)]
+    return f"gabp::{kernel}<float, {{m}}, {', '.join(parts)}>"
 
 
 def cpu_baseline(m, b, E, budget_s=12.0):
@@ -207,7 +222,8 @@ def run_c5(args, G, W, torch, dev):
                 bytes_full=lambda c: grid_bytes_per_sweep(N, E, False, True, c) / per,
                 bytes_frozen=lambda c: grid_bytes_per_sweep(N, E, True, True, c) / per,
                 kfull=f"{kf}<float,*,damped,const>", kfrozen=f"{kz}<float,*,damped,const>",
-                tkey_full=f"gabp::{kf}<float, ", tkey_frozen=f"gabp::{kz}<float, ")
+                tkey_full=grid_tkey(kf, True, False, False),
+                tkey_frozen=grid_tkey(kz, True, False, False))
 
 
 def run_c2(args, G, W, torch, dev):
@@ -254,10 +270,10 @@ def run_c2(args, G, W, torch, dev):
                             else "synchronous schedule"),
                 bytes_full=lambda c: (pair_bytes_per_sweep if pair else gather_bytes_per_sweep)(n, E, c) / ncol,
                 bytes_frozen=(lambda c: pair_frozen_bytes_per_sweep(n, E, c) / ncol) if pair else None,
-                tkey_full=("gabp::k_pair_col<float, " if colored else "gabp::k_pair_sweep<float, ")
-                          if pair else None,
-                tkey_frozen=("gabp::k_pair_frozen_col<float, " if colored
-                             else "gabp::k_pair_frozen<float, ") if pair else None,
+                tkey_full=("gabp::k_pair_col<float, {m}, false>" if colored
+                           else "gabp::k_pair_sweep<float, {m}, false>") if pair else None,
+                tkey_frozen=("gabp::k_pair_frozen_col<float, {m}, false>" if colored
+                             else "gabp::k_pair_frozen<float, {m}, false>") if pair else None,
                 kfull=(("k_pair_col<float,*> (one colour class: in-messages, totals, "
                         "out-messages)" if colored else
                         "k_pair_sweep<float,*> (A1 node broadcast + A2 edge update + A3 check)")
@@ -309,9 +325,10 @@ def run_lsq(args, G, W, torch, dev):
                          + ("coloured schedule (x, then z)" if colored else "synchronous schedule"),
                 bytes_full=lambda c: pair_bytes_per_sweep(n, E, c) / per,
                 bytes_frozen=lambda c: pair_frozen_bytes_per_sweep(n, E, c) / per,
-                tkey_full="gabp::k_pair_col<float, " if colored else "gabp::k_pair_sweep<float, ",
-                tkey_frozen=("gabp::k_pair_frozen_col<float, " if colored
-                             else "gabp::k_pair_frozen<float, "),
+                tkey_full=("gabp::k_pair_col<float, {m}, false>" if colored
+                           else "gabp::k_pair_sweep<float, {m}, false>"),
+                tkey_frozen=("gabp::k_pair_frozen_col<float, {m}, false>" if colored
+                             else "gabp::k_pair_frozen<float, {m}, false>"),
                 kfull=("k_pair_col<float,*> (one colour class)" if colored else
                        "k_pair_sweep<float,*> (A1 node broadcast + A2 edge update + A3 check)"),
                 kfrozen="k_pair_frozen_col<float,*>" if colored else "k_pair_frozen<float,*>")
@@ -778,14 +795,15 @@ def bench_c4(args, G, W, torch, dev):
                 "avg_launch_us": fz_avg_s * 1e6, "launches_timed": fz_launches,
                 "own_bytes_per_launch": fz_bpl, "achieved_GBps": fz_gbs,
                 "frac_of_hbm_peak": fz_gbs / HBM_PEAK_GBS,
-                "traffic": measured_traffic(f"gabp::{kz}<float, ", "c4", 1.0 / c_eff),
+                "traffic": measured_traffic(grid_tkey(kz, False, True, per == 2), "c4",
+                                            1.0 / c_eff),
                 "device_time_share": fz_ms / max(sum(st.sweep_ms for st in runs), 1e-30),
             },
         },
         "roofline": {
             "bound": "hbm", "achieved": full_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": full_gbs / HBM_PEAK_GBS,
-            "traffic": measured_traffic(f"gabp::{kf}<float, ", "c4"),
+            "traffic": measured_traffic(grid_tkey(kf, False, True, per == 2), "c4"),
             "kernel": f"{kf}<float,*,undamped> (full (P, h) sweep: A1 + A2 + A3"
                       f"{', one launch per colour' if per == 2 else ''})",
             "avg_launch_us": full_avg_s * 1e6, "algorithmic_bytes_per_launch": full_bpl,

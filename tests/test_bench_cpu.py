@@ -32,17 +32,33 @@ def _traffic(tmp_path, entries, src_text=b"kernel source"):
 
 
 def test_measured_traffic_weights_plain_and_check_launches(tmp_path, monkeypatch):
-    root = _traffic(tmp_path, {"gabp::k<float, 0, false>": 100.0, "gabp::k<float, 1, false>": 200.0})
+    """Only the named instantiation counts: records of the same kernel with
+    other template arguments (other modes, the coarse levels' variants) are
+    not mixed in."""
+    root = _traffic(tmp_path, {"gabp::k<float, 0, false>": 100.0, "gabp::k<float, 1, false>": 200.0,
+                               "gabp::k<float, 2, false>": 7.0, "gabp::k<float, 0, true>": 9.0})
     monkeypatch.setattr(bench, "ROOT", root)
-    assert bench.measured_traffic("gabp::k<float, ", "w", 0.25) == pytest.approx(125.0)
-    assert bench.measured_traffic("gabp::k<float, ", "w") == pytest.approx(150.0)
-    assert bench.measured_traffic("gabp::k<float, ", "other") is None
+    assert bench.measured_traffic("gabp::k<float, {m}, false>", "w", 0.25) == pytest.approx(125.0)
+    assert bench.measured_traffic("gabp::k<float, {m}, false>", "w") == pytest.approx(150.0)
+    assert bench.measured_traffic("gabp::k<float, {m}, true>", "w") == pytest.approx(9.0)
+    assert bench.measured_traffic("gabp::k<float, 2, false>", "w") == pytest.approx(7.0)
+    assert bench.measured_traffic("gabp::k<float, {m}, false>", "other") is None
 
 
 def test_measured_traffic_is_dropped_when_the_source_changed(tmp_path, monkeypatch):
     root = _traffic(tmp_path, {"gabp::k<float, 0, false>": 100.0}, src_text=b"edited source")
     monkeypatch.setattr(bench, "ROOT", root)
-    assert bench.measured_traffic("gabp::k<float, ", "w", 0.5) is None
+    assert bench.measured_traffic("gabp::k<float, {m}, false>", "w", 0.5) is None
+
+
+def test_grid_traffic_keys_name_the_template_arguments():
+    assert bench.grid_tkey("k_rb_sweep", False, True, True) == \
+        "gabp::k_rb_sweep<float, {m}, false, true, true>"
+    assert bench.grid_tkey("k_rb_frozen", False, True, True) == "gabp::k_rb_frozen<float, {m}, false, true>"
+    assert bench.grid_tkey("k_grid_sweep", True, False, False) == \
+        "gabp::k_grid_sweep<float, {m}, true, false>"
+    assert bench.grid_tkey("k_grid_frozen", True, False, False) == \
+        "gabp::k_grid_frozen<float, {m}, true, false>"
 
 
 def test_committed_traffic_matches_the_sources():
