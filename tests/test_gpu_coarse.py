@@ -230,3 +230,62 @@ def test_graph_replays_equal_eager_corrections(G):
         torch.cuda.synchronize()
     G.gabp_plan_destroy(pg)
     G.gabp_plan_destroy(pe)
+
+
+def test_damped_colored_cycles_match_oracle(G):
+    """The red-black schedule with damping (the plan's own factor smooths):
+    x after each of the first two cycles equals the oracle's in FP64 (the
+    last launch of every smoothing also writes its colour's means)."""
+    print("case: coarse-grid cycles FP64, red-black damped 0.3", flush=True)
+    nx, ny, nz, batch = 14, 12, 10, 2
+    A, arrs = _grid(G, nx, ny, nz, batch, 17)
+    b = W.normal_b(A.n, 18)
+    _, _, _, trail = OC.solve(nx, ny, nz, batch, *arrs, b, tol=0.0, max_cycles=2, colored=True,
+                              damping=0.3)
+    for k in (1, 2):
+        o = G.gabp_default_opts(msg_fp32=0, tol=0.0, max_restarts=k, freeze=0, damping=0.3,
+                                schedule=G.GABP_SCHEDULE_COLORED)
+        rc, plan = G.gabp_plan_create_grid(A, o)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
+        G.gabp_plan_destroy(plan)
+        assert rc == G.GABP_NOT_CONVERGED and st.restarts == k
+        xh = x.cpu().numpy()
+        assert np.linalg.norm(xh - trail[k - 1]) / np.linalg.norm(trail[k - 1]) < 1e-9, k
+
+
+@pytest.mark.parametrize("kind", ["colored", "colored_damped", "sync_damped"])
+def test_fp32_settled_levels_reach_tolerance(G, kind):
+    """FP32 messages with the levels' precisions settled after their first
+    smoothing (the informations dropped at the switch, not copied), for both
+    engines: every grid's FP64 residual, recomputed by the oracle, meets the
+    tolerance, and x agrees with the plain solve."""
+    print(f"case: coarse-grid FP32 settled levels, {kind}", flush=True)
+    if kind == "sync_damped":
+        nx = ny = nz = 32
+        batch, varc = 1, False
+        o = G.gabp_default_opts(damping=0.5)
+    else:
+        nx = ny = nz = 24
+        batch, varc = 3, True
+        o = G.gabp_default_opts(schedule=G.GABP_SCHEDULE_COLORED,
+                                damping=0.3 if kind == "colored_damped" else 0.0)
+    A, arrs = _grid(G, nx, ny, nz, batch, 19, varc)
+    b = W.normal_b(A.n, 20)
+    rc, plan = G.gabp_plan_create_grid(A, o)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
+    xp = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    rc2, st2 = G.gabp_plan_solve(plan, dev(b), xp)
+    G.gabp_plan_destroy(plan)
+    assert rc == G.GABP_OK and rc2 == G.GABP_OK, (G.status_name(rc), G.status_name(rc2))
+    n = nx * ny * nz
+    xh = x.cpu().numpy()
+    for t in range(batch):
+        sl = slice(t * n, (t + 1) * n)
+        _, rn = oracle.residual_grid(nx, ny, nz, 1, b[sl], xh[sl], diag=arrs[0][sl],
+                                     cx=arrs[1][sl], cy=arrs[2][sl], cz=arrs[3][sl])
+        assert rn / np.linalg.norm(b[sl]) <= 1e-8, t
+    print(f"{kind}: {st.restarts} corrections, plain {st2.sweeps} sweeps", flush=True)
+    assert st.restarts <= 20
+    np.testing.assert_allclose(xh, xp.cpu().numpy(), rtol=0, atol=1e-6 * np.abs(xh).max())
