@@ -95,6 +95,14 @@ struct GridEngine : Engine {
     return a;
   }
 
+  // the working right-hand side, for kernels that produce the FP64 one
+  virtual WorkRhs work_rhs() const {
+    WorkRhs w;
+    w.p = rhs;
+    w.fp32 = fp32;
+    return w;
+  }
+
   // a pending restart, carried out before anything but a sweep reads messages
   hipError_t settle_restart(hipStream_t s) { return hzero ? restart(s) : hipSuccess; }
 
@@ -256,6 +264,13 @@ struct RbGridEngine : GridEngine {
 
   int64_t means_slots() const override { return 2 * (int64_t)Nc; }
   int sweep_launches() const override { return 2; }
+
+  WorkRhs work_rhs() const override {
+    WorkRhs w = GridEngine::work_rhs();
+    w.hx = hx;
+    w.nc = Nc;
+    return w;
+  }
   int64_t rb_slots() const { return 12 * (int64_t)Nc; }
 
   RbArgs rargs(int mode, int colour, const Ctl *c) const {
@@ -466,10 +481,11 @@ struct CoarseHierarchy {
   struct Level {
     gabp_plan *plan = nullptr;  // levels >= 1 (level 0 is the caller's plan)
     Engine *eng = nullptr;
+    GridEngine *ge = nullptr;   // the same engine as a grid plan's
     GridGeom g{};
     double *dg = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;  // levels >= 1
     double *v = nullptr, *d = nullptr;  // right-hand side, correction
-    double *e = nullptr;  // levels >= 1: the coarse correction summed over the cycles
+    double *e = nullptr;  // levels >= 1: the first cycle's correction (a tail level: the tail's sum)
     double *Pt = nullptr; // tail levels: precision messages kept between tail launches
     double *inv = nullptr;  // the coarsest level (below the finest): inverse per grid
     GridCoef<double> k{};   // the level's FP64 operator
@@ -571,6 +587,7 @@ struct CoarseHierarchy {
     tail = (te && std::strcmp(te, "0") == 0) ? 0 : tail_start(shapes);
     Level L0;
     L0.eng = e0;
+    L0.ge = e0;
     L0.g = e0->g;
     L0.k = e0->k64;
     L0.varc = e0->varc;
@@ -620,6 +637,8 @@ struct CoarseHierarchy {
         const int rc = gabp_plan_create_grid(&Ag, &o, &lv.back().plan, s);
         if (rc) return rc;
         lv.back().eng = lv.back().plan->eng;
+        lv.back().ge = dynamic_cast<GridEngine *>(lv.back().eng);
+        if (!lv.back().ge) return GABP_ERR_UNSUPPORTED;
       }
       k = GridCoef<double>{C.dg, C.cx, C.cy, C.cz, 0.0, 0.0};
       varc = true;
@@ -628,10 +647,13 @@ struct CoarseHierarchy {
     return GABP_OK;
   }
 
-  // d_l (set: =, else +=) the means of `sweeps` GaBP sweeps on right-hand
-  // side v (NULL: the engine already holds it), from zero information
-  // messages (zeroed by the first sweep itself).  On level 0 the solve's FP64
-  // residual has just written v into the engine's right-hand side as well.
+  // d_l (set: =, else +=) the means of `sweeps` GaBP sweeps on the level's
+  // right-hand side, from zero information messages (zeroed by the first
+  // sweep itself).  The kernel that produced the FP64 right-hand side v has
+  // also written it into the engine's working right-hand side: the solve's
+  // residual on level 0, the level above's restriction or copy-residual
+  // below; v is needed only by a level's first smoothing in a solve, which
+  // resets the engine from it.
   int smooth(int l, const double *v, int sweeps, bool set, hipStream_t s) {
     Level &L = lv[l];
     if (v && L.fresh) {
@@ -639,7 +661,6 @@ struct CoarseHierarchy {
       L.fresh = false;
       L.swept = 0;
     } else {
-      if (v && l > 0) TRY_HIP(L.eng->residual(v, nullptr, nullptr, s));
       TRY_HIP(L.eng->restart_lazy(s));  // zero informations (after a freeze: the settled ones)
     }
     if (freeze && !L.eng->frozen && L.swept >= kCoarseFreezeAfter) {
@@ -667,8 +688,9 @@ struct CoarseHierarchy {
     int rc = smooth(l, L.v, kCoarsePre, true, s);
     if (rc) return rc;
     Level &C = lv[l + 1];
+    const WorkRhs cw = C.ge ? C.ge->work_rhs() : WorkRhs{};
     // the next level's right-hand side P^T (v - A d)
-    TRY_HIP(launch_coarse_residual_restrict(L.g, L.k, L.varc, C.g, L.v, L.d, C.v, s));
+    TRY_HIP(launch_coarse_residual_restrict(L.g, L.k, L.varc, C.g, L.v, L.d, C.v, cw, s));
     // the coarse system: kCoarseGamma cycles of the next level, each on the
     // residual the previous ones left; their corrections summed in C.e
     if (tail > 0 && l + 1 == tail) {
@@ -677,15 +699,16 @@ struct CoarseHierarchy {
       a.fresh = tail_fresh ? 1 : 0;
       TRY_HIP(launch_coarse_tail(a, s));
       tail_fresh = false;
+      TRY_HIP(launch_coarse_prolong(L.g, C.g, C.e, nullptr, kCoarseScale, L.d, s));
     } else {
       static_assert(kCoarseGamma == 2, "the second cycle's right-hand side below assumes two");
       if ((rc = cycle(l + 1, s))) return rc;
       // e = d, and the second cycle on what the first left: v_c = rc - A_c e
-      TRY_HIP(launch_coarse_copy_residual(C.g, C.k, C.varc, C.d, C.e, C.v, s));
+      TRY_HIP(launch_coarse_copy_residual(C.g, C.k, C.varc, C.d, C.e, C.v, cw, s));
       if ((rc = cycle(l + 1, s))) return rc;
-      TRY_HIP(launch_axpy(C.g.N, C.d, C.e, s));
+      // the two cycles' corrections summed (e + d) inside the prolongation
+      TRY_HIP(launch_coarse_prolong(L.g, C.g, C.e, C.d, kCoarseScale, L.d, s));
     }
-    TRY_HIP(launch_coarse_prolong(L.g, C.g, C.e, kCoarseScale, L.d, s));
     if (kCoarsePost > 0) {
       TRY_HIP(L.eng->residual(L.v, L.d, nullptr, s));  // the engine's right-hand side only
       if ((rc = smooth(l, nullptr, kCoarsePost, false, s))) return rc;

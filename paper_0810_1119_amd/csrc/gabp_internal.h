@@ -629,16 +629,28 @@ hipError_t launch_coarse_coef(const GridGeom &f, const GridCoef<double> &k, bool
                               hipStream_t s);
 hipError_t launch_coarse_restrict(const GridGeom &f, const GridGeom &c, const double *r, double *rc,
                                   hipStream_t s);
+// d += scale * P (dc + dc2) (dc2 NULL: d += scale * P dc)
 hipError_t launch_coarse_prolong(const GridGeom &f, const GridGeom &c, const double *dc,
-                                 double scale, double *d, hipStream_t s);
+                                 const double *dc2, double scale, double *d, hipStream_t s);
 hipError_t launch_axpy(int n, const double *d, double *x, hipStream_t s);  // x += d
-// rc = P^T (v - A d) in one pass (A: the fine level's FP64 coefficients)
+// A grid plan's working right-hand side, which a kernel producing the level's
+// FP64 right-hand side may write as well: natural order (hx == 0) or the
+// red-black colour-major order (hx slots per row and colour, nc slots per
+// colour); p == NULL: none
+struct WorkRhs {
+  void *p = nullptr;
+  bool fp32 = true;
+  int hx = 0, nc = 0;
+};
+// rc = P^T (v - A d) in one pass (A: the fine level's FP64 coefficients);
+// w: the coarse level's working right-hand side, set to rc as well
 hipError_t launch_coarse_residual_restrict(const GridGeom &f, const GridCoef<double> &k, bool varc,
                                            const GridGeom &c, const double *v, const double *d,
-                                           double *rc, hipStream_t s);
-// e = d, v = v - A d in one pass
+                                           double *rc, const WorkRhs &w, hipStream_t s);
+// e = d, v = v - A d in one pass; w set to the new v as well
 hipError_t launch_coarse_copy_residual(const GridGeom &g, const GridCoef<double> &k, bool varc,
-                                       const double *d, double *e, double *v, hipStream_t s);
+                                       const double *d, double *e, double *v, const WorkRhs &w,
+                                       hipStream_t s);
 
 // The coarsest levels of a hierarchy in one launch (one workgroup of
 // kTailThreads per grid of the stack, every vector and message of those

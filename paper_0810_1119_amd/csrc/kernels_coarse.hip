@@ -84,9 +84,11 @@ __global__ void k_coarse_restrict(GridGeom f, GridGeom c, const double *__restri
   rc[I] = s;
 }
 
-// d[i] += scale * dc[block of i]
+// d[i] += scale * (dc + dc2)[block of i] (the sum formed as e = e + d
+// would form it)
 __global__ void k_coarse_prolong(GridGeom f, GridGeom c, const double *__restrict__ dc,
-                                 double scale, double *__restrict__ d) {
+                                 const double *__restrict__ dc2, double scale,
+                                 double *__restrict__ d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= f.N) return;
   const int nc = c.nx * c.ny * c.nz;
@@ -94,7 +96,24 @@ __global__ void k_coarse_prolong(GridGeom f, GridGeom c, const double *__restric
   grid_coords(f, i, x, y, z, t);
   // an axis of extent 1 is not halved
   const int hx = f.nx > 1, hy = f.ny > 1, hz = f.nz > 1;
-  d[i] += scale * dc[t * nc + (x >> hx) + c.nx * ((y >> hy) + c.ny * (z >> hz))];
+  const int I = t * nc + (x >> hx) + c.nx * ((y >> hy) + c.ny * (z >> hz));
+  double e = dc[I];
+  if (dc2) e += dc2[I];
+  d[i] += scale * e;
+}
+
+// the working right-hand side of cell i (WorkRhs)
+__device__ __forceinline__ void put_work_rhs(const GridGeom &g, const WorkRhs &w, int i,
+                                             double r) {
+  if (!w.p) return;
+  int at = i;
+  if (w.hx > 0) {
+    int c, slot;
+    rb_place(g, w.hx, i, c, slot);
+    at = c * w.nc + slot;
+  }
+  if (w.fp32) ((float *)w.p)[at] = (float)r;
+  else ((double *)w.p)[at] = r;
 }
 
 // (A x)_i of a 5/7-point stack in FP64, terms in the order of the grid
@@ -144,7 +163,7 @@ __device__ __forceinline__ double stencil_ax(const GridGeom &g, const GridCoef<d
 template <bool VARC>
 __global__ __launch_bounds__(kBlock) void k_coarse_residual_restrict(
     GridGeom f, GridCoef<double> k, GridGeom c, const double *__restrict__ v,
-    const double *__restrict__ d, double *__restrict__ rc) {
+    const double *__restrict__ d, double *__restrict__ rc, WorkRhs w) {
   const int64_t t8 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int I = (int)(t8 >> 3), kid = threadIdx.x & 7;
   double r = 0.0;
@@ -164,19 +183,23 @@ __global__ __launch_bounds__(kBlock) void k_coarse_residual_restrict(
   r += __shfl_xor(r, 1, 8);
   r += __shfl_xor(r, 2, 8);
   r += __shfl_xor(r, 4, 8);
-  if (I < c.N && kid == 0) rc[I] = r;
+  if (I < c.N && kid == 0) {
+    rc[I] = r;
+    put_work_rhs(c, w, I, r);
+  }
 }
 
 // e = d and v = v - A d: the right-hand side of a level's next cycle
 template <bool VARC>
 __global__ void k_coarse_copy_residual(GridGeom g, GridCoef<double> k, const double *__restrict__ d,
-                                       double *__restrict__ e, double *__restrict__ v) {
+                                       double *__restrict__ e, double *__restrict__ v, WorkRhs w) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.N) return;
   e[i] = d[i];
   double r = v[i];
   r -= stencil_ax<VARC>(g, k, d, i);
   v[i] = r;
+  put_work_rhs(g, w, i, r);
 }
 
 __global__ void k_axpy(int n, const double *__restrict__ d, double *__restrict__ x) {
@@ -673,38 +696,44 @@ hipError_t launch_coarse_restrict(const GridGeom &f, const GridGeom &c, const do
 }
 
 hipError_t launch_coarse_prolong(const GridGeom &f, const GridGeom &c, const double *dc,
-                                 double scale, double *d, hipStream_t s) {
+                                 const double *dc2, double scale, double *d, hipStream_t s) {
   if (f.N <= 0) return hipSuccess;
   if (!geom_ok(f) || !geom_ok(c)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_coarse_prolong, blocks_for(f.N), dim3(kBlock), 0, s, f, c, dc, scale, d);
+  hipLaunchKernelGGL(k_coarse_prolong, blocks_for(f.N), dim3(kBlock), 0, s, f, c, dc, dc2, scale,
+                     d);
   return hipGetLastError();
+}
+
+static bool work_rhs_ok(const GridGeom &g, const WorkRhs &w) {
+  return !w.p || w.hx == 0 || (w.hx == g.fh.d && w.nc == w.hx * (g.N / g.nx));
 }
 
 hipError_t launch_coarse_residual_restrict(const GridGeom &f, const GridCoef<double> &k, bool varc,
                                            const GridGeom &c, const double *v, const double *d,
-                                           double *rc, hipStream_t s) {
+                                           double *rc, const WorkRhs &w, hipStream_t s) {
   if (c.N <= 0) return hipSuccess;
-  if (!geom_ok(f) || !geom_ok(c)) return hipErrorInvalidValue;
+  if (!geom_ok(f) || !geom_ok(c) || !work_rhs_ok(c, w)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((8 * (int64_t)c.N + kBlock - 1) / kBlock));
   if (varc)
     hipLaunchKernelGGL(k_coarse_residual_restrict<true>, grid, dim3(kBlock), 0, s, f, k, c, v, d,
-                       rc);
+                       rc, w);
   else
     hipLaunchKernelGGL(k_coarse_residual_restrict<false>, grid, dim3(kBlock), 0, s, f, k, c, v, d,
-                       rc);
+                       rc, w);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_copy_residual(const GridGeom &g, const GridCoef<double> &k, bool varc,
-                                       const double *d, double *e, double *v, hipStream_t s) {
+                                       const double *d, double *e, double *v, const WorkRhs &w,
+                                       hipStream_t s) {
   if (g.N <= 0) return hipSuccess;
-  if (!geom_ok(g)) return hipErrorInvalidValue;
+  if (!geom_ok(g) || !work_rhs_ok(g, w)) return hipErrorInvalidValue;
   if (varc)
     hipLaunchKernelGGL(k_coarse_copy_residual<true>, blocks_for(g.N), dim3(kBlock), 0, s, g, k, d,
-                       e, v);
+                       e, v, w);
   else
     hipLaunchKernelGGL(k_coarse_copy_residual<false>, blocks_for(g.N), dim3(kBlock), 0, s, g, k, d,
-                       e, v);
+                       e, v, w);
   return hipGetLastError();
 }
 
