@@ -25,7 +25,16 @@ removes slowly.  Written plainly from the definitions below:
   e += cycle(l + 1, rc - A_c e) (gamma = 2: a W-cycle), d += scale * P e, and
   d += smooth(v - A d, nu_post);
 * the solve: x = 0, then x += cycle(0, b - A x) until every grid's
-  ||b_t - A_t x_t|| / ||b_t|| <= tol.
+  ||b_t - A_t x_t|| / ||b_t|| <= tol;
+* with accel=True (the default) each grid's corrections are combined by the
+  generalized conjugate residual method truncated to the previous direction
+  (GCR(1)): with c = cycle(0, r), w = A c and (pc, pw) the previous step's
+  direction and its image, c' = c - beta pc and w' = w - beta pw with
+  beta = (w, pw) / (pw, pw), so that w' is orthogonal to pw, then
+  x += alpha c' with alpha = (r, w') / (w', w'), the step that minimises
+  ||r - alpha w'||; inner products over the grid's own cells.  A direction
+  whose w' keeps less than 1e-10 of ||w||^2 after the orthogonalisation is
+  used as it came (beta = 0).
 """
 from __future__ import annotations
 
@@ -161,11 +170,37 @@ def cycle(H, l, v, nu_pre, nu_post, nu_coarse, scale, gamma=2):
     return d
 
 
+GCR_PARALLEL = 1e-10  # (w', w') <= this * (w, w): beta = 0
+
+
+def gcr_step(r, c, w, prev, n, batch):
+    """One GCR(1) step per grid (n cells each): returns (dx, (c', w')) for
+    x += dx, given the residual r, the correction c, w = A c and the previous
+    step's (c', w') (None on the first step)."""
+    dx, cn, wn = np.empty_like(c), np.empty_like(c), np.empty_like(w)
+    for t in range(batch):
+        sl = slice(t * n, (t + 1) * n)
+        ct, wt = c[sl], w[sl]
+        if prev is not None:
+            pc, pw = prev[0][sl], prev[1][sl]
+            pp = float(pw @ pw)
+            if pp > 0.0:
+                beta = float(wt @ pw) / pp
+                wo = wt - beta * pw
+                if float(wo @ wo) > GCR_PARALLEL * float(wt @ wt):
+                    ct, wt = ct - beta * pc, wo
+        ww = float(wt @ wt)
+        alpha = float(r[sl] @ wt) / ww if ww > 0.0 else 0.0
+        dx[sl], cn[sl], wn[sl] = alpha * ct, ct, wt
+    return dx, (cn, wn)
+
+
 def solve(nx, ny, nz, batch, diag, cx, cy, cz, b, tol=1e-8, nu_pre=3, nu_post=3, nu_coarse=24,
-          scale=1.8, max_cycles=100, colored=True, damping=0.0, gamma=2):
+          scale=1.8, max_cycles=100, colored=True, damping=0.0, gamma=2, accel=True):
     """Returns (x, cycles, worst per-grid relative residual, list of the x
     after each cycle).  colored=False smooths with synchronous rounds; damping
-    as in the rounds (section VI-D reading)."""
+    as in the rounds (section VI-D reading); accel: the GCR(1) combination of
+    the corrections (above)."""
     H = Hierarchy(nx, ny, nz, batch, diag, cx, cy, cz, colored, damping)
     A = H.levels[0]["A"]
     b = np.asarray(b, dtype=np.float64)
@@ -175,15 +210,21 @@ def solve(nx, ny, nz, batch, diag, cx, cy, cz, b, tol=1e-8, nu_pre=3, nu_post=3,
     x = np.zeros_like(b)
     trail = []
     worst = np.inf
+    prev = None
     for k in range(max_cycles + 1):
         r = b - A @ x
         worst = max(np.linalg.norm(r[t * n:(t + 1) * n]) / bn[t] for t in range(batch))
         if worst <= tol or k == max_cycles:
             return x, k, worst, trail
-        x = x + cycle(H, 0, r, nu_pre, nu_post, nu_coarse, scale, gamma)
+        c = cycle(H, 0, r, nu_pre, nu_post, nu_coarse, scale, gamma)
+        if accel:
+            dx, prev = gcr_step(r, c, A @ c, prev, n, batch)
+            x = x + dx
+        else:
+            x = x + c
         trail.append(x.copy())
     return x, max_cycles, worst, trail
 
 
 __all__ = ["grid_matrix", "aggregation", "coefficients", "coarse_dims", "checkerboard",
-           "Hierarchy", "smooth", "cycle", "solve", "residual"]
+           "Hierarchy", "smooth", "cycle", "gcr_step", "solve", "residual"]
