@@ -544,12 +544,20 @@ int gabp_plan_solve_warm(gabp_plan *plan, const gabp_model *model, const double 
  *        a plan whose own grids have at most 64 cells is corrected by the
  *        means of 24 sweeps instead);
  *   d += means of 3 GaBP sweeps on r - A d;
- * then x += d, until every grid of the stack meets tol (each grid's own
+ * then, on every grid t of the stack, with w = A d and (pc, pw) the previous
+ * correction's direction and its image (none on the first):
+ *   beta = (w, pw) / (pw, pw), d' = d - beta pc, w' = w - beta pw,
+ *   x += alpha d', alpha = (r, w') / (w', w')
+ * (inner products over the grid's cells; beta = 0 when w' keeps less than
+ * 1e-10 of (w, w)): the generalized conjugate residual step over the last two
+ * corrections, which minimises the grid's residual over both; repeated
+ * until every grid of the stack meets tol (each grid's own
  * ||b_t - A_t x_t|| / ||b_t||).  The sweeps use the plan's damping, except
  * that an undamped synchronous plan sweeps with damping 0.3 here: undamped
  * synchronous sweeps leave the error mode that alternates between the two
  * colours of a grid, and the cycle diverges.  The coarse levels are built on the first call
- * and kept with the plan (about 1/7 of the plan's memory).  Grid plans only
+ * and kept with the plan (about 1/7 of the plan's memory, plus three FP64
+ * vectors of the plan's size for the combination of the corrections).  Grid plans only
  * (GABP_ERR_UNSUPPORTED otherwise); st->restarts counts the corrections
  * (at most opts.max_restarts), st->sweeps the sweeps on the plan's own grid.
  * Arguments as for gabp_plan_solve. */

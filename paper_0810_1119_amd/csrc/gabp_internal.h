@@ -633,6 +633,17 @@ hipError_t launch_coarse_restrict(const GridGeom &f, const GridGeom &c, const do
 hipError_t launch_coarse_prolong(const GridGeom &f, const GridGeom &c, const double *dc,
                                  const double *dc2, double scale, double *d, hipStream_t s);
 hipError_t launch_axpy(int n, const double *d, double *x, hipStream_t s);  // x += d
+// One GCR(1) step per grid of a stack (nseg grids, segb blocks each) that
+// adds the correction c to x: w = A c (the grid's FP64 operator k), then
+// per grid beta = (w, pw) / (pw, pw) and alpha = (r, w') / (w', w') with
+// w' = w - beta pw, x += alpha (c - beta pc), and (pc, pw) = (c', w') for the
+// next step.  first: no previous step (pc, pw, pp not read).  part: nseg *
+// segb * 4 doubles; pp, ab: nseg entries kept between steps.
+constexpr double kGcrParallel = 1e-10;
+hipError_t launch_gcr_step(const GridGeom &g, const GridCoef<double> &k, bool varc, int nseg,
+                           int segb, const double *c, const double *r, double *w, double *pc,
+                           double *pw, double *part, double *pp, double2 *ab, bool first,
+                           double *x, hipStream_t s);
 // A grid plan's working right-hand side, which a kernel producing the level's
 // FP64 right-hand side may write as well: natural order (hx == 0) or the
 // red-black colour-major order (hx slots per row and colour, nc slots per

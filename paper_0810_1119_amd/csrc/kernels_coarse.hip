@@ -9,7 +9,7 @@
 // the diagonal of I collects the fine diagonals of its cells and twice every
 // coupling inside the block; the coupling of I with its +x neighbour collects
 // the fine +x couplings that cross the block's +x face.
-#include "gabp_internal.h"
+#include "device_common.h"
 
 namespace gabp {
 namespace {
@@ -200,6 +200,105 @@ __global__ void k_coarse_copy_residual(GridGeom g, GridCoef<double> k, const dou
   r -= stencil_ax<VARC>(g, k, d, i);
   v[i] = r;
   put_work_rhs(g, w, i, r);
+}
+
+// GCR(1) combination of the coarse-grid corrections, one step per grid of
+// the stack.  Partial sums per block over one grid's cells (the blocks of a
+// segment, as in the grid residual): (r, w), (w, w), (w, pw), (r, pw) with
+// w = A c written out; pw is the previous step's direction image (not read
+// on the first step).
+template <bool VARC>
+__global__ __launch_bounds__(kBlock) void k_gcr_dots(GridGeom g, GridCoef<double> k,
+                                                     const double *__restrict__ c,
+                                                     const double *__restrict__ r,
+                                                     const double *__restrict__ pw,
+                                                     double *__restrict__ w,
+                                                     double *__restrict__ part, int nseg,
+                                                     int first) {
+  const int segb = gridDim.x / nseg;
+  const int seg = blockIdx.x / segb;
+  const int len = g.N / nseg;
+  const int hi = (seg + 1) * len;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = seg * len + (blockIdx.x - seg * segb) * kBlock + threadIdx.x; i < hi;
+       i += segb * kBlock) {
+    int xx, y, zl, t;
+    grid_coords(g, i, xx, y, zl, t);
+    const double wi = stencil_ax<VARC>(g, k, c, i, xx, y, zl);
+    w[i] = wi;
+    const double ri = r[i];
+    s[0] += ri * wi;
+    s[1] += wi * wi;
+    if (!first) {
+      const double p = pw[i];
+      s[2] += wi * p;
+      s[3] += ri * p;
+    }
+  }
+  __shared__ double sh[4][kBlock / 64];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double v = wave_sum(s[q]);
+    if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x / 64] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double v = 0.0;
+    for (int wv = 0; wv < kBlock / 64; ++wv) v += sh[threadIdx.x][wv];
+    part[(size_t)blockIdx.x * 4 + threadIdx.x] = v;
+  }
+}
+
+// alpha and beta of each grid's step from its blocks' partial sums (in block
+// order): beta = (w, pw) / (pw, pw), so that w' = w - beta pw is orthogonal
+// to pw, and alpha = (r, w') / (w', w'); (w', w') and (r, w') expanded from
+// the sums.  A w' keeping less than kGcrParallel of (w, w) takes beta = 0.
+// pp: (w', w') of each grid's last step, kept for the next.
+__global__ void k_gcr_coef(const double *__restrict__ part, int nseg, int segb, int first,
+                           double *__restrict__ pp, double2 *__restrict__ ab) {
+  for (int t = threadIdx.x; t < nseg; t += blockDim.x) {
+    double rw = 0.0, ww = 0.0, wp = 0.0, rp = 0.0;
+    for (int b = 0; b < segb; ++b) {
+      const double *q = part + ((size_t)t * segb + b) * 4;
+      rw += q[0];
+      ww += q[1];
+      wp += q[2];
+      rp += q[3];
+    }
+    double beta = 0.0, w2 = ww, rw2 = rw;
+    const double ppt = first ? 0.0 : pp[t];
+    if (ppt > 0.0) {
+      const double bt = wp / ppt;
+      const double wo = ww - 2.0 * bt * wp + bt * bt * ppt;
+      if (wo > kGcrParallel * ww) {
+        beta = bt;
+        w2 = wo;
+        rw2 = rw - bt * rp;
+      }
+    }
+    pp[t] = w2;
+    ab[t] = make_double2(w2 > 0.0 ? rw2 / w2 : 0.0, beta);
+  }
+}
+
+// c' = c - beta pc, w' = w - beta pw, x += alpha c', then (pc, pw) = (c', w')
+__global__ void k_gcr_update(GridGeom g, const double *__restrict__ c,
+                             const double *__restrict__ w, const double2 *__restrict__ ab,
+                             int first, double *__restrict__ pc, double *__restrict__ pw,
+                             double *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  int xx, y, z, t;
+  grid_coords(g, i, xx, y, z, t);
+  const double2 q = ab[t];
+  double ci = c[i], wi = w[i];
+  if (!first && q.y != 0.0) {
+    ci -= q.y * pc[i];
+    wi -= q.y * pw[i];
+  }
+  x[i] += q.x * ci;
+  pc[i] = ci;
+  pw[i] = wi;
 }
 
 __global__ void k_axpy(int n, const double *__restrict__ d, double *__restrict__ x) {
@@ -734,6 +833,27 @@ hipError_t launch_coarse_copy_residual(const GridGeom &g, const GridCoef<double>
   else
     hipLaunchKernelGGL(k_coarse_copy_residual<false>, blocks_for(g.N), dim3(kBlock), 0, s, g, k, d,
                        e, v, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_gcr_step(const GridGeom &g, const GridCoef<double> &k, bool varc, int nseg,
+                           int segb, const double *c, const double *r, double *w, double *pc,
+                           double *pw, double *part, double *pp, double2 *ab, bool first,
+                           double *x, hipStream_t s) {
+  if (g.N <= 0) return hipSuccess;
+  if (!geom_ok(g) || nseg < 1 || segb < 1 || g.N % nseg != 0 || g.batch % nseg != 0)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(nseg * segb));
+  if (varc)
+    hipLaunchKernelGGL(k_gcr_dots<true>, grid, dim3(kBlock), 0, s, g, k, c, r, pw, w, part, nseg,
+                       first ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_gcr_dots<false>, grid, dim3(kBlock), 0, s, g, k, c, r, pw, w, part, nseg,
+                       first ? 1 : 0);
+  hipLaunchKernelGGL(k_gcr_coef, dim3(1), dim3(kBlock), 0, s, part, nseg, segb, first ? 1 : 0, pp,
+                     ab);
+  hipLaunchKernelGGL(k_gcr_update, blocks_for(g.N), dim3(kBlock), 0, s, g, c, w, ab,
+                     first ? 1 : 0, pc, pw, x);
   return hipGetLastError();
 }
 

@@ -289,3 +289,24 @@ def test_fp32_settled_levels_reach_tolerance(G, kind):
     print(f"{kind}: {st.restarts} corrections, plain {st2.sweeps} sweeps", flush=True)
     assert st.restarts <= 20
     np.testing.assert_allclose(xh, xp.cpu().numpy(), rtol=0, atol=1e-6 * np.abs(xh).max())
+
+
+def test_plain_sum_of_corrections_matches_oracle(G):
+    """GABP_COARSE_GCR=0 at plan time adds the corrections as they come: x
+    after each of the first cycles equals the oracle's unaccelerated trail."""
+    print("case: coarse-grid cycles FP64 without the GCR combination", flush=True)
+    nx, ny, nz, batch = 16, 16, 16, 2
+    A, arrs = _grid(G, nx, ny, nz, batch, 21)
+    b = W.normal_b(A.n, 22)
+    _, _, _, trail = OC.solve(nx, ny, nz, batch, *arrs, b, tol=0.0, max_cycles=3, accel=False)
+    for k in (1, 3):
+        o = G.gabp_default_opts(msg_fp32=0, tol=0.0, max_restarts=k, freeze=0,
+                                schedule=G.GABP_SCHEDULE_COLORED)
+        rc, plan = G.gabp_plan_create_grid(A, o)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        with env("GABP_COARSE_GCR", "0"):
+            rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
+        G.gabp_plan_destroy(plan)
+        assert rc == G.GABP_NOT_CONVERGED and st.restarts == k
+        xh = x.cpu().numpy()
+        assert np.linalg.norm(xh - trail[k - 1]) / np.linalg.norm(trail[k - 1]) < 1e-9, k
