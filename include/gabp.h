@@ -539,10 +539,13 @@ int gabp_plan_solve_warm(gabp_plan *plan, const gabp_model *model, const double 
  *        procedure (e = the first's result, then e += the second's on
  *        rc - P^T A P e: a W-cycle), P the 2 x 2 x 2 block indicator (an axis
  *        of extent 1 is not halved) and P^T A P the Galerkin product (again a
- *        5/7-point stencil), recursively down to grids of at most 64 cells,
- *        whose systems are solved exactly (their dense inverses, built once;
- *        a plan whose own grids have at most 64 cells is corrected by the
- *        means of 24 sweeps instead);
+ *        5/7-point stencil), recursively down to the first grid below the
+ *        plan's with at most 512 cells (at most 64 when the dense inverses of
+ *        512-cell grids would take more than 1 GiB), whose systems are
+ *        solved exactly (their dense inverses, built once; the level above
+ *        takes that exact solution once instead of two cycles; a plan whose
+ *        own grids have at most 64 cells is corrected by the means of 24
+ *        sweeps instead);
  *   d += means of 3 GaBP sweeps on r - A d;
  * then, on every grid t of the stack, with w = A d and (pc, pw) the previous
  * correction's direction and its image (none on the first):

@@ -10,7 +10,9 @@ removes slowly.  Written plainly from the definitions below:
   (x // 2, y // 2, z // 2) (a dimension of extent 1 is not halved); P is the
   indicator matrix of that map, and the coarse operator is the Galerkin
   product A_c = P^T A P (a sparse matrix product), again a 5/7-point stencil;
-  the coarse hierarchy stops at a grid of at most 64 cells;
+  the coarse hierarchy stops at the first level below the finest with at
+  most `coarsest` cells per grid (512 by default; a finest grid of at most
+  64 cells is its own coarsest level);
 * smoothing on a level with right-hand side v: coloured GaBP rounds (the
   serial scheme in checkerboard order, colour (x + y + z) & 1 with z counted
   over the whole stack, colour 0 first; or synchronous rounds) from zero
@@ -18,12 +20,12 @@ removes slowly.  Written plainly from the definitions below:
   precision messages of that level's previous smoothing kept (zero at the
   start of a solve), and the marginal means of the final messages;
 * a cycle on level l with right-hand side v: on the coarsest level below
-  the finest, the exact solution of its Galerkin system (a dense solve of at
-  most 64 unknowns per grid); on a finest level that is already the
-  coarsest, nu_coarse GaBP sweeps; otherwise d = smooth(v, nu_pre), and with
-  rc = P^T (v - A d), e = cycle(l + 1, rc) and then gamma - 1 more times
-  e += cycle(l + 1, rc - A_c e) (gamma = 2: a W-cycle), d += scale * P e, and
-  d += smooth(v - A d, nu_post);
+  the finest, the exact solution of its Galerkin system (a dense solve per
+  grid); on a finest level that is already the coarsest, nu_coarse GaBP
+  sweeps; otherwise d = smooth(v, nu_pre), and with rc = P^T (v - A d),
+  e = cycle(l + 1, rc) and then, unless the next level is the exactly solved
+  coarsest one, gamma - 1 more times e += cycle(l + 1, rc - A_c e) (gamma =
+  2: a W-cycle), d += scale * P e, and d += smooth(v - A d, nu_post);
 * the solve: x = 0, then x += cycle(0, b - A x) until every grid's
   ||b_t - A_t x_t|| / ||b_t|| <= tol;
 * with accel=True (the default) each grid's corrections are combined by the
@@ -44,7 +46,8 @@ import scipy.sparse.linalg as spla
 
 from . import Rounds, residual
 
-MAX_COARSE_CELLS = 64
+MAX_COARSE_CELLS = 512   # the coarsest level below the finest: at most this many cells per grid
+MAX_FINEST_ALONE = 64    # a finest grid of at most this many cells is its own coarsest level
 
 
 def grid_matrix(nx, ny, nz, batch, diag, cx, cy, cz):
@@ -119,7 +122,8 @@ class Hierarchy:
     """The levels of a stack: operator, its CSR for the oracle's rounds, the
     checkerboard colouring, the aggregation to the next level."""
 
-    def __init__(self, nx, ny, nz, batch, diag, cx, cy, cz, colored=True, damping=0.0):
+    def __init__(self, nx, ny, nz, batch, diag, cx, cy, cz, colored=True, damping=0.0,
+                 coarsest=MAX_COARSE_CELLS):
         self.levels = []
         self.damping = damping
         A = grid_matrix(nx, ny, nz, batch, diag, cx, cy, cz)
@@ -129,7 +133,8 @@ class Hierarchy:
                    "colors": checkerboard(*dims, batch) if colored else None, "P_msg": None,
                    "damping": damping}
             self.levels.append(lev)
-            if dims[0] * dims[1] * dims[2] <= MAX_COARSE_CELLS:
+            if dims[0] * dims[1] * dims[2] <= (MAX_FINEST_ALONE if len(self.levels) == 1
+                                               else coarsest):
                 break
             P = aggregation(*dims, batch)
             lev["P"] = P
@@ -161,7 +166,8 @@ def cycle(H, l, v, nu_pre, nu_post, nu_coarse, scale, gamma=2):
     # the coarse system P^T A P e = rc: gamma cycles of the next level, each on
     # the residual the previous ones left
     e = cycle(H, l + 1, rc, nu_pre, nu_post, nu_coarse, scale, gamma)
-    for _ in range(gamma - 1):
+    exact = "P" not in H.levels[l + 1]  # the coarsest: e is already the exact solution
+    for _ in range(0 if exact else gamma - 1):
         e = e + cycle(H, l + 1, rc - H.levels[l + 1]["A"] @ e, nu_pre, nu_post, nu_coarse, scale,
                       gamma)
     d = d + scale * (lev["P"] @ e)
@@ -196,12 +202,13 @@ def gcr_step(r, c, w, prev, n, batch):
 
 
 def solve(nx, ny, nz, batch, diag, cx, cy, cz, b, tol=1e-8, nu_pre=3, nu_post=3, nu_coarse=24,
-          scale=1.8, max_cycles=100, colored=True, damping=0.0, gamma=2, accel=True):
+          scale=1.8, max_cycles=100, colored=True, damping=0.0, gamma=2, accel=True,
+          coarsest=MAX_COARSE_CELLS):
     """Returns (x, cycles, worst per-grid relative residual, list of the x
     after each cycle).  colored=False smooths with synchronous rounds; damping
     as in the rounds (section VI-D reading); accel: the GCR(1) combination of
     the corrections (above)."""
-    H = Hierarchy(nx, ny, nz, batch, diag, cx, cy, cz, colored, damping)
+    H = Hierarchy(nx, ny, nz, batch, diag, cx, cy, cz, colored, damping, coarsest)
     A = H.levels[0]["A"]
     b = np.asarray(b, dtype=np.float64)
     n = nx * ny * nz

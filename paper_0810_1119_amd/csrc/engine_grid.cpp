@@ -448,7 +448,15 @@ struct RbGridEngine : GridEngine {
 // 64^3 variable-coefficient stacks and damped synchronous grids, one more
 // on a few, at a quarter more sweeps).
 constexpr int kCoarsePre = 3, kCoarsePost = 3, kCoarseSweeps = 24;
-constexpr int kCoarseMaxCells = kCoarsestCells;
+// The coarsest level is the first below the finest with at most
+// kCoarsestCellsMax cells per grid, solved exactly by its dense inverses
+// when those take at most kCoarseInverseBytes (one mat-vec per visit
+// replaces a launch of the LDS tail, which on a single grid takes one
+// workgroup about 50 us); otherwise the first with at most kCoarsestCells,
+// the LDS tail running the levels between.  A finest grid of at most
+// kCoarsestCells cells is its own coarsest level.  GABP_COARSE_EXACT=64 at
+// plan time takes the small coarsest level.
+constexpr int64_t kCoarseInverseBytes = (int64_t)1 << 30;
 // Synchronous sweeps on a grid (a bipartite graph) do not damp the error mode
 // that alternates between the two colours, so as a smoother they need
 // damping: an undamped synchronous plan smooths with this factor (the FP64
@@ -499,6 +507,7 @@ struct CoarseHierarchy {
   // instead of a few hundred launches of their own; they have no plans.
   // GABP_COARSE_TAIL=0 at plan time runs them as plans too.
   int tail = 0;
+  int max_cells = kCoarsestCellsMax;  // of the coarsest level below the finest
   bool tail_fresh = true;  // the tail's precision messages not yet set in this solve
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // Once every level has been set up in a solve and (with opts.freeze) has
@@ -604,11 +613,25 @@ struct CoarseHierarchy {
     if (e0->o.schedule == GABP_SCHEDULE_SYNC && damping == 0.0) damping = kCoarseSyncDamping;
     TRY_HIP(hipEventCreate(&ev0));
     TRY_HIP(hipEventCreate(&ev1));
-    std::vector<GridGeom> shapes{e0->g};
-    while ((int64_t)shapes.back().nx * shapes.back().ny * shapes.back().nz > kCoarseMaxCells)
-      shapes.push_back(coarse_geom(shapes.back()));
+    auto cells_of = [](const GridGeom &g) { return (int64_t)g.nx * g.ny * g.nz; };
+    auto shapes_for = [&](int mc) {
+      std::vector<GridGeom> sh{e0->g};
+      while (cells_of(sh.back()) > (sh.size() == 1 ? kCoarsestCells : mc))
+        sh.push_back(coarse_geom(sh.back()));
+      return sh;
+    };
+    const char *xe = std::getenv("GABP_COARSE_EXACT");
+    if (xe && std::strcmp(xe, "64") == 0) {
+      max_cells = kCoarsestCells;
+    } else {
+      const std::vector<GridGeom> big = shapes_for(kCoarsestCellsMax);
+      const int64_t nc = cells_of(big.back());
+      if (big.size() > 1 && (int64_t)big.back().batch * nc * nc * 8 > kCoarseInverseBytes)
+        max_cells = kCoarsestCells;
+    }
+    const std::vector<GridGeom> shapes = shapes_for(max_cells);
     const char *te = std::getenv("GABP_COARSE_TAIL");
-    tail = (te && std::strcmp(te, "0") == 0) ? 0 : tail_start(shapes);
+    tail = (te && std::strcmp(te, "0") == 0) || max_cells > kCoarsestCells ? 0 : tail_start(shapes);
     Level L0;
     L0.eng = e0;
     L0.ge = e0;
@@ -623,7 +646,7 @@ struct CoarseHierarchy {
       TRY_HIP(dalloc(&F.v, F.g.N, sizeof(double)));
       TRY_HIP(dalloc(&F.d, F.g.N, sizeof(double)));
       if (lv.size() > 1) TRY_HIP(dalloc(&F.e, F.g.N, sizeof(double)));
-      if ((int64_t)F.g.nx * F.g.ny * F.g.nz <= kCoarseMaxCells) break;
+      if (cells_of(F.g) <= (lv.size() == 1 ? kCoarsestCells : max_cells)) break;
       Level C;
       C.g = coarse_geom(F.g);
       const GridGeom fg = F.g;  // F may move when lv grows
@@ -641,18 +664,25 @@ struct CoarseHierarchy {
       C.varc = true;
       lv.push_back(C);  // owned from here on (freed by the destructor)
       const int64_t cells = (int64_t)C.g.nx * C.g.ny * C.g.nz;
-      if (cells <= kCoarseMaxCells) {
+      if (cells <= max_cells) {
         // the coarsest level: its inverse per grid, no messages
         Level &Z = lv.back();
         uint32_t *bad = nullptr;
+        double *work = nullptr;  // [M | I] per grid for the larger inverses
         TRY_HIP(dalloc(&Z.inv, (size_t)cells * cells * C.g.batch, sizeof(double)));
         TRY_HIP(dalloc(&bad, 1, sizeof(uint32_t)));
+        hipError_t e = cells > kCoarsestCells
+                           ? dalloc(&work, (size_t)(2 * cells + 1) * cells * C.g.batch,
+                                    sizeof(double))
+                           : hipSuccess;
         uint32_t hb = 0;
-        hipError_t e = launch_fill_zero4(bad, 1, s);
-        if (e == hipSuccess) e = launch_coarse_inverse(C.g, C.dg, C.cx, C.cy, C.cz, Z.inv, bad, s);
+        if (e == hipSuccess) e = launch_fill_zero4(bad, 1, s);
+        if (e == hipSuccess)
+          e = launch_coarse_inverse(C.g, C.dg, C.cx, C.cy, C.cz, Z.inv, work, bad, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         dfree(bad);
+        if (work) dfree(work);
         TRY_HIP(e);
         if (hb & FLAG_BREAKDOWN) return GABP_ERR_BREAKDOWN;  // a singular coarse system
       } else if (tail > 0 && (int)lv.size() - 1 >= tail) {
@@ -724,6 +754,10 @@ struct CoarseHierarchy {
       TRY_HIP(launch_coarse_tail(a, s));
       tail_fresh = false;
       TRY_HIP(launch_coarse_prolong(L.g, C.g, C.e, nullptr, kCoarseScale, L.d, s));
+    } else if (l + 2 == (int)lv.size()) {
+      // the next level is the coarsest: its exact solution, once
+      if ((rc = cycle(l + 1, s))) return rc;
+      TRY_HIP(launch_coarse_prolong(L.g, C.g, C.d, nullptr, kCoarseScale, L.d, s));
     } else {
       static_assert(kCoarseGamma == 2, "the second cycle's right-hand side below assumes two");
       if ((rc = cycle(l + 1, s))) return rc;

@@ -687,13 +687,17 @@ struct TailArgs {
 };
 size_t coarse_tail_lds(const TailArgs &a);  // bytes of LDS per workgroup
 hipError_t launch_coarse_tail(const TailArgs &a, hipStream_t s);
-// The coarsest level (at most kCoarsestCells cells per grid) is solved
+// The coarsest level (at most kCoarsestCellsMax cells per grid; at most
+// kCoarsestCells when the LDS tail runs the levels above it) is solved
 // exactly: its dense inverse per grid by Gauss-Jordan elimination with
-// partial pivoting (once per hierarchy; FLAG_BREAKDOWN on a zero pivot), and
+// partial pivoting (once per hierarchy; FLAG_BREAKDOWN on a zero pivot; in
+// LDS up to kCoarsestCells cells, else on [M | I] in `work`, 2 n^2 + n
+// doubles per grid, one pivot step per pair of launches), and
 // d = inverse * v per grid.
 constexpr int kCoarsestCells = 64;
+constexpr int kCoarsestCellsMax = kTailThreads;
 hipError_t launch_coarse_inverse(const GridGeom &c, const double *dg, const double *cx,
-                                 const double *cy, const double *cz, double *inv,
+                                 const double *cy, const double *cz, double *inv, double *work,
                                  uint32_t *flags, hipStream_t s);
 hipError_t launch_coarse_dense_solve(const GridGeom &c, const double *inv, const double *v,
                                      double *d, hipStream_t s);

@@ -604,7 +604,8 @@ __global__ __launch_bounds__(kTailThreads) void k_coarse_tail(TailArgs a) {
     const int k = (int)((cnt >> (4 * l)) & 15u);
     if (i < L.n) S_[L.E + i] = k == 1 ? S_[L.D + i] : S_[L.E + i] + S_[L.D + i];
     __syncthreads();
-    if (k < a.gamma) {
+    // the coarsest level's first cycle is already its exact solution
+    if (k < (l == a.nlev - 1 ? 1 : a.gamma)) {
       tail_residual(L, L.RC, L.E, L.V);  // the next cycle's right-hand side
       cnt += 1u << (4 * l);
       entering = true;
@@ -703,17 +704,113 @@ __global__ __launch_bounds__(kCoarsestCells) void k_coarse_inverse(
     inv[(size_t)t * n * n + k] = gj[(k / n) * w + n + k % n];
 }
 
-// d = inverse * v on every grid of the coarsest level
-__global__ __launch_bounds__(kCoarsestCells) void k_coarse_dense_solve(
+// The same elimination for coarsest levels of up to kCoarsestCellsMax cells,
+// on [M | I] in global memory (`work`, n x 2n doubles per grid, row-major),
+// one pivot step per pair of launches so that every grid's elimination is
+// spread over the whole device: k_gj_setup writes [M | I]; k_gj_pivot (one
+// workgroup per grid) finds the pivot row of column k (the largest |M[q][k]|
+// over q >= k, ties to the lower row, by a tree reduction), swaps it into
+// row k, divides it by the pivot and saves column k in F; k_gj_elim
+// subtracts F[q] times row k from every other row q (one workgroup per row,
+// the threads on consecutive columns).  Columns left of k are zero in the
+// pivot row and are skipped.  A zero pivot flags the breakdown and leaves the
+// grid's matrix unchanged from then on.
+__global__ void k_gj_setup(GridGeom c, const double *__restrict__ dg,
+                           const double *__restrict__ cx, const double *__restrict__ cy,
+                           const double *__restrict__ cz, double *__restrict__ work) {
+  const int n = c.nx * c.ny * c.nz, w = 2 * n;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)n * c.batch) return;
+  const int t = (int)(q / n), r = (int)(q - (int64_t)t * n);
+  double *row = work + q * w;
+  for (int j = 0; j < w; ++j) row[j] = 0.0;
+  const size_t g = (size_t)q;
+  const int x = r % c.nx, y = (r / c.nx) % c.ny, z = r / (c.nx * c.ny);
+  const int sy = c.nx, sz = c.nx * c.ny;
+  row[r] = dg[g];
+  if (x < c.nx - 1) row[r + 1] = cx[g];
+  if (x > 0) row[r - 1] = cx[g - 1];
+  if (y < c.ny - 1) row[r + sy] = cy[g];
+  if (y > 0) row[r - sy] = cy[g - sy];
+  if (z < c.nz - 1) row[r + sz] = cz[g];
+  if (z > 0) row[r - sz] = cz[g - sz];
+  row[n + r] = 1.0;
+}
+
+__global__ __launch_bounds__(kCoarsestCellsMax) void k_gj_pivot(int n, int k,
+                                                                 double *__restrict__ work,
+                                                                 double *__restrict__ F,
+                                                                 uint32_t *__restrict__ flags) {
+  __shared__ double best[kCoarsestCellsMax];
+  __shared__ int arg[kCoarsestCellsMax];
+  const int w = 2 * n, t = blockIdx.x, r = threadIdx.x;
+  double *M = work + (size_t)t * n * w;
+  double *Ft = F + (size_t)t * n;
+  best[r] = (r >= k && r < n) ? fabs(M[(size_t)r * w + k]) : -1.0;
+  arg[r] = r;
+  __syncthreads();
+  for (int h = kCoarsestCellsMax / 2; h > 0; h >>= 1) {
+    if (r < h && (best[r + h] > best[r] || (best[r + h] == best[r] && arg[r + h] < arg[r]))) {
+      best[r] = best[r + h];
+      arg[r] = arg[r + h];
+    }
+    __syncthreads();
+  }
+  const int p = arg[0];
+  const double pv = M[(size_t)p * w + k];
+  if (pv == 0.0) {  // singular (or an earlier step was): nothing changes any more
+    if (r < n) Ft[r] = 0.0;
+    if (r == 0) atomicOr(flags, (uint32_t)FLAG_BREAKDOWN);
+    return;
+  }
+  __syncthreads();
+  for (int j = k + r; j < w; j += blockDim.x) {
+    const double a = M[(size_t)k * w + j], b = M[(size_t)p * w + j];
+    M[(size_t)k * w + j] = b / pv;
+    if (p != k) M[(size_t)p * w + j] = a;
+  }
+  __syncthreads();
+  if (r < n) Ft[r] = r == k ? 0.0 : M[(size_t)r * w + k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gj_elim(int n, int k, double *__restrict__ work,
+                                                    const double *__restrict__ F) {
+  const int w = 2 * n;
+  const int64_t q = blockIdx.x;  // grid t, row r
+  const int64_t t = q / n;
+  const double f = F[q];
+  if (f == 0.0) return;  // uniform over the workgroup (the pivot row has f = 0)
+  double *row = work + q * w;
+  const double *prow = work + (t * n + k) * w;
+  for (int j = k + threadIdx.x; j < w; j += blockDim.x) row[j] -= f * prow[j];
+}
+
+__global__ void k_gj_store(int n, int batch, const double *__restrict__ work,
+                           double *__restrict__ inv) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (q >= nn * batch) return;
+  const int64_t t = q / nn, e = q - t * nn;
+  const int r = (int)(e / n), j = (int)(e - (int64_t)r * n);
+  inv[q] = work[(t * n + r) * (2 * n) + n + j];
+}
+
+// d = inverse * v on every grid of the coarsest level: one wave per row (the
+// lanes on consecutive columns, a fixed-order wave sum)
+__global__ __launch_bounds__(kBlock) void k_coarse_dense_solve(
     GridGeom c, const double *__restrict__ inv, const double *__restrict__ v,
     double *__restrict__ d) {
-  const int n = c.nx * c.ny * c.nz, t = blockIdx.x, r = threadIdx.x;
-  if (r >= n) return;
-  const double *row = inv + ((size_t)t * n + r) * n;
-  const double *vt = v + (size_t)t * n;
+  const int n = c.nx * c.ny * c.nz;
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (row >= (int64_t)n * c.batch) return;  // uniform over the wave
+  const int64_t t = row / n;
+  const double *a = inv + row * n;
+  const double *vt = v + t * n;
   double s = 0.0;
-  for (int j = 0; j < n; ++j) s += row[j] * vt[j];
-  d[(size_t)t * n + r] = s;
+  for (int j = lane; j < n; j += 64) s += a[j] * vt[j];
+  s = wave_sum(s);
+  if (lane == 0) d[row] = s;
 }
 
 }  // namespace
@@ -726,11 +823,27 @@ size_t coarse_tail_lds(const TailArgs &a) {
 }
 
 hipError_t launch_coarse_inverse(const GridGeom &c, const double *dg, const double *cx,
-                                 const double *cy, const double *cz, double *inv,
+                                 const double *cy, const double *cz, double *inv, double *work,
                                  uint32_t *flags, hipStream_t s) {
   const int n = c.nx * c.ny * c.nz;
   if (c.batch <= 0 || n <= 0) return hipSuccess;
-  if (n > kCoarsestCells) return hipErrorInvalidValue;
+  if (n > kCoarsestCellsMax) return hipErrorInvalidValue;
+  if (n > kCoarsestCells) {
+    if (!work) return hipErrorInvalidValue;
+    const int64_t rows = (int64_t)n * c.batch;
+    double *F = work + rows * 2 * n;  // column k of every grid (work holds 2 n^2 + n per grid)
+    hipLaunchKernelGGL(k_gj_setup, dim3((unsigned)((rows + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, c, dg, cx, cy, cz, work);
+    for (int k = 0; k < n; ++k) {
+      hipLaunchKernelGGL(k_gj_pivot, dim3((unsigned)c.batch), dim3(kCoarsestCellsMax), 0, s, n, k,
+                         work, F, flags);
+      hipLaunchKernelGGL(k_gj_elim, dim3((unsigned)rows), dim3(kBlock), 0, s, n, k, work, F);
+    }
+    const int64_t all = rows * n;
+    hipLaunchKernelGGL(k_gj_store, dim3((unsigned)((all + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, n, c.batch, work, inv);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)n * (2 * n + 1) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void *)k_coarse_inverse,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -744,9 +857,10 @@ hipError_t launch_coarse_dense_solve(const GridGeom &c, const double *inv, const
                                      double *d, hipStream_t s) {
   const int n = c.nx * c.ny * c.nz;
   if (c.batch <= 0 || n <= 0) return hipSuccess;
-  if (n > kCoarsestCells) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_coarse_dense_solve, dim3((unsigned)c.batch), dim3(kCoarsestCells), 0, s, c,
-                     inv, v, d);
+  if (n > kCoarsestCellsMax) return hipErrorInvalidValue;
+  const int64_t threads = (int64_t)n * c.batch * 64;
+  hipLaunchKernelGGL(k_coarse_dense_solve, dim3((unsigned)((threads + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, c, inv, v, d);
   return hipGetLastError();
 }
 

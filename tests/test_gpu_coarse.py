@@ -4,9 +4,12 @@
 FP64 messages: the x after each of the first cycles equals the oracle's
 (same levels, Galerkin operators, smoothing sweeps and scale) to 1e-9
 relative -- the levels' GaBP rounds agree to ~1e-11 per sweep as on the plain
-grid path, and a cycle adds a handful of FP64 sums.  Both ways of running
-the smallest levels are checked: inside one tail launch per visit (the
-default) and as plans of their own (GABP_COARSE_TAIL=0).  FP32 messages:
+grid path, and a cycle adds a handful of FP64 sums.  The three ways of running the
+smallest levels are checked: a coarsest level of up to 512 cells per grid
+solved by its dense inverse (the default), a coarsest level of up to 64
+cells with the levels between inside one LDS tail launch per visit
+(GABP_COARSE_EXACT=64), and those levels as plans of their own
+(GABP_COARSE_EXACT=64, GABP_COARSE_TAIL=0).  FP32 messages:
 every grid of the stack meets the tolerance (its residual recomputed by the
 oracle)."""
 import os
@@ -75,7 +78,21 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("tail", ["tail", "plans"])
+# how the small levels run: "exact" (the default: the coarsest level below
+# the finest has at most 512 cells per grid, its dense inverse), "tail" (the
+# coarsest at most 64 cells, the levels between in the LDS tail launch),
+# "plans" (at most 64 cells, every level above it a plan of its own)
+LEVEL_MODES = {"exact": (None, None, 512), "tail": ("64", None, 64), "plans": ("64", "0", 64)}
+
+
+@contextmanager
+def level_mode(mode):
+    exact, tail, _ = LEVEL_MODES[mode]
+    with env("GABP_COARSE_EXACT", exact), env("GABP_COARSE_TAIL", tail):
+        yield
+
+
+@pytest.mark.parametrize("tail", sorted(LEVEL_MODES))
 @pytest.mark.parametrize("case", sorted(CASES))
 @pytest.mark.parametrize("schedule", ["colored", "sync"])
 def test_cycles_match_oracle_fp64(G, case, schedule, tail):
@@ -87,7 +104,8 @@ def test_cycles_match_oracle_fp64(G, case, schedule, tail):
     # an undamped synchronous plan smooths with damping 0.3 (the alternating
     # mode of a bipartite graph is not damped otherwise)
     ref_x, ref_c, ref_w, trail = OC.solve(nx, ny, nz, batch, *arrs, b, tol=0.0, max_cycles=3,
-                                          colored=colored, damping=0.0 if colored else 0.3)
+                                          colored=colored, damping=0.0 if colored else 0.3,
+                                          coarsest=LEVEL_MODES[tail][2])
     for k in (1, 2, 3):
         o = G.gabp_default_opts(msg_fp32=0, tol=0.0, max_restarts=k, freeze=0,
                                 schedule=G.GABP_SCHEDULE_COLORED if colored
@@ -95,7 +113,7 @@ def test_cycles_match_oracle_fp64(G, case, schedule, tail):
         rc, plan = G.gabp_plan_create_grid(A, o)
         assert rc == G.GABP_OK
         x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-        with env("GABP_COARSE_TAIL", None if tail == "tail" else "0"):
+        with level_mode(tail):
             rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
         G.gabp_plan_destroy(plan)
         assert rc == G.GABP_NOT_CONVERGED and st.restarts == k, (rc, st.restarts)
@@ -187,7 +205,7 @@ def test_tail_equals_plans_fp64(G):
     for tail in ("tail", "plans"):
         rc, p = G.gabp_plan_create_grid(A, o)
         x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-        with env("GABP_COARSE_TAIL", None if tail == "tail" else "0"):
+        with level_mode(tail):
             rc, st = G.gabp_plan_solve_coarse(p, b, x)
         G.gabp_plan_destroy(p)
         assert rc == G.GABP_OK, (tail, G.status_name(rc))

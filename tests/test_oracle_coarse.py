@@ -75,14 +75,21 @@ def test_row_sums_and_adjointness():
     assert np.array_equal(np.asarray(P.sum(axis=1)).ravel(), np.ones(A.shape[0]))
 
 
-@pytest.mark.parametrize("dims,levels", [((64, 64, 64), 5), ((32, 32, 1), 3), ((5, 5, 5), 2),
-                                         ((4, 4, 4), 1)])
-def test_level_count(dims, levels):
+@pytest.mark.parametrize("dims,levels512,levels64",
+                         [((64, 64, 64), 4, 5), ((32, 32, 1), 2, 3), ((8, 8, 8), 2, 2),
+                          ((5, 5, 5), 2, 2), ((4, 4, 4), 1, 1)])
+def test_level_count(dims, levels512, levels64):
+    """Levels down to the first one below the finest with at most 512 (or 64)
+    cells per grid; a finest grid of at most 64 cells is its own coarsest."""
     nx, ny, nz = dims
-    got = [dims]
-    while got[-1][0] * got[-1][1] * got[-1][2] > OC.MAX_COARSE_CELLS:
-        got.append(OC.coarse_dims(*got[-1]))
-    assert len(got) == levels
+    n = nx * ny * nz
+    one = np.ones(n)
+    for coarsest, levels in ((512, levels512), (64, levels64)):
+        H = OC.Hierarchy(nx, ny, nz, 1, 6.5 * one, -one, -one, -one if nz > 1 else None,
+                         coarsest=coarsest)
+        assert len(H.levels) == levels, (dims, coarsest)
+        sizes = [int(np.prod(L["dims"])) for L in H.levels]
+        assert all(s > coarsest for s in sizes[1:-1]) and (len(sizes) == 1 or sizes[-1] <= coarsest)
 
 
 def test_solve_matches_direct_solution():
@@ -100,13 +107,15 @@ def test_solve_matches_direct_solution():
     assert all(r1 < 0.5 * r0 for r0, r1 in zip(res, res[1:]))
 
 
-def test_coarsest_correction_is_exact():
+@pytest.mark.parametrize("coarsest", [512, 64])
+def test_coarsest_correction_is_exact(coarsest):
     """Below the finest level the coarsest correction solves its Galerkin
     system exactly: A_c e = rc to rounding, on every grid of the stack."""
-    nx, ny, nz, batch = 9, 7, 6, 3
+    nx, ny, nz, batch = (16, 14, 12, 2) if coarsest == 512 else (9, 7, 6, 3)
     coef = _stack(nx, ny, nz, batch, 8)
-    H = OC.Hierarchy(nx, ny, nz, batch, coef["diag"], coef["cx"], coef["cy"], coef["cz"])
-    assert len(H.levels) == 2
+    H = OC.Hierarchy(nx, ny, nz, batch, coef["diag"], coef["cx"], coef["cy"], coef["cz"],
+                     coarsest=coarsest)
+    assert len(H.levels) == 2 and np.prod(H.levels[-1]["dims"]) > coarsest // 8
     last = H.levels[-1]
     rc = np.random.default_rng(3).standard_normal(last["A"].shape[0])
     e = OC.cycle(H, 1, rc, 4, 4, 24, 1.8)
