@@ -713,8 +713,8 @@ __global__ __launch_bounds__(kCoarsestCells) void k_coarse_inverse(
 // row k, divides it by the pivot and saves column k in F; k_gj_elim
 // subtracts F[q] times row k from every other row q (one workgroup per row,
 // the threads on consecutive columns).  Columns left of k are zero in the
-// pivot row and are skipped.  A zero pivot flags the breakdown and leaves the
-// grid's matrix unchanged from then on.
+// pivot row and are skipped.  A zero pivot flags the breakdown (the hierarchy
+// is then not built) and skips that step's swap and elimination.
 __global__ void k_gj_setup(GridGeom c, const double *__restrict__ dg,
                            const double *__restrict__ cx, const double *__restrict__ cy,
                            const double *__restrict__ cz, double *__restrict__ work) {
@@ -758,7 +758,7 @@ __global__ __launch_bounds__(kCoarsestCellsMax) void k_gj_pivot(int n, int k,
   }
   const int p = arg[0];
   const double pv = M[(size_t)p * w + k];
-  if (pv == 0.0) {  // singular (or an earlier step was): nothing changes any more
+  if (pv == 0.0) {  // singular: no swap, and F = 0 makes the elimination a no-op
     if (r < n) Ft[r] = 0.0;
     if (r == 0) atomicOr(flags, (uint32_t)FLAG_BREAKDOWN);
     return;
