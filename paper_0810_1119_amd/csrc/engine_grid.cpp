@@ -871,10 +871,15 @@ int coarse_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, ga
     return finish(GABP_OK);
   }
   int status = GABP_NOT_CONVERGED;
+  // With the GCR step the residual in lv[0].v (and the working right-hand
+  // side and the norms' partial sums) follows x through the step itself, as
+  // r - alpha A c'; b - A x is formed at the start and again, to confirm, when
+  // the recursive residual meets the tolerance or the budget ends the loop.
+  bool recur = false;
   TRY_HIP(hipEventRecord(H.ev0, s));
-  for (int cyc = 0;; ++cyc) {
+  for (int cyc = 0;;) {
     // r = b - A x (FP64) and the worst grid's relative residual
-    TRY_HIP(e0->residual(b, x, H.lv[0].v, s));
+    if (!recur) TRY_HIP(e0->residual(b, x, H.lv[0].v, s));
     HostReadout rr;
     if ((rc = e0->read_sum(s, &rr, 2, bn))) return finish(rc);
     const double rel_all = std::sqrt(rr.sum) / bn;
@@ -886,18 +891,26 @@ int coarse_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, ga
       status = GABP_ERR_DIVERGED;
       break;
     }
-    if (rel <= e0->o.tol) { status = GABP_OK; break; }
-    if (cyc >= e0->o.max_restarts || stats.sweeps >= e0->o.max_sweeps) break;
+    const bool done = rel <= e0->o.tol;
+    const bool spent = cyc >= e0->o.max_restarts || stats.sweeps >= e0->o.max_sweeps;
+    if ((done || spent) && recur) {
+      recur = false;  // confirm on b - A x
+      continue;
+    }
+    if (done) { status = GABP_OK; break; }
+    if (spent) break;
     if ((rc = H.correction(s))) return finish(rc);
     if (H.gcr) {
       // lv[0].v still holds this iteration's residual r
       TRY_HIP(launch_gcr_step(e0->g, e0->k64, e0->varc, H.gseg, H.gsegb, H.lv[0].d, H.lv[0].v,
-                              H.gw, H.gpc, H.gpw, H.gpart, H.gpp, H.gab, cyc == 0, x, s));
+                              H.gw, H.gpc, H.gpw, H.gpart, H.gpp, H.gab, cyc == 0, x,
+                              e0->work_rhs(), e0->sumpart, s));
+      recur = true;
     } else {
       TRY_HIP(launch_axpy(e0->n, H.lv[0].d, x, s));
     }
     stats.sweeps += kCoarsePre + kCoarsePost;
-    stats.restarts = cyc + 1;
+    stats.restarts = ++cyc;
   }
   TRY_HIP(hipEventRecord(H.ev1, s));
   if (marg_prec) TRY_HIP(e0->infer(nullptr, marg_prec, nullptr, s));

@@ -633,17 +633,6 @@ hipError_t launch_coarse_restrict(const GridGeom &f, const GridGeom &c, const do
 hipError_t launch_coarse_prolong(const GridGeom &f, const GridGeom &c, const double *dc,
                                  const double *dc2, double scale, double *d, hipStream_t s);
 hipError_t launch_axpy(int n, const double *d, double *x, hipStream_t s);  // x += d
-// One GCR(1) step per grid of a stack (nseg grids, segb blocks each) that
-// adds the correction c to x: w = A c (the grid's FP64 operator k), then
-// per grid beta = (w, pw) / (pw, pw) and alpha = (r, w') / (w', w') with
-// w' = w - beta pw, x += alpha (c - beta pc), and (pc, pw) = (c', w') for the
-// next step.  first: no previous step (pc, pw, pp not read).  part: nseg *
-// segb * 4 doubles; pp, ab: nseg entries kept between steps.
-constexpr double kGcrParallel = 1e-10;
-hipError_t launch_gcr_step(const GridGeom &g, const GridCoef<double> &k, bool varc, int nseg,
-                           int segb, const double *c, const double *r, double *w, double *pc,
-                           double *pw, double *part, double *pp, double2 *ab, bool first,
-                           double *x, hipStream_t s);
 // A grid plan's working right-hand side, which a kernel producing the level's
 // FP64 right-hand side may write as well: natural order (hx == 0) or the
 // red-black colour-major order (hx slots per row and colour, nc slots per
@@ -653,6 +642,20 @@ struct WorkRhs {
   bool fp32 = true;
   int hx = 0, nc = 0;
 };
+// One GCR(1) step per grid of a stack (nseg = g.batch grids, segb blocks each) that
+// adds the correction c to x: w = A c (the grid's FP64 operator k), then
+// per grid beta = (w, pw) / (pw, pw) and alpha = (r, w') / (w', w') with
+// w' = w - beta pw, x += alpha (c - beta pc), and (pc, pw) = (c', w') for the
+// next step.  first: no previous step (pc, pw, pp not read).  part: nseg *
+// segb * 4 doubles; pp, ab: nseg entries kept between steps.  The residual r
+// follows x: r -= alpha w' (w' = A c', so r stays b - A x up to rounding),
+// also written to wr, with one partial sum of r^2 per block into sumpart
+// (nseg * segb entries, the grid residual's layout).
+constexpr double kGcrParallel = 1e-10;
+hipError_t launch_gcr_step(const GridGeom &g, const GridCoef<double> &k, bool varc, int nseg,
+                           int segb, const double *c, double *r, double *w, double *pc,
+                           double *pw, double *part, double *pp, double2 *ab, bool first,
+                           double *x, const WorkRhs &wr, double *sumpart, hipStream_t s);
 // rc = P^T (v - A d) in one pass (A: the fine level's FP64 coefficients);
 // w: the coarse level's working right-hand side, set to rc as well
 hipError_t launch_coarse_residual_restrict(const GridGeom &f, const GridCoef<double> &k, bool varc,

@@ -281,24 +281,47 @@ __global__ void k_gcr_coef(const double *__restrict__ part, int nseg, int segb, 
   }
 }
 
-// c' = c - beta pc, w' = w - beta pw, x += alpha c', then (pc, pw) = (c', w')
-__global__ void k_gcr_update(GridGeom g, const double *__restrict__ c,
-                             const double *__restrict__ w, const double2 *__restrict__ ab,
-                             int first, double *__restrict__ pc, double *__restrict__ pw,
-                             double *__restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.N) return;
-  int xx, y, z, t;
-  grid_coords(g, i, xx, y, z, t);
-  const double2 q = ab[t];
-  double ci = c[i], wi = w[i];
-  if (!first && q.y != 0.0) {
-    ci -= q.y * pc[i];
-    wi -= q.y * pw[i];
+// c' = c - beta pc, w' = w - beta pw, x += alpha c', then (pc, pw) = (c', w');
+// the residual follows: r -= alpha w', into wr as well, and one partial sum
+// of r^2 per block (the blocks of a segment, as in k_gcr_dots)
+__global__ __launch_bounds__(kBlock) void k_gcr_update(GridGeom g, const double *__restrict__ c,
+                                                       const double *__restrict__ w,
+                                                       const double2 *__restrict__ ab, int first,
+                                                       double *__restrict__ pc,
+                                                       double *__restrict__ pw,
+                                                       double *__restrict__ x,
+                                                       double *__restrict__ r, WorkRhs wr,
+                                                       double *__restrict__ sumpart, int nseg) {
+  const int segb = gridDim.x / nseg;
+  const int seg = blockIdx.x / segb;
+  const int len = g.N / nseg;
+  const int hi = (seg + 1) * len;
+  double sq = 0.0;
+  for (int i = seg * len + (blockIdx.x - seg * segb) * kBlock + threadIdx.x; i < hi;
+       i += segb * kBlock) {
+    const double2 q = ab[seg];  // a segment is one grid of the stack
+    double ci = c[i], wi = w[i];
+    if (!first && q.y != 0.0) {
+      ci -= q.y * pc[i];
+      wi -= q.y * pw[i];
+    }
+    x[i] += q.x * ci;
+    pc[i] = ci;
+    pw[i] = wi;
+    const double ri = r[i] - q.x * wi;
+    r[i] = ri;
+    put_work_rhs(g, wr, i, ri);
+    sq += ri * ri;
   }
-  x[i] += q.x * ci;
-  pc[i] = ci;
-  pw[i] = wi;
+  __shared__ double sh[kBlock / 64];
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x / 64] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = sh[0];
+    for (int wv = 1; wv < kBlock / 64; ++wv) v += sh[wv];
+    sumpart[blockIdx.x] = v;
+  }
 }
 
 __global__ void k_axpy(int n, const double *__restrict__ d, double *__restrict__ x) {
@@ -951,11 +974,11 @@ hipError_t launch_coarse_copy_residual(const GridGeom &g, const GridCoef<double>
 }
 
 hipError_t launch_gcr_step(const GridGeom &g, const GridCoef<double> &k, bool varc, int nseg,
-                           int segb, const double *c, const double *r, double *w, double *pc,
+                           int segb, const double *c, double *r, double *w, double *pc,
                            double *pw, double *part, double *pp, double2 *ab, bool first,
-                           double *x, hipStream_t s) {
+                           double *x, const WorkRhs &wr, double *sumpart, hipStream_t s) {
   if (g.N <= 0) return hipSuccess;
-  if (!geom_ok(g) || nseg < 1 || segb < 1 || g.N % nseg != 0 || g.batch % nseg != 0)
+  if (!geom_ok(g) || nseg != g.batch || segb < 1 || !work_rhs_ok(g, wr) || !sumpart)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)(nseg * segb));
   if (varc)
@@ -966,8 +989,8 @@ hipError_t launch_gcr_step(const GridGeom &g, const GridCoef<double> &k, bool va
                        first ? 1 : 0);
   hipLaunchKernelGGL(k_gcr_coef, dim3(1), dim3(kBlock), 0, s, part, nseg, segb, first ? 1 : 0, pp,
                      ab);
-  hipLaunchKernelGGL(k_gcr_update, blocks_for(g.N), dim3(kBlock), 0, s, g, c, w, ab,
-                     first ? 1 : 0, pc, pw, x);
+  hipLaunchKernelGGL(k_gcr_update, grid, dim3(kBlock), 0, s, g, c, w, ab, first ? 1 : 0, pc, pw,
+                     x, r, wr, sumpart, nseg);
   return hipGetLastError();
 }
 
