@@ -249,36 +249,51 @@ __global__ __launch_bounds__(kBlock) void k_gcr_dots(GridGeom g, GridCoef<double
   }
 }
 
-// alpha and beta of each grid's step from its blocks' partial sums (in block
-// order): beta = (w, pw) / (pw, pw), so that w' = w - beta pw is orthogonal
-// to pw, and alpha = (r, w') / (w', w'); (w', w') and (r, w') expanded from
-// the sums.  A w' keeping less than kGcrParallel of (w, w) takes beta = 0.
-// pp: (w', w') of each grid's last step, kept for the next.
-__global__ void k_gcr_coef(const double *__restrict__ part, int nseg, int segb, int first,
-                           double *__restrict__ pp, double2 *__restrict__ ab) {
-  for (int t = threadIdx.x; t < nseg; t += blockDim.x) {
-    double rw = 0.0, ww = 0.0, wp = 0.0, rp = 0.0;
-    for (int b = 0; b < segb; ++b) {
-      const double *q = part + ((size_t)t * segb + b) * 4;
-      rw += q[0];
-      ww += q[1];
-      wp += q[2];
-      rp += q[3];
-    }
-    double beta = 0.0, w2 = ww, rw2 = rw;
-    const double ppt = first ? 0.0 : pp[t];
-    if (ppt > 0.0) {
-      const double bt = wp / ppt;
-      const double wo = ww - 2.0 * bt * wp + bt * bt * ppt;
-      if (wo > kGcrParallel * ww) {
-        beta = bt;
-        w2 = wo;
-        rw2 = rw - bt * rp;
-      }
-    }
-    pp[t] = w2;
-    ab[t] = make_double2(w2 > 0.0 ? rw2 / w2 : 0.0, beta);
+// alpha and beta of each grid's step from its blocks' partial sums, one
+// workgroup per grid (thread k adds the partials of blocks k, k + kBlock, ...,
+// then a fixed-order reduction: the same sums on every run):
+// beta = (w, pw) / (pw, pw), so that w' = w - beta pw is orthogonal to pw, and
+// alpha = (r, w') / (w', w'); (w', w') and (r, w') expanded from the sums.  A
+// w' keeping less than kGcrParallel of (w, w) takes beta = 0.  pp: (w', w')
+// of each grid's last step, kept for the next.
+__global__ __launch_bounds__(kBlock) void k_gcr_coef(const double *__restrict__ part, int segb,
+                                                     int first, double *__restrict__ pp,
+                                                     double2 *__restrict__ ab) {
+  const int t = blockIdx.x;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < segb; b += kBlock) {
+    const double *q = part + ((size_t)t * segb + b) * 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] += q[j];
   }
+  __shared__ double sh[4][kBlock / 64];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double u = wave_sum(v[j]);
+    if ((threadIdx.x & 63) == 0) sh[j][threadIdx.x / 64] = u;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double rw = 0.0, ww = 0.0, wp = 0.0, rp = 0.0;
+  for (int wv = 0; wv < kBlock / 64; ++wv) {
+    rw += sh[0][wv];
+    ww += sh[1][wv];
+    wp += sh[2][wv];
+    rp += sh[3][wv];
+  }
+  double beta = 0.0, w2 = ww, rw2 = rw;
+  const double ppt = first ? 0.0 : pp[t];
+  if (ppt > 0.0) {
+    const double bt = wp / ppt;
+    const double wo = ww - 2.0 * bt * wp + bt * bt * ppt;
+    if (wo > kGcrParallel * ww) {
+      beta = bt;
+      w2 = wo;
+      rw2 = rw - bt * rp;
+    }
+  }
+  pp[t] = w2;
+  ab[t] = make_double2(w2 > 0.0 ? rw2 / w2 : 0.0, beta);
 }
 
 // c' = c - beta pc, w' = w - beta pw, x += alpha c', then (pc, pw) = (c', w');
@@ -987,8 +1002,8 @@ hipError_t launch_gcr_step(const GridGeom &g, const GridCoef<double> &k, bool va
   else
     hipLaunchKernelGGL(k_gcr_dots<false>, grid, dim3(kBlock), 0, s, g, k, c, r, pw, w, part, nseg,
                        first ? 1 : 0);
-  hipLaunchKernelGGL(k_gcr_coef, dim3(1), dim3(kBlock), 0, s, part, nseg, segb, first ? 1 : 0, pp,
-                     ab);
+  hipLaunchKernelGGL(k_gcr_coef, dim3((unsigned)nseg), dim3(kBlock), 0, s, part, segb,
+                     first ? 1 : 0, pp, ab);
   hipLaunchKernelGGL(k_gcr_update, grid, dim3(kBlock), 0, s, g, c, w, ab, first ? 1 : 0, pc, pw,
                      x, r, wr, sumpart, nseg);
   return hipGetLastError();
