@@ -24,8 +24,10 @@ removes slowly.  Written plainly from the definitions below:
   grid); on a finest level that is already the coarsest, nu_coarse GaBP
   sweeps; otherwise d = smooth(v, nu_pre), and with rc = P^T (v - A d),
   e = cycle(l + 1, rc) and then, unless the next level is the exactly solved
-  coarsest one, gamma - 1 more times e += cycle(l + 1, rc - A_c e) (gamma =
-  2: a W-cycle), d += scale * P e, and d += smooth(v - A d, nu_post);
+  coarsest one or has at most `v_cells` cells per grid (4096 by default),
+  gamma - 1 more times e += cycle(l + 1, rc - A_c e) (gamma = 2: a W-cycle
+  into the larger levels, a V-cycle into the small ones), d += scale * P e,
+  and d += smooth(v - A d, nu_post);
 * the solve: x = 0, then x += cycle(0, b - A x) until every grid's
   ||b_t - A_t x_t|| / ||b_t|| <= tol;
 * with accel=True (the default) each grid's corrections are combined by the
@@ -48,6 +50,7 @@ from . import Rounds, residual
 
 MAX_COARSE_CELLS = 512   # the coarsest level below the finest: at most this many cells per grid
 MAX_FINEST_ALONE = 64    # a finest grid of at most this many cells is its own coarsest level
+V_CELLS = 4096           # a level of at most this many cells per grid is cycled once
 
 
 def grid_matrix(nx, ny, nz, batch, diag, cx, cy, cz):
@@ -154,7 +157,7 @@ def smooth(lev, v, sweeps):
     return R.marginals()[0]
 
 
-def cycle(H, l, v, nu_pre, nu_post, nu_coarse, scale, gamma=2):
+def cycle(H, l, v, nu_pre, nu_post, nu_coarse, scale, gamma=2, v_cells=V_CELLS):
     lev = H.levels[l]
     if "P" not in lev:
         if l == 0:  # the grid is its own coarsest level: GaBP sweeps alone
@@ -163,13 +166,15 @@ def cycle(H, l, v, nu_pre, nu_post, nu_coarse, scale, gamma=2):
     d = smooth(lev, v, nu_pre)
     r = v - lev["A"] @ d
     rc = lev["P"].T @ r
-    # the coarse system P^T A P e = rc: gamma cycles of the next level, each on
-    # the residual the previous ones left
-    e = cycle(H, l + 1, rc, nu_pre, nu_post, nu_coarse, scale, gamma)
-    exact = "P" not in H.levels[l + 1]  # the coarsest: e is already the exact solution
-    for _ in range(0 if exact else gamma - 1):
-        e = e + cycle(H, l + 1, rc - H.levels[l + 1]["A"] @ e, nu_pre, nu_post, nu_coarse, scale,
-                      gamma)
+    # the coarse system P^T A P e = rc: gamma cycles of the next level (one of
+    # a small level), each on the residual the previous ones left
+    e = cycle(H, l + 1, rc, nu_pre, nu_post, nu_coarse, scale, gamma, v_cells)
+    nxt = H.levels[l + 1]
+    exact = "P" not in nxt  # the coarsest: e is already the exact solution
+    once = exact or nxt["dims"][0] * nxt["dims"][1] * nxt["dims"][2] <= v_cells
+    for _ in range(0 if once else gamma - 1):
+        e = e + cycle(H, l + 1, rc - nxt["A"] @ e, nu_pre, nu_post, nu_coarse, scale, gamma,
+                      v_cells)
     d = d + scale * (lev["P"] @ e)
     if nu_post:
         d = d + smooth(lev, v - lev["A"] @ d, nu_post)
@@ -203,11 +208,11 @@ def gcr_step(r, c, w, prev, n, batch):
 
 def solve(nx, ny, nz, batch, diag, cx, cy, cz, b, tol=1e-8, nu_pre=3, nu_post=3, nu_coarse=24,
           scale=1.8, max_cycles=100, colored=True, damping=0.0, gamma=2, accel=True,
-          coarsest=MAX_COARSE_CELLS):
+          coarsest=MAX_COARSE_CELLS, v_cells=V_CELLS):
     """Returns (x, cycles, worst per-grid relative residual, list of the x
     after each cycle).  colored=False smooths with synchronous rounds; damping
     as in the rounds (section VI-D reading); accel: the GCR(1) combination of
-    the corrections (above)."""
+    the corrections (above); v_cells=0: a W-cycle into every level."""
     H = Hierarchy(nx, ny, nz, batch, diag, cx, cy, cz, colored, damping, coarsest)
     A = H.levels[0]["A"]
     b = np.asarray(b, dtype=np.float64)
@@ -223,7 +228,7 @@ def solve(nx, ny, nz, batch, diag, cx, cy, cz, b, tol=1e-8, nu_pre=3, nu_post=3,
         worst = max(np.linalg.norm(r[t * n:(t + 1) * n]) / bn[t] for t in range(batch))
         if worst <= tol or k == max_cycles:
             return x, k, worst, trail
-        c = cycle(H, 0, r, nu_pre, nu_post, nu_coarse, scale, gamma)
+        c = cycle(H, 0, r, nu_pre, nu_post, nu_coarse, scale, gamma, v_cells)
         if accel:
             dx, prev = gcr_step(r, c, A @ c, prev, n, batch)
             x = x + dx

@@ -205,3 +205,43 @@ def test_accelerated_solve_needs_no_more_corrections(varcoef):
     assert runs[True][1] <= runs[False][1]
     if not varcoef:
         assert runs[True][1] < runs[False][1]
+
+
+@pytest.mark.parametrize("v_cells, visits", [(4096, {32768: 1, 4096: 1, 512: 1}),
+                                             (512, {32768: 1, 4096: 2, 512: 2}),
+                                             (0, {32768: 1, 4096: 2, 512: 4})])
+def test_small_levels_are_cycled_once(monkeypatch, v_cells, visits):
+    """The visits of each level in one cycle of a 32^3 grid (levels 32^3,
+    16^3, 8^3 and an exact 4^3): a level of at most v_cells cells per grid is
+    cycled once by the level above, a larger one twice; each visit smooths
+    twice (before and after the coarse prediction)."""
+    n = 32
+    coef = _stack(n, n, n, 1, 12)
+    H = OC.Hierarchy(n, n, n, 1, coef["diag"], coef["cx"], coef["cy"], coef["cz"], coarsest=64)
+    assert [int(np.prod(L["dims"])) for L in H.levels] == [32768, 4096, 512, 64]
+    calls = {}
+    smooth = OC.smooth
+
+    def counting(lev, v, sweeps):
+        k = int(np.prod(lev["dims"]))
+        calls[k] = calls.get(k, 0) + 1
+        return smooth(lev, v, sweeps)
+
+    monkeypatch.setattr(OC, "smooth", counting)
+    r = W.normal_b(n ** 3, 13)
+    OC.cycle(H, 0, r, 3, 3, 24, 1.8, 2, v_cells)
+    assert calls == {k: 2 * v for k, v in visits.items()}
+
+
+def test_v_cycle_into_small_levels_keeps_the_corrections():
+    """On a 32^3 variable-coefficient grid (levels down to an exact 4^3) the
+    V-cycle into the levels of at most 4096 cells needs no more corrections
+    to 1e-8 than W-cycles into every level, within one."""
+    n = 32
+    coef = _stack(n, n, n, 1, 14)
+    b = W.normal_b(n ** 3, 15)
+    args = (n, n, n, 1, coef["diag"], coef["cx"], coef["cy"], coef["cz"], b)
+    _, cv, wv, _ = OC.solve(*args, tol=1e-8, coarsest=64)
+    _, cw, ww, _ = OC.solve(*args, tol=1e-8, coarsest=64, v_cells=0)
+    assert wv <= 1e-8 and ww <= 1e-8
+    assert cv <= cw + 1, (cv, cw)
