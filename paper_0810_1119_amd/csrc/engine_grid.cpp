@@ -457,6 +457,13 @@ constexpr int kCoarsePre = 3, kCoarsePost = 3, kCoarseSweeps = 24;
 // kCoarsestCells cells is its own coarsest level.  GABP_COARSE_EXACT=64 at
 // plan time takes the small coarsest level.
 constexpr int64_t kCoarseInverseBytes = (int64_t)1 << 30;
+// A level whose grids have at most kCoarseVCells cells is cycled once by the
+// level above (a V-cycle into it), a larger one twice (a W-cycle): the small
+// levels are a handful of short launches per visit, and in the FP64 oracle
+// their second visits saved no correction (64^3 variable-coefficient grids
+// 6, 256^3 damped Poisson 8, with or without them; 128^3 damped Poisson 9
+// instead of 8).  GABP_COARSE_WCYCLE=1 at plan time cycles every level twice.
+constexpr int64_t kCoarseVCells = 4096;
 // Synchronous sweeps on a grid (a bipartite graph) do not damp the error mode
 // that alternates between the two colours, so as a smoother they need
 // damping: an undamped synchronous plan smooths with this factor (the FP64
@@ -508,6 +515,7 @@ struct CoarseHierarchy {
   // GABP_COARSE_TAIL=0 at plan time runs them as plans too.
   int tail = 0;
   int max_cells = kCoarsestCellsMax;  // of the coarsest level below the finest
+  int64_t vcells = kCoarseVCells;     // levels of at most this many cells per grid: one visit
   bool tail_fresh = true;  // the tail's precision messages not yet set in this solve
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // Once every level has been set up in a solve and (with opts.freeze) has
@@ -569,7 +577,8 @@ struct CoarseHierarchy {
     a.colored = colored ? 1 : 0;
     a.pre = kCoarsePre;
     a.post = kCoarsePost;
-    a.gamma = kCoarseGamma;
+    // every tail level has at most kTailThreads cells per grid
+    a.gamma = vcells >= kTailThreads ? 1 : kCoarseGamma;
     return a;
   }
 
@@ -600,6 +609,8 @@ struct CoarseHierarchy {
     colored = e0->o.schedule == GABP_SCHEDULE_COLORED;
     if (const char *g = std::getenv("GABP_COARSE_GRAPH")) use_graph = std::strcmp(g, "0") != 0;
     if (const char *g = std::getenv("GABP_COARSE_GCR")) gcr = std::strcmp(g, "0") != 0;
+    if (const char *g = std::getenv("GABP_COARSE_WCYCLE"); g && std::strcmp(g, "1") == 0)
+      vcells = 0;
     if (gcr) {
       gseg = e0->nseg > 1 ? e0->nseg : 1;
       gsegb = e0->nseg > 1 ? e0->segb : std::max(e0->nsum, 1);
@@ -745,8 +756,9 @@ struct CoarseHierarchy {
     const WorkRhs cw = C.ge ? C.ge->work_rhs() : WorkRhs{};
     // the next level's right-hand side P^T (v - A d)
     TRY_HIP(launch_coarse_residual_restrict(L.g, L.k, L.varc, C.g, L.v, L.d, C.v, cw, s));
-    // the coarse system: kCoarseGamma cycles of the next level, each on the
-    // residual the previous ones left; their corrections summed in C.e
+    // the coarse system: kCoarseGamma cycles of the next level (one of a
+    // small level), each on the residual the previous ones left; two
+    // cycles' corrections summed in C.e
     if (tail > 0 && l + 1 == tail) {
       TailArgs a = tail_args(C);
       a.sticky = lv[0].eng->sticky;
@@ -754,8 +766,8 @@ struct CoarseHierarchy {
       TRY_HIP(launch_coarse_tail(a, s));
       tail_fresh = false;
       TRY_HIP(launch_coarse_prolong(L.g, C.g, C.e, nullptr, kCoarseScale, L.d, s));
-    } else if (l + 2 == (int)lv.size()) {
-      // the next level is the coarsest: its exact solution, once
+    } else if (l + 2 == (int)lv.size() || (int64_t)C.g.nx * C.g.ny * C.g.nz <= vcells) {
+      // one cycle: the next level is the coarsest (its exact solution) or small
       if ((rc = cycle(l + 1, s))) return rc;
       TRY_HIP(launch_coarse_prolong(L.g, C.g, C.d, nullptr, kCoarseScale, L.d, s));
     } else {

@@ -81,15 +81,26 @@ CASES = {
 # how the small levels run: "exact" (the default: the coarsest level below
 # the finest has at most 512 cells per grid, its dense inverse), "tail" (the
 # coarsest at most 64 cells, the levels between in the LDS tail launch),
-# "plans" (at most 64 cells, every level above it a plan of its own)
-LEVEL_MODES = {"exact": (None, None, 512), "tail": ("64", None, 64), "plans": ("64", "0", 64)}
+# "plans" (at most 64 cells, every level above it a plan of its own); "_w":
+# W-cycles into every level (GABP_COARSE_WCYCLE=1; the oracle's v_cells=0)
+# instead of one cycle of a level of at most 4096 cells per grid
+LEVEL_MODES = {"exact": (None, None, 512, None), "tail": ("64", None, 64, None),
+               "plans": ("64", "0", 64, None), "tail_w": ("64", None, 64, "1"),
+               "plans_w": ("64", "0", 64, "1")}
 
 
 @contextmanager
 def level_mode(mode):
-    exact, tail, _ = LEVEL_MODES[mode]
-    with env("GABP_COARSE_EXACT", exact), env("GABP_COARSE_TAIL", tail):
+    exact, tail, _, wcycle = LEVEL_MODES[mode]
+    with env("GABP_COARSE_EXACT", exact), env("GABP_COARSE_TAIL", tail), \
+            env("GABP_COARSE_WCYCLE", wcycle):
         yield
+
+
+def oracle_mode(mode):
+    """OC.solve keywords of a level mode"""
+    _, _, coarsest, wcycle = LEVEL_MODES[mode]
+    return dict(coarsest=coarsest, v_cells=0 if wcycle else OC.V_CELLS)
 
 
 @pytest.mark.parametrize("tail", sorted(LEVEL_MODES))
@@ -105,7 +116,7 @@ def test_cycles_match_oracle_fp64(G, case, schedule, tail):
     # mode of a bipartite graph is not damped otherwise)
     ref_x, ref_c, ref_w, trail = OC.solve(nx, ny, nz, batch, *arrs, b, tol=0.0, max_cycles=3,
                                           colored=colored, damping=0.0 if colored else 0.3,
-                                          coarsest=LEVEL_MODES[tail][2])
+                                          **oracle_mode(tail))
     for k in (1, 2, 3):
         o = G.gabp_default_opts(msg_fp32=0, tol=0.0, max_restarts=k, freeze=0,
                                 schedule=G.GABP_SCHEDULE_COLORED if colored
@@ -202,7 +213,7 @@ def test_tail_equals_plans_fp64(G):
     o = G.gabp_default_opts(msg_fp32=0, freeze=0, tol=1e-10,
                             schedule=G.GABP_SCHEDULE_COLORED)
     out = {}
-    for tail in ("tail", "plans"):
+    for tail in ("tail", "plans", "tail_w", "plans_w"):
         rc, p = G.gabp_plan_create_grid(A, o)
         x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
         with level_mode(tail):
@@ -211,9 +222,10 @@ def test_tail_equals_plans_fp64(G):
         assert rc == G.GABP_OK, (tail, G.status_name(rc))
         out[tail] = (x.cpu().numpy(), st)
         print(f"{tail}: {st.restarts} corrections, {st.seconds * 1e3:.1f} ms", flush=True)
-    assert out["tail"][1].restarts == out["plans"][1].restarts
-    xt, xp = out["tail"][0], out["plans"][0]
-    assert np.abs(xt - xp).max() <= 1e-9 * np.abs(xp).max()
+    for w in ("", "_w"):
+        assert out["tail" + w][1].restarts == out["plans" + w][1].restarts, w
+        xt, xp = out["tail" + w][0], out["plans" + w][0]
+        assert np.abs(xt - xp).max() <= 1e-9 * np.abs(xp).max(), w
 
 
 def test_graph_replays_equal_eager_corrections(G):
@@ -328,3 +340,39 @@ def test_plain_sum_of_corrections_matches_oracle(G):
         assert rc == G.GABP_NOT_CONVERGED and st.restarts == k
         xh = x.cpu().numpy()
         assert np.linalg.norm(xh - trail[k - 1]) / np.linalg.norm(trail[k - 1]) < 1e-9, k
+
+
+@pytest.mark.parametrize("budget", [0, 2, None])
+def test_reported_residual_is_that_of_x(G, budget):
+    """The GCR step carries the residual along with x (r - alpha A c'); the
+    residual a solve reports is still b - A x of the x it returns, the worst
+    grid's, whether it stops at the tolerance or at the correction budget."""
+    print(f"case: coarse-grid reported residual, budget {budget}, 3 grids of 24^3", flush=True)
+    nx = ny = nz = 24
+    batch = 3
+    A, arrs = _grid(G, nx, ny, nz, batch, 31)
+    b = W.normal_b(A.n, 32)
+    kw = dict(msg_fp32=0, tol=1e-10, schedule=G.GABP_SCHEDULE_COLORED)
+    if budget is not None:
+        kw["max_restarts"] = budget
+    rc, plan = G.gabp_plan_create_grid(A, G.gabp_default_opts(**kw))
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    rc, st = G.gabp_plan_solve_coarse(plan, dev(b), x)
+    G.gabp_plan_destroy(plan)
+    if budget is None:
+        assert rc == G.GABP_OK
+    else:
+        assert rc == G.GABP_NOT_CONVERGED and st.restarts == budget
+    n = nx * ny * nz
+    xh = x.cpu().numpy()
+    worst = 0.0
+    for t in range(batch):
+        sl = slice(t * n, (t + 1) * n)
+        _, rn = oracle.residual_grid(nx, ny, nz, 1, b[sl], xh[sl], diag=arrs[0][sl],
+                                     cx=arrs[1][sl], cy=arrs[2][sl], cz=arrs[3][sl])
+        worst = max(worst, rn / np.linalg.norm(b[sl]))
+    print(f"reported {st.rel_residual:.6e}, b - A x {worst:.6e}, {st.restarts} corrections",
+          flush=True)
+    assert st.rel_residual == pytest.approx(worst, rel=1e-9)
+    if budget is None:
+        assert worst <= 1e-10
