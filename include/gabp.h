@@ -537,7 +537,8 @@ int gabp_plan_solve_warm(gabp_plan *plan, const gabp_model *model, const double 
  *   d += 1.8 P e, where e solves the next coarser grid's system
  *        P^T A P e = rc, rc = P^T (r - A d), by two applications of the same
  *        procedure (e = the first's result, then e += the second's on
- *        rc - P^T A P e: a W-cycle), P the 2 x 2 x 2 block indicator (an axis
+ *        rc - P^T A P e: a W-cycle; one application when the coarser grids
+ *        have at most 4096 cells), P the 2 x 2 x 2 block indicator (an axis
  *        of extent 1 is not halved) and P^T A P the Galerkin product (again a
  *        5/7-point stencil), recursively down to the first grid below the
  *        plan's with at most 512 cells (at most 64 when the dense inverses of
