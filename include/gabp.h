@@ -110,7 +110,11 @@ typedef struct {
                           update the information h = P mu only; the FP64
                           refinement absorbs the last-ulp difference.  0: never */
   int32_t batch_waves; /* batched solves: wavefronts (64 lanes) per workgroup,
-                          4, 8 or 16; 0 = chosen by the plan's autotuner */
+                          4, 8 or 16; 0 = chosen by the plan's autotuner,
+                          whose choices persist in a text file:
+                          $GABP_TUNE_CACHE, else $XDG_CACHE_HOME or
+                          $HOME/.cache, /gabp-mi355x/tune.txt
+                          (GABP_TUNE_CACHE=off: this process only) */
   double freeze_tol;    /* the settled-precision threshold (see freeze); 0 = the
                           default, 1e-6 for FP32 messages and 1e-14 for FP64 */
   int32_t adapt_damping; /* batched solves, 1 (default): an instance whose means
@@ -564,6 +568,13 @@ int gabp_plan_solve_warm(gabp_plan *plan, const gabp_model *model, const double 
  * vectors of the plan's size for the combination of the corrections).  Grid plans only
  * (GABP_ERR_UNSUPPORTED otherwise); st->restarts counts the corrections
  * (at most opts.max_restarts), st->sweeps the sweeps on the plan's own grid.
+ * The dense inverses of the coarsest level take at most 1 GiB, and building
+ * those of more than 64 cells per grid holds about twice their size for the
+ * duration of the first call.  Environment, read when the levels are built:
+ * GABP_COARSE_EXACT=64 (coarsest level of at most 64 cells), GABP_COARSE_TAIL=0
+ * (with it, the small levels as plans instead of one launch per visit),
+ * GABP_COARSE_WCYCLE=1 (two cycles of every level), GABP_COARSE_GCR=0 (the
+ * corrections added as they come), GABP_COARSE_GRAPH=0 (no graph replay).
  * Arguments as for gabp_plan_solve. */
 int gabp_plan_solve_coarse(gabp_plan *plan, const double *b, double *x, double *marg_prec,
                            gabp_stats *st, hipStream_t stream);
