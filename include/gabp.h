@@ -282,7 +282,8 @@ int gabp_plan_solve(gabp_plan *plan, const double *b, double *x, double *marg_pr
  * get/set_messages: P and h = P * mu of every directed message i->j at the
  *            CSR slot of A_ij (device [nnz] each, FP64; diagonal slots read
  *            as 0 and are ignored on set).  Coloured CSR plans run on a
- *            renumbering of A and return GABP_ERR_UNSUPPORTED here.
+ *            renumbering of A: their messages cross through its slot map
+ *            (two FP64 buffers of nnz are held for the call).
  * A coloured CSR plan (gabp_plan_create with GABP_SCHEDULE_COLORED, pair
  * layout) colours the graph of A on the device (Jones-Plassmann rounds with
  * fixed pseudo-random priorities and first-fit colours, deterministic; at

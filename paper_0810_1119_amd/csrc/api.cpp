@@ -447,8 +447,9 @@ int gabp_plan_get_messages(gabp_plan *p, double *P, double *h, hipStream_t s) {
   GABP_PLAN_SCOPE(p);
   clear_stale_error();
   if (p && p->small) return small_messages(p->small, P, h, false, s);
-  if (p && (p->bat || p->perm)) return GABP_ERR_UNSUPPORTED;
+  if (p && p->bat) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
+  if (p->perm) return perm_messages(p->perm, p->eng, P, h, false, s);
   return p->eng->get_messages(P, h, s);
 }
 
@@ -457,8 +458,11 @@ int gabp_plan_set_messages(gabp_plan *p, const double *P, const double *h, hipSt
   clear_stale_error();
   if (p && p->small)
     return small_messages(p->small, const_cast<double *>(P), const_cast<double *>(h), true, s);
-  if (p && (p->bat || p->perm)) return GABP_ERR_UNSUPPORTED;
+  if (p && p->bat) return GABP_ERR_UNSUPPORTED;
   if (!p || !p->eng || p->eng->frozen) return GABP_ERR_ARG;
+  if (p->perm)
+    return perm_messages(p->perm, p->eng, const_cast<double *>(P), const_cast<double *>(h), true,
+                         s);
   return p->eng->set_messages(P, h, s);
 }
 

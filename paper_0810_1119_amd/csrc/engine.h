@@ -253,6 +253,8 @@ int perm_solve(CsrPerm *q, Engine *e, const double *b, double *x, double *marg, 
                hipStream_t s);
 int perm_marginals(CsrPerm *q, Engine *e, double *mean, double *prec, hipStream_t s);
 int perm_colors(const CsrPerm *q, int32_t *colors, int32_t *ncolors, hipStream_t s);
+// get (set = false) or set messages in the caller's CSR slot order
+int perm_messages(CsrPerm *q, Engine *e, double *P, double *h, bool set, hipStream_t s);
 }  // namespace gabp
 
 // the opaque plan of the C ABI: one system (eng), a batch of dense instances

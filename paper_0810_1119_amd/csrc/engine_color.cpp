@@ -16,10 +16,12 @@ struct CsrPerm {
   int64_t *rp = nullptr;
   int32_t *col = nullptr;
   double *val = nullptr;
+  int64_t nnz = 0;
+  int32_t *slot = nullptr;  // the caller's CSR slot of each renumbered slot
   double *bp = nullptr, *xp = nullptr, *mp = nullptr;  // renumbered b, x, marginals
 
   ~CsrPerm() {
-    void *bufs[] = {new2old, old2new, color, rp, col, val, bp, xp, mp};
+    void *bufs[] = {new2old, old2new, color, rp, col, val, slot, bp, xp, mp};
     for (void *b : bufs)
       if (b) dfree(b);
   }
@@ -50,7 +52,8 @@ int build_perm(const gabp_csr *A, CsrPerm *q, std::vector<int> *classes, hipStre
   int64_t *deg = nullptr, *dpos = nullptr, *len = nullptr, *scan = nullptr;
   uint32_t *flags = nullptr, *left = nullptr, *keys = nullptr;
   int32_t *idx = nullptr, *first = nullptr, *cmax = nullptr, *col_tmp = nullptr;
-  double *val_tmp = nullptr;
+  int32_t *slot_tmp = nullptr;
+  if (nnz > (int64_t)INT32_MAX) return GABP_ERR_UNSUPPORTED;  // slots are int32
   TRY_HIP(w.alloc(&deg, n, sizeof(int64_t)));
   TRY_HIP(w.alloc(&dpos, n, sizeof(int64_t)));
   TRY_HIP(w.alloc(&flags, 1, sizeof(uint32_t)));
@@ -106,25 +109,30 @@ int build_perm(const gabp_csr *A, CsrPerm *q, std::vector<int> *classes, hipStre
   for (int32_t f : hfirst)
     if (f >= 0) classes->push_back(f);  // colours present, in colour order
   classes->push_back(n);
-  // the renumbered matrix, each row's columns sorted
+  // the renumbered matrix, each row's columns sorted, and the caller's slot
+  // of each of its slots (the values gathered through it; messages cross
+  // the boundary the same way)
   TRY_HIP(w.alloc(&len, n, sizeof(int64_t)));
   TRY_HIP(w.alloc(&scan, scan_tmp_elems(n), sizeof(int64_t)));
   TRY_HIP(dalloc(&q->rp, (size_t)n + 1, sizeof(int64_t)));
   TRY_HIP(dalloc(&q->col, nnz, sizeof(int32_t)));
   TRY_HIP(dalloc(&q->val, nnz, sizeof(double)));
+  TRY_HIP(dalloc(&q->slot, nnz, sizeof(int32_t)));
+  q->nnz = nnz;
   TRY_HIP(w.alloc(&col_tmp, nnz, sizeof(int32_t)));
-  TRY_HIP(w.alloc(&val_tmp, nnz, sizeof(double)));
+  TRY_HIP(w.alloc(&slot_tmp, nnz, sizeof(int32_t)));
   TRY_HIP(launch_perm_rowlen(n, A->row_ptr, q->new2old, len, s));
   TRY_HIP(launch_scan(len, q->rp, n, scan, s));
-  TRY_HIP(launch_perm_fill(n, A->row_ptr, A->col, A->val, q->new2old, q->old2new, q->rp, col_tmp,
-                           val_tmp, s));
+  TRY_HIP(launch_perm_fill(n, A->row_ptr, A->col, q->new2old, q->old2new, q->rp, col_tmp,
+                           slot_tmp, s));
   if (nnz > 0) {
     size_t sb = 0;
     void *stmp = nullptr;
-    TRY_HIP(launch_rows_sort(n, nnz, q->rp, col_tmp, q->col, val_tmp, q->val, nullptr, &sb, s));
+    TRY_HIP(launch_rows_sort(n, nnz, q->rp, col_tmp, q->col, slot_tmp, q->slot, nullptr, &sb, s));
     TRY_HIP(w.alloc((char **)&stmp, sb, 1));
-    TRY_HIP(launch_rows_sort(n, nnz, q->rp, col_tmp, q->col, val_tmp, q->val, stmp, &sb, s));
+    TRY_HIP(launch_rows_sort(n, nnz, q->rp, col_tmp, q->col, slot_tmp, q->slot, stmp, &sb, s));
   }
+  TRY_HIP(launch_slot_move(nnz, q->slot, A->val, q->val, true, s));
   TRY_HIP(dalloc(&q->bp, n, sizeof(double)));
   TRY_HIP(dalloc(&q->xp, n, sizeof(double)));
   TRY_HIP(dalloc(&q->mp, n, sizeof(double)));
@@ -189,6 +197,34 @@ int perm_marginals(CsrPerm *q, Engine *e, double *mean, double *prec, hipStream_
   if (prec) TRY_HIP(launch_permute(q->n, q->new2old, q->mp, prec, false, s));
   TRY_HIP(hipStreamSynchronize(s));
   return GABP_OK;
+}
+
+// Messages in the caller's CSR order: the plan's own (renumbered) slots moved
+// through the slot map, by way of two FP64 buffers of nnz held for the call.
+int perm_messages(CsrPerm *q, Engine *e, double *P, double *h, bool set, hipStream_t s) {
+  if (q->nnz == 0) return set ? e->set_messages(P, h, s) : e->get_messages(P, h, s);
+  if (!P || !h) return GABP_ERR_ARG;
+  double *Pn = nullptr, *hn = nullptr;
+  hipError_t err = dalloc(&Pn, q->nnz, sizeof(double));
+  if (err == hipSuccess) err = dalloc(&hn, q->nnz, sizeof(double));
+  int rc = from_hip(err);
+  if (!rc && set) {
+    err = launch_slot_move(q->nnz, q->slot, P, Pn, true, s);
+    if (err == hipSuccess) err = launch_slot_move(q->nnz, q->slot, h, hn, true, s);
+    rc = err == hipSuccess ? e->set_messages(Pn, hn, s) : from_hip(err);
+  } else if (!rc) {
+    rc = e->get_messages(Pn, hn, s);
+    if (!rc) {
+      err = launch_slot_move(q->nnz, q->slot, Pn, P, false, s);
+      if (err == hipSuccess) err = launch_slot_move(q->nnz, q->slot, hn, h, false, s);
+      if (err == hipSuccess) err = hipStreamSynchronize(s);
+      rc = from_hip(err);
+    }
+  }
+  (void)hipStreamSynchronize(s);  // the buffers are free only after their last reader
+  if (Pn) dfree(Pn);
+  if (hn) dfree(hn);
+  return rc;
 }
 
 int perm_colors(const CsrPerm *q, int32_t *colors, int32_t *ncolors, hipStream_t s) {

@@ -443,11 +443,16 @@ hipError_t launch_perm_finish(int n, const uint32_t *keys, const int32_t *new2ol
                               int32_t *old2new, int32_t *first, hipStream_t s);
 hipError_t launch_perm_rowlen(int n, const int64_t *rp, const int32_t *new2old, int64_t *len,
                               hipStream_t s);
-hipError_t launch_perm_fill(int n, const int64_t *rp, const int32_t *col, const double *val,
-                            const int32_t *new2old, const int32_t *old2new, const int64_t *rp2,
-                            int32_t *col2, double *val2, hipStream_t s);
+// the renumbered rows' columns and, for each of their slots, the caller's slot
+hipError_t launch_perm_fill(int n, const int64_t *rp, const int32_t *col, const int32_t *new2old,
+                            const int32_t *old2new, const int64_t *rp2, int32_t *col2,
+                            int32_t *slot2, hipStream_t s);
+// to_new: out[d] = in[slot[d]]; else out[slot[d]] = in[d] (d < nnz)
+hipError_t launch_slot_move(int64_t nnz, const int32_t *slot, const double *in, double *out,
+                            bool to_new, hipStream_t s);
+// every row's (column, slot) pairs sorted by column
 hipError_t launch_rows_sort(int n, int64_t nnz, const int64_t *rp, const int32_t *col_in,
-                            int32_t *col_out, const double *val_in, double *val_out, void *tmp,
+                            int32_t *col_out, const int32_t *val_in, int32_t *val_out, void *tmp,
                             size_t *bytes, hipStream_t s);
 // to_new: out[r] = in[new2old[r]]; else out[new2old[r]] = in[r]
 hipError_t launch_permute(int n, const int32_t *new2old, const double *in, double *out,

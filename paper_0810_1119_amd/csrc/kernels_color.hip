@@ -104,17 +104,26 @@ __global__ void k_perm_rowlen(int n, const int64_t *__restrict__ rp,
 }
 
 __global__ void k_perm_fill(int n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
-                            const double *__restrict__ val, const int32_t *__restrict__ new2old,
-                            const int32_t *__restrict__ old2new, const int64_t *__restrict__ rp2,
-                            int32_t *__restrict__ col2, double *__restrict__ val2) {
+                            const int32_t *__restrict__ new2old, const int32_t *__restrict__ old2new,
+                            const int64_t *__restrict__ rp2, int32_t *__restrict__ col2,
+                            int32_t *__restrict__ slot2) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int o = new2old[r];
   int64_t d = rp2[r];
   for (int64_t e = rp[o]; e < rp[o + 1]; ++e, ++d) {
     col2[d] = old2new[col[e]];
-    val2[d] = val[e];
+    slot2[d] = (int32_t)e;  // the caller's slot (nnz < 2^31, checked by the host)
   }
+}
+
+// per slot: v2[d] = v[slot[d]] (gather) or v[slot[d]] = v2[d] (scatter), FP64
+__global__ void k_slot_move(int64_t nnz, const int32_t *__restrict__ slot,
+                            const double *__restrict__ in, double *__restrict__ out, bool to_new) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= nnz) return;
+  if (to_new) out[d] = in[slot[d]];
+  else out[slot[d]] = in[d];
 }
 
 // v2[new] = v[old] (gather) or v[old] = v2[new] (scatter), FP64
@@ -173,18 +182,25 @@ hipError_t launch_perm_rowlen(int n, const int64_t *rp, const int32_t *new2old, 
   return hipGetLastError();
 }
 
-hipError_t launch_perm_fill(int n, const int64_t *rp, const int32_t *col, const double *val,
-                            const int32_t *new2old, const int32_t *old2new, const int64_t *rp2,
-                            int32_t *col2, double *val2, hipStream_t s) {
+hipError_t launch_perm_fill(int n, const int64_t *rp, const int32_t *col, const int32_t *new2old,
+                            const int32_t *old2new, const int64_t *rp2, int32_t *col2,
+                            int32_t *slot2, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_perm_fill, dim3(nblk(n)), dim3(kBlock), 0, s, n, rp, col, val, new2old,
-                     old2new, rp2, col2, val2);
+  hipLaunchKernelGGL(k_perm_fill, dim3(nblk(n)), dim3(kBlock), 0, s, n, rp, col, new2old, old2new,
+                     rp2, col2, slot2);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_move(int64_t nnz, const int32_t *slot, const double *in, double *out,
+                            bool to_new, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_move, dim3(nblk(nnz)), dim3(kBlock), 0, s, nnz, slot, in, out, to_new);
   return hipGetLastError();
 }
 
 // every row's entries sorted by column (tmp == NULL: only *bytes is set)
 hipError_t launch_rows_sort(int n, int64_t nnz, const int64_t *rp, const int32_t *col_in,
-                            int32_t *col_out, const double *val_in, double *val_out, void *tmp,
+                            int32_t *col_out, const int32_t *val_in, int32_t *val_out, void *tmp,
                             size_t *bytes, hipStream_t s) {
   return hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, *bytes, col_in, col_out, val_in, val_out,
                                                      (int)nnz, n, rp, rp + 1, 0, 32, s);

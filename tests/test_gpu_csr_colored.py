@@ -1,7 +1,8 @@
 """GPU parity of coloured CSR plans (pair layout): the plan's own colouring
 (checked proper and deterministic here), and the trajectory against the FP64
 CPU oracle's coloured rounds with that colouring (oracle.Rounds(colors=...),
-classes in increasing colour order).  Tolerances as in test_gpu_csr.py."""
+classes in increasing colour order): marginals and, through the plan's
+renumbering, every message.  Tolerances as in test_gpu_csr.py."""
 import numpy as np
 import pytest
 
@@ -156,14 +157,52 @@ def test_colored_csr_damped_and_deterministic(G):
     assert rn / np.linalg.norm(b) <= 1e-8
 
 
-def test_colored_csr_limits(G):
-    m = W.sdd_random(64, 1)
-    plan = _plan(G, m)
+def _messages(G, plan, nnz):
+    P = torch.zeros(nnz, dtype=torch.float64, device="cuda")
+    h = torch.zeros(nnz, dtype=torch.float64, device="cuda")
+    assert G.gabp_plan_get_messages(plan, P, h) == G.GABP_OK
+    return host(P), host(h)
+
+
+@pytest.mark.parametrize("name", ["sdd_3000", "poisson3d_9x8x7", "tree_500"])
+def test_colored_csr_messages_match_oracle(G, name):
+    """Per-message parity through the renumbering: after each coloured sweep
+    the (P, h) of every directed message, read in the caller's CSR order,
+    equal the oracle's coloured rounds; messages set from the oracle's
+    resume its trajectory."""
+    m = MATRICES[name]()
+    b = W.uniform_b(m.n, 8)
+    plan = _plan(G, m, msg_fp32=0, freeze=0)
     try:
-        P = torch.zeros(m.nnz, dtype=torch.float64, device="cuda")
-        assert G.gabp_plan_get_messages(plan, P, P) == G.GABP_ERR_UNSUPPORTED
+        col, _ = _colors(G, plan, m)
+        assert G.gabp_plan_reset(plan, dev(b)) == G.GABP_OK
+        R = oracle.Rounds(m, b, colors=col)
+        for t in range(1, 5):
+            R.step()
+            assert G.gabp_plan_sweeps(plan, 1) == G.GABP_OK
+            P, h = _messages(G, plan, m.nnz)
+            Po, ho = R.P, R.information()
+            np.testing.assert_allclose(P, Po, rtol=1e-10, atol=1e-12 * np.abs(Po).max(),
+                                       err_msg=f"P, sweep {t}")
+            np.testing.assert_allclose(h, ho, rtol=1e-10, atol=1e-12 * np.abs(ho).max(),
+                                       err_msg=f"h, sweep {t}")
+        # resume from the oracle's messages two rounds on
+        R.step(2)
+        assert G.gabp_plan_set_messages(plan, dev(R.P), dev(R.information())) == G.GABP_OK
+        P, h = _messages(G, plan, m.nnz)
+        np.testing.assert_allclose(P, R.P, rtol=1e-14, atol=0)
+        R.step()
+        assert G.gabp_plan_sweeps(plan, 1) == G.GABP_OK
+        mean = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+        assert G.gabp_plan_marginals(plan, mean) == G.GABP_OK
+        mo, _ = R.marginals()
+        np.testing.assert_allclose(host(mean), mo, rtol=1e-10, atol=1e-12 * np.abs(mo).max())
     finally:
         G.gabp_plan_destroy(plan)
+
+
+def test_colored_csr_limits(G):
+    m = W.sdd_random(64, 1)
     rc, plan = G.gabp_plan_create(G.DeviceCSR.from_host(m),
                                   opts(G, layout=G.GABP_LAYOUT_GATHER))
     assert rc == G.GABP_ERR_UNSUPPORTED
