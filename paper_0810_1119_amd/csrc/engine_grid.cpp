@@ -890,18 +890,27 @@ int coarse_solve(gabp_plan *p, const double *b, double *x, double *marg_prec, ga
   bool recur = false;
   TRY_HIP(hipEventRecord(H.ev0, s));
   for (int cyc = 0;;) {
-    // r = b - A x (FP64) and the worst grid's relative residual
-    if (!recur) TRY_HIP(e0->residual(b, x, H.lv[0].v, s));
-    HostReadout rr;
-    if ((rc = e0->read_sum(s, &rr, 2, bn))) return finish(rc);
-    const double rel_all = std::sqrt(rr.sum) / bn;
-    const double rel = (e0->nseg > 1 && std::isfinite(rel_all)) ? rr.segrel : rel_all;
-    stats.rel_residual = rel;
-    stats.residual_per_eq = std::sqrt(rr.sum) / e0->n;
-    if (rr.flags & FLAG_BREAKDOWN) { status = GABP_ERR_BREAKDOWN; break; }
-    if ((rr.flags & FLAG_NONFINITE) || !std::isfinite(rel) || rel > 1e6) {
-      status = GABP_ERR_DIVERGED;
-      break;
+    double rel = 1.0;
+    if (cyc == 0 && !recur && e0->o.tol < 1.0) {
+      // x = 0: r = b, whose working copy and norms the reset above produced
+      TRY_HIP(hipMemcpyAsync(H.lv[0].v, b, (size_t)e0->n * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      stats.rel_residual = 1.0;
+      stats.residual_per_eq = bn / e0->n;
+    } else {
+      // r = b - A x (FP64) and the worst grid's relative residual
+      if (!recur) TRY_HIP(e0->residual(b, x, H.lv[0].v, s));
+      HostReadout rr;
+      if ((rc = e0->read_sum(s, &rr, 2, bn))) return finish(rc);
+      const double rel_all = std::sqrt(rr.sum) / bn;
+      rel = (e0->nseg > 1 && std::isfinite(rel_all)) ? rr.segrel : rel_all;
+      stats.rel_residual = rel;
+      stats.residual_per_eq = std::sqrt(rr.sum) / e0->n;
+      if (rr.flags & FLAG_BREAKDOWN) { status = GABP_ERR_BREAKDOWN; break; }
+      if ((rr.flags & FLAG_NONFINITE) || !std::isfinite(rel) || rel > 1e6) {
+        status = GABP_ERR_DIVERGED;
+        break;
+      }
     }
     const bool done = rel <= e0->o.tol;
     const bool spent = cyc >= e0->o.max_restarts || stats.sweeps >= e0->o.max_sweeps;
